@@ -1,0 +1,276 @@
+"""Subcycled RK4 on a block hierarchy (reference driver).
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+Implements the algorithm summary of Sec. II step by step:
+
+  advance_level(l):
+      rk4_step(l)                       # steps 1/3/5: full RK4 update, keep k1..k4
+      if l has a child:
+          prolongate(l+1)               # step 2: y_n, k1..k4 of l to l+1's RB points
+          advance_level(l+1) at theta0 = 0    # step 3 (+ recursion, step 4)
+          advance_level(l+1) at theta0 = 1/2  # step 5 (+ recursion, step 6)
+          restrict(l+1 -> l)            # step 7
+      fill(l, y, end)                   # RB ghosts of y from dense output at theta0+1/2
+      t_l += dt_l
+
+  rk4_step(l):
+      y_n <- y; Y <- y_n
+      for s = 1..4:
+          fill(l, Y, s)                 # SYNC copy, RB ghost = stage value, PHYS frozen
+          k_s <- f(Y)  on owned points
+          if s < 4: Y <- y_n + c_{s+1} dt_l k_s  on owned points
+      y <- y_n + dt_l/6 (((k1 + 2k2) + 2k3) + k4)  on owned points
+
+Prolongation (once per parent step, for five vectors, Sec. II and Fig. 1):
+for each RB point q, P[V](q) is the tensor product over dimensions of a copy
+(even q_d) or the degree-5 Lagrange midpoint weights (3,-25,150,150,-25,3)/256
+on parent points floor(q_d/2)-2 .. floor(q_d/2)+3 (odd q_d), applied along x
+first, then y, then z, each sum left to right.  Only parent-owned points are
+read.  The RB ghost of stage s at substep theta0 is
+    P[y_n] + H * (((w1 P[k1] + w2 P[k2]) + w3 P[k3]) + w4 P[k4])
+with H = dt_{l-1} and w from oracle.dense.ghost_weights.
+
+Restriction is injection: y_{l-1}(I) <- y_l(2I) for every restriction pair.
+
+Time steps: dt_l = cfl * dx_l.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+
+from . import cbuild
+from .dense import ghost_weights_f64
+from .hierarchy import PHYS, RB, SYNC, Hierarchy
+
+PROLONG_W = tuple(w / 256.0 for w in (3.0, -25.0, 150.0, 150.0, -25.0, 3.0))
+RK_C_NEXT = (0.5, 0.5, 1.0)
+
+
+class _LevelState:
+    def __init__(self, hier: Hierarchy, l: int, nvars: int):
+        lev = hier.levels[l]
+        G = hier.G
+        self.G = G
+        nb = lev.nblocks
+        dims = lev.bdims
+        pdims = dims + 2 * G
+        psize = np.prod(pdims, axis=1)
+        base = np.zeros(nb, dtype=np.int64)
+        base[1:] = np.cumsum(psize)[:-1]
+        self.base = base
+        self.pdims = pdims
+        self.total = int(psize.sum())
+        self.desc = np.ascontiguousarray(
+            np.concatenate([base[:, None], dims], axis=1).astype(np.int64))
+        self.nvars = nvars
+        z = lambda: np.zeros((nvars, self.total))
+        self.y, self.yn, self.Y = z(), z(), z()
+        self.k = [z(), z(), z(), z()]
+        self.lev = lev
+        # ghost slot destinations and sources
+        sd, ss, rd, ri, pd = [], [], [], [], []
+        for b in range(nb):
+            kind, a, c = hier.ghosts[l][b]
+            p = lev.ghost_points(b)
+            dst = self.flat_local(b, p - lev.blocks[b, 0, :])
+            m = kind == SYNC
+            sd.append(dst[m]); ss.append(self.flat_offset(a[m], c[m]))
+            m = kind == RB
+            rd.append(dst[m]); ri.append(a[m])
+            m = kind == PHYS
+            pd.append(dst[m])
+        cat = lambda v: np.ascontiguousarray(np.concatenate(v).astype(np.int64)) if v else \
+            np.zeros(0, dtype=np.int64)
+        self.sync_dst, self.sync_src = cat(sd), cat(ss)
+        self.rb_dst, self.rb_idx = cat(rd), cat(ri)
+        self.phys_dst = cat(pd)
+        self.phys_vals = np.zeros((nvars, len(self.phys_dst)))
+        # canonical order of owned points
+        canon = []
+        for lo, hi in lev.boxes:
+            zz, yy, xx = np.meshgrid(np.arange(lo[2], hi[2] + 1), np.arange(lo[1], hi[1] + 1),
+                                     np.arange(lo[0], hi[0] + 1), indexing="ij")
+            q = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1).astype(np.int64)
+            blk, off = lev.owner(q)
+            canon.append(self.flat_offset(blk, off))
+        self.canon = np.concatenate(canon)
+        self.owned_mask = np.zeros(self.total, dtype=bool)
+        self.owned_mask[self.canon] = True
+
+    def flat_local(self, b, r):
+        """Flat index of block-local coordinates r (owned origin at 0, ghosts negative)."""
+        G = self.G
+        px, py = self.pdims[b, 0], self.pdims[b, 1]
+        return self.base[b] + ((r[:, 2] + G) * py + (r[:, 1] + G)) * px + (r[:, 0] + G)
+
+    def flat_offset(self, blk, off):
+        """Flat index of owned points given (owner block, owner-local offset)."""
+        blk = np.asarray(blk, dtype=np.int64)
+        off = np.asarray(off, dtype=np.int64)
+        n = self.lev.bdims[blk]
+        x = off % n[:, 0]
+        y = (off // n[:, 0]) % n[:, 1]
+        z = off // (n[:, 0] * n[:, 1])
+        G = self.G
+        px, py = self.pdims[blk, 0], self.pdims[blk, 1]
+        return self.base[blk] + ((z + G) * py + (y + G)) * px + (x + G)
+
+
+class _Prolongation:
+    """Gather plan of the five-vector prolongation into one level's RB list."""
+
+    def __init__(self, hier: Hierarchy, l: int, parent: _LevelState):
+        rb = hier.rb[l]
+        plev = hier.levels[l - 1]
+        self.n = len(rb)
+        self.par = np.ascontiguousarray(
+            ((rb[:, 0] % 2) | ((rb[:, 1] % 2) << 1) | ((rb[:, 2] % 2) << 2)).astype(np.int64))
+        counts = np.ones(self.n, dtype=np.int64)
+        for d in range(3):
+            counts *= np.where((self.par >> d) & 1, 6, 1)
+        self.start = np.zeros(self.n + 1, dtype=np.int64)
+        self.start[1:] = np.cumsum(counts)
+        self.idx = np.zeros(int(self.start[-1]), dtype=np.int64)
+        for cls in range(8):
+            sel = np.nonzero(self.par == cls)[0]
+            if len(sel) == 0:
+                continue
+            odd = [(cls >> d) & 1 for d in range(3)]
+            offs = [np.arange(-2, 4) if odd[d] else np.arange(0, 1) for d in range(3)]
+            base = rb[sel] // 2
+            X = base[:, 0][:, None, None, None] + offs[0][None, None, None, :]
+            Y = base[:, 1][:, None, None, None] + offs[1][None, None, :, None]
+            Z = base[:, 2][:, None, None, None] + offs[2][None, :, None, None]
+            X, Y, Z = np.broadcast_arrays(X, Y, Z)       # (n, sz, sy, sx): z-major order
+            pts = plev.wrap(np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1))
+            blk, off = plev.owner(pts)
+            assert (blk >= 0).all()
+            flat = parent.flat_offset(blk, off).reshape(len(sel), -1)
+            m = flat.shape[1]
+            pos = self.start[sel][:, None] + np.arange(m)[None, :]
+            self.idx[pos.ravel()] = flat.ravel()
+        self.vstride = parent.total
+
+    def apply(self, V: np.ndarray) -> np.ndarray:
+        out = np.empty((V.shape[0], self.n))
+        if self.n:
+            cbuild.lib().orc_prolong(self.n, cbuild.ptr(self.start), cbuild.ptr(self.par),
+                                     cbuild.ptr(self.idx), V.shape[0], self.vstride,
+                                     cbuild.ptr(V), cbuild.ptr(out))
+        return out
+
+
+class OracleRun:
+    """Reference evolution of one member of a hierarchy.
+
+    rhs: "wave" (variables u, Pi).  sigma: Kreiss-Oliger strength.  cfl:
+    dt_l = cfl * dx_l.
+    """
+
+    def __init__(self, hier: Hierarchy, rhs: str = "wave", sigma: float = 0.32,
+                 cfl: float = 0.25):
+        if rhs != "wave":
+            raise ValueError(rhs)
+        self.hier = hier
+        self.spec = hier.spec
+        self.nvars = 2
+        self.sigma = sigma
+        self.cfl = cfl
+        self.lib = cbuild.lib()
+        self.L = hier.nlevels
+        self.st = [_LevelState(hier, l, self.nvars) for l in range(self.L)]
+        self.pro = [None] + [_Prolongation(hier, l, self.st[l - 1]) for l in range(1, self.L)]
+        self.P = [None] * self.L           # prolonged (y_n, k1..k4) per level
+        self.theta0 = [0.0] * self.L
+        self.t = [0.0] * self.L
+        self.dx = [self.spec.dx(l) for l in range(self.L)]
+        self.dt = [cfl * self.dx[l] for l in range(self.L)]
+        self.weights = {(s, th): ghost_weights_f64(s, Fraction(th))
+                        for s in range(1, 6) for th in (0.0, 0.5)}
+
+    # -- data ----------------------------------------------------------------
+    def set_data(self, l: int, var: int, values) -> None:
+        st = self.st[l]
+        st.y[var, st.canon] = np.asarray(values, dtype=np.float64)
+
+    def get(self, l: int, var: int, which: str = "y") -> np.ndarray:
+        st = self.st[l]
+        arr = {"y": st.y, "yn": st.yn, "k1": st.k[0], "k2": st.k[1], "k3": st.k[2],
+               "k4": st.k[3]}[which]
+        return arr[var, st.canon].copy()
+
+    def set_phys(self, l: int, values: np.ndarray) -> None:
+        self.st[l].phys_vals[:] = values
+
+    # -- pieces of the algorithm ---------------------------------------------
+    def rb_values(self, l: int, stage: int) -> np.ndarray:
+        Py, Pk1, Pk2, Pk3, Pk4 = self.P[l]
+        w1, w2, w3, w4 = self.weights[(stage, self.theta0[l])]
+        H = self.dt[l - 1]
+        return Py + H * (((w1 * Pk1 + w2 * Pk2) + w3 * Pk3) + w4 * Pk4)
+
+    def fill(self, l: int, A: np.ndarray, stage: int) -> None:
+        st = self.st[l]
+        if len(st.sync_dst):
+            self.lib.orc_copy_points(len(st.sync_dst), cbuild.ptr(st.sync_dst),
+                                     cbuild.ptr(st.sync_src), self.nvars, st.total,
+                                     cbuild.ptr(A))
+        if l > 0 and len(st.rb_dst):
+            A[:, st.rb_dst] = self.rb_values(l, stage)[:, st.rb_idx]
+        if len(st.phys_dst):
+            A[:, st.phys_dst] = st.phys_vals
+
+    def rhs(self, l: int, Y: np.ndarray, k: np.ndarray) -> None:
+        st = self.st[l]
+        self.lib.orc_wave_rhs(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
+                              cbuild.ptr(Y), cbuild.ptr(k), self.dx[l], self.sigma)
+
+    def rk4_step(self, l: int) -> None:
+        st = self.st[l]
+        dt = self.dt[l]
+        st.yn[:] = st.y
+        st.Y[:] = st.yn
+        for s in range(1, 5):
+            self.fill(l, st.Y, s)
+            self.rhs(l, st.Y, st.k[s - 1])
+            if s < 4:
+                self.lib.orc_stage(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
+                                   self.nvars, cbuild.ptr(st.yn), cbuild.ptr(st.k[s - 1]),
+                                   cbuild.ptr(st.Y), RK_C_NEXT[s - 1] * dt)
+        k1, k2, k3, k4 = st.k
+        self.lib.orc_final(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total, self.nvars,
+                           cbuild.ptr(st.yn), cbuild.ptr(k1), cbuild.ptr(k2), cbuild.ptr(k3),
+                           cbuild.ptr(k4), cbuild.ptr(st.y), dt)
+
+    def prolongate(self, l: int) -> None:
+        par = self.st[l - 1]
+        pro = self.pro[l]
+        self.P[l] = [pro.apply(par.yn)] + [pro.apply(k) for k in par.k]
+
+    def restrict(self, l: int) -> None:
+        pairs = self.hier.restrict[l]
+        if len(pairs) == 0:
+            return
+        fine, coarse = self.st[l], self.st[l - 1]
+        src = fine.flat_offset(pairs[:, 2], pairs[:, 3])
+        dst = coarse.flat_offset(pairs[:, 0], pairs[:, 1])
+        coarse.y[:, dst] = fine.y[:, src]
+
+    def advance_level(self, l: int) -> None:
+        self.rk4_step(l)
+        if l + 1 < self.L:
+            self.prolongate(l + 1)
+            self.theta0[l + 1] = 0.0
+            self.advance_level(l + 1)
+            self.theta0[l + 1] = 0.5
+            self.advance_level(l + 1)
+            self.restrict(l + 1)
+        self.fill(l, self.st[l].y, 5)
+        self.t[l] += self.dt[l]
+
+    def advance(self, ncoarse: int = 1) -> None:
+        for _ in range(ncoarse):
+            self.advance_level(0)
