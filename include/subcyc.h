@@ -1,0 +1,223 @@
+/* subcyc: subcycled RK4 time integration on nested block-structured mesh
+ * refinement, with refinement-boundary ghost zones filled from the coarse
+ * level's RK4 dense output, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Ji, Haas, Zlochower, Brandt, Schnetter, Wen, "GPU-accelerated
+ * Subcycling Time Integration with the Einstein Toolkit" (arXiv:2503.09629),
+ * Sec. II.  The problem is dy/dt = f(y) (Sec. II, first equation) on a
+ * hierarchy of levels with refinement ratio 2 in space and time.
+ *
+ * Conventions shared by every call
+ *   - Return value: SC_OK (0) or a negative sc_status.  No call aborts or
+ *     throws; sc_last_error() describes the most recent failure.
+ *   - Grids are vertex centred.  On level l the index i sits at
+ *     x = origin + i * dx0 / 2^l; level l-1 index I coincides with level l
+ *     index 2I.  Boxes are inclusive index ranges on their own level.
+ *   - Host-side floating point arguments are always double.
+ *   - Device memory is owned by the caller: sc_device_bytes() reports the
+ *     arena size, the caller allocates it (any allocator) and binds it with
+ *     sc_bind_device_memory(); the library never allocates or frees device
+ *     memory itself and never creates streams.  Work is enqueued on the
+ *     caller's HIP stream given to sc_create(); calls that return host data
+ *     synchronise that stream.
+ *   - State machine: CREATED -> BUILT (sc_build_hierarchy) -> BOUND
+ *     (sc_bind_device_memory) -> READY (first sc_set_initial_data).  A call
+ *     made in the wrong state returns SC_E_STATE.
+ *   - One thread may use a context at a time.
+ */
+#ifndef SUBCYC_H
+#define SUBCYC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SC_ABI_VERSION 1
+
+typedef enum {
+  SC_OK = 0,
+  SC_E_ARG = -1,       /* bad argument (null pointer, out-of-range value, CFL > 0.5) */
+  SC_E_STATE = -2,     /* call out of order */
+  SC_E_NEST = -3,      /* hierarchy not properly nested or not aligned */
+  SC_E_MEM = -4,       /* bound arena too small or misaligned */
+  SC_E_HIP = -5,       /* a HIP runtime call failed; the message names it */
+  SC_E_NONFINITE = -6  /* sc_check_finite found a NaN or infinity */
+} sc_status;
+
+/* Right-hand sides.  SC_RHS_WAVE: the scalar wave as a first-order system,
+ * du/dt = Pi, dPi/dt = Laplacian(u) (Sec. IV.A); variables (u, Pi). */
+enum { SC_RHS_WAVE = 0 };
+
+/* Precision of the right-hand-side stencil.  SC_MIXED reads FP32 shadow
+ * copies of the stage vectors and evaluates the stencil in FP32; the state,
+ * RK4 accumulation, dense output, prolongation and restriction stay FP64. */
+enum { SC_FP64 = 0, SC_MIXED = 1 };
+
+/* Execution of one coarse step.  PER_BLOCK: one kernel launch per block per
+ * stage; BATCHED: one launch per level per stage covering all blocks of the
+ * level; GRAPH: BATCHED, captured once as a HIP graph and replayed. */
+enum { SC_EXEC_PER_BLOCK = 0, SC_EXEC_BATCHED = 1, SC_EXEC_GRAPH = 2 };
+
+/* Arrays that can be read back: the state y, the stored RK4 slopes k1..k4 of
+ * the last step (Sec. II, step 1 "Store k1..k4") and y_n, the state at the
+ * start of the last step. */
+enum { SC_ARR_Y = 0, SC_ARR_K1 = 1, SC_ARR_K2 = 2, SC_ARR_K3 = 3, SC_ARR_K4 = 4, SC_ARR_YN = 5 };
+
+/* Ghost fills at refinement boundaries: the fine stage vectors Y1..Y4
+ * (Sec. II, Eqs. Y1-Y4) and the state after a substep ("end", dense output
+ * at theta0 + 1/2, Sec. II steps 3 and 5). */
+enum { SC_FILL_Y1 = 1, SC_FILL_Y2 = 2, SC_FILL_Y3 = 3, SC_FILL_Y4 = 4, SC_FILL_END = 5 };
+
+typedef struct sc_ctx sc_ctx;
+
+typedef struct {
+  int64_t lo[3], hi[3]; /* inclusive vertex indices on the box's level, x, y, z */
+} sc_box;
+
+typedef struct {
+  int32_t abi_version; /* SC_ABI_VERSION */
+  int32_t rhs;         /* SC_RHS_* */
+  int32_t precision;   /* SC_FP64 or SC_MIXED */
+  int32_t exec;        /* SC_EXEC_* */
+  int32_t nghost;      /* ghost width; must be 3 (fourth-order FD with r = 4 dissipation) */
+  int32_t reserved;
+  double ko_sigma;     /* Kreiss-Oliger strength sigma (Sec. III.C), e.g. 0.32 */
+  double cfl;          /* dt_l = cfl * dx_l, 0 < cfl <= 0.5 */
+} sc_config;
+
+/* Fill *cfg with the defaults: wave RHS, FP64, batched, nghost 3,
+ * sigma 0.32, cfl 0.25. */
+int sc_config_default(sc_config* cfg);
+
+/* Create a context that enqueues on hip_stream (a hipStream_t owned by the
+ * caller, or NULL for the null stream).  No device memory is touched. */
+int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out);
+
+/* Destroy a context and its host-side tables and graphs.  Does not free the
+ * bound arena (the caller owns it).  NULL is accepted. */
+int sc_destroy(sc_ctx* ctx);
+
+/* Text of the last error on ctx, or of the last failed sc_create on this
+ * thread when ctx is NULL.  Owned by the library; valid until the next call. */
+const char* sc_last_error(const sc_ctx* ctx);
+
+/* Build the hierarchy and every index map (host only, once).
+ *   nmembers        independent copies evolved together (ensemble batching)
+ *   origin, dx0     coordinates of level-0 index 0 and level-0 spacing
+ *   ncells0         level-0 cells per dimension; level 0 holds indices
+ *                   [0, n-1] in a periodic dimension and [0, n] otherwise
+ *   periodic        per dimension, 0 or 1
+ *   nlevels         number of levels (>= 1)
+ *   nboxes_per_level  counts for levels 1..nlevels-1 (nlevels-1 entries)
+ *   boxes           the boxes of levels 1.. concatenated in level order
+ *   block_seed      seed of the block split (SplitMix64 stream per level,
+ *                   state block_seed + level)
+ *   min_block, max_block  block side limits (max_block >= 2*min_block - 1)
+ * Blocks: every level box is split recursively along its longest side (ties
+ * x, y, z) at min_block + (draw mod (n - 2 min_block + 1)), left part first.
+ * Fine boxes need even bounds (or to span a periodic dimension), must lie in
+ * the domain, must not overlap, and every parent point of every
+ * refinement-boundary prolongation stencil must be owned by one parent box;
+ * otherwise SC_E_NEST. */
+int sc_build_hierarchy(sc_ctx* ctx, int32_t nmembers, const double origin[3], double dx0,
+                       const int64_t ncells0[3], const int32_t periodic[3], int32_t nlevels,
+                       const int32_t* nboxes_per_level, const sc_box* boxes,
+                       uint64_t block_seed, int32_t min_block, int32_t max_block);
+
+/* Per level (one member): number of blocks, owned points, and distinct
+ * refinement-boundary (RB) points. */
+int sc_get_counts(const sc_ctx* ctx, int32_t level, int32_t* nblocks, int64_t* nowned,
+                  int64_t* nrb);
+
+/* Canonical little-endian int64 export of all maps; words == NULL returns the
+ * size in *nwords.  Layout: header [0x53554243, 1, nlevels, nmembers]; then
+ * per level: [level, nblocks, nowned, nrb, nrestrict], the blocks
+ * [lo x,y,z, hi x,y,z] in id order, every block's ghost slots in visiting
+ * order (z-major, y, x fastest over [lo-G, hi+G]^3 minus the block) as
+ * SYNC [0, owner block, owner-local offset] / RB [1, rb index, 0] /
+ * PHYS [2, -1, 0], the RB list sorted by (z, y, x) as
+ * [qx, qy, qz, qx/2, qy/2, qz/2, odd bits x=1 y=2 z=4], and the restriction
+ * pairs sorted by (parent block, parent offset) as
+ * [parent block, parent offset, block, offset].  Offsets are
+ * ((z - lo_z) n_y + (y - lo_y)) n_x + (x - lo_x) within the owning block. */
+int sc_export_maps(const sc_ctx* ctx, int64_t* words, int64_t* nwords);
+
+/* Device arena size in bytes for the built hierarchy and configuration. */
+int sc_device_bytes(const sc_ctx* ctx, size_t* nbytes);
+
+/* Bind a caller-owned device allocation of at least sc_device_bytes() bytes,
+ * 256-byte aligned, and upload the index tables (asynchronously, on the
+ * context's stream).  The caller keeps it alive until sc_destroy. */
+int sc_bind_device_memory(sc_ctx* ctx, void* dptr, size_t nbytes);
+
+/* Initial data of one variable on the owned points of one level of one
+ * member, n = owned points, in canonical order (the level's boxes in order,
+ * each z-major, y, x fastest).  The host array is copied before return. */
+int sc_set_initial_data(sc_ctx* ctx, int32_t member, int32_t level, int32_t var,
+                        const double* host, int64_t n);
+
+/* Advance the whole hierarchy by ncoarse coarse steps with the recursive
+ * subcycling schedule (Sec. II, steps 1-7): a level takes one RK4 step,
+ * prolongs (y_n, k1..k4) to its child's refinement boundary, the child takes
+ * two steps at theta0 = 0 and 1/2, and the child's solution is restricted by
+ * injection.  Asynchronous. */
+int sc_advance(sc_ctx* ctx, int32_t ncoarse);
+
+/* The pieces of sc_advance, for callers that drive the schedule themselves:
+ * one RK4 step of one level with its stage ghosts taken from the prolonged
+ * data of the given substep (0: theta0 = 0, 1: theta0 = 1/2; ignored on
+ * level 0), without recursion (Sec. II, steps 1, 3, 5); */
+int sc_step_level(sc_ctx* ctx, int32_t level, int32_t substep);
+/* prolongation of the parent's (y_n, k1..k4) to fine_level's refinement
+ * boundary, producing the ghost stage values of both substeps (step 2); */
+int sc_prolongate(sc_ctx* ctx, int32_t fine_level);
+/* ghost fill of the state y of a level: SYNC copies, and on refinement
+ * boundaries the dense-output value `which` (SC_FILL_*) of `substep`; */
+int sc_fill_ghosts(sc_ctx* ctx, int32_t level, int32_t which, int32_t substep);
+/* injection of fine_level's state into the parent (step 7). */
+int sc_restrict(sc_ctx* ctx, int32_t fine_level);
+
+/* Read one array (SC_ARR_*) of one variable on the owned points of a level of
+ * a member, canonical order, n = owned points.  Synchronises the stream. */
+int sc_read_back(sc_ctx* ctx, int32_t member, int32_t level, int32_t var, int32_t array,
+                 double* host, int64_t n);
+
+/* Refinement-boundary ghost values of a level as the stencil would see them
+ * for stage `which` (SC_FILL_Y1..Y4 from the stored stage tables,
+ * SC_FILL_END recomputed) of `substep`, in RB-list order, n = nrb of the
+ * level.  Requires a preceding sc_prolongate.  Synchronises the stream. */
+int sc_read_rb(sc_ctx* ctx, int32_t member, int32_t level, int32_t which, int32_t substep,
+               int32_t var, double* host, int64_t n);
+
+/* Deterministic norms of one array of one variable over the owned points of
+ * a level of a member: out[0] = max |a|, out[1] = sqrt(mean a^2),
+ * out[2] = number of non-finite values.  Synchronises the stream. */
+int sc_norms(sc_ctx* ctx, int32_t member, int32_t level, int32_t var, int32_t array,
+             double out[3]);
+
+/* SC_E_NONFINITE if any owned value of the state is not finite on any level. */
+int sc_check_finite(sc_ctx* ctx);
+
+/* Simulation time of a level (host bookkeeping). */
+int sc_level_time(const sc_ctx* ctx, int32_t level, double* t);
+
+/* Switch the execution mode (SC_EXEC_*) between calls to sc_advance. */
+int sc_set_exec(sc_ctx* ctx, int32_t exec);
+
+/* Fill every halo table and every slope array with quiet NaN, so that any
+ * read of a ghost value that the schedule did not fill first shows up as a
+ * non-finite result (a test aid for fill ordering).  SC_E_STATE if a level
+ * has physical-boundary ghosts, whose values this would erase. */
+int sc_poison_halos(sc_ctx* ctx);
+
+/* Point-updates of one coarse step of one member (sum over levels of owned
+ * points times level steps) and launches enqueued by the last sc_advance. */
+int sc_stats(const sc_ctx* ctx, int64_t* updates_per_coarse_step, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUBCYC_H */

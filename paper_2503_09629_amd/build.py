@@ -1,0 +1,73 @@
+"""Build libsubcyc.so in-tree with hipcc for gfx950.
+
+The HIP sources are compiled without floating-point contraction (every
+product and sum is rounded as written) and without packed-FP32 instructions.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "libsubcyc.so")
+BUILD = os.path.join(HERE, "_build")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
+          f"-I{os.path.join(HERE, '..', 'include')}"]
+DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def torch_lib_dir() -> str:
+    """Directory of the HIP runtime that PyTorch loads.
+
+    Device pointers and streams handed to the library come from that runtime,
+    so the library must link the same libamdhip64 (torch's copy has no
+    SONAME; a second runtime instance in the process would see no device)."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or spec.origin is None:
+        raise RuntimeError("PyTorch is required to locate the HIP runtime")
+    d = os.path.join(os.path.dirname(spec.origin), "lib")
+    if not os.path.exists(os.path.join(d, "libamdhip64.so")):
+        raise RuntimeError(f"no libamdhip64.so in {d}")
+    return d
+
+
+def sources():
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
+                  if f.endswith((".cpp", ".hip")))
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source and link the shared library (always rebuilds)."""
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    for src in sources():
+        obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+        cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+        if src.endswith(".hip"):
+            cmd[1:1] = ["-x", "hip", *DEVICE]
+        else:
+            cmd[1:1] = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = OUT + f".tmp{os.getpid()}"
+    tl = torch_lib_dir()
+    link = ["g++", "-shared", "-fPIC", "-o", tmp, *objs, f"-L{tl}", "-l:libamdhip64.so",
+            f"-Wl,-rpath,{tl}", "-Wl,--no-undefined"]
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
+    os.replace(tmp, OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)
+    print(OUT)

@@ -1,0 +1,1031 @@
+// C-ABI of libsubcyc: context, hierarchy, arena, scheduler, readers.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+
+#include "runtime.hpp"
+
+using namespace sc;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(sc_ctx* c, int code, const std::string& m) {
+  if (c) c->err = m;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, SC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Dense-output weights (Sec. II) in exact rational arithmetic.
+struct Rat {
+  int64_t n, d;
+  Rat(int64_t a = 0, int64_t b = 1) : n(a), d(b) { norm(); }
+  void norm() {
+    if (d < 0) n = -n, d = -d;
+    int64_t g = std::gcd(n < 0 ? -n : n, d);
+    if (g > 1) n /= g, d /= g;
+  }
+  Rat operator+(Rat o) const { return Rat(n * o.d + o.n * d, d * o.d); }
+  Rat operator-(Rat o) const { return Rat(n * o.d - o.n * d, d * o.d); }
+  Rat operator*(Rat o) const { return Rat(n * o.n, d * o.d); }
+  double f() const { return (double)n / (double)d; }
+};
+
+// b_i(theta) of the RK4 dense output and its theta-derivatives (order m).
+void dense_b(Rat th, int m, Rat out[4]) {
+  Rat t2 = th * th, t3 = t2 * th;
+  switch (m) {
+    case 0:
+      out[0] = th - Rat(3, 2) * t2 + Rat(2, 3) * t3;
+      out[1] = out[2] = t2 - Rat(2, 3) * t3;
+      out[3] = Rat(-1, 2) * t2 + Rat(2, 3) * t3;
+      break;
+    case 1:
+      out[0] = Rat(1) - Rat(3) * th + Rat(2) * t2;
+      out[1] = out[2] = Rat(2) * th - Rat(2) * t2;
+      out[3] = Rat(-1) * th + Rat(2) * t2;
+      break;
+    case 2:
+      out[0] = Rat(-3) + Rat(4) * th;
+      out[1] = out[2] = Rat(2) - Rat(4) * th;
+      out[3] = Rat(-1) + Rat(4) * th;
+      break;
+    default:
+      out[0] = Rat(4);
+      out[1] = out[2] = Rat(-4);
+      out[3] = Rat(4);
+  }
+}
+
+// Ghost value = y_n + H * sum_i w_i k_i for fine stage `fill` (1..4, Taylor
+// forms of Y1..Y4 with fine step h = H/2 and f_y y'' = 4 (k3 - k2) / H^2)
+// or the end value (5, dense output at theta0 + 1/2).
+void ghost_weights(int fill, Rat th0, double w[4]) {
+  Rat r[4];
+  if (fill == 5) {
+    dense_b(th0 + Rat(1, 2), 0, r);
+  } else {
+    Rat b0[4], b1[4], b2[4], b3[4];
+    dense_b(th0, 0, b0);
+    dense_b(th0, 1, b1);
+    dense_b(th0, 2, b2);
+    dense_b(th0, 3, b3);
+    const Rat fyy[4] = {Rat(0), Rat(-4), Rat(4), Rat(0)};
+    // coefficients of h y', h^2 y'', h^3 y''', h^3 f_y y'' in Eqs. Y1-Y4
+    Rat c1, c2, c3, cf;
+    if (fill == 2) c1 = Rat(1, 2);
+    if (fill == 3) c1 = Rat(1, 2), c2 = Rat(1, 4), c3 = Rat(1, 16), cf = Rat(-1, 16);
+    if (fill == 4) c1 = Rat(1), c2 = Rat(1, 2), c3 = Rat(1, 8), cf = Rat(1, 8);
+    const Rat h(1, 2), h2 = h * h, h3 = h2 * h;
+    for (int i = 0; i < 4; ++i)
+      r[i] = b0[i] + c1 * h * b1[i] + c2 * h2 * b2[i] + c3 * h3 * b3[i] + cf * h3 * fyy[i];
+  }
+  for (int i = 0; i < 4; ++i) w[i] = r[i].f();
+}
+
+// ---------------------------------------------------------------------------
+// Device layout.
+
+inline int64_t floordiv2(int64_t a) { return a >= 0 ? a / 2 : -((-a + 1) / 2); }
+
+void split_even(int64_t n, int64_t maxlen, std::vector<std::pair<int, int>>* out) {
+  out->clear();
+  const int64_t parts = (n + maxlen - 1) / maxlen;
+  int64_t start = 0;
+  for (int64_t p = 0; p < parts; ++p) {
+    const int64_t len = n / parts + (p < n % parts ? 1 : 0);
+    out->push_back({(int)start, (int)len});
+    start += len;
+  }
+}
+
+void tile_region(int box, const int64_t o[3], const int64_t n[3], const TileShape& s,
+                 std::vector<TileDev>* out) {
+  std::vector<std::pair<int, int>> sx, sy, sz;
+  split_even(n[0], s.tx, &sx);
+  split_even(n[1], s.ty, &sy);
+  split_even(n[2], s.tz, &sz);
+  for (auto& z : sz)
+    for (auto& y : sy)
+      for (auto& x : sx) {
+        TileDev t;
+        t.box = box;
+        t.x0 = (int)o[0] + x.first;
+        t.y0 = (int)o[1] + y.first;
+        t.z0 = (int)o[2] + z.first;
+        t.nx = x.second;
+        t.ny = y.second;
+        t.nz = z.second;
+        t.pad = 0;
+        out->push_back(t);
+      }
+}
+
+// parent box of level l-1 holding the whole prolongation stencil of q
+int stencil_parent(const LevelMaps& P, const int64_t q[3]) {
+  int64_t smin[3], smax[3];
+  for (int d = 0; d < 3; ++d) {
+    int64_t base = floordiv2(q[d]);
+    smin[d] = (q[d] & 1) ? base - 2 : base;
+    smax[d] = (q[d] & 1) ? base + 3 : base;
+  }
+  for (size_t i = 0; i < P.boxes.size(); ++i) {
+    const IBox& b = P.boxes[i];
+    bool in = true;
+    for (int d = 0; d < 3; ++d) {
+      bool full = P.periodic[d] && b.lo[d] == 0 && b.hi[d] == P.N[d] - 1;
+      if (!full) in = in && smin[d] >= b.lo[d] && smax[d] <= b.hi[d];
+    }
+    if (in) return (int)i;
+  }
+  return -1;
+}
+
+std::string build_layout(sc_ctx* c) {
+  const Hierarchy& H = c->hier;
+  const int nm = H.geo.nmembers;
+  const int nl = H.geo.nlevels;
+  c->lev.assign(nl, LevelDev());
+  for (int l = 0; l < nl; ++l) {
+    const LevelMaps& M = H.levels[l];
+    LevelDev& L = c->lev[l];
+    L.dx = H.geo.dx0 / (double)(int64_t(1) << l);
+    L.dt = c->cfg.cfl * L.dx;
+    L.nb_member = (int)M.boxes.size();
+    L.has_child = l + 1 < nl;
+    L.nyh = l == 0 ? 1 : 8;
+    // boxes of member 0
+    std::vector<BoxDev> b0(L.nb_member);
+    int64_t base = 0;
+    L.prefix.assign(L.nb_member + 1, 0);
+    for (int ib = 0; ib < L.nb_member; ++ib) {
+      const IBox& bx = M.boxes[ib];
+      BoxDev& B = b0[ib];
+      B.base = base;
+      B.nx = (int)bx.n(0);
+      B.ny = (int)bx.n(1);
+      B.nz = (int)bx.n(2);
+      B.px = B.nx + 2 * kG;
+      B.py = B.ny + 2 * kG;
+      for (int d = 0; d < 3; ++d) {
+        B.lo[d] = (int)bx.lo[d];
+        B.wrapN[d] = (M.periodic[d] && bx.lo[d] == 0 && bx.hi[d] == M.N[d] - 1) ? (int)M.N[d] : 0;
+      }
+      B.pad = 0;
+      base += (int64_t)B.px * B.py * (B.nz + 2 * kG);
+      L.prefix[ib + 1] = L.prefix[ib] + bx.volume();
+    }
+    L.member_total = base;
+    L.total = base * nm;
+    L.owned_member = L.prefix[L.nb_member];
+    for (int m = 0; m < nm; ++m)
+      for (int ib = 0; ib < L.nb_member; ++ib) {
+        BoxDev B = b0[ib];
+        B.base += m * L.member_total;
+        L.boxes.push_back(B);
+      }
+    // halo classification of every box (member 0), replicated per member
+    std::vector<SyncEntry> sync0;
+    std::vector<ProlongEntry> pro0;
+    std::vector<int64_t> phys0;
+    std::map<int64_t, int64_t> first;  // RB key -> first halo offset
+    for (int ib = 0; ib < L.nb_member; ++ib) {
+      const BoxDev& B = b0[ib];
+      for (int z = -kG; z < B.nz + kG; ++z)
+        for (int y = -kG; y < B.ny + kG; ++y)
+          for (int x = -kG; x < B.nx + kG; ++x) {
+            if (x >= 0 && x < B.nx && y >= 0 && y < B.ny && z >= 0 && z < B.nz) continue;
+            const int64_t dst = B.base + ((int64_t)(z + kG) * B.py + (y + kG)) * B.px + (x + kG);
+            int64_t p[3] = {B.lo[0] + x, B.lo[1] + y, B.lo[2] + z}, q[3];
+            M.wrap(p, q);
+            if (M.outside(q)) {
+              phys0.push_back(dst);
+              continue;
+            }
+            int ob = M.box_of(q);
+            if (ob >= 0) {
+              const BoxDev& O = b0[ob];
+              const int64_t src = O.base +
+                                  ((q[2] - O.lo[2] + kG) * O.py + (q[1] - O.lo[1] + kG)) * O.px +
+                                  (q[0] - O.lo[0] + kG);
+              sync0.push_back({dst, src});
+              continue;
+            }
+            if (l == 0) return "level 0 has unowned halo points";
+            const int pb = stencil_parent(H.levels[l - 1], q);
+            if (pb < 0) return "prolongation stencil not inside one parent box";
+            ProlongEntry e;
+            e.dst = dst;
+            for (int d = 0; d < 3; ++d) e.q[d] = (int32_t)q[d];
+            e.pbox = pb;
+            pro0.push_back(e);
+            const int64_t key = (q[2] << 42) | (q[1] << 21) | q[0];
+            first.emplace(key, dst);
+          }
+    }
+    const int npb = l > 0 ? c->lev[l - 1].nb_member : 0;
+    for (int m = 0; m < nm; ++m) {
+      const int64_t off = m * L.member_total;
+      for (auto e : sync0) L.sync.push_back({e.dst + off, e.src + off});
+      for (auto e : pro0) {
+        e.dst += off;
+        e.pbox += m * npb;
+        L.prolong.push_back(e);
+      }
+      for (auto d : phys0) L.phys.push_back(d + off);
+    }
+    // RB list (sorted) entries for readers
+    L.nrb = (int64_t)M.rb.size();
+    for (int m = 0; m < nm; ++m)
+      for (int64_t j = 0; j < L.nrb; ++j) {
+        const auto& q = M.rb[j];
+        ProlongEntry e;
+        e.dst = j;
+        for (int d = 0; d < 3; ++d) e.q[d] = (int32_t)q[d];
+        e.pbox = stencil_parent(H.levels[l - 1], q.data()) + m * npb;
+        L.rblist.push_back(e);
+        const int64_t key = (q[2] << 42) | (q[1] << 21) | q[0];
+        auto it = first.find(key);
+        if (it == first.end()) return "RB list entry without a halo slot";
+        L.rbfirst.push_back(it->second + m * L.member_total);
+      }
+    // restriction regions (this level as the fine level)
+    if (l > 0) {
+      const LevelMaps& P = H.levels[l - 1];
+      const int npbm = c->lev[l - 1].nb_member;
+      std::vector<RestrictRegion> r0;
+      for (int fb = 0; fb < L.nb_member; ++fb) {
+        const IBox& f = M.boxes[fb];
+        for (int pb = 0; pb < npbm; ++pb) {
+          const IBox& pbx = P.boxes[pb];
+          RestrictRegion R;
+          R.fbox = fb;
+          R.pbox = pb;
+          int64_t cnt = 1;
+          for (int d = 0; d < 3; ++d) {
+            int64_t a = std::max((f.lo[d] + 1) / 2, pbx.lo[d]);
+            int64_t b = std::min(f.hi[d] / 2, pbx.hi[d]);
+            R.c0[d] = (int)a;
+            R.n[d] = (int)std::max<int64_t>(0, b - a + 1);
+            cnt *= R.n[d];
+          }
+          if (cnt > 0) {
+            R.start = cnt;  // temporarily the count
+            r0.push_back(R);
+          }
+        }
+      }
+      int64_t start = 0;
+      for (int m = 0; m < nm; ++m)
+        for (auto R : r0) {
+          const int64_t cnt = R.start;
+          R.fbox += m * L.nb_member;
+          R.pbox += m * npbm;
+          R.start = start;
+          start += cnt;
+          L.restr.push_back(R);
+        }
+      L.restr_total = start;
+    }
+    // tiles: batched over boxes, and per block
+    for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
+      const BoxDev& B = L.boxes[ib];
+      const int64_t o[3] = {0, 0, 0}, n[3] = {B.nx, B.ny, B.nz};
+      tile_region(ib, o, n, L.shape, &L.tiles);
+    }
+    L.btile_start.push_back(0);
+    for (int m = 0; m < nm; ++m)
+      for (size_t b = 0; b < M.blocks.size(); ++b) {
+        const IBox& bl = M.blocks[b];
+        const int ib = M.block_box[b];
+        const IBox& bx = M.boxes[ib];
+        const int64_t o[3] = {bl.lo[0] - bx.lo[0], bl.lo[1] - bx.lo[1], bl.lo[2] - bx.lo[2]};
+        const int64_t n[3] = {bl.n(0), bl.n(1), bl.n(2)};
+        tile_region(m * L.nb_member + ib, o, n, L.shape, &L.btiles);
+        L.btile_start.push_back((int32_t)L.btiles.size());
+      }
+  }
+  return "";
+}
+
+// Host-side bounds check of every device table before anything is uploaded:
+// each kernel index derived from these tables stays inside its buffers.
+std::string validate_layout(const sc_ctx* c) {
+  for (size_t l = 0; l < c->lev.size(); ++l) {
+    const LevelDev& L = c->lev[l];
+    auto in_level = [&](int64_t o) { return o >= 0 && o < L.total; };
+    auto tile_ok = [&](const TileDev& t) {
+      if (t.box < 0 || t.box >= (int)L.boxes.size()) return false;
+      const BoxDev& B = L.boxes[t.box];
+      return t.nx >= 1 && t.ny >= 1 && t.nz >= 1 && t.nx <= kTileMaxX && t.ny <= kTileMaxY &&
+             t.x0 >= 0 && t.y0 >= 0 && t.z0 >= 0 && t.x0 + t.nx <= B.nx &&
+             t.y0 + t.ny <= B.ny && t.z0 + t.nz <= B.nz;
+    };
+    for (const TileDev& t : L.tiles)
+      if (!tile_ok(t)) return "tile outside its box";
+    for (const TileDev& t : L.btiles)
+      if (!tile_ok(t)) return "block tile outside its box";
+    for (const BoxDev& B : L.boxes)
+      if (!in_level(B.base) ||
+          B.base + (int64_t)B.px * B.py * (B.nz + 2 * kG) > L.total)
+        return "box array outside the level arrays";
+    for (const SyncEntry& e : L.sync)
+      if (!in_level(e.dst) || !in_level(e.src)) return "halo copy entry out of range";
+    for (int64_t d : L.phys)
+      if (!in_level(d)) return "physical ghost entry out of range";
+    for (int64_t d : L.rbfirst)
+      if (!in_level(d)) return "RB reader entry out of range";
+    if (l == 0 && (!L.prolong.empty() || !L.restr.empty())) return "level 0 has parent data";
+    if (l > 0) {
+      const LevelDev& P = c->lev[l - 1];
+      auto pro_ok = [&](const ProlongEntry& e) {
+        if (e.pbox < 0 || e.pbox >= (int)P.boxes.size()) return false;
+        const BoxDev& B = P.boxes[e.pbox];
+        const int n[3] = {B.nx, B.ny, B.nz};
+        for (int d = 0; d < 3; ++d) {
+          const int base = e.q[d] >> 1, odd = e.q[d] & 1;
+          if (e.q[d] < 0) return false;
+          if (B.wrapN[d] > 0) continue;
+          const int a = odd ? base - 2 : base, b = odd ? base + 3 : base;
+          if (a - B.lo[d] < 0 || b - B.lo[d] >= n[d]) return false;
+        }
+        return true;
+      };
+      for (const ProlongEntry& e : L.prolong)
+        if (!pro_ok(e) || !in_level(e.dst)) return "prolongation entry out of range";
+      for (const ProlongEntry& e : L.rblist)
+        if (!pro_ok(e) || e.dst < 0 || e.dst >= L.nrb) return "RB list entry out of range";
+      int64_t expect = 0;
+      for (const RestrictRegion& R : L.restr) {
+        if (R.fbox < 0 || R.fbox >= (int)L.boxes.size() || R.pbox < 0 ||
+            R.pbox >= (int)P.boxes.size() || R.start != expect)
+          return "restriction region malformed";
+        const BoxDev &F = L.boxes[R.fbox], &Pb = P.boxes[R.pbox];
+        const int fn[3] = {F.nx, F.ny, F.nz}, pn[3] = {Pb.nx, Pb.ny, Pb.nz};
+        for (int d = 0; d < 3; ++d) {
+          const int a = R.c0[d], b = R.c0[d] + R.n[d] - 1;
+          if (R.n[d] < 1 || 2 * a - F.lo[d] < 0 || 2 * b - F.lo[d] >= fn[d] ||
+              a - Pb.lo[d] < 0 || b - Pb.lo[d] >= pn[d])
+            return "restriction region outside its boxes";
+        }
+        expect += (int64_t)R.n[0] * R.n[1] * R.n[2];
+      }
+      if (expect != L.restr_total) return "restriction count mismatch";
+    }
+    if ((int64_t)L.prefix.back() != L.owned_member) return "canonical prefix mismatch";
+  }
+  return "";
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+void plan_arena(sc_ctx* c) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  int64_t maxowned = 0;
+  for (LevelDev& L : c->lev) {
+    const size_t arr = sizeof(double) * (size_t)c->nvars * (size_t)L.total;
+    for (int i = 0; i < 2; ++i) L.o_y[i] = take(arr);
+    for (int i = 0; i < 4; ++i) L.o_k[i] = take(arr);
+    for (int i = 0; i < L.nyh; ++i) L.o_yh[i] = take(arr);
+    L.o_boxes = take(sizeof(BoxDev) * L.boxes.size());
+    L.o_prefix = take(sizeof(int64_t) * L.prefix.size());
+    L.o_sync = take(sizeof(SyncEntry) * L.sync.size());
+    L.o_prolong = take(sizeof(ProlongEntry) * L.prolong.size());
+    L.o_rblist = take(sizeof(ProlongEntry) * L.rblist.size());
+    L.o_rbfirst = take(sizeof(int64_t) * L.rbfirst.size());
+    L.o_phys = take(sizeof(int64_t) * L.phys.size());
+    L.o_restr = take(sizeof(RestrictRegion) * L.restr.size());
+    L.o_tiles = take(sizeof(TileDev) * L.tiles.size());
+    L.o_btiles = take(sizeof(TileDev) * L.btiles.size());
+    maxowned = std::max(maxowned, std::max(L.owned_member, L.nrb * (int64_t)c->hier.geo.nmembers));
+  }
+  c->stage_elems = std::max<int64_t>(maxowned, 1);
+  c->o_stage = take(sizeof(double) * (size_t)c->stage_elems);
+  c->o_partials = take(sizeof(double) * 3 * 256);
+  c->o_norm_out = take(sizeof(double) * 4);
+  c->arena_bytes = off;
+}
+
+template <class T>
+T* at(sc_ctx* c, size_t o) {
+  return reinterpret_cast<T*>(c->arena + o);
+}
+
+template <class T>
+hipError_t upload(sc_ctx* c, T* dst, const std::vector<T>& v) {
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, c->stream);
+}
+
+// ---------------------------------------------------------------------------
+// Scheduler.
+
+int yh_index(int level, int substep, int stage) { return level == 0 ? 0 : substep * 4 + stage - 1; }
+
+int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const double* yn,
+                           const double* kprev, const double* yh, double* ynew) {
+  LevelDev& L = c->lev[l];
+  StageArgs a{};
+  a.stage = stage;
+  a.boxes = L.d_boxes;
+  a.yn = yn;
+  a.kprev = kprev;
+  a.Yh = yh;
+  a.k1 = L.k[0];
+  a.k2 = L.k[1];
+  a.k3 = L.k[2];
+  a.kout = L.k[stage - 1];
+  a.ynew = ynew;
+  a.vstride = L.total;
+  static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
+  a.cdt = cnext[stage] * L.dt;
+  a.dt6 = L.dt / 6.0;
+  a.clap = 1.0 / (12.0 * L.dx * L.dx);
+  a.cko = c->cfg.ko_sigma / (64.0 * L.dx);
+  a.write_k = 1;
+  if (!per_block) {
+    a.tiles = L.d_tiles;
+    a.ntiles = (int32_t)L.tiles.size();
+    const int grid = std::min<int>(a.ntiles, c->grid_cap);
+    HIPCHK(c, launch_stage(a, grid, true, c->stream));
+    ++c->launches;
+  } else {
+    const int nblk = (int)L.btile_start.size() - 1;
+    for (int b = 0; b < nblk; ++b) {
+      a.tiles = L.d_btiles + L.btile_start[b];
+      a.ntiles = L.btile_start[b + 1] - L.btile_start[b];
+      HIPCHK(c, launch_stage(a, a.ntiles, true, c->stream));
+      ++c->launches;
+    }
+  }
+  return SC_OK;
+}
+
+int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
+  LevelDev& L = c->lev[l];
+  double* yn = L.y[L.cur];
+  double* ynew = L.y[1 - L.cur];
+  for (int s = 1; s <= 4; ++s) {
+    double* yh = L.Yh[yh_index(l, substep, s)];
+    const double* kprev = s == 1 ? nullptr : L.k[s - 2];
+    if (!L.sync.empty()) {
+      SyncArgs sa{};
+      sa.e = L.d_sync;
+      sa.n = (int64_t)L.sync.size();
+      sa.yn = yn;
+      sa.kprev = kprev;
+      sa.out = yh;
+      sa.vstride = L.total;
+      static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
+      sa.cdt = cnext[s] * L.dt;
+      sa.nvars = c->nvars;
+      HIPCHK(c, launch_sync(sa, c->stream));
+      ++c->launches;
+    }
+    int rc = enqueue_stage_launches(c, l, s, per_block, yn, kprev, yh, ynew);
+    if (rc) return rc;
+  }
+  L.cur = 1 - L.cur;
+  return SC_OK;
+}
+
+int prolongate(sc_ctx* c, int fl) {
+  LevelDev& F = c->lev[fl];
+  LevelDev& P = c->lev[fl - 1];
+  if (F.prolong.empty()) return SC_OK;
+  ProlongArgs a{};
+  a.e = F.d_prolong;
+  a.n = (int64_t)F.prolong.size();
+  a.pboxes = P.d_boxes;
+  a.pv[0] = P.y[1 - P.cur];  // y_n of the parent's last step
+  for (int i = 0; i < 4; ++i) a.pv[1 + i] = P.k[i];
+  a.pvstride = P.total;
+  a.ovstride = F.total;
+  a.H = P.dt;
+  a.nout = 8;
+  a.nvars = c->nvars;
+  for (int sub = 0; sub < 2; ++sub)
+    for (int s = 1; s <= 4; ++s) {
+      const int o = sub * 4 + s - 1;
+      a.out[o] = F.Yh[o];
+      for (int i = 0; i < 4; ++i) a.w[o][i] = c->weights[sub][s - 1][i];
+    }
+  HIPCHK(c, launch_prolong(a, c->stream));
+  ++c->launches;
+  return SC_OK;
+}
+
+int restrict_level(sc_ctx* c, int fl) {
+  LevelDev& F = c->lev[fl];
+  LevelDev& P = c->lev[fl - 1];
+  if (F.restr_total == 0) return SC_OK;
+  RestrictArgs a{};
+  a.r = F.d_restr;
+  a.nregions = (int)F.restr.size();
+  a.ntotal = F.restr_total;
+  a.fboxes = F.d_boxes;
+  a.pboxes = P.d_boxes;
+  a.fy = F.y[F.cur];
+  a.py = P.y[P.cur];
+  a.fvstride = F.total;
+  a.pvstride = P.total;
+  a.nvars = c->nvars;
+  HIPCHK(c, launch_restrict(a, c->stream));
+  ++c->launches;
+  return SC_OK;
+}
+
+int advance_level(sc_ctx* c, int l, int substep, bool per_block) {
+  int rc = rk4_step(c, l, substep, per_block);
+  if (rc) return rc;
+  if (l + 1 < (int)c->lev.size()) {
+    if ((rc = prolongate(c, l + 1))) return rc;
+    if ((rc = advance_level(c, l + 1, 0, per_block))) return rc;
+    if ((rc = advance_level(c, l + 1, 1, per_block))) return rc;
+    if ((rc = restrict_level(c, l + 1))) return rc;
+  }
+  c->lev[l].t += c->lev[l].dt;
+  return SC_OK;
+}
+
+int check_ready(const sc_ctx* c, int need) {
+  if (!c) return SC_E_ARG;
+  if (c->state < need) {
+    const_cast<sc_ctx*>(c)->err = "call out of order (state machine)";
+    return SC_E_STATE;
+  }
+  return SC_OK;
+}
+
+double* array_ptr(sc_ctx* c, int l, int array) {
+  LevelDev& L = c->lev[l];
+  switch (array) {
+    case SC_ARR_Y: return L.y[L.cur];
+    case SC_ARR_YN: return L.y[1 - L.cur];
+    default: return L.k[array - 1];
+  }
+}
+
+PackArgs member_pack(sc_ctx* c, int member, int l, double* arr) {
+  LevelDev& L = c->lev[l];
+  PackArgs a{};
+  a.boxes = L.d_boxes + member * L.nb_member;
+  a.prefix = L.d_prefix;
+  a.nboxes = L.nb_member;
+  a.n = L.owned_member;
+  a.arr = arr;
+  a.buf = c->d_stage;
+  return a;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+int sc_config_default(sc_config* cfg) {
+  if (!cfg) return SC_E_ARG;
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->abi_version = SC_ABI_VERSION;
+  cfg->rhs = SC_RHS_WAVE;
+  cfg->precision = SC_FP64;
+  cfg->exec = SC_EXEC_BATCHED;
+  cfg->nghost = 3;
+  cfg->ko_sigma = 0.32;
+  cfg->cfl = 0.25;
+  return SC_OK;
+}
+
+int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
+  if (!cfg || !out) {
+    g_create_error = "null argument";
+    return SC_E_ARG;
+  }
+  *out = nullptr;
+  if (cfg->abi_version != SC_ABI_VERSION) {
+    g_create_error = "abi_version mismatch";
+    return SC_E_ARG;
+  }
+  if (cfg->rhs != SC_RHS_WAVE || cfg->nghost != 3 || !(cfg->cfl > 0.0 && cfg->cfl <= 0.5) ||
+      cfg->ko_sigma < 0.0 || (cfg->precision != SC_FP64) || cfg->exec < 0 || cfg->exec > 2) {
+    g_create_error = "unsupported configuration (rhs, nghost 3, 0 < cfl <= 0.5, sigma >= 0, "
+                     "precision, exec)";
+    return SC_E_ARG;
+  }
+  sc_ctx* c = new sc_ctx();
+  c->cfg = *cfg;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  for (int sub = 0; sub < 2; ++sub)
+    for (int f = 1; f <= 5; ++f) ghost_weights(f, sub ? Rat(1, 2) : Rat(0), c->weights[sub][f - 1]);
+  *out = c;
+  return SC_OK;
+}
+
+int sc_destroy(sc_ctx* c) {
+  if (!c) return SC_OK;
+  for (int i = 0; i < 2; ++i)
+    if (c->graph[i]) (void)hipGraphExecDestroy(c->graph[i]);
+  delete c;
+  return SC_OK;
+}
+
+const char* sc_last_error(const sc_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int sc_build_hierarchy(sc_ctx* c, int32_t nmembers, const double origin[3], double dx0,
+                       const int64_t ncells0[3], const int32_t periodic[3], int32_t nlevels,
+                       const int32_t* nboxes_per_level, const sc_box* boxes, uint64_t block_seed,
+                       int32_t min_block, int32_t max_block) {
+  if (!c) return SC_E_ARG;
+  if (c->state != 0) return fail(c, SC_E_STATE, "hierarchy already built");
+  if (!origin || !ncells0 || !periodic || nlevels < 1 || nmembers < 1 || !(dx0 > 0.0) ||
+      (nlevels > 1 && (!nboxes_per_level || !boxes)))
+    return fail(c, SC_E_ARG, "bad hierarchy arguments");
+  Geometry g;
+  g.nmembers = nmembers;
+  g.dx0 = dx0;
+  g.nlevels = nlevels;
+  for (int d = 0; d < 3; ++d) {
+    g.origin[d] = origin[d];
+    g.ncells0[d] = ncells0[d];
+    g.periodic[d] = periodic[d] != 0;
+    if (ncells0[d] < 1 || ncells0[d] > (int64_t(1) << 20) >> (nlevels - 1))
+      return fail(c, SC_E_ARG, "ncells0 out of range");
+  }
+  int64_t k = 0;
+  for (int l = 1; l < nlevels; ++l) {
+    if (nboxes_per_level[l - 1] < 1) return fail(c, SC_E_ARG, "a fine level needs a box");
+    std::vector<IBox> lv;
+    for (int i = 0; i < nboxes_per_level[l - 1]; ++i, ++k) {
+      IBox b;
+      for (int d = 0; d < 3; ++d) {
+        b.lo[d] = boxes[k].lo[d];
+        b.hi[d] = boxes[k].hi[d];
+      }
+      lv.push_back(b);
+    }
+    g.fine_boxes.push_back(lv);
+  }
+  bool nest = false;
+  std::string e = c->hier.build(g, c->cfg.nghost, block_seed, min_block, max_block, &nest);
+  if (!e.empty()) return fail(c, nest ? SC_E_NEST : SC_E_ARG, e);
+  e = build_layout(c);
+  if (!e.empty()) return fail(c, SC_E_NEST, e);
+  e = validate_layout(c);
+  if (!e.empty()) return fail(c, SC_E_ARG, "internal layout check: " + e);
+  plan_arena(c);
+  c->state = 1;
+  return SC_OK;
+}
+
+int sc_get_counts(const sc_ctx* c, int32_t level, int32_t* nblocks, int64_t* nowned,
+                  int64_t* nrb) {
+  int rc = check_ready(c, 1);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->hier.levels.size()) return SC_E_ARG;
+  const LevelMaps& M = c->hier.levels[level];
+  if (nblocks) *nblocks = (int32_t)M.blocks.size();
+  if (nowned) *nowned = M.nowned;
+  if (nrb) *nrb = (int64_t)M.rb.size();
+  return SC_OK;
+}
+
+int sc_export_maps(const sc_ctx* c, int64_t* words, int64_t* nwords) {
+  int rc = check_ready(c, 1);
+  if (rc) return rc;
+  if (!nwords) return SC_E_ARG;
+  std::vector<int64_t> w;
+  c->hier.export_words(&w);
+  if (!words) {
+    *nwords = (int64_t)w.size();
+    return SC_OK;
+  }
+  if (*nwords < (int64_t)w.size()) {
+    const_cast<sc_ctx*>(c)->err = "export buffer too small";
+    return SC_E_ARG;
+  }
+  std::memcpy(words, w.data(), sizeof(int64_t) * w.size());
+  *nwords = (int64_t)w.size();
+  return SC_OK;
+}
+
+int sc_device_bytes(const sc_ctx* c, size_t* nbytes) {
+  int rc = check_ready(c, 1);
+  if (rc) return rc;
+  if (!nbytes) return SC_E_ARG;
+  *nbytes = c->arena_bytes;
+  return SC_OK;
+}
+
+int sc_bind_device_memory(sc_ctx* c, void* dptr, size_t nbytes) {
+  int rc = check_ready(c, 1);
+  if (rc) return rc;
+  if (!dptr) return fail(c, SC_E_ARG, "null arena");
+  if (nbytes < c->arena_bytes) return fail(c, SC_E_MEM, "arena smaller than sc_device_bytes");
+  if (reinterpret_cast<uintptr_t>(dptr) & 255) return fail(c, SC_E_MEM, "arena not 256-byte aligned");
+  c->arena = static_cast<char*>(dptr);
+  int dev = 0, ncu = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  c->grid_cap = std::max(ncu, 1) * 8;
+  HIPCHK(c, hipMemsetAsync(c->arena, 0, c->arena_bytes, c->stream));
+  for (LevelDev& L : c->lev) {
+    for (int i = 0; i < 2; ++i) L.y[i] = at<double>(c, L.o_y[i]);
+    for (int i = 0; i < 4; ++i) L.k[i] = at<double>(c, L.o_k[i]);
+    for (int i = 0; i < L.nyh; ++i) L.Yh[i] = at<double>(c, L.o_yh[i]);
+    L.d_boxes = at<BoxDev>(c, L.o_boxes);
+    L.d_prefix = at<int64_t>(c, L.o_prefix);
+    L.d_sync = at<SyncEntry>(c, L.o_sync);
+    L.d_prolong = at<ProlongEntry>(c, L.o_prolong);
+    L.d_rblist = at<ProlongEntry>(c, L.o_rblist);
+    L.d_rbfirst = at<int64_t>(c, L.o_rbfirst);
+    L.d_phys = at<int64_t>(c, L.o_phys);
+    L.d_restr = at<RestrictRegion>(c, L.o_restr);
+    L.d_tiles = at<TileDev>(c, L.o_tiles);
+    L.d_btiles = at<TileDev>(c, L.o_btiles);
+    HIPCHK(c, upload(c, L.d_boxes, L.boxes));
+    HIPCHK(c, upload(c, L.d_prefix, L.prefix));
+    HIPCHK(c, upload(c, L.d_sync, L.sync));
+    HIPCHK(c, upload(c, L.d_prolong, L.prolong));
+    HIPCHK(c, upload(c, L.d_rblist, L.rblist));
+    HIPCHK(c, upload(c, L.d_rbfirst, L.rbfirst));
+    HIPCHK(c, upload(c, L.d_phys, L.phys));
+    HIPCHK(c, upload(c, L.d_restr, L.restr));
+    HIPCHK(c, upload(c, L.d_tiles, L.tiles));
+    HIPCHK(c, upload(c, L.d_btiles, L.btiles));
+  }
+  c->d_stage = at<double>(c, c->o_stage);
+  c->d_partials = at<double>(c, c->o_partials);
+  c->d_norm_out = at<double>(c, c->o_norm_out);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->state = 2;
+  return SC_OK;
+}
+
+int sc_set_initial_data(sc_ctx* c, int32_t member, int32_t level, int32_t var,
+                        const double* host, int64_t n) {
+  int rc = check_ready(c, 2);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || member < 0 ||
+      member >= c->hier.geo.nmembers || var < 0 || var >= c->nvars || !host)
+    return fail(c, SC_E_ARG, "bad initial-data arguments");
+  LevelDev& L = c->lev[level];
+  if (n != L.owned_member) return fail(c, SC_E_ARG, "n must equal the level's owned points");
+  HIPCHK(c, hipMemcpyAsync(c->d_stage, host, sizeof(double) * n, hipMemcpyHostToDevice,
+                           c->stream));
+  PackArgs a = member_pack(c, member, level, L.y[L.cur] + var * L.total);
+  HIPCHK(c, launch_pack(a, true, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->state = 3;
+  return SC_OK;
+}
+
+int sc_advance(sc_ctx* c, int32_t ncoarse) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  if (ncoarse < 0) return fail(c, SC_E_ARG, "ncoarse < 0");
+  c->launches = 0;
+  for (int i = 0; i < ncoarse; ++i) {
+    if (c->cfg.exec == SC_EXEC_GRAPH) {
+      const int parity = c->lev[0].cur;
+      if (!c->graph_ready[parity]) {
+        // capture one coarse step starting from this buffer parity
+        std::vector<int> cur0(c->lev.size());
+        std::vector<double> t0(c->lev.size());
+        for (size_t l = 0; l < c->lev.size(); ++l) cur0[l] = c->lev[l].cur, t0[l] = c->lev[l].t;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        rc = advance_level(c, 0, 0, false);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->stream, &g);
+        for (size_t l = 0; l < c->lev.size(); ++l) c->lev[l].cur = cur0[l], c->lev[l].t = t0[l];
+        if (rc) return rc;
+        if (e != hipSuccess) return fail(c, SC_E_HIP, std::string("capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->graph[parity], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess)
+          return fail(c, SC_E_HIP, std::string("instantiate: ") + hipGetErrorString(e));
+        c->graph_ready[parity] = true;
+      }
+      c->launches = 0;
+      HIPCHK(c, hipGraphLaunch(c->graph[parity], c->stream));
+      // replay the host bookkeeping of one coarse step
+      for (size_t l = 0; l < c->lev.size(); ++l) {
+        const int64_t steps = int64_t(1) << l;
+        if (steps & 1) c->lev[l].cur = 1 - c->lev[l].cur;
+        for (int64_t s = 0; s < steps; ++s) c->lev[l].t += c->lev[l].dt;
+      }
+      ++c->launches;
+    } else {
+      rc = advance_level(c, 0, 0, c->cfg.exec == SC_EXEC_PER_BLOCK);
+      if (rc) return rc;
+    }
+  }
+  return SC_OK;
+}
+
+int sc_step_level(sc_ctx* c, int32_t level, int32_t substep) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || substep < 0 || substep > 1)
+    return fail(c, SC_E_ARG, "bad level or substep");
+  rc = rk4_step(c, level, level == 0 ? 0 : substep, c->cfg.exec == SC_EXEC_PER_BLOCK);
+  if (!rc) c->lev[level].t += c->lev[level].dt;
+  return rc;
+}
+
+int sc_prolongate(sc_ctx* c, int32_t fine_level) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  if (fine_level < 1 || fine_level >= (int)c->lev.size()) return fail(c, SC_E_ARG, "bad level");
+  return prolongate(c, fine_level);
+}
+
+int sc_restrict(sc_ctx* c, int32_t fine_level) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  if (fine_level < 1 || fine_level >= (int)c->lev.size()) return fail(c, SC_E_ARG, "bad level");
+  return restrict_level(c, fine_level);
+}
+
+int sc_fill_ghosts(sc_ctx* c, int32_t level, int32_t which, int32_t substep) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || which < 1 || which > 5 || substep < 0 ||
+      substep > 1)
+    return fail(c, SC_E_ARG, "bad fill arguments");
+  LevelDev& L = c->lev[level];
+  double* y = L.y[L.cur];
+  if (!L.sync.empty()) {
+    SyncArgs sa{};
+    sa.e = L.d_sync;
+    sa.n = (int64_t)L.sync.size();
+    sa.yn = y;
+    sa.kprev = nullptr;
+    sa.out = y;
+    sa.vstride = L.total;
+    sa.nvars = c->nvars;
+    HIPCHK(c, launch_sync(sa, c->stream));
+  }
+  if (level > 0 && !L.prolong.empty()) {
+    LevelDev& P = c->lev[level - 1];
+    ProlongArgs a{};
+    a.e = L.d_prolong;
+    a.n = (int64_t)L.prolong.size();
+    a.pboxes = P.d_boxes;
+    a.pv[0] = P.y[1 - P.cur];
+    for (int i = 0; i < 4; ++i) a.pv[1 + i] = P.k[i];
+    a.pvstride = P.total;
+    a.ovstride = L.total;
+    a.H = P.dt;
+    a.nout = 1;
+    a.nvars = c->nvars;
+    a.out[0] = y;
+    for (int i = 0; i < 4; ++i) a.w[0][i] = c->weights[substep][which - 1][i];
+    HIPCHK(c, launch_prolong(a, c->stream));
+  }
+  return SC_OK;
+}
+
+int sc_read_back(sc_ctx* c, int32_t member, int32_t level, int32_t var, int32_t array,
+                 double* host, int64_t n) {
+  int rc = check_ready(c, 2);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || member < 0 ||
+      member >= c->hier.geo.nmembers || var < 0 || var >= c->nvars || array < 0 || array > 5 ||
+      !host)
+    return fail(c, SC_E_ARG, "bad read-back arguments");
+  LevelDev& L = c->lev[level];
+  if (n != L.owned_member) return fail(c, SC_E_ARG, "n must equal the level's owned points");
+  PackArgs a = member_pack(c, member, level, array_ptr(c, level, array) + var * L.total);
+  HIPCHK(c, launch_pack(a, false, c->stream));
+  HIPCHK(c, hipMemcpyAsync(host, c->d_stage, sizeof(double) * n, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SC_OK;
+}
+
+int sc_read_rb(sc_ctx* c, int32_t member, int32_t level, int32_t which, int32_t substep,
+               int32_t var, double* host, int64_t n) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  if (level < 1 || level >= (int)c->lev.size() || member < 0 ||
+      member >= c->hier.geo.nmembers || which < 1 || which > 5 || substep < 0 || substep > 1 ||
+      var < 0 || var >= c->nvars || !host)
+    return fail(c, SC_E_ARG, "bad RB read arguments");
+  LevelDev& L = c->lev[level];
+  if (n != L.nrb) return fail(c, SC_E_ARG, "n must equal the level's RB points");
+  if (which <= 4) {
+    const double* src = L.Yh[substep * 4 + which - 1] + var * L.total;
+    HIPCHK(c, launch_gather(L.d_rbfirst + member * L.nrb, L.nrb, src, c->d_stage, c->stream));
+  } else {
+    LevelDev& P = c->lev[level - 1];
+    ProlongArgs a{};
+    a.e = L.d_rblist + member * L.nrb;
+    a.n = L.nrb;
+    a.pboxes = P.d_boxes;
+    a.pv[0] = P.y[1 - P.cur];
+    for (int i = 0; i < 4; ++i) a.pv[1 + i] = P.k[i];
+    a.pvstride = P.total;
+    a.ovstride = 0;
+    a.H = P.dt;
+    a.nout = 1;
+    a.nvars = 1;
+    a.out[0] = c->d_stage;
+    for (int i = 0; i < 4; ++i) a.w[0][i] = c->weights[substep][4][i];
+    for (int m = 0; m < 5; ++m) a.pv[m] = a.pv[m] + var * P.total;
+    HIPCHK(c, launch_prolong(a, c->stream));
+  }
+  HIPCHK(c, hipMemcpyAsync(host, c->d_stage, sizeof(double) * n, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SC_OK;
+}
+
+int sc_norms(sc_ctx* c, int32_t member, int32_t level, int32_t var, int32_t array,
+             double out[3]) {
+  int rc = check_ready(c, 2);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || member < 0 ||
+      member >= c->hier.geo.nmembers || var < 0 || var >= c->nvars || array < 0 || array > 5 ||
+      !out)
+    return fail(c, SC_E_ARG, "bad norm arguments");
+  LevelDev& L = c->lev[level];
+  PackArgs a = member_pack(c, member, level, array_ptr(c, level, array) + var * L.total);
+  HIPCHK(c, launch_norms(a, c->d_partials, 256, c->d_norm_out, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out, c->d_norm_out, sizeof(double) * 3, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SC_OK;
+}
+
+int sc_check_finite(sc_ctx* c) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  for (int l = 0; l < (int)c->lev.size(); ++l)
+    for (int m = 0; m < c->hier.geo.nmembers; ++m)
+      for (int v = 0; v < c->nvars; ++v) {
+        double o[3];
+        if ((rc = sc_norms(c, m, l, v, SC_ARR_Y, o))) return rc;
+        if (o[2] > 0) {
+          char msg[128];
+          snprintf(msg, sizeof msg, "non-finite values on level %d member %d var %d", l, m, v);
+          return fail(c, SC_E_NONFINITE, msg);
+        }
+      }
+  return SC_OK;
+}
+
+int sc_level_time(const sc_ctx* c, int32_t level, double* t) {
+  int rc = check_ready(c, 1);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || !t) return SC_E_ARG;
+  *t = c->lev[level].t;
+  return SC_OK;
+}
+
+int sc_set_exec(sc_ctx* c, int32_t exec) {
+  if (!c) return SC_E_ARG;
+  if (exec < 0 || exec > 2) return fail(c, SC_E_ARG, "bad exec mode");
+  c->cfg.exec = exec;
+  return SC_OK;
+}
+
+int sc_poison_halos(sc_ctx* c) {
+  int rc = check_ready(c, 2);
+  if (rc) return rc;
+  const double nan = std::nan("");
+  for (LevelDev& L : c->lev) {
+    if (!L.phys.empty()) return fail(c, SC_E_STATE, "poisoning would erase physical ghosts");
+    for (int i = 0; i < L.nyh; ++i)
+      HIPCHK(c, launch_fill(L.Yh[i], c->nvars * L.total, nan, c->stream));
+    for (int i = 0; i < 4; ++i) HIPCHK(c, launch_fill(L.k[i], c->nvars * L.total, nan, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SC_OK;
+}
+
+int sc_stats(const sc_ctx* c, int64_t* updates_per_coarse_step, int64_t* launches) {
+  int rc = check_ready(c, 1);
+  if (rc) return rc;
+  if (updates_per_coarse_step)
+    *updates_per_coarse_step = c->hier.updates_per_coarse_step() * c->hier.geo.nmembers;
+  if (launches) *launches = c->launches;
+  return SC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// Device-side tables and kernel entry points.
+//
+// Storage on the GPU: every box of a level (for every ensemble member) is
+// one padded array per variable, owned points plus G = 3 halo layers per
+// side, x fastest, row pitch px = nx + 6, plane pitch px * (ny + 6).  The
+// blocks of a box are index ranges of that array, so a ghost point shared
+// between two blocks of the same box is simply the neighbour's owned point:
+// on one GPU the block-boundary exchange costs nothing.  Only the box halo
+// is ever written by a ghost fill.
+//
+// Per level and variable the arrays are: the state y (two buffers, swapped
+// every step), the slopes k1..k4, and the halo tables Yh: one per (substep,
+// stage) on refinement levels (8), holding the stage ghost values produced
+// by prolongation, and one on level 0 for the periodic/intra-level copies.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sc {
+
+constexpr int kG = 3;
+
+struct BoxDev {
+  int64_t base;         // offset of the padded array within the level arrays
+  int32_t nx, ny, nz;   // owned extents
+  int32_t px, py;       // padded row and plane pitches (nx + 6, ny + 6)
+  int32_t lo[3];        // global index of owned point (0,0,0)
+  int32_t wrapN[3];     // >0: this box spans a periodic dimension of N points
+  int32_t pad;
+};
+
+struct TileDev {
+  int32_t box;
+  int32_t x0, y0, z0;   // box-local owned coordinates of the tile origin
+  int32_t nx, ny, nz;
+  int32_t pad;
+};
+
+struct SyncEntry {      // halo point <- owned point of the same level
+  int64_t dst, src;     // offsets within the level arrays
+};
+
+struct ProlongEntry {   // refinement-boundary halo point
+  int64_t dst;          // offset within the fine level arrays (or output index)
+  int32_t q[3];         // global fine index (wrapped)
+  int32_t pbox;         // parent box holding the whole prolongation stencil
+};
+
+struct RestrictRegion {
+  int32_t fbox, pbox;
+  int32_t c0[3];        // first parent index (global)
+  int32_t n[3];         // parent points per dimension
+  int64_t start;        // prefix count of parent points before this region
+};
+
+constexpr int kMaxOut = 8;
+
+struct StageArgs {
+  const TileDev* tiles;
+  int32_t ntiles;
+  int32_t stage;
+  const BoxDev* boxes;
+  const double* yn;
+  const double* kprev;
+  const double* Yh;
+  const double* k1;
+  const double* k2;
+  const double* k3;
+  double* kout;
+  double* ynew;
+  int64_t vstride;
+  double cdt;    // c_s * dt: interior stage vector Y = y_n + cdt * k_{s-1}
+  double dt6;    // dt / 6
+  double clap;   // 1 / (12 h^2)
+  double cko;    // sigma / (64 h)
+  int32_t write_k;
+};
+
+struct SyncArgs {
+  const SyncEntry* e;
+  int64_t n;
+  const double* yn;
+  const double* kprev;   // null: copy y_n
+  double* out;
+  int64_t vstride;
+  double cdt;
+  int32_t nvars;
+};
+
+struct ProlongArgs {
+  const ProlongEntry* e;
+  int64_t n;
+  const BoxDev* pboxes;          // parent level boxes
+  const double* pv[5];           // parent y_n, k1..k4
+  int64_t pvstride;
+  double* out[kMaxOut];          // outputs, one per combination
+  int64_t ovstride;
+  double w[kMaxOut][4];          // dense-output weights per combination
+  double H;                      // parent time step
+  int32_t nout;
+  int32_t nvars;
+};
+
+struct RestrictArgs {
+  const RestrictRegion* r;
+  int32_t nregions;
+  int64_t ntotal;
+  const BoxDev* fboxes;
+  const BoxDev* pboxes;
+  const double* fy;
+  double* py;
+  int64_t fvstride, pvstride;
+  int32_t nvars;
+};
+
+struct PackArgs {
+  const BoxDev* boxes;    // boxes of one member of one level
+  const int64_t* prefix;  // nboxes + 1 canonical prefix counts (device)
+  int32_t nboxes;
+  int64_t n;
+  double* arr;            // level array of the variable (already offset by var)
+  double* buf;            // canonical buffer
+};
+
+// launchers (kernels.hip)
+hipError_t launch_stage(const StageArgs& a, int grid, bool write_k, hipStream_t s);
+hipError_t launch_sync(const SyncArgs& a, hipStream_t s);
+hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s);
+hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
+hipError_t launch_pack(const PackArgs& a, bool unpack, hipStream_t s);
+hipError_t launch_norms(const PackArgs& a, double* partials, int nparts, double* out,
+                        hipStream_t s);
+hipError_t launch_gather(const int64_t* idx, int64_t n, const double* src, double* dst,
+                         hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+
+constexpr int kStageThreads = 256;
+constexpr int kTileMaxX = 64;
+constexpr int kTileMaxY = 8;
+
+}  // namespace sc

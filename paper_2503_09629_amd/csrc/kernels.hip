@@ -1,0 +1,386 @@
+// HIP kernels for gfx950: wave RHS + RK4 stage update, halo copies,
+// five-vector prolongation with dense-output stage values, restriction,
+// canonical pack/unpack and deterministic norms.
+//
+// Every floating-point expression is written in one fixed evaluation order
+// and the file is compiled without FP contraction, so each value is the
+// correctly rounded result of the stated sequence of operations.
+#include "device.hpp"
+
+namespace sc {
+namespace {
+
+__device__ __forceinline__ double d2(double m2, double m1, double c, double p1, double p2) {
+  // fourth-order centred second difference, without the 1/(12 h^2) factor
+  return (((-m2 + 16.0 * m1) - 30.0 * c) + 16.0 * p1) - p2;
+}
+
+__device__ __forceinline__ double ko7(double m3, double m2, double m1, double c, double p1,
+                                      double p2, double p3) {
+  // sixth difference: h^6 D+^3 D-^3 u, the r = 4 Kreiss-Oliger stencil (Sec. III.C)
+  return (((((m3 - 6.0 * m2) + 15.0 * m1) - 20.0 * c) + 15.0 * p1) - 6.0 * p2) + p3;
+}
+
+__device__ __forceinline__ int64_t padded_offset(const BoxDev& B, int x, int y, int z) {
+  return B.base + ((int64_t)(z + kG) * B.py + (y + kG)) * (int64_t)B.px + (x + kG);
+}
+
+// Stage vector at box-local (x, y, z): owned points are formed on the fly as
+// y_n + (c_s dt) k_{s-1} (Y1 = y_n); halo points come from the halo table.
+template <int STAGE>
+__device__ __forceinline__ double stage_value(const StageArgs& a, const BoxDev& B, int x, int y,
+                                              int z, int v) {
+  const int64_t o = padded_offset(B, x, y, z) + v * a.vstride;
+  const bool in = (unsigned)x < (unsigned)B.nx && (unsigned)y < (unsigned)B.ny &&
+                  (unsigned)z < (unsigned)B.nz;
+  if (in) {
+    if constexpr (STAGE == 1) {
+      return a.yn[o];
+    } else {
+      return a.yn[o] + a.cdt * a.kprev[o];
+    }
+  }
+  return a.Yh[o];
+}
+
+// One RK4 stage of the scalar wave on a list of tiles (persistent: workgroups
+// stride over the tile list).  A tile is up to 64 x 8 points in x-y marching
+// through nz planes.  The x-y plane of stage values (tile plus 3-point ring)
+// is staged in LDS (double buffered); each thread keeps the 7-plane z column
+// of its two points in registers.
+//   k_u  = Pi + Q u,   k_Pi = Lap u + Q Pi
+//   Lap  = ((d2_x + d2_y) + d2_z) / (12 h^2),  Q = sigma/(64 h) ((ko_x + ko_y) + ko_z)
+// Stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4).
+template <int STAGE>
+__global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
+  constexpr int BX = kTileMaxX, BY = kStageThreads / kTileMaxX, RY = kTileMaxY / BY;
+  constexpr int LX = BX + 2 * kG, LY = kTileMaxY + 2 * kG;
+  __shared__ double lds[2][2][LY][LX];
+  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    const TileDev T = a.tiles[t];
+    const BoxDev B = a.boxes[T.box];
+    const int x = T.x0 + tx;
+    int yy[RY];
+    bool act[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      yy[r] = T.y0 + ty + r * BY;
+      act[r] = tx < T.nx && (ty + r * BY) < T.ny;
+    }
+    double q[2][RY][7];
+#pragma unroll
+    for (int j = 0; j < 6; ++j)
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+          q[v][r][j] = act[r] ? stage_value<STAGE>(a, B, x, yy[r], T.z0 - kG + j, v) : 0.0;
+    const int wx = T.nx + 2 * kG, wy = T.ny + 2 * kG;
+    for (int iz = 0; iz < T.nz; ++iz) {
+      const int z = T.z0 + iz;
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+          q[v][r][6] = act[r] ? stage_value<STAGE>(a, B, x, yy[r], z + kG, v) : 0.0;
+      double(*L)[LY][LX] = lds[iz & 1];
+      for (int i = threadIdx.x; i < wx * wy; i += kStageThreads) {
+        const int ly = i / wx, lx = i - ly * wx;
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+          L[v][ly][lx] = stage_value<STAGE>(a, B, T.x0 - kG + lx, T.y0 - kG + ly, z, v);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        if (act[r]) {
+          const int lx = tx + kG, ly = ty + r * BY + kG;
+          const double cu = q[0][r][3], cp = q[1][r][3];
+          const double lapx = d2(L[0][ly][lx - 2], L[0][ly][lx - 1], cu, L[0][ly][lx + 1],
+                                 L[0][ly][lx + 2]);
+          const double lapy = d2(L[0][ly - 2][lx], L[0][ly - 1][lx], cu, L[0][ly + 1][lx],
+                                 L[0][ly + 2][lx]);
+          const double lapz = d2(q[0][r][1], q[0][r][2], cu, q[0][r][4], q[0][r][5]);
+          const double lap = ((lapx + lapy) + lapz) * a.clap;
+          double Q[2];
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            const double c = q[v][r][3];
+            const double kx = ko7(L[v][ly][lx - 3], L[v][ly][lx - 2], L[v][ly][lx - 1], c,
+                                  L[v][ly][lx + 1], L[v][ly][lx + 2], L[v][ly][lx + 3]);
+            const double ky = ko7(L[v][ly - 3][lx], L[v][ly - 2][lx], L[v][ly - 1][lx], c,
+                                  L[v][ly + 1][lx], L[v][ly + 2][lx], L[v][ly + 3][lx]);
+            const double kz = ko7(q[v][r][0], q[v][r][1], q[v][r][2], c, q[v][r][4],
+                                  q[v][r][5], q[v][r][6]);
+            Q[v] = a.cko * ((kx + ky) + kz);
+          }
+          const double ku = cp + Q[0];
+          const double kp = lap + Q[1];
+          const int64_t o = padded_offset(B, x, yy[r], z);
+          if (a.write_k) {
+            a.kout[o] = ku;
+            a.kout[o + a.vstride] = kp;
+          }
+          if constexpr (STAGE == 4) {
+            const double su = ((a.k1[o] + 2.0 * a.k2[o]) + 2.0 * a.k3[o]) + ku;
+            a.ynew[o] = a.yn[o] + a.dt6 * su;
+            const int64_t o1 = o + a.vstride;
+            const double sp = ((a.k1[o1] + 2.0 * a.k2[o1]) + 2.0 * a.k3[o1]) + kp;
+            a.ynew[o1] = a.yn[o1] + a.dt6 * sp;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) q[v][r][j] = q[v][r][j + 1];
+    }
+    __syncthreads();
+  }
+}
+
+// Halo copy from an owned point of the same level: the stage vector there
+// (y_n + cdt k_{s-1}, or y_n), or the state for an end-of-step fill.
+__global__ __launch_bounds__(256) void k_sync(SyncArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const SyncEntry e = a.e[i];
+  for (int v = 0; v < a.nvars; ++v) {
+    const int64_t s = e.src + v * a.vstride;
+    const double val = a.kprev ? a.yn[s] + a.cdt * a.kprev[s] : a.yn[s];
+    a.out[e.dst + v * a.vstride] = val;
+  }
+}
+
+// Prolongation of the parent's (y_n, k1..k4) to one refinement-boundary
+// point, x first, then y, then z, with the degree-5 Lagrange midpoint
+// weights at odd fine indices and a copy at even ones; then each requested
+// dense-output combination  P[y_n] + H (((w1 P[k1] + w2 P[k2]) + w3 P[k3]) + w4 P[k4]).
+__global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const ProlongEntry e = a.e[i];
+  const BoxDev P = a.pboxes[e.pbox];
+  constexpr double W[6] = {3.0 / 256.0, -25.0 / 256.0, 150.0 / 256.0,
+                           150.0 / 256.0, -25.0 / 256.0, 3.0 / 256.0};
+  int ns[3];
+  int64_t off[3][6];
+  const int64_t pitch[3] = {1, (int64_t)P.px, (int64_t)P.px * P.py};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int qd = e.q[d];
+    const int odd = qd & 1;
+    const int base = qd >> 1;
+    ns[d] = odd ? 6 : 1;
+    for (int j = 0; j < 6; ++j) {
+      int I = odd ? base - 2 + j : base;
+      if (P.wrapN[d] > 0) I = ((I % P.wrapN[d]) + P.wrapN[d]) % P.wrapN[d];
+      off[d][j] = (int64_t)(I - P.lo[d] + kG) * pitch[d];
+    }
+  }
+  for (int v = 0; v < a.nvars; ++v) {
+    double Pv[5];
+    for (int m = 0; m < 5; ++m) {
+      const double* A = a.pv[m] + P.base + v * a.pvstride;
+      double pz = 0.0;
+      for (int jz = 0; jz < ns[2]; ++jz) {
+        double py = 0.0;
+        for (int jy = 0; jy < ns[1]; ++jy) {
+          const double* row = A + off[2][jz] + off[1][jy];
+          double px;
+          if (ns[0] == 6) {
+            px = W[0] * row[off[0][0]];
+#pragma unroll
+            for (int jx = 1; jx < 6; ++jx) px = px + W[jx] * row[off[0][jx]];
+          } else {
+            px = row[off[0][0]];
+          }
+          if (ns[1] == 6) py = (jy == 0) ? W[0] * px : py + W[jy] * px;
+          else py = px;
+        }
+        if (ns[2] == 6) pz = (jz == 0) ? W[0] * py : pz + W[jz] * py;
+        else pz = py;
+      }
+      Pv[m] = pz;
+    }
+    for (int o = 0; o < a.nout; ++o) {
+      const double s =
+          ((a.w[o][0] * Pv[1] + a.w[o][1] * Pv[2]) + a.w[o][2] * Pv[3]) + a.w[o][3] * Pv[4];
+      a.out[o][e.dst + v * a.ovstride] = Pv[0] + a.H * s;
+    }
+  }
+}
+
+// Injection y_parent(I) <- y_fine(2I) over (fine box, parent box) regions.
+__global__ __launch_bounds__(256) void k_restrict(RestrictArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.ntotal) return;
+  int r = 0;
+  while (r + 1 < a.nregions && a.r[r + 1].start <= i) ++r;
+  const RestrictRegion R = a.r[r];
+  const int64_t l = i - R.start;
+  const int cx = R.c0[0] + (int)(l % R.n[0]);
+  const int cy = R.c0[1] + (int)((l / R.n[0]) % R.n[1]);
+  const int cz = R.c0[2] + (int)(l / ((int64_t)R.n[0] * R.n[1]));
+  const BoxDev F = a.fboxes[R.fbox];
+  const BoxDev P = a.pboxes[R.pbox];
+  const int64_t fo = padded_offset(F, 2 * cx - F.lo[0], 2 * cy - F.lo[1], 2 * cz - F.lo[2]);
+  const int64_t po = padded_offset(P, cx - P.lo[0], cy - P.lo[1], cz - P.lo[2]);
+  for (int v = 0; v < a.nvars; ++v) a.py[po + v * a.pvstride] = a.fy[fo + v * a.fvstride];
+}
+
+__device__ __forceinline__ int64_t canonical_to_offset(const PackArgs& a, int64_t i) {
+  int b = 0;
+  while (b + 1 < a.nboxes && a.prefix[b + 1] <= i) ++b;
+  const BoxDev B = a.boxes[b];
+  const int64_t l = i - a.prefix[b];
+  const int x = (int)(l % B.nx);
+  const int y = (int)((l / B.nx) % B.ny);
+  const int z = (int)(l / ((int64_t)B.nx * B.ny));
+  return padded_offset(B, x, y, z);
+}
+
+__global__ __launch_bounds__(256) void k_pack(PackArgs a, int unpack) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t o = canonical_to_offset(a, i);
+  if (unpack) a.arr[o] = a.buf[i];
+  else a.buf[i] = a.arr[o];
+}
+
+// Deterministic norms: fixed grid, fixed per-thread stride, fixed tree order.
+__global__ __launch_bounds__(256) void k_norms_partial(PackArgs a, double* partials) {
+  __shared__ double smax[256], ssum[256], sbad[256];
+  double m = 0.0, s = 0.0, bad = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = a.arr[canonical_to_offset(a, i)];
+    if (!isfinite(v)) {
+      bad += 1.0;
+    } else {
+      m = fmax(m, fabs(v));
+      s += v * v;
+    }
+  }
+  smax[threadIdx.x] = m;
+  ssum[threadIdx.x] = s;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+      ssum[threadIdx.x] += ssum[threadIdx.x + w];
+      sbad[threadIdx.x] += sbad[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x + 0] = smax[0];
+    partials[3 * blockIdx.x + 1] = ssum[0];
+    partials[3 * blockIdx.x + 2] = sbad[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_norms_final(const double* partials, int nparts,
+                                                     int64_t n, double* out) {
+  __shared__ double smax[256], ssum[256], sbad[256];
+  double m = 0.0, s = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+    m = fmax(m, partials[3 * i]);
+    s += partials[3 * i + 1];
+    bad += partials[3 * i + 2];
+  }
+  smax[threadIdx.x] = m;
+  ssum[threadIdx.x] = s;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+      ssum[threadIdx.x] += ssum[threadIdx.x + w];
+      sbad[threadIdx.x] += sbad[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = smax[0];
+    out[1] = n > 0 ? sqrt(ssum[0] / (double)n) : 0.0;
+    out[2] = sbad[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gather(const int64_t* idx, int64_t n, const double* src,
+                                                double* dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+__global__ __launch_bounds__(256) void k_fill(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_stage(const StageArgs& a, int grid, bool /*write_k*/, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  const dim3 g(grid > 0 ? grid : a.ntiles), b(kStageThreads);
+  switch (a.stage) {
+    case 1: hipLaunchKernelGGL(k_wave_stage<1>, g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_wave_stage<2>, g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_wave_stage<3>, g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL(k_wave_stage<4>, g, b, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sync(const SyncArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sync, dim3(blocks_for(a.n)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prolong, dim3(blocks_for(a.n)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s) {
+  if (a.ntotal <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_restrict, dim3(blocks_for(a.ntotal)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const PackArgs& a, bool unpack, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack, dim3(blocks_for(a.n)), dim3(256), 0, s, a, unpack ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_norms(const PackArgs& a, double* partials, int nparts, double* out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_norms_partial, dim3(nparts), dim3(256), 0, s, a, partials);
+  hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(256), 0, s, partials, nparts, a.n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const int64_t* idx, int64_t n, const double* src, double* dst,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n)), dim3(256), 0, s, idx, n, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace sc

@@ -1,0 +1,83 @@
+// Context state: device layout of the hierarchy, arena plan and scheduler.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/subcyc.h"
+#include "device.hpp"
+#include "hierarchy.hpp"
+
+namespace sc {
+
+struct TileShape {
+  int tx = kTileMaxX, ty = kTileMaxY, tz = 16;
+};
+
+struct LevelDev {
+  int nb_member = 0;                 // boxes per member
+  int64_t member_total = 0;          // padded points per member
+  int64_t total = 0;                 // padded points, all members (variable stride)
+  int64_t owned_member = 0;          // owned points per member
+  int64_t nrb = 0;                   // distinct RB points per member
+  std::vector<BoxDev> boxes;         // all members
+  std::vector<int64_t> prefix;       // canonical prefix per member box (nb_member + 1)
+  std::vector<SyncEntry> sync;
+  std::vector<ProlongEntry> prolong; // RB halo slots
+  std::vector<ProlongEntry> rblist;  // RB list entries of every member, dst = list index j
+  std::vector<int64_t> rbfirst;      // halo offset of the first slot of each RB list entry
+  std::vector<int64_t> phys;
+  std::vector<RestrictRegion> restr;
+  int64_t restr_total = 0;
+  std::vector<TileDev> tiles;        // batched: tiles over the boxes
+  std::vector<TileDev> btiles;       // per block: tiles clipped to blocks
+  std::vector<int32_t> btile_start;  // nblocks (all members) + 1
+  TileShape shape;
+  int nyh = 1;
+  bool has_child = false;
+  // arena offsets (bytes)
+  size_t o_y[2], o_k[4], o_yh[8], o_boxes, o_prefix, o_sync, o_prolong, o_rblist, o_rbfirst,
+      o_phys, o_restr, o_tiles, o_btiles;
+  // device pointers after binding
+  double *y[2] = {nullptr, nullptr}, *k[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* Yh[8] = {nullptr};
+  BoxDev* d_boxes = nullptr;
+  int64_t* d_prefix = nullptr;
+  SyncEntry* d_sync = nullptr;
+  ProlongEntry* d_prolong = nullptr;
+  ProlongEntry* d_rblist = nullptr;
+  int64_t* d_rbfirst = nullptr;
+  int64_t* d_phys = nullptr;
+  RestrictRegion* d_restr = nullptr;
+  TileDev* d_tiles = nullptr;
+  TileDev* d_btiles = nullptr;
+  int cur = 0;
+  double t = 0.0;
+  double dx = 0.0, dt = 0.0;
+};
+
+}  // namespace sc
+
+struct sc_ctx {
+  sc_config cfg{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  int state = 0;  // 0 created, 1 built, 2 bound, 3 ready
+  sc::Hierarchy hier;
+  std::vector<sc::LevelDev> lev;
+  int nvars = 2;
+  size_t arena_bytes = 0;
+  size_t o_stage = 0, o_partials = 0, o_norm_out = 0;
+  int64_t stage_elems = 0;
+  char* arena = nullptr;
+  double* d_stage = nullptr;
+  double* d_partials = nullptr;
+  double* d_norm_out = nullptr;
+  int grid_cap = 0;  // persistent grid size cap for stage kernels
+  int64_t launches = 0;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  bool graph_ready[2] = {false, false};
+  double weights[2][5][4];  // [substep][fill-1][i]
+};

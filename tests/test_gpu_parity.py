@@ -1,0 +1,185 @@
+"""GPU parity: libsubcyc (HIP, gfx950) against the CPU reference.
+
+FP64 fields must agree within 1e-12 relative max-norm per variable per level
+(normalised by the reference's max |value|); the kernels evaluate every
+expression in the same order as the reference without FP contraction, so the
+observed difference is expected to be exactly zero, and the tests report it.
+"""
+import numpy as np
+import pytest
+
+import paper_2503_09629_amd as sc
+from oracle.evolve import OracleRun
+from oracle.hierarchy import Hierarchy
+from workloads import (HierarchySpec, config_c1, config_c2, config_c3, ensemble_c1,
+                       ensemble_on_spec, gaussian_on_spec, pulses_on_spec, standing_wave_on_spec)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _gpu(spec, exec=sc.SC_EXEC_BATCHED, sigma=0.32, **kw):
+    ctx = sc.Context(device="cuda:0", exec=exec, sigma=sigma)
+    ctx.build_spec(spec, **kw)
+    ctx.bind()
+    return ctx
+
+
+def _pair(spec, data_fn, sigma=0.32, exec=sc.SC_EXEC_BATCHED, **kw):
+    ctx = _gpu(spec, exec=exec, sigma=sigma, **kw)
+    ref = OracleRun(Hierarchy(spec, **kw), sigma=sigma)
+    for l in range(spec.nlevels):
+        for v, f in enumerate(data_fn(spec, l)):
+            ctx.set_initial_data(0, l, v, f)
+            ref.set_data(l, v, f)
+    return ctx, ref
+
+
+def _rel(a, b):
+    s = np.abs(b).max()
+    return np.abs(a - b).max() / (s if s > 0 else 1.0)
+
+
+def _compare_all(ctx, ref, arrays=("y",)):
+    worst = 0.0
+    amap = {"y": sc.SC_ARR_Y, "yn": sc.SC_ARR_YN, "k1": sc.SC_ARR_K1, "k2": sc.SC_ARR_K2,
+            "k3": sc.SC_ARR_K3, "k4": sc.SC_ARR_K4}
+    for l in range(ref.L):
+        for v in range(2):
+            for arr in arrays:
+                e = _rel(ctx.read_back(0, l, v, amap[arr]), ref.get(l, v, arr))
+                assert e <= TOL, (l, v, arr, e)
+                worst = max(worst, e)
+    return worst
+
+
+@pytest.mark.parametrize("max_block", [48, 16])
+def test_c1_single_level(max_block):
+    spec = config_c1(32)
+    ctx, ref = _pair(spec, lambda s, l: standing_wave_on_spec(s, l), min_block=8,
+                     max_block=max_block)
+    ctx.advance(16)
+    ref.advance(16)
+    w = _compare_all(ctx, ref, arrays=("y", "yn", "k1", "k2", "k3", "k4"))
+    print("c1 worst rel diff", w)
+    assert abs(ctx.level_time(0) - ref.t[0]) < 1e-15
+
+
+def test_c2_two_level_fields_and_slopes():
+    spec = config_c2(16)
+    ctx, ref = _pair(spec, gaussian_on_spec, min_block=4, max_block=9)
+    ctx.advance(3)
+    ref.advance(3)
+    w = _compare_all(ctx, ref, arrays=("y", "yn", "k1", "k2", "k3", "k4"))
+    print("c2 worst rel diff", w)
+
+
+def test_rb_ghost_values_match_reference():
+    spec = config_c2(16)
+    ctx, ref = _pair(spec, gaussian_on_spec, min_block=4, max_block=9)
+    ctx.advance(1)
+    ref.advance(1)
+    # one more parent step plus its prolongation, driven piece by piece
+    ctx.step_level(0)
+    ctx.prolongate(1)
+    ref.rk4_step(0)
+    ref.prolongate(1)
+    for sub, th in ((0, 0.0), (1, 0.5)):
+        ref.theta0[1] = th
+        for which in (1, 2, 3, 4, 5):
+            want = ref.rb_values(1, which)
+            for v in range(2):
+                got = ctx.read_rb(0, 1, which, sub, v)
+                e = _rel(got, want[v])
+                assert e <= TOL, (sub, which, v, e)
+
+
+def test_three_level_two_boxes():
+    spec = HierarchySpec((-1.0,) * 3, 2.0 / 12, (12, 12, 12), (True,) * 3,
+                         [[((4, 4, 4), (22, 22, 22))],
+                          [((16, 16, 16), (24, 26, 24)), ((28, 16, 18), (36, 24, 26))]])
+    ctx, ref = _pair(spec, lambda s, l: gaussian_on_spec(s, l, centre=(0.1, -0.05, 0.0),
+                                                         width=0.3),
+                     min_block=4, max_block=8, block_seed=9)
+    ctx.advance(2)
+    ref.advance(2)
+    _compare_all(ctx, ref, arrays=("y", "k2"))
+
+
+def test_c3_family_small():
+    spec = config_c3(64, nlev=4)
+    ctx, ref = _pair(spec, lambda s, l: pulses_on_spec(s, l))
+    ctx.advance(1)
+    ref.advance(1)
+    w = _compare_all(ctx, ref, arrays=("y", "k4"))
+    print("c3(64, 4 levels) worst rel diff", w)
+
+
+def test_exec_modes_bitwise_equal():
+    spec = config_c3(64, nlev=3)
+    outs = []
+    for mode in (sc.SC_EXEC_BATCHED, sc.SC_EXEC_PER_BLOCK, sc.SC_EXEC_GRAPH):
+        ctx = _gpu(spec, exec=mode)
+        for l in range(spec.nlevels):
+            for v, f in enumerate(pulses_on_spec(spec, l)):
+                ctx.set_initial_data(0, l, v, f)
+        ctx.advance(3)     # graph mode: captures both buffer parities and replays
+        outs.append([ctx.read_back(0, l, v) for l in range(spec.nlevels) for v in range(2)])
+        assert abs(ctx.level_time(2) - 3 * 4 * 0.25 * spec.dx(2)) < 1e-12
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
+
+
+def test_nan_poisoned_halos_are_never_read():
+    spec = config_c2(16)
+    clean = _gpu(spec, min_block=4, max_block=9)
+    dirty = _gpu(spec, min_block=4, max_block=9)
+    dirty.poison_halos()
+    for ctx in (clean, dirty):
+        for l in range(2):
+            for v, f in enumerate(gaussian_on_spec(spec, l)):
+                ctx.set_initial_data(0, l, v, f)
+        ctx.advance(2)
+    assert dirty.check_finite() == sc.SC_OK
+    for l in range(2):
+        for v in range(2):
+            assert np.array_equal(clean.read_back(0, l, v), dirty.read_back(0, l, v))
+
+
+def test_ensemble_members_match_their_own_reference():
+    nm = 6
+    spec = ensemble_c1(nm, 16)
+    ctx = _gpu(spec, min_block=8, max_block=16)
+    data = ensemble_on_spec(spec, nm)
+    for m in range(nm):
+        for v in range(2):
+            ctx.set_initial_data(m, 0, v, data[m][v])
+    ctx.advance(8)
+    single = config_c1(16)
+    for m in (0, 3, nm - 1):
+        ref = OracleRun(Hierarchy(single, min_block=8, max_block=16))
+        for v in range(2):
+            ref.set_data(0, v, data[m][v])
+        ref.advance(8)
+        for v in range(2):
+            assert _rel(ctx.read_back(m, 0, v), ref.get(0, v)) <= TOL
+
+
+def test_norms_and_nonfinite_flag():
+    spec = config_c2(16)
+    ctx, ref = _pair(spec, gaussian_on_spec, min_block=4, max_block=9)
+    ctx.advance(1)
+    ref.advance(1)
+    for l in range(2):
+        u = ref.get(l, 0)
+        n = ctx.norms(0, l, 0)
+        assert abs(n[0] - np.abs(u).max()) <= 1e-15 * np.abs(u).max()
+        assert abs(n[1] - np.sqrt(np.mean(u * u))) <= 1e-13 * n[1]
+        assert n[2] == 0
+    assert ctx.check_finite() == sc.SC_OK
+    bad = gaussian_on_spec(spec, 1)[0]
+    bad[17] = np.nan
+    ctx.set_initial_data(0, 1, 0, bad)
+    assert ctx.check_finite() == sc.SC_E_NONFINITE
+    assert ctx.norms(0, 1, 0)[2] == 1

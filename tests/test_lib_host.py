@@ -1,0 +1,128 @@
+"""Host-side checks of libsubcyc.so (no GPU needed).
+
+* every function declared in include/subcyc.h is exported;
+* the library's block, ghost, RB and restriction maps are bit-identical to
+  the reference builder's (canonical word stream);
+* argument, nesting and state-machine errors come back as status codes.
+"""
+import ctypes
+import hashlib
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2503_09629_amd as sc
+from oracle.hierarchy import Hierarchy, NestingError
+from workloads import HierarchySpec, config_c2, config_c3, config_c5
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "subcyc.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(sc_\w+)\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 20
+    L = sc.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(names) == sorted(sc.binding.EXPORTED)
+
+
+def _ctx_maps(spec, **kw):
+    ctx = sc.Context()
+    ctx.build_spec(spec, **kw)
+    return ctx
+
+
+SPECS = {
+    "two-level-tiny": (HierarchySpec((-1.0,) * 3, 2.0 / 12, (12, 12, 12), (True,) * 3,
+                                     [[((6, 4, 8), (18, 14, 16))]]), dict(min_block=4, max_block=8)),
+    "three-level-two-boxes": (HierarchySpec((-1.0,) * 3, 2.0 / 12, (12, 12, 12), (True,) * 3,
+                                            [[((4, 4, 4), (22, 22, 22))],
+                                             [((16, 16, 16), (24, 26, 24)),
+                                              ((28, 16, 18), (36, 24, 26))]]),
+                              dict(min_block=4, max_block=8, block_seed=9)),
+    "non-periodic": (HierarchySpec((0.0,) * 3, 0.1, (10, 10, 10), (False, True, False),
+                                   [[((8, 4, 8), (12, 12, 12))]]), dict(min_block=4, max_block=8)),
+    "full-cover": (HierarchySpec((-1.0,) * 3, 2.0 / 8, (8,) * 3, (True,) * 3,
+                                 [[((0, 0, 0), (15, 15, 15))]]), dict(min_block=4, max_block=8)),
+    "c2-16": (config_c2(16), dict(min_block=4, max_block=9)),
+    "c2-32": (config_c2(32), dict()),
+    "c3-64": (config_c3(64), dict()),
+    "c3-64-seed2": (config_c3(64), dict(block_seed=2, min_block=16, max_block=32)),
+    "c5-96": (config_c5(96), dict()),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SPECS))
+def test_maps_bit_identical_to_reference(name):
+    spec, kw = SPECS[name]
+    ref = Hierarchy(spec, **kw).export()
+    got = _ctx_maps(spec, **kw).export_maps()
+    assert got.shape == ref.shape
+    assert hashlib.sha256(got.tobytes()).hexdigest() == hashlib.sha256(ref.tobytes()).hexdigest()
+
+
+def test_counts_match_reference():
+    spec, kw = SPECS["c3-64"]
+    ref = Hierarchy(spec, **kw)
+    ctx = _ctx_maps(spec, **kw)
+    for l in range(spec.nlevels):
+        assert ctx.counts(l) == ref.counts(l)
+
+
+def test_nesting_errors_are_status_codes():
+    base = dict(origin=(-1.0,) * 3, dx0=2.0 / 16, ncells0=(16,) * 3, periodic=(True,) * 3)
+    bad = [
+        [[((8, 8, 8), (17, 24, 24))]],
+        [[((8, 8, 8), (34, 24, 24))]],
+        [[((8, 8, 8), (16, 16, 16)), ((14, 14, 14), (24, 24, 24))]],
+        [[((8, 8, 8), (24, 24, 24))], [((16, 18, 18), (30, 30, 30))]],
+    ]
+    for fb in bad:
+        spec = HierarchySpec(fine_boxes=fb, **base)
+        with pytest.raises(NestingError):
+            Hierarchy(spec, min_block=4)
+        with pytest.raises(sc.ScError) as e:
+            _ctx_maps(spec, min_block=4)
+        assert e.value.code == sc.SC_E_NEST
+
+
+def test_argument_and_state_errors():
+    with pytest.raises(sc.ScError) as e:
+        sc.Context(cfl=0.75)
+    assert e.value.code == sc.SC_E_ARG
+    ctx = sc.Context()
+    with pytest.raises(sc.ScError) as e:
+        ctx.advance(1)
+    assert e.value.code == sc.SC_E_STATE
+    with pytest.raises(sc.ScError) as e:
+        ctx.device_bytes()
+    assert e.value.code == sc.SC_E_STATE
+    spec, kw = SPECS["c2-16"]
+    ctx.build_spec(spec, **kw)
+    with pytest.raises(sc.ScError) as e:
+        ctx.build_spec(spec, **kw)
+    assert e.value.code == sc.SC_E_STATE
+    with pytest.raises(sc.ScError) as e:
+        ctx.advance(1)            # not bound yet
+    assert e.value.code == sc.SC_E_STATE
+    assert ctx.device_bytes() > 0
+    with pytest.raises(sc.ScError) as e:
+        ctx.counts(5)
+    assert e.value.code == sc.SC_E_ARG
+
+
+def test_arena_size_scales_with_members():
+    spec, kw = SPECS["c2-16"]
+    a = _ctx_maps(spec, **kw).device_bytes()
+    spec2 = HierarchySpec(spec.origin, spec.dx0, spec.ncells0, spec.periodic, spec.fine_boxes,
+                          nmembers=4)
+    b = _ctx_maps(spec2, **kw).device_bytes()
+    assert 3.5 * a < b < 4.5 * a
