@@ -213,6 +213,17 @@ int sc_set_exec(sc_ctx* ctx, int32_t exec);
  * has physical-boundary ghosts, whose values this would erase. */
 int sc_poison_halos(sc_ctx* ctx);
 
+/* Timing of the stencil stage kernel with HIP events recorded on the
+ * context's stream around every batched stage launch (eager modes only;
+ * SC_E_STATE in graph mode).  Enabling clears the record. */
+int sc_profile_enable(sc_ctx* ctx, int32_t on);
+/* Synchronise, then return the recorded launches, their summed duration in
+ * milliseconds and their summed algorithmic bytes: per owned point and
+ * variable, stage 1 reads y_n and writes k1 (16 B), stages 2 and 3 read y_n
+ * and the previous slope and write the next (24 B), stage 4 also reads k1,
+ * k2 and writes y_{n+1} (48 B).  Clears the record. */
+int sc_profile_read(sc_ctx* ctx, int64_t* nlaunches, double* total_ms, double* alg_bytes);
+
 /* Point-updates of one coarse step of one member (sum over levels of owned
  * points times level steps) and launches enqueued by the last sc_advance. */
 int sc_stats(const sc_ctx* ctx, int64_t* updates_per_coarse_step, int64_t* launches);

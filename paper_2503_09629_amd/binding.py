@@ -28,7 +28,8 @@ EXPORTED = [
     "sc_get_counts", "sc_export_maps", "sc_device_bytes", "sc_bind_device_memory",
     "sc_set_initial_data", "sc_advance", "sc_step_level", "sc_prolongate", "sc_fill_ghosts",
     "sc_restrict", "sc_read_back", "sc_read_rb", "sc_norms", "sc_check_finite",
-    "sc_level_time", "sc_set_exec", "sc_poison_halos", "sc_stats",
+    "sc_level_time", "sc_set_exec", "sc_poison_halos", "sc_profile_enable",
+    "sc_profile_read", "sc_stats",
 ]
 
 
@@ -88,6 +89,8 @@ def lib():
             "sc_level_time": [P, i32, P],
             "sc_set_exec": [P, i32],
             "sc_poison_halos": [P],
+            "sc_profile_enable": [P, i32],
+            "sc_profile_read": [P, P, P, P],
             "sc_stats": [P, P, P],
         }
         for name, args in sig.items():
@@ -263,6 +266,18 @@ class Context:
         t = ctypes.c_double()
         self._check(self.L.sc_level_time(self.ctx, level, ctypes.byref(t)))
         return t.value
+
+    def profile_enable(self, on: bool = True):
+        self._check(self.L.sc_profile_enable(self.ctx, int(bool(on))))
+
+    def profile_read(self):
+        """(launches, summed kernel ms, summed algorithmic bytes) since enable."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        b = ctypes.c_double()
+        self._check(self.L.sc_profile_read(self.ctx, ctypes.byref(n), ctypes.byref(ms),
+                                           ctypes.byref(b)))
+        return n.value, ms.value, b.value
 
     def stats(self):
         u = ctypes.c_int64()

@@ -438,6 +438,18 @@ hipError_t upload(sc_ctx* c, T* dst, const std::vector<T>& v) {
 
 int yh_index(int level, int substep, int stage) { return level == 0 ? 0 : substep * 4 + stage - 1; }
 
+int take_events(sc_ctx* c, hipEvent_t* e0, hipEvent_t* e1) {
+  while (c->ev_pool.size() < c->ev_used + 2) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  *e0 = c->ev_pool[c->ev_used];
+  *e1 = c->ev_pool[c->ev_used + 1];
+  c->ev_used += 2;
+  return SC_OK;
+}
+
 int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const double* yn,
                            const double* kprev, const double* yh, double* ynew) {
   LevelDev& L = c->lev[l];
@@ -463,7 +475,21 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const do
     a.tiles = L.d_tiles;
     a.ntiles = (int32_t)L.tiles.size();
     const int grid = std::min<int>(a.ntiles, c->grid_cap);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->profiling) {
+      int rc = take_events(c, &e0, &e1);
+      if (rc) return rc;
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
     HIPCHK(c, launch_stage(a, grid, true, c->stream));
+    if (c->profiling) {
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      // algorithmic bytes: y_n and the previous slope (stencil operands), the
+      // new slope, and for stage 4 k1, k2 and y_{n+1}, once per owned point
+      static const double per_var[5] = {0, 16, 24, 24, 48};
+      c->ev_bytes.push_back(per_var[stage] * c->nvars *
+                            (double)(L.owned_member * c->hier.geo.nmembers));
+    }
     ++c->launches;
   } else {
     const int nblk = (int)L.btile_start.size() - 1;
@@ -1016,6 +1042,37 @@ int sc_poison_halos(sc_ctx* c) {
     for (int i = 0; i < 4; ++i) HIPCHK(c, launch_fill(L.k[i], c->nvars * L.total, nan, c->stream));
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SC_OK;
+}
+
+int sc_profile_enable(sc_ctx* c, int32_t on) {
+  int rc = check_ready(c, 2);
+  if (rc) return rc;
+  if (on && c->cfg.exec == SC_EXEC_GRAPH)
+    return fail(c, SC_E_STATE, "kernel timing needs an eager execution mode");
+  c->profiling = on != 0;
+  c->ev_used = 0;
+  c->ev_bytes.clear();
+  return SC_OK;
+}
+
+int sc_profile_read(sc_ctx* c, int64_t* nlaunches, double* total_ms, double* alg_bytes) {
+  int rc = check_ready(c, 2);
+  if (rc) return rc;
+  if (!nlaunches || !total_ms || !alg_bytes) return fail(c, SC_E_ARG, "null output");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double ms = 0.0, bytes = 0.0;
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, c->ev_pool[i], c->ev_pool[i + 1]));
+    ms += t;
+  }
+  for (double b : c->ev_bytes) bytes += b;
+  *nlaunches = (int64_t)(c->ev_used / 2);
+  *total_ms = ms;
+  *alg_bytes = bytes;
+  c->ev_used = 0;
+  c->ev_bytes.clear();
   return SC_OK;
 }
 

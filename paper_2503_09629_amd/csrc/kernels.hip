@@ -43,11 +43,32 @@ __device__ __forceinline__ double stage_value(const StageArgs& a, const BoxDev& 
   return a.Yh[o];
 }
 
+// Ring of the LDS window of a tile (the 3-point frame around nx x ny owned
+// points): index i in [0, 6(nx+6) + 6ny) -> window coordinates (lx, ly).
+__device__ __forceinline__ void ring_coord(int i, int nx, int ny, int* lx, int* ly) {
+  const int W = nx + 2 * kG;
+  if (i < 3 * W) {
+    *ly = i / W;
+    *lx = i - *ly * W;
+  } else if (i < 6 * W) {
+    const int j = i - 3 * W;
+    *ly = ny + kG + j / W;
+    *lx = j % W;
+  } else {
+    const int j = i - 6 * W;
+    const int c = j % 6;
+    *ly = kG + j / 6;
+    *lx = c < 3 ? c : nx + c;
+  }
+}
+
 // One RK4 stage of the scalar wave on a list of tiles (persistent: workgroups
 // stride over the tile list).  A tile is up to 64 x 8 points in x-y marching
 // through nz planes.  The x-y plane of stage values (tile plus 3-point ring)
-// is staged in LDS (double buffered); each thread keeps the 7-plane z column
-// of its two points in registers.
+// is staged in LDS (double buffered): the tile's own points come from the
+// 7-plane z column each thread keeps in registers, only the ring is read from
+// memory, and both the ring and the next z plane are fetched one iteration
+// ahead so their latency overlaps the arithmetic.
 //   k_u  = Pi + Q u,   k_Pi = Lap u + Q Pi
 //   Lap  = ((d2_x + d2_y) + d2_z) / (12 h^2),  Q = sigma/(64 h) ((ko_x + ko_y) + ko_z)
 // Stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4).
@@ -55,6 +76,7 @@ template <int STAGE>
 __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
   constexpr int BX = kTileMaxX, BY = kStageThreads / kTileMaxX, RY = kTileMaxY / BY;
   constexpr int LX = BX + 2 * kG, LY = kTileMaxY + 2 * kG;
+  constexpr int RMAX = (6 * LX + 6 * kTileMaxY + kStageThreads - 1) / kStageThreads;
   __shared__ double lds[2][2][LY][LX];
   const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
@@ -68,30 +90,64 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
       yy[r] = T.y0 + ty + r * BY;
       act[r] = tx < T.nx && (ty + r * BY) < T.ny;
     }
-    double q[2][RY][7];
+    const int nring = 6 * (T.nx + 2 * kG) + 6 * T.ny;
+    int rx[RMAX], ry[RMAX];
+    bool ract[RMAX];
 #pragma unroll
-    for (int j = 0; j < 6; ++j)
+    for (int k = 0; k < RMAX; ++k) {
+      const int i = threadIdx.x + k * kStageThreads;
+      ract[k] = i < nring;
+      int lx = 0, ly = 0;
+      if (ract[k]) ring_coord(i, T.nx, T.ny, &lx, &ly);
+      rx[k] = lx;
+      ry[k] = ly;
+    }
+    double q[2][RY][7];
+    double ring[2][RMAX];
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
 #pragma unroll
       for (int r = 0; r < RY; ++r)
 #pragma unroll
         for (int v = 0; v < 2; ++v)
-          q[v][r][j] = act[r] ? stage_value<STAGE>(a, B, x, yy[r], T.z0 - kG + j, v) : 0.0;
-    const int wx = T.nx + 2 * kG, wy = T.ny + 2 * kG;
+          q[v][r][j] = (act[r] && j < 6) ? stage_value<STAGE>(a, B, x, yy[r], T.z0 - kG + j, v)
+                                         : 0.0;
+#pragma unroll
+    for (int k = 0; k < RMAX; ++k)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+        ring[v][k] = ract[k] ? stage_value<STAGE>(a, B, T.x0 - kG + rx[k], T.y0 - kG + ry[k],
+                                                  T.z0, v)
+                             : 0.0;
     for (int iz = 0; iz < T.nz; ++iz) {
       const int z = T.z0 + iz;
+      double(*L)[LY][LX] = lds[iz & 1];
+      // plane z of the stage vector into LDS: own points from the z column
+      // (plane z+3 arrives now: it is the last plane this column needs)
 #pragma unroll
       for (int r = 0; r < RY; ++r)
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
-          q[v][r][6] = act[r] ? stage_value<STAGE>(a, B, x, yy[r], z + kG, v) : 0.0;
-      double(*L)[LY][LX] = lds[iz & 1];
-      for (int i = threadIdx.x; i < wx * wy; i += kStageThreads) {
-        const int ly = i / wx, lx = i - ly * wx;
+        for (int v = 0; v < 2; ++v) {
+          if (act[r]) {
+            q[v][r][6] = stage_value<STAGE>(a, B, x, yy[r], z + kG, v);
+            L[v][ty + r * BY + kG][tx + kG] = q[v][r][3];
+          }
+        }
+#pragma unroll
+      for (int k = 0; k < RMAX; ++k)
 #pragma unroll
         for (int v = 0; v < 2; ++v)
-          L[v][ly][lx] = stage_value<STAGE>(a, B, T.x0 - kG + lx, T.y0 - kG + ly, z, v);
-      }
+          if (ract[k]) L[v][ry[k]][rx[k]] = ring[v][k];
       __syncthreads();
+      // ring of the next plane, in flight during the arithmetic
+      if (iz + 1 < T.nz) {
+#pragma unroll
+        for (int k = 0; k < RMAX; ++k)
+#pragma unroll
+          for (int v = 0; v < 2; ++v)
+            if (ract[k])
+              ring[v][k] = stage_value<STAGE>(a, B, T.x0 - kG + rx[k], T.y0 - kG + ry[k], z + 1, v);
+      }
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         if (act[r]) {

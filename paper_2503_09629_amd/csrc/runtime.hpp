@@ -80,4 +80,12 @@ struct sc_ctx {
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   bool graph_ready[2] = {false, false};
   double weights[2][5][4];  // [substep][fill-1][i]
+  // stage-kernel timing with HIP events (eager modes)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;                  // events handed out (pairs use 2)
+  std::vector<double> ev_bytes;        // algorithmic bytes per recorded launch
+  ~sc_ctx() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
 };
