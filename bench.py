@@ -34,8 +34,8 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_context(sc, spec, mode, data):
-    ctx = sc.Context(device="cuda:0", exec=mode)
+def make_context(sc, spec, mode, data, precision=0):
+    ctx = sc.Context(device="cuda:0", exec=mode, precision=precision)
     ctx.build_spec(spec, block_seed=1, min_block=16, max_block=48)
     ctx.bind()
     for l in range(spec.nlevels):
@@ -80,8 +80,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n0", type=int, default=128)
-    ap.add_argument("--modes", default="graph,batched,per_block")
+    ap.add_argument("--modes", default="graph,batched,per_block,mixed")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -102,27 +103,40 @@ def main():
     res = {}
     roof = None
     for m in modes:
+        log(f"mode {m} ...")
         mode = {"graph": sc.SC_EXEC_GRAPH, "batched": sc.SC_EXEC_BATCHED,
-                "per_block": sc.SC_EXEC_PER_BLOCK}[m]
-        ctx = make_context(sc, spec, mode, data)
+                "per_block": sc.SC_EXEC_PER_BLOCK, "mixed": sc.SC_EXEC_GRAPH,
+                "mixed_batched": sc.SC_EXEC_BATCHED}[m]
+        prec = sc.SC_MIXED if m.startswith("mixed") else sc.SC_FP64
+        ctx = make_context(sc, spec, mode, data, prec)
+        if m != "per_block" and not args.no_tune:
+            ctx.autotune(3)
+        shapes = [ctx.tile_shape(l) for l in range(spec.nlevels)]
         steps = args.steps if m != "per_block" else max(1, min(args.steps, 2))
         ctx.advance(max(1, args.warmup) if m != "per_block" else 1)
         ctx.synchronize()
         T = timed(ctx, torch, steps)
         res[m] = {"updates_per_s": U * steps / T, "ms_per_step": 1e3 * T / steps,
-                  "steps": steps}
+                  "steps": steps, "tz_per_level": [sh["tz"] for sh in shapes],
+                  "grid_per_level": [sh["grid"] for sh in shapes]}
         log(f"{m}: {1e3 * T / steps:.2f} ms/step, {U * steps / T:.4g} updates/s")
-        if m == "batched" and roof is None:
+        if m in ("batched", "mixed_batched"):
+            label = "roofline" if m == "batched" else "roofline_mixed"
             ctx.profile_enable(True)
             ctx.advance(steps)
             n, ms, nbytes = ctx.profile_read()
             ctx.profile_enable(False)
             achieved = nbytes / (ms * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "kernel": "k_wave_stage (all four stages, batched)",
-                    "launches": n, "avg_launch_us": 1e3 * ms / n,
-                    "alg_bytes_per_launch": nbytes / n}
+            r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                 "kernel": "k_wave_stage (all four stages, batched, "
+                           + ("FP64" if m == "batched" else "FP32 stencil") + ")",
+                 "launches": n, "avg_launch_us": 1e3 * ms / n,
+                 "alg_bytes_per_launch": nbytes / n}
+            if label == "roofline":
+                roof = r
+            else:
+                res[m]["roofline"] = r
             log(f"stage kernel: {n} launches, avg {1e3 * ms / n:.1f} us, {achieved:.0f} GB/s")
         if ctx.check_finite() != sc.SC_OK:
             raise SystemExit(f"non-finite values in mode {m}")

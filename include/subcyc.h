@@ -213,6 +213,17 @@ int sc_set_exec(sc_ctx* ctx, int32_t exec);
  * has physical-boundary ghosts, whose values this would erase. */
 int sc_poison_halos(sc_ctx* ctx);
 
+/* Autotune the batched stencil kernel: for every level, time candidate
+ * z-chunk depths of the tile table and persistent grid sizes with HIP events
+ * (reps launches each, on the bound data) and keep the fastest.  Overwrites
+ * the slopes k2 of every level (call it before a run, or between coarse
+ * steps of a run whose k2 is not read again).  Invalidates captured graphs.
+ * Synchronises the stream. */
+int sc_autotune(sc_ctx* ctx, int32_t reps);
+/* Tile shape of a level: out = {max tile x, max tile y, z-chunk, persistent
+ * workgroups, tiles}. */
+int sc_tile_shape(const sc_ctx* ctx, int32_t level, int32_t out[5]);
+
 /* Timing of the stencil stage kernel with HIP events recorded on the
  * context's stream around every batched stage launch (eager modes only;
  * SC_E_STATE in graph mode).  Enabling clears the record. */

@@ -48,7 +48,7 @@ def lib():
         for f in (_lib.orc_wave_rhs, _lib.orc_stage, _lib.orc_final, _lib.orc_copy_points):
             f.restype = None
         if hasattr(_lib, "orc_z4c_rhs"):
-            _lib.orc_z4c_rhs.argtypes = [i, i64p, i, L, i64p, i64p, d, d, i64p, i64p]
+            _lib.orc_z4c_rhs.argtypes = [i, i64p, i, L, i64p, i64p, d, i64p, i64p, i64p, i64p]
             _lib.orc_z4c_rhs.restype = None
     return _lib
 

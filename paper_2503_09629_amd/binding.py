@@ -28,7 +28,8 @@ EXPORTED = [
     "sc_get_counts", "sc_export_maps", "sc_device_bytes", "sc_bind_device_memory",
     "sc_set_initial_data", "sc_advance", "sc_step_level", "sc_prolongate", "sc_fill_ghosts",
     "sc_restrict", "sc_read_back", "sc_read_rb", "sc_norms", "sc_check_finite",
-    "sc_level_time", "sc_set_exec", "sc_poison_halos", "sc_profile_enable",
+    "sc_level_time", "sc_set_exec", "sc_poison_halos", "sc_autotune", "sc_tile_shape",
+    "sc_profile_enable",
     "sc_profile_read", "sc_stats",
 ]
 
@@ -89,6 +90,8 @@ def lib():
             "sc_level_time": [P, i32, P],
             "sc_set_exec": [P, i32],
             "sc_poison_halos": [P],
+            "sc_autotune": [P, i32],
+            "sc_tile_shape": [P, i32, P],
             "sc_profile_enable": [P, i32],
             "sc_profile_read": [P, P, P, P],
             "sc_stats": [P, P, P],
@@ -266,6 +269,14 @@ class Context:
         t = ctypes.c_double()
         self._check(self.L.sc_level_time(self.ctx, level, ctypes.byref(t)))
         return t.value
+
+    def autotune(self, reps: int = 3):
+        self._check(self.L.sc_autotune(self.ctx, reps))
+
+    def tile_shape(self, level: int):
+        out = (ctypes.c_int32 * 5)()
+        self._check(self.L.sc_tile_shape(self.ctx, level, out))
+        return dict(zip(("tx", "ty", "tz", "grid", "tiles"), list(out)))
 
     def profile_enable(self, on: bool = True):
         self._check(self.L.sc_profile_enable(self.ctx, int(bool(on))))

@@ -400,9 +400,11 @@ void plan_arena(sc_ctx* c) {
   int64_t maxowned = 0;
   for (LevelDev& L : c->lev) {
     const size_t arr = sizeof(double) * (size_t)c->nvars * (size_t)L.total;
+    const size_t arrs = c->esz * (size_t)c->nvars * (size_t)L.total;
     for (int i = 0; i < 2; ++i) L.o_y[i] = take(arr);
-    for (int i = 0; i < 4; ++i) L.o_k[i] = take(arr);
-    for (int i = 0; i < L.nyh; ++i) L.o_yh[i] = take(arr);
+    for (int i = 0; i < 2; ++i) L.o_y32[i] = c->mixed ? take(arr / 2) : 0;
+    for (int i = 0; i < 4; ++i) L.o_k[i] = take(arrs);
+    for (int i = 0; i < L.nyh; ++i) L.o_yh[i] = take(arrs);
     L.o_boxes = take(sizeof(BoxDev) * L.boxes.size());
     L.o_prefix = take(sizeof(int64_t) * L.prefix.size());
     L.o_sync = take(sizeof(SyncEntry) * L.sync.size());
@@ -411,7 +413,18 @@ void plan_arena(sc_ctx* c) {
     L.o_rbfirst = take(sizeof(int64_t) * L.rbfirst.size());
     L.o_phys = take(sizeof(int64_t) * L.phys.size());
     L.o_restr = take(sizeof(RestrictRegion) * L.restr.size());
-    L.o_tiles = take(sizeof(TileDev) * L.tiles.size());
+    {
+      std::vector<TileDev> most;
+      TileShape sh = L.shape;
+      sh.tz = kTuneTzMin;
+      for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
+        const BoxDev& B = L.boxes[ib];
+        const int64_t o[3] = {0, 0, 0}, n[3] = {B.nx, B.ny, B.nz};
+        tile_region(ib, o, n, sh, &most);
+      }
+      L.tiles_capacity = std::max(most.size(), L.tiles.size());
+    }
+    L.o_tiles = take(sizeof(TileDev) * L.tiles_capacity);
     L.o_btiles = take(sizeof(TileDev) * L.btiles.size());
     maxowned = std::max(maxowned, std::max(L.owned_member, L.nrb * (int64_t)c->hier.geo.nmembers));
   }
@@ -450,8 +463,11 @@ int take_events(sc_ctx* c, hipEvent_t* e0, hipEvent_t* e1) {
   return SC_OK;
 }
 
-int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const double* yn,
-                           const double* kprev, const double* yh, double* ynew) {
+// Element offset helper for the typed level arrays (k, Yh).
+inline void* elem(void* base, int64_t i, size_t esz) { return static_cast<char*>(base) + i * esz; }
+
+int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const void* yn,
+                           const void* kprev, const void* yh) {
   LevelDev& L = c->lev[l];
   StageArgs a{};
   a.stage = stage;
@@ -463,7 +479,9 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const do
   a.k2 = L.k[1];
   a.k3 = L.k[2];
   a.kout = L.k[stage - 1];
-  a.ynew = ynew;
+  a.yn64 = L.y[L.cur];
+  a.ynew = L.y[1 - L.cur];
+  a.ynew32 = c->mixed ? L.y32[1 - L.cur] : nullptr;
   a.vstride = L.total;
   static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
   a.cdt = cnext[stage] * L.dt;
@@ -474,21 +492,23 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const do
   if (!per_block) {
     a.tiles = L.d_tiles;
     a.ntiles = (int32_t)L.tiles.size();
-    const int grid = std::min<int>(a.ntiles, c->grid_cap);
+    const int grid = std::min<int>(a.ntiles, L.shape.grid > 0 ? L.shape.grid : c->grid_cap);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->profiling) {
       int rc = take_events(c, &e0, &e1);
       if (rc) return rc;
       HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    HIPCHK(c, launch_stage(a, grid, true, c->stream));
+    HIPCHK(c, launch_stage(a, grid, c->mixed, c->stream));
     if (c->profiling) {
       HIPCHK(c, hipEventRecord(e1, c->stream));
-      // algorithmic bytes: y_n and the previous slope (stencil operands), the
-      // new slope, and for stage 4 k1, k2 and y_{n+1}, once per owned point
-      static const double per_var[5] = {0, 16, 24, 24, 48};
-      c->ev_bytes.push_back(per_var[stage] * c->nvars *
-                            (double)(L.owned_member * c->hier.geo.nmembers));
+      // algorithmic bytes per owned point and variable: the stencil operands
+      // y_n and k_{s-1}, the new slope, and for stage 4 also k1, k2, the FP64
+      // y_n and y_{n+1} (plus its FP32 shadow in mixed mode)
+      static const double fp64[5] = {0, 16, 24, 24, 48};
+      static const double mixed[5] = {0, 8, 12, 12, 40};
+      const double per_var = c->mixed ? mixed[stage] : fp64[stage];
+      c->ev_bytes.push_back(per_var * c->nvars * (double)(L.owned_member * c->hier.geo.nmembers));
     }
     ++c->launches;
   } else {
@@ -496,7 +516,7 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const do
     for (int b = 0; b < nblk; ++b) {
       a.tiles = L.d_btiles + L.btile_start[b];
       a.ntiles = L.btile_start[b + 1] - L.btile_start[b];
-      HIPCHK(c, launch_stage(a, a.ntiles, true, c->stream));
+      HIPCHK(c, launch_stage(a, a.ntiles, c->mixed, c->stream));
       ++c->launches;
     }
   }
@@ -505,11 +525,10 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const do
 
 int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
   LevelDev& L = c->lev[l];
-  double* yn = L.y[L.cur];
-  double* ynew = L.y[1 - L.cur];
+  const void* yn = c->mixed ? static_cast<const void*>(L.y32[L.cur]) : L.y[L.cur];
   for (int s = 1; s <= 4; ++s) {
-    double* yh = L.Yh[yh_index(l, substep, s)];
-    const double* kprev = s == 1 ? nullptr : L.k[s - 2];
+    void* yh = L.Yh[yh_index(l, substep, s)];
+    const void* kprev = s == 1 ? nullptr : L.k[s - 2];
     if (!L.sync.empty()) {
       SyncArgs sa{};
       sa.e = L.d_sync;
@@ -521,40 +540,61 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
       static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
       sa.cdt = cnext[s] * L.dt;
       sa.nvars = c->nvars;
-      HIPCHK(c, launch_sync(sa, c->stream));
+      HIPCHK(c, launch_sync(sa, c->mixed, c->stream));
       ++c->launches;
     }
-    int rc = enqueue_stage_launches(c, l, s, per_block, yn, kprev, yh, ynew);
+    int rc = enqueue_stage_launches(c, l, s, per_block, yn, kprev, yh);
     if (rc) return rc;
   }
   L.cur = 1 - L.cur;
   return SC_OK;
 }
 
+// Prolongation from the parent's last step (y_n = the buffer it stepped from,
+// k1..k4) into the fine level: outputs[i] with weights[i].
+int prolong_into(sc_ctx* c, int fl, const ProlongEntry* entries, int64_t n, int nout,
+                 void* const* outs, const int* fills, const int* subs, int64_t ovstride,
+                 bool out_f32, int var_only) {
+  LevelDev& P = c->lev[fl - 1];
+  if (n <= 0) return SC_OK;
+  ProlongArgs a{};
+  a.e = entries;
+  a.n = n;
+  a.pboxes = P.d_boxes;
+  a.py = P.y[1 - P.cur];
+  for (int i = 0; i < 4; ++i) a.pk[i] = P.k[i];
+  a.pvstride = P.total;
+  a.ovstride = ovstride;
+  a.H = P.dt;
+  a.nout = nout;
+  a.nvars = c->nvars;
+  if (var_only >= 0) {  // a single variable, outputs unstrided
+    a.nvars = 1;
+    a.py += var_only * P.total;
+    for (int i = 0; i < 4; ++i) a.pk[i] = elem(P.k[i], var_only * P.total, c->esz);
+  }
+  for (int o = 0; o < nout; ++o) {
+    a.out[o] = outs[o];
+    for (int i = 0; i < 4; ++i) a.w[o][i] = c->weights[subs[o]][fills[o] - 1][i];
+  }
+  HIPCHK(c, launch_prolong(a, c->mixed, out_f32, c->stream));
+  ++c->launches;
+  return SC_OK;
+}
+
 int prolongate(sc_ctx* c, int fl) {
   LevelDev& F = c->lev[fl];
-  LevelDev& P = c->lev[fl - 1];
-  if (F.prolong.empty()) return SC_OK;
-  ProlongArgs a{};
-  a.e = F.d_prolong;
-  a.n = (int64_t)F.prolong.size();
-  a.pboxes = P.d_boxes;
-  a.pv[0] = P.y[1 - P.cur];  // y_n of the parent's last step
-  for (int i = 0; i < 4; ++i) a.pv[1 + i] = P.k[i];
-  a.pvstride = P.total;
-  a.ovstride = F.total;
-  a.H = P.dt;
-  a.nout = 8;
-  a.nvars = c->nvars;
+  void* outs[8];
+  int fills[8], subs[8];
   for (int sub = 0; sub < 2; ++sub)
     for (int s = 1; s <= 4; ++s) {
       const int o = sub * 4 + s - 1;
-      a.out[o] = F.Yh[o];
-      for (int i = 0; i < 4; ++i) a.w[o][i] = c->weights[sub][s - 1][i];
+      outs[o] = F.Yh[o];
+      fills[o] = s;
+      subs[o] = sub;
     }
-  HIPCHK(c, launch_prolong(a, c->stream));
-  ++c->launches;
-  return SC_OK;
+  return prolong_into(c, fl, F.d_prolong, (int64_t)F.prolong.size(), 8, outs, fills, subs,
+                      F.total, c->mixed, -1);
 }
 
 int restrict_level(sc_ctx* c, int fl) {
@@ -569,6 +609,7 @@ int restrict_level(sc_ctx* c, int fl) {
   a.pboxes = P.d_boxes;
   a.fy = F.y[F.cur];
   a.py = P.y[P.cur];
+  a.py32 = c->mixed ? P.y32[P.cur] : nullptr;
   a.fvstride = F.total;
   a.pvstride = P.total;
   a.nvars = c->nvars;
@@ -599,16 +640,20 @@ int check_ready(const sc_ctx* c, int need) {
   return SC_OK;
 }
 
-double* array_ptr(sc_ctx* c, int l, int array) {
+// Array of one variable: FP64 state buffers, or the typed slope arrays.
+void* array_ptr(sc_ctx* c, int l, int array, int var, bool* f32) {
   LevelDev& L = c->lev[l];
+  *f32 = false;
   switch (array) {
-    case SC_ARR_Y: return L.y[L.cur];
-    case SC_ARR_YN: return L.y[1 - L.cur];
-    default: return L.k[array - 1];
+    case SC_ARR_Y: return L.y[L.cur] + var * L.total;
+    case SC_ARR_YN: return L.y[1 - L.cur] + var * L.total;
+    default:
+      *f32 = c->mixed;
+      return elem(L.k[array - 1], var * L.total, c->esz);
   }
 }
 
-PackArgs member_pack(sc_ctx* c, int member, int l, double* arr) {
+PackArgs member_pack(sc_ctx* c, int member, int l, void* arr) {
   LevelDev& L = c->lev[l];
   PackArgs a{};
   a.boxes = L.d_boxes + member * L.nb_member;
@@ -649,13 +694,16 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
     return SC_E_ARG;
   }
   if (cfg->rhs != SC_RHS_WAVE || cfg->nghost != 3 || !(cfg->cfl > 0.0 && cfg->cfl <= 0.5) ||
-      cfg->ko_sigma < 0.0 || (cfg->precision != SC_FP64) || cfg->exec < 0 || cfg->exec > 2) {
+      cfg->ko_sigma < 0.0 || (cfg->precision != SC_FP64 && cfg->precision != SC_MIXED) ||
+      cfg->exec < 0 || cfg->exec > 2) {
     g_create_error = "unsupported configuration (rhs, nghost 3, 0 < cfl <= 0.5, sigma >= 0, "
                      "precision, exec)";
     return SC_E_ARG;
   }
   sc_ctx* c = new sc_ctx();
   c->cfg = *cfg;
+  c->mixed = cfg->precision == SC_MIXED;
+  c->esz = c->mixed ? sizeof(float) : sizeof(double);
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   for (int sub = 0; sub < 2; ++sub)
     for (int f = 1; f <= 5; ++f) ghost_weights(f, sub ? Rat(1, 2) : Rat(0), c->weights[sub][f - 1]);
@@ -772,8 +820,9 @@ int sc_bind_device_memory(sc_ctx* c, void* dptr, size_t nbytes) {
   HIPCHK(c, hipMemsetAsync(c->arena, 0, c->arena_bytes, c->stream));
   for (LevelDev& L : c->lev) {
     for (int i = 0; i < 2; ++i) L.y[i] = at<double>(c, L.o_y[i]);
-    for (int i = 0; i < 4; ++i) L.k[i] = at<double>(c, L.o_k[i]);
-    for (int i = 0; i < L.nyh; ++i) L.Yh[i] = at<double>(c, L.o_yh[i]);
+    for (int i = 0; i < 2; ++i) L.y32[i] = c->mixed ? at<float>(c, L.o_y32[i]) : nullptr;
+    for (int i = 0; i < 4; ++i) L.k[i] = at<char>(c, L.o_k[i]);
+    for (int i = 0; i < L.nyh; ++i) L.Yh[i] = at<char>(c, L.o_yh[i]);
     L.d_boxes = at<BoxDev>(c, L.o_boxes);
     L.d_prefix = at<int64_t>(c, L.o_prefix);
     L.d_sync = at<SyncEntry>(c, L.o_sync);
@@ -815,7 +864,10 @@ int sc_set_initial_data(sc_ctx* c, int32_t member, int32_t level, int32_t var,
   HIPCHK(c, hipMemcpyAsync(c->d_stage, host, sizeof(double) * n, hipMemcpyHostToDevice,
                            c->stream));
   PackArgs a = member_pack(c, member, level, L.y[L.cur] + var * L.total);
-  HIPCHK(c, launch_pack(a, true, c->stream));
+  HIPCHK(c, launch_pack(a, true, false, c->stream));
+  if (c->mixed)
+    HIPCHK(c, launch_to_f32(L.y[L.cur] + var * L.total, L.y32[L.cur] + var * L.total, L.total,
+                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->state = 3;
   return SC_OK;
@@ -905,24 +957,14 @@ int sc_fill_ghosts(sc_ctx* c, int32_t level, int32_t which, int32_t substep) {
     sa.out = y;
     sa.vstride = L.total;
     sa.nvars = c->nvars;
-    HIPCHK(c, launch_sync(sa, c->stream));
+    HIPCHK(c, launch_sync(sa, false, c->stream));
   }
-  if (level > 0 && !L.prolong.empty()) {
-    LevelDev& P = c->lev[level - 1];
-    ProlongArgs a{};
-    a.e = L.d_prolong;
-    a.n = (int64_t)L.prolong.size();
-    a.pboxes = P.d_boxes;
-    a.pv[0] = P.y[1 - P.cur];
-    for (int i = 0; i < 4; ++i) a.pv[1 + i] = P.k[i];
-    a.pvstride = P.total;
-    a.ovstride = L.total;
-    a.H = P.dt;
-    a.nout = 1;
-    a.nvars = c->nvars;
-    a.out[0] = y;
-    for (int i = 0; i < 4; ++i) a.w[0][i] = c->weights[substep][which - 1][i];
-    HIPCHK(c, launch_prolong(a, c->stream));
+  if (level > 0) {
+    void* outs[1] = {y};
+    const int fills[1] = {which}, subs[1] = {substep};
+    rc = prolong_into(c, level, L.d_prolong, (int64_t)L.prolong.size(), 1, outs, fills, subs,
+                      L.total, false, -1);
+    if (rc) return rc;
   }
   return SC_OK;
 }
@@ -937,8 +979,9 @@ int sc_read_back(sc_ctx* c, int32_t member, int32_t level, int32_t var, int32_t 
     return fail(c, SC_E_ARG, "bad read-back arguments");
   LevelDev& L = c->lev[level];
   if (n != L.owned_member) return fail(c, SC_E_ARG, "n must equal the level's owned points");
-  PackArgs a = member_pack(c, member, level, array_ptr(c, level, array) + var * L.total);
-  HIPCHK(c, launch_pack(a, false, c->stream));
+  bool f32 = false;
+  PackArgs a = member_pack(c, member, level, array_ptr(c, level, array, var, &f32));
+  HIPCHK(c, launch_pack(a, false, f32, c->stream));
   HIPCHK(c, hipMemcpyAsync(host, c->d_stage, sizeof(double) * n, hipMemcpyDeviceToHost,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -956,25 +999,15 @@ int sc_read_rb(sc_ctx* c, int32_t member, int32_t level, int32_t which, int32_t 
   LevelDev& L = c->lev[level];
   if (n != L.nrb) return fail(c, SC_E_ARG, "n must equal the level's RB points");
   if (which <= 4) {
-    const double* src = L.Yh[substep * 4 + which - 1] + var * L.total;
-    HIPCHK(c, launch_gather(L.d_rbfirst + member * L.nrb, L.nrb, src, c->d_stage, c->stream));
+    const void* src = elem(L.Yh[substep * 4 + which - 1], var * L.total, c->esz);
+    HIPCHK(c, launch_gather(L.d_rbfirst + member * L.nrb, L.nrb, src, c->mixed, c->d_stage,
+                            c->stream));
   } else {
-    LevelDev& P = c->lev[level - 1];
-    ProlongArgs a{};
-    a.e = L.d_rblist + member * L.nrb;
-    a.n = L.nrb;
-    a.pboxes = P.d_boxes;
-    a.pv[0] = P.y[1 - P.cur];
-    for (int i = 0; i < 4; ++i) a.pv[1 + i] = P.k[i];
-    a.pvstride = P.total;
-    a.ovstride = 0;
-    a.H = P.dt;
-    a.nout = 1;
-    a.nvars = 1;
-    a.out[0] = c->d_stage;
-    for (int i = 0; i < 4; ++i) a.w[0][i] = c->weights[substep][4][i];
-    for (int m = 0; m < 5; ++m) a.pv[m] = a.pv[m] + var * P.total;
-    HIPCHK(c, launch_prolong(a, c->stream));
+    void* outs[1] = {c->d_stage};
+    const int fills[1] = {5}, subs[1] = {substep};
+    rc = prolong_into(c, level, L.d_rblist + member * L.nrb, L.nrb, 1, outs, fills, subs, 0,
+                      false, var);
+    if (rc) return rc;
   }
   HIPCHK(c, hipMemcpyAsync(host, c->d_stage, sizeof(double) * n, hipMemcpyDeviceToHost,
                            c->stream));
@@ -990,9 +1023,9 @@ int sc_norms(sc_ctx* c, int32_t member, int32_t level, int32_t var, int32_t arra
       member >= c->hier.geo.nmembers || var < 0 || var >= c->nvars || array < 0 || array > 5 ||
       !out)
     return fail(c, SC_E_ARG, "bad norm arguments");
-  LevelDev& L = c->lev[level];
-  PackArgs a = member_pack(c, member, level, array_ptr(c, level, array) + var * L.total);
-  HIPCHK(c, launch_norms(a, c->d_partials, 256, c->d_norm_out, c->stream));
+  bool f32 = false;
+  PackArgs a = member_pack(c, member, level, array_ptr(c, level, array, var, &f32));
+  HIPCHK(c, launch_norms(a, f32, c->d_partials, 256, c->d_norm_out, c->stream));
   HIPCHK(c, hipMemcpyAsync(out, c->d_norm_out, sizeof(double) * 3, hipMemcpyDeviceToHost,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1038,10 +1071,96 @@ int sc_poison_halos(sc_ctx* c) {
   for (LevelDev& L : c->lev) {
     if (!L.phys.empty()) return fail(c, SC_E_STATE, "poisoning would erase physical ghosts");
     for (int i = 0; i < L.nyh; ++i)
-      HIPCHK(c, launch_fill(L.Yh[i], c->nvars * L.total, nan, c->stream));
-    for (int i = 0; i < 4; ++i) HIPCHK(c, launch_fill(L.k[i], c->nvars * L.total, nan, c->stream));
+      HIPCHK(c, launch_fill(L.Yh[i], c->nvars * L.total, nan, c->mixed, c->stream));
+    for (int i = 0; i < 4; ++i)
+      HIPCHK(c, launch_fill(L.k[i], c->nvars * L.total, nan, c->mixed, c->stream));
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SC_OK;
+}
+
+int sc_autotune(sc_ctx* c, int32_t reps) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  if (reps < 1 || reps > 1000) return fail(c, SC_E_ARG, "reps must be in [1, 1000]");
+  int dev = 0, ncu = 0;
+  HIPCHK(c, hipGetDevice(&dev));
+  HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const bool prof = c->profiling;
+  c->profiling = false;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  for (size_t l = 0; l < c->lev.size(); ++l) {
+    LevelDev& L = c->lev[l];
+    float best = 1e30f;
+    TileShape best_shape = L.shape;
+    std::vector<TileDev> best_tiles = L.tiles;
+    for (int tz : kTuneTz) {
+      TileShape sh = L.shape;
+      sh.tz = tz;
+      std::vector<TileDev> tl;
+      for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
+        const BoxDev& B = L.boxes[ib];
+        const int64_t o[3] = {0, 0, 0}, n[3] = {B.nx, B.ny, B.nz};
+        tile_region(ib, o, n, sh, &tl);
+      }
+      if (tl.size() > L.tiles_capacity) continue;
+      HIPCHK(c, upload(c, L.d_tiles, tl));
+      L.tiles = tl;
+      for (int g : {2 * ncu, 4 * ncu, 8 * ncu, 1 << 30}) {
+        sh.grid = std::min<int>(g, (int)tl.size());
+        L.shape = sh;
+        // stage 2 reads y_n, k1 and the halo table, writes k2
+        rc = enqueue_stage_launches(c, (int)l, 2, false, c->mixed ? (const void*)L.y32[L.cur]
+                                                                  : (const void*)L.y[L.cur],
+                                    L.k[0], L.Yh[0]);
+        if (rc) return rc;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r) {
+          rc = enqueue_stage_launches(c, (int)l, 2, false,
+                                      c->mixed ? (const void*)L.y32[L.cur] : (const void*)L.y[L.cur],
+                                      L.k[0], L.Yh[0]);
+          if (rc) return rc;
+        }
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+          best = ms;
+          best_shape = sh;
+          best_tiles = tl;
+        }
+        if (g >= (int)tl.size()) break;
+      }
+    }
+    L.shape = best_shape;
+    L.tiles = best_tiles;
+    HIPCHK(c, upload(c, L.d_tiles, L.tiles));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->profiling = prof;
+  for (int i = 0; i < 2; ++i) {
+    if (c->graph[i]) (void)hipGraphExecDestroy(c->graph[i]);
+    c->graph[i] = nullptr;
+    c->graph_ready[i] = false;
+  }
+  return SC_OK;
+}
+
+int sc_tile_shape(const sc_ctx* c, int32_t level, int32_t out[5]) {
+  int rc = check_ready(c, 1);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || !out) return SC_E_ARG;
+  const LevelDev& L = c->lev[level];
+  out[0] = L.shape.tx;
+  out[1] = L.shape.ty;
+  out[2] = L.shape.tz;
+  out[3] = L.shape.grid > 0 ? L.shape.grid : std::min<int>((int)L.tiles.size(), c->grid_cap);
+  out[4] = (int32_t)L.tiles.size();
   return SC_OK;
 }
 

@@ -57,19 +57,24 @@ struct RestrictRegion {
 
 constexpr int kMaxOut = 8;
 
+// Stencil operands are FP64 in SC_FP64 mode and FP32 shadows in SC_MIXED
+// mode (the `void` pointers below hold that type); the state, the RK4
+// combination and everything on the refinement boundary stay FP64.
 struct StageArgs {
   const TileDev* tiles;
   int32_t ntiles;
   int32_t stage;
   const BoxDev* boxes;
-  const double* yn;
-  const double* kprev;
-  const double* Yh;
-  const double* k1;
-  const double* k2;
-  const double* k3;
-  double* kout;
-  double* ynew;
+  const void* yn;      // stencil operand: y_n
+  const void* kprev;   // stencil operand: k_{s-1}
+  const void* Yh;      // halo table of this (substep, stage)
+  const void* k1;
+  const void* k2;
+  const void* k3;
+  void* kout;          // k_s
+  const double* yn64;  // FP64 y_n for the final combination (stage 4)
+  double* ynew;        // FP64 y_{n+1} (stage 4)
+  float* ynew32;       // FP32 shadow of y_{n+1} (mixed, stage 4)
   int64_t vstride;
   double cdt;    // c_s * dt: interior stage vector Y = y_n + cdt * k_{s-1}
   double dt6;    // dt / 6
@@ -81,9 +86,9 @@ struct StageArgs {
 struct SyncArgs {
   const SyncEntry* e;
   int64_t n;
-  const double* yn;
-  const double* kprev;   // null: copy y_n
-  double* out;
+  const void* yn;
+  const void* kprev;   // null: copy y_n
+  void* out;
   int64_t vstride;
   double cdt;
   int32_t nvars;
@@ -93,9 +98,10 @@ struct ProlongArgs {
   const ProlongEntry* e;
   int64_t n;
   const BoxDev* pboxes;          // parent level boxes
-  const double* pv[5];           // parent y_n, k1..k4
+  const double* py;              // parent y_n (FP64)
+  const void* pk[4];             // parent k1..k4 (FP64, or FP32 in mixed mode)
   int64_t pvstride;
-  double* out[kMaxOut];          // outputs, one per combination
+  void* out[kMaxOut];            // outputs, one per combination
   int64_t ovstride;
   double w[kMaxOut][4];          // dense-output weights per combination
   double H;                      // parent time step
@@ -111,6 +117,7 @@ struct RestrictArgs {
   const BoxDev* pboxes;
   const double* fy;
   double* py;
+  float* py32;            // parent FP32 shadow (mixed) or null
   int64_t fvstride, pvstride;
   int32_t nvars;
 };
@@ -120,21 +127,23 @@ struct PackArgs {
   const int64_t* prefix;  // nboxes + 1 canonical prefix counts (device)
   int32_t nboxes;
   int64_t n;
-  double* arr;            // level array of the variable (already offset by var)
+  void* arr;              // level array of the variable (already offset by var)
   double* buf;            // canonical buffer
 };
 
-// launchers (kernels.hip)
-hipError_t launch_stage(const StageArgs& a, int grid, bool write_k, hipStream_t s);
-hipError_t launch_sync(const SyncArgs& a, hipStream_t s);
-hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s);
+// launchers (kernels.hip); `f32` selects FP32 stencil operands / arrays
+hipError_t launch_stage(const StageArgs& a, int grid, bool f32, hipStream_t s);
+hipError_t launch_sync(const SyncArgs& a, bool f32, hipStream_t s);
+// k_f32: parent slopes are FP32; out_f32: outputs are FP32
+hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
-hipError_t launch_pack(const PackArgs& a, bool unpack, hipStream_t s);
-hipError_t launch_norms(const PackArgs& a, double* partials, int nparts, double* out,
+hipError_t launch_pack(const PackArgs& a, bool unpack, bool f32, hipStream_t s);
+hipError_t launch_norms(const PackArgs& a, bool f32, double* partials, int nparts, double* out,
                         hipStream_t s);
-hipError_t launch_gather(const int64_t* idx, int64_t n, const double* src, double* dst,
+hipError_t launch_gather(const int64_t* idx, int64_t n, const void* src, bool f32, double* dst,
                          hipStream_t s);
-hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill(void* p, int64_t n, double v, bool f32, hipStream_t s);
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 constexpr int kStageThreads = 256;
 constexpr int kTileMaxX = 64;

@@ -4,21 +4,24 @@
 //
 // Every floating-point expression is written in one fixed evaluation order
 // and the file is compiled without FP contraction, so each value is the
-// correctly rounded result of the stated sequence of operations.
+// correctly rounded result of the stated sequence of operations.  The
+// stencil type TS is double (FP64 mode) or float (mixed mode: FP32 shadows
+// in, FP32 arithmetic, FP32 slopes out; the state update stays FP64).
 #include "device.hpp"
 
 namespace sc {
 namespace {
 
-__device__ __forceinline__ double d2(double m2, double m1, double c, double p1, double p2) {
+template <typename T>
+__device__ __forceinline__ T d2(T m2, T m1, T c, T p1, T p2) {
   // fourth-order centred second difference, without the 1/(12 h^2) factor
-  return (((-m2 + 16.0 * m1) - 30.0 * c) + 16.0 * p1) - p2;
+  return (((-m2 + T(16) * m1) - T(30) * c) + T(16) * p1) - p2;
 }
 
-__device__ __forceinline__ double ko7(double m3, double m2, double m1, double c, double p1,
-                                      double p2, double p3) {
+template <typename T>
+__device__ __forceinline__ T ko7(T m3, T m2, T m1, T c, T p1, T p2, T p3) {
   // sixth difference: h^6 D+^3 D-^3 u, the r = 4 Kreiss-Oliger stencil (Sec. III.C)
-  return (((((m3 - 6.0 * m2) + 15.0 * m1) - 20.0 * c) + 15.0 * p1) - 6.0 * p2) + p3;
+  return (((((m3 - T(6) * m2) + T(15) * m1) - T(20) * c) + T(15) * p1) - T(6) * p2) + p3;
 }
 
 __device__ __forceinline__ int64_t padded_offset(const BoxDev& B, int x, int y, int z) {
@@ -27,20 +30,22 @@ __device__ __forceinline__ int64_t padded_offset(const BoxDev& B, int x, int y, 
 
 // Stage vector at box-local (x, y, z): owned points are formed on the fly as
 // y_n + (c_s dt) k_{s-1} (Y1 = y_n); halo points come from the halo table.
-template <int STAGE>
-__device__ __forceinline__ double stage_value(const StageArgs& a, const BoxDev& B, int x, int y,
-                                              int z, int v) {
+template <int STAGE, typename TS>
+__device__ __forceinline__ TS stage_value(const StageArgs& a, const BoxDev& B, int x, int y,
+                                          int z, int v) {
   const int64_t o = padded_offset(B, x, y, z) + v * a.vstride;
   const bool in = (unsigned)x < (unsigned)B.nx && (unsigned)y < (unsigned)B.ny &&
                   (unsigned)z < (unsigned)B.nz;
   if (in) {
+    const TS* yn = static_cast<const TS*>(a.yn);
     if constexpr (STAGE == 1) {
-      return a.yn[o];
+      return yn[o];
     } else {
-      return a.yn[o] + a.cdt * a.kprev[o];
+      const TS* kp = static_cast<const TS*>(a.kprev);
+      return yn[o] + TS(a.cdt) * kp[o];
     }
   }
-  return a.Yh[o];
+  return static_cast<const TS*>(a.Yh)[o];
 }
 
 // Ring of the LDS window of a tile (the 3-point frame around nx x ny owned
@@ -67,18 +72,18 @@ __device__ __forceinline__ void ring_coord(int i, int nx, int ny, int* lx, int* 
 // through nz planes.  The x-y plane of stage values (tile plus 3-point ring)
 // is staged in LDS (double buffered): the tile's own points come from the
 // 7-plane z column each thread keeps in registers, only the ring is read from
-// memory, and both the ring and the next z plane are fetched one iteration
-// ahead so their latency overlaps the arithmetic.
+// memory, and the ring of the next plane is fetched during the arithmetic.
 //   k_u  = Pi + Q u,   k_Pi = Lap u + Q Pi
 //   Lap  = ((d2_x + d2_y) + d2_z) / (12 h^2),  Q = sigma/(64 h) ((ko_x + ko_y) + ko_z)
-// Stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4).
-template <int STAGE>
+// Stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4) in FP64.
+template <int STAGE, typename TS>
 __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
   constexpr int BX = kTileMaxX, BY = kStageThreads / kTileMaxX, RY = kTileMaxY / BY;
   constexpr int LX = BX + 2 * kG, LY = kTileMaxY + 2 * kG;
   constexpr int RMAX = (6 * LX + 6 * kTileMaxY + kStageThreads - 1) / kStageThreads;
-  __shared__ double lds[2][2][LY][LX];
+  __shared__ TS lds[2][2][LY][LX];
   const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+  const TS clap = TS(a.clap), cko = TS(a.cko);
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
@@ -102,34 +107,35 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
       rx[k] = lx;
       ry[k] = ly;
     }
-    double q[2][RY][7];
-    double ring[2][RMAX];
+    TS q[2][RY][7];
+    TS ring[2][RMAX];
 #pragma unroll
     for (int j = 0; j < 7; ++j)
 #pragma unroll
       for (int r = 0; r < RY; ++r)
 #pragma unroll
         for (int v = 0; v < 2; ++v)
-          q[v][r][j] = (act[r] && j < 6) ? stage_value<STAGE>(a, B, x, yy[r], T.z0 - kG + j, v)
-                                         : 0.0;
+          q[v][r][j] = (act[r] && j < 6)
+                           ? stage_value<STAGE, TS>(a, B, x, yy[r], T.z0 - kG + j, v)
+                           : TS(0);
 #pragma unroll
     for (int k = 0; k < RMAX; ++k)
 #pragma unroll
       for (int v = 0; v < 2; ++v)
-        ring[v][k] = ract[k] ? stage_value<STAGE>(a, B, T.x0 - kG + rx[k], T.y0 - kG + ry[k],
-                                                  T.z0, v)
-                             : 0.0;
+        ring[v][k] = ract[k] ? stage_value<STAGE, TS>(a, B, T.x0 - kG + rx[k],
+                                                      T.y0 - kG + ry[k], T.z0, v)
+                             : TS(0);
     for (int iz = 0; iz < T.nz; ++iz) {
       const int z = T.z0 + iz;
-      double(*L)[LY][LX] = lds[iz & 1];
-      // plane z of the stage vector into LDS: own points from the z column
-      // (plane z+3 arrives now: it is the last plane this column needs)
+      TS(*L)[LY][LX] = lds[iz & 1];
+      // plane z into LDS: own points from the z column (whose last plane,
+      // z+3, is read now), the ring from the registers filled last iteration
 #pragma unroll
       for (int r = 0; r < RY; ++r)
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           if (act[r]) {
-            q[v][r][6] = stage_value<STAGE>(a, B, x, yy[r], z + kG, v);
+            q[v][r][6] = stage_value<STAGE, TS>(a, B, x, yy[r], z + kG, v);
             L[v][ty + r * BY + kG][tx + kG] = q[v][r][3];
           }
         }
@@ -139,51 +145,58 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
         for (int v = 0; v < 2; ++v)
           if (ract[k]) L[v][ry[k]][rx[k]] = ring[v][k];
       __syncthreads();
-      // ring of the next plane, in flight during the arithmetic
       if (iz + 1 < T.nz) {
 #pragma unroll
         for (int k = 0; k < RMAX; ++k)
 #pragma unroll
           for (int v = 0; v < 2; ++v)
             if (ract[k])
-              ring[v][k] = stage_value<STAGE>(a, B, T.x0 - kG + rx[k], T.y0 - kG + ry[k], z + 1, v);
+              ring[v][k] = stage_value<STAGE, TS>(a, B, T.x0 - kG + rx[k], T.y0 - kG + ry[k],
+                                                  z + 1, v);
       }
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         if (act[r]) {
           const int lx = tx + kG, ly = ty + r * BY + kG;
-          const double cu = q[0][r][3], cp = q[1][r][3];
-          const double lapx = d2(L[0][ly][lx - 2], L[0][ly][lx - 1], cu, L[0][ly][lx + 1],
+          const TS cu = q[0][r][3], cp = q[1][r][3];
+          const TS lapx = d2<TS>(L[0][ly][lx - 2], L[0][ly][lx - 1], cu, L[0][ly][lx + 1],
                                  L[0][ly][lx + 2]);
-          const double lapy = d2(L[0][ly - 2][lx], L[0][ly - 1][lx], cu, L[0][ly + 1][lx],
+          const TS lapy = d2<TS>(L[0][ly - 2][lx], L[0][ly - 1][lx], cu, L[0][ly + 1][lx],
                                  L[0][ly + 2][lx]);
-          const double lapz = d2(q[0][r][1], q[0][r][2], cu, q[0][r][4], q[0][r][5]);
-          const double lap = ((lapx + lapy) + lapz) * a.clap;
-          double Q[2];
+          const TS lapz = d2<TS>(q[0][r][1], q[0][r][2], cu, q[0][r][4], q[0][r][5]);
+          const TS lap = ((lapx + lapy) + lapz) * clap;
+          TS Q[2];
 #pragma unroll
           for (int v = 0; v < 2; ++v) {
-            const double c = q[v][r][3];
-            const double kx = ko7(L[v][ly][lx - 3], L[v][ly][lx - 2], L[v][ly][lx - 1], c,
+            const TS c = q[v][r][3];
+            const TS kx = ko7<TS>(L[v][ly][lx - 3], L[v][ly][lx - 2], L[v][ly][lx - 1], c,
                                   L[v][ly][lx + 1], L[v][ly][lx + 2], L[v][ly][lx + 3]);
-            const double ky = ko7(L[v][ly - 3][lx], L[v][ly - 2][lx], L[v][ly - 1][lx], c,
+            const TS ky = ko7<TS>(L[v][ly - 3][lx], L[v][ly - 2][lx], L[v][ly - 1][lx], c,
                                   L[v][ly + 1][lx], L[v][ly + 2][lx], L[v][ly + 3][lx]);
-            const double kz = ko7(q[v][r][0], q[v][r][1], q[v][r][2], c, q[v][r][4],
+            const TS kz = ko7<TS>(q[v][r][0], q[v][r][1], q[v][r][2], c, q[v][r][4],
                                   q[v][r][5], q[v][r][6]);
-            Q[v] = a.cko * ((kx + ky) + kz);
+            Q[v] = cko * ((kx + ky) + kz);
           }
-          const double ku = cp + Q[0];
-          const double kp = lap + Q[1];
+          const TS kv[2] = {cp + Q[0], lap + Q[1]};
           const int64_t o = padded_offset(B, x, yy[r], z);
           if (a.write_k) {
-            a.kout[o] = ku;
-            a.kout[o + a.vstride] = kp;
+            TS* ko = static_cast<TS*>(a.kout);
+            ko[o] = kv[0];
+            ko[o + a.vstride] = kv[1];
           }
           if constexpr (STAGE == 4) {
-            const double su = ((a.k1[o] + 2.0 * a.k2[o]) + 2.0 * a.k3[o]) + ku;
-            a.ynew[o] = a.yn[o] + a.dt6 * su;
-            const int64_t o1 = o + a.vstride;
-            const double sp = ((a.k1[o1] + 2.0 * a.k2[o1]) + 2.0 * a.k3[o1]) + kp;
-            a.ynew[o1] = a.yn[o1] + a.dt6 * sp;
+            const TS* k1 = static_cast<const TS*>(a.k1);
+            const TS* k2 = static_cast<const TS*>(a.k2);
+            const TS* k3 = static_cast<const TS*>(a.k3);
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+              const int64_t ov = o + v * a.vstride;
+              const double s = (((double)k1[ov] + 2.0 * (double)k2[ov]) + 2.0 * (double)k3[ov]) +
+                               (double)kv[v];
+              const double yv = a.yn64[ov] + a.dt6 * s;
+              a.ynew[ov] = yv;
+              if constexpr (sizeof(TS) == 4) a.ynew32[ov] = (float)yv;
+            }
           }
         }
       }
@@ -199,22 +212,27 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
 }
 
 // Halo copy from an owned point of the same level: the stage vector there
-// (y_n + cdt k_{s-1}, or y_n), or the state for an end-of-step fill.
+// (y_n + cdt k_{s-1}, evaluated exactly as the stencil kernel does), or y_n.
+template <typename TS>
 __global__ __launch_bounds__(256) void k_sync(SyncArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const SyncEntry e = a.e[i];
+  const TS* yn = static_cast<const TS*>(a.yn);
+  const TS* kp = static_cast<const TS*>(a.kprev);
+  TS* out = static_cast<TS*>(a.out);
   for (int v = 0; v < a.nvars; ++v) {
     const int64_t s = e.src + v * a.vstride;
-    const double val = a.kprev ? a.yn[s] + a.cdt * a.kprev[s] : a.yn[s];
-    a.out[e.dst + v * a.vstride] = val;
+    out[e.dst + v * a.vstride] = kp ? yn[s] + TS(a.cdt) * kp[s] : yn[s];
   }
 }
 
 // Prolongation of the parent's (y_n, k1..k4) to one refinement-boundary
 // point, x first, then y, then z, with the degree-5 Lagrange midpoint
 // weights at odd fine indices and a copy at even ones; then each requested
-// dense-output combination  P[y_n] + H (((w1 P[k1] + w2 P[k2]) + w3 P[k3]) + w4 P[k4]).
+// dense-output combination  P[y_n] + H (((w1 P[k1] + w2 P[k2]) + w3 P[k3]) + w4 P[k4]),
+// all in FP64.
+template <typename TK, typename TO>
 __global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
@@ -240,19 +258,23 @@ __global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
   for (int v = 0; v < a.nvars; ++v) {
     double Pv[5];
     for (int m = 0; m < 5; ++m) {
-      const double* A = a.pv[m] + P.base + v * a.pvstride;
+      const int64_t vb = P.base + v * a.pvstride;
       double pz = 0.0;
       for (int jz = 0; jz < ns[2]; ++jz) {
         double py = 0.0;
         for (int jy = 0; jy < ns[1]; ++jy) {
-          const double* row = A + off[2][jz] + off[1][jy];
+          const int64_t rowo = vb + off[2][jz] + off[1][jy];
+          auto at = [&](int jx) -> double {
+            return m == 0 ? a.py[rowo + off[0][jx]]
+                          : (double)static_cast<const TK*>(a.pk[m - 1])[rowo + off[0][jx]];
+          };
           double px;
           if (ns[0] == 6) {
-            px = W[0] * row[off[0][0]];
+            px = W[0] * at(0);
 #pragma unroll
-            for (int jx = 1; jx < 6; ++jx) px = px + W[jx] * row[off[0][jx]];
+            for (int jx = 1; jx < 6; ++jx) px = px + W[jx] * at(jx);
           } else {
-            px = row[off[0][0]];
+            px = at(0);
           }
           if (ns[1] == 6) py = (jy == 0) ? W[0] * px : py + W[jy] * px;
           else py = px;
@@ -265,7 +287,7 @@ __global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
     for (int o = 0; o < a.nout; ++o) {
       const double s =
           ((a.w[o][0] * Pv[1] + a.w[o][1] * Pv[2]) + a.w[o][2] * Pv[3]) + a.w[o][3] * Pv[4];
-      a.out[o][e.dst + v * a.ovstride] = Pv[0] + a.H * s;
+      static_cast<TO*>(a.out[o])[e.dst + v * a.ovstride] = (TO)(Pv[0] + a.H * s);
     }
   }
 }
@@ -285,7 +307,11 @@ __global__ __launch_bounds__(256) void k_restrict(RestrictArgs a) {
   const BoxDev P = a.pboxes[R.pbox];
   const int64_t fo = padded_offset(F, 2 * cx - F.lo[0], 2 * cy - F.lo[1], 2 * cz - F.lo[2]);
   const int64_t po = padded_offset(P, cx - P.lo[0], cy - P.lo[1], cz - P.lo[2]);
-  for (int v = 0; v < a.nvars; ++v) a.py[po + v * a.pvstride] = a.fy[fo + v * a.fvstride];
+  for (int v = 0; v < a.nvars; ++v) {
+    const double y = a.fy[fo + v * a.fvstride];
+    a.py[po + v * a.pvstride] = y;
+    if (a.py32) a.py32[po + v * a.pvstride] = (float)y;
+  }
 }
 
 __device__ __forceinline__ int64_t canonical_to_offset(const PackArgs& a, int64_t i) {
@@ -299,21 +325,25 @@ __device__ __forceinline__ int64_t canonical_to_offset(const PackArgs& a, int64_
   return padded_offset(B, x, y, z);
 }
 
+template <typename T>
 __global__ __launch_bounds__(256) void k_pack(PackArgs a, int unpack) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const int64_t o = canonical_to_offset(a, i);
-  if (unpack) a.arr[o] = a.buf[i];
-  else a.buf[i] = a.arr[o];
+  T* arr = static_cast<T*>(a.arr);
+  if (unpack) arr[o] = (T)a.buf[i];
+  else a.buf[i] = (double)arr[o];
 }
 
 // Deterministic norms: fixed grid, fixed per-thread stride, fixed tree order.
+template <typename T>
 __global__ __launch_bounds__(256) void k_norms_partial(PackArgs a, double* partials) {
   __shared__ double smax[256], ssum[256], sbad[256];
   double m = 0.0, s = 0.0, bad = 0.0;
+  const T* arr = static_cast<const T*>(a.arr);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = a.arr[canonical_to_offset(a, i)];
+    const double v = (double)arr[canonical_to_offset(a, i)];
     if (!isfinite(v)) {
       bad += 1.0;
     } else {
@@ -368,42 +398,61 @@ __global__ __launch_bounds__(256) void k_norms_final(const double* partials, int
   }
 }
 
-__global__ __launch_bounds__(256) void k_gather(const int64_t* idx, int64_t n, const double* src,
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(const int64_t* idx, int64_t n, const T* src,
                                                 double* dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = src[idx[i]];
+  if (i < n) dst[i] = (double)src[idx[i]];
 }
 
-__global__ __launch_bounds__(256) void k_fill(double* p, int64_t n, double v) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* p, int64_t n, T v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
 
+__global__ __launch_bounds__(256) void k_to_f32(const double* src, float* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
 inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+template <typename TS>
+void stage_dispatch(const StageArgs& a, dim3 g, hipStream_t s) {
+  const dim3 b(kStageThreads);
+  switch (a.stage) {
+    case 1: hipLaunchKernelGGL((k_wave_stage<1, TS>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_wave_stage<2, TS>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_wave_stage<3, TS>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_wave_stage<4, TS>), g, b, 0, s, a); break;
+  }
+}
 
 }  // namespace
 
-hipError_t launch_stage(const StageArgs& a, int grid, bool /*write_k*/, hipStream_t s) {
+hipError_t launch_stage(const StageArgs& a, int grid, bool f32, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
-  const dim3 g(grid > 0 ? grid : a.ntiles), b(kStageThreads);
-  switch (a.stage) {
-    case 1: hipLaunchKernelGGL(k_wave_stage<1>, g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_wave_stage<2>, g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_wave_stage<3>, g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL(k_wave_stage<4>, g, b, 0, s, a); break;
-  }
+  const dim3 g(grid > 0 ? grid : a.ntiles);
+  if (f32) stage_dispatch<float>(a, g, s);
+  else stage_dispatch<double>(a, g, s);
   return hipGetLastError();
 }
 
-hipError_t launch_sync(const SyncArgs& a, hipStream_t s) {
+hipError_t launch_sync(const SyncArgs& a, bool f32, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sync, dim3(blocks_for(a.n)), dim3(256), 0, s, a);
+  if (f32) hipLaunchKernelGGL(k_sync<float>, dim3(blocks_for(a.n)), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_sync<double>, dim3(blocks_for(a.n)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_prolong(const ProlongArgs& a, hipStream_t s) {
+hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prolong, dim3(blocks_for(a.n)), dim3(256), 0, s, a);
+  const dim3 g(blocks_for(a.n)), b(256);
+  if (!k_f32 && !out_f32) hipLaunchKernelGGL((k_prolong<double, double>), g, b, 0, s, a);
+  else if (k_f32 && out_f32) hipLaunchKernelGGL((k_prolong<float, float>), g, b, 0, s, a);
+  else if (k_f32) hipLaunchKernelGGL((k_prolong<float, double>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_prolong<double, float>), g, b, 0, s, a);
   return hipGetLastError();
 }
 
@@ -413,29 +462,49 @@ hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pack(const PackArgs& a, bool unpack, hipStream_t s) {
+hipError_t launch_pack(const PackArgs& a, bool unpack, bool f32, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pack, dim3(blocks_for(a.n)), dim3(256), 0, s, a, unpack ? 1 : 0);
+  if (f32)
+    hipLaunchKernelGGL(k_pack<float>, dim3(blocks_for(a.n)), dim3(256), 0, s, a, unpack ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_pack<double>, dim3(blocks_for(a.n)), dim3(256), 0, s, a, unpack ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_norms(const PackArgs& a, double* partials, int nparts, double* out,
+hipError_t launch_norms(const PackArgs& a, bool f32, double* partials, int nparts, double* out,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_norms_partial, dim3(nparts), dim3(256), 0, s, a, partials);
+  if (f32) hipLaunchKernelGGL(k_norms_partial<float>, dim3(nparts), dim3(256), 0, s, a, partials);
+  else hipLaunchKernelGGL(k_norms_partial<double>, dim3(nparts), dim3(256), 0, s, a, partials);
   hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(256), 0, s, partials, nparts, a.n, out);
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const int64_t* idx, int64_t n, const double* src, double* dst,
+hipError_t launch_gather(const int64_t* idx, int64_t n, const void* src, bool f32, double* dst,
                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n)), dim3(256), 0, s, idx, n, src, dst);
+  if (f32)
+    hipLaunchKernelGGL(k_gather<float>, dim3(blocks_for(n)), dim3(256), 0, s, idx, n,
+                       static_cast<const float*>(src), dst);
+  else
+    hipLaunchKernelGGL(k_gather<double>, dim3(blocks_for(n)), dim3(256), 0, s, idx, n,
+                       static_cast<const double*>(src), dst);
   return hipGetLastError();
 }
 
-hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+hipError_t launch_fill(void* p, int64_t n, double v, bool f32, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, s, p, n, v);
+  if (f32)
+    hipLaunchKernelGGL(k_fill<float>, dim3(blocks_for(n)), dim3(256), 0, s,
+                       static_cast<float*>(p), n, (float)v);
+  else
+    hipLaunchKernelGGL(k_fill<double>, dim3(blocks_for(n)), dim3(256), 0, s,
+                       static_cast<double*>(p), n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(n)), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
 

@@ -14,7 +14,13 @@ namespace sc {
 
 struct TileShape {
   int tx = kTileMaxX, ty = kTileMaxY, tz = 16;
+  int grid = 0;   // persistent workgroups for the batched stage kernel (0: context default)
 };
+
+// z-chunk depths the autotuner tries; the tile table region is sized for the
+// shallowest (most tiles).
+constexpr int kTuneTz[] = {8, 12, 16, 24, 32, 48, 64, 1 << 20};
+constexpr int kTuneTzMin = 8;
 
 struct LevelDev {
   int nb_member = 0;                 // boxes per member
@@ -32,17 +38,22 @@ struct LevelDev {
   std::vector<RestrictRegion> restr;
   int64_t restr_total = 0;
   std::vector<TileDev> tiles;        // batched: tiles over the boxes
+  size_t tiles_capacity = 0;         // tile slots reserved in the arena
   std::vector<TileDev> btiles;       // per block: tiles clipped to blocks
   std::vector<int32_t> btile_start;  // nblocks (all members) + 1
   TileShape shape;
   int nyh = 1;
   bool has_child = false;
   // arena offsets (bytes)
-  size_t o_y[2], o_k[4], o_yh[8], o_boxes, o_prefix, o_sync, o_prolong, o_rblist, o_rbfirst,
-      o_phys, o_restr, o_tiles, o_btiles;
-  // device pointers after binding
-  double *y[2] = {nullptr, nullptr}, *k[4] = {nullptr, nullptr, nullptr, nullptr};
-  double* Yh[8] = {nullptr};
+  size_t o_y[2], o_y32[2], o_k[4], o_yh[8], o_boxes, o_prefix, o_sync, o_prolong, o_rblist,
+      o_rbfirst, o_phys, o_restr, o_tiles, o_btiles;
+  // device pointers after binding.  y: FP64 state; y32: its FP32 shadow
+  // (mixed mode only); k and Yh hold the stencil type (FP64, or FP32 in
+  // mixed mode).
+  double *y[2] = {nullptr, nullptr};
+  float* y32[2] = {nullptr, nullptr};
+  void* k[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* Yh[8] = {nullptr};
   BoxDev* d_boxes = nullptr;
   int64_t* d_prefix = nullptr;
   SyncEntry* d_sync = nullptr;
@@ -68,6 +79,8 @@ struct sc_ctx {
   sc::Hierarchy hier;
   std::vector<sc::LevelDev> lev;
   int nvars = 2;
+  bool mixed = false;   // SC_MIXED: FP32 stencil operands
+  size_t esz = 8;       // bytes per element of k and Yh arrays
   size_t arena_bytes = 0;
   size_t o_stage = 0, o_partials = 0, o_norm_out = 0;
   int64_t stage_elems = 0;

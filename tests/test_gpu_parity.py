@@ -183,3 +183,20 @@ def test_norms_and_nonfinite_flag():
     ctx.set_initial_data(0, 1, 0, bad)
     assert ctx.check_finite() == sc.SC_E_NONFINITE
     assert ctx.norms(0, 1, 0)[2] == 1
+
+
+def test_autotuned_tiles_bitwise_equal():
+    spec = config_c3(64, nlev=4)
+    outs = []
+    for tune in (False, True):
+        ctx = _gpu(spec)
+        for l in range(spec.nlevels):
+            for v, f in enumerate(pulses_on_spec(spec, l)):
+                ctx.set_initial_data(0, l, v, f)
+        if tune:
+            ctx.autotune(1)
+            print([ctx.tile_shape(l) for l in range(spec.nlevels)])
+        ctx.advance(2)
+        outs.append([ctx.read_back(0, l, v) for l in range(spec.nlevels) for v in range(2)])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
