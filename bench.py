@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -74,6 +76,133 @@ def cpu_baseline():
                       f"({spec.total_points()} points, {u} point-updates), {dt:.1f} s"}
 
 
+def composite_weights(spec, level):
+    """dx^3 on points not covered by a finer level (each point counted on the
+    finest level that has it), else 0; canonical order of the level."""
+    from workloads import canonical_coords
+    n = spec.npoints(level)
+    w = np.full(n, spec.dx(level) ** 3)
+    if level + 1 < spec.nlevels:
+        idx = []
+        for lo, hi in spec.boxes(level):
+            z, y, x = np.meshgrid(*[np.arange(lo[d], hi[d] + 1) for d in (2, 1, 0)], indexing="ij")
+            idx.append(np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1))
+        idx = np.concatenate(idx)
+        cov = np.zeros(n, dtype=bool)
+        for lo, hi in spec.boxes(level + 1):
+            inside = np.ones(n, dtype=bool)
+            for d in range(3):
+                inside &= (2 * idx[:, d] >= lo[d]) & (2 * idx[:, d] <= hi[d])
+            cov |= inside
+        w[cov] = 0.0
+    return w
+
+
+def z4c_run(args):
+    """Z4c two-puncture evolution on the 7-level 96^3 tower hierarchy."""
+    import torch
+    import paper_2503_09629_amd as sc
+    from workloads import brill_lindquist, brill_lindquist_on_spec, canonical_coords, config_c5
+    spec = config_c5(96)
+    U = spec.updates_per_coarse_step()
+    log(f"workload {spec.name}: {spec.total_points()} points, {U} updates per coarse step")
+    ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=sc.SC_EXEC_GRAPH)
+    ctx.build_spec(spec)
+    ctx.bind()
+    for l in range(spec.nlevels):
+        for v, f in enumerate(brill_lindquist_on_spec(spec, l)):
+            ctx.set_initial_data(0, l, v, f)
+        p = ctx.phys_points(l)
+        if len(p):
+            vals = brill_lindquist(p[:, 0], p[:, 1], p[:, 2])
+            for v in range(22):
+                ctx.set_phys_data(0, l, v, vals[v])
+    masks = []
+    for l in range(spec.nlevels):
+        x, y, z = canonical_coords(spec, l)
+        masks.append((composite_weights(spec, l), np.sqrt(x * x + y * y + z * z) < 30.0))
+
+    def hnorm():
+        num = den = 0.0
+        for l in range(spec.nlevels):
+            H = ctx.hamiltonian(0, l)
+            alpha = ctx.read_back(0, l, 18)
+            w, inside = masks[l]
+            m = inside & (alpha > 0.3)
+            num += float(np.sum(w[m] * H[m] ** 2))
+            den += float(np.sum(w[m]))
+        return np.sqrt(num / den) if den > 0 else float("nan")
+
+    hist = []
+    ctx.advance(1)
+    ctx.synchronize()
+    hist.append((ctx.level_time(0), hnorm()))
+    steps = args.z4c_steps - 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.advance(steps)
+    ctx.synchronize()
+    T = time.perf_counter() - t0
+    hist.append((ctx.level_time(0), hnorm()))
+    log(f"z4c: {1e3 * T / steps:.1f} ms per coarse step, {U * steps / T:.4g} updates/s")
+    finite = ctx.check_finite() == sc.SC_OK
+    return {"metric": "Z4c grid-point updates/s (subcycled RK4, 22 variables)",
+            "value": U * steps / T, "unit": "grid-point updates/s", "n_gpus": 1,
+            "steps": steps, "ms_per_step": 1e3 * T / steps, "dtype": "f64",
+            "config": {"workload": "Z4c Brill-Lindquist punctures m=0.5 at x=+-3, 7 levels of "
+                                   "96^3, [-128,128]^3, graph mode"},
+            "hamiltonian_L2": [{"t": t, "H": h} for t, h in hist], "finite": finite}
+
+
+def precision_report(args):
+    """Mixed vs FP64: max-norm difference per level and observed orders."""
+    import paper_2503_09629_amd as sc
+    from workloads import config_c3, pulses_on_spec
+    res = {}
+    for n0 in args.report_n0:
+        spec = config_c3(n0)
+        nsteps = int(round(0.125 / (0.25 * 2.0 / n0)))
+        out = {}
+        for prec in (sc.SC_FP64, sc.SC_MIXED):
+            ctx = make_context(sc, spec, sc.SC_EXEC_GRAPH, [pulses_on_spec(spec, l) for l in
+                                                            range(spec.nlevels)], prec)
+            ctx.advance(nsteps)
+            out[prec] = [ctx.read_back(0, l, 0) for l in range(spec.nlevels)]
+            ctx.close()
+        res[n0] = out
+        log(f"precision report: N0={n0} done")
+    levels = []
+    n0s = list(args.report_n0)
+    for l in range(7):
+        row = {"level": l, "max_abs_mixed_minus_fp64": {}, "order_fp64": None, "order_mixed": None}
+        for n0 in n0s:
+            row["max_abs_mixed_minus_fp64"][n0] = float(np.abs(res[n0][0][l] - res[n0][1][l]).max())
+        if len(n0s) == 3:
+            for prec, key in ((0, "order_fp64"), (1, "order_mixed")):
+                a, b, c = (res[n].get(prec)[l] for n in n0s)
+                shp = [config_c3(n).boxes(l) for n in n0s]
+                fa = _common(a, shp[0], 1)
+                fb = _common(b, shp[1], 2)
+                fc = _common(c, shp[2], 4)
+                e1 = np.abs(fa - fb).max()
+                e2 = np.abs(fb - fc).max()
+                row[key] = float(np.log2(e1 / e2)) if e2 > 0 else None
+        levels.append(row)
+    return {"report": "mixed precision vs FP64, 7-level tower hierarchy, t = 1/8",
+            "n0": n0s, "levels": levels}
+
+
+def _common(u, boxes, stride):
+    """Points of a level common to all three resolutions (every stride-th point)."""
+    out, off = [], 0
+    for lo, hi in boxes:
+        n = [hi[d] - lo[d] + 1 for d in range(3)]
+        a = u[off:off + n[0] * n[1] * n[2]].reshape(n[2], n[1], n[0])
+        out.append(a[::stride, ::stride, ::stride].ravel())
+        off += n[0] * n[1] * n[2]
+    return np.concatenate(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,11 +212,20 @@ def main():
     ap.add_argument("--modes", default="graph,batched,per_block,mixed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--workload", default="wave", choices=("wave", "z4c", "precision"))
+    ap.add_argument("--z4c-steps", type=int, default=16)
+    ap.add_argument("--report-n0", type=int, nargs="+", default=[64, 128, 256])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "layout is a design, not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "z4c":
+        print(json.dumps(z4c_run(args)), flush=True)
+        return
+    if args.workload == "precision":
+        print(json.dumps(precision_report(args)), flush=True)
+        return
 
     import torch
     import paper_2503_09629_amd as sc

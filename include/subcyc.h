@@ -48,8 +48,12 @@ typedef enum {
 } sc_status;
 
 /* Right-hand sides.  SC_RHS_WAVE: the scalar wave as a first-order system,
- * du/dt = Pi, dPi/dt = Laplacian(u) (Sec. IV.A); variables (u, Pi). */
-enum { SC_RHS_WAVE = 0 };
+ * du/dt = Pi, dPi/dt = Laplacian(u) (Sec. IV.A); variables (u, Pi).
+ * SC_RHS_Z4C: the Z4c system with the puncture gauge (Sec. III.A), vacuum,
+ * 22 variables in the slot order W, gt_xx, gt_xy, gt_xz, gt_yy, gt_yz, gt_zz,
+ * Khat, At_xx, At_xy, At_xz, At_yy, At_yz, At_zz, Theta, Gt^x, Gt^y, Gt^z,
+ * alpha, beta^x, beta^y, beta^z (FP64 only). */
+enum { SC_RHS_WAVE = 0, SC_RHS_Z4C = 1 };
 
 /* Precision of the right-hand-side stencil.  SC_MIXED reads FP32 shadow
  * copies of the stage vectors and evaluates the stencil in FP32; the state,
@@ -86,10 +90,15 @@ typedef struct {
   int32_t reserved;
   double ko_sigma;     /* Kreiss-Oliger strength sigma (Sec. III.C), e.g. 0.32 */
   double cfl;          /* dt_l = cfl * dx_l, 0 < cfl <= 0.5 */
+  double z4c_kappa1;   /* Z4c constraint damping kappa_1 (default 0.02) */
+  double z4c_kappa2;   /* kappa_2 (default 0) */
+  double z4c_eta_c;    /* shift damping eta(r) = (eta_c - eta_o) exp(-(r/eta_s)^4) + eta_o, */
+  double z4c_eta_o;    /*   r the distance from the coordinate origin; defaults 2, 0.25, 40 */
+  double z4c_eta_s;    /*   (Sec. III.A, M = 1) */
 } sc_config;
 
 /* Fill *cfg with the defaults: wave RHS, FP64, batched, nghost 3,
- * sigma 0.32, cfl 0.25. */
+ * sigma 0.32, cfl 0.25, Z4c kappa1 0.02, kappa2 0, eta 2 / 0.25 / 40. */
 int sc_config_default(sc_config* cfg);
 
 /* Create a context that enqueues on hip_stream (a hipStream_t owned by the
@@ -159,6 +168,16 @@ int sc_bind_device_memory(sc_ctx* ctx, void* dptr, size_t nbytes);
 int sc_set_initial_data(sc_ctx* ctx, int32_t member, int32_t level, int32_t var,
                         const double* host, int64_t n);
 
+/* Physical-boundary ghosts (non-periodic domains) hold frozen values set by
+ * the caller.  sc_phys_count: number of such halo points of a level (one
+ * member); sc_phys_points: their coordinates as xyz triples (3n doubles) in
+ * the library's order; sc_set_phys_data: values of one variable at those
+ * points, same order, copied into every ghost table of the level. */
+int sc_phys_count(const sc_ctx* ctx, int32_t level, int64_t* n);
+int sc_phys_points(const sc_ctx* ctx, int32_t level, double* xyz, int64_t n);
+int sc_set_phys_data(sc_ctx* ctx, int32_t member, int32_t level, int32_t var,
+                     const double* host, int64_t n);
+
 /* Advance the whole hierarchy by ncoarse coarse steps with the recursive
  * subcycling schedule (Sec. II, steps 1-7): a level takes one RK4 step,
  * prolongs (y_n, k1..k4) to its child's refinement boundary, the child takes
@@ -181,7 +200,9 @@ int sc_fill_ghosts(sc_ctx* ctx, int32_t level, int32_t which, int32_t substep);
 int sc_restrict(sc_ctx* ctx, int32_t fine_level);
 
 /* Read one array (SC_ARR_*) of one variable on the owned points of a level of
- * a member, canonical order, n = owned points.  Synchronises the stream. */
+ * a member, canonical order, n = owned points.  Synchronises the stream.
+ * The wave stencil keeps k4 only on levels that have a finer level (nothing
+ * else reads it); SC_ARR_K4 on the finest level returns SC_E_STATE. */
 int sc_read_back(sc_ctx* ctx, int32_t member, int32_t level, int32_t var, int32_t array,
                  double* host, int64_t n);
 
@@ -197,6 +218,13 @@ int sc_read_rb(sc_ctx* ctx, int32_t member, int32_t level, int32_t which, int32_
  * out[2] = number of non-finite values.  Synchronises the stream. */
 int sc_norms(sc_ctx* ctx, int32_t member, int32_t level, int32_t var, int32_t array,
              double out[3]);
+
+/* Z4c only: Hamiltonian constraint H = R + 2/3 (Khat + 2 Theta)^2 - At_ij At^ij
+ * (vacuum) of the current state on the owned points of a level of a member,
+ * canonical order, n = owned points.  Fills the state's ghosts first (SYNC,
+ * physical, and the dense-output end value of the second substep on
+ * refinement boundaries), so call it between coarse steps.  Synchronises. */
+int sc_hamiltonian(sc_ctx* ctx, int32_t member, int32_t level, double* host, int64_t n);
 
 /* SC_E_NONFINITE if any owned value of the state is not finite on any level. */
 int sc_check_finite(sc_ctx* ctx);

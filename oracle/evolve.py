@@ -163,25 +163,39 @@ class _Prolongation:
         return out
 
 
+Z4C_DEFAULTS = dict(kappa1=0.02, kappa2=0.0, eta_c=2.0, eta_o=0.25, eta_s=40.0)
+
+
 class OracleRun:
     """Reference evolution of one member of a hierarchy.
 
-    rhs: "wave" (variables u, Pi).  sigma: Kreiss-Oliger strength.  cfl:
-    dt_l = cfl * dx_l.
+    rhs: "wave" (variables u, Pi) or "z4c" (22 variables, Sec. III.A; see
+    oracle/z4c.c).  sigma: Kreiss-Oliger strength.  cfl: dt_l = cfl * dx_l.
+    z4c: kappa1, kappa2, eta_c, eta_o, eta_s.
     """
 
     def __init__(self, hier: Hierarchy, rhs: str = "wave", sigma: float = 0.32,
-                 cfl: float = 0.25):
-        if rhs != "wave":
+                 cfl: float = 0.25, z4c: dict = None):
+        if rhs not in ("wave", "z4c"):
             raise ValueError(rhs)
+        self.rhs_kind = rhs
         self.hier = hier
         self.spec = hier.spec
-        self.nvars = 2
+        self.nvars = 2 if rhs == "wave" else 22
+        z = dict(Z4C_DEFAULTS, **(z4c or {}))
+        self.z4c_par = np.array([z["kappa1"], z["kappa2"], z["eta_c"], z["eta_o"], z["eta_s"],
+                                 sigma])
         self.sigma = sigma
         self.cfl = cfl
         self.lib = cbuild.lib()
         self.L = hier.nlevels
         self.st = [_LevelState(hier, l, self.nvars) for l in range(self.L)]
+        # coordinates of every block's owned point (0,0,0), for position-dependent terms
+        self.block_origin = []
+        for l in range(self.L):
+            lo = hier.levels[l].blocks[:, 0, :].astype(np.float64)
+            o = np.array(self.spec.origin)[None, :] + lo * self.spec.dx(l)
+            self.block_origin.append(np.ascontiguousarray(o.ravel()))
         self.pro = [None] + [_Prolongation(hier, l, self.st[l - 1]) for l in range(1, self.L)]
         self.P = [None] * self.L           # prolonged (y_n, k1..k4) per level
         self.theta0 = [0.0] * self.L
@@ -205,6 +219,17 @@ class OracleRun:
     def set_phys(self, l: int, values: np.ndarray) -> None:
         self.st[l].phys_vals[:] = values
 
+    def phys_coords(self, l: int) -> np.ndarray:
+        """x, y, z of the level's PHYS ghost slots, in fill order."""
+        lev = self.hier.levels[l]
+        pts = []
+        for b in range(lev.nblocks):
+            kind = self.hier.ghosts[l][b][0]
+            p = lev.ghost_points(b)
+            pts.append(p[kind == PHYS])
+        p = np.concatenate(pts) if pts else np.zeros((0, 3), dtype=np.int64)
+        return np.array(self.spec.origin)[None, :] + p * self.spec.dx(l)
+
     # -- pieces of the algorithm ---------------------------------------------
     def rb_values(self, l: int, stage: int) -> np.ndarray:
         Py, Pk1, Pk2, Pk3, Pk4 = self.P[l]
@@ -225,8 +250,32 @@ class OracleRun:
 
     def rhs(self, l: int, Y: np.ndarray, k: np.ndarray) -> None:
         st = self.st[l]
-        self.lib.orc_wave_rhs(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
-                              cbuild.ptr(Y), cbuild.ptr(k), self.dx[l], self.sigma)
+        if self.rhs_kind == "wave":
+            self.lib.orc_wave_rhs(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
+                                  cbuild.ptr(Y), cbuild.ptr(k), self.dx[l], self.sigma)
+        else:
+            self.lib.orc_z4c_rhs(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
+                                 cbuild.ptr(Y), cbuild.ptr(k), self.dx[l],
+                                 cbuild.ptr(self.z4c_par), cbuild.ptr(self.block_origin[l]),
+                                 None, None)
+
+    def hamiltonian(self, l: int) -> np.ndarray:
+        """Hamiltonian constraint of the current state on owned points (canonical order)."""
+        st = self.st[l]
+        A = st.y.copy()
+        saved = self.P[l]
+        if l > 0 and saved is None:
+            # before the first step: ghosts from the parent's current state
+            z = np.zeros((self.nvars, self.pro[l].n))
+            self.P[l] = [self.pro[l].apply(self.st[l - 1].y), z, z, z, z]
+        self.fill(l, A, 5)
+        self.P[l] = saved
+        k = np.zeros_like(A)
+        ham = np.zeros(st.total)
+        self.lib.orc_z4c_rhs(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
+                             cbuild.ptr(A), cbuild.ptr(k), self.dx[l], cbuild.ptr(self.z4c_par),
+                             cbuild.ptr(self.block_origin[l]), None, cbuild.ptr(ham))
+        return ham[st.canon]
 
     def rk4_step(self, l: int) -> None:
         st = self.st[l]

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libsubcyc.so")
 
 SC_OK, SC_E_ARG, SC_E_STATE, SC_E_NEST, SC_E_MEM, SC_E_HIP, SC_E_NONFINITE = 0, -1, -2, -3, -4, -5, -6
-SC_RHS_WAVE = 0
+SC_RHS_WAVE, SC_RHS_Z4C = 0, 1
 SC_FP64, SC_MIXED = 0, 1
 SC_EXEC_PER_BLOCK, SC_EXEC_BATCHED, SC_EXEC_GRAPH = 0, 1, 2
 SC_ARR_Y, SC_ARR_K1, SC_ARR_K2, SC_ARR_K3, SC_ARR_K4, SC_ARR_YN = range(6)
@@ -26,7 +26,8 @@ SC_ABI_VERSION = 1
 EXPORTED = [
     "sc_config_default", "sc_create", "sc_destroy", "sc_last_error", "sc_build_hierarchy",
     "sc_get_counts", "sc_export_maps", "sc_device_bytes", "sc_bind_device_memory",
-    "sc_set_initial_data", "sc_advance", "sc_step_level", "sc_prolongate", "sc_fill_ghosts",
+    "sc_set_initial_data", "sc_phys_count", "sc_phys_points", "sc_set_phys_data",
+    "sc_hamiltonian", "sc_advance", "sc_step_level", "sc_prolongate", "sc_fill_ghosts",
     "sc_restrict", "sc_read_back", "sc_read_rb", "sc_norms", "sc_check_finite",
     "sc_level_time", "sc_set_exec", "sc_poison_halos", "sc_autotune", "sc_tile_shape",
     "sc_profile_enable",
@@ -38,7 +39,10 @@ class ScConfig(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_int32), ("rhs", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("exec", ctypes.c_int32),
                 ("nghost", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("ko_sigma", ctypes.c_double), ("cfl", ctypes.c_double)]
+                ("ko_sigma", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("z4c_kappa1", ctypes.c_double), ("z4c_kappa2", ctypes.c_double),
+                ("z4c_eta_c", ctypes.c_double), ("z4c_eta_o", ctypes.c_double),
+                ("z4c_eta_s", ctypes.c_double)]
 
 
 class ScBox(ctypes.Structure):
@@ -78,6 +82,10 @@ def lib():
             "sc_device_bytes": [P, P],
             "sc_bind_device_memory": [P, P, sz],
             "sc_set_initial_data": [P, i32, i32, i32, P, i64],
+            "sc_phys_count": [P, i32, P],
+            "sc_phys_points": [P, i32, P, i64],
+            "sc_set_phys_data": [P, i32, i32, i32, P, i64],
+            "sc_hamiltonian": [P, i32, i32, P, i64],
             "sc_advance": [P, i32],
             "sc_step_level": [P, i32, i32],
             "sc_prolongate": [P, i32],
@@ -119,7 +127,8 @@ class Context:
     """
 
     def __init__(self, sigma: float = 0.32, cfl: float = 0.25, exec: int = SC_EXEC_BATCHED,
-                 precision: int = SC_FP64, stream=None, device: Optional[str] = None):
+                 precision: int = SC_FP64, stream=None, device: Optional[str] = None,
+                 rhs: int = SC_RHS_WAVE, z4c: Optional[dict] = None):
         self.L = lib()
         cfg = ScConfig()
         self._check(self.L.sc_config_default(ctypes.byref(cfg)), None)
@@ -127,6 +136,10 @@ class Context:
         cfg.cfl = cfl
         cfg.exec = exec
         cfg.precision = precision
+        cfg.rhs = rhs
+        for k, v in (z4c or {}).items():
+            setattr(cfg, "z4c_" + k, v)
+        self.nvars = 22 if rhs == SC_RHS_Z4C else 2
         self.torch = None
         self.stream = stream
         handle = None
@@ -222,6 +235,24 @@ class Context:
     def set_initial_data(self, member: int, level: int, var: int, values):
         a = np.ascontiguousarray(values, dtype=np.float64)
         self._check(self.L.sc_set_initial_data(self.ctx, member, level, var, _p(a), a.size))
+
+    def phys_points(self, level: int) -> np.ndarray:
+        n = ctypes.c_int64()
+        self._check(self.L.sc_phys_count(self.ctx, level, ctypes.byref(n)))
+        out = np.empty((n.value, 3))
+        if n.value:
+            self._check(self.L.sc_phys_points(self.ctx, level, _p(out), n.value))
+        return out
+
+    def set_phys_data(self, member: int, level: int, var: int, values):
+        a = np.ascontiguousarray(values, dtype=np.float64)
+        self._check(self.L.sc_set_phys_data(self.ctx, member, level, var, _p(a), a.size))
+
+    def hamiltonian(self, member: int, level: int) -> np.ndarray:
+        n = self.counts(level)[1]
+        out = np.empty(n)
+        self._check(self.L.sc_hamiltonian(self.ctx, member, level, _p(out), n))
+        return out
 
     def read_back(self, member: int, level: int, var: int, array: int = SC_ARR_Y) -> np.ndarray:
         n = self.counts(level)[1]

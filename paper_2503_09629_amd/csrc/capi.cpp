@@ -7,6 +7,7 @@
 #include <numeric>
 
 #include "runtime.hpp"
+#include "z4c.hpp"
 
 using namespace sc;
 
@@ -211,6 +212,7 @@ std::string build_layout(sc_ctx* c) {
             M.wrap(p, q);
             if (M.outside(q)) {
               phys0.push_back(dst);
+              L.phys_q.insert(L.phys_q.end(), {p[0], p[1], p[2]});
               continue;
             }
             int ob = M.box_of(q);
@@ -245,6 +247,16 @@ std::string build_layout(sc_ctx* c) {
       }
       for (auto d : phys0) L.phys.push_back(d + off);
     }
+    // prolongation entries grouped by parity class (stable: halo order kept
+    // within a class), so a workgroup runs one stencil shape
+    {
+      auto cls = [](const ProlongEntry& e) { return (e.q[0] & 1) | ((e.q[1] & 1) << 1) | ((e.q[2] & 1) << 2); };
+      std::stable_sort(L.prolong.begin(), L.prolong.end(),
+                       [&](const ProlongEntry& x, const ProlongEntry& y) { return cls(x) < cls(y); });
+      for (int k = 0; k < 9; ++k) L.prolong_cls[k] = 0;
+      for (const auto& e : L.prolong) ++L.prolong_cls[cls(e) + 1];
+      for (int k = 0; k < 8; ++k) L.prolong_cls[k + 1] += L.prolong_cls[k];
+    }
     // RB list (sorted) entries for readers
     L.nrb = (int64_t)M.rb.size();
     for (int m = 0; m < nm; ++m)
@@ -260,6 +272,15 @@ std::string build_layout(sc_ctx* c) {
         if (it == first.end()) return "RB list entry without a halo slot";
         L.rbfirst.push_back(it->second + m * L.member_total);
       }
+    {
+      auto cls = [](const ProlongEntry& e) { return (e.q[0] & 1) | ((e.q[1] & 1) << 1) | ((e.q[2] & 1) << 2); };
+      for (int m = 0; m < nm; ++m)
+        std::stable_sort(L.rblist.begin() + m * L.nrb, L.rblist.begin() + (m + 1) * L.nrb,
+                         [&](const ProlongEntry& x, const ProlongEntry& y) { return cls(x) < cls(y); });
+      for (int k = 0; k < 9; ++k) L.rblist_cls[k] = 0;
+      for (int64_t j = 0; j < L.nrb; ++j) ++L.rblist_cls[cls(L.rblist[j]) + 1];
+      for (int k = 0; k < 8; ++k) L.rblist_cls[k + 1] += L.rblist_cls[k];
+    }
     // restriction regions (this level as the fine level)
     if (l > 0) {
       const LevelMaps& P = H.levels[l - 1];
@@ -405,6 +426,7 @@ void plan_arena(sc_ctx* c) {
     for (int i = 0; i < 2; ++i) L.o_y32[i] = c->mixed ? take(arr / 2) : 0;
     for (int i = 0; i < 4; ++i) L.o_k[i] = take(arrs);
     for (int i = 0; i < L.nyh; ++i) L.o_yh[i] = take(arrs);
+    L.o_ys = c->cfg.rhs == SC_RHS_Z4C ? take(arr) : 0;
     L.o_boxes = take(sizeof(BoxDev) * L.boxes.size());
     L.o_prefix = take(sizeof(int64_t) * L.prefix.size());
     L.o_sync = take(sizeof(SyncEntry) * L.sync.size());
@@ -488,11 +510,13 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
   a.dt6 = L.dt / 6.0;
   a.clap = 1.0 / (12.0 * L.dx * L.dx);
   a.cko = c->cfg.ko_sigma / (64.0 * L.dx);
-  a.write_k = 1;
+  // k4 is read only by the prolongation into a finer level
+  a.write_k = (stage < 4 || L.has_child) ? 1 : 0;
   if (!per_block) {
     a.tiles = L.d_tiles;
     a.ntiles = (int32_t)L.tiles.size();
-    const int grid = std::min<int>(a.ntiles, L.shape.grid > 0 ? L.shape.grid : c->grid_cap);
+    int grid = std::min<int>(a.ntiles, L.shape.grid > 0 ? L.shape.grid : c->grid_cap);
+    grid = (grid + 7) / 8 * 8;  // a multiple of the XCD count (the kernel's tile remap)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->profiling) {
       int rc = take_events(c, &e0, &e1);
@@ -507,7 +531,8 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
       // y_n and y_{n+1} (plus its FP32 shadow in mixed mode)
       static const double fp64[5] = {0, 16, 24, 24, 48};
       static const double mixed[5] = {0, 8, 12, 12, 40};
-      const double per_var = c->mixed ? mixed[stage] : fp64[stage];
+      double per_var = c->mixed ? mixed[stage] : fp64[stage];
+      if (!a.write_k) per_var -= c->esz;  // k4 not stored on the finest level
       c->ev_bytes.push_back(per_var * c->nvars * (double)(L.owned_member * c->hier.geo.nmembers));
     }
     ++c->launches;
@@ -519,6 +544,82 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
       HIPCHK(c, launch_stage(a, a.ntiles, c->mixed, c->stream));
       ++c->launches;
     }
+  }
+  return SC_OK;
+}
+
+Z4cArgs z4c_args(sc_ctx* c, int l) {
+  LevelDev& L = c->lev[l];
+  Z4cArgs a{};
+  a.boxes = L.d_boxes;
+  a.vstride = L.total;
+  a.h = L.dx;
+  a.dt6 = L.dt / 6.0;
+  a.sigma = c->cfg.ko_sigma;
+  a.kappa1 = c->cfg.z4c_kappa1;
+  a.kappa2 = c->cfg.z4c_kappa2;
+  a.eta_c = c->cfg.z4c_eta_c;
+  a.eta_o = c->cfg.z4c_eta_o;
+  a.eta_s = c->cfg.z4c_eta_s;
+  for (int d = 0; d < 3; ++d) a.origin[d] = c->hier.geo.origin[d];
+  return a;
+}
+
+// Z4c stage: materialise Y_s = y_n + c_s dt k_{s-1} (s >= 2), then the RHS.
+int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void* kprev,
+                         const void* yh) {
+  LevelDev& L = c->lev[l];
+  static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
+  Z4cArgs a = z4c_args(c, l);
+  a.stage = stage;
+  a.Y = stage == 1 ? L.y[L.cur] : L.Ys;
+  a.Yh = static_cast<const double*>(yh);
+  a.yn = L.y[L.cur];
+  a.k1 = static_cast<const double*>(L.k[0]);
+  a.k2 = static_cast<const double*>(L.k[1]);
+  a.k3 = static_cast<const double*>(L.k[2]);
+  a.kout = static_cast<double*>(L.k[stage - 1]);
+  a.ynew = L.y[1 - L.cur];
+  Z4cCombineArgs cb{};
+  cb.nvars = c->nvars;
+  cb.boxes = L.d_boxes;
+  cb.yn = L.y[L.cur];
+  cb.kprev = static_cast<const double*>(kprev);
+  cb.Y = L.Ys;
+  cb.vstride = L.total;
+  cb.cdt = cnext[stage] * L.dt;
+  auto run = [&](const TileDev* tiles, int ntiles, int grid) -> int {
+    if (stage >= 2) {
+      cb.tiles = tiles;
+      cb.ntiles = ntiles;
+      HIPCHK(c, launch_z4c_combine(cb, grid, c->stream));
+      ++c->launches;
+    }
+    a.tiles = tiles;
+    a.ntiles = ntiles;
+    HIPCHK(c, launch_z4c_stage(a, grid, c->stream));
+    ++c->launches;
+    return SC_OK;
+  };
+  if (!per_block) return run(L.d_tiles, (int)L.tiles.size(), std::min<int>((int)L.tiles.size(), c->grid_cap));
+  // per block: every block's stage vector must be complete before any block's
+  // stencil reads its neighbours, so all combines go first
+  const int nblk = (int)L.btile_start.size() - 1;
+  if (stage >= 2) {
+    for (int b = 0; b < nblk; ++b) {
+      const int n = L.btile_start[b + 1] - L.btile_start[b];
+      cb.tiles = L.d_btiles + L.btile_start[b];
+      cb.ntiles = n;
+      HIPCHK(c, launch_z4c_combine(cb, n, c->stream));
+      ++c->launches;
+    }
+  }
+  for (int b = 0; b < nblk; ++b) {
+    const int n = L.btile_start[b + 1] - L.btile_start[b];
+    a.tiles = L.d_btiles + L.btile_start[b];
+    a.ntiles = n;
+    HIPCHK(c, launch_z4c_stage(a, n, c->stream));
+    ++c->launches;
   }
   return SC_OK;
 }
@@ -543,7 +644,8 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
       HIPCHK(c, launch_sync(sa, c->mixed, c->stream));
       ++c->launches;
     }
-    int rc = enqueue_stage_launches(c, l, s, per_block, yn, kprev, yh);
+    int rc = c->cfg.rhs == SC_RHS_Z4C ? enqueue_z4c_launches(c, l, s, per_block, kprev, yh)
+                                      : enqueue_stage_launches(c, l, s, per_block, yn, kprev, yh);
     if (rc) return rc;
   }
   L.cur = 1 - L.cur;
@@ -552,14 +654,19 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
 
 // Prolongation from the parent's last step (y_n = the buffer it stepped from,
 // k1..k4) into the fine level: outputs[i] with weights[i].
-int prolong_into(sc_ctx* c, int fl, const ProlongEntry* entries, int64_t n, int nout,
+int prolong_into(sc_ctx* c, int fl, const ProlongEntry* entries, const int64_t* cls, int nout,
                  void* const* outs, const int* fills, const int* subs, int64_t ovstride,
                  bool out_f32, int var_only) {
   LevelDev& P = c->lev[fl - 1];
+  const int64_t n = cls[8];
   if (n <= 0) return SC_OK;
   ProlongArgs a{};
   a.e = entries;
   a.n = n;
+  a.blk_start[0] = 0;
+  for (int k = 0; k < 9; ++k) a.cls_start[k] = cls[k];
+  for (int k = 0; k < 8; ++k)
+    a.blk_start[k + 1] = a.blk_start[k] + (int32_t)((cls[k + 1] - cls[k] + 255) / 256);
   a.pboxes = P.d_boxes;
   a.py = P.y[1 - P.cur];
   for (int i = 0; i < 4; ++i) a.pk[i] = P.k[i];
@@ -593,8 +700,8 @@ int prolongate(sc_ctx* c, int fl) {
       fills[o] = s;
       subs[o] = sub;
     }
-  return prolong_into(c, fl, F.d_prolong, (int64_t)F.prolong.size(), 8, outs, fills, subs,
-                      F.total, c->mixed, -1);
+  return prolong_into(c, fl, F.d_prolong, F.prolong_cls, 8, outs, fills, subs, F.total,
+                      c->mixed, -1);
 }
 
 int restrict_level(sc_ctx* c, int fl) {
@@ -680,6 +787,11 @@ int sc_config_default(sc_config* cfg) {
   cfg->nghost = 3;
   cfg->ko_sigma = 0.32;
   cfg->cfl = 0.25;
+  cfg->z4c_kappa1 = 0.02;
+  cfg->z4c_kappa2 = 0.0;
+  cfg->z4c_eta_c = 2.0;
+  cfg->z4c_eta_o = 0.25;
+  cfg->z4c_eta_s = 40.0;
   return SC_OK;
 }
 
@@ -693,7 +805,8 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
     g_create_error = "abi_version mismatch";
     return SC_E_ARG;
   }
-  if (cfg->rhs != SC_RHS_WAVE || cfg->nghost != 3 || !(cfg->cfl > 0.0 && cfg->cfl <= 0.5) ||
+  const bool rhs_ok = cfg->rhs == SC_RHS_WAVE || (cfg->rhs == SC_RHS_Z4C && cfg->precision == SC_FP64);
+  if (!rhs_ok || cfg->nghost != 3 || !(cfg->z4c_eta_s > 0.0) || !(cfg->cfl > 0.0 && cfg->cfl <= 0.5) ||
       cfg->ko_sigma < 0.0 || (cfg->precision != SC_FP64 && cfg->precision != SC_MIXED) ||
       cfg->exec < 0 || cfg->exec > 2) {
     g_create_error = "unsupported configuration (rhs, nghost 3, 0 < cfl <= 0.5, sigma >= 0, "
@@ -703,6 +816,7 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
   sc_ctx* c = new sc_ctx();
   c->cfg = *cfg;
   c->mixed = cfg->precision == SC_MIXED;
+  c->nvars = cfg->rhs == SC_RHS_Z4C ? 22 : 2;
   c->esz = c->mixed ? sizeof(float) : sizeof(double);
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   for (int sub = 0; sub < 2; ++sub)
@@ -823,6 +937,7 @@ int sc_bind_device_memory(sc_ctx* c, void* dptr, size_t nbytes) {
     for (int i = 0; i < 2; ++i) L.y32[i] = c->mixed ? at<float>(c, L.o_y32[i]) : nullptr;
     for (int i = 0; i < 4; ++i) L.k[i] = at<char>(c, L.o_k[i]);
     for (int i = 0; i < L.nyh; ++i) L.Yh[i] = at<char>(c, L.o_yh[i]);
+    L.Ys = c->cfg.rhs == SC_RHS_Z4C ? at<double>(c, L.o_ys) : nullptr;
     L.d_boxes = at<BoxDev>(c, L.o_boxes);
     L.d_prefix = at<int64_t>(c, L.o_prefix);
     L.d_sync = at<SyncEntry>(c, L.o_sync);
@@ -870,6 +985,77 @@ int sc_set_initial_data(sc_ctx* c, int32_t member, int32_t level, int32_t var,
                             c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->state = 3;
+  return SC_OK;
+}
+
+int sc_phys_count(const sc_ctx* c, int32_t level, int64_t* n) {
+  int rc = check_ready(c, 1);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || !n) return SC_E_ARG;
+  *n = (int64_t)c->lev[level].phys_q.size() / 3;
+  return SC_OK;
+}
+
+int sc_phys_points(const sc_ctx* c, int32_t level, double* xyz, int64_t n) {
+  int rc = check_ready(c, 1);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || !xyz) return SC_E_ARG;
+  const LevelDev& L = c->lev[level];
+  if (n != (int64_t)L.phys_q.size() / 3) return SC_E_ARG;
+  const double dx = L.dx;
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) xyz[3 * i + d] = c->hier.geo.origin[d] + L.phys_q[3 * i + d] * dx;
+  return SC_OK;
+}
+
+int sc_set_phys_data(sc_ctx* c, int32_t member, int32_t level, int32_t var, const double* host,
+                     int64_t n) {
+  int rc = check_ready(c, 2);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || member < 0 ||
+      member >= c->hier.geo.nmembers || var < 0 || var >= c->nvars || !host)
+    return fail(c, SC_E_ARG, "bad physical-ghost arguments");
+  LevelDev& L = c->lev[level];
+  const int64_t per = (int64_t)L.phys_q.size() / 3;
+  if (n != per) return fail(c, SC_E_ARG, "n must equal sc_phys_count");
+  if (per == 0) return SC_OK;
+  if (c->mixed) return fail(c, SC_E_STATE, "physical ghosts need FP64 halo tables");
+  HIPCHK(c, hipMemcpyAsync(c->d_stage, host, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  const int64_t* idx = L.d_phys + member * per;
+  for (int i = 0; i < L.nyh; ++i)
+    HIPCHK(c, launch_scatter(idx, n, c->d_stage, static_cast<double*>(L.Yh[i]) + var * L.total,
+                             c->stream));
+  for (int i = 0; i < 2; ++i)
+    HIPCHK(c, launch_scatter(idx, n, c->d_stage, L.y[i] + var * L.total, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SC_OK;
+}
+
+int sc_hamiltonian(sc_ctx* c, int32_t member, int32_t level, double* host, int64_t n) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  if (c->cfg.rhs != SC_RHS_Z4C) return fail(c, SC_E_STATE, "the Hamiltonian constraint needs Z4c");
+  if (level < 0 || level >= (int)c->lev.size() || member < 0 ||
+      member >= c->hier.geo.nmembers || !host)
+    return fail(c, SC_E_ARG, "bad constraint arguments");
+  LevelDev& L = c->lev[level];
+  if (n != L.owned_member) return fail(c, SC_E_ARG, "n must equal the level's owned points");
+  if (level > 0 && c->lev[level - 1].t == 0.0)
+    return fail(c, SC_E_STATE, "refinement-boundary ghosts need one parent step first");
+  rc = sc_fill_ghosts(c, level, SC_FILL_END, 1);
+  if (rc) return rc;
+  Z4cArgs a = z4c_args(c, level);
+  a.Y = L.y[L.cur];
+  a.Yh = L.y[L.cur];
+  a.ham = L.Ys;   // scratch: one variable's worth of the stage-vector array
+  a.tiles = L.d_tiles;
+  a.ntiles = (int32_t)L.tiles.size();
+  HIPCHK(c, launch_z4c_stage(a, std::min<int>(a.ntiles, c->grid_cap), c->stream));
+  PackArgs pa = member_pack(c, member, level, L.Ys);
+  HIPCHK(c, launch_pack(pa, false, false, c->stream));
+  HIPCHK(c, hipMemcpyAsync(host, c->d_stage, sizeof(double) * n, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return SC_OK;
 }
 
@@ -962,8 +1148,8 @@ int sc_fill_ghosts(sc_ctx* c, int32_t level, int32_t which, int32_t substep) {
   if (level > 0) {
     void* outs[1] = {y};
     const int fills[1] = {which}, subs[1] = {substep};
-    rc = prolong_into(c, level, L.d_prolong, (int64_t)L.prolong.size(), 1, outs, fills, subs,
-                      L.total, false, -1);
+    rc = prolong_into(c, level, L.d_prolong, L.prolong_cls, 1, outs, fills, subs, L.total,
+                      false, -1);
     if (rc) return rc;
   }
   return SC_OK;
@@ -979,6 +1165,8 @@ int sc_read_back(sc_ctx* c, int32_t member, int32_t level, int32_t var, int32_t 
     return fail(c, SC_E_ARG, "bad read-back arguments");
   LevelDev& L = c->lev[level];
   if (n != L.owned_member) return fail(c, SC_E_ARG, "n must equal the level's owned points");
+  if (array == SC_ARR_K4 && !L.has_child && c->cfg.rhs == SC_RHS_WAVE)
+    return fail(c, SC_E_STATE, "k4 is kept only on levels that have a finer level");
   bool f32 = false;
   PackArgs a = member_pack(c, member, level, array_ptr(c, level, array, var, &f32));
   HIPCHK(c, launch_pack(a, false, f32, c->stream));
@@ -1005,8 +1193,8 @@ int sc_read_rb(sc_ctx* c, int32_t member, int32_t level, int32_t which, int32_t 
   } else {
     void* outs[1] = {c->d_stage};
     const int fills[1] = {5}, subs[1] = {substep};
-    rc = prolong_into(c, level, L.d_rblist + member * L.nrb, L.nrb, 1, outs, fills, subs, 0,
-                      false, var);
+    rc = prolong_into(c, level, L.d_rblist + member * L.nrb, L.rblist_cls, 1, outs, fills, subs,
+                      0, false, var);
     if (rc) return rc;
   }
   HIPCHK(c, hipMemcpyAsync(host, c->d_stage, sizeof(double) * n, hipMemcpyDeviceToHost,
@@ -1083,6 +1271,7 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
   if (reps < 1 || reps > 1000) return fail(c, SC_E_ARG, "reps must be in [1, 1000]");
+  if (c->cfg.rhs != SC_RHS_WAVE) return fail(c, SC_E_STATE, "autotuning covers the wave stencil");
   int dev = 0, ncu = 0;
   HIPCHK(c, hipGetDevice(&dev));
   HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));

@@ -97,6 +97,11 @@ struct SyncArgs {
 struct ProlongArgs {
   const ProlongEntry* e;
   int64_t n;
+  // entries are sorted by parity class (odd x = 1, odd y = 2, odd z = 4):
+  // class c occupies [cls_start[c], cls_start[c+1]) and workgroups
+  // [blk_start[c], blk_start[c+1])
+  int64_t cls_start[9];
+  int32_t blk_start[9];
   const BoxDev* pboxes;          // parent level boxes
   const double* py;              // parent y_n (FP64)
   const void* pk[4];             // parent k1..k4 (FP64, or FP32 in mixed mode)
@@ -143,6 +148,8 @@ hipError_t launch_norms(const PackArgs& a, bool f32, double* partials, int npart
 hipError_t launch_gather(const int64_t* idx, int64_t n, const void* src, bool f32, double* dst,
                          hipStream_t s);
 hipError_t launch_fill(void* p, int64_t n, double v, bool f32, hipStream_t s);
+hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, double* dst,
+                          hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 constexpr int kStageThreads = 256;

@@ -72,7 +72,8 @@ __device__ __forceinline__ void ring_coord(int i, int nx, int ny, int* lx, int* 
 // through nz planes.  The x-y plane of stage values (tile plus 3-point ring)
 // is staged in LDS (double buffered): the tile's own points come from the
 // 7-plane z column each thread keeps in registers, only the ring is read from
-// memory, and the ring of the next plane is fetched during the arithmetic.
+// memory, and the loads for the next plane are issued before the arithmetic
+// so their latency overlaps it.
 //   k_u  = Pi + Q u,   k_Pi = Lap u + Q Pi
 //   Lap  = ((d2_x + d2_y) + d2_z) / (12 h^2),  Q = sigma/(64 h) ((ko_x + ko_y) + ko_z)
 // Stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4) in FP64.
@@ -84,7 +85,12 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
   __shared__ TS lds[2][2][LY][LX];
   const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
   const TS clap = TS(a.clap), cko = TS(a.cko);
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+  // consecutive workgroups land on different XCDs (round robin over 8); give
+  // each XCD a contiguous run of tiles so neighbouring tiles share its L2
+  const int g = (gridDim.x % 8 == 0)
+                    ? (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8)
+                    : (int)blockIdx.x;
+  for (int t = g; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
     const int x = T.x0 + tx;
@@ -108,6 +114,7 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
       ry[k] = ly;
     }
     TS q[2][RY][7];
+    TS qn[2][RY];
     TS ring[2][RMAX];
 #pragma unroll
     for (int j = 0; j < 7; ++j)
@@ -115,9 +122,7 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
       for (int r = 0; r < RY; ++r)
 #pragma unroll
         for (int v = 0; v < 2; ++v)
-          q[v][r][j] = (act[r] && j < 6)
-                           ? stage_value<STAGE, TS>(a, B, x, yy[r], T.z0 - kG + j, v)
-                           : TS(0);
+          q[v][r][j] = act[r] ? stage_value<STAGE, TS>(a, B, x, yy[r], T.z0 - kG + j, v) : TS(0);
 #pragma unroll
     for (int k = 0; k < RMAX; ++k)
 #pragma unroll
@@ -128,32 +133,35 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
     for (int iz = 0; iz < T.nz; ++iz) {
       const int z = T.z0 + iz;
       TS(*L)[LY][LX] = lds[iz & 1];
-      // plane z into LDS: own points from the z column (whose last plane,
-      // z+3, is read now), the ring from the registers filled last iteration
+      // plane z into LDS: own points from the z column, the ring from the
+      // registers filled during the previous iteration
 #pragma unroll
       for (int r = 0; r < RY; ++r)
 #pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          if (act[r]) {
-            q[v][r][6] = stage_value<STAGE, TS>(a, B, x, yy[r], z + kG, v);
-            L[v][ty + r * BY + kG][tx + kG] = q[v][r][3];
-          }
-        }
+        for (int v = 0; v < 2; ++v)
+          if (act[r]) L[v][ty + r * BY + kG][tx + kG] = q[v][r][3];
 #pragma unroll
       for (int k = 0; k < RMAX; ++k)
 #pragma unroll
         for (int v = 0; v < 2; ++v)
           if (ract[k]) L[v][ry[k]][rx[k]] = ring[v][k];
       __syncthreads();
-      if (iz + 1 < T.nz) {
+      // loads for the next iteration (ring of plane z+1, own points of plane
+      // z+4), in flight during this iteration's arithmetic
+      const bool more = iz + 1 < T.nz;
 #pragma unroll
-        for (int k = 0; k < RMAX; ++k)
+      for (int k = 0; k < RMAX; ++k)
 #pragma unroll
-          for (int v = 0; v < 2; ++v)
-            if (ract[k])
-              ring[v][k] = stage_value<STAGE, TS>(a, B, T.x0 - kG + rx[k], T.y0 - kG + ry[k],
-                                                  z + 1, v);
-      }
+        for (int v = 0; v < 2; ++v)
+          if (more && ract[k])
+            ring[v][k] = stage_value<STAGE, TS>(a, B, T.x0 - kG + rx[k], T.y0 - kG + ry[k],
+                                                z + 1, v);
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+          qn[v][r] = (more && act[r]) ? stage_value<STAGE, TS>(a, B, x, yy[r], z + kG + 1, v)
+                                      : TS(0);
 #pragma unroll
       for (int r = 0; r < RY; ++r) {
         if (act[r]) {
@@ -206,6 +214,10 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
         for (int r = 0; r < RY; ++r)
 #pragma unroll
           for (int v = 0; v < 2; ++v) q[v][r][j] = q[v][r][j + 1];
+#pragma unroll
+      for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) q[v][r][6] = qn[v][r];
     }
     __syncthreads();
   }
@@ -231,64 +243,88 @@ __global__ __launch_bounds__(256) void k_sync(SyncArgs a) {
 // point, x first, then y, then z, with the degree-5 Lagrange midpoint
 // weights at odd fine indices and a copy at even ones; then each requested
 // dense-output combination  P[y_n] + H (((w1 P[k1] + w2 P[k2]) + w3 P[k3]) + w4 P[k4]),
-// all in FP64.
-template <typename TK, typename TO>
-__global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const ProlongEntry e = a.e[i];
-  const BoxDev P = a.pboxes[e.pbox];
+// all in FP64.  The parity class is a template parameter, so every loop has
+// a compile-time trip count, and each stencil tap gathers all five vectors.
+template <int OX, int OY, int OZ, typename TK, typename TO>
+__device__ __forceinline__ void prolong_one(const ProlongArgs& a, int64_t i) {
+  constexpr int NX = OX ? 6 : 1, NY = OY ? 6 : 1, NZ = OZ ? 6 : 1;
   constexpr double W[6] = {3.0 / 256.0, -25.0 / 256.0, 150.0 / 256.0,
                            150.0 / 256.0, -25.0 / 256.0, 3.0 / 256.0};
-  int ns[3];
-  int64_t off[3][6];
+  const ProlongEntry e = a.e[i];
+  const BoxDev P = a.pboxes[e.pbox];
   const int64_t pitch[3] = {1, (int64_t)P.px, (int64_t)P.px * P.py};
+  int64_t ox[NX], oy[NY], oz[NZ];
+  auto offs = [&](int d, int odd, int j) -> int64_t {
+    const int base = e.q[d] >> 1;
+    int I = odd ? base - 2 + j : base;
+    if (P.wrapN[d] > 0) I = ((I % P.wrapN[d]) + P.wrapN[d]) % P.wrapN[d];
+    return (int64_t)(I - P.lo[d] + kG) * pitch[d];
+  };
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const int qd = e.q[d];
-    const int odd = qd & 1;
-    const int base = qd >> 1;
-    ns[d] = odd ? 6 : 1;
-    for (int j = 0; j < 6; ++j) {
-      int I = odd ? base - 2 + j : base;
-      if (P.wrapN[d] > 0) I = ((I % P.wrapN[d]) + P.wrapN[d]) % P.wrapN[d];
-      off[d][j] = (int64_t)(I - P.lo[d] + kG) * pitch[d];
-    }
-  }
+  for (int j = 0; j < NX; ++j) ox[j] = offs(0, OX, j);
+#pragma unroll
+  for (int j = 0; j < NY; ++j) oy[j] = offs(1, OY, j);
+#pragma unroll
+  for (int j = 0; j < NZ; ++j) oz[j] = offs(2, OZ, j);
+  const TK* k0 = static_cast<const TK*>(a.pk[0]);
+  const TK* k1 = static_cast<const TK*>(a.pk[1]);
+  const TK* k2 = static_cast<const TK*>(a.pk[2]);
+  const TK* k3 = static_cast<const TK*>(a.pk[3]);
   for (int v = 0; v < a.nvars; ++v) {
-    double Pv[5];
-    for (int m = 0; m < 5; ++m) {
-      const int64_t vb = P.base + v * a.pvstride;
-      double pz = 0.0;
-      for (int jz = 0; jz < ns[2]; ++jz) {
-        double py = 0.0;
-        for (int jy = 0; jy < ns[1]; ++jy) {
-          const int64_t rowo = vb + off[2][jz] + off[1][jy];
-          auto at = [&](int jx) -> double {
-            return m == 0 ? a.py[rowo + off[0][jx]]
-                          : (double)static_cast<const TK*>(a.pk[m - 1])[rowo + off[0][jx]];
-          };
-          double px;
-          if (ns[0] == 6) {
-            px = W[0] * at(0);
+    const int64_t vb = P.base + v * a.pvstride;
+    double pz[5];
 #pragma unroll
-            for (int jx = 1; jx < 6; ++jx) px = px + W[jx] * at(jx);
-          } else {
-            px = at(0);
+    for (int jz = 0; jz < NZ; ++jz) {
+      double py[5];
+#pragma unroll
+      for (int jy = 0; jy < NY; ++jy) {
+        double px[5];
+#pragma unroll
+        for (int jx = 0; jx < NX; ++jx) {
+          const int64_t o = vb + oz[jz] + oy[jy] + ox[jx];
+          const double t[5] = {a.py[o], (double)k0[o], (double)k1[o], (double)k2[o], (double)k3[o]};
+#pragma unroll
+          for (int m = 0; m < 5; ++m) {
+            if constexpr (NX == 1) px[m] = t[m];
+            else px[m] = jx == 0 ? W[0] * t[m] : px[m] + W[jx] * t[m];
           }
-          if (ns[1] == 6) py = (jy == 0) ? W[0] * px : py + W[jy] * px;
-          else py = px;
         }
-        if (ns[2] == 6) pz = (jz == 0) ? W[0] * py : pz + W[jz] * py;
-        else pz = py;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          if constexpr (NY == 1) py[m] = px[m];
+          else py[m] = jy == 0 ? W[0] * px[m] : py[m] + W[jy] * px[m];
+        }
       }
-      Pv[m] = pz;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        if constexpr (NZ == 1) pz[m] = py[m];
+        else pz[m] = jz == 0 ? W[0] * py[m] : pz[m] + W[jz] * py[m];
+      }
     }
     for (int o = 0; o < a.nout; ++o) {
       const double s =
-          ((a.w[o][0] * Pv[1] + a.w[o][1] * Pv[2]) + a.w[o][2] * Pv[3]) + a.w[o][3] * Pv[4];
-      static_cast<TO*>(a.out[o])[e.dst + v * a.ovstride] = (TO)(Pv[0] + a.H * s);
+          ((a.w[o][0] * pz[1] + a.w[o][1] * pz[2]) + a.w[o][2] * pz[3]) + a.w[o][3] * pz[4];
+      static_cast<TO*>(a.out[o])[e.dst + v * a.ovstride] = (TO)(pz[0] + a.H * s);
     }
+  }
+}
+
+template <typename TK, typename TO>
+__global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
+  const int b = blockIdx.x;
+  int cls = 0;
+  while (cls < 7 && b >= a.blk_start[cls + 1]) ++cls;
+  const int64_t i = a.cls_start[cls] + (int64_t)(b - a.blk_start[cls]) * 256 + threadIdx.x;
+  if (i >= a.cls_start[cls + 1]) return;
+  switch (cls) {
+    case 0: prolong_one<0, 0, 0, TK, TO>(a, i); break;
+    case 1: prolong_one<1, 0, 0, TK, TO>(a, i); break;
+    case 2: prolong_one<0, 1, 0, TK, TO>(a, i); break;
+    case 3: prolong_one<1, 1, 0, TK, TO>(a, i); break;
+    case 4: prolong_one<0, 0, 1, TK, TO>(a, i); break;
+    case 5: prolong_one<1, 0, 1, TK, TO>(a, i); break;
+    case 6: prolong_one<0, 1, 1, TK, TO>(a, i); break;
+    default: prolong_one<1, 1, 1, TK, TO>(a, i); break;
   }
 }
 
@@ -411,6 +447,12 @@ __global__ __launch_bounds__(256) void k_fill(T* p, int64_t n, T v) {
   if (i < n) p[i] = v;
 }
 
+__global__ __launch_bounds__(256) void k_scatter(const int64_t* idx, int64_t n, const double* src,
+                                                 double* dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[idx[i]] = src[i];
+}
+
 __global__ __launch_bounds__(256) void k_to_f32(const double* src, float* dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = (float)src[i];
@@ -448,7 +490,7 @@ hipError_t launch_sync(const SyncArgs& a, bool f32, hipStream_t s) {
 
 hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  const dim3 g(blocks_for(a.n)), b(256);
+  const dim3 g(a.blk_start[8]), b(256);
   if (!k_f32 && !out_f32) hipLaunchKernelGGL((k_prolong<double, double>), g, b, 0, s, a);
   else if (k_f32 && out_f32) hipLaunchKernelGGL((k_prolong<float, float>), g, b, 0, s, a);
   else if (k_f32) hipLaunchKernelGGL((k_prolong<float, double>), g, b, 0, s, a);
@@ -499,6 +541,13 @@ hipError_t launch_fill(void* p, int64_t n, double v, bool f32, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_fill<double>, dim3(blocks_for(n)), dim3(256), 0, s,
                        static_cast<double*>(p), n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, double* dst,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(256), 0, s, idx, n, src, dst);
   return hipGetLastError();
 }
 

@@ -19,8 +19,8 @@ struct TileShape {
 
 // z-chunk depths the autotuner tries; the tile table region is sized for the
 // shallowest (most tiles).
-constexpr int kTuneTz[] = {8, 12, 16, 24, 32, 48, 64, 1 << 20};
-constexpr int kTuneTzMin = 8;
+constexpr int kTuneTz[] = {4, 6, 8, 12, 16, 24, 32, 48, 64, 1 << 20};
+constexpr int kTuneTzMin = 4;
 
 struct LevelDev {
   int nb_member = 0;                 // boxes per member
@@ -31,10 +31,13 @@ struct LevelDev {
   std::vector<BoxDev> boxes;         // all members
   std::vector<int64_t> prefix;       // canonical prefix per member box (nb_member + 1)
   std::vector<SyncEntry> sync;
-  std::vector<ProlongEntry> prolong; // RB halo slots
+  std::vector<ProlongEntry> prolong; // RB halo slots, sorted by parity class
+  int64_t prolong_cls[9] = {0};      // class prefix of `prolong`
+  int64_t rblist_cls[9] = {0};       // class prefix of one member's `rblist`
   std::vector<ProlongEntry> rblist;  // RB list entries of every member, dst = list index j
   std::vector<int64_t> rbfirst;      // halo offset of the first slot of each RB list entry
-  std::vector<int64_t> phys;
+  std::vector<int64_t> phys;         // physical-boundary halo offsets, all members
+  std::vector<int64_t> phys_q;       // their global indices (member 0), xyz triples
   std::vector<RestrictRegion> restr;
   int64_t restr_total = 0;
   std::vector<TileDev> tiles;        // batched: tiles over the boxes
@@ -46,7 +49,7 @@ struct LevelDev {
   bool has_child = false;
   // arena offsets (bytes)
   size_t o_y[2], o_y32[2], o_k[4], o_yh[8], o_boxes, o_prefix, o_sync, o_prolong, o_rblist,
-      o_rbfirst, o_phys, o_restr, o_tiles, o_btiles;
+      o_rbfirst, o_phys, o_restr, o_tiles, o_btiles, o_ys;
   // device pointers after binding.  y: FP64 state; y32: its FP32 shadow
   // (mixed mode only); k and Yh hold the stencil type (FP64, or FP32 in
   // mixed mode).
@@ -54,6 +57,7 @@ struct LevelDev {
   float* y32[2] = {nullptr, nullptr};
   void* k[4] = {nullptr, nullptr, nullptr, nullptr};
   void* Yh[8] = {nullptr};
+  double* Ys = nullptr;              // Z4c: materialised stage vector
   BoxDev* d_boxes = nullptr;
   int64_t* d_prefix = nullptr;
   SyncEntry* d_sync = nullptr;

@@ -11,8 +11,10 @@ error below 32 eps32 max|u| / h^2 per evaluation (the dissipation terms are
 O(1/h) and smaller).  RK4 integrates it over time t with weights summing to
 one per step, giving the per-level model bound
     |Pi_mixed - Pi_fp64| <= t * 32 eps32 max|u| / h^2
-(u picks up at most t times that).  The tests check the measured error
-against that bound and that fourth-order convergence is kept.
+(u picks up at most t times that).  Restriction copies finer-level values
+into the coarser levels, so a level's error is bounded by the finest spacing
+in the hierarchy, h = dx of the finest level.  The tests check the measured
+error against that bound and that fourth-order convergence is kept.
 """
 import numpy as np
 import pytest
@@ -45,7 +47,7 @@ def test_mixed_error_within_bound(spec, ncoarse):
     b, _ = _run(spec, sc.SC_MIXED, ncoarse, data)
     for l in range(spec.nlevels):
         umax = np.abs(a[l][0]).max()
-        h = spec.dx(l)
+        h = spec.dx(spec.nlevels - 1)
         bound = t * 32 * EPS32 * umax / (h * h)
         for v in range(2):
             err = np.abs(a[l][v] - b[l][v]).max()

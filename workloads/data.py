@@ -145,3 +145,29 @@ def ensemble_on_spec(spec: HierarchySpec, nmembers: int, seed: int = 2):
     for m, a0 in ensemble_params(nmembers, seed):
         out.append(standing_wave_on_spec(spec, 0, m, a0))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Z4c initial data (22 variables in the library's slot order: W, gt_xx,xy,xz,
+# yy,yz,zz, Khat, At_xx..zz, Theta, Gt^x,y,z, alpha, beta^x,y,z).
+
+def brill_lindquist(x, y, z, m: float = 0.5, c: float = 3.0):
+    """Two Brill-Lindquist punctures of bare mass m at (+-c, 0, 0), time symmetric:
+    psi = 1 + m/(2 r+) + m/(2 r-), W = psi^-2, conformally flat, K = 0, zero
+    shift, and the initial lapse 1/2 (1 + (1 - m/2r+ - m/2r-)/(1 + m/2r+ + m/2r-)),
+    which equals 1/psi."""
+    rp = np.sqrt((x - c) ** 2 + y ** 2 + z ** 2)
+    rm = np.sqrt((x + c) ** 2 + y ** 2 + z ** 2)
+    a = m / (2 * rp) + m / (2 * rm)
+    psi = 1.0 + a
+    zero = np.zeros_like(x)
+    one = np.ones_like(x)
+    alpha = 0.5 * (1.0 + (1.0 - a) / (1.0 + a))
+    return ([psi ** -2, one, zero.copy(), zero.copy(), one.copy(), zero.copy(), one.copy(),
+             zero.copy()] + [zero.copy() for _ in range(6)] + [zero.copy()] +
+            [zero.copy() for _ in range(3)] + [alpha] + [zero.copy() for _ in range(3)])
+
+
+def brill_lindquist_on_spec(spec: HierarchySpec, level: int, m: float = 0.5, c: float = 3.0):
+    x, y, z = canonical_coords(spec, level)
+    return brill_lindquist(x, y, z, m, c)

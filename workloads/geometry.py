@@ -151,3 +151,11 @@ def config_c5(n0: int = 96, nlev: int = 7) -> HierarchySpec:
     origin = (-128.0, -128.0 + dfine / 2, -128.0 + dfine / 2)
     return tower_family(n0, 96, 128.0, 96, 3.0, nlev, origin, False,
                         name=f"z4c-{nlev}level-towers-{n0}^3")
+
+
+def config_z4c_small(n0: int = 24, nlev: int = 3, half: float = 16.0, nt: int = 16) -> HierarchySpec:
+    """A small puncture layout for tests: [-half, half]^3, towers at x = -3, +3."""
+    dfine = (2.0 * half / n0) / (1 << (nlev - 1))
+    origin = (-half, -half + dfine / 2, -half + dfine / 2)
+    return tower_family(n0, n0, half, nt, 3.0, nlev, origin, False,
+                        name=f"z4c-{nlev}level-towers-{n0}^3")
