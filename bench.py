@@ -212,6 +212,10 @@ def main():
     ap.add_argument("--modes", default="graph,batched,per_block,mixed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--shapes", default=None,
+                    help="JSON line of an earlier run: take its tile shapes instead of tuning")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--workload", default="wave", choices=("wave", "z4c", "precision"))
     ap.add_argument("--z4c-steps", type=int, default=16)
     ap.add_argument("--report-n0", type=int, nargs="+", default=[64, 128, 256])
@@ -220,6 +224,16 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "layout is a design, not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe_mib > 0:
+        import torch
+        n = args.copy_probe_mib << 17          # float64 elements
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": n * 8, "launches": 3}), flush=True)
+        return
     if args.workload == "z4c":
         print(json.dumps(z4c_run(args)), flush=True)
         return
@@ -247,7 +261,13 @@ def main():
                 "mixed_batched": sc.SC_EXEC_BATCHED}[m]
         prec = sc.SC_MIXED if m.startswith("mixed") else sc.SC_FP64
         ctx = make_context(sc, spec, mode, data, prec)
-        if m != "per_block" and not args.no_tune:
+        if m != "per_block" and args.shapes:
+            with open(args.shapes) as f:
+                tuned = json.loads(f.read().strip().splitlines()[-1])["modes"][m]
+            for l in range(spec.nlevels):
+                ctx.set_tile_shape(l, tuned["tz_per_level"][l], tuned["grid_per_level"][l],
+                                   tuned["pz_per_level"][l])
+        elif m != "per_block" and not args.no_tune:
             ctx.autotune(3)
         shapes = [ctx.tile_shape(l) for l in range(spec.nlevels)]
         steps = args.steps if m != "per_block" else max(1, min(args.steps, 2))
@@ -256,7 +276,8 @@ def main():
         T = timed(ctx, torch, steps)
         res[m] = {"updates_per_s": U * steps / T, "ms_per_step": 1e3 * T / steps,
                   "steps": steps, "tz_per_level": [sh["tz"] for sh in shapes],
-                  "grid_per_level": [sh["grid"] for sh in shapes]}
+                  "grid_per_level": [sh["grid"] for sh in shapes],
+                  "pz_per_level": [sh["pz"] for sh in shapes]}
         log(f"{m}: {1e3 * T / steps:.2f} ms/step, {U * steps / T:.4g} updates/s")
         if m in ("batched", "mixed_batched"):
             label = "roofline" if m == "batched" else "roofline_mixed"

@@ -30,7 +30,7 @@ EXPORTED = [
     "sc_hamiltonian", "sc_advance", "sc_step_level", "sc_prolongate", "sc_fill_ghosts",
     "sc_restrict", "sc_read_back", "sc_read_rb", "sc_norms", "sc_check_finite",
     "sc_level_time", "sc_set_exec", "sc_poison_halos", "sc_autotune", "sc_tile_shape",
-    "sc_profile_enable",
+    "sc_set_tile_shape", "sc_profile_enable",
     "sc_profile_read", "sc_stats",
 ]
 
@@ -100,6 +100,7 @@ def lib():
             "sc_poison_halos": [P],
             "sc_autotune": [P, i32],
             "sc_tile_shape": [P, i32, P],
+            "sc_set_tile_shape": [P, i32, i32, i32, i32],
             "sc_profile_enable": [P, i32],
             "sc_profile_read": [P, P, P, P],
             "sc_stats": [P, P, P],
@@ -305,9 +306,12 @@ class Context:
         self._check(self.L.sc_autotune(self.ctx, reps))
 
     def tile_shape(self, level: int):
-        out = (ctypes.c_int32 * 5)()
+        out = (ctypes.c_int32 * 6)()
         self._check(self.L.sc_tile_shape(self.ctx, level, out))
-        return dict(zip(("tx", "ty", "tz", "grid", "tiles"), list(out)))
+        return dict(zip(("tx", "ty", "tz", "grid", "tiles", "pz"), list(out)))
+
+    def set_tile_shape(self, level: int, tz: int, grid: int = 0, pz: int = 1):
+        self._check(self.L.sc_set_tile_shape(self.ctx, level, tz, grid, pz))
 
     def profile_enable(self, on: bool = True):
         self._check(self.L.sc_profile_enable(self.ctx, int(bool(on))))

@@ -111,11 +111,29 @@ void split_even(int64_t n, int64_t maxlen, std::vector<std::pair<int, int>>* out
   }
 }
 
+// Largest tile height for tiles at most nxm points wide: at most
+// kStageSlots owned points per thread, an LDS window of at most kWinCap points
+// and at most kRingSlots ring points per thread.
+int tile_ty_cap(int nxm) {
+  int t = kStageThreads * kStageSlots / nxm;
+  t = std::min(t, kWinCap / (nxm + 2 * kG) - 2 * kG);
+  t = std::min(t, (kStageThreads * kRingSlots - 6 * (nxm + 2 * kG)) / 6);
+  return std::max(t, 1);
+}
+
+bool tile_fits(int nx, int ny) {
+  return nx >= 1 && ny >= 1 && nx <= kTileMaxX && nx * ny <= kStageThreads * kStageSlots &&
+         (nx + 2 * kG) * (ny + 2 * kG) <= kWinCap &&
+         6 * (nx + 2 * kG) + 6 * ny <= kStageThreads * kRingSlots;
+}
+
 void tile_region(int box, const int64_t o[3], const int64_t n[3], const TileShape& s,
                  std::vector<TileDev>* out) {
   std::vector<std::pair<int, int>> sx, sy, sz;
-  split_even(n[0], s.tx, &sx);
-  split_even(n[1], s.ty, &sy);
+  split_even(n[0], std::min(s.tx, kTileMaxX), &sx);
+  int nxm = 1;
+  for (auto& x : sx) nxm = std::max(nxm, x.second);
+  split_even(n[1], std::min(s.ty, tile_ty_cap(nxm)), &sy);
   split_even(n[2], s.tz, &sz);
   for (auto& z : sz)
     for (auto& y : sy)
@@ -237,13 +255,74 @@ std::string build_layout(sc_ctx* c) {
           }
     }
     const int npb = l > 0 ? c->lev[l - 1].nb_member : 0;
+    // group RB halo slots into bricks of at most 8^3 fine points (cells of a
+    // global 8-point lattice, shrunk to the bounding box of their RB slots);
+    // slots that wrap periodically or whose brick spans two parent boxes stay
+    // per point
+    std::vector<ProlongEntry> rest0;
+    std::vector<ProlongBrick> bricks0;
+    {
+      std::map<std::array<int64_t, 4>, std::vector<size_t>> cells;  // (box, cell) -> slots
+      for (size_t i = 0; i < pro0.size(); ++i) {
+        const ProlongEntry& e = pro0[i];
+        int ib = -1;
+        for (int b = 0; b < L.nb_member; ++b)
+          if (e.dst >= b0[b].base &&
+              e.dst < b0[b].base + (int64_t)b0[b].px * b0[b].py * (b0[b].nz + 2 * kG))
+            ib = b;
+        const BoxDev& B = b0[ib];
+        const int64_t r = e.dst - B.base;
+        const int64_t hx = r % B.px - kG, hy = (r / B.px) % B.py - kG, hz = r / ((int64_t)B.px * B.py) - kG;
+        const int64_t p[3] = {B.lo[0] + hx, B.lo[1] + hy, B.lo[2] + hz};
+        if (p[0] != e.q[0] || p[1] != e.q[1] || p[2] != e.q[2]) {
+          rest0.push_back(e);
+          continue;
+        }
+        cells[{(int64_t)ib, p[0] >> 3, p[1] >> 3, p[2] >> 3}].push_back(i);
+      }
+      for (auto& kv : cells) {
+        const auto& idx = kv.second;
+        const int pb = pro0[idx[0]].pbox;
+        bool same = true;
+        int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+        for (size_t i : idx) {
+          same = same && pro0[i].pbox == pb;
+          for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], pro0[i].q[d]);
+            hi[d] = std::max(hi[d], pro0[i].q[d]);
+          }
+        }
+        if (!same) {
+          for (size_t i : idx) rest0.push_back(pro0[i]);
+          continue;
+        }
+        ProlongBrick bk{};
+        bk.fbox = (int32_t)kv.first[0];
+        bk.pbox = pb;
+        for (int d = 0; d < 3; ++d) {
+          bk.a[d] = lo[d];
+          bk.n[d] = hi[d] - lo[d] + 1;
+        }
+        for (size_t i : idx) {
+          const int fx = pro0[i].q[0] - lo[0], fy = pro0[i].q[1] - lo[1], fz = pro0[i].q[2] - lo[2];
+          const int bit = (fz * bk.n[1] + fy) * bk.n[0] + fx;
+          bk.mask[bit >> 6] |= uint64_t(1) << (bit & 63);
+        }
+        bricks0.push_back(bk);
+      }
+    }
     for (int m = 0; m < nm; ++m) {
       const int64_t off = m * L.member_total;
       for (auto e : sync0) L.sync.push_back({e.dst + off, e.src + off});
-      for (auto e : pro0) {
+      for (auto e : rest0) {
         e.dst += off;
         e.pbox += m * npb;
         L.prolong.push_back(e);
+      }
+      for (auto bk : bricks0) {
+        bk.fbox += m * L.nb_member;
+        bk.pbox += m * npb;
+        L.bricks.push_back(bk);
       }
       for (auto d : phys0) L.phys.push_back(d + off);
     }
@@ -349,7 +428,7 @@ std::string validate_layout(const sc_ctx* c) {
     auto tile_ok = [&](const TileDev& t) {
       if (t.box < 0 || t.box >= (int)L.boxes.size()) return false;
       const BoxDev& B = L.boxes[t.box];
-      return t.nx >= 1 && t.ny >= 1 && t.nz >= 1 && t.nx <= kTileMaxX && t.ny <= kTileMaxY &&
+      return tile_fits(t.nx, t.ny) && t.nz >= 1 &&
              t.x0 >= 0 && t.y0 >= 0 && t.z0 >= 0 && t.x0 + t.nx <= B.nx &&
              t.y0 + t.ny <= B.ny && t.z0 + t.nz <= B.nz;
     };
@@ -385,6 +464,30 @@ std::string validate_layout(const sc_ctx* c) {
       };
       for (const ProlongEntry& e : L.prolong)
         if (!pro_ok(e) || !in_level(e.dst)) return "prolongation entry out of range";
+      for (const ProlongBrick& bk : L.bricks) {
+        if (bk.fbox < 0 || bk.fbox >= (int)L.boxes.size() || bk.pbox < 0 ||
+            bk.pbox >= (int)P.boxes.size())
+          return "brick box out of range";
+        const BoxDev& F = L.boxes[bk.fbox];
+        const int fn[3] = {F.nx, F.ny, F.nz};
+        for (int d = 0; d < 3; ++d)
+          if (bk.n[d] < 1 || bk.n[d] > 8 || bk.a[d] < 0 || bk.a[d] - F.lo[d] < -kG ||
+              bk.a[d] + bk.n[d] - 1 - F.lo[d] >= fn[d] + kG)
+            return "brick outside its fine box halo";
+        for (int z = 0; z < bk.n[2]; ++z)
+          for (int y = 0; y < bk.n[1]; ++y)
+            for (int x = 0; x < bk.n[0]; ++x) {
+              const int bit = (z * bk.n[1] + y) * bk.n[0] + x;
+              if (!((bk.mask[bit >> 6] >> (bit & 63)) & 1)) continue;
+              ProlongEntry e;
+              e.dst = 0;
+              e.q[0] = bk.a[0] + x;
+              e.q[1] = bk.a[1] + y;
+              e.q[2] = bk.a[2] + z;
+              e.pbox = bk.pbox;
+              if (!pro_ok(e)) return "brick point stencil outside its parent box";
+            }
+      }
       for (const ProlongEntry& e : L.rblist)
         if (!pro_ok(e) || e.dst < 0 || e.dst >= L.nrb) return "RB list entry out of range";
       int64_t expect = 0;
@@ -431,6 +534,7 @@ void plan_arena(sc_ctx* c) {
     L.o_prefix = take(sizeof(int64_t) * L.prefix.size());
     L.o_sync = take(sizeof(SyncEntry) * L.sync.size());
     L.o_prolong = take(sizeof(ProlongEntry) * L.prolong.size());
+    L.o_bricks = take(sizeof(ProlongBrick) * L.bricks.size());
     L.o_rblist = take(sizeof(ProlongEntry) * L.rblist.size());
     L.o_rbfirst = take(sizeof(int64_t) * L.rbfirst.size());
     L.o_phys = take(sizeof(int64_t) * L.phys.size());
@@ -523,7 +627,7 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
       if (rc) return rc;
       HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    HIPCHK(c, launch_stage(a, grid, c->mixed, c->stream));
+    HIPCHK(c, launch_stage(a, grid, c->mixed, L.shape.pz, c->stream));
     if (c->profiling) {
       HIPCHK(c, hipEventRecord(e1, c->stream));
       // algorithmic bytes per owned point and variable: the stencil operands
@@ -541,7 +645,7 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
     for (int b = 0; b < nblk; ++b) {
       a.tiles = L.d_btiles + L.btile_start[b];
       a.ntiles = L.btile_start[b + 1] - L.btile_start[b];
-      HIPCHK(c, launch_stage(a, a.ntiles, c->mixed, c->stream));
+      HIPCHK(c, launch_stage(a, a.ntiles, c->mixed, 1, c->stream));
       ++c->launches;
     }
   }
@@ -656,8 +760,29 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
 // k1..k4) into the fine level: outputs[i] with weights[i].
 int prolong_into(sc_ctx* c, int fl, const ProlongEntry* entries, const int64_t* cls, int nout,
                  void* const* outs, const int* fills, const int* subs, int64_t ovstride,
-                 bool out_f32, int var_only) {
+                 bool out_f32, int var_only, bool with_bricks) {
   LevelDev& P = c->lev[fl - 1];
+  LevelDev& F = c->lev[fl];
+  if (with_bricks && !F.bricks.empty()) {
+    BrickArgs b{};
+    b.b = F.d_bricks;
+    b.nbricks = (int32_t)F.bricks.size();
+    b.nout = nout;
+    b.nvars = c->nvars;
+    b.fboxes = F.d_boxes;
+    b.pboxes = P.d_boxes;
+    b.py = P.y[1 - P.cur];
+    for (int i = 0; i < 4; ++i) b.pk[i] = P.k[i];
+    b.pvstride = P.total;
+    b.ovstride = ovstride;
+    b.H = P.dt;
+    for (int o = 0; o < nout; ++o) {
+      b.out[o] = outs[o];
+      for (int i = 0; i < 4; ++i) b.w[o][i] = c->weights[subs[o]][fills[o] - 1][i];
+    }
+    HIPCHK(c, launch_prolong_bricks(b, c->mixed, out_f32, c->stream));
+    ++c->launches;
+  }
   const int64_t n = cls[8];
   if (n <= 0) return SC_OK;
   ProlongArgs a{};
@@ -701,7 +826,7 @@ int prolongate(sc_ctx* c, int fl) {
       subs[o] = sub;
     }
   return prolong_into(c, fl, F.d_prolong, F.prolong_cls, 8, outs, fills, subs, F.total,
-                      c->mixed, -1);
+                      c->mixed, -1, true);
 }
 
 int restrict_level(sc_ctx* c, int fl) {
@@ -942,6 +1067,7 @@ int sc_bind_device_memory(sc_ctx* c, void* dptr, size_t nbytes) {
     L.d_prefix = at<int64_t>(c, L.o_prefix);
     L.d_sync = at<SyncEntry>(c, L.o_sync);
     L.d_prolong = at<ProlongEntry>(c, L.o_prolong);
+    L.d_bricks = at<ProlongBrick>(c, L.o_bricks);
     L.d_rblist = at<ProlongEntry>(c, L.o_rblist);
     L.d_rbfirst = at<int64_t>(c, L.o_rbfirst);
     L.d_phys = at<int64_t>(c, L.o_phys);
@@ -952,6 +1078,7 @@ int sc_bind_device_memory(sc_ctx* c, void* dptr, size_t nbytes) {
     HIPCHK(c, upload(c, L.d_prefix, L.prefix));
     HIPCHK(c, upload(c, L.d_sync, L.sync));
     HIPCHK(c, upload(c, L.d_prolong, L.prolong));
+    HIPCHK(c, upload(c, L.d_bricks, L.bricks));
     HIPCHK(c, upload(c, L.d_rblist, L.rblist));
     HIPCHK(c, upload(c, L.d_rbfirst, L.rbfirst));
     HIPCHK(c, upload(c, L.d_phys, L.phys));
@@ -1149,7 +1276,7 @@ int sc_fill_ghosts(sc_ctx* c, int32_t level, int32_t which, int32_t substep) {
     void* outs[1] = {y};
     const int fills[1] = {which}, subs[1] = {substep};
     rc = prolong_into(c, level, L.d_prolong, L.prolong_cls, 1, outs, fills, subs, L.total,
-                      false, -1);
+                      false, -1, true);
     if (rc) return rc;
   }
   return SC_OK;
@@ -1194,7 +1321,7 @@ int sc_read_rb(sc_ctx* c, int32_t member, int32_t level, int32_t which, int32_t 
     void* outs[1] = {c->d_stage};
     const int fills[1] = {5}, subs[1] = {substep};
     rc = prolong_into(c, level, L.d_rblist + member * L.nrb, L.rblist_cls, 1, outs, fills, subs,
-                      0, false, var);
+                      0, false, var, false);
     if (rc) return rc;
   }
   HIPCHK(c, hipMemcpyAsync(host, c->d_stage, sizeof(double) * n, hipMemcpyDeviceToHost,
@@ -1267,6 +1394,43 @@ int sc_poison_halos(sc_ctx* c) {
   return SC_OK;
 }
 
+static void drop_graphs(sc_ctx* c) {
+  for (int i = 0; i < 2; ++i) {
+    if (c->graph[i]) (void)hipGraphExecDestroy(c->graph[i]);
+    c->graph[i] = nullptr;
+    c->graph_ready[i] = false;
+  }
+}
+
+int sc_set_tile_shape(sc_ctx* c, int32_t level, int32_t tz, int32_t grid, int32_t pz) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size()) return fail(c, SC_E_ARG, "level out of range");
+  if (tz < kTuneTzMin || tz > (1 << 20)) return fail(c, SC_E_ARG, "z-chunk out of range");
+  if (grid < 0) return fail(c, SC_E_ARG, "grid must be >= 0");
+  if (pz != 1 && pz != 2) return fail(c, SC_E_ARG, "planes per step must be 1 or 2");
+  LevelDev& L = c->lev[level];
+  TileShape sh = L.shape;
+  sh.tz = tz;
+  sh.pz = pz;
+  std::vector<TileDev> tl;
+  for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
+    const BoxDev& B = L.boxes[ib];
+    const int64_t o[3] = {0, 0, 0}, n[3] = {B.nx, B.ny, B.nz};
+    tile_region(ib, o, n, sh, &tl);
+  }
+  if (tl.size() > L.tiles_capacity)
+    return fail(c, SC_E_ARG, "z-chunk gives more tiles than the tile table holds");
+  sh.grid = grid == 0 ? 0 : std::min<int>(grid, (int)tl.size());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, upload(c, L.d_tiles, tl));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  L.tiles = tl;
+  L.shape = sh;
+  drop_graphs(c);
+  return SC_OK;
+}
+
 int sc_autotune(sc_ctx* c, int32_t reps) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
@@ -1297,8 +1461,10 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
       if (tl.size() > L.tiles_capacity) continue;
       HIPCHK(c, upload(c, L.d_tiles, tl));
       L.tiles = tl;
+      for (int pz : {1, 2})
       for (int g : {2 * ncu, 4 * ncu, 8 * ncu, 1 << 30}) {
         sh.grid = std::min<int>(g, (int)tl.size());
+        sh.pz = pz;
         L.shape = sh;
         // stage 2 reads y_n, k1 and the halo table, writes k2
         rc = enqueue_stage_launches(c, (int)l, 2, false, c->mixed ? (const void*)L.y32[L.cur]
@@ -1332,24 +1498,25 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
   (void)hipEventDestroy(e1);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->profiling = prof;
-  for (int i = 0; i < 2; ++i) {
-    if (c->graph[i]) (void)hipGraphExecDestroy(c->graph[i]);
-    c->graph[i] = nullptr;
-    c->graph_ready[i] = false;
-  }
+  drop_graphs(c);
   return SC_OK;
 }
 
-int sc_tile_shape(const sc_ctx* c, int32_t level, int32_t out[5]) {
+int sc_tile_shape(const sc_ctx* c, int32_t level, int32_t out[6]) {
   int rc = check_ready(c, 1);
   if (rc) return rc;
   if (level < 0 || level >= (int)c->lev.size() || !out) return SC_E_ARG;
   const LevelDev& L = c->lev[level];
-  out[0] = L.shape.tx;
-  out[1] = L.shape.ty;
+  out[0] = 0;
+  out[1] = 0;
+  for (const TileDev& t : L.tiles) {
+    out[0] = std::max<int32_t>(out[0], t.nx);
+    out[1] = std::max<int32_t>(out[1], t.ny);
+  }
   out[2] = L.shape.tz;
   out[3] = L.shape.grid > 0 ? L.shape.grid : std::min<int>((int)L.tiles.size(), c->grid_cap);
   out[4] = (int32_t)L.tiles.size();
+  out[5] = L.shape.pz;
   return SC_OK;
 }
 

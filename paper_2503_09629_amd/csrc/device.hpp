@@ -48,6 +48,17 @@ struct ProlongEntry {   // refinement-boundary halo point
   int32_t pbox;         // parent box holding the whole prolongation stencil
 };
 
+// A brick of refinement-boundary halo points of one fine box: the fine
+// index range [a, a + n) (n <= 8 per dimension), the parent box holding every
+// stencil of its RB points, and a bitmask of which points are RB slots
+// (bit (z * n_y + y) * n_x + x).
+struct ProlongBrick {
+  int32_t fbox, pbox;
+  int32_t a[3];
+  int32_t n[3];
+  uint64_t mask[8];
+};
+
 struct RestrictRegion {
   int32_t fbox, pbox;
   int32_t c0[3];        // first parent index (global)
@@ -114,6 +125,22 @@ struct ProlongArgs {
   int32_t nvars;
 };
 
+struct BrickArgs {
+  const ProlongBrick* b;
+  int32_t nbricks;
+  int32_t nout;
+  int32_t nvars;
+  const BoxDev* fboxes;
+  const BoxDev* pboxes;
+  const double* py;
+  const void* pk[4];
+  int64_t pvstride;
+  void* out[kMaxOut];
+  int64_t ovstride;
+  double w[kMaxOut][4];
+  double H;
+};
+
 struct RestrictArgs {
   const RestrictRegion* r;
   int32_t nregions;
@@ -137,10 +164,12 @@ struct PackArgs {
 };
 
 // launchers (kernels.hip); `f32` selects FP32 stencil operands / arrays
-hipError_t launch_stage(const StageArgs& a, int grid, bool f32, hipStream_t s);
+// pz: z planes per barrier step (1 or 2)
+hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int pz, hipStream_t s);
 hipError_t launch_sync(const SyncArgs& a, bool f32, hipStream_t s);
 // k_f32: parent slopes are FP32; out_f32: outputs are FP32
 hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s);
+hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, bool out_f32, hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, bool unpack, bool f32, hipStream_t s);
 hipError_t launch_norms(const PackArgs& a, bool f32, double* partials, int nparts, double* out,
@@ -153,7 +182,9 @@ hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, doub
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 constexpr int kStageThreads = 256;
-constexpr int kTileMaxX = 64;
-constexpr int kTileMaxY = 8;
+constexpr int kStageSlots = 2;    // owned points per thread and plane of a stencil tile
+constexpr int kRingSlots = 2;     // ring points per thread and plane
+constexpr int kWinCap = 1024;     // LDS window points per variable and plane: (nx+6)(ny+6)
+constexpr int kTileMaxX = 64;     // tile width (the Z4c kernels map one lane per x)
 
 }  // namespace sc

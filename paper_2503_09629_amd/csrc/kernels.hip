@@ -28,26 +28,6 @@ __device__ __forceinline__ int64_t padded_offset(const BoxDev& B, int x, int y, 
   return B.base + ((int64_t)(z + kG) * B.py + (y + kG)) * (int64_t)B.px + (x + kG);
 }
 
-// Stage vector at box-local (x, y, z): owned points are formed on the fly as
-// y_n + (c_s dt) k_{s-1} (Y1 = y_n); halo points come from the halo table.
-template <int STAGE, typename TS>
-__device__ __forceinline__ TS stage_value(const StageArgs& a, const BoxDev& B, int x, int y,
-                                          int z, int v) {
-  const int64_t o = padded_offset(B, x, y, z) + v * a.vstride;
-  const bool in = (unsigned)x < (unsigned)B.nx && (unsigned)y < (unsigned)B.ny &&
-                  (unsigned)z < (unsigned)B.nz;
-  if (in) {
-    const TS* yn = static_cast<const TS*>(a.yn);
-    if constexpr (STAGE == 1) {
-      return yn[o];
-    } else {
-      const TS* kp = static_cast<const TS*>(a.kprev);
-      return yn[o] + TS(a.cdt) * kp[o];
-    }
-  }
-  return static_cast<const TS*>(a.Yh)[o];
-}
-
 // Ring of the LDS window of a tile (the 3-point frame around nx x ny owned
 // points): index i in [0, 6(nx+6) + 6ny) -> window coordinates (lx, ly).
 __device__ __forceinline__ void ring_coord(int i, int nx, int ny, int* lx, int* ly) {
@@ -67,24 +47,47 @@ __device__ __forceinline__ void ring_coord(int i, int nx, int ny, int* lx, int* 
   }
 }
 
+template <typename TS>
+__device__ __forceinline__ TS load_at(const char* base, uint32_t byte_off) {
+  return *reinterpret_cast<const TS*>(base + byte_off);
+}
+
+// Stage vector from its raw loads: owned points (in) are y_n + (c_s dt) k_{s-1}
+// (Y1 = y_n); halo points are the halo-table value, loaded into ra.
+template <int STAGE, typename TS>
+__device__ __forceinline__ TS stage_form(TS ra, TS rk, TS cdt, bool in) {
+  if constexpr (STAGE == 1) {
+    return ra;
+  } else {
+    const TS y = ra + cdt * rk;
+    return in ? y : ra;
+  }
+}
+
 // One RK4 stage of the scalar wave on a list of tiles (persistent: workgroups
-// stride over the tile list).  A tile is up to 64 x 8 points in x-y marching
-// through nz planes.  The x-y plane of stage values (tile plus 3-point ring)
-// is staged in LDS (double buffered): the tile's own points come from the
-// 7-plane z column each thread keeps in registers, only the ring is read from
-// memory, and the loads for the next plane are issued before the arithmetic
-// so their latency overlaps it.
+// stride over the tile list).  A tile is nx x ny points in x-y (at most
+// kStageSlots per thread, threads mapped row by row) marching through nz
+// planes, PZ planes per step.  The x-y planes of stage values (tile plus the
+// 3-point ring) are staged in LDS (double buffered, row pitch nx + 6): the
+// tile's own points come from the z column each thread keeps in registers,
+// only the ring is read from memory.  Every load has a valid address (lanes
+// without a point read a clamped one and drop the value), so no load sits
+// behind a branch: the loads for the next step are all in flight during this
+// step's arithmetic, and the stage value Y = y_n + c dt k is formed once they
+// have arrived.  One barrier per step.
 //   k_u  = Pi + Q u,   k_Pi = Lap u + Q Pi
 //   Lap  = ((d2_x + d2_y) + d2_z) / (12 h^2),  Q = sigma/(64 h) ((ko_x + ko_y) + ko_z)
 // Stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4) in FP64.
-template <int STAGE, typename TS>
+template <int STAGE, typename TS, int PZ>
 __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
-  constexpr int BX = kTileMaxX, BY = kStageThreads / kTileMaxX, RY = kTileMaxY / BY;
-  constexpr int LX = BX + 2 * kG, LY = kTileMaxY + 2 * kG;
-  constexpr int RMAX = (6 * LX + 6 * kTileMaxY + kStageThreads - 1) / kStageThreads;
-  __shared__ TS lds[2][2][LY][LX];
-  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
-  const TS clap = TS(a.clap), cko = TS(a.cko);
+  constexpr int S = kStageSlots, RM = kRingSlots;
+  constexpr int QN = 2 * kG + PZ;  // z column: planes z-3 .. z+PZ+2
+  constexpr int NT = kStageThreads;
+  __shared__ TS lds[2][PZ][2][kWinCap];
+  const TS clap = TS(a.clap), cko = TS(a.cko), cdt = TS(a.cdt);
+  const char* yn = static_cast<const char*>(a.yn);
+  const char* kp = static_cast<const char*>(a.kprev);
+  const char* yh = static_cast<const char*>(a.Yh);
   // consecutive workgroups land on different XCDs (round robin over 8); give
   // each XCD a contiguous run of tiles so neighbouring tiles share its L2
   const int g = (gridDim.x % 8 == 0)
@@ -93,131 +96,198 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
   for (int t = g; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
-    const int x = T.x0 + tx;
-    int yy[RY];
-    bool act[RY];
+    const int W = T.nx + 2 * kG;
+    const int64_t ps = (int64_t)B.px * B.py;     // points per z plane
+    const int zlast = T.z0 + T.nz + kG - 1;      // last plane the tile reads
+    // byte offset of plane z of variable v within the level arrays
+    auto plane = [&](int z, int v) -> int64_t {
+      return (int64_t)sizeof(TS) * (B.base + (int64_t)(z + kG) * ps + (int64_t)v * a.vstride);
+    };
+    bool act[S];
+    int li[S];
+    uint32_t cb[S];  // byte offset of the point within its plane
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      yy[r] = T.y0 + ty + r * BY;
-      act[r] = tx < T.nx && (ty + r * BY) < T.ny;
+    for (int s = 0; s < S; ++s) {
+      const int i = threadIdx.x + s * NT;
+      act[s] = i < T.nx * T.ny;
+      const int ic = act[s] ? i : 0;
+      const int px = ic % T.nx, py = ic / T.nx;
+      li[s] = (py + kG) * W + px + kG;
+      cb[s] = (uint32_t)sizeof(TS) * (uint32_t)((T.y0 + py + kG) * B.px + (T.x0 + px + kG));
     }
-    const int nring = 6 * (T.nx + 2 * kG) + 6 * T.ny;
-    int rx[RMAX], ry[RMAX];
-    bool ract[RMAX];
+    const int nring = 6 * W + 6 * T.ny;
+    bool ract[RM], rin[RM];
+    int rli[RM];
+    uint32_t rb[RM];
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k) {
-      const int i = threadIdx.x + k * kStageThreads;
+    for (int k = 0; k < RM; ++k) {
+      const int i = threadIdx.x + k * NT;
       ract[k] = i < nring;
       int lx = 0, ly = 0;
-      if (ract[k]) ring_coord(i, T.nx, T.ny, &lx, &ly);
-      rx[k] = lx;
-      ry[k] = ly;
+      ring_coord(ract[k] ? i : 0, T.nx, T.ny, &lx, &ly);
+      rli[k] = ly * W + lx;
+      const int x = T.x0 - kG + lx, y = T.y0 - kG + ly;
+      rin[k] = (unsigned)x < (unsigned)B.nx && (unsigned)y < (unsigned)B.ny;
+      rb[k] = (uint32_t)sizeof(TS) * (uint32_t)((y + kG) * B.px + (x + kG));
     }
-    TS q[2][RY][7];
-    TS qn[2][RY];
-    TS ring[2][RMAX];
+    TS q[2][S][QN];          // stage values of the z column
+    TS na[2][S][PZ], nk[2][S][PZ];   // raw loads of the next column planes
+    TS ra[PZ][2][RM], rk[PZ][2][RM]; // raw loads of the ring planes
+    // prologue: z column z0-3 .. z0+PZ+2, ring of planes z0 .. z0+PZ-1
 #pragma unroll
-    for (int j = 0; j < 7; ++j)
+    for (int j = 0; j < QN; ++j) {
+      const int z = min(T.z0 - kG + j, zlast);
+      const bool zin = (unsigned)z < (unsigned)B.nz;
 #pragma unroll
-      for (int r = 0; r < RY; ++r)
+      for (int v = 0; v < 2; ++v) {
+        const int64_t pb = plane(z, v);
+        const char* src = (zin ? yn : yh) + pb;
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
-          q[v][r][j] = act[r] ? stage_value<STAGE, TS>(a, B, x, yy[r], T.z0 - kG + j, v) : TS(0);
+        for (int s = 0; s < S; ++s) {
+          const TS va = load_at<TS>(src, cb[s]);
+          const TS vk = STAGE > 1 ? load_at<TS>(kp + pb, cb[s]) : TS(0);
+          q[v][s][j] = stage_form<STAGE, TS>(va, vk, cdt, zin);
+        }
+      }
+    }
 #pragma unroll
-    for (int k = 0; k < RMAX; ++k)
+    for (int p = 0; p < PZ; ++p) {
+      const int z = min(T.z0 + p, T.z0 + T.nz - 1);
 #pragma unroll
-      for (int v = 0; v < 2; ++v)
-        ring[v][k] = ract[k] ? stage_value<STAGE, TS>(a, B, T.x0 - kG + rx[k],
-                                                      T.y0 - kG + ry[k], T.z0, v)
-                             : TS(0);
-    for (int iz = 0; iz < T.nz; ++iz) {
-      const int z = T.z0 + iz;
-      TS(*L)[LY][LX] = lds[iz & 1];
-      // plane z into LDS: own points from the z column, the ring from the
-      // registers filled during the previous iteration
+      for (int v = 0; v < 2; ++v) {
+        const int64_t pb = plane(z, v);
 #pragma unroll
-      for (int r = 0; r < RY; ++r)
+        for (int k = 0; k < RM; ++k) {
+          ra[p][v][k] = load_at<TS>((rin[k] ? yn : yh) + pb, rb[k]);
+          rk[p][v][k] = STAGE > 1 ? load_at<TS>(kp + pb, rb[k]) : TS(0);
+        }
+      }
+    }
+    for (int iz = 0, it = 0; iz < T.nz; iz += PZ, ++it) {
+      TS* L = &lds[it & 1][0][0][0];
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
-          if (act[r]) L[v][ty + r * BY + kG][tx + kG] = q[v][r][3];
+      for (int p = 0; p < PZ; ++p) {
+        const int z = T.z0 + iz + p;
+        const bool zin = (unsigned)z < (unsigned)B.nz;
 #pragma unroll
-      for (int k = 0; k < RMAX; ++k)
+        for (int v = 0; v < 2; ++v) {
+          TS* Lv = L + (p * 2 + v) * kWinCap;
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
-          if (ract[k]) L[v][ry[k]][rx[k]] = ring[v][k];
+          for (int s = 0; s < S; ++s)
+            if (act[s]) Lv[li[s]] = q[v][s][kG + p];
+#pragma unroll
+          for (int k = 0; k < RM; ++k)
+            if (ract[k]) Lv[rli[k]] = stage_form<STAGE, TS>(ra[p][v][k], rk[p][v][k], cdt, rin[k] && zin);
+        }
+      }
       __syncthreads();
-      // loads for the next iteration (ring of plane z+1, own points of plane
-      // z+4), in flight during this iteration's arithmetic
-      const bool more = iz + 1 < T.nz;
+      // loads for the next step (ring planes z+PZ.., column planes z+PZ+3..),
+      // in flight during this step's arithmetic
 #pragma unroll
-      for (int k = 0; k < RMAX; ++k)
+      for (int p = 0; p < PZ; ++p) {
+        const int zr = min(T.z0 + iz + PZ + p, T.z0 + T.nz - 1);
+        const int zq = min(T.z0 + iz + PZ + p + kG, zlast);
+        const bool zqin = (unsigned)zq < (unsigned)B.nz;
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
-          if (more && ract[k])
-            ring[v][k] = stage_value<STAGE, TS>(a, B, T.x0 - kG + rx[k], T.y0 - kG + ry[k],
-                                                z + 1, v);
+        for (int v = 0; v < 2; ++v) {
+          const int64_t pr = plane(zr, v);
 #pragma unroll
-      for (int r = 0; r < RY; ++r)
+          for (int k = 0; k < RM; ++k) {
+            ra[p][v][k] = load_at<TS>((rin[k] ? yn : yh) + pr, rb[k]);
+            rk[p][v][k] = STAGE > 1 ? load_at<TS>(kp + pr, rb[k]) : TS(0);
+          }
+          const int64_t pq = plane(zq, v);
+          const char* src = (zqin ? yn : yh) + pq;
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
-          qn[v][r] = (more && act[r]) ? stage_value<STAGE, TS>(a, B, x, yy[r], z + kG + 1, v)
-                                      : TS(0);
+          for (int s = 0; s < S; ++s) {
+            na[v][s][p] = load_at<TS>(src, cb[s]);
+            nk[v][s][p] = STAGE > 1 ? load_at<TS>(kp + pq, cb[s]) : TS(0);
+          }
+        }
+      }
 #pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        if (act[r]) {
-          const int lx = tx + kG, ly = ty + r * BY + kG;
-          const TS cu = q[0][r][3], cp = q[1][r][3];
-          const TS lapx = d2<TS>(L[0][ly][lx - 2], L[0][ly][lx - 1], cu, L[0][ly][lx + 1],
-                                 L[0][ly][lx + 2]);
-          const TS lapy = d2<TS>(L[0][ly - 2][lx], L[0][ly - 1][lx], cu, L[0][ly + 1][lx],
-                                 L[0][ly + 2][lx]);
-          const TS lapz = d2<TS>(q[0][r][1], q[0][r][2], cu, q[0][r][4], q[0][r][5]);
+      for (int p = 0; p < PZ; ++p) {
+        if (iz + p >= T.nz) break;
+        const int z = T.z0 + iz + p;
+        const TS* Lu = L + (p * 2) * kWinCap;
+        const TS* Lp = L + (p * 2 + 1) * kWinCap;
+        // stage 4 reads the slopes and y_n at the point: issue those loads first
+        TS c1[2][S], c2[2][S], c3[2][S];
+        double c0[2][S];
+        const int64_t pe = B.base + (int64_t)(z + kG) * ps;   // element offset of the plane
+        if constexpr (STAGE == 4) {
+          const TS* k1 = static_cast<const TS*>(a.k1);
+          const TS* k2 = static_cast<const TS*>(a.k2);
+          const TS* k3 = static_cast<const TS*>(a.k3);
+#pragma unroll
+          for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+              const int64_t o = pe + cb[s] / (uint32_t)sizeof(TS) + v * a.vstride;
+              c1[v][s] = k1[o];
+              c2[v][s] = k2[o];
+              c3[v][s] = k3[o];
+              c0[v][s] = a.yn64[o];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          if (!act[s]) continue;
+          const int c = li[s];
+          const TS cu = q[0][s][kG + p], cp = q[1][s][kG + p];
+          const TS lapx = d2<TS>(Lu[c - 2], Lu[c - 1], cu, Lu[c + 1], Lu[c + 2]);
+          const TS lapy = d2<TS>(Lu[c - 2 * W], Lu[c - W], cu, Lu[c + W], Lu[c + 2 * W]);
+          const TS lapz = d2<TS>(q[0][s][p + 1], q[0][s][p + 2], cu, q[0][s][p + 4], q[0][s][p + 5]);
           const TS lap = ((lapx + lapy) + lapz) * clap;
           TS Q[2];
 #pragma unroll
           for (int v = 0; v < 2; ++v) {
-            const TS c = q[v][r][3];
-            const TS kx = ko7<TS>(L[v][ly][lx - 3], L[v][ly][lx - 2], L[v][ly][lx - 1], c,
-                                  L[v][ly][lx + 1], L[v][ly][lx + 2], L[v][ly][lx + 3]);
-            const TS ky = ko7<TS>(L[v][ly - 3][lx], L[v][ly - 2][lx], L[v][ly - 1][lx], c,
-                                  L[v][ly + 1][lx], L[v][ly + 2][lx], L[v][ly + 3][lx]);
-            const TS kz = ko7<TS>(q[v][r][0], q[v][r][1], q[v][r][2], c, q[v][r][4],
-                                  q[v][r][5], q[v][r][6]);
+            const TS* Lv = v == 0 ? Lu : Lp;
+            const TS cc = q[v][s][kG + p];
+            const TS kx = ko7<TS>(Lv[c - 3], Lv[c - 2], Lv[c - 1], cc, Lv[c + 1], Lv[c + 2], Lv[c + 3]);
+            const TS ky = ko7<TS>(Lv[c - 3 * W], Lv[c - 2 * W], Lv[c - W], cc, Lv[c + W],
+                                  Lv[c + 2 * W], Lv[c + 3 * W]);
+            const TS kz = ko7<TS>(q[v][s][p], q[v][s][p + 1], q[v][s][p + 2], cc, q[v][s][p + 4],
+                                  q[v][s][p + 5], q[v][s][p + 6]);
             Q[v] = cko * ((kx + ky) + kz);
           }
           const TS kv[2] = {cp + Q[0], lap + Q[1]};
-          const int64_t o = padded_offset(B, x, yy[r], z);
+          const int64_t o = pe + cb[s] / (uint32_t)sizeof(TS);
           if (a.write_k) {
             TS* ko = static_cast<TS*>(a.kout);
             ko[o] = kv[0];
             ko[o + a.vstride] = kv[1];
           }
           if constexpr (STAGE == 4) {
-            const TS* k1 = static_cast<const TS*>(a.k1);
-            const TS* k2 = static_cast<const TS*>(a.k2);
-            const TS* k3 = static_cast<const TS*>(a.k3);
 #pragma unroll
             for (int v = 0; v < 2; ++v) {
               const int64_t ov = o + v * a.vstride;
-              const double s = (((double)k1[ov] + 2.0 * (double)k2[ov]) + 2.0 * (double)k3[ov]) +
-                               (double)kv[v];
-              const double yv = a.yn64[ov] + a.dt6 * s;
+              const double sm = (((double)c1[v][s] + 2.0 * (double)c2[v][s]) + 2.0 * (double)c3[v][s]) +
+                                (double)kv[v];
+              const double yv = c0[v][s] + a.dt6 * sm;
               a.ynew[ov] = yv;
               if constexpr (sizeof(TS) == 4) a.ynew32[ov] = (float)yv;
             }
           }
         }
       }
+      // advance the z column by PZ planes
 #pragma unroll
-      for (int j = 0; j < 6; ++j)
+      for (int j = 0; j < QN - PZ; ++j)
 #pragma unroll
-        for (int r = 0; r < RY; ++r)
+        for (int s = 0; s < S; ++s)
 #pragma unroll
-          for (int v = 0; v < 2; ++v) q[v][r][j] = q[v][r][j + 1];
+          for (int v = 0; v < 2; ++v) q[v][s][j] = q[v][s][j + PZ];
 #pragma unroll
-      for (int r = 0; r < RY; ++r)
+      for (int p = 0; p < PZ; ++p) {
+        const int zq = T.z0 + iz + PZ + p + kG;
+        const bool zqin = (unsigned)zq < (unsigned)B.nz;
 #pragma unroll
-        for (int v = 0; v < 2; ++v) q[v][r][6] = qn[v][r];
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int v = 0; v < 2; ++v)
+            q[v][s][QN - PZ + p] = stage_form<STAGE, TS>(na[v][s][p], nk[v][s][p], cdt, zqin);
+      }
     }
     __syncthreads();
   }
@@ -325,6 +395,126 @@ __global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
     case 5: prolong_one<1, 0, 1, TK, TO>(a, i); break;
     case 6: prolong_one<0, 1, 1, TK, TO>(a, i); break;
     default: prolong_one<1, 1, 1, TK, TO>(a, i); break;
+  }
+}
+
+// Brick prolongation: one workgroup per brick.  For each variable and each
+// of the five vectors, the coarse region under the brick (at most 10^3
+// points) is staged in LDS, interpolated along x for every fine x of the
+// brick, then along y, then along z (the same left-to-right sums as the
+// per-point form, so the values are identical), and the eight dense-output
+// combinations are written for the brick's RB points.
+constexpr int kBrick = 8, kBrickC = 10;
+
+template <typename TK, typename TO>
+__global__ __launch_bounds__(256) void k_prolong_bricks(BrickArgs a) {
+  __shared__ double V[kBrickC][kBrickC][kBrickC];
+  __shared__ double PX[kBrickC][kBrickC][kBrick];
+  __shared__ double PY[kBrickC][kBrick][kBrick];
+  constexpr double W[6] = {3.0 / 256.0, -25.0 / 256.0, 150.0 / 256.0,
+                           150.0 / 256.0, -25.0 / 256.0, 3.0 / 256.0};
+  const ProlongBrick Bk = a.b[blockIdx.x];
+  const BoxDev F = a.fboxes[Bk.fbox];
+  const BoxDev P = a.pboxes[Bk.pbox];
+  int C0[3], cn[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    C0[d] = (Bk.a[d] >> 1) - 2;                       // a >= 0: shift is floor
+    cn[d] = ((Bk.a[d] + Bk.n[d] - 1) >> 1) + 3 - C0[d] + 1;
+  }
+  const int pn[3] = {P.nx, P.ny, P.nz};
+  const int64_t pitch[3] = {1, (int64_t)P.px, (int64_t)P.px * P.py};
+  const int npts = Bk.n[0] * Bk.n[1] * Bk.n[2];
+  const int tid = threadIdx.x;
+  // this thread's fine points (at most two)
+  double Pv[2][5];
+  for (int v = 0; v < a.nvars; ++v) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const int64_t vb = P.base + v * a.pvstride;
+      for (int i = tid; i < cn[0] * cn[1] * cn[2]; i += 256) {
+        const int cx = i % cn[0], cy = (i / cn[0]) % cn[1], cz = i / (cn[0] * cn[1]);
+        const int c[3] = {cx, cy, cz};
+        int64_t o = vb;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          int I = C0[d] + c[d];
+          if (P.wrapN[d] > 0) I = ((I % P.wrapN[d]) + P.wrapN[d]) % P.wrapN[d];
+          int loc = I - P.lo[d];
+          loc = loc < -kG ? -kG : (loc > pn[d] + kG - 1 ? pn[d] + kG - 1 : loc);
+          o += (int64_t)(loc + kG) * pitch[d];
+        }
+        V[cz][cy][cx] = m == 0 ? a.py[o] : (double)static_cast<const TK*>(a.pk[m - 1])[o];
+      }
+      __syncthreads();
+      // x: PX[cz][cy][fx]
+      for (int i = tid; i < cn[2] * cn[1] * Bk.n[0]; i += 256) {
+        const int fx = i % Bk.n[0], cy = (i / Bk.n[0]) % cn[1], cz = i / (Bk.n[0] * cn[1]);
+        const int q = Bk.a[0] + fx;
+        const int b = (q >> 1) - C0[0];
+        double px;
+        if (q & 1) {
+          px = W[0] * V[cz][cy][b - 2];
+#pragma unroll
+          for (int j = 1; j < 6; ++j) px = px + W[j] * V[cz][cy][b - 2 + j];
+        } else {
+          px = V[cz][cy][b];
+        }
+        PX[cz][cy][fx] = px;
+      }
+      __syncthreads();
+      // y: PY[cz][fy][fx]
+      for (int i = tid; i < cn[2] * Bk.n[1] * Bk.n[0]; i += 256) {
+        const int fx = i % Bk.n[0], fy = (i / Bk.n[0]) % Bk.n[1], cz = i / (Bk.n[0] * Bk.n[1]);
+        const int q = Bk.a[1] + fy;
+        const int b = (q >> 1) - C0[1];
+        double py;
+        if (q & 1) {
+          py = W[0] * PX[cz][b - 2][fx];
+#pragma unroll
+          for (int j = 1; j < 6; ++j) py = py + W[j] * PX[cz][b - 2 + j][fx];
+        } else {
+          py = PX[cz][b][fx];
+        }
+        PY[cz][fy][fx] = py;
+      }
+      __syncthreads();
+      // z: this thread's points
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int i = tid + k * 256;
+        if (i < npts) {
+          const int fx = i % Bk.n[0], fy = (i / Bk.n[0]) % Bk.n[1], fz = i / (Bk.n[0] * Bk.n[1]);
+          const int q = Bk.a[2] + fz;
+          const int b = (q >> 1) - C0[2];
+          double pz;
+          if (q & 1) {
+            pz = W[0] * PY[b - 2][fy][fx];
+#pragma unroll
+            for (int j = 1; j < 6; ++j) pz = pz + W[j] * PY[b - 2 + j][fy][fx];
+          } else {
+            pz = PY[b][fy][fx];
+          }
+          Pv[k][m] = pz;
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int i = tid + k * 256;
+      if (i < npts && ((a.b[blockIdx.x].mask[i >> 6] >> (i & 63)) & 1)) {
+        const int fx = i % Bk.n[0], fy = (i / Bk.n[0]) % Bk.n[1], fz = i / (Bk.n[0] * Bk.n[1]);
+        const int64_t dst = F.base +
+                            ((int64_t)(Bk.a[2] + fz - F.lo[2] + kG) * F.py + (Bk.a[1] + fy - F.lo[1] + kG)) *
+                                (int64_t)F.px + (Bk.a[0] + fx - F.lo[0] + kG) + v * a.ovstride;
+        for (int o = 0; o < a.nout; ++o) {
+          const double s = ((a.w[o][0] * Pv[k][1] + a.w[o][1] * Pv[k][2]) + a.w[o][2] * Pv[k][3]) +
+                           a.w[o][3] * Pv[k][4];
+          static_cast<TO*>(a.out[o])[dst] = (TO)(Pv[k][0] + a.H * s);
+        }
+      }
+    }
   }
 }
 
@@ -460,24 +650,29 @@ __global__ __launch_bounds__(256) void k_to_f32(const double* src, float* dst, i
 
 inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-template <typename TS>
+template <typename TS, int PZ>
 void stage_dispatch(const StageArgs& a, dim3 g, hipStream_t s) {
   const dim3 b(kStageThreads);
   switch (a.stage) {
-    case 1: hipLaunchKernelGGL((k_wave_stage<1, TS>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_wave_stage<2, TS>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_wave_stage<3, TS>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_wave_stage<4, TS>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_wave_stage<1, TS, PZ>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_wave_stage<2, TS, PZ>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_wave_stage<3, TS, PZ>), g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_wave_stage<4, TS, PZ>), g, b, 0, s, a); break;
   }
 }
 
 }  // namespace
 
-hipError_t launch_stage(const StageArgs& a, int grid, bool f32, hipStream_t s) {
+hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int pz, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g(grid > 0 ? grid : a.ntiles);
-  if (f32) stage_dispatch<float>(a, g, s);
-  else stage_dispatch<double>(a, g, s);
+  if (f32) {
+    if (pz == 2) stage_dispatch<float, 2>(a, g, s);
+    else stage_dispatch<float, 1>(a, g, s);
+  } else {
+    if (pz == 2) stage_dispatch<double, 2>(a, g, s);
+    else stage_dispatch<double, 1>(a, g, s);
+  }
   return hipGetLastError();
 }
 
@@ -495,6 +690,16 @@ hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStr
   else if (k_f32 && out_f32) hipLaunchKernelGGL((k_prolong<float, float>), g, b, 0, s, a);
   else if (k_f32) hipLaunchKernelGGL((k_prolong<float, double>), g, b, 0, s, a);
   else hipLaunchKernelGGL((k_prolong<double, float>), g, b, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, bool out_f32, hipStream_t s) {
+  if (a.nbricks <= 0) return hipSuccess;
+  const dim3 g(a.nbricks), b(256);
+  if (!k_f32 && !out_f32) hipLaunchKernelGGL((k_prolong_bricks<double, double>), g, b, 0, s, a);
+  else if (k_f32 && out_f32) hipLaunchKernelGGL((k_prolong_bricks<float, float>), g, b, 0, s, a);
+  else if (k_f32) hipLaunchKernelGGL((k_prolong_bricks<float, double>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_prolong_bricks<double, float>), g, b, 0, s, a);
   return hipGetLastError();
 }
 

@@ -13,8 +13,9 @@
 namespace sc {
 
 struct TileShape {
-  int tx = kTileMaxX, ty = kTileMaxY, tz = 16;
+  int tx = kTileMaxX, ty = 1 << 20, tz = 16;   // tx, ty: caps on the tile width and height
   int grid = 0;   // persistent workgroups for the batched stage kernel (0: context default)
+  int pz = 1;     // z planes per barrier step of the stage kernel
 };
 
 // z-chunk depths the autotuner tries; the tile table region is sized for the
@@ -31,7 +32,8 @@ struct LevelDev {
   std::vector<BoxDev> boxes;         // all members
   std::vector<int64_t> prefix;       // canonical prefix per member box (nb_member + 1)
   std::vector<SyncEntry> sync;
-  std::vector<ProlongEntry> prolong; // RB halo slots, sorted by parity class
+  std::vector<ProlongBrick> bricks;   // RB halo slots grouped in bricks (all members)
+  std::vector<ProlongEntry> prolong; // remaining RB halo slots, sorted by parity class
   int64_t prolong_cls[9] = {0};      // class prefix of `prolong`
   int64_t rblist_cls[9] = {0};       // class prefix of one member's `rblist`
   std::vector<ProlongEntry> rblist;  // RB list entries of every member, dst = list index j
@@ -49,7 +51,7 @@ struct LevelDev {
   bool has_child = false;
   // arena offsets (bytes)
   size_t o_y[2], o_y32[2], o_k[4], o_yh[8], o_boxes, o_prefix, o_sync, o_prolong, o_rblist,
-      o_rbfirst, o_phys, o_restr, o_tiles, o_btiles, o_ys;
+      o_rbfirst, o_phys, o_restr, o_tiles, o_btiles, o_ys, o_bricks;
   // device pointers after binding.  y: FP64 state; y32: its FP32 shadow
   // (mixed mode only); k and Yh hold the stencil type (FP64, or FP32 in
   // mixed mode).
@@ -62,6 +64,7 @@ struct LevelDev {
   int64_t* d_prefix = nullptr;
   SyncEntry* d_sync = nullptr;
   ProlongEntry* d_prolong = nullptr;
+  ProlongBrick* d_bricks = nullptr;
   ProlongEntry* d_rblist = nullptr;
   int64_t* d_rbfirst = nullptr;
   int64_t* d_phys = nullptr;
