@@ -227,12 +227,14 @@ def main():
     if args.copy_probe_mib > 0:
         import torch
         n = args.copy_probe_mib << 17          # float64 elements
-        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        src = torch.ones(n + 1, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+        for _ in range(3):                     # runtime copy kernel, 16 B per lane
+            dst[:n].copy_(src[:n])
+        for _ in range(3):                     # elementwise kernel at an odd offset: 8 B per lane
+            torch.mul(src[1:], 1.0, out=dst[1:])
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_each_way": n * 8, "launches": 3}), flush=True)
+        print(json.dumps({"copy_probe_bytes_each_way": n * 8, "launches": 6}), flush=True)
         return
     if args.workload == "z4c":
         print(json.dumps(z4c_run(args)), flush=True)
@@ -266,7 +268,7 @@ def main():
                 tuned = json.loads(f.read().strip().splitlines()[-1])["modes"][m]
             for l in range(spec.nlevels):
                 ctx.set_tile_shape(l, tuned["tz_per_level"][l], tuned["grid_per_level"][l],
-                                   tuned["pz_per_level"][l])
+                                   tuned["pz_per_level"][l], tuned["slots_per_level"][l])
         elif m != "per_block" and not args.no_tune:
             ctx.autotune(3)
         shapes = [ctx.tile_shape(l) for l in range(spec.nlevels)]
@@ -277,7 +279,8 @@ def main():
         res[m] = {"updates_per_s": U * steps / T, "ms_per_step": 1e3 * T / steps,
                   "steps": steps, "tz_per_level": [sh["tz"] for sh in shapes],
                   "grid_per_level": [sh["grid"] for sh in shapes],
-                  "pz_per_level": [sh["pz"] for sh in shapes]}
+                  "pz_per_level": [sh["pz"] for sh in shapes],
+                  "slots_per_level": [sh["slots"] for sh in shapes]}
         log(f"{m}: {1e3 * T / steps:.2f} ms/step, {U * steps / T:.4g} updates/s")
         if m in ("batched", "mixed_batched"):
             label = "roofline" if m == "batched" else "roofline_mixed"

@@ -114,15 +114,15 @@ void split_even(int64_t n, int64_t maxlen, std::vector<std::pair<int, int>>* out
 // Largest tile height for tiles at most nxm points wide: at most
 // kStageSlots owned points per thread, an LDS window of at most kWinCap points
 // and at most kRingSlots ring points per thread.
-int tile_ty_cap(int nxm) {
-  int t = kStageThreads * kStageSlots / nxm;
+int tile_ty_cap(int nxm, int slots) {
+  int t = kStageThreads * slots / nxm;
   t = std::min(t, kWinCap / (nxm + 2 * kG) - 2 * kG);
   t = std::min(t, (kStageThreads * kRingSlots - 6 * (nxm + 2 * kG)) / 6);
   return std::max(t, 1);
 }
 
-bool tile_fits(int nx, int ny) {
-  return nx >= 1 && ny >= 1 && nx <= kTileMaxX && nx * ny <= kStageThreads * kStageSlots &&
+bool tile_fits(int nx, int ny, int slots) {
+  return nx >= 1 && ny >= 1 && nx <= kTileMaxX && nx * ny <= kStageThreads * slots &&
          (nx + 2 * kG) * (ny + 2 * kG) <= kWinCap &&
          6 * (nx + 2 * kG) + 6 * ny <= kStageThreads * kRingSlots;
 }
@@ -133,20 +133,22 @@ void tile_region(int box, const int64_t o[3], const int64_t n[3], const TileShap
   split_even(n[0], std::min(s.tx, kTileMaxX), &sx);
   int nxm = 1;
   for (auto& x : sx) nxm = std::max(nxm, x.second);
-  split_even(n[1], std::min(s.ty, tile_ty_cap(nxm)), &sy);
+  split_even(n[1], std::min(s.ty, tile_ty_cap(nxm, s.slots)), &sy);
   split_even(n[2], s.tz, &sz);
-  for (auto& z : sz)
+  for (size_t iz = 0; iz < sz.size(); ++iz)
     for (auto& y : sy)
       for (auto& x : sx) {
         TileDev t;
         t.box = box;
         t.x0 = (int)o[0] + x.first;
         t.y0 = (int)o[1] + y.first;
-        t.z0 = (int)o[2] + z.first;
+        t.z0 = (int)o[2] + sz[iz].first;
         t.nx = x.second;
         t.ny = y.second;
-        t.nz = z.second;
-        t.pad = 0;
+        t.nz = sz[iz].second;
+        // neighbouring z chunks march towards (and away from) their common
+        // face at the same time, so its halo planes are read while cached
+        t.dir = (int32_t)(iz & 1);
         out->push_back(t);
       }
 }
@@ -425,17 +427,17 @@ std::string validate_layout(const sc_ctx* c) {
   for (size_t l = 0; l < c->lev.size(); ++l) {
     const LevelDev& L = c->lev[l];
     auto in_level = [&](int64_t o) { return o >= 0 && o < L.total; };
-    auto tile_ok = [&](const TileDev& t) {
+    auto tile_ok = [&](const TileDev& t, int slots) {
       if (t.box < 0 || t.box >= (int)L.boxes.size()) return false;
       const BoxDev& B = L.boxes[t.box];
-      return tile_fits(t.nx, t.ny) && t.nz >= 1 &&
+      return tile_fits(t.nx, t.ny, slots) && t.nz >= 1 && (t.dir == 0 || t.dir == 1) &&
              t.x0 >= 0 && t.y0 >= 0 && t.z0 >= 0 && t.x0 + t.nx <= B.nx &&
              t.y0 + t.ny <= B.ny && t.z0 + t.nz <= B.nz;
     };
     for (const TileDev& t : L.tiles)
-      if (!tile_ok(t)) return "tile outside its box";
+      if (!tile_ok(t, L.shape.slots)) return "tile outside its box";
     for (const TileDev& t : L.btiles)
-      if (!tile_ok(t)) return "block tile outside its box";
+      if (!tile_ok(t, kStageSlotsMax)) return "block tile outside its box";
     for (const BoxDev& B : L.boxes)
       if (!in_level(B.base) ||
           B.base + (int64_t)B.px * B.py * (B.nz + 2 * kG) > L.total)
@@ -543,6 +545,7 @@ void plan_arena(sc_ctx* c) {
       std::vector<TileDev> most;
       TileShape sh = L.shape;
       sh.tz = kTuneTzMin;
+      sh.slots = 1;
       for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
         const BoxDev& B = L.boxes[ib];
         const int64_t o[3] = {0, 0, 0}, n[3] = {B.nx, B.ny, B.nz};
@@ -627,7 +630,7 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
       if (rc) return rc;
       HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    HIPCHK(c, launch_stage(a, grid, c->mixed, L.shape.pz, c->stream));
+    HIPCHK(c, launch_stage(a, grid, c->mixed, L.shape.pz, L.shape.slots, c->stream));
     if (c->profiling) {
       HIPCHK(c, hipEventRecord(e1, c->stream));
       // algorithmic bytes per owned point and variable: the stencil operands
@@ -645,7 +648,7 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
     for (int b = 0; b < nblk; ++b) {
       a.tiles = L.d_btiles + L.btile_start[b];
       a.ntiles = L.btile_start[b + 1] - L.btile_start[b];
-      HIPCHK(c, launch_stage(a, a.ntiles, c->mixed, 1, c->stream));
+      HIPCHK(c, launch_stage(a, a.ntiles, c->mixed, 1, kStageSlotsMax, c->stream));
       ++c->launches;
     }
   }
@@ -1402,17 +1405,20 @@ static void drop_graphs(sc_ctx* c) {
   }
 }
 
-int sc_set_tile_shape(sc_ctx* c, int32_t level, int32_t tz, int32_t grid, int32_t pz) {
+int sc_set_tile_shape(sc_ctx* c, int32_t level, int32_t tz, int32_t grid, int32_t pz,
+                      int32_t slots) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
   if (level < 0 || level >= (int)c->lev.size()) return fail(c, SC_E_ARG, "level out of range");
   if (tz < kTuneTzMin || tz > (1 << 20)) return fail(c, SC_E_ARG, "z-chunk out of range");
   if (grid < 0) return fail(c, SC_E_ARG, "grid must be >= 0");
   if (pz != 1 && pz != 2) return fail(c, SC_E_ARG, "planes per step must be 1 or 2");
+  if (slots != 1 && slots != 2) return fail(c, SC_E_ARG, "points per thread must be 1 or 2");
   LevelDev& L = c->lev[level];
   TileShape sh = L.shape;
   sh.tz = tz;
   sh.pz = pz;
+  sh.slots = slots;
   std::vector<TileDev> tl;
   for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
     const BoxDev& B = L.boxes[ib];
@@ -1449,9 +1455,11 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
     float best = 1e30f;
     TileShape best_shape = L.shape;
     std::vector<TileDev> best_tiles = L.tiles;
+    for (int slots : {2, 1})
     for (int tz : kTuneTz) {
       TileShape sh = L.shape;
       sh.tz = tz;
+      sh.slots = slots;
       std::vector<TileDev> tl;
       for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
         const BoxDev& B = L.boxes[ib];
@@ -1502,7 +1510,7 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
   return SC_OK;
 }
 
-int sc_tile_shape(const sc_ctx* c, int32_t level, int32_t out[6]) {
+int sc_tile_shape(const sc_ctx* c, int32_t level, int32_t out[7]) {
   int rc = check_ready(c, 1);
   if (rc) return rc;
   if (level < 0 || level >= (int)c->lev.size() || !out) return SC_E_ARG;
@@ -1517,6 +1525,7 @@ int sc_tile_shape(const sc_ctx* c, int32_t level, int32_t out[6]) {
   out[3] = L.shape.grid > 0 ? L.shape.grid : std::min<int>((int)L.tiles.size(), c->grid_cap);
   out[4] = (int32_t)L.tiles.size();
   out[5] = L.shape.pz;
+  out[6] = L.shape.slots;
   return SC_OK;
 }
 

@@ -35,7 +35,7 @@ struct TileDev {
   int32_t box;
   int32_t x0, y0, z0;   // box-local owned coordinates of the tile origin
   int32_t nx, ny, nz;
-  int32_t pad;
+  int32_t dir;          // stage kernel z marching direction: 0 upward, 1 downward
 };
 
 struct SyncEntry {      // halo point <- owned point of the same level
@@ -164,8 +164,9 @@ struct PackArgs {
 };
 
 // launchers (kernels.hip); `f32` selects FP32 stencil operands / arrays
-// pz: z planes per barrier step (1 or 2)
-hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int pz, hipStream_t s);
+// pz: z planes per barrier step (1 or 2); slots: owned points per thread (1 or 2),
+// which the tiles must have been cut for
+hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int pz, int slots, hipStream_t s);
 hipError_t launch_sync(const SyncArgs& a, bool f32, hipStream_t s);
 // k_f32: parent slopes are FP32; out_f32: outputs are FP32
 hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s);
@@ -182,7 +183,7 @@ hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, doub
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
 constexpr int kStageThreads = 256;
-constexpr int kStageSlots = 2;    // owned points per thread and plane of a stencil tile
+constexpr int kStageSlotsMax = 2; // owned points per thread and plane of a stencil tile (1 or 2)
 constexpr int kRingSlots = 2;     // ring points per thread and plane
 constexpr int kWinCap = 1024;     // LDS window points per variable and plane: (nx+6)(ny+6)
 constexpr int kTileMaxX = 64;     // tile width (the Z4c kernels map one lane per x)

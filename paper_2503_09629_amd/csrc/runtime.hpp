@@ -16,6 +16,7 @@ struct TileShape {
   int tx = kTileMaxX, ty = 1 << 20, tz = 16;   // tx, ty: caps on the tile width and height
   int grid = 0;   // persistent workgroups for the batched stage kernel (0: context default)
   int pz = 1;     // z planes per barrier step of the stage kernel
+  int slots = 2;  // owned points per stage-kernel thread (tiles of at most 256 slots points)
 };
 
 // z-chunk depths the autotuner tries; the tile table region is sized for the
