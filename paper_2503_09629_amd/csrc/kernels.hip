@@ -420,17 +420,40 @@ __global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
 // points) is staged in LDS, interpolated along x for every fine x of the
 // brick, then along y, then along z (the same left-to-right sums as the
 // per-point form, so the values are identical), and the eight dense-output
-// combinations are written for the brick's RB points.
+// combinations are written for the brick's RB points.  Each thread's share
+// of every pass (source and destination places in LDS) is worked out once
+// per brick; the coarse values of all five vectors of the next variable are
+// loaded into registers while the current variable is interpolated.
 constexpr int kBrick = 8, kBrickC = 10;
+constexpr int kBrickLoads = (kBrickC * kBrickC * kBrickC + 255) / 256;   // per thread and vector
+constexpr int kBrickXE = (kBrickC * kBrickC * kBrick + 255) / 256;       // x-pass outputs per thread
+constexpr int kBrickYE = (kBrickC * kBrick * kBrick + 255) / 256;        // y-pass outputs per thread
+constexpr int kBrickZE = (kBrick * kBrick * kBrick + 255) / 256;         // fine points per thread
+
+// 6-point Lagrange value at the midpoint, or a copy, from src[0], src[st], ...
+__device__ __forceinline__ double brick_tap(const double* src, int st, bool odd) {
+  constexpr double W[6] = {3.0 / 256.0, -25.0 / 256.0, 150.0 / 256.0,
+                           150.0 / 256.0, -25.0 / 256.0, 3.0 / 256.0};
+  if (!odd) return src[0];
+  double r = W[0] * src[0];
+#pragma unroll
+  for (int j = 1; j < 6; ++j) r = r + W[j] * src[j * st];
+  return r;
+}
 
 template <typename TK, typename TO>
 __global__ __launch_bounds__(256) void k_prolong_bricks(BrickArgs a) {
-  __shared__ double V[kBrickC][kBrickC][kBrickC];
-  __shared__ double PX[kBrickC][kBrickC][kBrick];
-  __shared__ double PY[kBrickC][kBrick][kBrick];
-  constexpr double W[6] = {3.0 / 256.0, -25.0 / 256.0, 150.0 / 256.0,
-                           150.0 / 256.0, -25.0 / 256.0, 3.0 / 256.0};
-  const ProlongBrick Bk = a.b[blockIdx.x];
+  __shared__ double V[kBrickC * kBrickC * kBrickC];     // [cz][cy][cx]
+  __shared__ double PX[kBrickC * kBrickC * kBrick];     // [cz][cy][fx]
+  __shared__ double PY[kBrickC * kBrick * kBrick];      // [cz][fy][fx]
+  constexpr int NL = kBrickLoads, XE = kBrickXE, YE = kBrickYE, ZE = kBrickZE;
+  // consecutive workgroups land on different XCDs; give each XCD a
+  // contiguous run of bricks so overlapping coarse regions share its L2
+  const int g = (gridDim.x % 8 == 0)
+                    ? (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8)
+                    : (int)blockIdx.x;
+  if (g >= a.nbricks) return;
+  const ProlongBrick Bk = a.b[g];
   const BoxDev F = a.fboxes[Bk.fbox];
   const BoxDev P = a.pboxes[Bk.pbox];
   int C0[3], cn[3];
@@ -439,99 +462,119 @@ __global__ __launch_bounds__(256) void k_prolong_bricks(BrickArgs a) {
     C0[d] = (Bk.a[d] >> 1) - 2;                       // a >= 0: shift is floor
     cn[d] = ((Bk.a[d] + Bk.n[d] - 1) >> 1) + 3 - C0[d] + 1;
   }
+  const int n0 = Bk.n[0], n1 = Bk.n[1];
   const int pn[3] = {P.nx, P.ny, P.nz};
   const int64_t pitch[3] = {1, (int64_t)P.px, (int64_t)P.px * P.py};
-  const int npts = Bk.n[0] * Bk.n[1] * Bk.n[2];
+  const int npts = n0 * n1 * Bk.n[2];
+  const int ncoarse = cn[0] * cn[1] * cn[2];
   const int tid = threadIdx.x;
-  // this thread's fine points (at most two)
-  double Pv[2][5];
+  // coarse points of this thread: offset in the parent arrays (periodic wrap,
+  // then clamped into the padded box) and place in V
+  int64_t co[NL];
+  int vi[NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const int i = tid + j * 256;
+    const int ic = i < ncoarse ? i : 0;
+    const int c[3] = {ic % cn[0], (ic / cn[0]) % cn[1], ic / (cn[0] * cn[1])};
+    int64_t o = P.base;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int I = C0[d] + c[d];
+      if (P.wrapN[d] > 0) I = ((I % P.wrapN[d]) + P.wrapN[d]) % P.wrapN[d];
+      int loc = I - P.lo[d];
+      loc = loc < -kG ? -kG : (loc > pn[d] + kG - 1 ? pn[d] + kG - 1 : loc);
+      o += (int64_t)(loc + kG) * pitch[d];
+    }
+    co[j] = o;
+    vi[j] = i < ncoarse ? (c[2] * kBrickC + c[1]) * kBrickC + c[0] : -1;
+  }
+  // pass assignments: source base and stride in the input array, output place
+  int xs[XE], xd[XE], ys[YE], yd[YE], zs[ZE];
+  bool xo[XE], yo[YE], zo[ZE];
+#pragma unroll
+  for (int e = 0; e < XE; ++e) {
+    const int i = tid + e * 256;
+    const bool ok = i < cn[2] * cn[1] * n0;
+    const int ic = ok ? i : 0;
+    const int fx = ic % n0, cy = (ic / n0) % cn[1], cz = ic / (n0 * cn[1]);
+    const int q = Bk.a[0] + fx, b = (q >> 1) - C0[0];
+    xo[e] = q & 1;
+    xs[e] = (cz * kBrickC + cy) * kBrickC + (xo[e] ? b - 2 : b);
+    xd[e] = ok ? (cz * kBrickC + cy) * kBrick + fx : -1;
+  }
+#pragma unroll
+  for (int e = 0; e < YE; ++e) {
+    const int i = tid + e * 256;
+    const bool ok = i < cn[2] * n1 * n0;
+    const int ic = ok ? i : 0;
+    const int fx = ic % n0, fy = (ic / n0) % n1, cz = ic / (n0 * n1);
+    const int q = Bk.a[1] + fy, b = (q >> 1) - C0[1];
+    yo[e] = q & 1;
+    ys[e] = (cz * kBrickC + (yo[e] ? b - 2 : b)) * kBrick + fx;
+    yd[e] = ok ? (cz * kBrick + fy) * kBrick + fx : -1;
+  }
+  int64_t dst[ZE];
+  bool zw[ZE];
+#pragma unroll
+  for (int e = 0; e < ZE; ++e) {
+    const int i = tid + e * 256;
+    const bool ok = i < npts;
+    const int ic = ok ? i : 0;
+    const int fx = ic % n0, fy = (ic / n0) % n1, fz = ic / (n0 * n1);
+    const int q = Bk.a[2] + fz, b = (q >> 1) - C0[2];
+    zo[e] = q & 1;
+    zs[e] = ((zo[e] ? b - 2 : b) * kBrick + fy) * kBrick + fx;
+    zw[e] = ok && ((a.b[g].mask[ic >> 6] >> (ic & 63)) & 1);
+    dst[e] = F.base + ((int64_t)(Bk.a[2] + fz - F.lo[2] + kG) * F.py + (Bk.a[1] + fy - F.lo[1] + kG)) *
+                          (int64_t)F.px + (Bk.a[0] + fx - F.lo[0] + kG);
+  }
+  auto load_var = [&](int v, double (&R)[5][NL]) {
+    const int64_t vo = (int64_t)v * a.pvstride;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) R[0][j] = a.py[co[j] + vo];
+#pragma unroll
+    for (int m = 1; m < 5; ++m)
+#pragma unroll
+      for (int j = 0; j < NL; ++j)
+        R[m][j] = (double)static_cast<const TK*>(a.pk[m - 1])[co[j] + vo];
+  };
+  double R[5][NL], Rn[5][NL];
+  load_var(0, R);
   for (int v = 0; v < a.nvars; ++v) {
+    load_var(v + 1 < a.nvars ? v + 1 : v, Rn);   // in flight while v is interpolated
+    double Pv[ZE][5];
 #pragma unroll
     for (int m = 0; m < 5; ++m) {
-      const int64_t vb = P.base + v * a.pvstride;
-      for (int i = tid; i < cn[0] * cn[1] * cn[2]; i += 256) {
-        const int cx = i % cn[0], cy = (i / cn[0]) % cn[1], cz = i / (cn[0] * cn[1]);
-        const int c[3] = {cx, cy, cz};
-        int64_t o = vb;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          int I = C0[d] + c[d];
-          if (P.wrapN[d] > 0) I = ((I % P.wrapN[d]) + P.wrapN[d]) % P.wrapN[d];
-          int loc = I - P.lo[d];
-          loc = loc < -kG ? -kG : (loc > pn[d] + kG - 1 ? pn[d] + kG - 1 : loc);
-          o += (int64_t)(loc + kG) * pitch[d];
-        }
-        V[cz][cy][cx] = m == 0 ? a.py[o] : (double)static_cast<const TK*>(a.pk[m - 1])[o];
-      }
+      for (int j = 0; j < NL; ++j)
+        if (vi[j] >= 0) V[vi[j]] = R[m][j];
       __syncthreads();
-      // x: PX[cz][cy][fx]
-      for (int i = tid; i < cn[2] * cn[1] * Bk.n[0]; i += 256) {
-        const int fx = i % Bk.n[0], cy = (i / Bk.n[0]) % cn[1], cz = i / (Bk.n[0] * cn[1]);
-        const int q = Bk.a[0] + fx;
-        const int b = (q >> 1) - C0[0];
-        double px;
-        if (q & 1) {
-          px = W[0] * V[cz][cy][b - 2];
 #pragma unroll
-          for (int j = 1; j < 6; ++j) px = px + W[j] * V[cz][cy][b - 2 + j];
-        } else {
-          px = V[cz][cy][b];
-        }
-        PX[cz][cy][fx] = px;
-      }
+      for (int e = 0; e < XE; ++e)
+        if (xd[e] >= 0) PX[xd[e]] = brick_tap(V + xs[e], 1, xo[e]);
       __syncthreads();
-      // y: PY[cz][fy][fx]
-      for (int i = tid; i < cn[2] * Bk.n[1] * Bk.n[0]; i += 256) {
-        const int fx = i % Bk.n[0], fy = (i / Bk.n[0]) % Bk.n[1], cz = i / (Bk.n[0] * Bk.n[1]);
-        const int q = Bk.a[1] + fy;
-        const int b = (q >> 1) - C0[1];
-        double py;
-        if (q & 1) {
-          py = W[0] * PX[cz][b - 2][fx];
 #pragma unroll
-          for (int j = 1; j < 6; ++j) py = py + W[j] * PX[cz][b - 2 + j][fx];
-        } else {
-          py = PX[cz][b][fx];
-        }
-        PY[cz][fy][fx] = py;
-      }
+      for (int e = 0; e < YE; ++e)
+        if (yd[e] >= 0) PY[yd[e]] = brick_tap(PX + ys[e], kBrick, yo[e]);
       __syncthreads();
-      // z: this thread's points
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int i = tid + k * 256;
-        if (i < npts) {
-          const int fx = i % Bk.n[0], fy = (i / Bk.n[0]) % Bk.n[1], fz = i / (Bk.n[0] * Bk.n[1]);
-          const int q = Bk.a[2] + fz;
-          const int b = (q >> 1) - C0[2];
-          double pz;
-          if (q & 1) {
-            pz = W[0] * PY[b - 2][fy][fx];
-#pragma unroll
-            for (int j = 1; j < 6; ++j) pz = pz + W[j] * PY[b - 2 + j][fy][fx];
-          } else {
-            pz = PY[b][fy][fx];
-          }
-          Pv[k][m] = pz;
-        }
-      }
-      __syncthreads();
+      for (int e = 0; e < ZE; ++e) Pv[e][m] = brick_tap(PY + zs[e], kBrick * kBrick, zo[e]);
     }
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int i = tid + k * 256;
-      if (i < npts && ((a.b[blockIdx.x].mask[i >> 6] >> (i & 63)) & 1)) {
-        const int fx = i % Bk.n[0], fy = (i / Bk.n[0]) % Bk.n[1], fz = i / (Bk.n[0] * Bk.n[1]);
-        const int64_t dst = F.base +
-                            ((int64_t)(Bk.a[2] + fz - F.lo[2] + kG) * F.py + (Bk.a[1] + fy - F.lo[1] + kG)) *
-                                (int64_t)F.px + (Bk.a[0] + fx - F.lo[0] + kG) + v * a.ovstride;
-        for (int o = 0; o < a.nout; ++o) {
-          const double s = ((a.w[o][0] * Pv[k][1] + a.w[o][1] * Pv[k][2]) + a.w[o][2] * Pv[k][3]) +
-                           a.w[o][3] * Pv[k][4];
-          static_cast<TO*>(a.out[o])[dst] = (TO)(Pv[k][0] + a.H * s);
-        }
+    for (int e = 0; e < ZE; ++e) {
+      if (!zw[e]) continue;
+      const int64_t d = dst[e] + v * a.ovstride;
+      for (int o = 0; o < a.nout; ++o) {
+        const double s = ((a.w[o][0] * Pv[e][1] + a.w[o][1] * Pv[e][2]) + a.w[o][2] * Pv[e][3]) +
+                         a.w[o][3] * Pv[e][4];
+        static_cast<TO*>(a.out[o])[d] = (TO)(Pv[e][0] + a.H * s);
       }
     }
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+#pragma unroll
+      for (int j = 0; j < NL; ++j) R[m][j] = Rn[m][j];
   }
 }
 
@@ -718,7 +761,7 @@ hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStr
 
 hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, bool out_f32, hipStream_t s) {
   if (a.nbricks <= 0) return hipSuccess;
-  const dim3 g(a.nbricks), b(256);
+  const dim3 g((unsigned)((a.nbricks + 7) / 8 * 8)), b(256);   // whole XCD rounds; extra groups exit
   if (!k_f32 && !out_f32) hipLaunchKernelGGL((k_prolong_bricks<double, double>), g, b, 0, s, a);
   else if (k_f32 && out_f32) hipLaunchKernelGGL((k_prolong_bricks<float, float>), g, b, 0, s, a);
   else if (k_f32) hipLaunchKernelGGL((k_prolong_bricks<float, double>), g, b, 0, s, a);
