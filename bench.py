@@ -18,8 +18,10 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes ...] [--no-c
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,6 +32,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-point updates/s (subcycled RK4) batched/mixed vs plain FP64; % HBM peak"
 HBM_PEAK_GBS = 8000.0
+
+
+def measured_traffic():
+    """HBM bytes per stage-kernel launch (scaled FETCH_SIZE + WRITE_SIZE) from the
+    committed counter summary, or None unless it was taken on the current
+    kernel source."""
+    path = os.path.join(ROOT, "profiles", "wave_stage_n0128_fp64_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2503_09629_amd", "csrc", "kernels.hip")
+    try:
+        txt = open(path).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*(\S+)", txt)
+    h = re.search(r"kernel_source_sha256:\s*(\w+)", txt)
+    if not m or not h:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+        return None
+    return float(m.group(1))
 
 
 def log(msg):
@@ -296,6 +317,12 @@ def main():
                  "launches": n, "avg_launch_us": 1e3 * ms / n,
                  "alg_bytes_per_launch": nbytes / n}
             if label == "roofline":
+                if args.n0 == 128:
+                    t = measured_traffic()
+                    if t is not None:
+                        r["traffic"] = t
+                        r["traffic_unit"] = "HBM bytes per launch (rocprofv3 counters)"
+                        r["traffic_over_algorithmic"] = t / r["alg_bytes_per_launch"]
                 roof = r
             else:
                 res[m]["roofline"] = r
