@@ -289,7 +289,7 @@ def main():
                 tuned = json.loads(f.read().strip().splitlines()[-1])["modes"][m]
             for l in range(spec.nlevels):
                 ctx.set_tile_shape(l, tuned["tz_per_level"][l], tuned["grid_per_level"][l],
-                                   tuned["pz_per_level"][l], tuned["slots_per_level"][l])
+                                   tuned["depth_per_level"][l], tuned["slots_per_level"][l])
         elif m != "per_block" and not args.no_tune:
             ctx.autotune(3)
         shapes = [ctx.tile_shape(l) for l in range(spec.nlevels)]
@@ -300,7 +300,7 @@ def main():
         res[m] = {"updates_per_s": U * steps / T, "ms_per_step": 1e3 * T / steps,
                   "steps": steps, "tz_per_level": [sh["tz"] for sh in shapes],
                   "grid_per_level": [sh["grid"] for sh in shapes],
-                  "pz_per_level": [sh["pz"] for sh in shapes],
+                  "depth_per_level": [sh["depth"] for sh in shapes],
                   "slots_per_level": [sh["slots"] for sh in shapes]}
         log(f"{m}: {1e3 * T / steps:.2f} ms/step, {U * steps / T:.4g} updates/s")
         if m in ("batched", "mixed_batched"):

@@ -308,10 +308,10 @@ class Context:
     def tile_shape(self, level: int):
         out = (ctypes.c_int32 * 7)()
         self._check(self.L.sc_tile_shape(self.ctx, level, out))
-        return dict(zip(("tx", "ty", "tz", "grid", "tiles", "pz", "slots"), list(out)))
+        return dict(zip(("tx", "ty", "tz", "grid", "tiles", "depth", "slots"), list(out)))
 
-    def set_tile_shape(self, level: int, tz: int, grid: int = 0, pz: int = 1, slots: int = 2):
-        self._check(self.L.sc_set_tile_shape(self.ctx, level, tz, grid, pz, slots))
+    def set_tile_shape(self, level: int, tz: int, grid: int = 0, depth: int = 1, slots: int = 2):
+        self._check(self.L.sc_set_tile_shape(self.ctx, level, tz, grid, depth, slots))
 
     def profile_enable(self, on: bool = True):
         self._check(self.L.sc_profile_enable(self.ctx, int(bool(on))))

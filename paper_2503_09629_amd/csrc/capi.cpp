@@ -121,6 +121,11 @@ int tile_ty_cap(int nxm, int slots) {
   return std::max(t, 1);
 }
 
+// stencil kernel variants: (points per thread, planes of loads in flight)
+bool stage_variant_ok(int slots, int depth) {
+  return (slots == 2 && (depth == 1 || depth == 2)) || (slots == 1 && depth == 2);
+}
+
 bool tile_fits(int nx, int ny, int slots) {
   return nx >= 1 && ny >= 1 && nx <= kTileMaxX && nx * ny <= kStageThreads * slots &&
          (nx + 2 * kG) * (ny + 2 * kG) <= kWinCap &&
@@ -135,8 +140,11 @@ void tile_region(int box, const int64_t o[3], const int64_t n[3], const TileShap
   for (auto& x : sx) nxm = std::max(nxm, x.second);
   split_even(n[1], std::min(s.ty, tile_ty_cap(nxm, s.slots)), &sy);
   split_even(n[2], s.tz, &sz);
-  for (size_t iz = 0; iz < sz.size(); ++iz)
-    for (auto& y : sy)
+  // order: y rows of tiles, then z chunks, then x, so that a contiguous run of
+  // the table (one XCD's share) is a slab holding whole z stacks: the halo
+  // planes shared by neighbouring chunks are then read from one L2
+  for (auto& y : sy)
+    for (size_t iz = 0; iz < sz.size(); ++iz)
       for (auto& x : sx) {
         TileDev t;
         t.box = box;
@@ -630,7 +638,7 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
       if (rc) return rc;
       HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    HIPCHK(c, launch_stage(a, grid, c->mixed, L.shape.pz, L.shape.slots, c->stream));
+    HIPCHK(c, launch_stage(a, grid, c->mixed, L.shape.depth, L.shape.slots, c->stream));
     if (c->profiling) {
       HIPCHK(c, hipEventRecord(e1, c->stream));
       // algorithmic bytes per owned point and variable: the stencil operands
@@ -1405,19 +1413,19 @@ static void drop_graphs(sc_ctx* c) {
   }
 }
 
-int sc_set_tile_shape(sc_ctx* c, int32_t level, int32_t tz, int32_t grid, int32_t pz,
+int sc_set_tile_shape(sc_ctx* c, int32_t level, int32_t tz, int32_t grid, int32_t depth,
                       int32_t slots) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
   if (level < 0 || level >= (int)c->lev.size()) return fail(c, SC_E_ARG, "level out of range");
   if (tz < kTuneTzMin || tz > (1 << 20)) return fail(c, SC_E_ARG, "z-chunk out of range");
   if (grid < 0) return fail(c, SC_E_ARG, "grid must be >= 0");
-  if (pz != 1 && pz != 2) return fail(c, SC_E_ARG, "planes per step must be 1 or 2");
-  if (slots != 1 && slots != 2) return fail(c, SC_E_ARG, "points per thread must be 1 or 2");
+  if (!stage_variant_ok(slots, depth))
+    return fail(c, SC_E_ARG, "(points per thread, planes in flight) must be (2, 1), (2, 2) or (1, 2)");
   LevelDev& L = c->lev[level];
   TileShape sh = L.shape;
   sh.tz = tz;
-  sh.pz = pz;
+  sh.depth = depth;
   sh.slots = slots;
   std::vector<TileDev> tl;
   for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
@@ -1469,10 +1477,11 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
       if (tl.size() > L.tiles_capacity) continue;
       HIPCHK(c, upload(c, L.d_tiles, tl));
       L.tiles = tl;
-      for (int pz : {1, 2})
+      for (int depth : {1, 2})
       for (int g : {2 * ncu, 4 * ncu, 8 * ncu, 1 << 30}) {
+        if (!stage_variant_ok(slots, depth)) break;
         sh.grid = std::min<int>(g, (int)tl.size());
-        sh.pz = pz;
+        sh.depth = depth;
         L.shape = sh;
         // stage 2 reads y_n, k1 and the halo table, writes k2
         rc = enqueue_stage_launches(c, (int)l, 2, false, c->mixed ? (const void*)L.y32[L.cur]
@@ -1524,7 +1533,7 @@ int sc_tile_shape(const sc_ctx* c, int32_t level, int32_t out[7]) {
   out[2] = L.shape.tz;
   out[3] = L.shape.grid > 0 ? L.shape.grid : std::min<int>((int)L.tiles.size(), c->grid_cap);
   out[4] = (int32_t)L.tiles.size();
-  out[5] = L.shape.pz;
+  out[5] = L.shape.depth;
   out[6] = L.shape.slots;
   return SC_OK;
 }

@@ -164,9 +164,9 @@ struct PackArgs {
 };
 
 // launchers (kernels.hip); `f32` selects FP32 stencil operands / arrays
-// pz: z planes per barrier step (1 or 2); slots: owned points per thread (1 or 2),
+// depth: planes of loads in flight (1 or 2); slots: owned points per thread (1 or 2),
 // which the tiles must have been cut for
-hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int pz, int slots, hipStream_t s);
+hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int depth, int slots, hipStream_t s);
 hipError_t launch_sync(const SyncArgs& a, bool f32, hipStream_t s);
 // k_f32: parent slopes are FP32; out_f32: outputs are FP32
 hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s);
@@ -186,6 +186,7 @@ constexpr int kStageThreads = 256;
 constexpr int kStageSlotsMax = 2; // owned points per thread and plane of a stencil tile (1 or 2)
 constexpr int kRingSlots = 2;     // ring points per thread and plane
 constexpr int kWinCap = 1024;     // LDS window points per variable and plane: (nx+6)(ny+6)
+constexpr int kWinStride = kWinCap + 8;   // per-variable LDS stride: window plus a spare slot
 constexpr int kTileMaxX = 64;     // tile width (the Z4c kernels map one lane per x)
 
 }  // namespace sc

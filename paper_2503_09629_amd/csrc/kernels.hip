@@ -66,24 +66,32 @@ __device__ __forceinline__ TS stage_form(TS ra, TS rk, TS cdt, bool in) {
 
 // One RK4 stage of the scalar wave on one tile of nx x ny points in x-y (at
 // most S per thread, threads mapped row by row) and nz planes, marched in z
-// direction DZ (+1 upward, -1 downward), PZ planes per step.  The x-y planes
-// of stage values (tile plus the 3-point ring) are staged in LDS (double
-// buffered, row pitch nx + 6): the tile's own points come from the z column
-// each thread keeps in registers, only the ring is read from memory.  Every
-// load has a valid address (lanes without a point read a clamped one and
-// drop the value), so no load sits behind a branch: the loads for the next
-// step are all in flight during this step's arithmetic, and the stage value
-// Y = y_n + c dt k is formed once they have arrived.  One barrier per step.
+// direction DZ (+1 upward, -1 downward) one plane per step.  The x-y plane of
+// stage values (tile plus the 3-point ring) is staged in LDS (double
+// buffered, row pitch nx + 6): the tile's own points come from the 7-plane z
+// column each thread keeps in registers, only the ring is read from memory.
+// Every load has a valid address (lanes without a point read a clamped one
+// and drop the value), so no load sits behind a branch.  The loads of plane
+// z + D (ring) and z + D + 3 (column) are issued while plane z is computed,
+// D = DEPTH planes ahead (two register sets alternate when D = 2); the stage
+// value Y = y_n + c dt k is formed when a set is consumed.  One barrier per
+// plane.
 //   k_u  = Pi + Q u,   k_Pi = Lap u + Q Pi
 //   Lap  = ((d2_x + d2_y) + d2_z) / (12 h^2),  Q = sigma/(64 h) ((ko_x + ko_y) + ko_z)
 // Stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4) in FP64.
 // The z stencils take their taps in increasing z whatever the direction, so
 // both directions give the same bits.
-template <int STAGE, typename TS, int PZ, int S, int DZ>
+template <typename TS, int S, int RM>
+struct StageRaw {   // raw loads of one ring plane and one column plane
+  TS ra[2][RM], rk[2][RM];
+  TS ca[2][S], ck[2][S];
+};
+
+template <int STAGE, typename TS, int DEPTH, int S, bool WK>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T, const BoxDev& B,
                                            TS* lds) {
   constexpr int RM = kRingSlots;
-  constexpr int QN = 2 * kG + PZ;  // z column: planes z-3 .. z+PZ+2 along DZ
+  constexpr int QN = 2 * kG + 1;   // z column: planes z-3 .. z+3 along DZ
   constexpr int NT = kStageThreads;
   const TS clap = TS(a.clap), cko = TS(a.cko), cdt = TS(a.cdt);
   const char* yn = static_cast<const char*>(a.yn);
@@ -93,8 +101,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
   const int64_t ps = (int64_t)B.px * B.py;     // points per z plane
   // planes the tile reads and computes, and the first computed plane
   const int zlo = T.z0 - kG, zhi = T.z0 + T.nz + kG - 1;
-  const int z0 = DZ > 0 ? T.z0 : T.z0 + T.nz - 1;
+  const bool up = T.dir == 0;
+  const int DZ = up ? 1 : -1;
+  const int z0 = up ? T.z0 : T.z0 + T.nz - 1;
   auto clampz = [&](int z, int lo, int hi) { return z < lo ? lo : (z > hi ? hi : z); };
+  auto zin = [&](int z) { return (unsigned)z < (unsigned)B.nz; };
   // byte offset of plane z of variable v within the level arrays
   auto plane = [&](int z, int v) -> int64_t {
     return (int64_t)sizeof(TS) * (B.base + (int64_t)(z + kG) * ps + (int64_t)v * a.vstride);
@@ -126,177 +137,161 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
     rin[k] = (unsigned)x < (unsigned)B.nx && (unsigned)y < (unsigned)B.ny;
     rb[k] = (uint32_t)sizeof(TS) * (uint32_t)((y + kG) * B.px + (x + kG));
   }
-  TS q[2][S][QN];                   // stage values of the z column, in marching order
-  TS na[2][S][PZ], nk[2][S][PZ];    // raw loads of the next column planes
-  TS ra[PZ][2][RM], rk[PZ][2][RM];  // raw loads of the ring planes
-  // prologue: column planes z0 - 3 DZ .. z0 + (PZ+2) DZ, ring planes z0 .. z0 + (PZ-1) DZ
+  // raw loads of ring plane z0 + DZ j and column plane z0 + DZ (j + 3)
+  auto issue = [&](StageRaw<TS, S, RM>& R, int j) {
+    const int zr = clampz(z0 + DZ * j, T.z0, T.z0 + T.nz - 1);
+    const int zq = clampz(z0 + DZ * (j + kG), zlo, zhi);
+    const bool qin = zin(zq);
 #pragma unroll
-  for (int j = 0; j < QN; ++j) {
-    const int z = clampz(z0 + DZ * (j - kG), zlo, zhi);
-    const bool zin = (unsigned)z < (unsigned)B.nz;
+    for (int v = 0; v < 2; ++v) {
+      const int64_t pr = plane(zr, v);
+#pragma unroll
+      for (int k = 0; k < RM; ++k) {
+        R.ra[v][k] = load_at<TS>((rin[k] ? yn : yh) + pr, rb[k]);
+        R.rk[v][k] = STAGE > 1 ? load_at<TS>(kp + pr, rb[k]) : TS(0);
+      }
+      const int64_t pq = plane(zq, v);
+      const char* src = (qin ? yn : yh) + pq;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        R.ca[v][s] = load_at<TS>(src, cb[s]);
+        R.ck[v][s] = STAGE > 1 ? load_at<TS>(kp + pq, cb[s]) : TS(0);
+      }
+    }
+  };
+  TS q[2][S][QN];   // stage values of the z column, in marching order
+  // prologue: column planes z0 - 3 DZ .. z0 + 2 DZ into q[1..6]
+#pragma unroll
+  for (int j = 1; j < QN; ++j) {
+    const int z = clampz(z0 + DZ * (j - 1 - kG), zlo, zhi);
+    const bool in = zin(z);
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
       const int64_t pb = plane(z, v);
-      const char* src = (zin ? yn : yh) + pb;
+      const char* src = (in ? yn : yh) + pb;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const TS va = load_at<TS>(src, cb[s]);
         const TS vk = STAGE > 1 ? load_at<TS>(kp + pb, cb[s]) : TS(0);
-        q[v][s][j] = stage_form<STAGE, TS>(va, vk, cdt, zin);
+        q[v][s][j] = stage_form<STAGE, TS>(va, vk, cdt, in);
       }
     }
   }
+  StageRaw<TS, S, RM> R[DEPTH];
 #pragma unroll
-  for (int p = 0; p < PZ; ++p) {
-    const int z = clampz(z0 + DZ * p, T.z0, T.z0 + T.nz - 1);
+  for (int j = 0; j < DEPTH; ++j) issue(R[j], j);
+  // one plane: consume R (ring plane iz, column plane iz + 3), refill it
+  // with the planes DEPTH further on, compute plane iz
+  auto step = [&](int iz, StageRaw<TS, S, RM>& P, TS* L) {
+    const int z = z0 + DZ * iz;
+    const bool zc = zin(z0 + DZ * (iz + kG));
+#pragma unroll
+    for (int j = 0; j < QN - 1; ++j)
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) q[v][s][j] = q[v][s][j + 1];
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+        q[v][s][QN - 1] = stage_form<STAGE, TS>(P.ca[v][s], P.ck[v][s], cdt, zc);
+    const bool zr = zin(z);
+    // lanes without a point write the spare slot past the window: no branch
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
-      const int64_t pb = plane(z, v);
+      TS* Lv = L + v * kWinStride;
 #pragma unroll
-      for (int k = 0; k < RM; ++k) {
-        ra[p][v][k] = load_at<TS>((rin[k] ? yn : yh) + pb, rb[k]);
-        rk[p][v][k] = STAGE > 1 ? load_at<TS>(kp + pb, rb[k]) : TS(0);
-      }
-    }
-  }
-  for (int iz = 0, it = 0; iz < T.nz; iz += PZ, ++it) {
-    TS* L = lds + (it & 1) * (PZ * 2 * kWinCap);
+      for (int s = 0; s < S; ++s) Lv[act[s] ? li[s] : kWinCap] = q[v][s][kG];
 #pragma unroll
-    for (int p = 0; p < PZ; ++p) {
-      const int z = z0 + DZ * (iz + p);
-      const bool zin = (unsigned)z < (unsigned)B.nz;
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        TS* Lv = L + (p * 2 + v) * kWinCap;
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-          if (act[s]) Lv[li[s]] = q[v][s][kG + p];
-#pragma unroll
-        for (int k = 0; k < RM; ++k)
-          if (ract[k]) Lv[rli[k]] = stage_form<STAGE, TS>(ra[p][v][k], rk[p][v][k], cdt, rin[k] && zin);
-      }
+      for (int k = 0; k < RM; ++k)
+        Lv[ract[k] ? rli[k] : kWinCap] = stage_form<STAGE, TS>(P.ra[v][k], P.rk[v][k], cdt, rin[k] && zr);
     }
     __syncthreads();
-    // loads for the next step (ring planes z + PZ DZ .., column planes
-    // z + (PZ+3) DZ ..), in flight during this step's arithmetic
+    issue(P, iz + DEPTH);   // in flight during this plane's arithmetic
+    const TS* Lu = L;
+    const TS* Lp = L + kWinStride;
+    // column taps in increasing z: zt[m] is plane z + m - 3
+    auto zt = [&](int v, int s, int m) -> TS { return up ? q[v][s][m] : q[v][s][2 * kG - m]; };
+    // stage 4 reads the slopes and y_n at the point: issue those loads first
+    TS c1[2][S], c2[2][S], c3[2][S];
+    double c0[2][S];
+    const int64_t pe = B.base + (int64_t)(z + kG) * ps;   // element offset of the plane
+    if constexpr (STAGE == 4) {
+      const TS* k1 = static_cast<const TS*>(a.k1);
+      const TS* k2 = static_cast<const TS*>(a.k2);
+      const TS* k3 = static_cast<const TS*>(a.k3);
 #pragma unroll
-    for (int p = 0; p < PZ; ++p) {
-      const int zr = clampz(z0 + DZ * (iz + PZ + p), T.z0, T.z0 + T.nz - 1);
-      const int zq = clampz(z0 + DZ * (iz + PZ + p + kG), zlo, zhi);
-      const bool zqin = (unsigned)zq < (unsigned)B.nz;
-#pragma unroll
-      for (int v = 0; v < 2; ++v) {
-        const int64_t pr = plane(zr, v);
-#pragma unroll
-        for (int k = 0; k < RM; ++k) {
-          ra[p][v][k] = load_at<TS>((rin[k] ? yn : yh) + pr, rb[k]);
-          rk[p][v][k] = STAGE > 1 ? load_at<TS>(kp + pr, rb[k]) : TS(0);
-        }
-        const int64_t pq = plane(zq, v);
-        const char* src = (zqin ? yn : yh) + pq;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          na[v][s][p] = load_at<TS>(src, cb[s]);
-          nk[v][s][p] = STAGE > 1 ? load_at<TS>(kp + pq, cb[s]) : TS(0);
-        }
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < PZ; ++p) {
-      if (iz + p >= T.nz) break;
-      const int z = z0 + DZ * (iz + p);
-      const TS* Lu = L + (p * 2) * kWinCap;
-      const TS* Lp = L + (p * 2 + 1) * kWinCap;
-      // column taps in increasing z: zt[m] is plane z + m - 3
-      auto zt = [&](int v, int s, int m) -> TS {
-        return DZ > 0 ? q[v][s][p + m] : q[v][s][p + 2 * kG - m];
-      };
-      // stage 4 reads the slopes and y_n at the point: issue those loads first
-      TS c1[2][S], c2[2][S], c3[2][S];
-      double c0[2][S];
-      const int64_t pe = B.base + (int64_t)(z + kG) * ps;   // element offset of the plane
-      if constexpr (STAGE == 4) {
-        const TS* k1 = static_cast<const TS*>(a.k1);
-        const TS* k2 = static_cast<const TS*>(a.k2);
-        const TS* k3 = static_cast<const TS*>(a.k3);
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-#pragma unroll
-          for (int v = 0; v < 2; ++v) {
-            const int64_t o = pe + cb[s] / (uint32_t)sizeof(TS) + v * a.vstride;
-            c1[v][s] = k1[o];
-            c2[v][s] = k2[o];
-            c3[v][s] = k3[o];
-            c0[v][s] = a.yn64[o];
-          }
-      }
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        if (!act[s]) continue;
-        const int c = li[s];
-        const TS cu = q[0][s][kG + p], cp = q[1][s][kG + p];
-        const TS lapx = d2<TS>(Lu[c - 2], Lu[c - 1], cu, Lu[c + 1], Lu[c + 2]);
-        const TS lapy = d2<TS>(Lu[c - 2 * W], Lu[c - W], cu, Lu[c + W], Lu[c + 2 * W]);
-        const TS lapz = d2<TS>(zt(0, s, 1), zt(0, s, 2), cu, zt(0, s, 4), zt(0, s, 5));
-        const TS lap = ((lapx + lapy) + lapz) * clap;
-        TS Q[2];
+      for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
-          const TS* Lv = v == 0 ? Lu : Lp;
-          const TS cc = q[v][s][kG + p];
-          const TS kx = ko7<TS>(Lv[c - 3], Lv[c - 2], Lv[c - 1], cc, Lv[c + 1], Lv[c + 2], Lv[c + 3]);
-          const TS ky = ko7<TS>(Lv[c - 3 * W], Lv[c - 2 * W], Lv[c - W], cc, Lv[c + W],
-                                Lv[c + 2 * W], Lv[c + 3 * W]);
-          const TS kz = ko7<TS>(zt(v, s, 0), zt(v, s, 1), zt(v, s, 2), cc, zt(v, s, 4),
-                                zt(v, s, 5), zt(v, s, 6));
-          Q[v] = cko * ((kx + ky) + kz);
+          const int64_t o = pe + cb[s] / (uint32_t)sizeof(TS) + v * a.vstride;
+          c1[v][s] = k1[o];
+          c2[v][s] = k2[o];
+          c3[v][s] = k3[o];
+          c0[v][s] = a.yn64[o];
         }
-        const TS kv[2] = {cp + Q[0], lap + Q[1]};
-        const int64_t o = pe + cb[s] / (uint32_t)sizeof(TS);
-        if (a.write_k) {
-          TS* ko = static_cast<TS*>(a.kout);
-          ko[o] = kv[0];
-          ko[o + a.vstride] = kv[1];
-        }
-        if constexpr (STAGE == 4) {
+    }
+    // lanes without a point compute and store the tile's first point again
+    // (same inputs, same bits), so the stores need no branch either
 #pragma unroll
-          for (int v = 0; v < 2; ++v) {
-            const int64_t ov = o + v * a.vstride;
-            const double sm = (((double)c1[v][s] + 2.0 * (double)c2[v][s]) + 2.0 * (double)c3[v][s]) +
-                              (double)kv[v];
-            const double yv = c0[v][s] + a.dt6 * sm;
-            a.ynew[ov] = yv;
-            if constexpr (sizeof(TS) == 4) a.ynew32[ov] = (float)yv;
-          }
+    for (int s = 0; s < S; ++s) {
+      const int c = li[s];
+      const TS cu = q[0][s][kG], cp = q[1][s][kG];
+      const TS lapx = d2<TS>(Lu[c - 2], Lu[c - 1], cu, Lu[c + 1], Lu[c + 2]);
+      const TS lapy = d2<TS>(Lu[c - 2 * W], Lu[c - W], cu, Lu[c + W], Lu[c + 2 * W]);
+      const TS lapz = d2<TS>(zt(0, s, 1), zt(0, s, 2), cu, zt(0, s, 4), zt(0, s, 5));
+      const TS lap = ((lapx + lapy) + lapz) * clap;
+      TS Q[2];
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const TS* Lv = v == 0 ? Lu : Lp;
+        const TS cc = q[v][s][kG];
+        const TS kx = ko7<TS>(Lv[c - 3], Lv[c - 2], Lv[c - 1], cc, Lv[c + 1], Lv[c + 2], Lv[c + 3]);
+        const TS ky = ko7<TS>(Lv[c - 3 * W], Lv[c - 2 * W], Lv[c - W], cc, Lv[c + W],
+                              Lv[c + 2 * W], Lv[c + 3 * W]);
+        const TS kz = ko7<TS>(zt(v, s, 0), zt(v, s, 1), zt(v, s, 2), cc, zt(v, s, 4),
+                              zt(v, s, 5), zt(v, s, 6));
+        Q[v] = cko * ((kx + ky) + kz);
+      }
+      const TS kv[2] = {cp + Q[0], lap + Q[1]};
+      const int64_t o = pe + cb[s] / (uint32_t)sizeof(TS);
+      if constexpr (WK) {
+        TS* ko = static_cast<TS*>(a.kout);
+        ko[o] = kv[0];
+        ko[o + a.vstride] = kv[1];
+      }
+      if constexpr (STAGE == 4) {
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const int64_t ov = o + v * a.vstride;
+          const double sm = (((double)c1[v][s] + 2.0 * (double)c2[v][s]) + 2.0 * (double)c3[v][s]) +
+                            (double)kv[v];
+          const double yv = c0[v][s] + a.dt6 * sm;
+          a.ynew[ov] = yv;
+          if constexpr (sizeof(TS) == 4) a.ynew32[ov] = (float)yv;
         }
       }
     }
-    // advance the z column by PZ planes
+  };
+  // DEPTH planes per trip, each with its own register set (static names);
+  // the last partial trip is guarded
+  int iz = 0;
+  for (; iz + DEPTH <= T.nz; iz += DEPTH) {
 #pragma unroll
-    for (int j = 0; j < QN - PZ; ++j)
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) q[v][s][j] = q[v][s][j + PZ];
-#pragma unroll
-    for (int p = 0; p < PZ; ++p) {
-      const int zq = z0 + DZ * (iz + PZ + p + kG);
-      const bool zqin = (unsigned)zq < (unsigned)B.nz;
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-#pragma unroll
-        for (int v = 0; v < 2; ++v)
-          q[v][s][QN - PZ + p] = stage_form<STAGE, TS>(na[v][s][p], nk[v][s][p], cdt, zqin);
-    }
+    for (int j = 0; j < DEPTH; ++j) step(iz + j, R[j], lds + ((iz + j) & 1) * 2 * kWinStride);
   }
+#pragma unroll
+  for (int j = 0; j < DEPTH - 1; ++j)
+    if (iz + j < T.nz) step(iz + j, R[j], lds + ((iz + j) & 1) * 2 * kWinStride);
   __syncthreads();
 }
 
 // Persistent stage kernel: workgroups stride over the tile list; a tile's
 // dir field picks its z marching direction.
-template <int STAGE, typename TS, int PZ, int S>
+template <int STAGE, typename TS, int DEPTH, int S, bool WK>
 __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
-  __shared__ TS lds[2 * PZ * 2 * kWinCap];
+  __shared__ TS lds[2 * 2 * kWinStride];
   // consecutive workgroups land on different XCDs (round robin over 8); give
   // each XCD a contiguous run of tiles so neighbouring tiles share its L2
   const int g = (gridDim.x % 8 == 0)
@@ -305,8 +300,7 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
   for (int t = g; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
-    if (T.dir) stage_tile<STAGE, TS, PZ, S, -1>(a, T, B, lds);
-    else stage_tile<STAGE, TS, PZ, S, 1>(a, T, B, lds);
+    stage_tile<STAGE, TS, DEPTH, S, WK>(a, T, B, lds);
   }
 }
 
@@ -710,35 +704,38 @@ __global__ __launch_bounds__(256) void k_to_f32(const double* src, float* dst, i
 
 inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-template <typename TS, int PZ, int S>
+template <typename TS, int DEPTH, int S>
 void stage_dispatch(const StageArgs& a, dim3 g, hipStream_t s) {
   const dim3 b(kStageThreads);
   switch (a.stage) {
-    case 1: hipLaunchKernelGGL((k_wave_stage<1, TS, PZ, S>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_wave_stage<2, TS, PZ, S>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_wave_stage<3, TS, PZ, S>), g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_wave_stage<4, TS, PZ, S>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_wave_stage<1, TS, DEPTH, S, true>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_wave_stage<2, TS, DEPTH, S, true>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_wave_stage<3, TS, DEPTH, S, true>), g, b, 0, s, a); break;
+    default:
+      if (a.write_k) hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, false>), g, b, 0, s, a);
+      break;
   }
 }
 
+// (points per thread, planes in flight): (2, 1), (2, 2), (1, 2)
 template <typename TS>
-void stage_variant(const StageArgs& a, dim3 g, int pz, int slots, hipStream_t s) {
+void stage_variant(const StageArgs& a, dim3 g, int depth, int slots, hipStream_t s) {
   if (slots == 1) {
-    if (pz == 2) stage_dispatch<TS, 2, 1>(a, g, s);
-    else stage_dispatch<TS, 1, 1>(a, g, s);
+    stage_dispatch<TS, 2, 1>(a, g, s);
   } else {
-    if (pz == 2) stage_dispatch<TS, 2, 2>(a, g, s);
+    if (depth == 2) stage_dispatch<TS, 2, 2>(a, g, s);
     else stage_dispatch<TS, 1, 2>(a, g, s);
   }
 }
 
 }  // namespace
 
-hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int pz, int slots, hipStream_t s) {
+hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int depth, int slots, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g(grid > 0 ? grid : a.ntiles);
-  if (f32) stage_variant<float>(a, g, pz, slots, s);
-  else stage_variant<double>(a, g, pz, slots, s);
+  if (f32) stage_variant<float>(a, g, depth, slots, s);
+  else stage_variant<double>(a, g, depth, slots, s);
   return hipGetLastError();
 }
 

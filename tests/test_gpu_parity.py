@@ -207,11 +207,12 @@ def test_autotuned_tiles_bitwise_equal():
 @pytest.mark.parametrize("mixed", [False, True])
 def test_pinned_tile_shapes_bitwise_equal(mixed):
     """Every stencil-kernel variant (one or two points per thread, one or two
-    planes per barrier, z-chunks that split boxes into upward and downward
-    marching pieces, ragged last chunks) gives the same bits."""
+    planes of loads in flight, z-chunks that split boxes into upward and
+    downward marching pieces, odd and ragged chunks) gives the same bits."""
     spec = config_c3(64, nlev=4)
     prec = sc.SC_MIXED if mixed else sc.SC_FP64
-    shapes = [None, (4, 0, 1, 1), (7, 0, 2, 2), (12, 64, 1, 2), (1 << 20, 0, 2, 1), (5, 16, 2, 1)]
+    shapes = [None, (4, 0, 2, 1), (7, 0, 2, 2), (12, 64, 1, 2), (1 << 20, 0, 2, 1), (5, 16, 2, 1),
+              (9, 0, 2, 2), (6, 24, 1, 2)]
     outs = []
     for sh in shapes:
         ctx = _gpu(spec, precision=prec)
@@ -222,7 +223,7 @@ def test_pinned_tile_shapes_bitwise_equal(mixed):
             for l in range(spec.nlevels):
                 ctx.set_tile_shape(l, *sh)
                 got = ctx.tile_shape(l)
-                assert (got["tz"], got["pz"], got["slots"]) == (sh[0], sh[2], sh[3])
+                assert (got["tz"], got["depth"], got["slots"]) == (sh[0], sh[2], sh[3])
         ctx.advance(2)
         outs.append([ctx.read_back(0, l, v) for l in range(spec.nlevels) for v in range(2)])
         ctx.close()
@@ -237,11 +238,12 @@ def test_set_tile_shape_rejects_bad_arguments():
     for l in range(spec.nlevels):
         for v, f in enumerate(pulses_on_spec(spec, l)):
             ctx.set_initial_data(0, l, v, f)
-    for args in ((0, 3, 0, 1, 2), (0, 8, -1, 1, 2), (0, 8, 0, 3, 2), (0, 8, 0, 1, 4), (5, 8, 0, 1, 2)):
+    for args in ((0, 3, 0, 1, 2), (0, 8, -1, 1, 2), (0, 8, 0, 3, 2), (0, 8, 0, 1, 4), (5, 8, 0, 1, 2),
+                 (0, 8, 0, 1, 1), (0, 8, 0, 4, 2), (0, 8, 0, 4, 1)):
         with pytest.raises(sc.ScError):
             ctx.set_tile_shape(*args)
-    ctx.set_tile_shape(0, 8, 0, 1, 1)
-    assert ctx.tile_shape(0)["slots"] == 1
+    ctx.set_tile_shape(0, 8, 0, 2, 1)
+    assert ctx.tile_shape(0)["slots"] == 1 and ctx.tile_shape(0)["depth"] == 2
 
 
 def test_k4_not_kept_on_finest_level():
