@@ -680,15 +680,17 @@ Z4cArgs z4c_args(sc_ctx* c, int l) {
   return a;
 }
 
-// Z4c stage: materialise Y_s = y_n + c_s dt k_{s-1} (s >= 2), then the RHS.
+// Z4c stage: write Y_s = y_n + c_s dt k_{s-1} (y_n for s = 1) on the owned
+// points into the stage's halo table, whose halo the fills have written, then
+// the RHS reads the table alone.
 int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void* kprev,
                          const void* yh) {
   LevelDev& L = c->lev[l];
   static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
   Z4cArgs a = z4c_args(c, l);
   a.stage = stage;
-  a.Y = stage == 1 ? L.y[L.cur] : L.Ys;
-  a.Yh = static_cast<const double*>(yh);
+  double* table = static_cast<double*>(const_cast<void*>(yh));
+  a.Y = table;
   a.yn = L.y[L.cur];
   a.k1 = static_cast<const double*>(L.k[0]);
   a.k2 = static_cast<const double*>(L.k[1]);
@@ -699,17 +701,15 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
   cb.nvars = c->nvars;
   cb.boxes = L.d_boxes;
   cb.yn = L.y[L.cur];
-  cb.kprev = static_cast<const double*>(kprev);
-  cb.Y = L.Ys;
+  cb.kprev = stage >= 2 ? static_cast<const double*>(kprev) : nullptr;
+  cb.Y = table;
   cb.vstride = L.total;
   cb.cdt = cnext[stage] * L.dt;
   auto run = [&](const TileDev* tiles, int ntiles, int grid) -> int {
-    if (stage >= 2) {
-      cb.tiles = tiles;
-      cb.ntiles = ntiles;
-      HIPCHK(c, launch_z4c_combine(cb, grid, c->stream));
-      ++c->launches;
-    }
+    cb.tiles = tiles;
+    cb.ntiles = ntiles;
+    HIPCHK(c, launch_z4c_combine(cb, grid, c->stream));
+    ++c->launches;
     a.tiles = tiles;
     a.ntiles = ntiles;
     HIPCHK(c, launch_z4c_stage(a, grid, c->stream));
@@ -720,14 +720,12 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
   // per block: every block's stage vector must be complete before any block's
   // stencil reads its neighbours, so all combines go first
   const int nblk = (int)L.btile_start.size() - 1;
-  if (stage >= 2) {
-    for (int b = 0; b < nblk; ++b) {
-      const int n = L.btile_start[b + 1] - L.btile_start[b];
-      cb.tiles = L.d_btiles + L.btile_start[b];
-      cb.ntiles = n;
-      HIPCHK(c, launch_z4c_combine(cb, n, c->stream));
-      ++c->launches;
-    }
+  for (int b = 0; b < nblk; ++b) {
+    const int n = L.btile_start[b + 1] - L.btile_start[b];
+    cb.tiles = L.d_btiles + L.btile_start[b];
+    cb.ntiles = n;
+    HIPCHK(c, launch_z4c_combine(cb, n, c->stream));
+    ++c->launches;
   }
   for (int b = 0; b < nblk; ++b) {
     const int n = L.btile_start[b + 1] - L.btile_start[b];
@@ -1183,8 +1181,7 @@ int sc_hamiltonian(sc_ctx* c, int32_t member, int32_t level, double* host, int64
   rc = sc_fill_ghosts(c, level, SC_FILL_END, 1);
   if (rc) return rc;
   Z4cArgs a = z4c_args(c, level);
-  a.Y = L.y[L.cur];
-  a.Yh = L.y[L.cur];
+  a.Y = L.y[L.cur];   // the END fill wrote the state's own halo
   a.ham = L.Ys;   // scratch: one variable's worth of the stage-vector array
   a.tiles = L.d_tiles;
   a.ntiles = (int32_t)L.tiles.size();

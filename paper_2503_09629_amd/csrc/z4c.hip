@@ -12,10 +12,10 @@
 // D^i D_i alpha = W^2 gt^ij D_i D_j alpha, R = W^2 gt^ij R_ij,
 // [X]^TF = X - gt gt^kl X_kl / 3.
 //
-// The stage vector on owned points is materialised once per stage
-// (k_z4c_combine), because every one of its 22 components is read about 40
-// times by the stencils; halo points come from the halo tables as in the wave
-// kernel.  One thread computes one point: the 66 first derivatives live in
+// The stage vector is materialised once per stage (k_z4c_combine writes the
+// owned points into the stage's halo table, whose halo the ghost fills have
+// written), because every one of its 22 components is read about 40 times by
+// the stencils; a stencil tap is then one load from one padded array.  One thread computes one point: the 66 first derivatives live in
 // registers and every second derivative is contracted as soon as it is
 // formed.
 #include "device.hpp"
@@ -38,11 +38,10 @@ struct Pt {
   int x, y, z;
   int64_t o;
   int64_t px, pxy;
+  // the stage vector on the whole padded box (owned points and halo) is one
+  // array, so a tap is one unconditional load
   __device__ double at(int v, int dx, int dy, int dz) const {
-    const int64_t off = o + dx + dy * px + dz * pxy + v * a->vstride;
-    const bool in = (unsigned)(x + dx) < (unsigned)B.nx && (unsigned)(y + dy) < (unsigned)B.ny &&
-                    (unsigned)(z + dz) < (unsigned)B.nz;
-    return in ? a->Y[off] : a->Yh[off];
+    return a->Y[o + dx + dy * px + dz * pxy + v * a->vstride];
   }
   __device__ double tap(int v, int d, int j) const {
     return at(v, d == 0 ? j : 0, d == 1 ? j : 0, d == 2 ? j : 0);
@@ -399,7 +398,8 @@ __global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
   }
 }
 
-// Y = y_n + cdt k_{s-1} on the owned points of the tiles (all variables).
+// Y = y_n + cdt k_{s-1} on the owned points of the tiles (all variables);
+// Y = y_n when kprev is null (stage 1).
 __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
   const int tx = threadIdx.x % kTileMaxX, ty = threadIdx.x / kTileMaxX;
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
                                        (int64_t)B.px + (T.x0 + tx + kG);
         for (int i = 0; i < a.nvars; ++i) {
           const int64_t oi = o + i * a.vstride;
-          a.Y[oi] = a.yn[oi] + a.cdt * a.kprev[oi];
+          a.Y[oi] = a.kprev ? a.yn[oi] + a.cdt * a.kprev[oi] : a.yn[oi];
         }
       }
     }

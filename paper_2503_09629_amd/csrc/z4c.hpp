@@ -12,8 +12,7 @@ struct Z4cArgs {
   int32_t ntiles;
   int32_t stage;
   const BoxDev* boxes;
-  const double* Y;    // stage vector on owned points
-  const double* Yh;   // halo table (stage ghosts), or the state itself
+  const double* Y;    // stage vector on the padded boxes (owned points and halo)
   const double* yn;   // y_n (stage 4)
   const double* k1;
   const double* k2;
