@@ -191,12 +191,18 @@ def precision_report(args):
         spec = config_c3(n0)
         nsteps = int(round(0.125 / (0.25 * 2.0 / n0)))
         out = {}
+        log(f"precision report: N0={n0}, {spec.total_points()} points, {nsteps} coarse steps")
+        data = [pulses_on_spec(spec, l) for l in range(spec.nlevels)]
         for prec in (sc.SC_FP64, sc.SC_MIXED):
-            ctx = make_context(sc, spec, sc.SC_EXEC_GRAPH, [pulses_on_spec(spec, l) for l in
-                                                            range(spec.nlevels)], prec)
-            ctx.advance(nsteps)
+            ctx = make_context(sc, spec, sc.SC_EXEC_GRAPH, data, prec)
+            for i in range(nsteps):
+                ctx.advance(1)
+                if (i + 1) % 16 == 0 or i + 1 == nsteps:
+                    ctx.synchronize()
+                    log(f"  {'mixed' if prec == sc.SC_MIXED else 'fp64'}: {i + 1}/{nsteps} coarse steps")
             out[prec] = [ctx.read_back(0, l, 0) for l in range(spec.nlevels)]
             ctx.close()
+        del data
         res[n0] = out
         log(f"precision report: N0={n0} done")
     levels = []
