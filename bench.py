@@ -127,7 +127,9 @@ def z4c_run(args):
     spec = config_c5(96)
     U = spec.updates_per_coarse_step()
     log(f"workload {spec.name}: {spec.total_points()} points, {U} updates per coarse step")
-    ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=sc.SC_EXEC_GRAPH)
+    mixed = args.z4c_precision == "mixed"
+    ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=sc.SC_EXEC_GRAPH,
+                     precision=sc.SC_MIXED if mixed else sc.SC_FP64)
     ctx.build_spec(spec)
     ctx.bind()
     for l in range(spec.nlevels):
@@ -176,9 +178,11 @@ def z4c_run(args):
     finite = ctx.check_finite() == sc.SC_OK
     return {"metric": "Z4c grid-point updates/s (subcycled RK4, 22 variables)",
             "value": U * steps / T, "unit": "grid-point updates/s", "n_gpus": 1,
-            "steps": steps, "ms_per_step": 1e3 * T / steps, "dtype": "f64",
+            "steps": steps, "ms_per_step": 1e3 * T / steps,
+            "dtype": "f32 RHS, f64 state" if mixed else "f64",
             "config": {"workload": "Z4c Brill-Lindquist punctures m=0.5 at x=+-3, 7 levels of "
-                                   "96^3, [-128,128]^3, graph mode"},
+                                   "96^3, [-128,128]^3, graph mode"
+                                   + (", FP32 right-hand side" if mixed else "")},
             "hamiltonian_L2": [{"t": t, "H": h} for t, h in hist], "finite": finite}
 
 
@@ -252,6 +256,7 @@ def main():
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--workload", default="wave", choices=("wave", "z4c", "precision"))
     ap.add_argument("--z4c-steps", type=int, default=16)
+    ap.add_argument("--z4c-precision", default="fp64", choices=("fp64", "mixed"))
     ap.add_argument("--report-n0", type=int, nargs="+", default=[64, 128, 256])
     args = ap.parse_args()
     if args.gpus != 1:

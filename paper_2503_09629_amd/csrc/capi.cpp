@@ -689,30 +689,31 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
   static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
   Z4cArgs a = z4c_args(c, l);
   a.stage = stage;
-  double* table = static_cast<double*>(const_cast<void*>(yh));
+  void* table = const_cast<void*>(yh);
   a.Y = table;
   a.yn = L.y[L.cur];
-  a.k1 = static_cast<const double*>(L.k[0]);
-  a.k2 = static_cast<const double*>(L.k[1]);
-  a.k3 = static_cast<const double*>(L.k[2]);
-  a.kout = static_cast<double*>(L.k[stage - 1]);
+  a.k1 = L.k[0];
+  a.k2 = L.k[1];
+  a.k3 = L.k[2];
+  a.kout = L.k[stage - 1];
   a.ynew = L.y[1 - L.cur];
+  a.ynew32 = c->mixed ? L.y32[1 - L.cur] : nullptr;
   Z4cCombineArgs cb{};
   cb.nvars = c->nvars;
   cb.boxes = L.d_boxes;
-  cb.yn = L.y[L.cur];
-  cb.kprev = stage >= 2 ? static_cast<const double*>(kprev) : nullptr;
+  cb.yn = c->mixed ? static_cast<const void*>(L.y32[L.cur]) : L.y[L.cur];
+  cb.kprev = stage >= 2 ? kprev : nullptr;
   cb.Y = table;
   cb.vstride = L.total;
   cb.cdt = cnext[stage] * L.dt;
   auto run = [&](const TileDev* tiles, int ntiles, int grid) -> int {
     cb.tiles = tiles;
     cb.ntiles = ntiles;
-    HIPCHK(c, launch_z4c_combine(cb, grid, c->stream));
+    HIPCHK(c, launch_z4c_combine(cb, grid, c->mixed, c->stream));
     ++c->launches;
     a.tiles = tiles;
     a.ntiles = ntiles;
-    HIPCHK(c, launch_z4c_stage(a, grid, c->stream));
+    HIPCHK(c, launch_z4c_stage(a, grid, c->mixed, c->stream));
     ++c->launches;
     return SC_OK;
   };
@@ -724,14 +725,14 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
     const int n = L.btile_start[b + 1] - L.btile_start[b];
     cb.tiles = L.d_btiles + L.btile_start[b];
     cb.ntiles = n;
-    HIPCHK(c, launch_z4c_combine(cb, n, c->stream));
+    HIPCHK(c, launch_z4c_combine(cb, n, c->mixed, c->stream));
     ++c->launches;
   }
   for (int b = 0; b < nblk; ++b) {
     const int n = L.btile_start[b + 1] - L.btile_start[b];
     a.tiles = L.d_btiles + L.btile_start[b];
     a.ntiles = n;
-    HIPCHK(c, launch_z4c_stage(a, n, c->stream));
+    HIPCHK(c, launch_z4c_stage(a, n, c->mixed, c->stream));
     ++c->launches;
   }
   return SC_OK;
@@ -939,7 +940,7 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
     g_create_error = "abi_version mismatch";
     return SC_E_ARG;
   }
-  const bool rhs_ok = cfg->rhs == SC_RHS_WAVE || (cfg->rhs == SC_RHS_Z4C && cfg->precision == SC_FP64);
+  const bool rhs_ok = cfg->rhs == SC_RHS_WAVE || cfg->rhs == SC_RHS_Z4C;
   if (!rhs_ok || cfg->nghost != 3 || !(cfg->z4c_eta_s > 0.0) || !(cfg->cfl > 0.0 && cfg->cfl <= 0.5) ||
       cfg->ko_sigma < 0.0 || (cfg->precision != SC_FP64 && cfg->precision != SC_MIXED) ||
       cfg->exec < 0 || cfg->exec > 2) {
@@ -1155,14 +1156,13 @@ int sc_set_phys_data(sc_ctx* c, int32_t member, int32_t level, int32_t var, cons
   const int64_t per = (int64_t)L.phys_q.size() / 3;
   if (n != per) return fail(c, SC_E_ARG, "n must equal sc_phys_count");
   if (per == 0) return SC_OK;
-  if (c->mixed) return fail(c, SC_E_STATE, "physical ghosts need FP64 halo tables");
   HIPCHK(c, hipMemcpyAsync(c->d_stage, host, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
   const int64_t* idx = L.d_phys + member * per;
   for (int i = 0; i < L.nyh; ++i)
-    HIPCHK(c, launch_scatter(idx, n, c->d_stage, static_cast<double*>(L.Yh[i]) + var * L.total,
+    HIPCHK(c, launch_scatter(idx, n, c->d_stage, elem(L.Yh[i], var * L.total, c->esz), c->mixed,
                              c->stream));
   for (int i = 0; i < 2; ++i)
-    HIPCHK(c, launch_scatter(idx, n, c->d_stage, L.y[i] + var * L.total, c->stream));
+    HIPCHK(c, launch_scatter(idx, n, c->d_stage, L.y[i] + var * L.total, false, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return SC_OK;
 }
@@ -1185,7 +1185,7 @@ int sc_hamiltonian(sc_ctx* c, int32_t member, int32_t level, double* host, int64
   a.ham = L.Ys;   // scratch: one variable's worth of the stage-vector array
   a.tiles = L.d_tiles;
   a.ntiles = (int32_t)L.tiles.size();
-  HIPCHK(c, launch_z4c_stage(a, std::min<int>(a.ntiles, c->grid_cap), c->stream));
+  HIPCHK(c, launch_z4c_stage(a, std::min<int>(a.ntiles, c->grid_cap), false, c->stream));
   PackArgs pa = member_pack(c, member, level, L.Ys);
   HIPCHK(c, launch_pack(pa, false, false, c->stream));
   HIPCHK(c, hipMemcpyAsync(host, c->d_stage, sizeof(double) * n, hipMemcpyDeviceToHost,

@@ -178,7 +178,7 @@ hipError_t launch_norms(const PackArgs& a, bool f32, double* partials, int npart
 hipError_t launch_gather(const int64_t* idx, int64_t n, const void* src, bool f32, double* dst,
                          hipStream_t s);
 hipError_t launch_fill(void* p, int64_t n, double v, bool f32, hipStream_t s);
-hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, double* dst,
+hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, void* dst, bool f32,
                           hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 

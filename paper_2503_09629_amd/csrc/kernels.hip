@@ -691,10 +691,11 @@ __global__ __launch_bounds__(256) void k_fill(T* p, int64_t n, T v) {
   if (i < n) p[i] = v;
 }
 
+template <typename T>
 __global__ __launch_bounds__(256) void k_scatter(const int64_t* idx, int64_t n, const double* src,
-                                                 double* dst) {
+                                                 T* dst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[idx[i]] = src[i];
+  if (i < n) dst[idx[i]] = (T)src[i];
 }
 
 __global__ __launch_bounds__(256) void k_to_f32(const double* src, float* dst, int64_t n) {
@@ -812,10 +813,15 @@ hipError_t launch_fill(void* p, int64_t n, double v, bool f32, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, double* dst,
+hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, void* dst, bool f32,
                           hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(256), 0, s, idx, n, src, dst);
+  if (f32)
+    hipLaunchKernelGGL(k_scatter<float>, dim3(blocks_for(n)), dim3(256), 0, s, idx, n, src,
+                       static_cast<float*>(dst));
+  else
+    hipLaunchKernelGGL(k_scatter<double>, dim3(blocks_for(n)), dim3(256), 0, s, idx, n, src,
+                       static_cast<double*>(dst));
   return hipGetLastError();
 }
 

@@ -12,6 +12,10 @@
 // D^i D_i alpha = W^2 gt^ij D_i D_j alpha, R = W^2 gt^ij R_ij,
 // [X]^TF = X - gt gt^kl X_kl / 3.
 //
+// The arithmetic type TS is double, or float for the FP32-RHS variant (FP32
+// stage vector and slopes, FP32 right-hand side; y_{n+1} is formed in FP64
+// from FP64 y_n and the stored slopes, with its FP32 shadow beside it).
+//
 // The stage vector is materialised once per stage (k_z4c_combine writes the
 // owned points into the stage's halo table, whose halo the ghost fills have
 // written), because every one of its 22 components is read about 40 times by
@@ -32,6 +36,7 @@ __device__ __forceinline__ int sym(int i, int j) {
   return a == 0 ? b : (a == 1 ? 2 + b : 5);
 }
 
+template <typename TS>
 struct Pt {
   const Z4cArgs* a;
   BoxDev B;
@@ -40,52 +45,53 @@ struct Pt {
   int64_t px, pxy;
   // the stage vector on the whole padded box (owned points and halo) is one
   // array, so a tap is one unconditional load
-  __device__ double at(int v, int dx, int dy, int dz) const {
-    return a->Y[o + dx + dy * px + dz * pxy + v * a->vstride];
+  __device__ TS at(int v, int dx, int dy, int dz) const {
+    return static_cast<const TS*>(a->Y)[o + dx + dy * px + dz * pxy + v * a->vstride];
   }
-  __device__ double tap(int v, int d, int j) const {
+  __device__ TS tap(int v, int d, int j) const {
     return at(v, d == 0 ? j : 0, d == 1 ? j : 0, d == 2 ? j : 0);
   }
-  __device__ double d1(int v, int d, double c1) const {
-    return (((tap(v, d, -2) - 8.0 * tap(v, d, -1)) + 8.0 * tap(v, d, 1)) - tap(v, d, 2)) * c1;
+  __device__ TS d1(int v, int d, TS c1) const {
+    return (((tap(v, d, -2) - TS(8.0) * tap(v, d, -1)) + TS(8.0) * tap(v, d, 1)) - tap(v, d, 2)) * c1;
   }
-  __device__ double d2(int v, int d, double c2) const {
-    return ((((-tap(v, d, -2) + 16.0 * tap(v, d, -1)) - 30.0 * tap(v, d, 0)) + 16.0 * tap(v, d, 1)) -
+  __device__ TS d2(int v, int d, TS c2) const {
+    return ((((-tap(v, d, -2) + TS(16.0) * tap(v, d, -1)) - TS(30.0) * tap(v, d, 0)) + TS(16.0) * tap(v, d, 1)) -
             tap(v, d, 2)) * c2;
   }
   // D1 along d of D1 along e
-  __device__ double dm(int v, int d, int e, double c1) const {
+  __device__ TS dm(int v, int d, int e, TS c1) const {
     auto inner = [&](int j) {
       const int sx = (d == 0 ? j : 0), sy = (d == 1 ? j : 0), sz = (d == 2 ? j : 0);
       auto t = [&](int i) {
         return at(v, sx + (e == 0 ? i : 0), sy + (e == 1 ? i : 0), sz + (e == 2 ? i : 0));
       };
-      return (((t(-2) - 8.0 * t(-1)) + 8.0 * t(1)) - t(2)) * c1;
+      return (((t(-2) - TS(8.0) * t(-1)) + TS(8.0) * t(1)) - t(2)) * c1;
     };
-    return (((inner(-2) - 8.0 * inner(-1)) + 8.0 * inner(1)) - inner(2)) * c1;
+    return (((inner(-2) - TS(8.0) * inner(-1)) + TS(8.0) * inner(1)) - inner(2)) * c1;
   }
-  __device__ double ko(int v, int d) const {
-    return (((((tap(v, d, -3) - 6.0 * tap(v, d, -2)) + 15.0 * tap(v, d, -1)) - 20.0 * tap(v, d, 0)) +
-             15.0 * tap(v, d, 1)) - 6.0 * tap(v, d, 2)) + tap(v, d, 3);
+  __device__ TS ko(int v, int d) const {
+    return (((((tap(v, d, -3) - TS(6.0) * tap(v, d, -2)) + TS(15.0) * tap(v, d, -1)) - TS(20.0) * tap(v, d, 0)) +
+             TS(15.0) * tap(v, d, 1)) - TS(6.0) * tap(v, d, 2)) + tap(v, d, 3);
   }
   // second derivative (k, l) with k <= l
-  __device__ double dd(int v, int k, int l, double c1, double c2) const {
+  __device__ TS dd(int v, int k, int l, TS c1, TS c2) const {
     return k == l ? d2(v, k, c2) : dm(v, k, l, c1);
   }
 };
 
-__device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ham_out) {
-  const double h = a.h;
-  const double c1 = 1.0 / (12.0 * h), c2 = 1.0 / (12.0 * h * h);
-  double v[NV], d[NV][3];
+template <typename TS>
+__device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ham_out) {
+  const TS h = TS(a.h);
+  const TS c1 = TS(1.0) / (TS(12.0) * h), c2 = TS(1.0) / (TS(12.0) * h * h);
+  TS v[NV], d[NV][3];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     v[i] = p.at(i, 0, 0, 0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) d[i][k] = p.d1(i, k, c1);
   }
-  const double W = v[VW], Kh = v[VKH], Th = v[VTH], alp = v[VALP];
-  double gt[3][3], At[3][3];
+  const TS W = v[VW], Kh = v[VKH], Th = v[VTH], alp = v[VALP];
+  TS gt[3][3], At[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -93,10 +99,10 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
       gt[i][j] = v[VG + sym(i, j)];
       At[i][j] = v[VA + sym(i, j)];
     }
-  const double det = gt[0][0] * (gt[1][1] * gt[2][2] - gt[1][2] * gt[2][1]) -
+  const TS det = gt[0][0] * (gt[1][1] * gt[2][2] - gt[1][2] * gt[2][1]) -
                      gt[0][1] * (gt[1][0] * gt[2][2] - gt[1][2] * gt[2][0]) +
                      gt[0][2] * (gt[1][0] * gt[2][1] - gt[1][1] * gt[2][0]);
-  double gu[3][3];
+  TS gu[3][3];
   gu[0][0] = (gt[1][1] * gt[2][2] - gt[1][2] * gt[2][1]) / det;
   gu[0][1] = (gt[0][2] * gt[2][1] - gt[0][1] * gt[2][2]) / det;
   gu[0][2] = (gt[0][1] * gt[1][2] - gt[0][2] * gt[1][1]) / det;
@@ -107,28 +113,28 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
   gu[2][0] = gu[0][2];
   gu[2][1] = gu[1][2];
   // Christoffel symbols of the conformal metric: Gl[k][i][j] = Gt_kij, G = Gt^k_ij
-  double Gl[3][3][3], G[3][3][3], Gd[3];
+  TS Gl[3][3][3], G[3][3][3], Gd[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j)
-        Gl[k][i][j] = 0.5 * ((d[VG + sym(j, k)][i] + d[VG + sym(i, k)][j]) - d[VG + sym(i, j)][k]);
+        Gl[k][i][j] = TS(0.5) * ((d[VG + sym(j, k)][i] + d[VG + sym(i, k)][j]) - d[VG + sym(i, j)][k]);
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        double s = 0.0;
+        TS s = TS(0.0);
 #pragma unroll
         for (int l = 0; l < 3; ++l) s += gu[k][l] * Gl[l][i][j];
         G[k][i][j] = s;
       }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    double s = 0.0;
+    TS s = TS(0.0);
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
@@ -136,10 +142,10 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
     Gd[i] = s;
   }
   // -1/2 gt^lm d_l d_m gt_ij, contracted as each second derivative is formed
-  double Rlap[6];
+  TS Rlap[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    double dd[3][3];
+    TS dd[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -147,14 +153,14 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
         dd[k][l] = p.dd(VG + c, k, l, c1, c2);
         dd[l][k] = dd[k][l];
       }
-    double s = 0.0;
+    TS s = TS(0.0);
 #pragma unroll
     for (int l = 0; l < 3; ++l)
 #pragma unroll
-      for (int m = 0; m < 3; ++m) s -= 0.5 * gu[l][m] * dd[l][m];
+      for (int m = 0; m < 3; ++m) s -= TS(0.5) * gu[l][m] * dd[l][m];
     Rlap[c] = s;
   }
-  double ddW[3][3], dda[3][3];
+  TS ddW[3][3], dda[3][3];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -165,10 +171,10 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
       dda[l][k] = dda[k][l];
     }
   // shift: gt^jk d_j d_k beta^i and d_j (d_k beta^k)
-  double lapb[3], gdivb[3] = {0.0, 0.0, 0.0};
+  TS lapb[3], gdivb[3] = {TS(0.0), TS(0.0), TS(0.0)};
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    double dd[3][3];
+    TS dd[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -176,7 +182,7 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
         dd[k][l] = p.dd(VB + i, k, l, c1, c2);
         dd[l][k] = dd[k][l];
       }
-    double s = 0.0;
+    TS s = TS(0.0);
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
@@ -186,13 +192,13 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
     for (int j = 0; j < 3; ++j) gdivb[j] += dd[j][i];
   }
   // Ricci tensor R_ij = R^W_ij + Rt_ij
-  const double dW[3] = {d[VW][0], d[VW][1], d[VW][2]};
-  double DDW[3][3], lapW = 0.0, dWsq = 0.0;
+  const TS dW[3] = {d[VW][0], d[VW][1], d[VW][2]};
+  TS DDW[3][3], lapW = TS(0.0), dWsq = TS(0.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      double s = ddW[i][j];
+      TS s = ddW[i][j];
 #pragma unroll
       for (int k = 0; k < 3; ++k) s -= G[k][i][j] * dW[k];
       DDW[i][j] = s;
@@ -205,43 +211,43 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
       dWsq += gu[i][j] * dW[i] * dW[j];
     }
   dWsq /= W * W;
-  double R[3][3];
+  TS R[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      double rt = Rlap[sym(i, j)];
+      TS rt = Rlap[sym(i, j)];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        rt += 0.5 * (gt[k][i] * d[VGAM + k][j] + gt[k][j] * d[VGAM + k][i]);
-        rt += Gd[k] * 0.5 * (Gl[i][j][k] + Gl[j][i][k]);
+        rt += TS(0.5) * (gt[k][i] * d[VGAM + k][j] + gt[k][j] * d[VGAM + k][i]);
+        rt += Gd[k] * TS(0.5) * (Gl[i][j][k] + Gl[j][i][k]);
       }
 #pragma unroll
       for (int l = 0; l < 3; ++l)
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-          double s = 0.0;
+          TS s = TS(0.0);
 #pragma unroll
           for (int k = 0; k < 3; ++k)
             s += (G[k][l][i] * Gl[j][k][m] + G[k][l][j] * Gl[i][k][m]) + G[k][i][m] * Gl[k][l][j];
           rt += gu[l][m] * s;
         }
-      const double rw = DDW[i][j] / W + gt[i][j] * lapW / W - 2.0 * gt[i][j] * dWsq;
+      const TS rw = DDW[i][j] / W + gt[i][j] * lapW / W - TS(2.0) * gt[i][j] * dWsq;
       R[i][j] = rw + rt;
     }
-  double Rs = 0.0;
+  TS Rs = TS(0.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) Rs += gu[i][j] * R[i][j];
   Rs *= W * W;
   // raised At
-  double Atu[3][3], Atm[3][3], AtA = 0.0;
+  TS Atu[3][3], Atm[3][3], AtA = TS(0.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      double s = 0.0, m = 0.0;
+      TS s = TS(0.0), m = TS(0.0);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         m += gu[i][k] * At[k][j];
@@ -255,30 +261,30 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) AtA += At[i][j] * Atu[i][j];
-  const double Kt = Kh + 2.0 * Th;
+  const TS Kt = Kh + TS(2.0) * Th;
   if (ham_out) {
-    *ham_out = Rs + (2.0 / 3.0) * Kt * Kt - AtA;
+    *ham_out = (double)(Rs + (TS(2.0) / TS(3.0)) * Kt * Kt - AtA);
     return;
   }
   // lapse: D_i D_j alpha with the physical Christoffels
-  const double da[3] = {d[VALP][0], d[VALP][1], d[VALP][2]};
-  double gudW[3];
+  const TS da[3] = {d[VALP][0], d[VALP][1], d[VALP][2]};
+  TS gudW[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    double s = 0.0;
+    TS s = TS(0.0);
 #pragma unroll
     for (int l = 0; l < 3; ++l) s += gu[k][l] * dW[l];
     gudW[k] = s;
   }
-  double DDa[3][3], lapa = 0.0;
+  TS DDa[3][3], lapa = TS(0.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      double s = dda[i][j];
+      TS s = dda[i][j];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const double Gp = G[k][i][j] - (((k == i ? dW[j] : 0.0) + (k == j ? dW[i] : 0.0)) -
+        const TS Gp = G[k][i][j] - (((k == i ? dW[j] : TS(0.0)) + (k == j ? dW[i] : TS(0.0))) -
                                          gt[i][j] * gudW[k]) / W;
         s -= Gp * da[k];
       }
@@ -289,18 +295,18 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
 #pragma unroll
     for (int j = 0; j < 3; ++j) lapa += gu[i][j] * DDa[i][j];
   lapa *= W * W;
-  const double beta[3] = {v[VB], v[VB + 1], v[VB + 2]};
-  double divb = 0.0;
+  const TS beta[3] = {v[VB], v[VB + 1], v[VB + 2]};
+  TS divb = TS(0.0);
 #pragma unroll
   for (int k = 0; k < 3; ++k) divb += d[VB + k][k];
   auto adv = [&](int i) {
-    double s = 0.0;
+    TS s = TS(0.0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) s += beta[k] * d[i][k];
     return s;
   };
-  rhs[VW] = adv(VW) + (1.0 / 3.0) * W * (alp * Kt - divb);
-  double trX = 0.0;
+  rhs[VW] = adv(VW) + (TS(1.0) / TS(3.0)) * W * (alp * Kt - divb);
+  TS trX = TS(0.0);
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -309,7 +315,7 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = i; j < 3; ++j) {
-      double lg = 0.0, la = 0.0, aa = 0.0;
+      TS lg = TS(0.0), la = TS(0.0), aa = TS(0.0);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         lg += gt[k][i] * d[VB + k][j] + gt[k][j] * d[VB + k][i];
@@ -317,57 +323,62 @@ __device__ void z4c_point(const Pt& p, const Z4cArgs& a, double* rhs, double* ha
         aa += Atm[k][i] * At[k][j];
       }
       const int s = sym(i, j);
-      rhs[VG + s] = adv(VG + s) - 2.0 * alp * At[i][j] + lg - (2.0 / 3.0) * gt[i][j] * divb;
-      const double tf = (-DDa[i][j] + alp * R[i][j]) - (1.0 / 3.0) * gt[i][j] * trX;
-      rhs[VA + s] = adv(VA + s) + W * W * tf + alp * (Kt * At[i][j] - 2.0 * aa) + la -
-                    (2.0 / 3.0) * At[i][j] * divb;
+      rhs[VG + s] = adv(VG + s) - TS(2.0) * alp * At[i][j] + lg - (TS(2.0) / TS(3.0)) * gt[i][j] * divb;
+      const TS tf = (-DDa[i][j] + alp * R[i][j]) - (TS(1.0) / TS(3.0)) * gt[i][j] * trX;
+      rhs[VA + s] = adv(VA + s) + W * W * tf + alp * (Kt * At[i][j] - TS(2.0) * aa) + la -
+                    (TS(2.0) / TS(3.0)) * At[i][j] * divb;
     }
-  rhs[VKH] = adv(VKH) - lapa + alp * (AtA + (1.0 / 3.0) * Kt * Kt) +
-             alp * a.kappa1 * (1.0 - a.kappa2) * Th;
+  rhs[VKH] = adv(VKH) - lapa + alp * (AtA + (TS(1.0) / TS(3.0)) * Kt * Kt) +
+             alp * TS(a.kappa1) * (TS(1.0) - TS(a.kappa2)) * Th;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    double t1 = 0.0, t2 = 0.0, t3 = 0.0, t4 = 0.0, t6 = 0.0, t7 = 0.0;
+    TS t1 = TS(0.0), t2 = TS(0.0), t3 = TS(0.0), t4 = TS(0.0), t6 = TS(0.0), t7 = TS(0.0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       t1 += Atu[i][j] * da[j];
       t3 += Atu[i][j] * dW[j] / W;
-      t4 += gu[i][j] * (2.0 * d[VKH][j] + d[VTH][j]);
+      t4 += gu[i][j] * (TS(2.0) * d[VKH][j] + d[VTH][j]);
       t6 += gu[i][j] * gdivb[j];
       t7 += Gd[j] * d[VB + i][j];
 #pragma unroll
       for (int k = 0; k < 3; ++k) t2 += G[i][j][k] * Atu[j][k];
     }
-    rhs[VGAM + i] = adv(VGAM + i) - 2.0 * t1 + 2.0 * alp * (t2 - 3.0 * t3 - (1.0 / 3.0) * t4) +
-                    lapb[i] + (1.0 / 3.0) * t6 - t7 + (2.0 / 3.0) * Gd[i] * divb -
-                    2.0 * alp * a.kappa1 * (v[VGAM + i] - Gd[i]);
+    rhs[VGAM + i] = adv(VGAM + i) - TS(2.0) * t1 + TS(2.0) * alp * (t2 - TS(3.0) * t3 - (TS(1.0) / TS(3.0)) * t4) +
+                    lapb[i] + (TS(1.0) / TS(3.0)) * t6 - t7 + (TS(2.0) / TS(3.0)) * Gd[i] * divb -
+                    TS(2.0) * alp * TS(a.kappa1) * (v[VGAM + i] - Gd[i]);
   }
-  rhs[VTH] = adv(VTH) + 0.5 * alp * (Rs - AtA + (2.0 / 3.0) * Kt * Kt) -
-             alp * a.kappa1 * (2.0 + a.kappa2) * Th;
-  rhs[VALP] = adv(VALP) - 2.0 * alp * Kh;
-  const double xc = a.origin[0] + (p.B.lo[0] + p.x) * h;
-  const double yc = a.origin[1] + (p.B.lo[1] + p.y) * h;
-  const double zc = a.origin[2] + (p.B.lo[2] + p.z) * h;
+  rhs[VTH] = adv(VTH) + TS(0.5) * alp * (Rs - AtA + (TS(2.0) / TS(3.0)) * Kt * Kt) -
+             alp * TS(a.kappa1) * (TS(2.0) + TS(a.kappa2)) * Th;
+  rhs[VALP] = adv(VALP) - TS(2.0) * alp * Kh;
+  // damping eta(r) from the point's coordinates, in FP64
+  const double xc = a.origin[0] + (p.B.lo[0] + p.x) * a.h;
+  const double yc = a.origin[1] + (p.B.lo[1] + p.y) * a.h;
+  const double zc = a.origin[2] + (p.B.lo[2] + p.z) * a.h;
   const double r = sqrt(xc * xc + yc * yc + zc * zc);
   const double rq = r / a.eta_s;
-  const double eta = (a.eta_c - a.eta_o) * exp(-(rq * rq) * (rq * rq)) + a.eta_o;
+  const TS eta = TS((a.eta_c - a.eta_o) * exp(-(rq * rq) * (rq * rq)) + a.eta_o);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) rhs[VB + i] = adv(VB + i) + 0.75 * v[VGAM + i] - eta * beta[i];
-  const double cko = a.sigma / (64.0 * h);
+  for (int i = 0; i < 3; ++i) rhs[VB + i] = adv(VB + i) + TS(0.75) * v[VGAM + i] - eta * beta[i];
+  const TS cko = TS(a.sigma) / (TS(64.0) * h);
 #pragma unroll
   for (int i = 0; i < NV; ++i) rhs[i] += cko * ((p.ko(i, 0) + p.ko(i, 1)) + p.ko(i, 2));
 }
 
-template <int STAGE>
+template <int STAGE, typename TS>
 __global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
   const int tx = threadIdx.x % kTileMaxX, ty = threadIdx.x / kTileMaxX;
   constexpr int BY = kZ4cThreads / kTileMaxX;
+  TS* kout = static_cast<TS*>(a.kout);
+  const TS* k1 = static_cast<const TS*>(a.k1);
+  const TS* k2 = static_cast<const TS*>(a.k2);
+  const TS* k3 = static_cast<const TS*>(a.k3);
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
     for (int ry = ty; ry < T.ny; ry += BY) {
       if (tx >= T.nx) continue;
       for (int iz = 0; iz < T.nz; ++iz) {
-        Pt p;
+        Pt<TS> p;
         p.a = &a;
         p.B = B;
         p.x = T.x0 + tx;
@@ -376,21 +387,27 @@ __global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
         p.px = B.px;
         p.pxy = (int64_t)B.px * B.py;
         p.o = B.base + ((int64_t)(p.z + kG) * B.py + (p.y + kG)) * (int64_t)B.px + (p.x + kG);
-        if (a.ham) {
-          double hm;
-          z4c_point(p, a, nullptr, &hm);
-          a.ham[p.o] = hm;
-          continue;
+        if constexpr (sizeof(TS) == 8) {
+          if (a.ham) {
+            double hm;
+            z4c_point<TS>(p, a, nullptr, &hm);
+            a.ham[p.o] = hm;
+            continue;
+          }
         }
-        double rhs[NV];
-        z4c_point(p, a, rhs, nullptr);
+        TS rhs[NV];
+        z4c_point<TS>(p, a, rhs, nullptr);
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
           const int64_t oi = p.o + i * a.vstride;
-          if (a.kout) a.kout[oi] = rhs[i];
+          if (kout) kout[oi] = rhs[i];
           if constexpr (STAGE == 4) {
-            const double s = ((a.k1[oi] + 2.0 * a.k2[oi]) + 2.0 * a.k3[oi]) + rhs[i];
-            a.ynew[oi] = a.yn[oi] + a.dt6 * s;
+            // y_{n+1} in FP64 from the stored slopes
+            const double s = (((double)k1[oi] + 2.0 * (double)k2[oi]) + 2.0 * (double)k3[oi]) +
+                             (double)rhs[i];
+            const double yv = a.yn[oi] + a.dt6 * s;
+            a.ynew[oi] = yv;
+            if constexpr (sizeof(TS) == 4) a.ynew32[oi] = (float)yv;
           }
         }
       }
@@ -400,8 +417,13 @@ __global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
 
 // Y = y_n + cdt k_{s-1} on the owned points of the tiles (all variables);
 // Y = y_n when kprev is null (stage 1).
+template <typename TS>
 __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
   const int tx = threadIdx.x % kTileMaxX, ty = threadIdx.x / kTileMaxX;
+  const TS* yn = static_cast<const TS*>(a.yn);
+  const TS* kprev = static_cast<const TS*>(a.kprev);
+  TS* Y = static_cast<TS*>(a.Y);
+  const TS cdt = TS(a.cdt);
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
@@ -412,7 +434,7 @@ __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
                                        (int64_t)B.px + (T.x0 + tx + kG);
         for (int i = 0; i < a.nvars; ++i) {
           const int64_t oi = o + i * a.vstride;
-          a.Y[oi] = a.kprev ? a.yn[oi] + a.cdt * a.kprev[oi] : a.yn[oi];
+          Y[oi] = kprev ? yn[oi] + cdt * kprev[oi] : yn[oi];
         }
       }
     }
@@ -421,19 +443,24 @@ __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
 
 }  // namespace
 
-hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, hipStream_t s) {
+hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, bool f32, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g(grid > 0 ? grid : a.ntiles), b(kZ4cThreads);
-  switch (a.stage) {
-    case 4: hipLaunchKernelGGL(k_z4c_stage<4>, g, b, 0, s, a); break;
-    default: hipLaunchKernelGGL(k_z4c_stage<1>, g, b, 0, s, a); break;
+  if (f32) {
+    if (a.stage == 4) hipLaunchKernelGGL((k_z4c_stage<4, float>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_z4c_stage<1, float>), g, b, 0, s, a);
+  } else {
+    if (a.stage == 4) hipLaunchKernelGGL((k_z4c_stage<4, double>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_z4c_stage<1, double>), g, b, 0, s, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_z4c_combine(const Z4cCombineArgs& a, int grid, hipStream_t s) {
+hipError_t launch_z4c_combine(const Z4cCombineArgs& a, int grid, bool f32, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_z4c_combine, dim3(grid > 0 ? grid : a.ntiles), dim3(256), 0, s, a);
+  const dim3 g(grid > 0 ? grid : a.ntiles), b(256);
+  if (f32) hipLaunchKernelGGL(k_z4c_combine<float>, g, b, 0, s, a);
+  else hipLaunchKernelGGL(k_z4c_combine<double>, g, b, 0, s, a);
   return hipGetLastError();
 }
 

@@ -12,14 +12,15 @@ struct Z4cArgs {
   int32_t ntiles;
   int32_t stage;
   const BoxDev* boxes;
-  const double* Y;    // stage vector on the padded boxes (owned points and halo)
-  const double* yn;   // y_n (stage 4)
-  const double* k1;
-  const double* k2;
-  const double* k3;
-  double* kout;       // k_s (null in constraint mode)
-  double* ynew;       // y_{n+1} (stage 4)
-  double* ham;        // constraint mode: Hamiltonian constraint out, else null
+  const void* Y;      // stage vector on the padded boxes (owned points and halo), TS
+  const double* yn;   // FP64 y_n (stage 4)
+  const void* k1;     // slopes, TS
+  const void* k2;
+  const void* k3;
+  void* kout;         // k_s, TS (null in constraint mode)
+  double* ynew;       // FP64 y_{n+1} (stage 4)
+  float* ynew32;      // its FP32 shadow (FP32 variant, stage 4)
+  double* ham;        // constraint mode (FP64 only): Hamiltonian constraint out, else null
   int64_t vstride;
   double h, dt6, sigma, kappa1, kappa2, eta_c, eta_o, eta_s;
   double origin[3];   // coordinates of global index (0,0,0) of the level
@@ -30,14 +31,15 @@ struct Z4cCombineArgs {
   int32_t ntiles;
   int32_t nvars;
   const BoxDev* boxes;
-  const double* yn;
-  const double* kprev;
-  double* Y;
+  const void* yn;     // y_n, TS (the FP32 shadow in the FP32 variant)
+  const void* kprev;  // k_{s-1}, TS, or null at stage 1
+  void* Y;            // stage vector out, TS
   int64_t vstride;
   double cdt;
 };
 
-hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, hipStream_t s);
-hipError_t launch_z4c_combine(const Z4cCombineArgs& a, int grid, hipStream_t s);
+// f32: FP32-RHS variant (TS = float)
+hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, bool f32, hipStream_t s);
+hipError_t launch_z4c_combine(const Z4cCombineArgs& a, int grid, bool f32, hipStream_t s);
 
 }  // namespace sc

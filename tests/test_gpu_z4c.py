@@ -18,8 +18,8 @@ TOL = 1e-12
 KW = dict(min_block=8, max_block=16)
 
 
-def _pair(spec, exec=sc.SC_EXEC_BATCHED):
-    ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=exec)
+def _pair(spec, exec=sc.SC_EXEC_BATCHED, precision=sc.SC_FP64):
+    ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=exec, precision=precision)
     ctx.build_spec(spec, **KW)
     ctx.bind()
     ref = OracleRun(Hierarchy(spec, **KW), rhs="z4c")
@@ -86,3 +86,46 @@ def test_z4c_hamiltonian_constraint_matches_reference():
         e = np.abs(a - b).max() / np.abs(b).max()
         print("level", l, "H max", np.abs(b).max(), "rel diff", e)
         assert e <= 1e-10
+
+
+def test_z4c_fp32_rhs_variant_within_bound():
+    """FP32 stage vectors, slopes and right-hand side, FP64 state update: after
+    two coarse steps every variable on every level is within
+    t * 32 eps32 * max|y| / h_finest^2 of the FP64 run (the FP32 rounding of
+    the stage values, amplified by the second differences, accumulated over
+    the run; the same form as the wave system's bound)."""
+    spec = config_z4c_small()
+    out = {}
+    for prec in (sc.SC_FP64, sc.SC_MIXED):
+        ctx, _ = _pair(spec, precision=prec)
+        ctx.advance(2)
+        out[prec] = [[ctx.read_back(0, l, v) for v in range(22)] for l in range(spec.nlevels)]
+        t = ctx.level_time(0)
+        ctx.close()
+    eps32 = float(np.finfo(np.float32).eps)
+    hf = spec.dx(spec.nlevels - 1)
+    ymax = max(np.abs(a).max() for lev in out[sc.SC_FP64] for a in lev)
+    bound = t * 32.0 * eps32 * ymax / hf ** 2
+    worst = 0.0
+    for l in range(spec.nlevels):
+        for v in range(22):
+            d = np.abs(out[sc.SC_MIXED][l][v] - out[sc.SC_FP64][l][v]).max()
+            worst = max(worst, d)
+            assert np.isfinite(d) and d <= bound, (l, v, d, bound)
+    print("z4c fp32-rhs worst |mixed - fp64|", worst, "bound", bound)
+    assert worst > 0.0   # the variant really ran in FP32
+
+
+def test_z4c_fp32_rhs_variant_hamiltonian():
+    spec = config_z4c_small()
+    hs = {}
+    for prec in (sc.SC_FP64, sc.SC_MIXED):
+        ctx, _ = _pair(spec, precision=prec)
+        ctx.advance(1)
+        hs[prec] = [ctx.hamiltonian(0, l) for l in range(spec.nlevels)]
+        ctx.close()
+    for l in range(spec.nlevels):
+        a, b = hs[sc.SC_MIXED][l], hs[sc.SC_FP64][l]
+        e = np.abs(a - b).max() / np.abs(b).max()
+        print("level", l, "H rel diff fp32-rhs vs fp64", e)
+        assert e < 1e-3
