@@ -299,13 +299,7 @@ __device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ha
   TS divb = TS(0.0);
 #pragma unroll
   for (int k = 0; k < 3; ++k) divb += d[VB + k][k];
-  auto adv = [&](int i) {
-    TS s = TS(0.0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) s += beta[k] * d[i][k];
-    return s;
-  };
-  rhs[VW] = adv(VW) + (TS(1.0) / TS(3.0)) * W * (alp * Kt - divb);
+  rhs[VW] = (TS(1.0) / TS(3.0)) * W * (alp * Kt - divb);
   TS trX = TS(0.0);
 #pragma unroll
   for (int k = 0; k < 3; ++k)
@@ -323,12 +317,12 @@ __device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ha
         aa += Atm[k][i] * At[k][j];
       }
       const int s = sym(i, j);
-      rhs[VG + s] = adv(VG + s) - TS(2.0) * alp * At[i][j] + lg - (TS(2.0) / TS(3.0)) * gt[i][j] * divb;
+      rhs[VG + s] = -TS(2.0) * alp * At[i][j] + lg - (TS(2.0) / TS(3.0)) * gt[i][j] * divb;
       const TS tf = (-DDa[i][j] + alp * R[i][j]) - (TS(1.0) / TS(3.0)) * gt[i][j] * trX;
-      rhs[VA + s] = adv(VA + s) + W * W * tf + alp * (Kt * At[i][j] - TS(2.0) * aa) + la -
+      rhs[VA + s] = W * W * tf + alp * (Kt * At[i][j] - TS(2.0) * aa) + la -
                     (TS(2.0) / TS(3.0)) * At[i][j] * divb;
     }
-  rhs[VKH] = adv(VKH) - lapa + alp * (AtA + (TS(1.0) / TS(3.0)) * Kt * Kt) +
+  rhs[VKH] = -lapa + alp * (AtA + (TS(1.0) / TS(3.0)) * Kt * Kt) +
              alp * TS(a.kappa1) * (TS(1.0) - TS(a.kappa2)) * Th;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -343,13 +337,13 @@ __device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ha
 #pragma unroll
       for (int k = 0; k < 3; ++k) t2 += G[i][j][k] * Atu[j][k];
     }
-    rhs[VGAM + i] = adv(VGAM + i) - TS(2.0) * t1 + TS(2.0) * alp * (t2 - TS(3.0) * t3 - (TS(1.0) / TS(3.0)) * t4) +
+    rhs[VGAM + i] = -TS(2.0) * t1 + TS(2.0) * alp * (t2 - TS(3.0) * t3 - (TS(1.0) / TS(3.0)) * t4) +
                     lapb[i] + (TS(1.0) / TS(3.0)) * t6 - t7 + (TS(2.0) / TS(3.0)) * Gd[i] * divb -
                     TS(2.0) * alp * TS(a.kappa1) * (v[VGAM + i] - Gd[i]);
   }
-  rhs[VTH] = adv(VTH) + TS(0.5) * alp * (Rs - AtA + (TS(2.0) / TS(3.0)) * Kt * Kt) -
+  rhs[VTH] = TS(0.5) * alp * (Rs - AtA + (TS(2.0) / TS(3.0)) * Kt * Kt) -
              alp * TS(a.kappa1) * (TS(2.0) + TS(a.kappa2)) * Th;
-  rhs[VALP] = adv(VALP) - TS(2.0) * alp * Kh;
+  rhs[VALP] = -TS(2.0) * alp * Kh;
   // damping eta(r) from the point's coordinates, in FP64
   const double xc = a.origin[0] + (p.B.lo[0] + p.x) * a.h;
   const double yc = a.origin[1] + (p.B.lo[1] + p.y) * a.h;
@@ -358,20 +352,17 @@ __device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ha
   const double rq = r / a.eta_s;
   const TS eta = TS((a.eta_c - a.eta_o) * exp(-(rq * rq) * (rq * rq)) + a.eta_o);
 #pragma unroll
-  for (int i = 0; i < 3; ++i) rhs[VB + i] = adv(VB + i) + TS(0.75) * v[VGAM + i] - eta * beta[i];
-  const TS cko = TS(a.sigma) / (TS(64.0) * h);
-#pragma unroll
-  for (int i = 0; i < NV; ++i) rhs[i] += cko * ((p.ko(i, 0) + p.ko(i, 1)) + p.ko(i, 2));
+  for (int i = 0; i < 3; ++i) rhs[VB + i] = TS(0.75) * v[VGAM + i] - eta * beta[i];
+  // the advection terms beta^k d_k and the dissipation are added by k_z4c_advko
 }
 
-template <int STAGE, typename TS>
+// Curvature, gauge and constraint-damping terms of the right-hand side (no
+// advection, no dissipation), or the Hamiltonian constraint.
+template <typename TS>
 __global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
   const int tx = threadIdx.x % kTileMaxX, ty = threadIdx.x / kTileMaxX;
   constexpr int BY = kZ4cThreads / kTileMaxX;
   TS* kout = static_cast<TS*>(a.kout);
-  const TS* k1 = static_cast<const TS*>(a.k1);
-  const TS* k2 = static_cast<const TS*>(a.k2);
-  const TS* k3 = static_cast<const TS*>(a.k3);
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
@@ -398,13 +389,57 @@ __global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
         TS rhs[NV];
         z4c_point<TS>(p, a, rhs, nullptr);
 #pragma unroll
+        for (int i = 0; i < NV; ++i) kout[p.o + i * a.vstride] = rhs[i];
+      }
+    }
+  }
+}
+
+// Completes k_s: adds the advection terms beta^k d_k Y (centred fourth-order
+// first differences) and the Kreiss-Oliger dissipation of every variable;
+// at stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4) in
+// FP64.  Both stencils read the same seven taps per axis.
+template <int STAGE, typename TS>
+__global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
+  const int tx = threadIdx.x % kTileMaxX, ty = threadIdx.x / kTileMaxX;
+  const TS* Y = static_cast<const TS*>(a.Y);
+  TS* kout = static_cast<TS*>(a.kout);
+  const TS* k1 = static_cast<const TS*>(a.k1);
+  const TS* k2 = static_cast<const TS*>(a.k2);
+  const TS* k3 = static_cast<const TS*>(a.k3);
+  const TS h = TS(a.h);
+  const TS c1 = TS(1.0) / (TS(12.0) * h);
+  const TS cko = TS(a.sigma) / (TS(64.0) * h);
+  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    const TileDev T = a.tiles[t];
+    const BoxDev B = a.boxes[T.box];
+    const int64_t st[3] = {1, (int64_t)B.px, (int64_t)B.px * B.py};
+    for (int ry = ty; ry < T.ny; ry += 256 / kTileMaxX) {
+      if (tx >= T.nx) continue;
+      for (int iz = 0; iz < T.nz; ++iz) {
+        const int64_t o = B.base + ((int64_t)(T.z0 + iz + kG) * B.py + (T.y0 + ry + kG)) *
+                                       (int64_t)B.px + (T.x0 + tx + kG);
+        TS beta[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) beta[k] = Y[o + (VB + k) * a.vstride];
         for (int i = 0; i < NV; ++i) {
-          const int64_t oi = p.o + i * a.vstride;
-          if (kout) kout[oi] = rhs[i];
+          const int64_t oi = o + i * a.vstride;
+          TS adv = TS(0.0), ko[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            TS tp[7];
+#pragma unroll
+            for (int j = 0; j < 7; ++j) tp[j] = Y[oi + (j - 3) * st[d]];
+            const TS d1 = (((tp[1] - TS(8.0) * tp[2]) + TS(8.0) * tp[4]) - tp[5]) * c1;
+            adv += beta[d] * d1;
+            ko[d] = (((((tp[0] - TS(6.0) * tp[1]) + TS(15.0) * tp[2]) - TS(20.0) * tp[3]) +
+                      TS(15.0) * tp[4]) - TS(6.0) * tp[5]) + tp[6];
+          }
+          const TS k = (kout[oi] + adv) + cko * ((ko[0] + ko[1]) + ko[2]);
+          kout[oi] = k;
           if constexpr (STAGE == 4) {
-            // y_{n+1} in FP64 from the stored slopes
             const double s = (((double)k1[oi] + 2.0 * (double)k2[oi]) + 2.0 * (double)k3[oi]) +
-                             (double)rhs[i];
+                             (double)k;
             const double yv = a.yn[oi] + a.dt6 * s;
             a.ynew[oi] = yv;
             if constexpr (sizeof(TS) == 4) a.ynew32[oi] = (float)yv;
@@ -445,13 +480,17 @@ __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
 
 hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, bool f32, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
-  const dim3 g(grid > 0 ? grid : a.ntiles), b(kZ4cThreads);
+  const dim3 g(grid > 0 ? grid : a.ntiles);
   if (f32) {
-    if (a.stage == 4) hipLaunchKernelGGL((k_z4c_stage<4, float>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_z4c_stage<1, float>), g, b, 0, s, a);
+    hipLaunchKernelGGL(k_z4c_stage<float>, g, dim3(kZ4cThreads), 0, s, a);
+    if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, float>), g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_z4c_advko<1, float>), g, dim3(256), 0, s, a);
   } else {
-    if (a.stage == 4) hipLaunchKernelGGL((k_z4c_stage<4, double>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_z4c_stage<1, double>), g, b, 0, s, a);
+    hipLaunchKernelGGL(k_z4c_stage<double>, g, dim3(kZ4cThreads), 0, s, a);
+    if (!a.ham) {
+      if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, double>), g, dim3(256), 0, s, a);
+      else hipLaunchKernelGGL((k_z4c_advko<1, double>), g, dim3(256), 0, s, a);
+    }
   }
   return hipGetLastError();
 }
