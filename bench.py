@@ -186,6 +186,67 @@ def z4c_run(args):
             "hamiltonian_L2": [{"t": t, "H": h} for t, h in hist], "finite": finite}
 
 
+def e1_run(args):
+    """The paper's scalar-wave test (Sec. IV.A): outgoing spherical Gaussian on a
+    periodic [-6,6]^3 with refined boxes over [-4,4]^3 and [-1,1]^3, coarse
+    spacing 0.032/1.2^k; max-norm error of u on the second refined level
+    against the exact solution, subcycled and uniform time steps."""
+    import torch
+    import paper_2503_09629_amd as sc
+    from workloads import canonical_coords, config_e1, spherical_gaussian, spherical_gaussian_on_spec
+    checkpoints = [round(0.4 * (i + 1), 10) for i in range(int(round(args.e1_t / 0.4)))]
+    modes = [m.strip() for m in args.e1_modes.split(",") if m.strip()]
+    out = {"workload": "scalar wave E1: spherical Gaussian A=1, sigma=0.25/sqrt(2), periodic "
+                       "[-6,6]^3, refined boxes [-4,4]^3 and [-1,1]^3 (snapped outward)",
+           "checkpoints": checkpoints, "runs": []}
+    for mode in modes:
+        uniform = mode == "uniform"
+        for n0 in args.e1_n0:
+            spec = config_e1(n0)
+            dt_steps = 0.25 * spec.dx(spec.nlevels - 1 if uniform else 0)
+            U = spec.total_points() if uniform else spec.updates_per_coarse_step()
+            log(f"e1 {mode} n0={n0}: {spec.total_points()} points, dt {dt_steps:.6g}")
+            ctx = sc.Context(device="cuda:0", exec=sc.SC_EXEC_GRAPH,
+                             time_stepping=sc.SC_UNIFORM_DT if uniform else sc.SC_SUBCYCLED)
+            ctx.build_spec(spec, block_seed=1, min_block=16, max_block=48)
+            ctx.bind()
+            for l in range(spec.nlevels):
+                for v, f in enumerate(spherical_gaussian_on_spec(spec, l, 0.0)):
+                    ctx.set_initial_data(0, l, v, f)
+            lev = spec.nlevels - 1
+            x, y, z = canonical_coords(spec, lev)
+            errs, steps_done, T = [], 0, 0.0
+            for tc in checkpoints:
+                nsteps = int(round(tc / dt_steps)) - steps_done
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.advance(nsteps)
+                ctx.synchronize()
+                T += time.perf_counter() - t0
+                steps_done += nsteps
+                t = ctx.level_time(lev)
+                ue, _ = spherical_gaussian(t, x, y, z)
+                e = float(np.abs(ctx.read_back(0, lev, 0) - ue).max())
+                errs.append(e)
+                log(f"  t = {t:.4f}: max |u - u_exact| on level {lev} = {e:.4e} "
+                    f"({steps_done} steps, {U * steps_done / T:.4g} updates/s)")
+            out["runs"].append({"mode": mode, "n0": n0, "coarse_dx": spec.dx(0),
+                                "finest_dx": spec.dx(lev), "points": spec.total_points(),
+                                "steps": steps_done, "errors": errs,
+                                "updates_per_s": U * steps_done / T, "seconds": T})
+            ctx.close()
+            del ctx, x, y, z
+            torch.cuda.empty_cache()
+    # observed orders between successive resolutions (ratio 1.2)
+    for mode in modes:
+        runs = [r for r in out["runs"] if r["mode"] == mode]
+        for a, b in zip(runs, runs[1:]):
+            ratio = a["coarse_dx"] / b["coarse_dx"]
+            b["order_vs_previous"] = [float(np.log(ea / eb) / np.log(ratio)) if eb > 0 else None
+                                      for ea, eb in zip(a["errors"], b["errors"])]
+    return out
+
+
 def precision_report(args):
     """Mixed vs FP64: max-norm difference per level and observed orders."""
     import paper_2503_09629_amd as sc
@@ -254,7 +315,10 @@ def main():
                     help="JSON line of an earlier run: take its tile shapes instead of tuning")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--workload", default="wave", choices=("wave", "z4c", "precision"))
+    ap.add_argument("--workload", default="wave", choices=("wave", "z4c", "precision", "e1"))
+    ap.add_argument("--e1-n0", type=int, nargs="+", default=[375, 450, 540])
+    ap.add_argument("--e1-t", type=float, default=1.6)
+    ap.add_argument("--e1-modes", default="subcycled,uniform")
     ap.add_argument("--z4c-steps", type=int, default=16)
     ap.add_argument("--z4c-precision", default="fp64", choices=("fp64", "mixed"))
     ap.add_argument("--report-n0", type=int, nargs="+", default=[64, 128, 256])
@@ -277,6 +341,9 @@ def main():
         return
     if args.workload == "z4c":
         print(json.dumps(z4c_run(args)), flush=True)
+        return
+    if args.workload == "e1":
+        print(json.dumps(e1_run(args)), flush=True)
         return
     if args.workload == "precision":
         print(json.dumps(precision_report(args)), flush=True)

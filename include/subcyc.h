@@ -77,6 +77,15 @@ enum { SC_FILL_Y1 = 1, SC_FILL_Y2 = 2, SC_FILL_Y3 = 3, SC_FILL_Y4 = 4, SC_FILL_E
 
 typedef struct sc_ctx sc_ctx;
 
+/* Time stepping (Sec. IV.A compares both).  SC_SUBCYCLED: level l steps with
+ * dt_l = cfl dx_l, two fine steps per parent step, fine refinement-boundary
+ * ghosts from the parent's cubic dense output (Sec. II).  SC_UNIFORM_DT: every
+ * level steps with the finest level's dt, one fine step per parent step, and
+ * the fine ghosts of stage s take the parent's own stage value at the same
+ * time, y_n + c_s dt k_{s-1} (RK4 nodes c = 0, 1/2, 1/2, 1), prolonged in space;
+ * the parent's step is complete before the fine step starts. */
+enum { SC_SUBCYCLED = 0, SC_UNIFORM_DT = 1 };
+
 typedef struct {
   int64_t lo[3], hi[3]; /* inclusive vertex indices on the box's level, x, y, z */
 } sc_box;
@@ -87,7 +96,7 @@ typedef struct {
   int32_t precision;   /* SC_FP64 or SC_MIXED */
   int32_t exec;        /* SC_EXEC_* */
   int32_t nghost;      /* ghost width; must be 3 (fourth-order FD with r = 4 dissipation) */
-  int32_t reserved;
+  int32_t time_stepping; /* SC_SUBCYCLED (default) or SC_UNIFORM_DT */
   double ko_sigma;     /* Kreiss-Oliger strength sigma (Sec. III.C), e.g. 0.32 */
   double cfl;          /* dt_l = cfl * dx_l, 0 < cfl <= 0.5 */
   double z4c_kappa1;   /* Z4c constraint damping kappa_1 (default 0.02) */

@@ -92,3 +92,16 @@ def ghost_weights(stage: int, theta0):
 
 def ghost_weights_f64(stage: int, theta0):
     return tuple(float(w.numerator) / float(w.denominator) for w in ghost_weights(stage, theta0))
+
+
+def aligned_weights(stage: int):
+    """Uniform time steps (the comparison runs of Sec. IV.A): parent and child
+    take the same step H, so the ghost of fine stage s is the parent's own stage
+    vector at the same time, Y_s = y_n + c_s H k_{s-1} (Eqs. rk2-rk4), and the
+    ghost after the step is y_{n+1} (Eq. rk5); returned as (w1..w4) of H k_i."""
+    w = [F(0)] * 4
+    if stage == 5:
+        return RK4_B
+    if stage >= 2:
+        w[stage - 2] = RK4_C[stage - 1]
+    return tuple(w)

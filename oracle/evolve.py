@@ -34,6 +34,12 @@ with H = dt_{l-1} and w from oracle.dense.ghost_weights.
 Restriction is injection: y_{l-1}(I) <- y_l(2I) for every restriction pair.
 
 Time steps: dt_l = cfl * dx_l.
+
+Uniform time steps (subcycling=False; the comparison runs of Sec. IV.A):
+every level steps with the finest level's dt, advance_level takes one child
+step per parent step, and the RB ghost of stage s is the parent's stage vector
+at the same time, P[y_n] + dt * c_s P[k_{s-1}] (oracle.dense.aligned_weights),
+with the parent's step already complete.
 """
 from __future__ import annotations
 
@@ -42,7 +48,7 @@ from fractions import Fraction
 import numpy as np
 
 from . import cbuild
-from .dense import ghost_weights_f64
+from .dense import aligned_weights, ghost_weights_f64
 from .hierarchy import PHYS, RB, SYNC, Hierarchy
 
 PROLONG_W = tuple(w / 256.0 for w in (3.0, -25.0, 150.0, 150.0, -25.0, 3.0))
@@ -175,7 +181,7 @@ class OracleRun:
     """
 
     def __init__(self, hier: Hierarchy, rhs: str = "wave", sigma: float = 0.32,
-                 cfl: float = 0.25, z4c: dict = None):
+                 cfl: float = 0.25, z4c: dict = None, subcycling: bool = True):
         if rhs not in ("wave", "z4c"):
             raise ValueError(rhs)
         self.rhs_kind = rhs
@@ -201,9 +207,15 @@ class OracleRun:
         self.theta0 = [0.0] * self.L
         self.t = [0.0] * self.L
         self.dx = [self.spec.dx(l) for l in range(self.L)]
-        self.dt = [cfl * self.dx[l] for l in range(self.L)]
-        self.weights = {(s, th): ghost_weights_f64(s, Fraction(th))
-                        for s in range(1, 6) for th in (0.0, 0.5)}
+        self.subcycling = subcycling
+        if subcycling:
+            self.dt = [cfl * self.dx[l] for l in range(self.L)]
+            self.weights = {(s, th): ghost_weights_f64(s, Fraction(th))
+                            for s in range(1, 6) for th in (0.0, 0.5)}
+        else:
+            self.dt = [cfl * self.dx[self.L - 1]] * self.L
+            self.weights = {(s, th): tuple(float(w) for w in aligned_weights(s))
+                            for s in range(1, 6) for th in (0.0, 0.5)}
 
     # -- data ----------------------------------------------------------------
     def set_data(self, l: int, var: int, values) -> None:
@@ -314,8 +326,9 @@ class OracleRun:
             self.prolongate(l + 1)
             self.theta0[l + 1] = 0.0
             self.advance_level(l + 1)
-            self.theta0[l + 1] = 0.5
-            self.advance_level(l + 1)
+            if self.subcycling:
+                self.theta0[l + 1] = 0.5
+                self.advance_level(l + 1)
             self.restrict(l + 1)
         self.fill(l, self.st[l].y, 5)
         self.t[l] += self.dt[l]

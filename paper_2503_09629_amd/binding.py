@@ -22,6 +22,7 @@ SC_EXEC_PER_BLOCK, SC_EXEC_BATCHED, SC_EXEC_GRAPH = 0, 1, 2
 SC_ARR_Y, SC_ARR_K1, SC_ARR_K2, SC_ARR_K3, SC_ARR_K4, SC_ARR_YN = range(6)
 SC_FILL_Y1, SC_FILL_Y2, SC_FILL_Y3, SC_FILL_Y4, SC_FILL_END = 1, 2, 3, 4, 5
 SC_ABI_VERSION = 1
+SC_SUBCYCLED, SC_UNIFORM_DT = 0, 1
 
 EXPORTED = [
     "sc_config_default", "sc_create", "sc_destroy", "sc_last_error", "sc_build_hierarchy",
@@ -38,7 +39,7 @@ EXPORTED = [
 class ScConfig(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_int32), ("rhs", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("exec", ctypes.c_int32),
-                ("nghost", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("nghost", ctypes.c_int32), ("time_stepping", ctypes.c_int32),
                 ("ko_sigma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("z4c_kappa1", ctypes.c_double), ("z4c_kappa2", ctypes.c_double),
                 ("z4c_eta_c", ctypes.c_double), ("z4c_eta_o", ctypes.c_double),
@@ -129,10 +130,12 @@ class Context:
 
     def __init__(self, sigma: float = 0.32, cfl: float = 0.25, exec: int = SC_EXEC_BATCHED,
                  precision: int = SC_FP64, stream=None, device: Optional[str] = None,
-                 rhs: int = SC_RHS_WAVE, z4c: Optional[dict] = None):
+                 rhs: int = SC_RHS_WAVE, z4c: Optional[dict] = None,
+                 time_stepping: int = SC_SUBCYCLED):
         self.L = lib()
         cfg = ScConfig()
         self._check(self.L.sc_config_default(ctypes.byref(cfg)), None)
+        cfg.time_stepping = time_stepping
         cfg.ko_sigma = sigma
         cfg.cfl = cfl
         cfg.exec = exec

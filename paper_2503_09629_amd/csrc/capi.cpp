@@ -72,6 +72,20 @@ void dense_b(Rat th, int m, Rat out[4]) {
 // Ghost value = y_n + H * sum_i w_i k_i for fine stage `fill` (1..4, Taylor
 // forms of Y1..Y4 with fine step h = H/2 and f_y y'' = 4 (k3 - k2) / H^2)
 // or the end value (5, dense output at theta0 + 1/2).
+// Uniform time steps: the stage value of the parent at the fine stage's own
+// time, y_n + c_s H k_{s-1} (fills 1-4), and y_{n+1} (fill 5), as weights of
+// H k_i.
+void aligned_weights(int fill, double w[4]) {
+  static const Rat c[4] = {Rat(0), Rat(1, 2), Rat(1, 2), Rat(1)};
+  Rat r[4];
+  if (fill == 5) {
+    r[0] = Rat(1, 6), r[1] = Rat(1, 3), r[2] = Rat(1, 3), r[3] = Rat(1, 6);
+  } else if (fill >= 2) {
+    r[fill - 2] = c[fill - 1];
+  }
+  for (int i = 0; i < 4; ++i) w[i] = r[i].f();
+}
+
 void ghost_weights(int fill, Rat th0, double w[4]) {
   Rat r[4];
   if (fill == 5) {
@@ -190,7 +204,10 @@ std::string build_layout(sc_ctx* c) {
     const LevelMaps& M = H.levels[l];
     LevelDev& L = c->lev[l];
     L.dx = H.geo.dx0 / (double)(int64_t(1) << l);
-    L.dt = c->cfg.cfl * L.dx;
+    // subcycled: dt_l = cfl dx_l; uniform: the finest level's step everywhere
+    L.dt = c->cfg.cfl * (c->cfg.time_stepping == SC_UNIFORM_DT
+                             ? H.geo.dx0 / (double)(int64_t(1) << (nl - 1))
+                             : L.dx);
     L.nb_member = (int)M.boxes.size();
     L.has_child = l + 1 < nl;
     L.nyh = l == 0 ? 1 : 8;
@@ -828,14 +845,15 @@ int prolongate(sc_ctx* c, int fl) {
   LevelDev& F = c->lev[fl];
   void* outs[8];
   int fills[8], subs[8];
-  for (int sub = 0; sub < 2; ++sub)
+  const int nsub = c->cfg.time_stepping == SC_UNIFORM_DT ? 1 : 2;   // fine steps per parent step
+  for (int sub = 0; sub < nsub; ++sub)
     for (int s = 1; s <= 4; ++s) {
       const int o = sub * 4 + s - 1;
       outs[o] = F.Yh[o];
       fills[o] = s;
       subs[o] = sub;
     }
-  return prolong_into(c, fl, F.d_prolong, F.prolong_cls, 8, outs, fills, subs, F.total,
+  return prolong_into(c, fl, F.d_prolong, F.prolong_cls, 4 * nsub, outs, fills, subs, F.total,
                       c->mixed, -1, true);
 }
 
@@ -866,7 +884,9 @@ int advance_level(sc_ctx* c, int l, int substep, bool per_block) {
   if (l + 1 < (int)c->lev.size()) {
     if ((rc = prolongate(c, l + 1))) return rc;
     if ((rc = advance_level(c, l + 1, 0, per_block))) return rc;
-    if ((rc = advance_level(c, l + 1, 1, per_block))) return rc;
+    if (c->cfg.time_stepping != SC_UNIFORM_DT &&
+        (rc = advance_level(c, l + 1, 1, per_block)))
+      return rc;
     if ((rc = restrict_level(c, l + 1))) return rc;
   }
   c->lev[l].t += c->lev[l].dt;
@@ -940,12 +960,13 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
     g_create_error = "abi_version mismatch";
     return SC_E_ARG;
   }
-  const bool rhs_ok = cfg->rhs == SC_RHS_WAVE || cfg->rhs == SC_RHS_Z4C;
+  const bool rhs_ok = (cfg->rhs == SC_RHS_WAVE || cfg->rhs == SC_RHS_Z4C) &&
+                     (cfg->time_stepping == SC_SUBCYCLED || cfg->time_stepping == SC_UNIFORM_DT);
   if (!rhs_ok || cfg->nghost != 3 || !(cfg->z4c_eta_s > 0.0) || !(cfg->cfl > 0.0 && cfg->cfl <= 0.5) ||
       cfg->ko_sigma < 0.0 || (cfg->precision != SC_FP64 && cfg->precision != SC_MIXED) ||
       cfg->exec < 0 || cfg->exec > 2) {
-    g_create_error = "unsupported configuration (rhs, nghost 3, 0 < cfl <= 0.5, sigma >= 0, "
-                     "precision, exec)";
+    g_create_error = "unsupported configuration (rhs, time stepping, nghost 3, 0 < cfl <= 0.5, "
+                     "sigma >= 0, precision, exec)";
     return SC_E_ARG;
   }
   sc_ctx* c = new sc_ctx();
@@ -955,7 +976,10 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
   c->esz = c->mixed ? sizeof(float) : sizeof(double);
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   for (int sub = 0; sub < 2; ++sub)
-    for (int f = 1; f <= 5; ++f) ghost_weights(f, sub ? Rat(1, 2) : Rat(0), c->weights[sub][f - 1]);
+    for (int f = 1; f <= 5; ++f) {
+      if (cfg->time_stepping == SC_UNIFORM_DT) aligned_weights(f, c->weights[sub][f - 1]);
+      else ghost_weights(f, sub ? Rat(1, 2) : Rat(0), c->weights[sub][f - 1]);
+    }
   *out = c;
   return SC_OK;
 }
@@ -1224,7 +1248,7 @@ int sc_advance(sc_ctx* c, int32_t ncoarse) {
       HIPCHK(c, hipGraphLaunch(c->graph[parity], c->stream));
       // replay the host bookkeeping of one coarse step
       for (size_t l = 0; l < c->lev.size(); ++l) {
-        const int64_t steps = int64_t(1) << l;
+        const int64_t steps = c->cfg.time_stepping == SC_UNIFORM_DT ? 1 : int64_t(1) << l;
         if (steps & 1) c->lev[l].cur = 1 - c->lev[l].cur;
         for (int64_t s = 0; s < steps; ++s) c->lev[l].t += c->lev[l].dt;
       }
@@ -1569,8 +1593,14 @@ int sc_profile_read(sc_ctx* c, int64_t* nlaunches, double* total_ms, double* alg
 int sc_stats(const sc_ctx* c, int64_t* updates_per_coarse_step, int64_t* launches) {
   int rc = check_ready(c, 1);
   if (rc) return rc;
-  if (updates_per_coarse_step)
-    *updates_per_coarse_step = c->hier.updates_per_coarse_step() * c->hier.geo.nmembers;
+  if (updates_per_coarse_step) {
+    int64_t u = 0;
+    if (c->cfg.time_stepping == SC_UNIFORM_DT)
+      for (const LevelDev& L : c->lev) u += L.owned_member;
+    else
+      u = c->hier.updates_per_coarse_step();
+    *updates_per_coarse_step = u * c->hier.geo.nmembers;
+  }
   if (launches) *launches = c->launches;
   return SC_OK;
 }

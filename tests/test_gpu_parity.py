@@ -12,14 +12,16 @@ import paper_2503_09629_amd as sc
 from oracle.evolve import OracleRun
 from oracle.hierarchy import Hierarchy
 from workloads import (HierarchySpec, config_c1, config_c2, config_c3, ensemble_c1,
-                       ensemble_on_spec, gaussian_on_spec, pulses_on_spec, standing_wave_on_spec)
+                       ensemble_on_spec, gaussian_on_spec, pulses_on_spec, standing_wave_on_spec, config_e1, spherical_gaussian_on_spec)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
-def _gpu(spec, exec=sc.SC_EXEC_BATCHED, sigma=0.32, precision=sc.SC_FP64, **kw):
-    ctx = sc.Context(device="cuda:0", exec=exec, sigma=sigma, precision=precision)
+def _gpu(spec, exec=sc.SC_EXEC_BATCHED, sigma=0.32, precision=sc.SC_FP64,
+         time_stepping=sc.SC_SUBCYCLED, **kw):
+    ctx = sc.Context(device="cuda:0", exec=exec, sigma=sigma, precision=precision,
+                     time_stepping=time_stepping)
     ctx.build_spec(spec, **kw)
     ctx.bind()
     return ctx
@@ -254,3 +256,44 @@ def test_k4_not_kept_on_finest_level():
     with pytest.raises(sc.ScError) as e:
         ctx.read_back(0, 1, 0, sc.SC_ARR_K4)
     assert e.value.code == sc.SC_E_STATE
+
+
+@pytest.mark.parametrize("exec", [sc.SC_EXEC_BATCHED, sc.SC_EXEC_GRAPH, sc.SC_EXEC_PER_BLOCK])
+def test_uniform_time_steps_match_reference(exec):
+    """Every level on the finest step, ghosts from the parent's stage values at
+    the same time (the paper's non-subcycled comparison mode)."""
+    spec = HierarchySpec((-1.0,) * 3, 2.0 / 12, (12, 12, 12), (True,) * 3,
+                         [[((4, 4, 4), (22, 22, 22))],
+                          [((16, 16, 16), (24, 26, 24)), ((28, 16, 18), (36, 24, 26))]])
+    kw = dict(min_block=4, max_block=8, block_seed=9)
+    ctx = _gpu(spec, exec=exec, time_stepping=sc.SC_UNIFORM_DT, **kw)
+    ref = OracleRun(Hierarchy(spec, **kw), sigma=0.32, subcycling=False)
+    for l in range(spec.nlevels):
+        for v, f in enumerate(gaussian_on_spec(spec, l, centre=(0.1, -0.05, 0.0), width=0.3)):
+            ctx.set_initial_data(0, l, v, f)
+            ref.set_data(l, v, f)
+    ctx.advance(5)
+    ref.advance(5)
+    for l in range(spec.nlevels):
+        assert abs(ctx.level_time(l) - ref.t[l]) < 1e-15
+    w = _compare_all(ctx, ref, arrays=("y", "k3"))
+    print("uniform time steps worst rel diff", w)
+
+
+@pytest.mark.parametrize("ts", [sc.SC_SUBCYCLED, sc.SC_UNIFORM_DT])
+def test_e1_layout_matches_reference(ts):
+    """The scalar-wave test layout of Sec. IV.A at a coarse resolution (periodic
+    [-6,6]^3 of 24 cells, refined boxes over [-4,4]^3 and [-1,1]^3) with the
+    spherical Gaussian, both time-stepping modes."""
+    spec = config_e1(24)
+    kw = dict(min_block=8, max_block=16)
+    ctx = _gpu(spec, time_stepping=ts, **kw)
+    ref = OracleRun(Hierarchy(spec, **kw), sigma=0.32, subcycling=ts == sc.SC_SUBCYCLED)
+    for l in range(spec.nlevels):
+        for v, f in enumerate(spherical_gaussian_on_spec(spec, l, 0.0)):
+            ctx.set_initial_data(0, l, v, f)
+            ref.set_data(l, v, f)
+    n = 2 if ts == sc.SC_SUBCYCLED else 8
+    ctx.advance(n)
+    ref.advance(n)
+    print("e1 layout worst rel diff", _compare_all(ctx, ref, arrays=("y", "k1")))

@@ -263,3 +263,22 @@ def test_f64_conversion():
             wf = dense.ghost_weights_f64(s, th)
             for a, b in zip(w, wf):
                 assert b == float(a)
+
+
+def test_aligned_weights_are_the_rk4_stages_on_a_linear_problem():
+    """Uniform time steps: on y' = z y (H = 1, y_n = 1) the weights must give
+    the classical RK4 stage vectors Y_s = 1 + c_s z Y_{s-1}, and stage 5 the
+    RK4 amplification 1 + z + z^2/2 + z^3/6 + z^4/24, for any z."""
+    from oracle.dense import aligned_weights
+    for z in (F(1, 3), F(-2, 7), F(5, 2)):
+        # brute force: the four stage slopes of RK4 on y' = z y
+        Y = [F(1)]
+        k = [z * Y[0]]
+        for c in (F(1, 2), F(1, 2), F(1)):
+            Y.append(1 + c * k[-1])
+            k.append(z * Y[-1])
+        for s in range(1, 5):
+            w = aligned_weights(s)
+            assert 1 + sum(wi * ki for wi, ki in zip(w, k)) == Y[s - 1]
+        w = aligned_weights(5)
+        assert 1 + sum(wi * ki for wi, ki in zip(w, k)) == 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24

@@ -185,3 +185,69 @@ def test_two_level_agrees_with_unigrid_fine_to_truncation():
                      np.abs(d[::4, ::4, ::4]).max())
     assert diffs[1] > 0
     assert 8.0 < diffs[0] / diffs[1] < 40.0, diffs
+
+
+# --- uniform time steps (the paper's comparison mode, Sec. IV.A) ------------
+
+def _uniform_run(spec, nsteps, sigma=0.32, **hk):
+    run = OracleRun(Hierarchy(spec, **hk), sigma=sigma, subcycling=False)
+    for l in range(spec.nlevels):
+        u, p = gaussian_on_spec(spec, l)
+        run.set_data(l, 0, u)
+        run.set_data(l, 1, p)
+    run.advance(nsteps)
+    return run
+
+
+def test_uniform_dt_full_cover_equals_single_level_fine():
+    """Every level takes the finest step once per parent step: with the fine
+    level covering the periodic domain, the fine level is a unigrid run with
+    one step per coarse step and the coarse level its injection."""
+    n = 12
+    spec = HierarchySpec((-1.0,) * 3, 2.0 / n, (n,) * 3, (True,) * 3,
+                         [[((0, 0, 0), (2 * n - 1,) * 3)]])
+    two = _uniform_run(spec, 5, min_block=4, max_block=12)
+    assert two.dt[0] == two.dt[1] == 0.25 * 2.0 / (2 * n)
+    fine_spec = single_level(2 * n)
+    one = OracleRun(Hierarchy(fine_spec, min_block=6, max_block=12), sigma=0.32)
+    u, p = gaussian_on_spec(fine_spec, 0)
+    one.set_data(0, 0, u)
+    one.set_data(0, 1, p)
+    one.advance(5)
+    for v in range(2):
+        assert np.array_equal(two.get(1, v), one.get(0, v))
+        assert np.array_equal(two.get(0, v), one.get(0, v).reshape((2 * n,) * 3)[::2, ::2, ::2]
+                              .ravel())
+
+
+def test_uniform_dt_agrees_with_unigrid_fine_to_truncation():
+    """The fine level of a two-level uniform-step run differs from a unigrid
+    fine run only through the coarse solution behind its refinement boundary:
+    the difference falls by about 2^4 under refinement."""
+    diffs = []
+    for nc in (16, 32):
+        ncoarse = nc // 4     # t = 0.125 on the fine step
+        two = _uniform_run(config_c2(nc), 2 * ncoarse, max_block=256)
+        n1 = nc + 1
+        d = two.get(1, 0).reshape((n1,) * 3) - _unigrid_fine(nc, ncoarse)
+        diffs.append(np.abs(d[::2, ::2, ::2]).max() if nc == 16 else
+                     np.abs(d[::4, ::4, ::4]).max())
+    assert diffs[1] > 0
+    assert 8.0 < diffs[0] / diffs[1] < 40.0, diffs
+
+
+def test_uniform_dt_and_subcycling_agree_to_truncation():
+    """Both schedules converge to the same solution: their difference on the
+    fine level falls by about 2^4 under refinement."""
+    diffs = []
+    for nc in (16, 32):
+        ncoarse = nc // 4
+        sub = _two_level_run(config_c2(nc), ncoarse, max_block=256)
+        uni = _uniform_run(config_c2(nc), 2 * ncoarse, max_block=256)
+        assert abs(sub.t[1] - uni.t[1]) < 1e-15 and abs(sub.t[0] - uni.t[0]) < 1e-15
+        n1 = nc + 1
+        d = (sub.get(1, 0) - uni.get(1, 0)).reshape((n1,) * 3)
+        diffs.append(np.abs(d[::2, ::2, ::2]).max() if nc == 16 else
+                     np.abs(d[::4, ::4, ::4]).max())
+    assert diffs[1] > 0
+    assert 8.0 < diffs[0] / diffs[1] < 40.0, diffs

@@ -171,3 +171,32 @@ def brill_lindquist(x, y, z, m: float = 0.5, c: float = 3.0):
 def brill_lindquist_on_spec(spec: HierarchySpec, level: int, m: float = 0.5, c: float = 3.0):
     x, y, z = canonical_coords(spec, level)
     return brill_lindquist(x, y, z, m, c)
+
+
+# ---------------------------------------------------------------------------
+# The paper's scalar-wave test (Sec. IV.A): an outgoing spherical Gaussian.
+
+E1_AMPLITUDE = 1.0
+E1_SIGMA = 0.25 / math.sqrt(2.0)
+
+
+def spherical_gaussian(t: float, x, y, z, A: float = E1_AMPLITUDE, sigma: float = E1_SIGMA):
+    """Exact solution u = (f(t-r) - f(t+r))/r, Pi = du/dt of the scalar wave,
+    f(v) = A exp(-v^2 / (2 sigma^2)); at r = 0 the limits -2 f'(t) and
+    -2 (t f(t))' / sigma^2 are used."""
+    r = np.sqrt(x * x + y * y + z * z)
+    s2 = sigma * sigma
+    f = lambda v: A * np.exp(-v * v / (2.0 * s2))
+    small = r < 1e-9
+    rs = np.where(small, 1.0, r)
+    u = (f(t - rs) - f(t + rs)) / rs
+    p = -(f(t - rs) * (t - rs) - f(t + rs) * (t + rs)) / (s2 * rs)
+    ft = A * math.exp(-t * t / (2.0 * s2))
+    u = np.where(small, 2.0 * t / s2 * ft, u)
+    p = np.where(small, 2.0 * ft * (1.0 - t * t / s2) / s2, p)
+    return u, p
+
+
+def spherical_gaussian_on_spec(spec: HierarchySpec, level: int, t: float = 0.0):
+    x, y, z = canonical_coords(spec, level)
+    return list(spherical_gaussian(t, x, y, z))

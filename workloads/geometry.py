@@ -11,6 +11,7 @@ distinct vertices) and [0, N0] in a non-periodic one.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 from typing import List, Sequence, Tuple
 
@@ -159,3 +160,22 @@ def config_z4c_small(n0: int = 24, nlev: int = 3, half: float = 16.0, nt: int = 
     origin = (-half, -half + dfine / 2, -half + dfine / 2)
     return tower_family(n0, n0, half, nt, 3.0, nlev, origin, False,
                         name=f"z4c-{nlev}level-towers-{n0}^3")
+
+
+def config_e1(n0: int = 375, half: float = 6.0, radii=(4.0, 1.0)) -> HierarchySpec:
+    """The paper's scalar-wave test layout (Sec. IV.A): a periodic cube
+    [-half, half]^3 of n0 cells and two refined levels whose boxes cover
+    [-r, r]^3 for r = 4 and 1, each snapped outward to even indices of its
+    parent.  n0 = 375, 450, 540 give the coarse spacings 0.032, 0.032/1.2 and
+    0.032/1.44 on [-6, 6]^3."""
+    dx0 = 2.0 * half / n0
+    levels: List[List[Box]] = []
+    for l, r in enumerate(radii, start=1):
+        dxl = dx0 / (1 << l)
+        a = (half - r) / dxl            # index of x = -r on level l
+        b = (half + r) / dxl            # index of x = +r
+        lo = 2 * math.floor(round(a, 9) / 2)
+        hi = 2 * math.ceil(round(b, 9) / 2)
+        levels.append([((lo,) * 3, (hi,) * 3)])
+    return HierarchySpec((-half,) * 3, dx0, (n0,) * 3, (True,) * 3, levels, 1,
+                         name=f"wave-e1-{n0}^3")
