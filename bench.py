@@ -374,7 +374,8 @@ def main():
                 tuned = json.loads(f.read().strip().splitlines()[-1])["modes"][m]
             for l in range(spec.nlevels):
                 ctx.set_tile_shape(l, tuned["tz_per_level"][l], tuned["grid_per_level"][l],
-                                   tuned["depth_per_level"][l], tuned["slots_per_level"][l])
+                                   tuned["depth_per_level"][l], tuned["slots_per_level"][l],
+                                   tuned["threads_per_level"][l])
         elif m != "per_block" and not args.no_tune:
             ctx.autotune(3)
         shapes = [ctx.tile_shape(l) for l in range(spec.nlevels)]
@@ -386,7 +387,8 @@ def main():
                   "steps": steps, "tz_per_level": [sh["tz"] for sh in shapes],
                   "grid_per_level": [sh["grid"] for sh in shapes],
                   "depth_per_level": [sh["depth"] for sh in shapes],
-                  "slots_per_level": [sh["slots"] for sh in shapes]}
+                  "slots_per_level": [sh["slots"] for sh in shapes],
+                  "threads_per_level": [sh["threads"] for sh in shapes]}
         log(f"{m}: {1e3 * T / steps:.2f} ms/step, {U * steps / T:.4g} updates/s")
         if m in ("batched", "mixed_batched"):
             label = "roofline" if m == "batched" else "roofline_mixed"

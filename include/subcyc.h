@@ -252,26 +252,29 @@ int sc_poison_halos(sc_ctx* ctx);
 
 /* Autotune the batched stencil kernel: for every level, time candidate
  * z-chunk depths of the tile table, persistent grid sizes and the stencil
- * variant (owned points per thread, planes of loads kept in flight ahead of
- * the computed plane: see sc_set_tile_shape) with HIP events
- * (reps launches each, on the bound data) and keep the fastest.  Overwrites
- * the slopes k2 of every level (call it before a run, or between coarse
- * steps of a run whose k2 is not read again).  Invalidates captured graphs.
- * Synchronises the stream. */
+ * variant (threads per workgroup, owned points per thread, planes of loads
+ * kept in flight ahead of the computed plane: see sc_set_tile_shape) with
+ * HIP events (reps times the four stage launches of one RK4 step, on the
+ * bound data) and keep the fastest.  Overwrites the slopes of every level
+ * and the state buffer that the next step writes (call it before a run or
+ * between coarse steps).  Invalidates captured graphs.  Synchronises the
+ * stream. */
 int sc_autotune(sc_ctx* ctx, int32_t reps);
 /* Tile shape of a level: out = {widest tile, tallest tile, z-chunk, persistent
- * workgroups, tiles, planes of loads in flight, points per thread}. */
-int sc_tile_shape(const sc_ctx* ctx, int32_t level, int32_t out[7]);
+ * workgroups, tiles, planes of loads in flight, points per thread, threads per
+ * workgroup}. */
+int sc_tile_shape(const sc_ctx* ctx, int32_t level, int32_t out[8]);
 /* Set a level's stencil tile shape without timing (for instance one found by
  * sc_autotune in an earlier run): z-chunk tz >= 4, persistent workgroups grid
  * (0: the context default, capped at the tile count), planes of loads in
- * flight ahead of the computed plane (depth) and owned points per thread
- * (slots; tiles hold at most 256 slots points), (slots, depth) one of (2, 1),
- * (2, 2), (1, 2).  SC_E_ARG if a value is out of range or the shape
- * gives more tiles than the tile table was sized for.  Invalidates captured
- * graphs; synchronises the stream. */
+ * flight ahead of the computed plane (depth), owned points per thread (slots)
+ * and threads per workgroup (threads; a tile holds at most threads * slots
+ * points), (threads, slots, depth) one of (256, 2, 1), (256, 2, 2),
+ * (256, 1, 2), (512, 2, 1), (512, 2, 2).  SC_E_ARG if a value is out of range
+ * or the shape gives more tiles than the tile table was sized for.
+ * Invalidates captured graphs; synchronises the stream. */
 int sc_set_tile_shape(sc_ctx* ctx, int32_t level, int32_t tz, int32_t grid, int32_t depth,
-                      int32_t slots);
+                      int32_t slots, int32_t threads);
 
 /* Timing of the stencil stage kernel with HIP events recorded on the
  * context's stream around every batched stage launch (eager modes only;

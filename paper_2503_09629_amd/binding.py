@@ -101,7 +101,7 @@ def lib():
             "sc_poison_halos": [P],
             "sc_autotune": [P, i32],
             "sc_tile_shape": [P, i32, P],
-            "sc_set_tile_shape": [P, i32, i32, i32, i32, i32],
+            "sc_set_tile_shape": [P, i32, i32, i32, i32, i32, i32],
             "sc_profile_enable": [P, i32],
             "sc_profile_read": [P, P, P, P],
             "sc_stats": [P, P, P],
@@ -309,12 +309,13 @@ class Context:
         self._check(self.L.sc_autotune(self.ctx, reps))
 
     def tile_shape(self, level: int):
-        out = (ctypes.c_int32 * 7)()
+        out = (ctypes.c_int32 * 8)()
         self._check(self.L.sc_tile_shape(self.ctx, level, out))
-        return dict(zip(("tx", "ty", "tz", "grid", "tiles", "depth", "slots"), list(out)))
+        return dict(zip(("tx", "ty", "tz", "grid", "tiles", "depth", "slots", "threads"), list(out)))
 
-    def set_tile_shape(self, level: int, tz: int, grid: int = 0, depth: int = 1, slots: int = 2):
-        self._check(self.L.sc_set_tile_shape(self.ctx, level, tz, grid, depth, slots))
+    def set_tile_shape(self, level: int, tz: int, grid: int = 0, depth: int = 1, slots: int = 2,
+                       threads: int = 256):
+        self._check(self.L.sc_set_tile_shape(self.ctx, level, tz, grid, depth, slots, threads))
 
     def profile_enable(self, on: bool = True):
         self._check(self.L.sc_profile_enable(self.ctx, int(bool(on))))

@@ -128,22 +128,24 @@ void split_even(int64_t n, int64_t maxlen, std::vector<std::pair<int, int>>* out
 // Largest tile height for tiles at most nxm points wide: at most
 // kStageSlots owned points per thread, an LDS window of at most kWinCap points
 // and at most kRingSlots ring points per thread.
-int tile_ty_cap(int nxm, int slots) {
-  int t = kStageThreads * slots / nxm;
-  t = std::min(t, kWinCap / (nxm + 2 * kG) - 2 * kG);
-  t = std::min(t, (kStageThreads * kRingSlots - 6 * (nxm + 2 * kG)) / 6);
+int tile_ty_cap(int nxm, int slots, int threads) {
+  int t = threads * slots / nxm;
+  t = std::min(t, stage_win_cap(threads) / (nxm + 2 * kG) - 2 * kG);
+  t = std::min(t, (threads * stage_ring_slots(threads) - 6 * (nxm + 2 * kG)) / 6);
   return std::max(t, 1);
 }
 
-// stencil kernel variants: (points per thread, planes of loads in flight)
-bool stage_variant_ok(int slots, int depth) {
+// stencil kernel variants: (threads, points per thread, planes of loads in flight)
+bool stage_variant_ok(int slots, int depth, int threads = 256) {
+  if (threads == 512) return slots == 2 && (depth == 1 || depth == 2);
+  if (threads != 256) return false;
   return (slots == 2 && (depth == 1 || depth == 2)) || (slots == 1 && depth == 2);
 }
 
-bool tile_fits(int nx, int ny, int slots) {
-  return nx >= 1 && ny >= 1 && nx <= kTileMaxX && nx * ny <= kStageThreads * slots &&
-         (nx + 2 * kG) * (ny + 2 * kG) <= kWinCap &&
-         6 * (nx + 2 * kG) + 6 * ny <= kStageThreads * kRingSlots;
+bool tile_fits(int nx, int ny, int slots, int threads) {
+  return nx >= 1 && ny >= 1 && nx <= kTileMaxX && nx * ny <= threads * slots &&
+         (nx + 2 * kG) * (ny + 2 * kG) <= stage_win_cap(threads) &&
+         6 * (nx + 2 * kG) + 6 * ny <= threads * stage_ring_slots(threads);
 }
 
 void tile_region(int box, const int64_t o[3], const int64_t n[3], const TileShape& s,
@@ -152,7 +154,7 @@ void tile_region(int box, const int64_t o[3], const int64_t n[3], const TileShap
   split_even(n[0], std::min(s.tx, kTileMaxX), &sx);
   int nxm = 1;
   for (auto& x : sx) nxm = std::max(nxm, x.second);
-  split_even(n[1], std::min(s.ty, tile_ty_cap(nxm, s.slots)), &sy);
+  split_even(n[1], std::min(s.ty, tile_ty_cap(nxm, s.slots, s.threads)), &sy);
   split_even(n[2], s.tz, &sz);
   // order: y rows of tiles, then z chunks, then x, so that a contiguous run of
   // the table (one XCD's share) is a slab holding whole z stacks: the halo
@@ -452,17 +454,17 @@ std::string validate_layout(const sc_ctx* c) {
   for (size_t l = 0; l < c->lev.size(); ++l) {
     const LevelDev& L = c->lev[l];
     auto in_level = [&](int64_t o) { return o >= 0 && o < L.total; };
-    auto tile_ok = [&](const TileDev& t, int slots) {
+    auto tile_ok = [&](const TileDev& t, int slots, int threads) {
       if (t.box < 0 || t.box >= (int)L.boxes.size()) return false;
       const BoxDev& B = L.boxes[t.box];
-      return tile_fits(t.nx, t.ny, slots) && t.nz >= 1 && (t.dir == 0 || t.dir == 1) &&
+      return tile_fits(t.nx, t.ny, slots, threads) && t.nz >= 1 && (t.dir == 0 || t.dir == 1) &&
              t.x0 >= 0 && t.y0 >= 0 && t.z0 >= 0 && t.x0 + t.nx <= B.nx &&
              t.y0 + t.ny <= B.ny && t.z0 + t.nz <= B.nz;
     };
     for (const TileDev& t : L.tiles)
-      if (!tile_ok(t, L.shape.slots)) return "tile outside its box";
+      if (!tile_ok(t, L.shape.slots, L.shape.threads)) return "tile outside its box";
     for (const TileDev& t : L.btiles)
-      if (!tile_ok(t, kStageSlotsMax)) return "block tile outside its box";
+      if (!tile_ok(t, kStageSlotsMax, kStageThreads)) return "block tile outside its box";
     for (const BoxDev& B : L.boxes)
       if (!in_level(B.base) ||
           B.base + (int64_t)B.px * B.py * (B.nz + 2 * kG) > L.total)
@@ -655,7 +657,8 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
       if (rc) return rc;
       HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    HIPCHK(c, launch_stage(a, grid, c->mixed, L.shape.depth, L.shape.slots, c->stream));
+    HIPCHK(c, launch_stage(a, grid, c->mixed, L.shape.depth, L.shape.slots, L.shape.threads,
+                           c->stream));
     if (c->profiling) {
       HIPCHK(c, hipEventRecord(e1, c->stream));
       // algorithmic bytes per owned point and variable: the stencil operands
@@ -673,7 +676,7 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
     for (int b = 0; b < nblk; ++b) {
       a.tiles = L.d_btiles + L.btile_start[b];
       a.ntiles = L.btile_start[b + 1] - L.btile_start[b];
-      HIPCHK(c, launch_stage(a, a.ntiles, c->mixed, 1, kStageSlotsMax, c->stream));
+      HIPCHK(c, launch_stage(a, a.ntiles, c->mixed, 1, kStageSlotsMax, kStageThreads, c->stream));
       ++c->launches;
     }
   }
@@ -1435,19 +1438,21 @@ static void drop_graphs(sc_ctx* c) {
 }
 
 int sc_set_tile_shape(sc_ctx* c, int32_t level, int32_t tz, int32_t grid, int32_t depth,
-                      int32_t slots) {
+                      int32_t slots, int32_t threads) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
   if (level < 0 || level >= (int)c->lev.size()) return fail(c, SC_E_ARG, "level out of range");
   if (tz < kTuneTzMin || tz > (1 << 20)) return fail(c, SC_E_ARG, "z-chunk out of range");
   if (grid < 0) return fail(c, SC_E_ARG, "grid must be >= 0");
-  if (!stage_variant_ok(slots, depth))
-    return fail(c, SC_E_ARG, "(points per thread, planes in flight) must be (2, 1), (2, 2) or (1, 2)");
+  if (!stage_variant_ok(slots, depth, threads))
+    return fail(c, SC_E_ARG, "(threads, points per thread, planes in flight) must be (256, 2, 1), "
+                             "(256, 2, 2), (256, 1, 2), (512, 2, 1) or (512, 2, 2)");
   LevelDev& L = c->lev[level];
   TileShape sh = L.shape;
   sh.tz = tz;
   sh.depth = depth;
   sh.slots = slots;
+  sh.threads = threads;
   std::vector<TileDev> tl;
   for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
     const BoxDev& B = L.boxes[ib];
@@ -1484,11 +1489,14 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
     float best = 1e30f;
     TileShape best_shape = L.shape;
     std::vector<TileDev> best_tiles = L.tiles;
+    for (int threads : {256, 512})
     for (int slots : {2, 1})
     for (int tz : kTuneTz) {
+      if (!stage_variant_ok(slots, 2, threads)) continue;
       TileShape sh = L.shape;
       sh.tz = tz;
       sh.slots = slots;
+      sh.threads = threads;
       std::vector<TileDev> tl;
       for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
         const BoxDev& B = L.boxes[ib];
@@ -1500,22 +1508,26 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
       L.tiles = tl;
       for (int depth : {1, 2})
       for (int g : {2 * ncu, 4 * ncu, 8 * ncu, 1 << 30}) {
-        if (!stage_variant_ok(slots, depth)) break;
+        if (!stage_variant_ok(slots, depth, threads)) break;
         sh.grid = std::min<int>(g, (int)tl.size());
         sh.depth = depth;
         L.shape = sh;
-        // stage 2 reads y_n, k1 and the halo table, writes k2
-        rc = enqueue_stage_launches(c, (int)l, 2, false, c->mixed ? (const void*)L.y32[L.cur]
-                                                                  : (const void*)L.y[L.cur],
-                                    L.k[0], L.Yh[0]);
-        if (rc) return rc;
+        // one RK4 step's four stage launches on the bound data (stage s reads
+        // y_n, k_{s-1} and a halo table, writes k_s; stage 4 writes the
+        // state buffer the next step writes anyway)
+        const void* yn = c->mixed ? (const void*)L.y32[L.cur] : (const void*)L.y[L.cur];
+        auto rk_stages = [&]() -> int {
+          for (int st = 1; st <= 4; ++st) {
+            const int r2 = enqueue_stage_launches(c, (int)l, st, false, yn,
+                                                  st == 1 ? nullptr : L.k[st - 2], L.Yh[0]);
+            if (r2) return r2;
+          }
+          return SC_OK;
+        };
+        if ((rc = rk_stages())) return rc;
         HIPCHK(c, hipEventRecord(e0, c->stream));
-        for (int r = 0; r < reps; ++r) {
-          rc = enqueue_stage_launches(c, (int)l, 2, false,
-                                      c->mixed ? (const void*)L.y32[L.cur] : (const void*)L.y[L.cur],
-                                      L.k[0], L.Yh[0]);
-          if (rc) return rc;
-        }
+        for (int r = 0; r < reps; ++r)
+          if ((rc = rk_stages())) return rc;
         HIPCHK(c, hipEventRecord(e1, c->stream));
         HIPCHK(c, hipEventSynchronize(e1));
         float ms = 0.f;
@@ -1540,7 +1552,7 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
   return SC_OK;
 }
 
-int sc_tile_shape(const sc_ctx* c, int32_t level, int32_t out[7]) {
+int sc_tile_shape(const sc_ctx* c, int32_t level, int32_t out[8]) {
   int rc = check_ready(c, 1);
   if (rc) return rc;
   if (level < 0 || level >= (int)c->lev.size() || !out) return SC_E_ARG;
@@ -1556,6 +1568,7 @@ int sc_tile_shape(const sc_ctx* c, int32_t level, int32_t out[7]) {
   out[4] = (int32_t)L.tiles.size();
   out[5] = L.shape.depth;
   out[6] = L.shape.slots;
+  out[7] = L.shape.threads;
   return SC_OK;
 }
 

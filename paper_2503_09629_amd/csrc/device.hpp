@@ -164,9 +164,10 @@ struct PackArgs {
 };
 
 // launchers (kernels.hip); `f32` selects FP32 stencil operands / arrays
-// depth: planes of loads in flight (1 or 2); slots: owned points per thread (1 or 2),
-// which the tiles must have been cut for
-hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int depth, int slots, hipStream_t s);
+// depth: planes of loads in flight (1 or 2); slots: owned points per thread (1 or 2);
+// threads: 256 or 512 per workgroup; the tiles must have been cut for slots and threads
+hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int depth, int slots, int threads,
+                        hipStream_t s);
 hipError_t launch_sync(const SyncArgs& a, bool f32, hipStream_t s);
 // k_f32: parent slopes are FP32; out_f32: outputs are FP32
 hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s);
@@ -182,11 +183,17 @@ hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, void
                           hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 
-constexpr int kStageThreads = 256;
-constexpr int kStageSlotsMax = 2; // owned points per thread and plane of a stencil tile (1 or 2)
-constexpr int kRingSlots = 2;     // ring points per thread and plane
-constexpr int kWinCap = 1024;     // LDS window points per variable and plane: (nx+6)(ny+6)
-constexpr int kWinStride = kWinCap + 8;   // per-variable LDS stride: window plus a spare slot
+// Stencil-kernel workgroup families: threads, ring points per thread and plane,
+// and LDS window capacity per variable and plane ((nx+6)(ny+6) points).  The
+// wide family runs one larger tile per CU: a smaller ring per owned point and
+// fewer tiles sharing each XCD's L2.
+template <int NT> struct StageFamily;
+template <> struct StageFamily<256> { static constexpr int ring = 2, wincap = 1024; };
+template <> struct StageFamily<512> { static constexpr int ring = 1, wincap = 1600; };
+constexpr int kStageThreads = 256;   // the default family (per-block mode uses it)
+constexpr int kStageSlotsMax = 2;    // owned points per thread and plane of a stencil tile (1 or 2)
+inline int stage_ring_slots(int threads) { return threads == 512 ? 1 : 2; }
+inline int stage_win_cap(int threads) { return threads == 512 ? 1600 : 1024; }
 constexpr int kTileMaxX = 64;     // tile width (the Z4c kernels map one lane per x)
 
 }  // namespace sc

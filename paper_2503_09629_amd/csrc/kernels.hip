@@ -87,12 +87,13 @@ struct StageRaw {   // raw loads of one ring plane and one column plane
   TS ca[2][S], ck[2][S];
 };
 
-template <int STAGE, typename TS, int DEPTH, int S, bool WK>
+template <int STAGE, typename TS, int DEPTH, int S, bool WK, int NT>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T, const BoxDev& B,
                                            TS* lds) {
-  constexpr int RM = kRingSlots;
+  constexpr int RM = StageFamily<NT>::ring;
+  constexpr int kWinCap = StageFamily<NT>::wincap;
+  constexpr int kWinStride = kWinCap + 8;   // per-variable LDS stride: window plus a spare slot
   constexpr int QN = 2 * kG + 1;   // z column: planes z-3 .. z+3 along DZ
-  constexpr int NT = kStageThreads;
   const TS clap = TS(a.clap), cko = TS(a.cko), cdt = TS(a.cdt);
   const char* yn = static_cast<const char*>(a.yn);
   const char* kp = static_cast<const char*>(a.kprev);
@@ -289,9 +290,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
 
 // Persistent stage kernel: workgroups stride over the tile list; a tile's
 // dir field picks its z marching direction.
-template <int STAGE, typename TS, int DEPTH, int S, bool WK>
-__global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
-  __shared__ TS lds[2 * 2 * kWinStride];
+template <int STAGE, typename TS, int DEPTH, int S, bool WK, int NT>
+__global__ __launch_bounds__(NT) void k_wave_stage(StageArgs a) {
+  __shared__ TS lds[2 * 2 * (StageFamily<NT>::wincap + 8)];
   // consecutive workgroups land on different XCDs (round robin over 8); give
   // each XCD a contiguous run of tiles so neighbouring tiles share its L2
   const int g = (gridDim.x % 8 == 0)
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(kStageThreads) void k_wave_stage(StageArgs a) {
   for (int t = g; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
-    stage_tile<STAGE, TS, DEPTH, S, WK>(a, T, B, lds);
+    stage_tile<STAGE, TS, DEPTH, S, WK, NT>(a, T, B, lds);
   }
 }
 
@@ -705,38 +706,43 @@ __global__ __launch_bounds__(256) void k_to_f32(const double* src, float* dst, i
 
 inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-template <typename TS, int DEPTH, int S>
+template <typename TS, int DEPTH, int S, int NT>
 void stage_dispatch(const StageArgs& a, dim3 g, hipStream_t s) {
-  const dim3 b(kStageThreads);
+  const dim3 b(NT);
   switch (a.stage) {
-    case 1: hipLaunchKernelGGL((k_wave_stage<1, TS, DEPTH, S, true>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_wave_stage<2, TS, DEPTH, S, true>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_wave_stage<3, TS, DEPTH, S, true>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_wave_stage<1, TS, DEPTH, S, true, NT>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_wave_stage<2, TS, DEPTH, S, true, NT>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_wave_stage<3, TS, DEPTH, S, true, NT>), g, b, 0, s, a); break;
     default:
-      if (a.write_k) hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, false>), g, b, 0, s, a);
+      if (a.write_k) hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, true, NT>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, false, NT>), g, b, 0, s, a);
       break;
   }
 }
 
-// (points per thread, planes in flight): (2, 1), (2, 2), (1, 2)
+// (threads, points per thread, planes in flight): (256, 2, 1), (256, 2, 2),
+// (256, 1, 2), (512, 2, 1), (512, 2, 2)
 template <typename TS>
-void stage_variant(const StageArgs& a, dim3 g, int depth, int slots, hipStream_t s) {
-  if (slots == 1) {
-    stage_dispatch<TS, 2, 1>(a, g, s);
+void stage_variant(const StageArgs& a, dim3 g, int depth, int slots, int threads, hipStream_t s) {
+  if (threads == 512) {
+    if (depth == 2) stage_dispatch<TS, 2, 2, 512>(a, g, s);
+    else stage_dispatch<TS, 1, 2, 512>(a, g, s);
+  } else if (slots == 1) {
+    stage_dispatch<TS, 2, 1, 256>(a, g, s);
   } else {
-    if (depth == 2) stage_dispatch<TS, 2, 2>(a, g, s);
-    else stage_dispatch<TS, 1, 2>(a, g, s);
+    if (depth == 2) stage_dispatch<TS, 2, 2, 256>(a, g, s);
+    else stage_dispatch<TS, 1, 2, 256>(a, g, s);
   }
 }
 
 }  // namespace
 
-hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int depth, int slots, hipStream_t s) {
+hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int depth, int slots, int threads,
+                        hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g(grid > 0 ? grid : a.ntiles);
-  if (f32) stage_variant<float>(a, g, depth, slots, s);
-  else stage_variant<double>(a, g, depth, slots, s);
+  if (f32) stage_variant<float>(a, g, depth, slots, threads, s);
+  else stage_variant<double>(a, g, depth, slots, threads, s);
   return hipGetLastError();
 }
 

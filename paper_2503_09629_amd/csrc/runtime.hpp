@@ -16,7 +16,8 @@ struct TileShape {
   int tx = kTileMaxX, ty = 1 << 20, tz = 16;   // tx, ty: caps on the tile width and height
   int grid = 0;   // persistent workgroups for the batched stage kernel (0: context default)
   int depth = 1;  // stage kernel: planes of loads in flight ahead of the computed plane
-  int slots = 2;  // owned points per stage-kernel thread (tiles of at most 256 slots points)
+  int slots = 2;  // owned points per stage-kernel thread (tiles of at most threads * slots points)
+  int threads = 256;  // stage-kernel workgroup size (256 or 512)
 };
 
 // z-chunk depths the autotuner tries; the tile table region is sized for the

@@ -214,7 +214,7 @@ def test_pinned_tile_shapes_bitwise_equal(mixed):
     spec = config_c3(64, nlev=4)
     prec = sc.SC_MIXED if mixed else sc.SC_FP64
     shapes = [None, (4, 0, 2, 1), (7, 0, 2, 2), (12, 64, 1, 2), (1 << 20, 0, 2, 1), (5, 16, 2, 1),
-              (9, 0, 2, 2), (6, 24, 1, 2)]
+              (9, 0, 2, 2), (6, 24, 1, 2), (8, 0, 2, 2, 512), (13, 16, 1, 2, 512), (5, 0, 1, 2, 512)]
     outs = []
     for sh in shapes:
         ctx = _gpu(spec, precision=prec)
@@ -226,6 +226,7 @@ def test_pinned_tile_shapes_bitwise_equal(mixed):
                 ctx.set_tile_shape(l, *sh)
                 got = ctx.tile_shape(l)
                 assert (got["tz"], got["depth"], got["slots"]) == (sh[0], sh[2], sh[3])
+                assert got["threads"] == (sh[4] if len(sh) > 4 else 256)
         ctx.advance(2)
         outs.append([ctx.read_back(0, l, v) for l in range(spec.nlevels) for v in range(2)])
         ctx.close()
@@ -241,7 +242,8 @@ def test_set_tile_shape_rejects_bad_arguments():
         for v, f in enumerate(pulses_on_spec(spec, l)):
             ctx.set_initial_data(0, l, v, f)
     for args in ((0, 3, 0, 1, 2), (0, 8, -1, 1, 2), (0, 8, 0, 3, 2), (0, 8, 0, 1, 4), (5, 8, 0, 1, 2),
-                 (0, 8, 0, 1, 1), (0, 8, 0, 4, 2), (0, 8, 0, 4, 1)):
+                 (0, 8, 0, 1, 1), (0, 8, 0, 4, 2), (0, 8, 0, 4, 1), (0, 8, 0, 2, 1, 512),
+                 (0, 8, 0, 2, 2, 384)):
         with pytest.raises(sc.ScError):
             ctx.set_tile_shape(*args)
     ctx.set_tile_shape(0, 8, 0, 2, 1)
