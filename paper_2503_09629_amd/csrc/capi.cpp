@@ -558,7 +558,7 @@ void plan_arena(sc_ctx* c) {
     for (int i = 0; i < 2; ++i) L.o_y32[i] = c->mixed ? take(arr / 2) : 0;
     for (int i = 0; i < 4; ++i) L.o_k[i] = take(arrs);
     for (int i = 0; i < L.nyh; ++i) L.o_yh[i] = take(arrs);
-    L.o_ys = c->cfg.rhs == SC_RHS_Z4C ? take(arr) : 0;
+    L.o_ys = c->cfg.rhs == SC_RHS_Z4C ? take(sizeof(double) * (size_t)kZ4cScratch * (size_t)L.total) : 0;
     L.o_boxes = take(sizeof(BoxDev) * L.boxes.size());
     L.o_prefix = take(sizeof(int64_t) * L.prefix.size());
     L.o_sync = take(sizeof(SyncEntry) * L.sync.size());
@@ -718,6 +718,7 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
   a.kout = L.k[stage - 1];
   a.ynew = L.y[1 - L.cur];
   a.ynew32 = c->mixed ? L.y32[1 - L.cur] : nullptr;
+  a.geo = L.Ys;   // kZ4cScratch arrays of double: room for the curvature arrays in either precision
   Z4cCombineArgs cb{};
   cb.nvars = c->nvars;
   cb.boxes = L.d_boxes;

@@ -79,8 +79,14 @@ struct Pt {
   }
 };
 
+// Curvature pass (one point): the Ricci tensor R_ij, D_i D_j alpha, the
+// contracted conformal Christoffels Gt^i, Gt^i_jk At^jk and the shift's
+// gt^jk d_j d_k beta^i and d_i (d_k beta^k), written to the per-point scratch
+// (24 values: R and D_i D_j alpha in symmetric order, then Gt^i,
+// Gt^i_jk At^jk, gt^jk d_j d_k beta^i, d_i d_k beta^k), or the Hamiltonian
+// constraint.
 template <typename TS>
-__device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ham_out) {
+__device__ void z4c_geom(const Pt<TS>& p, const Z4cArgs& a, TS* out, double* ham_out) {
   const TS h = TS(a.h);
   const TS c1 = TS(1.0) / (TS(12.0) * h), c2 = TS(1.0) / (TS(12.0) * h * h);
   TS v[NV], d[NV][3];
@@ -90,7 +96,7 @@ __device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ha
 #pragma unroll
     for (int k = 0; k < 3; ++k) d[i][k] = p.d1(i, k, c1);
   }
-  const TS W = v[VW], Kh = v[VKH], Th = v[VTH], alp = v[VALP];
+  [[maybe_unused]] const TS W = v[VW], Kh = v[VKH], Th = v[VTH], alp = v[VALP];
   TS gt[3][3], At[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -170,27 +176,6 @@ __device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ha
       dda[k][l] = p.dd(VALP, k, l, c1, c2);
       dda[l][k] = dda[k][l];
     }
-  // shift: gt^jk d_j d_k beta^i and d_j (d_k beta^k)
-  TS lapb[3], gdivb[3] = {TS(0.0), TS(0.0), TS(0.0)};
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    TS dd[3][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int l = k; l < 3; ++l) {
-        dd[k][l] = p.dd(VB + i, k, l, c1, c2);
-        dd[l][k] = dd[k][l];
-      }
-    TS s = TS(0.0);
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) s += gu[j][k] * dd[j][k];
-    lapb[i] = s;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) gdivb[j] += dd[j][i];
-  }
   // Ricci tensor R_ij = R^W_ij + Rt_ij
   const TS dW[3] = {d[VW][0], d[VW][1], d[VW][2]};
   TS DDW[3][3], lapW = TS(0.0), dWsq = TS(0.0);
@@ -276,7 +261,7 @@ __device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ha
     for (int l = 0; l < 3; ++l) s += gu[k][l] * dW[l];
     gudW[k] = s;
   }
-  TS DDa[3][3], lapa = TS(0.0);
+  TS DDa[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -290,11 +275,140 @@ __device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ha
       }
       DDa[i][j] = s;
     }
+  TS t2[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    TS s = TS(0.0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s += G[i][j][k] * Atu[j][k];
+    t2[i] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      out[sym(i, j)] = R[i][j];
+      out[6 + sym(i, j)] = DDa[i][j];
+    }
+  // shift: gt^jk d_j d_k beta^i and d_j (d_k beta^k)
+  TS lapb[3], gdivb[3] = {TS(0.0), TS(0.0), TS(0.0)};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    TS dd[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = k; l < 3; ++l) {
+        dd[k][l] = p.dd(VB + i, k, l, c1, c2);
+        dd[l][k] = dd[k][l];
+      }
+    TS s = TS(0.0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s += gu[j][k] * dd[j][k];
+    lapb[i] = s;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gdivb[j] += dd[j][i];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    out[12 + i] = Gd[i];
+    out[15 + i] = t2[i];
+    out[18 + i] = lapb[i];
+    out[21 + i] = gdivb[i];
+  }
+}
+
+// Evolution pass (one point): every right-hand side except advection and
+// dissipation, from the curvature scratch of the same point.
+// geo(c) returns curvature value c of the point (the order z4c_geom writes).
+template <typename TS, typename Geo>
+__device__ void z4c_evol(const Pt<TS>& p, const Z4cArgs& a, const Geo& geo, TS* rhs) {
+  const TS h = TS(a.h);
+  const TS c1 = TS(1.0) / (TS(12.0) * h);
+  TS v[NV], d[NV][3];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    v[i] = p.at(i, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[i][k] = p.d1(i, k, c1);
+  }
+  [[maybe_unused]] const TS W = v[VW], Kh = v[VKH], Th = v[VTH], alp = v[VALP];
+  TS gt[3][3], At[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      gt[i][j] = v[VG + sym(i, j)];
+      At[i][j] = v[VA + sym(i, j)];
+    }
+  const TS det = gt[0][0] * (gt[1][1] * gt[2][2] - gt[1][2] * gt[2][1]) -
+                     gt[0][1] * (gt[1][0] * gt[2][2] - gt[1][2] * gt[2][0]) +
+                     gt[0][2] * (gt[1][0] * gt[2][1] - gt[1][1] * gt[2][0]);
+  TS gu[3][3];
+  gu[0][0] = (gt[1][1] * gt[2][2] - gt[1][2] * gt[2][1]) / det;
+  gu[0][1] = (gt[0][2] * gt[2][1] - gt[0][1] * gt[2][2]) / det;
+  gu[0][2] = (gt[0][1] * gt[1][2] - gt[0][2] * gt[1][1]) / det;
+  gu[1][1] = (gt[0][0] * gt[2][2] - gt[0][2] * gt[2][0]) / det;
+  gu[1][2] = (gt[0][2] * gt[1][0] - gt[0][0] * gt[1][2]) / det;
+  gu[2][2] = (gt[0][0] * gt[1][1] - gt[0][1] * gt[1][0]) / det;
+  gu[1][0] = gu[0][1];
+  gu[2][0] = gu[0][2];
+  gu[2][1] = gu[1][2];
+  TS R[3][3], DDa[3][3], Gd[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      R[i][j] = geo(sym(i, j));
+      DDa[i][j] = geo(6 + sym(i, j));
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Gd[i] = geo(12 + i);
+  TS lapb[3], gdivb[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    lapb[i] = geo(18 + i);
+    gdivb[i] = geo(21 + i);
+  }
+  const TS dW[3] = {d[VW][0], d[VW][1], d[VW][2]};
+  const TS da[3] = {d[VALP][0], d[VALP][1], d[VALP][2]};
+  TS Rs = TS(0.0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Rs += gu[i][j] * R[i][j];
+  Rs *= W * W;
+  TS lapa = TS(0.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) lapa += gu[i][j] * DDa[i][j];
   lapa *= W * W;
+  // raised At
+  TS Atu[3][3], Atm[3][3], AtA = TS(0.0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      TS s = TS(0.0), m = TS(0.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        m += gu[i][k] * At[k][j];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) s += gu[i][k] * gu[j][l] * At[k][l];
+      }
+      Atu[i][j] = s;
+      Atm[i][j] = m;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) AtA += At[i][j] * Atu[i][j];
+  const TS Kt = Kh + TS(2.0) * Th;
   const TS beta[3] = {v[VB], v[VB + 1], v[VB + 2]};
   TS divb = TS(0.0);
 #pragma unroll
@@ -326,7 +440,8 @@ __device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ha
              alp * TS(a.kappa1) * (TS(1.0) - TS(a.kappa2)) * Th;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    TS t1 = TS(0.0), t2 = TS(0.0), t3 = TS(0.0), t4 = TS(0.0), t6 = TS(0.0), t7 = TS(0.0);
+    TS t1 = TS(0.0), t3 = TS(0.0), t4 = TS(0.0), t6 = TS(0.0), t7 = TS(0.0);
+    const TS t2 = geo(15 + i);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       t1 += Atu[i][j] * da[j];
@@ -334,8 +449,6 @@ __device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ha
       t4 += gu[i][j] * (TS(2.0) * d[VKH][j] + d[VTH][j]);
       t6 += gu[i][j] * gdivb[j];
       t7 += Gd[j] * d[VB + i][j];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) t2 += G[i][j][k] * Atu[j][k];
     }
     rhs[VGAM + i] = -TS(2.0) * t1 + TS(2.0) * alp * (t2 - TS(3.0) * t3 - (TS(1.0) / TS(3.0)) * t4) +
                     lapb[i] + (TS(1.0) / TS(3.0)) * t6 - t7 + (TS(2.0) / TS(3.0)) * Gd[i] * divb -
@@ -356,13 +469,11 @@ __device__ void z4c_point(const Pt<TS>& p, const Z4cArgs& a, TS* rhs, double* ha
   // the advection terms beta^k d_k and the dissipation are added by k_z4c_advko
 }
 
-// Curvature, gauge and constraint-damping terms of the right-hand side (no
-// advection, no dissipation), or the Hamiltonian constraint.
-template <typename TS>
-__global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
+// One thread per owned point of the tiles: calls point(p) for each.
+template <typename TS, typename F>
+__device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
   const int tx = threadIdx.x % kTileMaxX, ty = threadIdx.x / kTileMaxX;
   constexpr int BY = kZ4cThreads / kTileMaxX;
-  TS* kout = static_cast<TS*>(a.kout);
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
@@ -378,21 +489,52 @@ __global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
         p.px = B.px;
         p.pxy = (int64_t)B.px * B.py;
         p.o = B.base + ((int64_t)(p.z + kG) * B.py + (p.y + kG)) * (int64_t)B.px + (p.x + kG);
-        if constexpr (sizeof(TS) == 8) {
-          if (a.ham) {
-            double hm;
-            z4c_point<TS>(p, a, nullptr, &hm);
-            a.ham[p.o] = hm;
-            continue;
-          }
-        }
-        TS rhs[NV];
-        z4c_point<TS>(p, a, rhs, nullptr);
-#pragma unroll
-        for (int i = 0; i < NV; ++i) kout[p.o + i * a.vstride] = rhs[i];
+        point(p);
       }
     }
   }
+}
+
+// Curvature pass into the per-point scratch, or the Hamiltonian constraint.
+template <typename TS>
+__global__ __launch_bounds__(kZ4cThreads) void k_z4c_geom(Z4cArgs a) {
+  TS* geo = static_cast<TS*>(a.geo);
+  z4c_points<TS>(a, [&](const Pt<TS>& p) {
+    if constexpr (sizeof(TS) == 8) {
+      if (a.ham) {
+        double hm;
+        z4c_geom<TS>(p, a, nullptr, &hm);
+        a.ham[p.o] = hm;
+        return;
+      }
+    }
+    TS g[kZ4cGeo];
+    z4c_geom<TS>(p, a, g, nullptr);
+#pragma unroll
+    for (int c = 0; c < kZ4cGeo; ++c) geo[p.o + c * a.vstride] = g[c];
+  });
+}
+
+// Gauge, constraint-damping and source terms of the right-hand side (no
+// advection, no dissipation) from the curvature scratch.
+// FUSED: the curvature pass runs in the same thread and hands its values over
+// in registers (no scratch traffic, more registers live).
+template <typename TS, bool FUSED>
+__global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
+  TS* kout = static_cast<TS*>(a.kout);
+  z4c_points<TS>(a, [&](const Pt<TS>& p) {
+    TS rhs[NV];
+    if constexpr (FUSED) {
+      TS g[kZ4cGeo];
+      z4c_geom<TS>(p, a, g, nullptr);
+      z4c_evol<TS>(p, a, [&](int c) -> TS { return g[c]; }, rhs);
+    } else {
+      const TS* geo = static_cast<const TS*>(a.geo);
+      z4c_evol<TS>(p, a, [&](int c) -> TS { return geo[p.o + c * a.vstride]; }, rhs);
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) kout[p.o + i * a.vstride] = rhs[i];
+  });
 }
 
 // Completes k_s: adds the advection terms beta^k d_k Y (centred fourth-order
@@ -480,16 +622,19 @@ __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
 
 hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, bool f32, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
-  const dim3 g(grid > 0 ? grid : a.ntiles);
+  const dim3 g(grid > 0 ? grid : a.ntiles), b(kZ4cThreads), b2(256);
   if (f32) {
-    hipLaunchKernelGGL(k_z4c_stage<float>, g, dim3(kZ4cThreads), 0, s, a);
-    if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, float>), g, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_z4c_advko<1, float>), g, dim3(256), 0, s, a);
+    // FP32: the fused kernel fits the register file; FP64: two passes, since
+    // one would spill
+    hipLaunchKernelGGL((k_z4c_stage<float, true>), g, b, 0, s, a);
+    if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, float>), g, b2, 0, s, a);
+    else hipLaunchKernelGGL((k_z4c_advko<1, float>), g, b2, 0, s, a);
   } else {
-    hipLaunchKernelGGL(k_z4c_stage<double>, g, dim3(kZ4cThreads), 0, s, a);
+    hipLaunchKernelGGL(k_z4c_geom<double>, g, b, 0, s, a);
     if (!a.ham) {
-      if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, double>), g, dim3(256), 0, s, a);
-      else hipLaunchKernelGGL((k_z4c_advko<1, double>), g, dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_z4c_stage<double, false>), g, b, 0, s, a);
+      if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, double>), g, b2, 0, s, a);
+      else hipLaunchKernelGGL((k_z4c_advko<1, double>), g, b2, 0, s, a);
     }
   }
   return hipGetLastError();

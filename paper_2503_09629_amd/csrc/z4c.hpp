@@ -6,6 +6,10 @@
 namespace sc {
 
 constexpr int kZ4cThreads = 128;
+// Curvature values per point that the curvature pass hands to the evolution
+// pass; the level's scratch array holds this many arrays of double.
+constexpr int kZ4cGeo = 24;
+constexpr int kZ4cScratch = kZ4cGeo;
 
 struct Z4cArgs {
   const TileDev* tiles;
@@ -21,6 +25,7 @@ struct Z4cArgs {
   double* ynew;       // FP64 y_{n+1} (stage 4)
   float* ynew32;      // its FP32 shadow (FP32 variant, stage 4)
   double* ham;        // constraint mode (FP64 only): Hamiltonian constraint out, else null
+  void* geo;          // curvature scratch: 24 arrays of TS in the level's padded layout
   int64_t vstride;
   double h, dt6, sigma, kappa1, kappa2, eta_c, eta_o, eta_s;
   double origin[3];   // coordinates of global index (0,0,0) of the level
