@@ -35,6 +35,24 @@ Restriction is injection: y_{l-1}(I) <- y_l(2I) for every restriction pair.
 
 Time steps: dt_l = cfl * dx_l.
 
+Buffer zones (buffer_zones=True; the Carpet scheme of Sec. II and Fig. 1,
+the baseline of the paper's cost comparison; the hierarchy carries buffer
+points, oracle.hierarchy):
+
+  advance_level(l, theta0):
+      if l > 0: prolong the parent's state at t_parent + theta0 H into the
+                RB points and the buffer points (one vector)
+      rk4_step(l)                       # RB ghosts keep that value at every stage
+      if l has a child: advance_level(l+1, 0); advance_level(l+1, 1/2); restrict
+      t_l += dt_l
+
+The parent state at t_n + theta0 H is the Lagrange interpolant in time over
+the parent's last three states y_{n-1}, y_n, y_{n+1} (nodes -H, 0, H), each
+prolonged in space first: theta0 = 0 gives P[y_n]; theta0 = 1/2 gives
+((-1/8 P[y_{n-1}] + 3/4 P[y_n]) + 3/8 P[y_{n+1}]).  Before the parent has a
+y_{n-1} (its first step) the interpolant is linear over y_n, y_{n+1}:
+((0 P[y_n] + 1/2 P[y_n]) + 1/2 P[y_{n+1}]).  Restriction skips buffer points.
+
 Uniform time steps (subcycling=False; the comparison runs of Sec. IV.A):
 every level steps with the finest level's dt, advance_level takes one child
 step per parent step, and the RB ghost of stage s is the parent's stage vector
@@ -125,11 +143,21 @@ class _LevelState:
         return self.base[blk] + ((z + G) * py + (y + G)) * px + (x + G)
 
 
-class _Prolongation:
-    """Gather plan of the five-vector prolongation into one level's RB list."""
+def time_interp_weights(theta: Fraction, history: bool):
+    """Lagrange weights in time at t_n + theta H over the nodes -H, 0, H (three
+    states) or 0, H (two states; the first weight is then 0)."""
+    th = Fraction(theta)
+    if history:
+        return (th * (th - 1) / 2, (1 - th) * (1 + th), th * (th + 1) / 2)
+    return (Fraction(0), 1 - th, th)
 
-    def __init__(self, hier: Hierarchy, l: int, parent: _LevelState):
-        rb = hier.rb[l]
+
+class _Prolongation:
+    """Gather plan of the prolongation into a list of fine points (default:
+    the level's RB list)."""
+
+    def __init__(self, hier: Hierarchy, l: int, parent: _LevelState, pts=None):
+        rb = hier.rb[l] if pts is None else pts
         plev = hier.levels[l - 1]
         self.n = len(rb)
         self.par = np.ascontiguousarray(
@@ -181,9 +209,12 @@ class OracleRun:
     """
 
     def __init__(self, hier: Hierarchy, rhs: str = "wave", sigma: float = 0.32,
-                 cfl: float = 0.25, z4c: dict = None, subcycling: bool = True):
+                 cfl: float = 0.25, z4c: dict = None, subcycling: bool = True,
+                 buffer_zones: bool = False):
         if rhs not in ("wave", "z4c"):
             raise ValueError(rhs)
+        if buffer_zones and (not subcycling or hier.B <= 0):
+            raise ValueError("buffer zones need subcycling and a hierarchy with buffer points")
         self.rhs_kind = rhs
         self.hier = hier
         self.spec = hier.spec
@@ -208,6 +239,19 @@ class OracleRun:
         self.t = [0.0] * self.L
         self.dx = [self.spec.dx(l) for l in range(self.L)]
         self.subcycling = subcycling
+        self.buffer_zones = buffer_zones
+        if buffer_zones:
+            self.bz_pro = [None]
+            self.bz_dst = [None]
+            for l in range(1, self.L):
+                pts = np.concatenate([hier.rb[l], hier.buffer[l]])
+                self.bz_pro.append(_Prolongation(hier, l, self.st[l - 1], pts))
+                blk, off = hier.levels[l].owner(hier.buffer[l])
+                self.bz_dst.append(self.st[l].flat_offset(blk, off))
+            for st in self.st:
+                st.yprev = np.zeros_like(st.y)
+                st.nsteps = 0
+                st.history = False
         if subcycling:
             self.dt = [cfl * self.dx[l] for l in range(self.L)]
             self.weights = {(s, th): ghost_weights_f64(s, Fraction(th))
@@ -244,6 +288,8 @@ class OracleRun:
 
     # -- pieces of the algorithm ---------------------------------------------
     def rb_values(self, l: int, stage: int) -> np.ndarray:
+        if self.buffer_zones:
+            return self.P[l]              # the step's prolonged state, every stage
         Py, Pk1, Pk2, Pk3, Pk4 = self.P[l]
         w1, w2, w3, w4 = self.weights[(stage, self.theta0[l])]
         H = self.dt[l - 1]
@@ -292,6 +338,10 @@ class OracleRun:
     def rk4_step(self, l: int) -> None:
         st = self.st[l]
         dt = self.dt[l]
+        if self.buffer_zones:
+            st.yprev[:] = st.yn
+            st.history = st.nsteps > 0
+            st.nsteps += 1
         st.yn[:] = st.y
         st.Y[:] = st.yn
         for s in range(1, 5):
@@ -311,6 +361,22 @@ class OracleRun:
         pro = self.pro[l]
         self.P[l] = [pro.apply(par.yn)] + [pro.apply(k) for k in par.k]
 
+    def prolongate_buffer(self, l: int, theta0: float) -> None:
+        """Buffer-zone scheme: the parent's state at t + theta0 H into the RB
+        slots (kept for every stage of the step) and the buffer points."""
+        par = self.st[l - 1]
+        pro = self.bz_pro[l]
+        nrb = len(self.hier.rb[l])
+        if theta0 == 0.0:
+            V = pro.apply(par.yn)
+        else:
+            a, b, c = (float(w) for w in time_interp_weights(Fraction(theta0), par.history))
+            older = par.yprev if par.history else par.yn
+            V = (a * pro.apply(older) + b * pro.apply(par.yn)) + c * pro.apply(par.y)
+        self.P[l] = V[:, :nrb]
+        st = self.st[l]
+        st.y[:, self.bz_dst[l]] = V[:, nrb:]
+
     def restrict(self, l: int) -> None:
         pairs = self.hier.restrict[l]
         if len(pairs) == 0:
@@ -320,7 +386,21 @@ class OracleRun:
         dst = coarse.flat_offset(pairs[:, 0], pairs[:, 1])
         coarse.y[:, dst] = fine.y[:, src]
 
+    def advance_level_buffer(self, l: int, theta0: float) -> None:
+        if l > 0:
+            self.prolongate_buffer(l, theta0)
+        self.rk4_step(l)
+        if l + 1 < self.L:
+            self.advance_level_buffer(l + 1, 0.0)
+            self.advance_level_buffer(l + 1, 0.5)
+            self.restrict(l + 1)
+        self.fill(l, self.st[l].y, 5)
+        self.t[l] += self.dt[l]
+
     def advance_level(self, l: int) -> None:
+        if self.buffer_zones:
+            self.advance_level_buffer(l, 0.0)
+            return
         self.rk4_step(l)
         if l + 1 < self.L:
             self.prolongate(l + 1)

@@ -27,6 +27,15 @@ follows from that structure:
   prolongation stencil is parent-owned.
 * canonical export: one int64 word stream holding all of the above.
 
+Buffer zones (the Carpet scheme the paper compares against, Sec. II and
+Fig. 1), when `buffer` = B > 0: the buffer points of a fine level are its
+owned points within Chebyshev distance B of one of its RB points (periodic
+dimensions measured across the wrap).  They are evolved like any owned point
+but refilled from the parent with the RB points before every fine step, and
+they are not restricted.  Every parent point of the prolongation stencil of
+an RB or buffer point must be parent-owned and, on a parent that has buffer
+points itself, not one of them.
+
 Pinned by tests/test_oracle_maps.py: brute-force pure-Python classification
 on tiny hierarchies, tiling and size invariants, sortedness/uniqueness, and
 the SplitMix64 published outputs.
@@ -151,11 +160,14 @@ class Hierarchy:
     """All levels with their maps.  `spec` is a workloads.HierarchySpec."""
 
     def __init__(self, spec, block_seed: int = 1, min_block: int = 16, max_block: int = 48,
-                 G: int = 3):
+                 G: int = 3, buffer: int = 0):
         if max_block < 2 * min_block - 1:
             raise ValueError("max_block must be at least 2*min_block-1")
+        if buffer < 0:
+            raise ValueError("buffer must be >= 0")
         self.spec = spec
         self.G = G
+        self.B = buffer
         self.nlevels = spec.nlevels
         self.levels: List[Level] = []
         self._check_boxes()
@@ -166,6 +178,9 @@ class Hierarchy:
         self.restrict = []    # per level: (npairs,4) int64 (empty for level 0)
         for l in range(self.nlevels):
             self._classify(l)
+        empty = np.zeros((0, 3), dtype=np.int64)
+        self.buffer = [empty] + [self._buffer_points(l) if buffer else empty
+                                 for l in range(1, self.nlevels)]
         for l in range(1, self.nlevels):
             self._check_stencils(l)
         self.restrict.append(np.zeros((0, 4), dtype=np.int64))
@@ -238,7 +253,44 @@ class Hierarchy:
         base = qd // 2
         return list(range(base - 2, base + 4))
 
+    def _buffer_points(self, l: int) -> np.ndarray:
+        """Owned points within Chebyshev distance B of an RB point, sorted by (z, y, x)."""
+        lev = self.levels[l]
+        B = self.B
+        rbkeys = self._key(self.rb[l])
+        out = []
+        for lo, hi in lev.boxes:
+            lo = np.array(lo, dtype=np.int64)
+            hi = np.array(hi, dtype=np.int64)
+            n = hi - lo + 1 + 2 * B
+            zz, yy, xx = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]),
+                                     indexing="ij")
+            w = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1) + (lo - B)
+            q = lev.wrap(w)
+            isrb = np.isin(self._key(q), rbkeys) & ~lev.outside_domain(q)
+            m = isrb.reshape(n[2], n[1], n[0])
+            # Chebyshev dilation by B: one pass of shifted ORs per axis
+            for ax in range(3):
+                acc = m.copy()
+                for sft in range(1, B + 1):
+                    lo_sl = [slice(None)] * 3
+                    hi_sl = [slice(None)] * 3
+                    lo_sl[ax] = slice(sft, None)
+                    hi_sl[ax] = slice(None, -sft)
+                    acc[tuple(lo_sl)] |= m[tuple(hi_sl)]
+                    acc[tuple(hi_sl)] |= m[tuple(lo_sl)]
+                m = acc
+            inner = m[B:n[2] - B, B:n[1] - B, B:n[0] - B]
+            z, y, x = np.nonzero(inner)
+            out.append(np.stack([x, y, z], axis=1) + lo)
+        pts = np.concatenate(out).astype(np.int64) if out else np.zeros((0, 3), dtype=np.int64)
+        order = np.argsort(self._key(pts), kind="stable")
+        return pts[order]
+
     def _check_stencils(self, l: int):
+        if self.B:
+            self._check_stencils_buffer(l)
+            return
         parent = self.levels[l - 1]
         rb = self.rb[l]
         if len(rb) == 0:
@@ -276,6 +328,34 @@ class Hierarchy:
                         raise NestingError(
                             f"level {l}: prolongation stencil leaves the parent level")
 
+    def _check_stencils_buffer(self, l: int):
+        """Every stencil point of every RB and buffer point is parent-owned and
+        not a parent buffer point."""
+        parent = self.levels[l - 1]
+        pts = np.concatenate([self.rb[l], self.buffer[l]])
+        if len(pts) == 0:
+            return
+        pbuf = self._key(self.buffer[l - 1])
+        base = pts // 2
+        odd = (pts % 2) == 1
+        for ox in range(-2, 4):
+            for oy in range(-2, 4):
+                for oz in range(-2, 4):
+                    off = np.array([ox, oy, oz])
+                    r = np.nonzero(np.all(odd | (off == 0), axis=1))[0]
+                    if len(r) == 0:
+                        continue
+                    q = parent.wrap(base[r] + np.where(odd[r], off, 0))
+                    if parent.outside_domain(q).any():
+                        raise NestingError(f"level {l}: prolongation stencil leaves the domain")
+                    blk, _ = parent.owner(q)
+                    if (blk < 0).any():
+                        raise NestingError(
+                            f"level {l}: prolongation stencil leaves the parent level")
+                    if len(pbuf) and np.isin(self._key(q), pbuf).any():
+                        raise NestingError(
+                            f"level {l}: prolongation stencil reads parent buffer points")
+
     def _restriction_pairs(self, l: int):
         fine = self.levels[l]
         parent = self.levels[l - 1]
@@ -287,6 +367,10 @@ class Hierarchy:
                 continue
             z, y, x = np.meshgrid(ev[2], ev[1], ev[0], indexing="ij")
             q = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+            if len(self.buffer[l]):
+                q = q[~np.isin(self._key(q), self._key(self.buffer[l]))]
+                if len(q) == 0:
+                    continue
             r = q - lo
             n = fine.bdims[b]
             foff = (r[:, 2] * n[1] + r[:, 1]) * n[0] + r[:, 0]
@@ -307,7 +391,8 @@ class Hierarchy:
 
     def export(self) -> np.ndarray:
         """Canonical little-endian int64 word stream of all maps."""
-        words = [np.array([MAGIC, 1, self.nlevels, self.spec.nmembers], dtype=np.int64)]
+        version = 2 if self.B else 1
+        words = [np.array([MAGIC, version, self.nlevels, self.spec.nmembers], dtype=np.int64)]
         for l in range(self.nlevels):
             lev = self.levels[l]
             rb = self.rb[l]
@@ -323,4 +408,10 @@ class Hierarchy:
                 words.append(np.concatenate([rb, rb // 2, par[:, None]], axis=1))
             if len(rs):
                 words.append(rs)
+            if self.B:
+                bz = self.buffer[l]
+                words.append(np.array([len(bz)], dtype=np.int64))
+                if len(bz):
+                    par = (bz[:, 0] % 2) | ((bz[:, 1] % 2) << 1) | ((bz[:, 2] % 2) << 2)
+                    words.append(np.concatenate([bz, bz // 2, par[:, None]], axis=1))
         return np.concatenate([w.ravel() for w in words]).astype("<i8")

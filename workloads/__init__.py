@@ -7,7 +7,8 @@ Runge-Kutta, no dense output, no prolongation, no block splitting.  Both the
 CPU reference implementation and the GPU library receive what it produces.
 """
 from .geometry import (HierarchySpec, single_level, two_level_cube, tower_family, config_z4c_small,
-                       config_c1, config_c2, config_c3, config_c5, config_e1, ensemble_c1)
+                       config_c1, config_c2, config_c3, config_c5, config_e1, ensemble_c1,
+                       grown_for_buffer_zones)
 from .data import (SplitMix64Stream, canonical_coords, standing_wave, periodic_gaussian,
                    pulse_params, pulses_on_spec, standing_wave_on_spec,
                    gaussian_on_spec, ensemble_params, ensemble_on_spec, brill_lindquist,

@@ -179,3 +179,30 @@ def config_e1(n0: int = 375, half: float = 6.0, radii=(4.0, 1.0)) -> HierarchySp
         levels.append([((lo,) * 3, (hi,) * 3)])
     return HierarchySpec((-half,) * 3, dx0, (n0,) * 3, (True,) * 3, levels, 1,
                          name=f"wave-e1-{n0}^3")
+
+
+def grown_for_buffer_zones(spec: HierarchySpec, grow: int) -> HierarchySpec:
+    """The same layout with every fine box grown by `grow` points (even) of its
+    own level on each side, clipped to the domain, so that a buffer-zone run
+    whose buffers are at most `grow` wide keeps at least the original boxes as
+    its valid region."""
+    if grow % 2:
+        raise ValueError("grow must be even (box bounds stay even)")
+    levels: List[List[Box]] = []
+    for l, boxes in enumerate(spec.fine_boxes, start=1):
+        N = [n << l for n in spec.ncells0]
+        out = []
+        for lo, hi in boxes:
+            nlo, nhi = [], []
+            for d in range(3):
+                top = N[d] - 1 if spec.periodic[d] else N[d]
+                if spec.periodic[d] and lo[d] == 0 and hi[d] == N[d] - 1:
+                    nlo.append(lo[d]); nhi.append(hi[d])
+                    continue
+                nlo.append(max(lo[d] - grow, 0))
+                h = min(hi[d] + grow, top)
+                nhi.append(h - (h % 2))
+            out.append((tuple(nlo), tuple(nhi)))
+        levels.append(out)
+    return HierarchySpec(spec.origin, spec.dx0, spec.ncells0, spec.periodic, levels,
+                         spec.nmembers, spec.name + f"-grown{grow}")
