@@ -83,8 +83,21 @@ typedef struct sc_ctx sc_ctx;
  * level steps with the finest level's dt, one fine step per parent step, and
  * the fine ghosts of stage s take the parent's own stage value at the same
  * time, y_n + c_s dt k_{s-1} (RK4 nodes c = 0, 1/2, 1/2, 1), prolonged in space;
- * the parent's step is complete before the fine step starts. */
-enum { SC_SUBCYCLED = 0, SC_UNIFORM_DT = 1 };
+ * the parent's step is complete before the fine step starts.
+ * SC_BUFFER_ZONES: the buffer-zone subcycling the paper compares against
+ * (Carpet, Sec. II and Fig. 1; wave RHS, FP64 only).  Steps as SC_SUBCYCLED,
+ * but the owned points of a fine level within 3 G (Chebyshev) of a refinement-
+ * boundary point are buffer points: before every fine step the parent's state
+ * at the step's start time, interpolated in time over the parent's last three
+ * states (quadratic; linear over two while the parent has made one step) and
+ * prolonged in space, is written into the buffer points and the refinement-
+ * boundary ghosts; the ghosts keep that value through all four stages, the
+ * buffer points are evolved and then discarded, and restriction skips them.
+ * The valid region of a fine box is thus the box minus 3 G layers on each
+ * refinement-boundary face, and the stencils of its ghosts and buffer points
+ * must avoid the parent's buffer points (SC_E_NEST otherwise).  Only
+ * sc_advance steps this mode; the single-step pieces return SC_E_STATE. */
+enum { SC_SUBCYCLED = 0, SC_UNIFORM_DT = 1, SC_BUFFER_ZONES = 2 };
 
 typedef struct {
   int64_t lo[3], hi[3]; /* inclusive vertex indices on the box's level, x, y, z */
@@ -96,7 +109,7 @@ typedef struct {
   int32_t precision;   /* SC_FP64 or SC_MIXED */
   int32_t exec;        /* SC_EXEC_* */
   int32_t nghost;      /* ghost width; must be 3 (fourth-order FD with r = 4 dissipation) */
-  int32_t time_stepping; /* SC_SUBCYCLED (default) or SC_UNIFORM_DT */
+  int32_t time_stepping; /* SC_SUBCYCLED (default), SC_UNIFORM_DT or SC_BUFFER_ZONES */
   double ko_sigma;     /* Kreiss-Oliger strength sigma (Sec. III.C), e.g. 0.32 */
   double cfl;          /* dt_l = cfl * dx_l, 0 < cfl <= 0.5 */
   double z4c_kappa1;   /* Z4c constraint damping kappa_1 (default 0.02) */
@@ -160,7 +173,10 @@ int sc_get_counts(const sc_ctx* ctx, int32_t level, int32_t* nblocks, int64_t* n
  * [qx, qy, qz, qx/2, qy/2, qz/2, odd bits x=1 y=2 z=4], and the restriction
  * pairs sorted by (parent block, parent offset) as
  * [parent block, parent offset, block, offset].  Offsets are
- * ((z - lo_z) n_y + (y - lo_y)) n_x + (x - lo_x) within the owning block. */
+ * ((z - lo_z) n_y + (y - lo_y)) n_x + (x - lo_x) within the owning block.
+ * With SC_BUFFER_ZONES the header's second word is 2, restriction pairs
+ * leave out buffer points, and each level ends with [nbuffer] and its buffer
+ * points sorted by (z, y, x) in the RB-list format. */
 int sc_export_maps(const sc_ctx* ctx, int64_t* words, int64_t* nwords);
 
 /* Device arena size in bytes for the built hierarchy and configuration. */

@@ -1,5 +1,7 @@
 // C-ABI of libsubcyc: context, hierarchy, arena, scheduler, readers.
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -212,6 +214,7 @@ std::string build_layout(sc_ctx* c) {
                              : L.dx);
     L.nb_member = (int)M.boxes.size();
     L.has_child = l + 1 < nl;
+    L.nbuf = c->cfg.time_stepping == SC_BUFFER_ZONES ? 3 : 2;
     L.nyh = l == 0 ? 1 : 8;
     // boxes of member 0
     std::vector<BoxDev> b0(L.nb_member);
@@ -283,8 +286,22 @@ std::string build_layout(sc_ctx* c) {
             first.emplace(key, dst);
           }
     }
+    // buffer zones: the buffer points (owned) take the same prolonged value as
+    // the RB slots before every fine step, so they join the prolongation list
+    for (const auto& q : M.buffer) {
+      const int ib = M.box_of(q.data());
+      if (ib < 0) return "buffer point outside the level's boxes";
+      const BoxDev& B = b0[ib];
+      ProlongEntry e;
+      e.dst = B.base + ((q[2] - B.lo[2] + kG) * B.py + (q[1] - B.lo[1] + kG)) * B.px +
+              (q[0] - B.lo[0] + kG);
+      for (int d = 0; d < 3; ++d) e.q[d] = (int32_t)q[d];
+      e.pbox = stencil_parent(H.levels[l - 1], q.data());
+      if (e.pbox < 0) return "prolongation stencil not inside one parent box";
+      pro0.push_back(e);
+    }
     const int npb = l > 0 ? c->lev[l - 1].nb_member : 0;
-    // group RB halo slots into bricks of at most 8^3 fine points (cells of a
+    // group RB halo slots (and buffer points) into bricks of at most 8^3 fine points (cells of a
     // global 8-point lattice, shrunk to the bounding box of their RB slots);
     // slots that wrap periodically or whose brick spans two parent boxes stay
     // per point
@@ -409,10 +426,64 @@ std::string build_layout(sc_ctx* c) {
             R.n[d] = (int)std::max<int64_t>(0, b - a + 1);
             cnt *= R.n[d];
           }
-          if (cnt > 0) {
+          if (cnt <= 0) continue;
+          if (M.buffer.empty()) {
             R.start = cnt;  // temporarily the count
             r0.push_back(R);
+            continue;
           }
+          // buffer zones: only parent points whose image is not a buffer
+          // point; one region if they form a box, else one per x run
+          std::vector<uint8_t> ok((size_t)cnt);
+          int64_t nok = 0, vlo[3] = {INT64_MAX, INT64_MAX, INT64_MAX}, vhi[3] = {-1, -1, -1};
+          size_t i = 0;
+          for (int z = 0; z < R.n[2]; ++z)
+            for (int y = 0; y < R.n[1]; ++y)
+              for (int x = 0; x < R.n[0]; ++x, ++i) {
+                const int64_t q[3] = {2 * (int64_t)(R.c0[0] + x), 2 * (int64_t)(R.c0[1] + y),
+                                      2 * (int64_t)(R.c0[2] + z)};
+                ok[i] = !M.is_buffer(q);
+                if (!ok[i]) continue;
+                ++nok;
+                const int64_t v[3] = {x, y, z};
+                for (int d = 0; d < 3; ++d) {
+                  vlo[d] = std::min(vlo[d], v[d]);
+                  vhi[d] = std::max(vhi[d], v[d]);
+                }
+              }
+          if (nok == 0) continue;
+          const int64_t bvol = (vhi[0] - vlo[0] + 1) * (vhi[1] - vlo[1] + 1) * (vhi[2] - vlo[2] + 1);
+          if (bvol == nok) {
+            RestrictRegion Q = R;
+            for (int d = 0; d < 3; ++d) {
+              Q.c0[d] = R.c0[d] + (int)vlo[d];
+              Q.n[d] = (int)(vhi[d] - vlo[d] + 1);
+            }
+            Q.start = nok;
+            r0.push_back(Q);
+            continue;
+          }
+          for (int z = 0; z < R.n[2]; ++z)
+            for (int y = 0; y < R.n[1]; ++y) {
+              const size_t row = ((size_t)z * R.n[1] + y) * R.n[0];
+              for (int x = 0; x < R.n[0];) {
+                if (!ok[row + x]) {
+                  ++x;
+                  continue;
+                }
+                int e = x;
+                while (e < R.n[0] && ok[row + e]) ++e;
+                RestrictRegion Q = R;
+                Q.c0[0] = R.c0[0] + x;
+                Q.c0[1] = R.c0[1] + y;
+                Q.c0[2] = R.c0[2] + z;
+                Q.n[0] = e - x;
+                Q.n[1] = Q.n[2] = 1;
+                Q.start = e - x;
+                r0.push_back(Q);
+                x = e;
+              }
+            }
         }
       }
       int64_t start = 0;
@@ -554,7 +625,7 @@ void plan_arena(sc_ctx* c) {
   for (LevelDev& L : c->lev) {
     const size_t arr = sizeof(double) * (size_t)c->nvars * (size_t)L.total;
     const size_t arrs = c->esz * (size_t)c->nvars * (size_t)L.total;
-    for (int i = 0; i < 2; ++i) L.o_y[i] = take(arr);
+    for (int i = 0; i < L.nbuf; ++i) L.o_y[i] = take(arr);
     for (int i = 0; i < 2; ++i) L.o_y32[i] = c->mixed ? take(arr / 2) : 0;
     for (int i = 0; i < 4; ++i) L.o_k[i] = take(arrs);
     for (int i = 0; i < L.nyh; ++i) L.o_yh[i] = take(arrs);
@@ -607,6 +678,14 @@ hipError_t upload(sc_ctx* c, T* dst, const std::vector<T>& v) {
 
 int yh_index(int level, int substep, int stage) { return level == 0 ? 0 : substep * 4 + stage - 1; }
 
+// State buffers rotate: y[cur] is the current state, y[nxt] receives the next
+// one, y[prv] holds the state the last step started from (two buffers: nxt ==
+// prv; three with buffer zones, where y[nxt] still holds y_{n-1} until the
+// level's next step overwrites it).
+inline int nxt(const LevelDev& L) { return (L.cur + 1) % L.nbuf; }
+inline int prv(const LevelDev& L) { return (L.cur + L.nbuf - 1) % L.nbuf; }
+inline bool buffer_zones(const sc_ctx* c) { return c->cfg.time_stepping == SC_BUFFER_ZONES; }
+
 int take_events(sc_ctx* c, hipEvent_t* e0, hipEvent_t* e1) {
   while (c->ev_pool.size() < c->ev_used + 2) {
     hipEvent_t e;
@@ -636,7 +715,7 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
   a.k3 = L.k[2];
   a.kout = L.k[stage - 1];
   a.yn64 = L.y[L.cur];
-  a.ynew = L.y[1 - L.cur];
+  a.ynew = L.y[nxt(L)];
   a.ynew32 = c->mixed ? L.y32[1 - L.cur] : nullptr;
   a.vstride = L.total;
   static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
@@ -716,7 +795,7 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
   a.k2 = L.k[1];
   a.k3 = L.k[2];
   a.kout = L.k[stage - 1];
-  a.ynew = L.y[1 - L.cur];
+  a.ynew = L.y[nxt(L)];
   a.ynew32 = c->mixed ? L.y32[1 - L.cur] : nullptr;
   a.geo = L.Ys;   // kZ4cScratch arrays of double: room for the curvature arrays in either precision
   Z4cCombineArgs cb{};
@@ -763,7 +842,8 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
   LevelDev& L = c->lev[l];
   const void* yn = c->mixed ? static_cast<const void*>(L.y32[L.cur]) : L.y[L.cur];
   for (int s = 1; s <= 4; ++s) {
-    void* yh = L.Yh[yh_index(l, substep, s)];
+    // buffer zones: the RB ghosts keep the step's prolonged value at every stage
+    void* yh = L.Yh[buffer_zones(c) ? (l == 0 ? 0 : substep * 4) : yh_index(l, substep, s)];
     const void* kprev = s == 1 ? nullptr : L.k[s - 2];
     if (!L.sync.empty()) {
       SyncArgs sa{};
@@ -783,7 +863,8 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
                                       : enqueue_stage_launches(c, l, s, per_block, yn, kprev, yh);
     if (rc) return rc;
   }
-  L.cur = 1 - L.cur;
+  L.cur = nxt(L);
+  ++L.steps_done;
   return SC_OK;
 }
 
@@ -802,7 +883,7 @@ int prolong_into(sc_ctx* c, int fl, const ProlongEntry* entries, const int64_t* 
     b.nvars = c->nvars;
     b.fboxes = F.d_boxes;
     b.pboxes = P.d_boxes;
-    b.py = P.y[1 - P.cur];
+    b.py = P.y[prv(P)];
     for (int i = 0; i < 4; ++i) b.pk[i] = P.k[i];
     b.pvstride = P.total;
     b.ovstride = ovstride;
@@ -824,7 +905,7 @@ int prolong_into(sc_ctx* c, int fl, const ProlongEntry* entries, const int64_t* 
   for (int k = 0; k < 8; ++k)
     a.blk_start[k + 1] = a.blk_start[k] + (int32_t)((cls[k + 1] - cls[k] + 255) / 256);
   a.pboxes = P.d_boxes;
-  a.py = P.y[1 - P.cur];
+  a.py = P.y[prv(P)];
   for (int i = 0; i < 4; ++i) a.pk[i] = P.k[i];
   a.pvstride = P.total;
   a.ovstride = ovstride;
@@ -861,6 +942,72 @@ int prolongate(sc_ctx* c, int fl) {
                       c->mixed, -1, true);
 }
 
+// Buffer zones: the parent's state at the start of fine substep `sub`
+// (theta0 = sub / 2), interpolated in time over its last three states
+// (two while it has made one step), prolonged into the RB slots of the
+// substep's ghost table and into the buffer points of the fine state.  The
+// parent has completed its step: y_{n+1} = y[cur], y_n = y[prv], y_{n-1} =
+// y[nxt].
+int prolongate_buffer(sc_ctx* c, int fl, int sub) {
+  LevelDev& P = c->lev[fl - 1];
+  LevelDev& F = c->lev[fl];
+  const double* yn = P.y[prv(P)];
+  const double* ynew = P.y[P.cur];
+  const bool history = P.steps_done >= 2;
+  const double* yold = history ? P.y[nxt(P)] : yn;   // weight 0 without history
+  const int nin = sub == 0 ? 1 : 3;
+  double w[3] = {0.0, 0.5, 0.5};
+  if (history) w[0] = -0.125, w[1] = 0.75, w[2] = 0.375;
+  void* outs[2] = {F.y[F.cur], F.Yh[sub * 4]};
+  if (!F.bricks.empty()) {
+    BrickArgs b{};
+    b.b = F.d_bricks;
+    b.nbricks = (int32_t)F.bricks.size();
+    b.nout = 2;
+    b.nvars = c->nvars;
+    b.fboxes = F.d_boxes;
+    b.pboxes = P.d_boxes;
+    b.py = yn;
+    b.pk[0] = yold;
+    b.pk[1] = ynew;
+    b.pvstride = P.total;
+    b.ovstride = F.total;
+    b.H = P.dt;
+    for (int o = 0; o < 2; ++o) {
+      b.out[o] = outs[o];
+      for (int i = 0; i < 3; ++i) b.w[o][i] = w[i];
+    }
+    HIPCHK(c, launch_prolong_bricks(b, false, false, c->stream, nin));
+    ++c->launches;
+  }
+  const int64_t n = F.prolong_cls[8];
+  if (n <= 0) return SC_OK;
+  ProlongArgs a{};
+  a.e = F.d_prolong;
+  a.n = n;
+  a.blk_start[0] = 0;
+  for (int k = 0; k < 9; ++k) a.cls_start[k] = F.prolong_cls[k];
+  for (int k = 0; k < 8; ++k)
+    a.blk_start[k + 1] =
+        a.blk_start[k] + (int32_t)((F.prolong_cls[k + 1] - F.prolong_cls[k] + 255) / 256);
+  a.pboxes = P.d_boxes;
+  a.py = yn;
+  a.pk[0] = yold;
+  a.pk[1] = ynew;
+  a.pvstride = P.total;
+  a.ovstride = F.total;
+  a.H = P.dt;
+  a.nout = 2;
+  a.nvars = c->nvars;
+  for (int o = 0; o < 2; ++o) {
+    a.out[o] = outs[o];
+    for (int i = 0; i < 3; ++i) a.w[o][i] = w[i];
+  }
+  HIPCHK(c, launch_prolong(a, false, false, c->stream, nin));
+  ++c->launches;
+  return SC_OK;
+}
+
 int restrict_level(sc_ctx* c, int fl) {
   LevelDev& F = c->lev[fl];
   LevelDev& P = c->lev[fl - 1];
@@ -882,7 +1029,22 @@ int restrict_level(sc_ctx* c, int fl) {
   return SC_OK;
 }
 
+// Buffer zones (Carpet): refill from the parent, step, recurse, restrict.
+int advance_level_buffer(sc_ctx* c, int l, int substep, bool per_block) {
+  int rc;
+  if (l > 0 && (rc = prolongate_buffer(c, l, substep))) return rc;
+  if ((rc = rk4_step(c, l, substep, per_block))) return rc;
+  if (l + 1 < (int)c->lev.size()) {
+    if ((rc = advance_level_buffer(c, l + 1, 0, per_block))) return rc;
+    if ((rc = advance_level_buffer(c, l + 1, 1, per_block))) return rc;
+    if ((rc = restrict_level(c, l + 1))) return rc;
+  }
+  c->lev[l].t += c->lev[l].dt;
+  return SC_OK;
+}
+
 int advance_level(sc_ctx* c, int l, int substep, bool per_block) {
+  if (buffer_zones(c)) return advance_level_buffer(c, l, substep, per_block);
   int rc = rk4_step(c, l, substep, per_block);
   if (rc) return rc;
   if (l + 1 < (int)c->lev.size()) {
@@ -912,7 +1074,7 @@ void* array_ptr(sc_ctx* c, int l, int array, int var, bool* f32) {
   *f32 = false;
   switch (array) {
     case SC_ARR_Y: return L.y[L.cur] + var * L.total;
-    case SC_ARR_YN: return L.y[1 - L.cur] + var * L.total;
+    case SC_ARR_YN: return L.y[prv(L)] + var * L.total;
     default:
       *f32 = c->mixed;
       return elem(L.k[array - 1], var * L.total, c->esz);
@@ -965,12 +1127,14 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
     return SC_E_ARG;
   }
   const bool rhs_ok = (cfg->rhs == SC_RHS_WAVE || cfg->rhs == SC_RHS_Z4C) &&
-                     (cfg->time_stepping == SC_SUBCYCLED || cfg->time_stepping == SC_UNIFORM_DT);
+                     (cfg->time_stepping == SC_SUBCYCLED || cfg->time_stepping == SC_UNIFORM_DT ||
+                      (cfg->time_stepping == SC_BUFFER_ZONES && cfg->rhs == SC_RHS_WAVE &&
+                       cfg->precision == SC_FP64));
   if (!rhs_ok || cfg->nghost != 3 || !(cfg->z4c_eta_s > 0.0) || !(cfg->cfl > 0.0 && cfg->cfl <= 0.5) ||
       cfg->ko_sigma < 0.0 || (cfg->precision != SC_FP64 && cfg->precision != SC_MIXED) ||
       cfg->exec < 0 || cfg->exec > 2) {
-    g_create_error = "unsupported configuration (rhs, time stepping, nghost 3, 0 < cfl <= 0.5, "
-                     "sigma >= 0, precision, exec)";
+    g_create_error = "unsupported configuration (rhs, time stepping (buffer zones: wave, FP64), "
+                     "nghost 3, 0 < cfl <= 0.5, sigma >= 0, precision, exec)";
     return SC_E_ARG;
   }
   sc_ctx* c = new sc_ctx();
@@ -990,7 +1154,7 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
 
 int sc_destroy(sc_ctx* c) {
   if (!c) return SC_OK;
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 3; ++i)
     if (c->graph[i]) (void)hipGraphExecDestroy(c->graph[i]);
   delete c;
   return SC_OK;
@@ -1033,7 +1197,10 @@ int sc_build_hierarchy(sc_ctx* c, int32_t nmembers, const double origin[3], doub
     g.fine_boxes.push_back(lv);
   }
   bool nest = false;
-  std::string e = c->hier.build(g, c->cfg.nghost, block_seed, min_block, max_block, &nest);
+  // buffer zones: three ghost widths of buffer points (the RK4 stages after
+  // the first each spoil one ghost width of the fine level's edge)
+  const int bz = c->cfg.time_stepping == SC_BUFFER_ZONES ? 3 * c->cfg.nghost : 0;
+  std::string e = c->hier.build(g, c->cfg.nghost, block_seed, min_block, max_block, &nest, bz);
   if (!e.empty()) return fail(c, nest ? SC_E_NEST : SC_E_ARG, e);
   e = build_layout(c);
   if (!e.empty()) return fail(c, SC_E_NEST, e);
@@ -1096,7 +1263,7 @@ int sc_bind_device_memory(sc_ctx* c, void* dptr, size_t nbytes) {
   c->grid_cap = std::max(ncu, 1) * 8;
   HIPCHK(c, hipMemsetAsync(c->arena, 0, c->arena_bytes, c->stream));
   for (LevelDev& L : c->lev) {
-    for (int i = 0; i < 2; ++i) L.y[i] = at<double>(c, L.o_y[i]);
+    for (int i = 0; i < L.nbuf; ++i) L.y[i] = at<double>(c, L.o_y[i]);
     for (int i = 0; i < 2; ++i) L.y32[i] = c->mixed ? at<float>(c, L.o_y32[i]) : nullptr;
     for (int i = 0; i < 4; ++i) L.k[i] = at<char>(c, L.o_k[i]);
     for (int i = 0; i < L.nyh; ++i) L.Yh[i] = at<char>(c, L.o_yh[i]);
@@ -1189,7 +1356,7 @@ int sc_set_phys_data(sc_ctx* c, int32_t member, int32_t level, int32_t var, cons
   for (int i = 0; i < L.nyh; ++i)
     HIPCHK(c, launch_scatter(idx, n, c->d_stage, elem(L.Yh[i], var * L.total, c->esz), c->mixed,
                              c->stream));
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < L.nbuf; ++i)
     HIPCHK(c, launch_scatter(idx, n, c->d_stage, L.y[i] + var * L.total, false, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return SC_OK;
@@ -1228,18 +1395,24 @@ int sc_advance(sc_ctx* c, int32_t ncoarse) {
   if (ncoarse < 0) return fail(c, SC_E_ARG, "ncoarse < 0");
   c->launches = 0;
   for (int i = 0; i < ncoarse; ++i) {
-    if (c->cfg.exec == SC_EXEC_GRAPH) {
+    // buffer zones: the first coarse step interpolates linearly in time at
+    // each level's first step, later ones quadratically; only the latter
+    // repeat, so the first runs eagerly
+    if (c->cfg.exec == SC_EXEC_GRAPH && !(buffer_zones(c) && c->lev[0].steps_done == 0)) {
       const int parity = c->lev[0].cur;
       if (!c->graph_ready[parity]) {
         // capture one coarse step starting from this buffer parity
         std::vector<int> cur0(c->lev.size());
         std::vector<double> t0(c->lev.size());
-        for (size_t l = 0; l < c->lev.size(); ++l) cur0[l] = c->lev[l].cur, t0[l] = c->lev[l].t;
+        std::vector<int64_t> n0(c->lev.size());
+        for (size_t l = 0; l < c->lev.size(); ++l)
+          cur0[l] = c->lev[l].cur, t0[l] = c->lev[l].t, n0[l] = c->lev[l].steps_done;
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         rc = advance_level(c, 0, 0, false);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->stream, &g);
-        for (size_t l = 0; l < c->lev.size(); ++l) c->lev[l].cur = cur0[l], c->lev[l].t = t0[l];
+        for (size_t l = 0; l < c->lev.size(); ++l)
+          c->lev[l].cur = cur0[l], c->lev[l].t = t0[l], c->lev[l].steps_done = n0[l];
         if (rc) return rc;
         if (e != hipSuccess) return fail(c, SC_E_HIP, std::string("capture: ") + hipGetErrorString(e));
         e = hipGraphInstantiate(&c->graph[parity], g, nullptr, nullptr, 0);
@@ -1253,8 +1426,10 @@ int sc_advance(sc_ctx* c, int32_t ncoarse) {
       // replay the host bookkeeping of one coarse step
       for (size_t l = 0; l < c->lev.size(); ++l) {
         const int64_t steps = c->cfg.time_stepping == SC_UNIFORM_DT ? 1 : int64_t(1) << l;
-        if (steps & 1) c->lev[l].cur = 1 - c->lev[l].cur;
-        for (int64_t s = 0; s < steps; ++s) c->lev[l].t += c->lev[l].dt;
+        LevelDev& L = c->lev[l];
+        L.cur = (int)((L.cur + steps) % L.nbuf);
+        L.steps_done += steps;
+        for (int64_t s = 0; s < steps; ++s) L.t += L.dt;
       }
       ++c->launches;
     } else {
@@ -1268,6 +1443,7 @@ int sc_advance(sc_ctx* c, int32_t ncoarse) {
 int sc_step_level(sc_ctx* c, int32_t level, int32_t substep) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
+  if (buffer_zones(c)) return fail(c, SC_E_STATE, "buffer zones: use sc_advance");
   if (level < 0 || level >= (int)c->lev.size() || substep < 0 || substep > 1)
     return fail(c, SC_E_ARG, "bad level or substep");
   rc = rk4_step(c, level, level == 0 ? 0 : substep, c->cfg.exec == SC_EXEC_PER_BLOCK);
@@ -1278,6 +1454,7 @@ int sc_step_level(sc_ctx* c, int32_t level, int32_t substep) {
 int sc_prolongate(sc_ctx* c, int32_t fine_level) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
+  if (buffer_zones(c)) return fail(c, SC_E_STATE, "buffer zones: use sc_advance");
   if (fine_level < 1 || fine_level >= (int)c->lev.size()) return fail(c, SC_E_ARG, "bad level");
   return prolongate(c, fine_level);
 }
@@ -1292,6 +1469,7 @@ int sc_restrict(sc_ctx* c, int32_t fine_level) {
 int sc_fill_ghosts(sc_ctx* c, int32_t level, int32_t which, int32_t substep) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
+  if (buffer_zones(c)) return fail(c, SC_E_STATE, "buffer zones: use sc_advance");
   if (level < 0 || level >= (int)c->lev.size() || which < 1 || which > 5 || substep < 0 ||
       substep > 1)
     return fail(c, SC_E_ARG, "bad fill arguments");
@@ -1347,6 +1525,7 @@ int sc_read_rb(sc_ctx* c, int32_t member, int32_t level, int32_t which, int32_t 
       member >= c->hier.geo.nmembers || which < 1 || which > 5 || substep < 0 || substep > 1 ||
       var < 0 || var >= c->nvars || !host)
     return fail(c, SC_E_ARG, "bad RB read arguments");
+  if (buffer_zones(c)) return fail(c, SC_E_STATE, "buffer zones: no dense-output RB values");
   LevelDev& L = c->lev[level];
   if (n != L.nrb) return fail(c, SC_E_ARG, "n must equal the level's RB points");
   if (which <= 4) {
@@ -1431,7 +1610,7 @@ int sc_poison_halos(sc_ctx* c) {
 }
 
 static void drop_graphs(sc_ctx* c) {
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < 3; ++i) {
     if (c->graph[i]) (void)hipGraphExecDestroy(c->graph[i]);
     c->graph[i] = nullptr;
     c->graph_ready[i] = false;

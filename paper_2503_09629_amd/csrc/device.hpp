@@ -115,7 +115,7 @@ struct ProlongArgs {
   int32_t blk_start[9];
   const BoxDev* pboxes;          // parent level boxes
   const double* py;              // parent y_n (FP64)
-  const void* pk[4];             // parent k1..k4 (FP64, or FP32 in mixed mode)
+  const void* pk[4];             // parent k1..k4 (FP64, or FP32 in mixed mode); see nin
   int64_t pvstride;
   void* out[kMaxOut];            // outputs, one per combination
   int64_t ovstride;
@@ -170,8 +170,12 @@ hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int depth, int s
                         hipStream_t s);
 hipError_t launch_sync(const SyncArgs& a, bool f32, hipStream_t s);
 // k_f32: parent slopes are FP32; out_f32: outputs are FP32
-hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s);
-hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, bool out_f32, hipStream_t s);
+// nin: 5 = (y_n, k1..k4) with dense-output weights; 3 = (y_n, y_{n-1}, y_{n+1})
+// with time-interpolation weights w[o][0..2] on (y_{n-1}, y_n, y_{n+1}) (pk[0] =
+// y_{n-1}, pk[1] = y_{n+1}, FP64); 1 = y_n alone
+hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s, int nin = 5);
+hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, bool out_f32, hipStream_t s,
+                                 int nin = 5);
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, bool unpack, bool f32, hipStream_t s);
 hipError_t launch_norms(const PackArgs& a, bool f32, double* partials, int nparts, double* out,

@@ -66,6 +66,10 @@ int LevelMaps::box_of(const int64_t q[3]) const {
   return -1;
 }
 
+bool LevelMaps::is_buffer(const int64_t q[3]) const {
+  return std::binary_search(buffer_keys.begin(), buffer_keys.end(), rb_key(q));
+}
+
 bool LevelMaps::owner(const int64_t q[3], int32_t* block, int64_t* offset) const {
   int ib = box_of(q);
   if (ib < 0) return false;
@@ -78,14 +82,74 @@ bool LevelMaps::owner(const int64_t q[3], int32_t* block, int64_t* offset) const
   return true;
 }
 
+// Buffer points of one level: per box, mark the RB points of the window
+// [lo - B, hi + B] (wrapped into the domain), dilate the marks by B along x,
+// y and z in turn with running counts, and keep the marked box points.
+static void find_buffer(LevelMaps& L, int B) {
+  std::vector<int64_t> rbk(L.rb.size());
+  for (size_t i = 0; i < L.rb.size(); ++i) rbk[i] = rb_key(L.rb[i].data());   // ascending
+  std::vector<std::array<int64_t, 3>> pts;
+  for (const IBox& bx : L.boxes) {
+    int64_t n[3], lo[3];
+    for (int d = 0; d < 3; ++d) {
+      n[d] = bx.n(d) + 2 * B;
+      lo[d] = bx.lo[d] - B;
+    }
+    std::vector<uint8_t> m((size_t)(n[0] * n[1] * n[2]), 0), t(m.size());
+    int64_t w[3], q[3];
+    size_t i = 0;
+    for (w[2] = 0; w[2] < n[2]; ++w[2])
+      for (w[1] = 0; w[1] < n[1]; ++w[1])
+        for (w[0] = 0; w[0] < n[0]; ++w[0], ++i) {
+          const int64_t p[3] = {lo[0] + w[0], lo[1] + w[1], lo[2] + w[2]};
+          L.wrap(p, q);
+          if (!L.outside(q) && std::binary_search(rbk.begin(), rbk.end(), rb_key(q))) m[i] = 1;
+        }
+    const int64_t stride[3] = {1, n[0], n[0] * n[1]};
+    for (int d = 0; d < 3; ++d) {
+      // t = 1 where some mark lies within B along axis d
+      const int64_t nd = n[d], sd = stride[d];
+      const int64_t nlines = (int64_t)m.size() / nd;
+      for (int64_t line = 0; line < nlines; ++line) {
+        // base of the line: decompose the line index over the other two axes
+        int64_t base;
+        if (d == 0) base = line * n[0];
+        else if (d == 1) base = (line / n[0]) * n[0] * n[1] + line % n[0];
+        else base = line;
+        int cnt = 0;
+        for (int64_t k = 0; k < std::min<int64_t>(B, nd); ++k) cnt += m[base + k * sd];
+        for (int64_t k = 0; k < nd; ++k) {
+          if (k + B < nd) cnt += m[base + (k + B) * sd];
+          if (k - B - 1 >= 0) cnt -= m[base + (k - B - 1) * sd];
+          t[base + k * sd] = cnt > 0;
+        }
+      }
+      m.swap(t);
+    }
+    for (int64_t z = 0; z < bx.n(2); ++z)
+      for (int64_t y = 0; y < bx.n(1); ++y)
+        for (int64_t x = 0; x < bx.n(0); ++x)
+          if (m[(size_t)(((z + B) * n[1] + (y + B)) * n[0] + (x + B))])
+            pts.push_back({bx.lo[0] + x, bx.lo[1] + y, bx.lo[2] + z});
+  }
+  std::sort(pts.begin(), pts.end(), [](const std::array<int64_t, 3>& a, const std::array<int64_t, 3>& b) {
+    return rb_key(a.data()) < rb_key(b.data());
+  });
+  L.buffer = pts;
+  L.buffer_keys.resize(pts.size());
+  for (size_t k = 0; k < pts.size(); ++k) L.buffer_keys[k] = rb_key(pts[k].data());
+}
+
 std::string Hierarchy::build(const Geometry& g, int G_, uint64_t block_seed, int min_block,
-                             int max_block, bool* nest_error) {
+                             int max_block, bool* nest_error, int buffer) {
   geo = g;
   G = G_;
+  B = buffer;
   *nest_error = false;
   char msg[256];
   if (max_block < 2 * min_block - 1 || min_block < 1)
     return "max_block must be at least 2*min_block-1 and min_block >= 1";
+  if (buffer < 0) return "buffer width must be >= 0";
   levels.assign(g.nlevels, LevelMaps());
   // ---- boxes, alignment, containment, overlap
   for (int l = 0; l < g.nlevels; ++l) {
@@ -217,11 +281,48 @@ std::string Hierarchy::build(const Geometry& g, int G_, uint64_t block_seed, int
     for (size_t i = 0; i < uk.size(); ++i)
       L.rb[i] = {uk[i] & m21, (uk[i] >> 21) & m21, uk[i] >> 42};
   }
-  // ---- nesting of prolongation stencils: each RB point's stencil must lie in
-  //      one parent box (periodic dimensions spanned by that box wrap)
+  if (B > 0)
+    for (int l = 1; l < g.nlevels; ++l) find_buffer(levels[l], B);
+  // ---- nesting of prolongation stencils: each RB (and buffer) point's
+  //      stencil must lie in one parent box (periodic dimensions spanned by
+  //      that box wrap) and, with buffer zones, avoid the parent's buffer points
   for (int l = 1; l < g.nlevels; ++l) {
     const LevelMaps& P = levels[l - 1];
-    for (const auto& q : levels[l].rb) {
+    std::vector<std::array<int64_t, 3>> pts = levels[l].rb;
+    pts.insert(pts.end(), levels[l].buffer.begin(), levels[l].buffer.end());
+    // parent buffer points per parent box as summed-volume tables, so that a
+    // stencil's box is tested in O(1)
+    std::vector<std::vector<int32_t>> sat(P.buffer.empty() ? 0 : P.boxes.size());
+    for (size_t ib = 0; ib < sat.size(); ++ib) {
+      const IBox& b = P.boxes[ib];
+      const int64_t n0 = b.n(0) + 1, n1 = b.n(1) + 1, n2 = b.n(2) + 1;
+      std::vector<int32_t>& S = sat[ib];
+      S.assign((size_t)(n0 * n1 * n2), 0);
+      for (const auto& c : P.buffer) {
+        if (!b.contains(c.data())) continue;
+        S[(size_t)(((c[2] - b.lo[2] + 1) * n1 + (c[1] - b.lo[1] + 1)) * n0 + (c[0] - b.lo[0] + 1))] = 1;
+      }
+      for (int64_t z = 1; z < n2; ++z)
+        for (int64_t y = 1; y < n1; ++y)
+          for (int64_t x = 1; x < n0; ++x) {
+            auto at = [&](int64_t zz, int64_t yy, int64_t xx) -> int32_t& {
+              return S[(size_t)((zz * n1 + yy) * n0 + xx)];
+            };
+            at(z, y, x) += at(z - 1, y, x) + at(z, y - 1, x) + at(z, y, x - 1) - at(z - 1, y - 1, x) -
+                           at(z - 1, y, x - 1) - at(z, y - 1, x - 1) + at(z - 1, y - 1, x - 1);
+          }
+    }
+    // buffer points of parent box ib in the box-local ranges [a, b] (inclusive)
+    auto count = [&](size_t ib, const int64_t a[3], const int64_t b[3]) -> int64_t {
+      const IBox& bx = P.boxes[ib];
+      const int64_t n0 = bx.n(0) + 1, n1 = bx.n(1) + 1;
+      const std::vector<int32_t>& S = sat[ib];
+      auto at = [&](int64_t z, int64_t y, int64_t x) -> int64_t { return S[(size_t)((z * n1 + y) * n0 + x)]; };
+      const int64_t x0 = a[0], x1 = b[0] + 1, y0 = a[1], y1 = b[1] + 1, z0 = a[2], z1 = b[2] + 1;
+      return at(z1, y1, x1) - at(z0, y1, x1) - at(z1, y0, x1) - at(z1, y1, x0) + at(z0, y0, x1) +
+             at(z0, y1, x0) + at(z1, y0, x0) - at(z0, y0, x0);
+    };
+    for (const auto& q : pts) {
       int64_t smin[3], smax[3];
       for (int d = 0; d < 3; ++d) {
         int64_t base = floordiv2(q[d]);
@@ -229,7 +330,9 @@ std::string Hierarchy::build(const Geometry& g, int G_, uint64_t block_seed, int
         smax[d] = (q[d] & 1) ? base + 3 : base;
       }
       bool ok = false;
-      for (const IBox& b : P.boxes) {
+      size_t pbox = 0;
+      for (size_t ib = 0; ib < P.boxes.size(); ++ib) {
+        const IBox& b = P.boxes[ib];
         bool in = true;
         for (int d = 0; d < 3; ++d) {
           bool full = P.periodic[d] && b.lo[d] == 0 && b.hi[d] == P.N[d] - 1;
@@ -237,6 +340,7 @@ std::string Hierarchy::build(const Geometry& g, int G_, uint64_t block_seed, int
         }
         if (in) {
           ok = true;
+          pbox = ib;
           break;
         }
       }
@@ -247,6 +351,38 @@ std::string Hierarchy::build(const Geometry& g, int G_, uint64_t block_seed, int
                  "parent box",
                  l, (long long)q[0], (long long)q[1], (long long)q[2]);
         return msg;
+      }
+      if (!P.buffer.empty()) {
+        // the stencil range in box-local coordinates, split where a
+        // box-spanning periodic dimension wraps
+        const IBox& b = P.boxes[pbox];
+        int64_t ra[3][2], rb[3][2];
+        int nr[3];
+        for (int d = 0; d < 3; ++d) {
+          const int64_t a = smin[d] - b.lo[d], e = smax[d] - b.lo[d], n = b.n(d);
+          if (a >= 0 && e < n) {
+            nr[d] = 1, ra[d][0] = a, rb[d][0] = e;
+          } else if (a < 0) {   // wraps below: [a + n, n - 1] and [0, e]
+            nr[d] = 2, ra[d][0] = a + n, rb[d][0] = n - 1, ra[d][1] = 0, rb[d][1] = e;
+          } else {              // wraps above: [a, n - 1] and [0, e - n]
+            nr[d] = 2, ra[d][0] = a, rb[d][0] = n - 1, ra[d][1] = 0, rb[d][1] = e - n;
+          }
+        }
+        int64_t hits = 0;
+        for (int i = 0; i < nr[0]; ++i)
+          for (int j = 0; j < nr[1]; ++j)
+            for (int k = 0; k < nr[2]; ++k) {
+              const int64_t a[3] = {ra[0][i], ra[1][j], ra[2][k]};
+              const int64_t e[3] = {rb[0][i], rb[1][j], rb[2][k]};
+              hits += count(pbox, a, e);
+            }
+        if (hits > 0) {
+          *nest_error = true;
+          snprintf(msg, sizeof msg,
+                   "level %d: prolongation stencil of (%lld,%lld,%lld) reads parent buffer points",
+                   l, (long long)q[0], (long long)q[1], (long long)q[2]);
+          return msg;
+        }
       }
     }
   }
@@ -260,6 +396,7 @@ std::string Hierarchy::build(const Geometry& g, int G_, uint64_t block_seed, int
       for (q[2] = bl.lo[2] + (bl.lo[2] & 1); q[2] <= bl.hi[2]; q[2] += 2)
         for (q[1] = bl.lo[1] + (bl.lo[1] & 1); q[1] <= bl.hi[1]; q[1] += 2)
           for (q[0] = bl.lo[0] + (bl.lo[0] & 1); q[0] <= bl.hi[0]; q[0] += 2) {
+            if (!F.buffer.empty() && F.is_buffer(q)) continue;
             int64_t h[3] = {q[0] / 2, q[1] / 2, q[2] / 2};
             P.wrap(h, c);
             int32_t cb;
@@ -285,7 +422,7 @@ std::string Hierarchy::build(const Geometry& g, int G_, uint64_t block_seed, int
 void Hierarchy::export_words(std::vector<int64_t>* out) const {
   std::vector<int64_t>& w = *out;
   w.clear();
-  w.insert(w.end(), {0x53554243, 1, geo.nlevels, geo.nmembers});
+  w.insert(w.end(), {0x53554243, B > 0 ? 2 : 1, geo.nlevels, geo.nmembers});
   for (const LevelMaps& L : levels) {
     w.insert(w.end(), {L.level, (int64_t)L.blocks.size(), L.nowned, (int64_t)L.rb.size(),
                        (int64_t)L.restrict_pairs.size()});
@@ -297,6 +434,12 @@ void Hierarchy::export_words(std::vector<int64_t>* out) const {
       w.insert(w.end(), {q[0], q[1], q[2], q[0] / 2, q[1] / 2, q[2] / 2,
                          (q[0] & 1) | ((q[1] & 1) << 1) | ((q[2] & 1) << 2)});
     for (const auto& r : L.restrict_pairs) w.insert(w.end(), {r[0], r[1], r[2], r[3]});
+    if (B > 0) {
+      w.push_back((int64_t)L.buffer.size());
+      for (const auto& q : L.buffer)
+        w.insert(w.end(), {q[0], q[1], q[2], q[0] / 2, q[1] / 2, q[2] / 2,
+                           (q[0] & 1) | ((q[1] & 1) << 1) | ((q[2] & 1) << 2)});
+    }
   }
 }
 

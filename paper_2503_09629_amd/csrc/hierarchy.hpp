@@ -7,6 +7,12 @@
 // level (SYNC), from the parent level at a refinement boundary (RB), or by
 // the physical boundary (PHYS).  The refinement-boundary ghost width equals
 // the block-boundary ghost width, which is the point of the method.
+//
+// Buffer zones (the Carpet scheme the paper compares against, Sec. II and
+// Fig. 1): with a buffer width B > 0 the buffer points of a fine level are its
+// owned points within Chebyshev distance B of one of its RB points; they are
+// refilled from the parent before every fine step and never restricted, and
+// the parent points that prolongation reads must not be buffer points.
 #pragma once
 
 #include <array>
@@ -43,6 +49,9 @@ struct LevelMaps {
   std::vector<int64_t> ga, gc;       // SYNC: owner, offset; RB: rb index, 0; PHYS: -1, 0
   std::vector<std::array<int64_t, 3>> rb;  // distinct RB points sorted by (z, y, x)
   std::vector<std::array<int64_t, 4>> restrict_pairs;  // [pblock, poffset, block, offset]
+  std::vector<std::array<int64_t, 3>> buffer;  // buffer points sorted by (z, y, x)
+  std::vector<int64_t> buffer_keys;            // their keys, ascending
+  bool is_buffer(const int64_t q[3]) const;
 
   void wrap(const int64_t p[3], int64_t q[3]) const;
   bool outside(const int64_t q[3]) const;
@@ -65,12 +74,13 @@ struct Geometry {
 struct Hierarchy {
   Geometry geo;
   int G = 3;
+  int B = 0;   // buffer width (0: no buffer zones)
   std::vector<LevelMaps> levels;
 
   // Returns an empty string on success, else the reason; *nest_error tells a
   // nesting/alignment violation from a plain argument error.
   std::string build(const Geometry& g, int G, uint64_t block_seed, int min_block,
-                    int max_block, bool* nest_error);
+                    int max_block, bool* nest_error, int buffer = 0);
   void export_words(std::vector<int64_t>* out) const;
   int64_t updates_per_coarse_step() const;
 };

@@ -321,13 +321,32 @@ __global__ __launch_bounds__(256) void k_sync(SyncArgs a) {
   }
 }
 
-// Prolongation of the parent's (y_n, k1..k4) to one refinement-boundary
-// point, x first, then y, then z, with the degree-5 Lagrange midpoint
-// weights at odd fine indices and a copy at even ones; then each requested
-// dense-output combination  P[y_n] + H (((w1 P[k1] + w2 P[k2]) + w3 P[k3]) + w4 P[k4]),
-// all in FP64.  The parity class is a template parameter, so every loop has
-// a compile-time trip count, and each stencil tap gathers all five vectors.
-template <int OX, int OY, int OZ, typename TK, typename TO>
+// Combination of the prolonged input vectors v[0..NIN-1] for output o.
+// NIN = 5 (dense output): v = (y_n, k1..k4),
+//   P[y_n] + H (((w1 P[k1] + w2 P[k2]) + w3 P[k3]) + w4 P[k4]);
+// NIN = 3 (buffer zones, time interpolation): v = (y_n, y_{n-1}, y_{n+1}),
+//   ((w1 P[y_{n-1}] + w2 P[y_n]) + w3 P[y_{n+1}]);
+// NIN = 1 (buffer zones at the parent's own time): P[y_n].
+template <int NIN>
+__device__ __forceinline__ double prolong_combine(const double (&v)[NIN], const double* w,
+                                                  double H) {
+  if constexpr (NIN == 5) {
+    const double s = ((w[0] * v[1] + w[1] * v[2]) + w[2] * v[3]) + w[3] * v[4];
+    return v[0] + H * s;
+  } else if constexpr (NIN == 3) {
+    return (w[0] * v[1] + w[1] * v[0]) + w[2] * v[2];
+  } else {
+    return v[0];
+  }
+}
+
+// Prolongation of NIN parent vectors (y_n first, then the pk[]) to one fine
+// point, x first, then y, then z, with the degree-5 Lagrange midpoint weights
+// at odd fine indices and a copy at even ones; then each requested
+// combination (prolong_combine), all in FP64.  The parity class is a
+// template parameter, so every loop has a compile-time trip count, and each
+// stencil tap gathers all NIN vectors.
+template <int NIN, int OX, int OY, int OZ, typename TK, typename TO>
 __device__ __forceinline__ void prolong_one(const ProlongArgs& a, int64_t i) {
   constexpr int NX = OX ? 6 : 1, NY = OY ? 6 : 1, NZ = OZ ? 6 : 1;
   constexpr double W[6] = {3.0 / 256.0, -25.0 / 256.0, 150.0 / 256.0,
@@ -348,50 +367,46 @@ __device__ __forceinline__ void prolong_one(const ProlongArgs& a, int64_t i) {
   for (int j = 0; j < NY; ++j) oy[j] = offs(1, OY, j);
 #pragma unroll
   for (int j = 0; j < NZ; ++j) oz[j] = offs(2, OZ, j);
-  const TK* k0 = static_cast<const TK*>(a.pk[0]);
-  const TK* k1 = static_cast<const TK*>(a.pk[1]);
-  const TK* k2 = static_cast<const TK*>(a.pk[2]);
-  const TK* k3 = static_cast<const TK*>(a.pk[3]);
   for (int v = 0; v < a.nvars; ++v) {
     const int64_t vb = P.base + v * a.pvstride;
-    double pz[5];
+    double pz[NIN];
 #pragma unroll
     for (int jz = 0; jz < NZ; ++jz) {
-      double py[5];
+      double py[NIN];
 #pragma unroll
       for (int jy = 0; jy < NY; ++jy) {
-        double px[5];
+        double px[NIN];
 #pragma unroll
         for (int jx = 0; jx < NX; ++jx) {
           const int64_t o = vb + oz[jz] + oy[jy] + ox[jx];
-          const double t[5] = {a.py[o], (double)k0[o], (double)k1[o], (double)k2[o], (double)k3[o]};
+          double t[NIN];
+          t[0] = a.py[o];
 #pragma unroll
-          for (int m = 0; m < 5; ++m) {
+          for (int m = 1; m < NIN; ++m) t[m] = (double)static_cast<const TK*>(a.pk[m - 1])[o];
+#pragma unroll
+          for (int m = 0; m < NIN; ++m) {
             if constexpr (NX == 1) px[m] = t[m];
             else px[m] = jx == 0 ? W[0] * t[m] : px[m] + W[jx] * t[m];
           }
         }
 #pragma unroll
-        for (int m = 0; m < 5; ++m) {
+        for (int m = 0; m < NIN; ++m) {
           if constexpr (NY == 1) py[m] = px[m];
           else py[m] = jy == 0 ? W[0] * px[m] : py[m] + W[jy] * px[m];
         }
       }
 #pragma unroll
-      for (int m = 0; m < 5; ++m) {
+      for (int m = 0; m < NIN; ++m) {
         if constexpr (NZ == 1) pz[m] = py[m];
         else pz[m] = jz == 0 ? W[0] * py[m] : pz[m] + W[jz] * py[m];
       }
     }
-    for (int o = 0; o < a.nout; ++o) {
-      const double s =
-          ((a.w[o][0] * pz[1] + a.w[o][1] * pz[2]) + a.w[o][2] * pz[3]) + a.w[o][3] * pz[4];
-      static_cast<TO*>(a.out[o])[e.dst + v * a.ovstride] = (TO)(pz[0] + a.H * s);
-    }
+    for (int o = 0; o < a.nout; ++o)
+      static_cast<TO*>(a.out[o])[e.dst + v * a.ovstride] = (TO)prolong_combine<NIN>(pz, a.w[o], a.H);
   }
 }
 
-template <typename TK, typename TO>
+template <int NIN, typename TK, typename TO>
 __global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
   const int b = blockIdx.x;
   int cls = 0;
@@ -399,14 +414,14 @@ __global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
   const int64_t i = a.cls_start[cls] + (int64_t)(b - a.blk_start[cls]) * 256 + threadIdx.x;
   if (i >= a.cls_start[cls + 1]) return;
   switch (cls) {
-    case 0: prolong_one<0, 0, 0, TK, TO>(a, i); break;
-    case 1: prolong_one<1, 0, 0, TK, TO>(a, i); break;
-    case 2: prolong_one<0, 1, 0, TK, TO>(a, i); break;
-    case 3: prolong_one<1, 1, 0, TK, TO>(a, i); break;
-    case 4: prolong_one<0, 0, 1, TK, TO>(a, i); break;
-    case 5: prolong_one<1, 0, 1, TK, TO>(a, i); break;
-    case 6: prolong_one<0, 1, 1, TK, TO>(a, i); break;
-    default: prolong_one<1, 1, 1, TK, TO>(a, i); break;
+    case 0: prolong_one<NIN, 0, 0, 0, TK, TO>(a, i); break;
+    case 1: prolong_one<NIN, 1, 0, 0, TK, TO>(a, i); break;
+    case 2: prolong_one<NIN, 0, 1, 0, TK, TO>(a, i); break;
+    case 3: prolong_one<NIN, 1, 1, 0, TK, TO>(a, i); break;
+    case 4: prolong_one<NIN, 0, 0, 1, TK, TO>(a, i); break;
+    case 5: prolong_one<NIN, 1, 0, 1, TK, TO>(a, i); break;
+    case 6: prolong_one<NIN, 0, 1, 1, TK, TO>(a, i); break;
+    default: prolong_one<NIN, 1, 1, 1, TK, TO>(a, i); break;
   }
 }
 
@@ -436,7 +451,7 @@ __device__ __forceinline__ double brick_tap(const double* src, int st, bool odd)
   return r;
 }
 
-template <typename TK, typename TO>
+template <int NIN, typename TK, typename TO>
 __global__ __launch_bounds__(256) void k_prolong_bricks(BrickArgs a) {
   __shared__ double V[kBrickC * kBrickC * kBrickC];     // [cz][cy][cx]
   __shared__ double PX[kBrickC * kBrickC * kBrick];     // [cz][cy][fx]
@@ -524,23 +539,23 @@ __global__ __launch_bounds__(256) void k_prolong_bricks(BrickArgs a) {
     dst[e] = F.base + ((int64_t)(Bk.a[2] + fz - F.lo[2] + kG) * F.py + (Bk.a[1] + fy - F.lo[1] + kG)) *
                           (int64_t)F.px + (Bk.a[0] + fx - F.lo[0] + kG);
   }
-  auto load_var = [&](int v, double (&R)[5][NL]) {
+  auto load_var = [&](int v, double (&R)[NIN][NL]) {
     const int64_t vo = (int64_t)v * a.pvstride;
 #pragma unroll
     for (int j = 0; j < NL; ++j) R[0][j] = a.py[co[j] + vo];
 #pragma unroll
-    for (int m = 1; m < 5; ++m)
+    for (int m = 1; m < NIN; ++m)
 #pragma unroll
       for (int j = 0; j < NL; ++j)
         R[m][j] = (double)static_cast<const TK*>(a.pk[m - 1])[co[j] + vo];
   };
-  double R[5][NL], Rn[5][NL];
+  double R[NIN][NL], Rn[NIN][NL];
   load_var(0, R);
   for (int v = 0; v < a.nvars; ++v) {
     load_var(v + 1 < a.nvars ? v + 1 : v, Rn);   // in flight while v is interpolated
-    double Pv[ZE][5];
+    double Pv[ZE][NIN];
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
+    for (int m = 0; m < NIN; ++m) {
 #pragma unroll
       for (int j = 0; j < NL; ++j)
         if (vi[j] >= 0) V[vi[j]] = R[m][j];
@@ -560,14 +575,11 @@ __global__ __launch_bounds__(256) void k_prolong_bricks(BrickArgs a) {
     for (int e = 0; e < ZE; ++e) {
       if (!zw[e]) continue;
       const int64_t d = dst[e] + v * a.ovstride;
-      for (int o = 0; o < a.nout; ++o) {
-        const double s = ((a.w[o][0] * Pv[e][1] + a.w[o][1] * Pv[e][2]) + a.w[o][2] * Pv[e][3]) +
-                         a.w[o][3] * Pv[e][4];
-        static_cast<TO*>(a.out[o])[d] = (TO)(Pv[e][0] + a.H * s);
-      }
+      for (int o = 0; o < a.nout; ++o)
+        static_cast<TO*>(a.out[o])[d] = (TO)prolong_combine<NIN>(Pv[e], a.w[o], a.H);
     }
 #pragma unroll
-    for (int m = 0; m < 5; ++m)
+    for (int m = 0; m < NIN; ++m)
 #pragma unroll
       for (int j = 0; j < NL; ++j) R[m][j] = Rn[m][j];
   }
@@ -753,23 +765,36 @@ hipError_t launch_sync(const SyncArgs& a, bool f32, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s) {
+hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s, int nin) {
   if (a.n <= 0) return hipSuccess;
   const dim3 g(a.blk_start[8]), b(256);
-  if (!k_f32 && !out_f32) hipLaunchKernelGGL((k_prolong<double, double>), g, b, 0, s, a);
-  else if (k_f32 && out_f32) hipLaunchKernelGGL((k_prolong<float, float>), g, b, 0, s, a);
-  else if (k_f32) hipLaunchKernelGGL((k_prolong<float, double>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_prolong<double, float>), g, b, 0, s, a);
+  if (nin != 5) {   // buffer zones: FP64 state vectors only
+    if (k_f32 || out_f32 || (nin != 1 && nin != 3)) return hipErrorInvalidValue;
+    if (nin == 1) hipLaunchKernelGGL((k_prolong<1, double, double>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_prolong<3, double, double>), g, b, 0, s, a);
+    return hipGetLastError();
+  }
+  if (!k_f32 && !out_f32) hipLaunchKernelGGL((k_prolong<5, double, double>), g, b, 0, s, a);
+  else if (k_f32 && out_f32) hipLaunchKernelGGL((k_prolong<5, float, float>), g, b, 0, s, a);
+  else if (k_f32) hipLaunchKernelGGL((k_prolong<5, float, double>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_prolong<5, double, float>), g, b, 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, bool out_f32, hipStream_t s) {
+hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, bool out_f32, hipStream_t s,
+                                 int nin) {
   if (a.nbricks <= 0) return hipSuccess;
   const dim3 g((unsigned)((a.nbricks + 7) / 8 * 8)), b(256);   // whole XCD rounds; extra groups exit
-  if (!k_f32 && !out_f32) hipLaunchKernelGGL((k_prolong_bricks<double, double>), g, b, 0, s, a);
-  else if (k_f32 && out_f32) hipLaunchKernelGGL((k_prolong_bricks<float, float>), g, b, 0, s, a);
-  else if (k_f32) hipLaunchKernelGGL((k_prolong_bricks<float, double>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_prolong_bricks<double, float>), g, b, 0, s, a);
+  if (nin != 5) {   // buffer zones: FP64 state vectors only
+    if (k_f32 || out_f32 || (nin != 1 && nin != 3)) return hipErrorInvalidValue;
+    if (nin == 1) hipLaunchKernelGGL((k_prolong_bricks<1, double, double>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_prolong_bricks<3, double, double>), g, b, 0, s, a);
+    return hipGetLastError();
+  }
+  if (!k_f32 && !out_f32) hipLaunchKernelGGL((k_prolong_bricks<5, double, double>), g, b, 0, s, a);
+  else if (k_f32 && out_f32) hipLaunchKernelGGL((k_prolong_bricks<5, float, float>), g, b, 0, s, a);
+  else if (k_f32) hipLaunchKernelGGL((k_prolong_bricks<5, float, double>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_prolong_bricks<5, double, float>), g, b, 0, s, a);
   return hipGetLastError();
 }
 

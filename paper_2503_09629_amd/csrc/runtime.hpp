@@ -52,12 +52,12 @@ struct LevelDev {
   int nyh = 1;
   bool has_child = false;
   // arena offsets (bytes)
-  size_t o_y[2], o_y32[2], o_k[4], o_yh[8], o_boxes, o_prefix, o_sync, o_prolong, o_rblist,
+  size_t o_y[3], o_y32[2], o_k[4], o_yh[8], o_boxes, o_prefix, o_sync, o_prolong, o_rblist,
       o_rbfirst, o_phys, o_restr, o_tiles, o_btiles, o_ys, o_bricks;
   // device pointers after binding.  y: FP64 state; y32: its FP32 shadow
   // (mixed mode only); k and Yh hold the stencil type (FP64, or FP32 in
   // mixed mode).
-  double *y[2] = {nullptr, nullptr};
+  double* y[3] = {nullptr, nullptr, nullptr};
   float* y32[2] = {nullptr, nullptr};
   void* k[4] = {nullptr, nullptr, nullptr, nullptr};
   void* Yh[8] = {nullptr};
@@ -74,6 +74,8 @@ struct LevelDev {
   TileDev* d_tiles = nullptr;
   TileDev* d_btiles = nullptr;
   int cur = 0;
+  int nbuf = 2;                      // state buffers in rotation (3 with buffer zones)
+  int64_t steps_done = 0;            // RK4 steps taken (buffer zones: time-interpolation history)
   double t = 0.0;
   double dx = 0.0, dt = 0.0;
 };
@@ -99,8 +101,8 @@ struct sc_ctx {
   double* d_norm_out = nullptr;
   int grid_cap = 0;  // persistent grid size cap for stage kernels
   int64_t launches = 0;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
-  bool graph_ready[2] = {false, false};
+  hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};   // one per level-0 buffer index
+  bool graph_ready[3] = {false, false, false};
   double weights[2][5][4];  // [substep][fill-1][i]
   // stage-kernel timing with HIP events (eager modes)
   bool profiling = false;

@@ -12,7 +12,8 @@ import paper_2503_09629_amd as sc
 from oracle.evolve import OracleRun
 from oracle.hierarchy import Hierarchy
 from workloads import (HierarchySpec, config_c1, config_c2, config_c3, ensemble_c1,
-                       ensemble_on_spec, gaussian_on_spec, pulses_on_spec, standing_wave_on_spec, config_e1, spherical_gaussian_on_spec)
+                       ensemble_on_spec, gaussian_on_spec, pulses_on_spec, standing_wave_on_spec, config_e1, spherical_gaussian_on_spec,
+                       grown_for_buffer_zones)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -299,3 +300,36 @@ def test_e1_layout_matches_reference(ts):
     ctx.advance(n)
     ref.advance(n)
     print("e1 layout worst rel diff", _compare_all(ctx, ref, arrays=("y", "k1")))
+
+
+# --- buffer zones (the Carpet scheme the paper compares against, Sec. II) ---
+
+def _bz_spec():
+    return grown_for_buffer_zones(
+        HierarchySpec((-1.0,) * 3, 2.0 / 32, (32,) * 3, (True,) * 3,
+                      [[((16,) * 3, (48,) * 3)], [((48,) * 3, (78,) * 3)]]), 10)
+
+
+@pytest.mark.parametrize("exec", [sc.SC_EXEC_BATCHED, sc.SC_EXEC_GRAPH, sc.SC_EXEC_PER_BLOCK])
+def test_buffer_zones_match_reference(exec):
+    """Five coarse steps: the first with linear time interpolation at each
+    level's first step, then quadratic; in graph mode the first runs eagerly
+    and the next four capture and replay the three buffer rotations."""
+    spec = _bz_spec()
+    kw = dict(min_block=16, max_block=48, block_seed=5)
+    ctx = _gpu(spec, exec=exec, time_stepping=sc.SC_BUFFER_ZONES, **kw)
+    ref = OracleRun(Hierarchy(spec, buffer=9, **kw), sigma=0.32, buffer_zones=True)
+    for l in range(spec.nlevels):
+        for v, f in enumerate(pulses_on_spec(spec, l)):
+            ctx.set_initial_data(0, l, v, f)
+            ref.set_data(l, v, f)
+    ctx.advance(2)
+    ctx.advance(3)
+    ref.advance(5)
+    w = _compare_all(ctx, ref, arrays=("y", "yn", "k1", "k2", "k3", "k4"))
+    print("buffer zones exec", exec, "worst rel diff", w)
+    for l in range(spec.nlevels):
+        assert abs(ctx.level_time(l) - ref.t[l]) < 1e-15
+    with pytest.raises(sc.ScError) as e:
+        ctx.step_level(1, 0)
+    assert e.value.code == sc.SC_E_STATE

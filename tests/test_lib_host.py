@@ -3,7 +3,9 @@
 * every function declared in include/subcyc.h is exported;
 * the library's block, ghost, RB and restriction maps are bit-identical to
   the reference builder's (canonical word stream);
-* argument, nesting and state-machine errors come back as status codes.
+* argument, nesting and state-machine errors come back as status codes;
+* with buffer zones (B = 3G) the buffer lists, the restriction pairs without
+  buffer points and the nesting rule against parent buffer points match too.
 """
 import ctypes
 import hashlib
@@ -15,7 +17,7 @@ import pytest
 
 import paper_2503_09629_amd as sc
 from oracle.hierarchy import Hierarchy, NestingError
-from workloads import HierarchySpec, config_c2, config_c3, config_c5
+from workloads import HierarchySpec, config_c2, config_c3, config_c5, grown_for_buffer_zones
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -126,3 +128,47 @@ def test_arena_size_scales_with_members():
                           nmembers=4)
     b = _ctx_maps(spec2, **kw).device_bytes()
     assert 3.5 * a < b < 4.5 * a
+
+
+BZ_SPECS = {
+    "c2-24-grown": (grown_for_buffer_zones(config_c2(24), 10), dict(min_block=16, max_block=48)),
+    "three-level-grown": (grown_for_buffer_zones(
+        HierarchySpec((-1.0,) * 3, 2.0 / 32, (32,) * 3, (True,) * 3,
+                      [[((16,) * 3, (48,) * 3)], [((48,) * 3, (78,) * 3)]]), 10),
+        dict(min_block=16, max_block=48, block_seed=5)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BZ_SPECS))
+def test_buffer_zone_maps_bit_identical_to_reference(name):
+    spec, kw = BZ_SPECS[name]
+    ref = Hierarchy(spec, buffer=9, **kw)
+    assert all(len(b) > 0 for b in ref.buffer[1:])
+    ctx = sc.Context(time_stepping=sc.SC_BUFFER_ZONES)
+    ctx.build_spec(spec, **kw)
+    got = ctx.export_maps()
+    want = ref.export()
+    assert got[1] == 2
+    assert got.shape == want.shape
+    assert hashlib.sha256(got.tobytes()).hexdigest() == hashlib.sha256(want.tobytes()).hexdigest()
+
+
+def test_buffer_zone_nesting_error():
+    # level 2's stencils stay in level 1 but reach its buffer points
+    spec = HierarchySpec((-1.0,) * 3, 2.0 / 32, (32,) * 3, (True,) * 3,
+                         [[((16,) * 3, (48,) * 3)], [((40,) * 3, (86,) * 3)]])
+    Hierarchy(spec, min_block=8, max_block=24)
+    _ctx_maps(spec, min_block=8, max_block=24)
+    with pytest.raises(NestingError):
+        Hierarchy(spec, min_block=8, max_block=24, buffer=9)
+    ctx = sc.Context(time_stepping=sc.SC_BUFFER_ZONES)
+    with pytest.raises(sc.ScError) as e:
+        ctx.build_spec(spec, min_block=8, max_block=24)
+    assert e.value.code == sc.SC_E_NEST
+
+
+def test_buffer_zones_need_wave_fp64():
+    for kw in (dict(precision=sc.SC_MIXED), dict(rhs=sc.SC_RHS_Z4C)):
+        with pytest.raises(sc.ScError) as e:
+            sc.Context(time_stepping=sc.SC_BUFFER_ZONES, **kw)
+        assert e.value.code == sc.SC_E_ARG
