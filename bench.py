@@ -193,7 +193,8 @@ def e1_run(args):
     against the exact solution, subcycled and uniform time steps."""
     import torch
     import paper_2503_09629_amd as sc
-    from workloads import canonical_coords, config_e1, spherical_gaussian, spherical_gaussian_on_spec
+    from workloads import (canonical_coords, config_e1, grown_for_buffer_zones, spherical_gaussian,
+                           spherical_gaussian_on_spec)
     checkpoints = [round(0.4 * (i + 1), 10) for i in range(int(round(args.e1_t / 0.4)))]
     modes = [m.strip() for m in args.e1_modes.split(",") if m.strip()]
     out = {"workload": "scalar wave E1: spherical Gaussian A=1, sigma=0.25/sqrt(2), periodic "
@@ -201,13 +202,19 @@ def e1_run(args):
            "checkpoints": checkpoints, "runs": []}
     for mode in modes:
         uniform = mode == "uniform"
+        buffered = mode == "buffer"
         for n0 in args.e1_n0:
             spec = config_e1(n0)
+            if buffered:
+                # buffer zones: the boxes grow by 10 so that the valid region
+                # (9 buffer layers inside) covers the paper's boxes
+                spec0, spec = spec, grown_for_buffer_zones(spec, 10)
             dt_steps = 0.25 * spec.dx(spec.nlevels - 1 if uniform else 0)
             U = spec.total_points() if uniform else spec.updates_per_coarse_step()
             log(f"e1 {mode} n0={n0}: {spec.total_points()} points, dt {dt_steps:.6g}")
-            ctx = sc.Context(device="cuda:0", exec=sc.SC_EXEC_GRAPH,
-                             time_stepping=sc.SC_UNIFORM_DT if uniform else sc.SC_SUBCYCLED)
+            ts = (sc.SC_UNIFORM_DT if uniform else sc.SC_BUFFER_ZONES if buffered
+                  else sc.SC_SUBCYCLED)
+            ctx = sc.Context(device="cuda:0", exec=sc.SC_EXEC_GRAPH, time_stepping=ts)
             ctx.build_spec(spec, block_seed=1, min_block=16, max_block=48)
             ctx.bind()
             for l in range(spec.nlevels):
@@ -215,6 +222,15 @@ def e1_run(args):
                     ctx.set_initial_data(0, l, v, f)
             lev = spec.nlevels - 1
             x, y, z = canonical_coords(spec, lev)
+            sel = slice(None)
+            if buffered:   # the error is taken on the paper's finest box only
+                (glo, ghi), = spec.fine_boxes[-1]
+                (olo, ohi), = spec0.fine_boxes[-1]
+                n = [ghi[d] - glo[d] + 1 for d in range(3)]
+                idx = np.arange(n[0] * n[1] * n[2]).reshape(n[2], n[1], n[0])
+                sel = idx[olo[2] - glo[2]:ohi[2] - glo[2] + 1, olo[1] - glo[1]:ohi[1] - glo[1] + 1,
+                          olo[0] - glo[0]:ohi[0] - glo[0] + 1].ravel()
+                x, y, z = x[sel], y[sel], z[sel]
             errs, steps_done, T = [], 0, 0.0
             for tc in checkpoints:
                 nsteps = int(round(tc / dt_steps)) - steps_done
@@ -226,7 +242,7 @@ def e1_run(args):
                 steps_done += nsteps
                 t = ctx.level_time(lev)
                 ue, _ = spherical_gaussian(t, x, y, z)
-                e = float(np.abs(ctx.read_back(0, lev, 0) - ue).max())
+                e = float(np.abs(ctx.read_back(0, lev, 0)[sel] - ue).max())
                 errs.append(e)
                 log(f"  t = {t:.4f}: max |u - u_exact| on level {lev} = {e:.4e} "
                     f"({steps_done} steps, {U * steps_done / T:.4g} updates/s)")
@@ -244,6 +260,69 @@ def e1_run(args):
             ratio = a["coarse_dx"] / b["coarse_dx"]
             b["order_vs_previous"] = [float(np.log(ea / eb) / np.log(ratio)) if eb > 0 else None
                                       for ea, eb in zip(a["errors"], b["errors"])]
+    return out
+
+
+def carpet_run(args):
+    """The paper's cost comparison (Sec. II, Fig. 1) on the tower hierarchy:
+    dense-output subcycling on the benchmark boxes against buffer-zone
+    (Carpet) subcycling on the same boxes grown by 10 points per side, whose
+    valid region (the boxes minus 3G = 9 buffer layers) covers the original
+    boxes.  Both in graph mode with autotuned tile shapes."""
+    import torch
+    import paper_2503_09629_amd as sc
+    from workloads import config_c3, grown_for_buffer_zones, pulses_on_spec
+    base = config_c3(args.n0)
+    grown = grown_for_buffer_zones(base, 10)
+    out = {"workload": f"wave, 7-level towers N0={args.n0}: dense output on the benchmark boxes "
+                       f"vs buffer zones on the boxes grown by 10", "runs": []}
+    for name, spec, ts in (("dense-output", base, sc.SC_SUBCYCLED),
+                           ("buffer-zones", grown, sc.SC_BUFFER_ZONES)):
+        t0 = time.perf_counter()
+        ctx = sc.Context(device="cuda:0", exec=sc.SC_EXEC_GRAPH, time_stepping=ts)
+        ctx.build_spec(spec, block_seed=1, min_block=16, max_block=48)
+        tbuild = time.perf_counter() - t0
+        ctx.bind()
+        for l in range(spec.nlevels):
+            for v, f in enumerate(pulses_on_spec(spec, l)):
+                ctx.set_initial_data(0, l, v, f)
+        log(f"carpet: {name}: {spec.total_points()} points, hierarchy built in {tbuild:.1f} s")
+        ctx.autotune(3)
+        nl = spec.nlevels
+        owned = [ctx.counts(l)[1] for l in range(nl)]
+        nrb = [ctx.counts(l)[2] for l in range(nl)]
+        nbuf = [ctx.buffer_count(l) for l in range(nl)]
+        U = sum(owned[l] << l for l in range(nl))
+        if ts == sc.SC_BUFFER_ZONES:
+            # one state vector per fine step into RB and buffer points
+            prolonged = sum((nrb[l] + nbuf[l]) << l for l in range(1, nl))
+        else:
+            # five vectors (y_n, k1..k4) once per parent step into the RB points
+            prolonged = sum(5 * (nrb[l] << (l - 1)) for l in range(1, nl))
+        for i in range(args.carpet_warmup):
+            ctx.advance(1)
+        ctx.synchronize()
+        log(f"carpet: {name}: warm ({args.carpet_warmup} coarse steps)")
+        T = timed(ctx, torch, args.carpet_steps)
+        ms = 1e3 * T / args.carpet_steps
+        log(f"carpet: {name}: {ms:.2f} ms per coarse step, {U * args.carpet_steps / T:.4g} updates/s")
+        fin = ctx.norms(0, nl - 1, 0)
+        out["runs"].append({
+            "scheme": name, "ms_per_coarse_step": ms, "updates_per_coarse_step": U,
+            "updates_per_s": U * args.carpet_steps / T,
+            "owned_points": sum(owned), "buffer_points": sum(nbuf),
+            "valid_points": sum(owned) - sum(nbuf), "rb_points": sum(nrb),
+            "prolonged_points_per_coarse_step": prolonged,
+            "per_level": {"owned": owned, "rb": nrb, "buffer": nbuf},
+            "finest_level_max_abs_u": float(fin[0]), "finite": bool(fin[2] == 0)})
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    d, b = out["runs"]
+    out["dense_over_buffer"] = {
+        "time": d["ms_per_coarse_step"] / b["ms_per_coarse_step"],
+        "prolonged_points": d["prolonged_points_per_coarse_step"] / b["prolonged_points_per_coarse_step"],
+        "rhs_updates": d["updates_per_coarse_step"] / b["updates_per_coarse_step"]}
     return out
 
 
@@ -315,7 +394,10 @@ def main():
                     help="JSON line of an earlier run: take its tile shapes instead of tuning")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--workload", default="wave", choices=("wave", "z4c", "precision", "e1"))
+    ap.add_argument("--workload", default="wave",
+                    choices=("wave", "z4c", "precision", "e1", "carpet"))
+    ap.add_argument("--carpet-steps", type=int, default=8)
+    ap.add_argument("--carpet-warmup", type=int, default=4)
     ap.add_argument("--e1-n0", type=int, nargs="+", default=[375, 450, 540])
     ap.add_argument("--e1-t", type=float, default=1.6)
     ap.add_argument("--e1-modes", default="subcycled,uniform")
@@ -347,6 +429,9 @@ def main():
         return
     if args.workload == "precision":
         print(json.dumps(precision_report(args)), flush=True)
+        return
+    if args.workload == "carpet":
+        print(json.dumps(carpet_run(args)), flush=True)
         return
 
     import torch

@@ -163,6 +163,11 @@ int sc_build_hierarchy(sc_ctx* ctx, int32_t nmembers, const double origin[3], do
 int sc_get_counts(const sc_ctx* ctx, int32_t level, int32_t* nblocks, int64_t* nowned,
                   int64_t* nrb);
 
+/* Per level (one member): number of buffer points (SC_BUFFER_ZONES; 0 in the
+ * other modes and on level 0).  Buffer points are owned points, included in
+ * sc_get_counts' nowned. */
+int sc_buffer_count(const sc_ctx* ctx, int32_t level, int64_t* nbuffer);
+
 /* Canonical little-endian int64 export of all maps; words == NULL returns the
  * size in *nwords.  Layout: header [0x53554243, 1, nlevels, nmembers]; then
  * per level: [level, nblocks, nowned, nrb, nrestrict], the blocks

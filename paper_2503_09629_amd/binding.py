@@ -26,7 +26,7 @@ SC_SUBCYCLED, SC_UNIFORM_DT, SC_BUFFER_ZONES = 0, 1, 2
 
 EXPORTED = [
     "sc_config_default", "sc_create", "sc_destroy", "sc_last_error", "sc_build_hierarchy",
-    "sc_get_counts", "sc_export_maps", "sc_device_bytes", "sc_bind_device_memory",
+    "sc_get_counts", "sc_buffer_count", "sc_export_maps", "sc_device_bytes", "sc_bind_device_memory",
     "sc_set_initial_data", "sc_phys_count", "sc_phys_points", "sc_set_phys_data",
     "sc_hamiltonian", "sc_advance", "sc_step_level", "sc_prolongate", "sc_fill_ghosts",
     "sc_restrict", "sc_read_back", "sc_read_rb", "sc_norms", "sc_check_finite",
@@ -79,6 +79,7 @@ def lib():
             "sc_destroy": [P],
             "sc_build_hierarchy": [P, i32, P, f64, P, P, i32, P, P, u64, i32, i32],
             "sc_get_counts": [P, i32, P, P, P],
+            "sc_buffer_count": [P, i32, P],
             "sc_export_maps": [P, P, P],
             "sc_device_bytes": [P, P],
             "sc_bind_device_memory": [P, P, sz],
@@ -210,6 +211,11 @@ class Context:
         self._check(self.L.sc_get_counts(self.ctx, level, ctypes.byref(nb), ctypes.byref(no),
                                          ctypes.byref(nr)))
         return nb.value, no.value, nr.value
+
+    def buffer_count(self, level: int) -> int:
+        n = ctypes.c_int64()
+        self._check(self.L.sc_buffer_count(self.ctx, level, ctypes.byref(n)))
+        return n.value
 
     def export_maps(self) -> np.ndarray:
         n = ctypes.c_int64()

@@ -1223,6 +1223,14 @@ int sc_get_counts(const sc_ctx* c, int32_t level, int32_t* nblocks, int64_t* now
   return SC_OK;
 }
 
+int sc_buffer_count(const sc_ctx* c, int32_t level, int64_t* nbuffer) {
+  int rc = check_ready(c, 1);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->hier.levels.size() || !nbuffer) return SC_E_ARG;
+  *nbuffer = (int64_t)c->hier.levels[level].buffer.size();
+  return SC_OK;
+}
+
 int sc_export_maps(const sc_ctx* c, int64_t* words, int64_t* nwords) {
   int rc = check_ready(c, 1);
   if (rc) return rc;

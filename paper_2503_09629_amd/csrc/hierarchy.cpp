@@ -82,12 +82,11 @@ bool LevelMaps::owner(const int64_t q[3], int32_t* block, int64_t* offset) const
   return true;
 }
 
-// Buffer points of one level: per box, mark the RB points of the window
-// [lo - B, hi + B] (wrapped into the domain), dilate the marks by B along x,
-// y and z in turn with running counts, and keep the marked box points.
+// Buffer points of one level: per box, mark the RB points that fall in the
+// window [lo - B, hi + B] (each RB point at every periodic image), dilate the
+// marks by B along x, y and z in turn with running counts, and keep the
+// marked box points.
 static void find_buffer(LevelMaps& L, int B) {
-  std::vector<int64_t> rbk(L.rb.size());
-  for (size_t i = 0; i < L.rb.size(); ++i) rbk[i] = rb_key(L.rb[i].data());   // ascending
   std::vector<std::array<int64_t, 3>> pts;
   for (const IBox& bx : L.boxes) {
     int64_t n[3], lo[3];
@@ -96,15 +95,22 @@ static void find_buffer(LevelMaps& L, int B) {
       lo[d] = bx.lo[d] - B;
     }
     std::vector<uint8_t> m((size_t)(n[0] * n[1] * n[2]), 0), t(m.size());
-    int64_t w[3], q[3];
-    size_t i = 0;
-    for (w[2] = 0; w[2] < n[2]; ++w[2])
-      for (w[1] = 0; w[1] < n[1]; ++w[1])
-        for (w[0] = 0; w[0] < n[0]; ++w[0], ++i) {
-          const int64_t p[3] = {lo[0] + w[0], lo[1] + w[1], lo[2] + w[2]};
-          L.wrap(p, q);
-          if (!L.outside(q) && std::binary_search(rbk.begin(), rbk.end(), rb_key(q))) m[i] = 1;
+    for (const auto& q : L.rb) {
+      // window coordinates of q and of its periodic images
+      int64_t c[3][3];
+      int nc[3];
+      for (int d = 0; d < 3; ++d) {
+        nc[d] = 0;
+        const int nk = L.periodic[d] ? 1 : 0;
+        for (int k = -nk; k <= nk; ++k) {
+          const int64_t v = q[d] + k * L.N[d] - lo[d];
+          if (v >= 0 && v < n[d]) c[d][nc[d]++] = v;
         }
+      }
+      for (int a = 0; a < nc[2]; ++a)
+        for (int b = 0; b < nc[1]; ++b)
+          for (int e = 0; e < nc[0]; ++e) m[(size_t)((c[2][a] * n[1] + c[1][b]) * n[0] + c[0][e])] = 1;
+    }
     const int64_t stride[3] = {1, n[0], n[0] * n[1]};
     for (int d = 0; d < 3; ++d) {
       // t = 1 where some mark lies within B along axis d

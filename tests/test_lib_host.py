@@ -148,6 +148,7 @@ def test_buffer_zone_maps_bit_identical_to_reference(name):
     ctx.build_spec(spec, **kw)
     got = ctx.export_maps()
     want = ref.export()
+    assert [ctx.buffer_count(l) for l in range(spec.nlevels)] == [len(b) for b in ref.buffer]
     assert got[1] == 2
     assert got.shape == want.shape
     assert hashlib.sha256(got.tobytes()).hexdigest() == hashlib.sha256(want.tobytes()).hexdigest()
