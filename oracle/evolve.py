@@ -152,13 +152,22 @@ def time_interp_weights(theta: Fraction, history: bool):
     return (Fraction(0), 1 - th, th)
 
 
-class _Prolongation:
-    """Gather plan of the prolongation into a list of fine points (default:
-    the level's RB list)."""
+def dense_ghost_value(Py, Pk, w, H):
+    """Ghost stage value from the prolonged parent data (Sec. II dense output):
+    P[y_n] + H * (((w1 P[k1] + w2 P[k2]) + w3 P[k3]) + w4 P[k4])."""
+    return Py + H * (((w[0] * Pk[0] + w[1] * Pk[1]) + w[2] * Pk[2]) + w[3] * Pk[3])
 
-    def __init__(self, hier: Hierarchy, l: int, parent: _LevelState, pts=None):
+
+class Prolongation:
+    """Gather plan of the prolongation into a list of fine points (default:
+    the level's RB list).  index_of, if given, maps parent global indices
+    (k, 3) to positions in the arrays passed to apply() (default: the parent
+    level's per-block storage)."""
+
+    def __init__(self, hier: Hierarchy, l: int, parent: _LevelState, pts=None,
+                 index_of=None, vstride=None):
         rb = hier.rb[l] if pts is None else pts
-        plev = hier.levels[l - 1]
+        plev = hier.levels[l - 1] if hier is not None else None
         self.n = len(rb)
         self.par = np.ascontiguousarray(
             ((rb[:, 0] % 2) | ((rb[:, 1] % 2) << 1) | ((rb[:, 2] % 2) << 2)).astype(np.int64))
@@ -179,14 +188,17 @@ class _Prolongation:
             Y = base[:, 1][:, None, None, None] + offs[1][None, None, :, None]
             Z = base[:, 2][:, None, None, None] + offs[2][None, :, None, None]
             X, Y, Z = np.broadcast_arrays(X, Y, Z)       # (n, sz, sy, sx): z-major order
-            pts = plev.wrap(np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1))
-            blk, off = plev.owner(pts)
-            assert (blk >= 0).all()
-            flat = parent.flat_offset(blk, off).reshape(len(sel), -1)
+            pts = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+            if index_of is not None:
+                flat = np.asarray(index_of(pts), dtype=np.int64).reshape(len(sel), -1)
+            else:
+                blk, off = plev.owner(plev.wrap(pts))
+                assert (blk >= 0).all()
+                flat = parent.flat_offset(blk, off).reshape(len(sel), -1)
             m = flat.shape[1]
             pos = self.start[sel][:, None] + np.arange(m)[None, :]
             self.idx[pos.ravel()] = flat.ravel()
-        self.vstride = parent.total
+        self.vstride = parent.total if vstride is None else vstride
 
     def apply(self, V: np.ndarray) -> np.ndarray:
         out = np.empty((V.shape[0], self.n))
@@ -233,7 +245,7 @@ class OracleRun:
             lo = hier.levels[l].blocks[:, 0, :].astype(np.float64)
             o = np.array(self.spec.origin)[None, :] + lo * self.spec.dx(l)
             self.block_origin.append(np.ascontiguousarray(o.ravel()))
-        self.pro = [None] + [_Prolongation(hier, l, self.st[l - 1]) for l in range(1, self.L)]
+        self.pro = [None] + [Prolongation(hier, l, self.st[l - 1]) for l in range(1, self.L)]
         self.P = [None] * self.L           # prolonged (y_n, k1..k4) per level
         self.theta0 = [0.0] * self.L
         self.t = [0.0] * self.L
@@ -245,7 +257,7 @@ class OracleRun:
             self.bz_dst = [None]
             for l in range(1, self.L):
                 pts = np.concatenate([hier.rb[l], hier.buffer[l]])
-                self.bz_pro.append(_Prolongation(hier, l, self.st[l - 1], pts))
+                self.bz_pro.append(Prolongation(hier, l, self.st[l - 1], pts))
                 blk, off = hier.levels[l].owner(hier.buffer[l])
                 self.bz_dst.append(self.st[l].flat_offset(blk, off))
             for st in self.st:
@@ -291,9 +303,8 @@ class OracleRun:
         if self.buffer_zones:
             return self.P[l]              # the step's prolonged state, every stage
         Py, Pk1, Pk2, Pk3, Pk4 = self.P[l]
-        w1, w2, w3, w4 = self.weights[(stage, self.theta0[l])]
-        H = self.dt[l - 1]
-        return Py + H * (((w1 * Pk1 + w2 * Pk2) + w3 * Pk3) + w4 * Pk4)
+        return dense_ghost_value(Py, (Pk1, Pk2, Pk3, Pk4), self.weights[(stage, self.theta0[l])],
+                                 self.dt[l - 1])
 
     def fill(self, l: int, A: np.ndarray, stage: int) -> None:
         st = self.st[l]
