@@ -1,6 +1,8 @@
-"""GPU parity at the benchmark's full size: the 7-level towers at N0 = 128
-(27,424,754 owned points) in the launch configuration the benchmark times
-(autotuned tile shapes; graph mode for whole coarse steps).
+"""GPU parity at the benchmark configurations' full sizes: the 7-level towers
+at N0 = 128 (27,424,754 owned points) in the launch configuration the
+benchmark times (autotuned tile shapes; graph mode for whole coarse steps),
+its FP32-shadow variant, the single-level and two-level wave runs, and the
+7-level Z4c puncture hierarchy (8,581,008 points, 22 variables).
 
 The reference cannot evolve this hierarchy in seconds, so:
 * level 0's RK4 step (y_{n+1} and k1..k4) is checked at sampled points, each
@@ -12,7 +14,12 @@ The reference cannot evolve this hierarchy in seconds, so:
   prolongation and dense-output combination of level 0's y_n and k1..k4;
 * a whole coarse step is compared bitwise between the benchmark
   configuration and per-block launches (the tiling must not change a bit);
-* after the coarse step every restricted parent point equals its child value.
+* after the coarse step every restricted parent point equals its child value;
+* the FP32-shadow run stays within the stated bound of the FP64 run;
+* the single-level run to t = 1 and the two-level run at coarse 64^3 are
+  small enough for the reference to evolve whole;
+* Z4c: level 0's step at sampled interior points against reference patch
+  runs, and the FP32 right-hand side within its bound after a coarse step.
 """
 from fractions import Fraction
 
@@ -23,7 +30,9 @@ import paper_2503_09629_amd as sc
 from oracle.dense import ghost_weights_f64
 from oracle.evolve import OracleRun, Prolongation, dense_ghost_value
 from oracle.hierarchy import Hierarchy
-from workloads import HierarchySpec, config_c3, pulses_on_spec
+from workloads import (HierarchySpec, brill_lindquist, brill_lindquist_on_spec, config_c1,
+                       config_c2, config_c3, config_c5, gaussian_on_spec, pulses_on_spec,
+                       standing_wave_on_spec)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -133,13 +142,21 @@ def _canon_index(spec, l, pts):
     return out
 
 
-def test_coarse_step_graph_equals_per_block_and_restriction(towers):
+@pytest.fixture(scope="module")
+def towers_step(towers):
+    """One coarse step of the towers in the benchmark configuration (FP64)."""
     spec, data = towers
     g = _ctx(spec, data, sc.SC_EXEC_GRAPH, tune=True)
     g.advance(1)
     yg = [[g.read_back(0, l, v) for v in range(2)] for l in range(spec.nlevels)]
     tg = [g.level_time(l) for l in range(spec.nlevels)]
     g.close()
+    return yg, tg
+
+
+def test_coarse_step_graph_equals_per_block_and_restriction(towers, towers_step):
+    spec, data = towers
+    yg, tg = towers_step
     p = _ctx(spec, data, sc.SC_EXEC_PER_BLOCK)
     p.advance(1)
     for l in range(spec.nlevels):
@@ -159,3 +176,148 @@ def test_coarse_step_graph_equals_per_block_and_restriction(towers):
             for v in range(2):
                 assert np.array_equal(yg[l - 1][v][ci], yg[l][v][fi]), (l, v)
     print("restriction holds on every level pair", flush=True)
+
+
+def test_mixed_full_size_within_bound(towers, towers_step):
+    """The FP32-shadow variant of the towers (the benchmark's mixed line) after
+    one coarse step: |mixed - fp64| <= t * 32 eps32 max|u| / h_finest^2 per
+    variable and level (the bound derived in test_gpu_mixed)."""
+    spec, data = towers
+    yg, tg = towers_step
+    ctx = sc.Context(device="cuda:0", exec=sc.SC_EXEC_GRAPH, precision=sc.SC_MIXED)
+    ctx.build_spec(spec, block_seed=1, min_block=16, max_block=48)
+    ctx.bind()
+    for l in range(spec.nlevels):
+        for v in range(2):
+            ctx.set_initial_data(0, l, v, data[l][v])
+    ctx.autotune(3)
+    ctx.advance(1)
+    h = spec.dx(spec.nlevels - 1)
+    for l in range(spec.nlevels):
+        bound = tg[0] * 32 * 2.0 ** -24 * np.abs(yg[l][0]).max() / (h * h)
+        for v in range(2):
+            err = np.abs(ctx.read_back(0, l, v) - yg[l][v]).max()
+            print(f"mixed level {l} var {v}: {err:.3e} (bound {bound:.3e})", flush=True)
+            assert 0 < err <= bound, (l, v, err, bound)
+    ctx.close()
+
+
+def _whole(spec, data_fn, ncoarse, **kw):
+    ctx = sc.Context(device="cuda:0", exec=sc.SC_EXEC_GRAPH)
+    ctx.build_spec(spec, **kw)
+    ctx.bind()
+    ref = OracleRun(Hierarchy(spec, **kw), sigma=0.32)
+    for l in range(spec.nlevels):
+        for v, f in enumerate(data_fn(spec, l)):
+            ctx.set_initial_data(0, l, v, f)
+            ref.set_data(l, v, f)
+    ctx.autotune(3)
+    ctx.advance(ncoarse)
+    ref.advance(ncoarse)
+    worst = 0.0
+    for l in range(spec.nlevels):
+        assert ctx.level_time(l) == ref.t[l]
+        for v in range(2):
+            b = ref.get(l, v)
+            e = np.abs(ctx.read_back(0, l, v) - b).max() / np.abs(b).max()
+            assert e <= TOL, (l, v, e)
+            worst = max(worst, e)
+    ctx.close()
+    return worst
+
+
+def test_single_level_to_t1_matches_reference():
+    """32^3 periodic standing wave, dt = 0.25 dx, 64 steps to t = 1."""
+    w = _whole(config_c1(32), standing_wave_on_spec, 64, min_block=16, max_block=48)
+    print("single level to t = 1: worst rel diff", w)
+
+
+def test_two_level_coarse64_matches_reference():
+    """Coarse 64^3 with the fine box [-1/2, 1/2]^3 (65^3 fine points), Gaussian
+    pulse, 4 coarse steps."""
+    w = _whole(config_c2(64), gaussian_on_spec, 4, min_block=16, max_block=48)
+    print("two levels, coarse 64^3: worst rel diff", w)
+
+
+@pytest.fixture(scope="module")
+def punctures():
+    spec = config_c5(96)
+    print("full-size Z4c:", spec.total_points(), "points", flush=True)
+    return spec, [brill_lindquist_on_spec(spec, l) for l in range(spec.nlevels)]
+
+
+def _z4c_ctx(spec, data, precision=sc.SC_FP64):
+    ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=sc.SC_EXEC_GRAPH,
+                     precision=precision)
+    ctx.build_spec(spec)
+    ctx.bind()
+    for l in range(spec.nlevels):
+        for v in range(22):
+            ctx.set_initial_data(0, l, v, data[l][v])
+        p = ctx.phys_points(l)
+        if len(p):
+            vals = brill_lindquist(p[:, 0], p[:, 1], p[:, 2])
+            for v in range(22):
+                ctx.set_phys_data(0, l, v, vals[v])
+    return ctx
+
+
+def test_z4c_level0_step_sampled(punctures):
+    """Level 0 of the puncture hierarchy (97^3 points, frozen outer ghosts):
+    one RK4 step at 6 sampled interior points against reference runs on 31^3
+    patches whose edges are exact at stage 1 and 15 points from the centre."""
+    spec, data = punctures
+    ctx = _z4c_ctx(spec, data)
+    ctx.step_level(0, 0)
+    n = spec.ncells0[0] + 1
+    got = [ctx.read_back(0, 0, v).reshape(n, n, n) for v in range(22)]
+    gk1 = [ctx.read_back(0, 0, v, sc.SC_ARR_K1).reshape(n, n, n) for v in range(22)]
+    u0 = [data[0][v].reshape(n, n, n) for v in range(22)]
+    R = 15
+    rng = np.random.default_rng(5)
+    worst = 0.0
+    for p in rng.integers(R + 3, n - R - 3, size=(6, 3)):
+        corner = np.asarray(spec.origin) + (p - R) * spec.dx0
+        pspec = HierarchySpec(tuple(corner), spec.dx0, (2 * R,) * 3, (False,) * 3, [])
+        run = OracleRun(Hierarchy(pspec, min_block=16, max_block=48), rhs="z4c")
+        sl = tuple(slice(p[d] - R, p[d] + R + 1) for d in (2, 1, 0))
+        for v in range(22):
+            run.set_data(0, v, u0[v][sl].ravel())
+        q = np.rint((run.phys_coords(0) - corner[None, :]) / spec.dx0).astype(np.int64)
+        g = q + (p - R)[None, :]
+        run.set_phys(0, np.stack([u0[v][g[:, 2], g[:, 1], g[:, 0]] for v in range(22)]))
+        run.advance(1)
+        c = (R * (2 * R + 1) + R) * (2 * R + 1) + R
+        for v in range(22):
+            for arr, a, ref in ((got, "y", run.get(0, v)[c]), (gk1, "k1", run.get(0, v, "k1")[c])):
+                s_ = max(np.abs(arr[v]).max(), 1e-300)
+                e = abs(arr[v][p[2], p[1], p[0]] - ref) / s_
+                assert e <= TOL, (tuple(p), v, a, e)
+                worst = max(worst, e)
+    print("z4c level-0 step at 6 sampled points: worst rel diff", worst, flush=True)
+    ctx.close()
+
+
+def test_z4c_fp32_rhs_full_size_within_bound(punctures):
+    """After one coarse step of the 7-level puncture hierarchy the FP32
+    right-hand side stays within t * 32 eps32 max|y| / h_finest^2 of FP64."""
+    spec, data = punctures
+    out, t = {}, None
+    for prec in (sc.SC_FP64, sc.SC_MIXED):
+        ctx = _z4c_ctx(spec, data, prec)
+        ctx.advance(1)
+        out[prec] = [[ctx.read_back(0, l, v) for v in range(22)] for l in range(spec.nlevels)]
+        t = ctx.level_time(0)
+        ctx.close()
+    eps32 = float(np.finfo(np.float32).eps)
+    hf = spec.dx(spec.nlevels - 1)
+    ymax = max(np.abs(a).max() for lev in out[sc.SC_FP64] for a in lev)
+    bound = t * 32.0 * eps32 * ymax / hf ** 2
+    worst = 0.0
+    for l in range(spec.nlevels):
+        for v in range(22):
+            d = np.abs(out[sc.SC_MIXED][l][v] - out[sc.SC_FP64][l][v]).max()
+            assert np.isfinite(d) and d <= bound, (l, v, d, bound)
+            worst = max(worst, d)
+    print("z4c full size fp32-rhs worst |mixed - fp64|", worst, "bound", bound, flush=True)
+    assert worst > 0.0
