@@ -216,15 +216,19 @@ class OracleRun:
     """Reference evolution of one member of a hierarchy.
 
     rhs: "wave" (variables u, Pi) or "z4c" (22 variables, Sec. III.A; see
-    oracle/z4c.c).  sigma: Kreiss-Oliger strength.  cfl: dt_l = cfl * dx_l.
+    oracle/z4c.c).  fd_order: 4, or 8 for the wave system's eighth-order
+    Laplacian (oracle/stencil.c; needs a hierarchy with G >= 4).  sigma: Kreiss-Oliger strength.  cfl: dt_l = cfl * dx_l.
     z4c: kappa1, kappa2, eta_c, eta_o, eta_s.
     """
 
     def __init__(self, hier: Hierarchy, rhs: str = "wave", sigma: float = 0.32,
                  cfl: float = 0.25, z4c: dict = None, subcycling: bool = True,
-                 buffer_zones: bool = False):
+                 buffer_zones: bool = False, fd_order: int = 4):
         if rhs not in ("wave", "z4c"):
             raise ValueError(rhs)
+        if fd_order not in (4, 8) or (fd_order == 8 and (rhs != "wave" or hier.G < 4)):
+            raise ValueError("fd_order 8 needs the wave system and G >= 4")
+        self.fd_order = fd_order
         if buffer_zones and (not subcycling or hier.B <= 0):
             raise ValueError("buffer zones need subcycling and a hierarchy with buffer points")
         self.rhs_kind = rhs
@@ -320,8 +324,9 @@ class OracleRun:
     def rhs(self, l: int, Y: np.ndarray, k: np.ndarray) -> None:
         st = self.st[l]
         if self.rhs_kind == "wave":
-            self.lib.orc_wave_rhs(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
-                                  cbuild.ptr(Y), cbuild.ptr(k), self.dx[l], self.sigma)
+            f = self.lib.orc_wave_rhs8 if self.fd_order == 8 else self.lib.orc_wave_rhs
+            f(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total, cbuild.ptr(Y), cbuild.ptr(k),
+              self.dx[l], self.sigma)
         else:
             self.lib.orc_z4c_rhs(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
                                  cbuild.ptr(Y), cbuild.ptr(k), self.dx[l],

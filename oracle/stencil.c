@@ -18,6 +18,11 @@
  * Kreiss-Oliger dissipation with r = 4:
  *   Q u = (-1)^(r/2) sigma / 2^(r+2) * sum_i h^(r+1) D+^3 D-^3 u
  *       = sigma/(64 h) * sum_i (u[-3] - 6u[-2] + 15u[-1] - 20u[0] + 15u[+1] - 6u[+2] + u[+3])
+ * Eighth order (the production stencil, Sec. III.C; orc_wave_rhs8): per dimension
+ *   (-9u[-4] + 128u[-3] - 1008u[-2] + 8064u[-1] - 14350u[0] + 8064u[+1]
+ *    - 1008u[+2] + 128u[+3] - 9u[+4]), summed x + y + z, times 1/(5040 h^2)
+ *   (the centred weights -1/560, 8/315, -1/5, 8/5, -205/72 over 5040), with the
+ *   same fifth-order (r = 4) dissipation; needs G >= 4.
  * RK4 (Eqs. rk1-rk5): Y_{s+1} = y_n + (c_{s+1} dt) k_s with c = 1/2, 1/2, 1;
  *   y_{n+1} = y_n + (dt/6) * (((k1 + 2 k2) + 2 k3) + k4).
  */
@@ -55,6 +60,54 @@ void orc_wave_rhs(int nb, const int64_t* desc, int G, int64_t vstride, const dou
           const double ly = d2(P(U, o - 2 * sy), P(U, o - sy), P(U, o), P(U, o + sy), P(U, o + 2 * sy));
           const double lz = d2(P(U, o - 2 * sz), P(U, o - sz), P(U, o), P(U, o + sz), P(U, o + 2 * sz));
           const double lap = ((lx + ly) + lz) * clap;
+          double q[2];
+          for (int v = 0; v < 2; ++v) {
+            const double* A = v == 0 ? U : PI;
+            const double kx = ko(P(A, o - 3 * sx), P(A, o - 2 * sx), P(A, o - sx), P(A, o),
+                                 P(A, o + sx), P(A, o + 2 * sx), P(A, o + 3 * sx));
+            const double ky = ko(P(A, o - 3 * sy), P(A, o - 2 * sy), P(A, o - sy), P(A, o),
+                                 P(A, o + sy), P(A, o + 2 * sy), P(A, o + 3 * sy));
+            const double kz = ko(P(A, o - 3 * sz), P(A, o - 2 * sz), P(A, o - sz), P(A, o),
+                                 P(A, o + sz), P(A, o + 2 * sz), P(A, o + 3 * sz));
+            q[v] = cko * ((kx + ky) + kz);
+          }
+          KU[o] = P(PI, o) + q[0];
+          KP[o] = lap + q[1];
+        }
+  }
+}
+
+static inline double d8(double m4, double m3, double m2, double m1, double c, double p1,
+                        double p2, double p3, double p4) {
+  return (((((((-9.0 * m4 + 128.0 * m3) - 1008.0 * m2) + 8064.0 * m1) - 14350.0 * c) +
+            8064.0 * p1) - 1008.0 * p2) + 128.0 * p3) - 9.0 * p4;
+}
+
+void orc_wave_rhs8(int nb, const int64_t* desc, int G, int64_t vstride, const double* Y,
+                   double* k, double h, double sigma) {
+  const double clap = 1.0 / (5040.0 * h * h);
+  const double cko = sigma / (64.0 * h);
+  for (int b = 0; b < nb; ++b) {
+    const int64_t base = desc[4 * b];
+    const int nx = (int)desc[4 * b + 1], ny = (int)desc[4 * b + 2], nz = (int)desc[4 * b + 3];
+    const int64_t sx = 1, sy = nx + 2 * G, sz = (int64_t)(nx + 2 * G) * (ny + 2 * G);
+    const double* U = Y + base;
+    const double* PI = Y + vstride + base;
+    double* KU = k + base;
+    double* KP = k + vstride + base;
+#pragma omp parallel for schedule(static)
+    for (int z = G; z < G + nz; ++z)
+      for (int y = G; y < G + ny; ++y)
+        for (int x = G; x < G + nx; ++x) {
+          const int64_t o = z * sz + y * sy + x * sx;
+          double l[3];
+          const int64_t st[3] = {sx, sy, sz};
+          for (int d = 0; d < 3; ++d) {
+            const int64_t s = st[d];
+            l[d] = d8(P(U, o - 4 * s), P(U, o - 3 * s), P(U, o - 2 * s), P(U, o - s), P(U, o),
+                      P(U, o + s), P(U, o + 2 * s), P(U, o + 3 * s), P(U, o + 4 * s));
+          }
+          const double lap = ((l[0] + l[1]) + l[2]) * clap;
           double q[2];
           for (int v = 0; v < 2; ++v) {
             const double* A = v == 0 ? U : PI;
