@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define SC_ABI_VERSION 1
+#define SC_ABI_VERSION 2
 
 typedef enum {
   SC_OK = 0,
@@ -108,7 +108,7 @@ typedef struct {
   int32_t rhs;         /* SC_RHS_* */
   int32_t precision;   /* SC_FP64 or SC_MIXED */
   int32_t exec;        /* SC_EXEC_* */
-  int32_t nghost;      /* ghost width; must be 3 (fourth-order FD with r = 4 dissipation) */
+  int32_t nghost;      /* ghost width: 3 for fd_order 4, 4 for fd_order 8 */
   int32_t time_stepping; /* SC_SUBCYCLED (default), SC_UNIFORM_DT or SC_BUFFER_ZONES */
   double ko_sigma;     /* Kreiss-Oliger strength sigma (Sec. III.C), e.g. 0.32 */
   double cfl;          /* dt_l = cfl * dx_l, 0 < cfl <= 0.5 */
@@ -117,9 +117,14 @@ typedef struct {
   double z4c_eta_c;    /* shift damping eta(r) = (eta_c - eta_o) exp(-(r/eta_s)^4) + eta_o, */
   double z4c_eta_o;    /*   r the distance from the coordinate origin; defaults 2, 0.25, 40 */
   double z4c_eta_s;    /*   (Sec. III.A, M = 1) */
+  int32_t fd_order;    /* wave Laplacian order: 4 (default), or 8 with nghost 4 (the
+                          production stencil of Sec. III.C: nine-point centred second
+                          differences, the same fifth-order dissipation; wave RHS,
+                          FP64, SC_SUBCYCLED or SC_UNIFORM_DT) */
+  int32_t reserved;    /* 0 */
 } sc_config;
 
-/* Fill *cfg with the defaults: wave RHS, FP64, batched, nghost 3,
+/* Fill *cfg with the defaults: wave RHS, FP64, batched, nghost 3, fd_order 4,
  * sigma 0.32, cfl 0.25, Z4c kappa1 0.02, kappa2 0, eta 2 / 0.25 / 40. */
 int sc_config_default(sc_config* cfg);
 

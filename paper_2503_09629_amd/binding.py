@@ -21,7 +21,7 @@ SC_FP64, SC_MIXED = 0, 1
 SC_EXEC_PER_BLOCK, SC_EXEC_BATCHED, SC_EXEC_GRAPH = 0, 1, 2
 SC_ARR_Y, SC_ARR_K1, SC_ARR_K2, SC_ARR_K3, SC_ARR_K4, SC_ARR_YN = range(6)
 SC_FILL_Y1, SC_FILL_Y2, SC_FILL_Y3, SC_FILL_Y4, SC_FILL_END = 1, 2, 3, 4, 5
-SC_ABI_VERSION = 1
+SC_ABI_VERSION = 2
 SC_SUBCYCLED, SC_UNIFORM_DT, SC_BUFFER_ZONES = 0, 1, 2
 
 EXPORTED = [
@@ -43,7 +43,8 @@ class ScConfig(ctypes.Structure):
                 ("ko_sigma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("z4c_kappa1", ctypes.c_double), ("z4c_kappa2", ctypes.c_double),
                 ("z4c_eta_c", ctypes.c_double), ("z4c_eta_o", ctypes.c_double),
-                ("z4c_eta_s", ctypes.c_double)]
+                ("z4c_eta_s", ctypes.c_double), ("fd_order", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ScBox(ctypes.Structure):
@@ -132,11 +133,13 @@ class Context:
     def __init__(self, sigma: float = 0.32, cfl: float = 0.25, exec: int = SC_EXEC_BATCHED,
                  precision: int = SC_FP64, stream=None, device: Optional[str] = None,
                  rhs: int = SC_RHS_WAVE, z4c: Optional[dict] = None,
-                 time_stepping: int = SC_SUBCYCLED):
+                 time_stepping: int = SC_SUBCYCLED, fd_order: int = 4):
         self.L = lib()
         cfg = ScConfig()
         self._check(self.L.sc_config_default(ctypes.byref(cfg)), None)
         cfg.time_stepping = time_stepping
+        cfg.fd_order = fd_order
+        cfg.nghost = 4 if fd_order == 8 else 3
         cfg.ko_sigma = sigma
         cfg.cfl = cfl
         cfg.exec = exec

@@ -9,6 +9,7 @@
 #include <numeric>
 
 #include "runtime.hpp"
+#include "wave8.hpp"
 #include "z4c.hpp"
 
 using namespace sc;
@@ -201,6 +202,7 @@ int stencil_parent(const LevelMaps& P, const int64_t q[3]) {
 
 std::string build_layout(sc_ctx* c) {
   const Hierarchy& H = c->hier;
+  const int G = c->G;   // ghost layers = padding of every box array
   const int nm = H.geo.nmembers;
   const int nl = H.geo.nlevels;
   c->lev.assign(nl, LevelDev());
@@ -227,14 +229,14 @@ std::string build_layout(sc_ctx* c) {
       B.nx = (int)bx.n(0);
       B.ny = (int)bx.n(1);
       B.nz = (int)bx.n(2);
-      B.px = B.nx + 2 * kG;
-      B.py = B.ny + 2 * kG;
+      B.px = B.nx + 2 * G;
+      B.py = B.ny + 2 * G;
       for (int d = 0; d < 3; ++d) {
         B.lo[d] = (int)bx.lo[d];
         B.wrapN[d] = (M.periodic[d] && bx.lo[d] == 0 && bx.hi[d] == M.N[d] - 1) ? (int)M.N[d] : 0;
       }
-      B.pad = 0;
-      base += (int64_t)B.px * B.py * (B.nz + 2 * kG);
+      B.pad = G;
+      base += (int64_t)B.px * B.py * (B.nz + 2 * G);
       L.prefix[ib + 1] = L.prefix[ib] + bx.volume();
     }
     L.member_total = base;
@@ -253,11 +255,11 @@ std::string build_layout(sc_ctx* c) {
     std::map<int64_t, int64_t> first;  // RB key -> first halo offset
     for (int ib = 0; ib < L.nb_member; ++ib) {
       const BoxDev& B = b0[ib];
-      for (int z = -kG; z < B.nz + kG; ++z)
-        for (int y = -kG; y < B.ny + kG; ++y)
-          for (int x = -kG; x < B.nx + kG; ++x) {
+      for (int z = -G; z < B.nz + G; ++z)
+        for (int y = -G; y < B.ny + G; ++y)
+          for (int x = -G; x < B.nx + G; ++x) {
             if (x >= 0 && x < B.nx && y >= 0 && y < B.ny && z >= 0 && z < B.nz) continue;
-            const int64_t dst = B.base + ((int64_t)(z + kG) * B.py + (y + kG)) * B.px + (x + kG);
+            const int64_t dst = B.base + ((int64_t)(z + G) * B.py + (y + G)) * B.px + (x + G);
             int64_t p[3] = {B.lo[0] + x, B.lo[1] + y, B.lo[2] + z}, q[3];
             M.wrap(p, q);
             if (M.outside(q)) {
@@ -269,8 +271,8 @@ std::string build_layout(sc_ctx* c) {
             if (ob >= 0) {
               const BoxDev& O = b0[ob];
               const int64_t src = O.base +
-                                  ((q[2] - O.lo[2] + kG) * O.py + (q[1] - O.lo[1] + kG)) * O.px +
-                                  (q[0] - O.lo[0] + kG);
+                                  ((q[2] - O.lo[2] + G) * O.py + (q[1] - O.lo[1] + G)) * O.px +
+                                  (q[0] - O.lo[0] + G);
               sync0.push_back({dst, src});
               continue;
             }
@@ -293,8 +295,8 @@ std::string build_layout(sc_ctx* c) {
       if (ib < 0) return "buffer point outside the level's boxes";
       const BoxDev& B = b0[ib];
       ProlongEntry e;
-      e.dst = B.base + ((q[2] - B.lo[2] + kG) * B.py + (q[1] - B.lo[1] + kG)) * B.px +
-              (q[0] - B.lo[0] + kG);
+      e.dst = B.base + ((q[2] - B.lo[2] + G) * B.py + (q[1] - B.lo[1] + G)) * B.px +
+              (q[0] - B.lo[0] + G);
       for (int d = 0; d < 3; ++d) e.q[d] = (int32_t)q[d];
       e.pbox = stencil_parent(H.levels[l - 1], q.data());
       if (e.pbox < 0) return "prolongation stencil not inside one parent box";
@@ -314,11 +316,11 @@ std::string build_layout(sc_ctx* c) {
         int ib = -1;
         for (int b = 0; b < L.nb_member; ++b)
           if (e.dst >= b0[b].base &&
-              e.dst < b0[b].base + (int64_t)b0[b].px * b0[b].py * (b0[b].nz + 2 * kG))
+              e.dst < b0[b].base + (int64_t)b0[b].px * b0[b].py * (b0[b].nz + 2 * G))
             ib = b;
         const BoxDev& B = b0[ib];
         const int64_t r = e.dst - B.base;
-        const int64_t hx = r % B.px - kG, hy = (r / B.px) % B.py - kG, hz = r / ((int64_t)B.px * B.py) - kG;
+        const int64_t hx = r % B.px - G, hy = (r / B.px) % B.py - G, hz = r / ((int64_t)B.px * B.py) - G;
         const int64_t p[3] = {B.lo[0] + hx, B.lo[1] + hy, B.lo[2] + hz};
         if (p[0] != e.q[0] || p[1] != e.q[1] || p[2] != e.q[2]) {
           rest0.push_back(e);
@@ -522,6 +524,7 @@ std::string build_layout(sc_ctx* c) {
 // Host-side bounds check of every device table before anything is uploaded:
 // each kernel index derived from these tables stays inside its buffers.
 std::string validate_layout(const sc_ctx* c) {
+  const int G = c->G;
   for (size_t l = 0; l < c->lev.size(); ++l) {
     const LevelDev& L = c->lev[l];
     auto in_level = [&](int64_t o) { return o >= 0 && o < L.total; };
@@ -538,7 +541,7 @@ std::string validate_layout(const sc_ctx* c) {
       if (!tile_ok(t, kStageSlotsMax, kStageThreads)) return "block tile outside its box";
     for (const BoxDev& B : L.boxes)
       if (!in_level(B.base) ||
-          B.base + (int64_t)B.px * B.py * (B.nz + 2 * kG) > L.total)
+          B.base + (int64_t)B.px * B.py * (B.nz + 2 * G) > L.total)
         return "box array outside the level arrays";
     for (const SyncEntry& e : L.sync)
       if (!in_level(e.dst) || !in_level(e.src)) return "halo copy entry out of range";
@@ -571,8 +574,8 @@ std::string validate_layout(const sc_ctx* c) {
         const BoxDev& F = L.boxes[bk.fbox];
         const int fn[3] = {F.nx, F.ny, F.nz};
         for (int d = 0; d < 3; ++d)
-          if (bk.n[d] < 1 || bk.n[d] > 8 || bk.a[d] < 0 || bk.a[d] - F.lo[d] < -kG ||
-              bk.a[d] + bk.n[d] - 1 - F.lo[d] >= fn[d] + kG)
+          if (bk.n[d] < 1 || bk.n[d] > 8 || bk.a[d] < 0 || bk.a[d] - F.lo[d] < -G ||
+              bk.a[d] + bk.n[d] - 1 - F.lo[d] >= fn[d] + G)
             return "brick outside its fine box halo";
         for (int z = 0; z < bk.n[2]; ++z)
           for (int y = 0; y < bk.n[1]; ++y)
@@ -838,6 +841,64 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
   return SC_OK;
 }
 
+// Eighth-order wave stage: the combine writes Y_s = y_n + c_s dt k_{s-1} on
+// the owned points into the stage's halo table (whose halo the fills have
+// written), then the stencil kernel reads the table alone.
+int enqueue_wave8_launches(sc_ctx* c, int l, int stage, bool per_block, const void* kprev,
+                           const void* yh) {
+  LevelDev& L = c->lev[l];
+  static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
+  void* table = const_cast<void*>(yh);
+  Z4cCombineArgs cb{};
+  cb.nvars = c->nvars;
+  cb.boxes = L.d_boxes;
+  cb.yn = L.y[L.cur];
+  cb.kprev = stage >= 2 ? kprev : nullptr;
+  cb.Y = table;
+  cb.vstride = L.total;
+  cb.cdt = cnext[stage] * L.dt;
+  Wave8Args a{};
+  a.stage = stage;
+  a.boxes = L.d_boxes;
+  a.Y = static_cast<const double*>(yh);
+  a.yn = L.y[L.cur];
+  a.k1 = static_cast<const double*>(L.k[0]);
+  a.k2 = static_cast<const double*>(L.k[1]);
+  a.k3 = static_cast<const double*>(L.k[2]);
+  // k4 is read only by the prolongation into a finer level
+  a.kout = (stage < 4 || L.has_child) ? static_cast<double*>(L.k[stage - 1]) : nullptr;
+  a.ynew = L.y[nxt(L)];
+  a.vstride = L.total;
+  a.clap = 1.0 / (5040.0 * L.dx * L.dx);
+  a.cko = c->cfg.ko_sigma / (64.0 * L.dx);
+  a.dt6 = L.dt / 6.0;
+  if (!per_block) {
+    const int n = (int)L.tiles.size(), grid = std::min<int>(n, c->grid_cap);
+    cb.tiles = a.tiles = L.d_tiles;
+    cb.ntiles = a.ntiles = n;
+    HIPCHK(c, launch_z4c_combine(cb, grid, false, c->stream));
+    HIPCHK(c, launch_wave8_stage(a, grid, c->stream));
+    c->launches += 2;
+    return SC_OK;
+  }
+  // per block: every block's stage vector must be complete before any block's
+  // stencil reads its neighbours, so all combines go first
+  const int nblk = (int)L.btile_start.size() - 1;
+  for (int b = 0; b < nblk; ++b) {
+    cb.tiles = L.d_btiles + L.btile_start[b];
+    cb.ntiles = L.btile_start[b + 1] - L.btile_start[b];
+    HIPCHK(c, launch_z4c_combine(cb, cb.ntiles, false, c->stream));
+    ++c->launches;
+  }
+  for (int b = 0; b < nblk; ++b) {
+    a.tiles = L.d_btiles + L.btile_start[b];
+    a.ntiles = L.btile_start[b + 1] - L.btile_start[b];
+    HIPCHK(c, launch_wave8_stage(a, a.ntiles, c->stream));
+    ++c->launches;
+  }
+  return SC_OK;
+}
+
 int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
   LevelDev& L = c->lev[l];
   const void* yn = c->mixed ? static_cast<const void*>(L.y32[L.cur]) : L.y[L.cur];
@@ -860,6 +921,7 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
       ++c->launches;
     }
     int rc = c->cfg.rhs == SC_RHS_Z4C ? enqueue_z4c_launches(c, l, s, per_block, kprev, yh)
+             : c->fd_order == 8      ? enqueue_wave8_launches(c, l, s, per_block, kprev, yh)
                                       : enqueue_stage_launches(c, l, s, per_block, yn, kprev, yh);
     if (rc) return rc;
   }
@@ -1106,6 +1168,7 @@ int sc_config_default(sc_config* cfg) {
   cfg->precision = SC_FP64;
   cfg->exec = SC_EXEC_BATCHED;
   cfg->nghost = 3;
+  cfg->fd_order = 4;
   cfg->ko_sigma = 0.32;
   cfg->cfl = 0.25;
   cfg->z4c_kappa1 = 0.02;
@@ -1130,17 +1193,26 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
                      (cfg->time_stepping == SC_SUBCYCLED || cfg->time_stepping == SC_UNIFORM_DT ||
                       (cfg->time_stepping == SC_BUFFER_ZONES && cfg->rhs == SC_RHS_WAVE &&
                        cfg->precision == SC_FP64));
-  if (!rhs_ok || cfg->nghost != 3 || !(cfg->z4c_eta_s > 0.0) || !(cfg->cfl > 0.0 && cfg->cfl <= 0.5) ||
+  // eighth order: wave, FP64, four ghost layers, subcycled or uniform steps
+  const bool order_ok =
+      (cfg->fd_order == 4 && cfg->nghost == 3) ||
+      (cfg->fd_order == 8 && cfg->nghost == 4 && cfg->rhs == SC_RHS_WAVE &&
+       cfg->precision == SC_FP64 && cfg->time_stepping != SC_BUFFER_ZONES);
+  if (!rhs_ok || !order_ok || cfg->reserved != 0 || !(cfg->z4c_eta_s > 0.0) ||
+      !(cfg->cfl > 0.0 && cfg->cfl <= 0.5) ||
       cfg->ko_sigma < 0.0 || (cfg->precision != SC_FP64 && cfg->precision != SC_MIXED) ||
       cfg->exec < 0 || cfg->exec > 2) {
     g_create_error = "unsupported configuration (rhs, time stepping (buffer zones: wave, FP64), "
-                     "nghost 3, 0 < cfl <= 0.5, sigma >= 0, precision, exec)";
+                     "fd_order 4 with nghost 3 or 8 with nghost 4 (wave, FP64, no buffer zones), "
+                     "0 < cfl <= 0.5, sigma >= 0, precision, exec)";
     return SC_E_ARG;
   }
   sc_ctx* c = new sc_ctx();
   c->cfg = *cfg;
   c->mixed = cfg->precision == SC_MIXED;
   c->nvars = cfg->rhs == SC_RHS_Z4C ? 22 : 2;
+  c->G = cfg->nghost;
+  c->fd_order = cfg->fd_order;
   c->esz = c->mixed ? sizeof(float) : sizeof(double);
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   for (int sub = 0; sub < 2; ++sub)
@@ -1663,7 +1735,8 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
   if (reps < 1 || reps > 1000) return fail(c, SC_E_ARG, "reps must be in [1, 1000]");
-  if (c->cfg.rhs != SC_RHS_WAVE) return fail(c, SC_E_STATE, "autotuning covers the wave stencil");
+  if (c->cfg.rhs != SC_RHS_WAVE || c->fd_order != 4)
+    return fail(c, SC_E_STATE, "autotuning covers the fourth-order wave stencil");
   int dev = 0, ncu = 0;
   HIPCHK(c, hipGetDevice(&dev));
   HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));

@@ -1,8 +1,9 @@
 // Device-side tables and kernel entry points.
 //
 // Storage on the GPU: every box of a level (for every ensemble member) is
-// one padded array per variable, owned points plus G = 3 halo layers per
-// side, x fastest, row pitch px = nx + 6, plane pitch px * (ny + 6).  The
+// one padded array per variable, owned points plus G halo layers per side
+// (BoxDev::pad; 3 for the fourth-order stencils, 4 for the eighth-order
+// wave), x fastest, row pitch px = nx + 2G, plane pitch px * (ny + 2G).  The
 // blocks of a box are index ranges of that array, so a ghost point shared
 // between two blocks of the same box is simply the neighbour's owned point:
 // on one GPU the block-boundary exchange costs nothing.  Only the box halo
@@ -20,15 +21,15 @@
 
 namespace sc {
 
-constexpr int kG = 3;
+constexpr int kG = 3;   // stencil radius of the fourth-order kernels (their ghost width)
 
 struct BoxDev {
   int64_t base;         // offset of the padded array within the level arrays
   int32_t nx, ny, nz;   // owned extents
-  int32_t px, py;       // padded row and plane pitches (nx + 6, ny + 6)
+  int32_t px, py;       // padded row and plane pitches (nx + 2 pad, ny + 2 pad)
   int32_t lo[3];        // global index of owned point (0,0,0)
   int32_t wrapN[3];     // >0: this box spans a periodic dimension of N points
-  int32_t pad;
+  int32_t pad;          // ghost layers around the owned points (the context's G)
 };
 
 struct TileDev {

@@ -25,7 +25,7 @@ __device__ __forceinline__ T ko7(T m3, T m2, T m1, T c, T p1, T p2, T p3) {
 }
 
 __device__ __forceinline__ int64_t padded_offset(const BoxDev& B, int x, int y, int z) {
-  return B.base + ((int64_t)(z + kG) * B.py + (y + kG)) * (int64_t)B.px + (x + kG);
+  return B.base + ((int64_t)(z + B.pad) * B.py + (y + B.pad)) * (int64_t)B.px + (x + B.pad);
 }
 
 // Ring of the LDS window of a tile (the 3-point frame around nx x ny owned
@@ -109,7 +109,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
   auto zin = [&](int z) { return (unsigned)z < (unsigned)B.nz; };
   // byte offset of plane z of variable v within the level arrays
   auto plane = [&](int z, int v) -> int64_t {
-    return (int64_t)sizeof(TS) * (B.base + (int64_t)(z + kG) * ps + (int64_t)v * a.vstride);
+    return (int64_t)sizeof(TS) * (B.base + (int64_t)(z + B.pad) * ps + (int64_t)v * a.vstride);
   };
   bool act[S];
   int li[S];
@@ -121,7 +121,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
     const int ic = act[s] ? i : 0;
     const int px = ic % T.nx, py = ic / T.nx;
     li[s] = (py + kG) * W + px + kG;
-    cb[s] = (uint32_t)sizeof(TS) * (uint32_t)((T.y0 + py + kG) * B.px + (T.x0 + px + kG));
+    cb[s] = (uint32_t)sizeof(TS) * (uint32_t)((T.y0 + py + B.pad) * B.px + (T.x0 + px + B.pad));
   }
   const int nring = 6 * W + 6 * T.ny;
   bool ract[RM], rin[RM];
@@ -136,7 +136,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
     rli[k] = ly * W + lx;
     const int x = T.x0 - kG + lx, y = T.y0 - kG + ly;
     rin[k] = (unsigned)x < (unsigned)B.nx && (unsigned)y < (unsigned)B.ny;
-    rb[k] = (uint32_t)sizeof(TS) * (uint32_t)((y + kG) * B.px + (x + kG));
+    rb[k] = (uint32_t)sizeof(TS) * (uint32_t)((y + B.pad) * B.px + (x + B.pad));
   }
   // raw loads of ring plane z0 + DZ j and column plane z0 + DZ (j + 3)
   auto issue = [&](StageRaw<TS, S, RM>& R, int j) {
@@ -217,7 +217,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
     // stage 4 reads the slopes and y_n at the point: issue those loads first
     TS c1[2][S], c2[2][S], c3[2][S];
     double c0[2][S];
-    const int64_t pe = B.base + (int64_t)(z + kG) * ps;   // element offset of the plane
+    const int64_t pe = B.base + (int64_t)(z + B.pad) * ps;   // element offset of the plane
     if constexpr (STAGE == 4) {
       const TS* k1 = static_cast<const TS*>(a.k1);
       const TS* k2 = static_cast<const TS*>(a.k2);
@@ -359,7 +359,7 @@ __device__ __forceinline__ void prolong_one(const ProlongArgs& a, int64_t i) {
     const int base = e.q[d] >> 1;
     int I = odd ? base - 2 + j : base;
     if (P.wrapN[d] > 0) I = ((I % P.wrapN[d]) + P.wrapN[d]) % P.wrapN[d];
-    return (int64_t)(I - P.lo[d] + kG) * pitch[d];
+    return (int64_t)(I - P.lo[d] + P.pad) * pitch[d];
   };
 #pragma unroll
   for (int j = 0; j < NX; ++j) ox[j] = offs(0, OX, j);
@@ -493,8 +493,8 @@ __global__ __launch_bounds__(256) void k_prolong_bricks(BrickArgs a) {
       int I = C0[d] + c[d];
       if (P.wrapN[d] > 0) I = ((I % P.wrapN[d]) + P.wrapN[d]) % P.wrapN[d];
       int loc = I - P.lo[d];
-      loc = loc < -kG ? -kG : (loc > pn[d] + kG - 1 ? pn[d] + kG - 1 : loc);
-      o += (int64_t)(loc + kG) * pitch[d];
+      loc = loc < -P.pad ? -P.pad : (loc > pn[d] + P.pad - 1 ? pn[d] + P.pad - 1 : loc);
+      o += (int64_t)(loc + P.pad) * pitch[d];
     }
     co[j] = o;
     vi[j] = i < ncoarse ? (c[2] * kBrickC + c[1]) * kBrickC + c[0] : -1;
@@ -536,8 +536,8 @@ __global__ __launch_bounds__(256) void k_prolong_bricks(BrickArgs a) {
     zo[e] = q & 1;
     zs[e] = ((zo[e] ? b - 2 : b) * kBrick + fy) * kBrick + fx;
     zw[e] = ok && ((a.b[g].mask[ic >> 6] >> (ic & 63)) & 1);
-    dst[e] = F.base + ((int64_t)(Bk.a[2] + fz - F.lo[2] + kG) * F.py + (Bk.a[1] + fy - F.lo[1] + kG)) *
-                          (int64_t)F.px + (Bk.a[0] + fx - F.lo[0] + kG);
+    dst[e] = F.base + ((int64_t)(Bk.a[2] + fz - F.lo[2] + F.pad) * F.py + (Bk.a[1] + fy - F.lo[1] + F.pad)) *
+                          (int64_t)F.px + (Bk.a[0] + fx - F.lo[0] + F.pad);
   }
   auto load_var = [&](int v, double (&R)[NIN][NL]) {
     const int64_t vo = (int64_t)v * a.pvstride;

@@ -90,6 +90,8 @@ struct sc_ctx {
   sc::Hierarchy hier;
   std::vector<sc::LevelDev> lev;
   int nvars = 2;
+  int G = 3;            // ghost layers (3: fourth-order stencils; 4: eighth-order wave)
+  int fd_order = 4;     // wave Laplacian order (4 or 8)
   bool mixed = false;   // SC_MIXED: FP32 stencil operands
   size_t esz = 8;       // bytes per element of k and Yh arrays
   size_t arena_bytes = 0;

@@ -488,7 +488,7 @@ __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
         p.z = T.z0 + iz;
         p.px = B.px;
         p.pxy = (int64_t)B.px * B.py;
-        p.o = B.base + ((int64_t)(p.z + kG) * B.py + (p.y + kG)) * (int64_t)B.px + (p.x + kG);
+        p.o = B.base + ((int64_t)(p.z + B.pad) * B.py + (p.y + B.pad)) * (int64_t)B.px + (p.x + B.pad);
         point(p);
       }
     }
@@ -559,8 +559,8 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
     for (int ry = ty; ry < T.ny; ry += 256 / kTileMaxX) {
       if (tx >= T.nx) continue;
       for (int iz = 0; iz < T.nz; ++iz) {
-        const int64_t o = B.base + ((int64_t)(T.z0 + iz + kG) * B.py + (T.y0 + ry + kG)) *
-                                       (int64_t)B.px + (T.x0 + tx + kG);
+        const int64_t o = B.base + ((int64_t)(T.z0 + iz + B.pad) * B.py + (T.y0 + ry + B.pad)) *
+                                       (int64_t)B.px + (T.x0 + tx + B.pad);
         TS beta[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) beta[k] = Y[o + (VB + k) * a.vstride];
@@ -607,8 +607,8 @@ __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
     for (int ry = ty; ry < T.ny; ry += 256 / kTileMaxX) {
       if (tx >= T.nx) continue;
       for (int iz = 0; iz < T.nz; ++iz) {
-        const int64_t o = B.base + ((int64_t)(T.z0 + iz + kG) * B.py + (T.y0 + ry + kG)) *
-                                       (int64_t)B.px + (T.x0 + tx + kG);
+        const int64_t o = B.base + ((int64_t)(T.z0 + iz + B.pad) * B.py + (T.y0 + ry + B.pad)) *
+                                       (int64_t)B.px + (T.x0 + tx + B.pad);
         for (int i = 0; i < a.nvars; ++i) {
           const int64_t oi = o + i * a.vstride;
           Y[oi] = kprev ? yn[oi] + cdt * kprev[oi] : yn[oi];

@@ -173,3 +173,24 @@ def test_buffer_zones_need_wave_fp64():
         with pytest.raises(sc.ScError) as e:
             sc.Context(time_stepping=sc.SC_BUFFER_ZONES, **kw)
         assert e.value.code == sc.SC_E_ARG
+
+
+@pytest.mark.parametrize("name", ["two-level-tiny", "three-level-two-boxes", "c2-16"])
+def test_four_ghost_layer_maps_bit_identical_to_reference(name):
+    spec, kw = SPECS[name]
+    ref = Hierarchy(spec, G=4, **kw).export()
+    ctx = sc.Context(fd_order=8)
+    ctx.build_spec(spec, **kw)
+    got = ctx.export_maps()
+    assert got.shape == ref.shape
+    assert hashlib.sha256(got.tobytes()).hexdigest() == hashlib.sha256(ref.tobytes()).hexdigest()
+
+
+def test_eighth_order_configuration_rules():
+    sc.Context(fd_order=8)
+    sc.Context(fd_order=8, time_stepping=sc.SC_UNIFORM_DT)
+    for kw in (dict(precision=sc.SC_MIXED), dict(rhs=sc.SC_RHS_Z4C),
+               dict(time_stepping=sc.SC_BUFFER_ZONES), dict(fd_order=6)):
+        with pytest.raises(sc.ScError) as e:
+            sc.Context(**dict(dict(fd_order=8), **kw))
+        assert e.value.code == sc.SC_E_ARG
