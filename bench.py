@@ -326,6 +326,44 @@ def carpet_run(args):
     return out
 
 
+def fd8_run(args):
+    """The tower hierarchy with the eighth-order Laplacian (four ghost
+    layers, Sec. III.C's production stencil) against the fourth-order run,
+    both in graph mode (the fourth order with autotuned tiles)."""
+    import torch
+    import paper_2503_09629_amd as sc
+    from workloads import config_c3, pulses_on_spec
+    spec = config_c3(args.n0)
+    data = [pulses_on_spec(spec, l) for l in range(spec.nlevels)]
+    U = spec.updates_per_coarse_step()
+    out = {"workload": f"wave, 7-level towers N0={args.n0}, fourth vs eighth order", "runs": []}
+    for order in (4, 8):
+        ctx = sc.Context(device="cuda:0", exec=sc.SC_EXEC_GRAPH, fd_order=order)
+        ctx.build_spec(spec, block_seed=1, min_block=16, max_block=48)
+        ctx.bind()
+        for l in range(spec.nlevels):
+            for v in range(2):
+                ctx.set_initial_data(0, l, v, data[l][v])
+        if order == 4:
+            ctx.autotune(3)
+        for i in range(args.carpet_warmup):
+            ctx.advance(1)
+        ctx.synchronize()
+        log(f"fd{order}: warm")
+        T = timed(ctx, torch, args.carpet_steps)
+        ms = 1e3 * T / args.carpet_steps
+        fin = ctx.norms(0, spec.nlevels - 1, 0)
+        log(f"fd{order}: {ms:.2f} ms per coarse step, {U * args.carpet_steps / T:.4g} updates/s")
+        out["runs"].append({"fd_order": order, "ms_per_coarse_step": ms,
+                            "updates_per_s": U * args.carpet_steps / T,
+                            "arena_gib": ctx.device_bytes() / 2 ** 30,
+                            "finest_level_max_abs_u": float(fin[0]), "finite": bool(fin[2] == 0)})
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def precision_report(args):
     """Mixed vs FP64: max-norm difference per level and observed orders."""
     import paper_2503_09629_amd as sc
@@ -395,7 +433,7 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--workload", default="wave",
-                    choices=("wave", "z4c", "precision", "e1", "carpet"))
+                    choices=("wave", "z4c", "precision", "e1", "carpet", "fd8"))
     ap.add_argument("--carpet-steps", type=int, default=8)
     ap.add_argument("--carpet-warmup", type=int, default=4)
     ap.add_argument("--e1-n0", type=int, nargs="+", default=[375, 450, 540])
@@ -432,6 +470,9 @@ def main():
         return
     if args.workload == "carpet":
         print(json.dumps(carpet_run(args)), flush=True)
+        return
+    if args.workload == "fd8":
+        print(json.dumps(fd8_run(args)), flush=True)
         return
 
     import torch
