@@ -9,7 +9,6 @@
 #include <numeric>
 
 #include "runtime.hpp"
-#include "wave8.hpp"
 #include "z4c.hpp"
 
 using namespace sc;
@@ -131,11 +130,19 @@ void split_even(int64_t n, int64_t maxlen, std::vector<std::pair<int, int>>* out
 // Largest tile height for tiles at most nxm points wide: at most
 // kStageSlots owned points per thread, an LDS window of at most kWinCap points
 // and at most kRingSlots ring points per thread.
-int tile_ty_cap(int nxm, int slots, int threads) {
+int tile_ty_cap(int nxm, int slots, int threads, int R) {
   int t = threads * slots / nxm;
-  t = std::min(t, stage_win_cap(threads) / (nxm + 2 * kG) - 2 * kG);
-  t = std::min(t, (threads * stage_ring_slots(threads) - 6 * (nxm + 2 * kG)) / 6);
+  t = std::min(t, stage_win_cap(threads) / (nxm + 2 * R) - 2 * R);
+  t = std::min(t, (threads * stage_ring_slots(threads) - 2 * R * (nxm + 2 * R)) / (2 * R));
   return std::max(t, 1);
+}
+
+// Widest tile whose one-row window and ring fit the family's LDS window and
+// ring slots (64 for radius 3; 55 for radius 4).
+int tile_tx_cap(int threads, int R) {
+  const int by_ring = threads * stage_ring_slots(threads) / (2 * R) - 2 * R - 1;
+  const int by_win = stage_win_cap(threads) / (1 + 2 * R) - 2 * R;
+  return std::max(1, std::min(kTileMaxX, std::min(by_ring, by_win)));
 }
 
 // stencil kernel variants: (threads, points per thread, planes of loads in flight)
@@ -145,19 +152,19 @@ bool stage_variant_ok(int slots, int depth, int threads = 256) {
   return (slots == 2 && (depth == 1 || depth == 2)) || (slots == 1 && depth == 2);
 }
 
-bool tile_fits(int nx, int ny, int slots, int threads) {
+bool tile_fits(int nx, int ny, int slots, int threads, int R) {
   return nx >= 1 && ny >= 1 && nx <= kTileMaxX && nx * ny <= threads * slots &&
-         (nx + 2 * kG) * (ny + 2 * kG) <= stage_win_cap(threads) &&
-         6 * (nx + 2 * kG) + 6 * ny <= threads * stage_ring_slots(threads);
+         (nx + 2 * R) * (ny + 2 * R) <= stage_win_cap(threads) &&
+         2 * R * (nx + 2 * R) + 2 * R * ny <= threads * stage_ring_slots(threads);
 }
 
 void tile_region(int box, const int64_t o[3], const int64_t n[3], const TileShape& s,
                  std::vector<TileDev>* out) {
   std::vector<std::pair<int, int>> sx, sy, sz;
-  split_even(n[0], std::min(s.tx, kTileMaxX), &sx);
+  split_even(n[0], std::min(s.tx, tile_tx_cap(s.threads, s.radius)), &sx);
   int nxm = 1;
   for (auto& x : sx) nxm = std::max(nxm, x.second);
-  split_even(n[1], std::min(s.ty, tile_ty_cap(nxm, s.slots, s.threads)), &sy);
+  split_even(n[1], std::min(s.ty, tile_ty_cap(nxm, s.slots, s.threads, s.radius)), &sy);
   split_even(n[2], s.tz, &sz);
   // order: y rows of tiles, then z chunks, then x, so that a contiguous run of
   // the table (one XCD's share) is a slab holding whole z stacks: the halo
@@ -217,6 +224,7 @@ std::string build_layout(sc_ctx* c) {
     L.nb_member = (int)M.boxes.size();
     L.has_child = l + 1 < nl;
     L.nbuf = c->cfg.time_stepping == SC_BUFFER_ZONES ? 3 : 2;
+    L.shape.radius = c->fd_order == 8 ? 4 : 3;
     L.nyh = l == 0 ? 1 : 8;
     // boxes of member 0
     std::vector<BoxDev> b0(L.nb_member);
@@ -531,7 +539,8 @@ std::string validate_layout(const sc_ctx* c) {
     auto tile_ok = [&](const TileDev& t, int slots, int threads) {
       if (t.box < 0 || t.box >= (int)L.boxes.size()) return false;
       const BoxDev& B = L.boxes[t.box];
-      return tile_fits(t.nx, t.ny, slots, threads) && t.nz >= 1 && (t.dir == 0 || t.dir == 1) &&
+      return tile_fits(t.nx, t.ny, slots, threads, L.shape.radius) && t.nz >= 1 &&
+             (t.dir == 0 || t.dir == 1) &&
              t.x0 >= 0 && t.y0 >= 0 && t.z0 >= 0 && t.x0 + t.nx <= B.nx &&
              t.y0 + t.ny <= B.ny && t.z0 + t.nz <= B.nz;
     };
@@ -643,16 +652,21 @@ void plan_arena(sc_ctx* c) {
     L.o_phys = take(sizeof(int64_t) * L.phys.size());
     L.o_restr = take(sizeof(RestrictRegion) * L.restr.size());
     {
-      std::vector<TileDev> most;
-      TileShape sh = L.shape;
-      sh.tz = kTuneTzMin;
-      sh.slots = 1;
-      for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
-        const BoxDev& B = L.boxes[ib];
-        const int64_t o[3] = {0, 0, 0}, n[3] = {B.nx, B.ny, B.nz};
-        tile_region(ib, o, n, sh, &most);
+      // the most tiles any shape the autotuner tries can make
+      L.tiles_capacity = L.tiles.size();
+      for (int tx : {kTileMaxX, 32}) {
+        std::vector<TileDev> most;
+        TileShape sh = L.shape;
+        sh.tx = tx;
+        sh.tz = kTuneTzMin;
+        sh.slots = 1;
+        for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
+          const BoxDev& B = L.boxes[ib];
+          const int64_t o[3] = {0, 0, 0}, n[3] = {B.nx, B.ny, B.nz};
+          tile_region(ib, o, n, sh, &most);
+        }
+        L.tiles_capacity = std::max(L.tiles_capacity, most.size());
       }
-      L.tiles_capacity = std::max(most.size(), L.tiles.size());
     }
     L.o_tiles = take(sizeof(TileDev) * L.tiles_capacity);
     L.o_btiles = take(sizeof(TileDev) * L.btiles.size());
@@ -724,7 +738,8 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
   static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
   a.cdt = cnext[stage] * L.dt;
   a.dt6 = L.dt / 6.0;
-  a.clap = 1.0 / (12.0 * L.dx * L.dx);
+  a.radius = L.shape.radius;
+  a.clap = a.radius == 4 ? 1.0 / (5040.0 * L.dx * L.dx) : 1.0 / (12.0 * L.dx * L.dx);
   a.cko = c->cfg.ko_sigma / (64.0 * L.dx);
   // k4 is read only by the prolongation into a finer level
   a.write_k = (stage < 4 || L.has_child) ? 1 : 0;
@@ -841,64 +856,6 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
   return SC_OK;
 }
 
-// Eighth-order wave stage: the combine writes Y_s = y_n + c_s dt k_{s-1} on
-// the owned points into the stage's halo table (whose halo the fills have
-// written), then the stencil kernel reads the table alone.
-int enqueue_wave8_launches(sc_ctx* c, int l, int stage, bool per_block, const void* kprev,
-                           const void* yh) {
-  LevelDev& L = c->lev[l];
-  static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
-  void* table = const_cast<void*>(yh);
-  Z4cCombineArgs cb{};
-  cb.nvars = c->nvars;
-  cb.boxes = L.d_boxes;
-  cb.yn = L.y[L.cur];
-  cb.kprev = stage >= 2 ? kprev : nullptr;
-  cb.Y = table;
-  cb.vstride = L.total;
-  cb.cdt = cnext[stage] * L.dt;
-  Wave8Args a{};
-  a.stage = stage;
-  a.boxes = L.d_boxes;
-  a.Y = static_cast<const double*>(yh);
-  a.yn = L.y[L.cur];
-  a.k1 = static_cast<const double*>(L.k[0]);
-  a.k2 = static_cast<const double*>(L.k[1]);
-  a.k3 = static_cast<const double*>(L.k[2]);
-  // k4 is read only by the prolongation into a finer level
-  a.kout = (stage < 4 || L.has_child) ? static_cast<double*>(L.k[stage - 1]) : nullptr;
-  a.ynew = L.y[nxt(L)];
-  a.vstride = L.total;
-  a.clap = 1.0 / (5040.0 * L.dx * L.dx);
-  a.cko = c->cfg.ko_sigma / (64.0 * L.dx);
-  a.dt6 = L.dt / 6.0;
-  if (!per_block) {
-    const int n = (int)L.tiles.size(), grid = std::min<int>(n, c->grid_cap);
-    cb.tiles = a.tiles = L.d_tiles;
-    cb.ntiles = a.ntiles = n;
-    HIPCHK(c, launch_z4c_combine(cb, grid, false, c->stream));
-    HIPCHK(c, launch_wave8_stage(a, grid, c->stream));
-    c->launches += 2;
-    return SC_OK;
-  }
-  // per block: every block's stage vector must be complete before any block's
-  // stencil reads its neighbours, so all combines go first
-  const int nblk = (int)L.btile_start.size() - 1;
-  for (int b = 0; b < nblk; ++b) {
-    cb.tiles = L.d_btiles + L.btile_start[b];
-    cb.ntiles = L.btile_start[b + 1] - L.btile_start[b];
-    HIPCHK(c, launch_z4c_combine(cb, cb.ntiles, false, c->stream));
-    ++c->launches;
-  }
-  for (int b = 0; b < nblk; ++b) {
-    a.tiles = L.d_btiles + L.btile_start[b];
-    a.ntiles = L.btile_start[b + 1] - L.btile_start[b];
-    HIPCHK(c, launch_wave8_stage(a, a.ntiles, c->stream));
-    ++c->launches;
-  }
-  return SC_OK;
-}
-
 int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
   LevelDev& L = c->lev[l];
   const void* yn = c->mixed ? static_cast<const void*>(L.y32[L.cur]) : L.y[L.cur];
@@ -921,7 +878,6 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
       ++c->launches;
     }
     int rc = c->cfg.rhs == SC_RHS_Z4C ? enqueue_z4c_launches(c, l, s, per_block, kprev, yh)
-             : c->fd_order == 8      ? enqueue_wave8_launches(c, l, s, per_block, kprev, yh)
                                       : enqueue_stage_launches(c, l, s, per_block, yn, kprev, yh);
     if (rc) return rc;
   }
@@ -1735,8 +1691,7 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
   if (reps < 1 || reps > 1000) return fail(c, SC_E_ARG, "reps must be in [1, 1000]");
-  if (c->cfg.rhs != SC_RHS_WAVE || c->fd_order != 4)
-    return fail(c, SC_E_STATE, "autotuning covers the fourth-order wave stencil");
+  if (c->cfg.rhs != SC_RHS_WAVE) return fail(c, SC_E_STATE, "autotuning covers the wave stencil");
   int dev = 0, ncu = 0;
   HIPCHK(c, hipGetDevice(&dev));
   HIPCHK(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1750,11 +1705,13 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
     float best = 1e30f;
     TileShape best_shape = L.shape;
     std::vector<TileDev> best_tiles = L.tiles;
+    for (int tx : {kTileMaxX, 32})
     for (int threads : {256, 512})
     for (int slots : {2, 1})
     for (int tz : kTuneTz) {
       if (!stage_variant_ok(slots, 2, threads)) continue;
       TileShape sh = L.shape;
+      sh.tx = tx;
       sh.tz = tz;
       sh.slots = slots;
       sh.threads = threads;

@@ -90,9 +90,11 @@ struct StageArgs {
   int64_t vstride;
   double cdt;    // c_s * dt: interior stage vector Y = y_n + cdt * k_{s-1}
   double dt6;    // dt / 6
-  double clap;   // 1 / (12 h^2)
+  double clap;   // 1 / (12 h^2) (radius 3) or 1 / (5040 h^2) (radius 4)
   double cko;    // sigma / (64 h)
   int32_t write_k;
+  int32_t radius;  // stencil radius: 3 (fourth order) or 4 (eighth order, FP64); the
+                   // boxes must be padded by at least this much
 };
 
 struct SyncArgs {

@@ -28,23 +28,31 @@ __device__ __forceinline__ int64_t padded_offset(const BoxDev& B, int x, int y, 
   return B.base + ((int64_t)(z + B.pad) * B.py + (y + B.pad)) * (int64_t)B.px + (x + B.pad);
 }
 
-// Ring of the LDS window of a tile (the 3-point frame around nx x ny owned
-// points): index i in [0, 6(nx+6) + 6ny) -> window coordinates (lx, ly).
+// Ring of the LDS window of a tile (the R-point frame around nx x ny owned
+// points): index i in [0, 2R(nx+2R) + 2R ny) -> window coordinates (lx, ly).
+template <int R>
 __device__ __forceinline__ void ring_coord(int i, int nx, int ny, int* lx, int* ly) {
-  const int W = nx + 2 * kG;
-  if (i < 3 * W) {
+  const int W = nx + 2 * R;
+  if (i < R * W) {
     *ly = i / W;
     *lx = i - *ly * W;
-  } else if (i < 6 * W) {
-    const int j = i - 3 * W;
-    *ly = ny + kG + j / W;
+  } else if (i < 2 * R * W) {
+    const int j = i - R * W;
+    *ly = ny + R + j / W;
     *lx = j % W;
   } else {
-    const int j = i - 6 * W;
-    const int c = j % 6;
-    *ly = kG + j / 6;
-    *lx = c < 3 ? c : nx + c;
+    const int j = i - 2 * R * W;
+    const int c = j % (2 * R);
+    *ly = R + j / (2 * R);
+    *lx = c < R ? c : nx + c;
   }
+}
+
+template <typename T>
+__device__ __forceinline__ T d8(T m4, T m3, T m2, T m1, T c, T p1, T p2, T p3, T p4) {
+  // eighth-order centred second difference times 5040 h^2 (Sec. III.C's production stencil)
+  return (((((((T(-9) * m4 + T(128) * m3) - T(1008) * m2) + T(8064) * m1) - T(14350) * c) +
+            T(8064) * p1) - T(1008) * p2) + T(128) * p3) - T(9) * p4;
 }
 
 template <typename TS>
@@ -66,10 +74,12 @@ __device__ __forceinline__ TS stage_form(TS ra, TS rk, TS cdt, bool in) {
 
 // One RK4 stage of the scalar wave on one tile of nx x ny points in x-y (at
 // most S per thread, threads mapped row by row) and nz planes, marched in z
-// direction DZ (+1 upward, -1 downward) one plane per step.  The x-y plane of
-// stage values (tile plus the 3-point ring) is staged in LDS (double
-// buffered, row pitch nx + 6): the tile's own points come from the 7-plane z
-// column each thread keeps in registers, only the ring is read from memory.
+// direction DZ (+1 upward, -1 downward) one plane per step.  R is the stencil
+// radius: 3 for the fourth-order Laplacian, 4 for the eighth-order one.  The
+// x-y plane of stage values (tile plus the R-point ring) is staged in LDS
+// (double buffered, row pitch nx + 2R): the tile's own points come from the
+// (2R+1)-plane z column each thread keeps in registers, only the ring is read
+// from memory.
 // Every load has a valid address (lanes without a point read a clamped one
 // and drop the value), so no load sits behind a branch.  The loads of plane
 // z + D (ring) and z + D + 3 (column) are issued while plane z is computed,
@@ -77,7 +87,9 @@ __device__ __forceinline__ TS stage_form(TS ra, TS rk, TS cdt, bool in) {
 // value Y = y_n + c dt k is formed when a set is consumed.  One barrier per
 // plane.
 //   k_u  = Pi + Q u,   k_Pi = Lap u + Q Pi
-//   Lap  = ((d2_x + d2_y) + d2_z) / (12 h^2),  Q = sigma/(64 h) ((ko_x + ko_y) + ko_z)
+//   Lap  = ((d2_x + d2_y) + d2_z) / (12 h^2)        (R = 3)
+//        = ((d8_x + d8_y) + d8_z) / (5040 h^2)      (R = 4)
+//   Q    = sigma/(64 h) ((ko_x + ko_y) + ko_z)       (both)
 // Stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4) in FP64.
 // The z stencils take their taps in increasing z whatever the direction, so
 // both directions give the same bits.
@@ -87,21 +99,21 @@ struct StageRaw {   // raw loads of one ring plane and one column plane
   TS ca[2][S], ck[2][S];
 };
 
-template <int STAGE, typename TS, int DEPTH, int S, bool WK, int NT>
+template <int STAGE, typename TS, int DEPTH, int S, bool WK, int NT, int R>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T, const BoxDev& B,
                                            TS* lds) {
   constexpr int RM = StageFamily<NT>::ring;
   constexpr int kWinCap = StageFamily<NT>::wincap;
   constexpr int kWinStride = kWinCap + 8;   // per-variable LDS stride: window plus a spare slot
-  constexpr int QN = 2 * kG + 1;   // z column: planes z-3 .. z+3 along DZ
+  constexpr int QN = 2 * R + 1;   // z column: planes z-R .. z+R along DZ
   const TS clap = TS(a.clap), cko = TS(a.cko), cdt = TS(a.cdt);
   const char* yn = static_cast<const char*>(a.yn);
   const char* kp = static_cast<const char*>(a.kprev);
   const char* yh = static_cast<const char*>(a.Yh);
-  const int W = T.nx + 2 * kG;
+  const int W = T.nx + 2 * R;
   const int64_t ps = (int64_t)B.px * B.py;     // points per z plane
   // planes the tile reads and computes, and the first computed plane
-  const int zlo = T.z0 - kG, zhi = T.z0 + T.nz + kG - 1;
+  const int zlo = T.z0 - R, zhi = T.z0 + T.nz + R - 1;
   const bool up = T.dir == 0;
   const int DZ = up ? 1 : -1;
   const int z0 = up ? T.z0 : T.z0 + T.nz - 1;
@@ -120,10 +132,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
     act[s] = i < T.nx * T.ny;
     const int ic = act[s] ? i : 0;
     const int px = ic % T.nx, py = ic / T.nx;
-    li[s] = (py + kG) * W + px + kG;
+    li[s] = (py + R) * W + px + R;
     cb[s] = (uint32_t)sizeof(TS) * (uint32_t)((T.y0 + py + B.pad) * B.px + (T.x0 + px + B.pad));
   }
-  const int nring = 6 * W + 6 * T.ny;
+  const int nring = 2 * R * W + 2 * R * T.ny;
   bool ract[RM], rin[RM];
   int rli[RM];
   uint32_t rb[RM];
@@ -132,39 +144,39 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
     const int i = threadIdx.x + k * NT;
     ract[k] = i < nring;
     int lx = 0, ly = 0;
-    ring_coord(ract[k] ? i : 0, T.nx, T.ny, &lx, &ly);
+    ring_coord<R>(ract[k] ? i : 0, T.nx, T.ny, &lx, &ly);
     rli[k] = ly * W + lx;
-    const int x = T.x0 - kG + lx, y = T.y0 - kG + ly;
+    const int x = T.x0 - R + lx, y = T.y0 - R + ly;
     rin[k] = (unsigned)x < (unsigned)B.nx && (unsigned)y < (unsigned)B.ny;
     rb[k] = (uint32_t)sizeof(TS) * (uint32_t)((y + B.pad) * B.px + (x + B.pad));
   }
-  // raw loads of ring plane z0 + DZ j and column plane z0 + DZ (j + 3)
-  auto issue = [&](StageRaw<TS, S, RM>& R, int j) {
+  // raw loads of ring plane z0 + DZ j and column plane z0 + DZ (j + R)
+  auto issue = [&](StageRaw<TS, S, RM>& X, int j) {
     const int zr = clampz(z0 + DZ * j, T.z0, T.z0 + T.nz - 1);
-    const int zq = clampz(z0 + DZ * (j + kG), zlo, zhi);
+    const int zq = clampz(z0 + DZ * (j + R), zlo, zhi);
     const bool qin = zin(zq);
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
       const int64_t pr = plane(zr, v);
 #pragma unroll
       for (int k = 0; k < RM; ++k) {
-        R.ra[v][k] = load_at<TS>((rin[k] ? yn : yh) + pr, rb[k]);
-        R.rk[v][k] = STAGE > 1 ? load_at<TS>(kp + pr, rb[k]) : TS(0);
+        X.ra[v][k] = load_at<TS>((rin[k] ? yn : yh) + pr, rb[k]);
+        X.rk[v][k] = STAGE > 1 ? load_at<TS>(kp + pr, rb[k]) : TS(0);
       }
       const int64_t pq = plane(zq, v);
       const char* src = (qin ? yn : yh) + pq;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        R.ca[v][s] = load_at<TS>(src, cb[s]);
-        R.ck[v][s] = STAGE > 1 ? load_at<TS>(kp + pq, cb[s]) : TS(0);
+        X.ca[v][s] = load_at<TS>(src, cb[s]);
+        X.ck[v][s] = STAGE > 1 ? load_at<TS>(kp + pq, cb[s]) : TS(0);
       }
     }
   };
   TS q[2][S][QN];   // stage values of the z column, in marching order
-  // prologue: column planes z0 - 3 DZ .. z0 + 2 DZ into q[1..6]
+  // prologue: column planes z0 - R DZ .. z0 + (R - 1) DZ into q[1..2R]
 #pragma unroll
   for (int j = 1; j < QN; ++j) {
-    const int z = clampz(z0 + DZ * (j - 1 - kG), zlo, zhi);
+    const int z = clampz(z0 + DZ * (j - 1 - R), zlo, zhi);
     const bool in = zin(z);
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
@@ -178,14 +190,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
       }
     }
   }
-  StageRaw<TS, S, RM> R[DEPTH];
+  StageRaw<TS, S, RM> regs[DEPTH];
 #pragma unroll
-  for (int j = 0; j < DEPTH; ++j) issue(R[j], j);
-  // one plane: consume R (ring plane iz, column plane iz + 3), refill it
+  for (int j = 0; j < DEPTH; ++j) issue(regs[j], j);
+  // one plane: consume a register set (ring plane iz, column plane iz + R), refill it
   // with the planes DEPTH further on, compute plane iz
   auto step = [&](int iz, StageRaw<TS, S, RM>& P, TS* L) {
     const int z = z0 + DZ * iz;
-    const bool zc = zin(z0 + DZ * (iz + kG));
+    const bool zc = zin(z0 + DZ * (iz + R));
 #pragma unroll
     for (int j = 0; j < QN - 1; ++j)
 #pragma unroll
@@ -203,7 +215,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
     for (int v = 0; v < 2; ++v) {
       TS* Lv = L + v * kWinStride;
 #pragma unroll
-      for (int s = 0; s < S; ++s) Lv[act[s] ? li[s] : kWinCap] = q[v][s][kG];
+      for (int s = 0; s < S; ++s) Lv[act[s] ? li[s] : kWinCap] = q[v][s][R];
 #pragma unroll
       for (int k = 0; k < RM; ++k)
         Lv[ract[k] ? rli[k] : kWinCap] = stage_form<STAGE, TS>(P.ra[v][k], P.rk[v][k], cdt, rin[k] && zr);
@@ -212,8 +224,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
     issue(P, iz + DEPTH);   // in flight during this plane's arithmetic
     const TS* Lu = L;
     const TS* Lp = L + kWinStride;
-    // column taps in increasing z: zt[m] is plane z + m - 3
-    auto zt = [&](int v, int s, int m) -> TS { return up ? q[v][s][m] : q[v][s][2 * kG - m]; };
+    // column taps in increasing z: zt[m] is plane z + m - R
+    auto zt = [&](int v, int s, int m) -> TS { return up ? q[v][s][m] : q[v][s][2 * R - m]; };
     // stage 4 reads the slopes and y_n at the point: issue those loads first
     TS c1[2][S], c2[2][S], c3[2][S];
     double c0[2][S];
@@ -238,21 +250,31 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int c = li[s];
-      const TS cu = q[0][s][kG], cp = q[1][s][kG];
-      const TS lapx = d2<TS>(Lu[c - 2], Lu[c - 1], cu, Lu[c + 1], Lu[c + 2]);
-      const TS lapy = d2<TS>(Lu[c - 2 * W], Lu[c - W], cu, Lu[c + W], Lu[c + 2 * W]);
-      const TS lapz = d2<TS>(zt(0, s, 1), zt(0, s, 2), cu, zt(0, s, 4), zt(0, s, 5));
+      const TS cu = q[0][s][R], cp = q[1][s][R];
+      TS lapx, lapy, lapz;
+      if constexpr (R == 3) {
+        lapx = d2<TS>(Lu[c - 2], Lu[c - 1], cu, Lu[c + 1], Lu[c + 2]);
+        lapy = d2<TS>(Lu[c - 2 * W], Lu[c - W], cu, Lu[c + W], Lu[c + 2 * W]);
+        lapz = d2<TS>(zt(0, s, 1), zt(0, s, 2), cu, zt(0, s, 4), zt(0, s, 5));
+      } else {
+        lapx = d8<TS>(Lu[c - 4], Lu[c - 3], Lu[c - 2], Lu[c - 1], cu, Lu[c + 1], Lu[c + 2],
+                      Lu[c + 3], Lu[c + 4]);
+        lapy = d8<TS>(Lu[c - 4 * W], Lu[c - 3 * W], Lu[c - 2 * W], Lu[c - W], cu, Lu[c + W],
+                      Lu[c + 2 * W], Lu[c + 3 * W], Lu[c + 4 * W]);
+        lapz = d8<TS>(zt(0, s, 0), zt(0, s, 1), zt(0, s, 2), zt(0, s, 3), cu, zt(0, s, 5),
+                      zt(0, s, 6), zt(0, s, 7), zt(0, s, 8));
+      }
       const TS lap = ((lapx + lapy) + lapz) * clap;
       TS Q[2];
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
         const TS* Lv = v == 0 ? Lu : Lp;
-        const TS cc = q[v][s][kG];
+        const TS cc = q[v][s][R];
         const TS kx = ko7<TS>(Lv[c - 3], Lv[c - 2], Lv[c - 1], cc, Lv[c + 1], Lv[c + 2], Lv[c + 3]);
         const TS ky = ko7<TS>(Lv[c - 3 * W], Lv[c - 2 * W], Lv[c - W], cc, Lv[c + W],
                               Lv[c + 2 * W], Lv[c + 3 * W]);
-        const TS kz = ko7<TS>(zt(v, s, 0), zt(v, s, 1), zt(v, s, 2), cc, zt(v, s, 4),
-                              zt(v, s, 5), zt(v, s, 6));
+        const TS kz = ko7<TS>(zt(v, s, R - 3), zt(v, s, R - 2), zt(v, s, R - 1), cc,
+                              zt(v, s, R + 1), zt(v, s, R + 2), zt(v, s, R + 3));
         Q[v] = cko * ((kx + ky) + kz);
       }
       const TS kv[2] = {cp + Q[0], lap + Q[1]};
@@ -280,17 +302,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
   int iz = 0;
   for (; iz + DEPTH <= T.nz; iz += DEPTH) {
 #pragma unroll
-    for (int j = 0; j < DEPTH; ++j) step(iz + j, R[j], lds + ((iz + j) & 1) * 2 * kWinStride);
+    for (int j = 0; j < DEPTH; ++j) step(iz + j, regs[j], lds + ((iz + j) & 1) * 2 * kWinStride);
   }
 #pragma unroll
   for (int j = 0; j < DEPTH - 1; ++j)
-    if (iz + j < T.nz) step(iz + j, R[j], lds + ((iz + j) & 1) * 2 * kWinStride);
+    if (iz + j < T.nz) step(iz + j, regs[j], lds + ((iz + j) & 1) * 2 * kWinStride);
   __syncthreads();
 }
 
 // Persistent stage kernel: workgroups stride over the tile list; a tile's
 // dir field picks its z marching direction.
-template <int STAGE, typename TS, int DEPTH, int S, bool WK, int NT>
+template <int STAGE, typename TS, int DEPTH, int S, bool WK, int NT, int R>
 __global__ __launch_bounds__(NT) void k_wave_stage(StageArgs a) {
   __shared__ TS lds[2 * 2 * (StageFamily<NT>::wincap + 8)];
   // consecutive workgroups land on different XCDs (round robin over 8); give
@@ -301,7 +323,7 @@ __global__ __launch_bounds__(NT) void k_wave_stage(StageArgs a) {
   for (int t = g; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
-    stage_tile<STAGE, TS, DEPTH, S, WK, NT>(a, T, B, lds);
+    stage_tile<STAGE, TS, DEPTH, S, WK, NT, R>(a, T, B, lds);
   }
 }
 
@@ -718,32 +740,32 @@ __global__ __launch_bounds__(256) void k_to_f32(const double* src, float* dst, i
 
 inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-template <typename TS, int DEPTH, int S, int NT>
+template <typename TS, int DEPTH, int S, int NT, int R>
 void stage_dispatch(const StageArgs& a, dim3 g, hipStream_t s) {
   const dim3 b(NT);
   switch (a.stage) {
-    case 1: hipLaunchKernelGGL((k_wave_stage<1, TS, DEPTH, S, true, NT>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_wave_stage<2, TS, DEPTH, S, true, NT>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_wave_stage<3, TS, DEPTH, S, true, NT>), g, b, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_wave_stage<1, TS, DEPTH, S, true, NT, R>), g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_wave_stage<2, TS, DEPTH, S, true, NT, R>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_wave_stage<3, TS, DEPTH, S, true, NT, R>), g, b, 0, s, a); break;
     default:
-      if (a.write_k) hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, true, NT>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, false, NT>), g, b, 0, s, a);
+      if (a.write_k) hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, true, NT, R>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, false, NT, R>), g, b, 0, s, a);
       break;
   }
 }
 
 // (threads, points per thread, planes in flight): (256, 2, 1), (256, 2, 2),
 // (256, 1, 2), (512, 2, 1), (512, 2, 2)
-template <typename TS>
+template <typename TS, int R>
 void stage_variant(const StageArgs& a, dim3 g, int depth, int slots, int threads, hipStream_t s) {
   if (threads == 512) {
-    if (depth == 2) stage_dispatch<TS, 2, 2, 512>(a, g, s);
-    else stage_dispatch<TS, 1, 2, 512>(a, g, s);
+    if (depth == 2) stage_dispatch<TS, 2, 2, 512, R>(a, g, s);
+    else stage_dispatch<TS, 1, 2, 512, R>(a, g, s);
   } else if (slots == 1) {
-    stage_dispatch<TS, 2, 1, 256>(a, g, s);
+    stage_dispatch<TS, 2, 1, 256, R>(a, g, s);
   } else {
-    if (depth == 2) stage_dispatch<TS, 2, 2, 256>(a, g, s);
-    else stage_dispatch<TS, 1, 2, 256>(a, g, s);
+    if (depth == 2) stage_dispatch<TS, 2, 2, 256, R>(a, g, s);
+    else stage_dispatch<TS, 1, 2, 256, R>(a, g, s);
   }
 }
 
@@ -753,8 +775,15 @@ hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int depth, int s
                         hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g(grid > 0 ? grid : a.ntiles);
-  if (f32) stage_variant<float>(a, g, depth, slots, threads, s);
-  else stage_variant<double>(a, g, depth, slots, threads, s);
+  if (a.radius == 4) {   // eighth order: FP64 only
+    if (f32) return hipErrorInvalidValue;
+    stage_variant<double, 4>(a, g, depth, slots, threads, s);
+  } else if (a.radius == 3) {
+    if (f32) stage_variant<float, 3>(a, g, depth, slots, threads, s);
+    else stage_variant<double, 3>(a, g, depth, slots, threads, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

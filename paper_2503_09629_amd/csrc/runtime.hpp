@@ -18,6 +18,7 @@ struct TileShape {
   int depth = 1;  // stage kernel: planes of loads in flight ahead of the computed plane
   int slots = 2;  // owned points per stage-kernel thread (tiles of at most threads * slots points)
   int threads = 256;  // stage-kernel workgroup size (256 or 512)
+  int radius = 3;     // stencil radius (3: fourth order, 4: eighth order); sizes the LDS frame
 };
 
 // z-chunk depths the autotuner tries; the tile table region is sized for the
