@@ -53,6 +53,12 @@ prolonged in space first: theta0 = 0 gives P[y_n]; theta0 = 1/2 gives
 y_{n-1} (its first step) the interpolant is linear over y_n, y_{n+1}:
 ((0 P[y_n] + 1/2 P[y_n]) + 1/2 P[y_{n+1}]).  Restriction skips buffer points.
 
+Radiative outer boundary (outer_bc="radiative", Z4c on a non-periodic
+domain): the physical-boundary ghosts of level 0 are evolved, not frozen.
+Each RK4 stage gives them the stage value y_n + c_s dt k_{s-1} like an owned
+point and the right-hand side of oracle.radiative; the step ends with
+y_{n+1} = y_n + dt/6 (((k1 + 2k2) + 2k3) + k4) there as well.
+
 Uniform time steps (subcycling=False; the comparison runs of Sec. IV.A):
 every level steps with the finest level's dt, advance_level takes one child
 step per parent step, and the RB ghost of stage s is the parent's stage vector
@@ -68,6 +74,7 @@ import numpy as np
 from . import cbuild
 from .dense import aligned_weights, ghost_weights_f64
 from .hierarchy import PHYS, RB, SYNC, Hierarchy
+from .radiative import radiative_rhs
 
 PROLONG_W = tuple(w / 256.0 for w in (3.0, -25.0, 150.0, 150.0, -25.0, 3.0))
 RK_C_NEXT = (0.5, 0.5, 1.0)
@@ -223,12 +230,17 @@ class OracleRun:
 
     def __init__(self, hier: Hierarchy, rhs: str = "wave", sigma: float = 0.32,
                  cfl: float = 0.25, z4c: dict = None, subcycling: bool = True,
-                 buffer_zones: bool = False, fd_order: int = 4):
+                 buffer_zones: bool = False, fd_order: int = 4, outer_bc: str = "frozen"):
         if rhs not in ("wave", "z4c"):
             raise ValueError(rhs)
         if fd_order not in (4, 8) or (fd_order == 8 and (rhs != "wave" or hier.G < 4)):
             raise ValueError("fd_order 8 needs the wave system and G >= 4")
         self.fd_order = fd_order
+        if outer_bc not in ("frozen", "radiative"):
+            raise ValueError(outer_bc)
+        if outer_bc == "radiative" and (rhs != "z4c" or any(hier.spec.periodic)):
+            raise ValueError("the radiative boundary needs Z4c on a non-periodic domain")
+        self.radiative = outer_bc == "radiative"
         if buffer_zones and (not subcycling or hier.B <= 0):
             raise ValueError("buffer zones need subcycling and a hierarchy with buffer points")
         self.rhs_kind = rhs
@@ -268,6 +280,8 @@ class OracleRun:
                 st.yprev = np.zeros_like(st.y)
                 st.nsteps = 0
                 st.history = False
+        if self.radiative:
+            self._init_radiative()
         if subcycling:
             self.dt = [cfl * self.dx[l] for l in range(self.L)]
             self.weights = {(s, th): ghost_weights_f64(s, Fraction(th))
@@ -276,6 +290,64 @@ class OracleRun:
             self.dt = [cfl * self.dx[self.L - 1]] * self.L
             self.weights = {(s, th): tuple(float(w) for w in aligned_weights(s))
                             for s in range(1, 6) for th in (0.0, 0.5)}
+
+    def _init_radiative(self) -> None:
+        """Distinct physical-boundary points of level 0 (the whole ghost shell
+        of its box) and the map from the blocks' ghost slots to them."""
+        for l in range(1, self.L):
+            if len(self.st[l].phys_dst):
+                raise ValueError("the radiative boundary applies to level 0 only")
+        lev = self.hier.levels[0]
+        pts = [lev.ghost_points(b)[self.hier.ghosts[0][b][0] == PHYS] for b in range(lev.nblocks)]
+        pts = np.concatenate(pts)
+        q = pts + self.hier.G                      # non-negative for the key
+        key = (q[:, 2] << 42) | (q[:, 1] << 21) | q[:, 0]
+        _, first, inv = np.unique(key, return_index=True, return_inverse=True)
+        self.rad_pts = pts[first]
+        self.rad_first = first
+        self.rad_inv = inv
+        self.rad_n = tuple(int(v) + 1 for v in self.spec.ncells0)   # owned points per dimension
+        G = self.hier.G
+        shell = np.prod([v + 2 * G for v in self.rad_n]) - np.prod(self.rad_n)
+        assert len(self.rad_pts) == shell
+        self.rad_y = np.zeros((self.nvars, len(self.rad_pts)))
+        self.rad_k = [np.zeros_like(self.rad_y) for _ in range(4)]
+
+    def _padded_level0(self, A: np.ndarray, ghosts: np.ndarray) -> np.ndarray:
+        G = self.hier.G
+        nx, ny, nz = self.rad_n
+        out = np.zeros((self.nvars, nz + 2 * G, ny + 2 * G, nx + 2 * G))
+        out[:, G:G + nz, G:G + ny, G:G + nx] = A[:, self.st[0].canon].reshape(self.nvars, nz, ny, nx)
+        P = self.rad_pts + G
+        out[:, P[:, 2], P[:, 1], P[:, 0]] = ghosts
+        return out
+
+    def _radiative_step(self) -> None:
+        """One RK4 step of level 0 with evolved outer ghosts."""
+        st = self.st[0]
+        dt = self.dt[0]
+        yn = self.rad_y.copy()
+        st.yn[:] = st.y
+        st.Y[:] = st.yn
+        for s in range(1, 5):
+            g = yn if s == 1 else yn + (RK_C_NEXT[s - 2] * dt) * self.rad_k[s - 2]
+            st.phys_vals = g[:, self.rad_inv]
+            self.fill(0, st.Y, s)
+            self.rhs(0, st.Y, st.k[s - 1])
+            self.rad_k[s - 1] = radiative_rhs(self._padded_level0(st.Y, g), self.hier.G,
+                                              self.rad_n, self.dx[0], self.spec.origin,
+                                              self.rad_pts)
+            if s < 4:
+                self.lib.orc_stage(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
+                                   self.nvars, cbuild.ptr(st.yn), cbuild.ptr(st.k[s - 1]),
+                                   cbuild.ptr(st.Y), RK_C_NEXT[s - 1] * dt)
+        k1, k2, k3, k4 = st.k
+        self.lib.orc_final(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total, self.nvars,
+                           cbuild.ptr(st.yn), cbuild.ptr(k1), cbuild.ptr(k2), cbuild.ptr(k3),
+                           cbuild.ptr(k4), cbuild.ptr(st.y), dt)
+        r1, r2, r3, r4 = self.rad_k
+        self.rad_y = yn + (dt / 6.0) * (((r1 + 2.0 * r2) + 2.0 * r3) + r4)
+        st.phys_vals = self.rad_y[:, self.rad_inv]
 
     # -- data ----------------------------------------------------------------
     def set_data(self, l: int, var: int, values) -> None:
@@ -290,6 +362,8 @@ class OracleRun:
 
     def set_phys(self, l: int, values: np.ndarray) -> None:
         self.st[l].phys_vals[:] = values
+        if self.radiative and l == 0:
+            self.rad_y = np.array(values, dtype=np.float64)[:, self.rad_first]
 
     def phys_coords(self, l: int) -> np.ndarray:
         """x, y, z of the level's PHYS ghost slots, in fill order."""
@@ -352,6 +426,9 @@ class OracleRun:
         return ham[st.canon]
 
     def rk4_step(self, l: int) -> None:
+        if self.radiative and l == 0:
+            self._radiative_step()
+            return
         st = self.st[l]
         dt = self.dt[l]
         if self.buffer_zones:
