@@ -99,6 +99,18 @@ typedef struct sc_ctx sc_ctx;
  * sc_advance steps this mode; the single-step pieces return SC_E_STATE. */
 enum { SC_SUBCYCLED = 0, SC_UNIFORM_DT = 1, SC_BUFFER_ZONES = 2 };
 
+/* Outer boundary of a non-periodic domain (Sec. III.A applies an outgoing
+ * condition to the dynamical variables).  SC_BC_FROZEN: the physical-boundary
+ * ghosts keep the values the caller set with sc_set_phys_data.
+ * SC_BC_RADIATIVE (Z4c, FP64, physical-boundary ghosts on level 0 only): the
+ * level-0 ghosts are evolved with d_t f = -(v/r)(x^i d_i f + (f - f0)), r the
+ * distance from the coordinate origin, f0 = 1 for W, the conformal metric's
+ * diagonal and the lapse and 0 otherwise, v = sqrt(2) for the lapse and 1
+ * otherwise; derivatives are second-order one-sided (inwards) across the
+ * boundary and centred along it; the ghosts take the same RK4 stages as owned
+ * points, starting from the values set with sc_set_phys_data. */
+enum { SC_BC_FROZEN = 0, SC_BC_RADIATIVE = 1 };
+
 typedef struct {
   int64_t lo[3], hi[3]; /* inclusive vertex indices on the box's level, x, y, z */
 } sc_box;
@@ -121,7 +133,7 @@ typedef struct {
                           production stencil of Sec. III.C: nine-point centred second
                           differences, the same fifth-order dissipation; wave RHS,
                           FP64, SC_SUBCYCLED or SC_UNIFORM_DT) */
-  int32_t reserved;    /* 0 */
+  int32_t outer_bc;    /* SC_BC_FROZEN (default) or SC_BC_RADIATIVE */
 } sc_config;
 
 /* Fill *cfg with the defaults: wave RHS, FP64, batched, nghost 3, fd_order 4,

@@ -23,6 +23,7 @@ SC_ARR_Y, SC_ARR_K1, SC_ARR_K2, SC_ARR_K3, SC_ARR_K4, SC_ARR_YN = range(6)
 SC_FILL_Y1, SC_FILL_Y2, SC_FILL_Y3, SC_FILL_Y4, SC_FILL_END = 1, 2, 3, 4, 5
 SC_ABI_VERSION = 2
 SC_SUBCYCLED, SC_UNIFORM_DT, SC_BUFFER_ZONES = 0, 1, 2
+SC_BC_FROZEN, SC_BC_RADIATIVE = 0, 1
 
 EXPORTED = [
     "sc_config_default", "sc_create", "sc_destroy", "sc_last_error", "sc_build_hierarchy",
@@ -44,7 +45,7 @@ class ScConfig(ctypes.Structure):
                 ("z4c_kappa1", ctypes.c_double), ("z4c_kappa2", ctypes.c_double),
                 ("z4c_eta_c", ctypes.c_double), ("z4c_eta_o", ctypes.c_double),
                 ("z4c_eta_s", ctypes.c_double), ("fd_order", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("outer_bc", ctypes.c_int32)]
 
 
 class ScBox(ctypes.Structure):
@@ -133,13 +134,15 @@ class Context:
     def __init__(self, sigma: float = 0.32, cfl: float = 0.25, exec: int = SC_EXEC_BATCHED,
                  precision: int = SC_FP64, stream=None, device: Optional[str] = None,
                  rhs: int = SC_RHS_WAVE, z4c: Optional[dict] = None,
-                 time_stepping: int = SC_SUBCYCLED, fd_order: int = 4):
+                 time_stepping: int = SC_SUBCYCLED, fd_order: int = 4,
+                 outer_bc: int = SC_BC_FROZEN):
         self.L = lib()
         cfg = ScConfig()
         self._check(self.L.sc_config_default(ctypes.byref(cfg)), None)
         cfg.time_stepping = time_stepping
         cfg.fd_order = fd_order
         cfg.nghost = 4 if fd_order == 8 else 3
+        cfg.outer_bc = outer_bc
         cfg.ko_sigma = sigma
         cfg.cfl = cfl
         cfg.exec = exec

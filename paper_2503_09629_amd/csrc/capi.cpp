@@ -816,6 +816,33 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
   a.ynew = L.y[nxt(L)];
   a.ynew32 = c->mixed ? L.y32[1 - L.cur] : nullptr;
   a.geo = L.Ys;   // kZ4cScratch arrays of double: room for the curvature arrays in either precision
+  // radiative outer boundary: level 0's ghost stage values go into the table
+  // before any stencil reads them; their right-hand side follows the interior's
+  const bool rad = c->cfg.outer_bc == SC_BC_RADIATIVE && l == 0 && !L.phys.empty();
+  Z4cRadArgs ra{};
+  if (rad) {
+    ra.idx = L.d_phys;
+    ra.n = (int64_t)L.phys.size();
+    ra.per_member = ra.n / c->hier.geo.nmembers;
+    ra.boxes = L.d_boxes;
+    ra.Y = static_cast<const double*>(yh);
+    ra.yn = L.y[L.cur];
+    ra.kprev = stage >= 2 ? static_cast<const double*>(kprev) : nullptr;
+    ra.k1 = static_cast<const double*>(L.k[0]);
+    ra.k2 = static_cast<const double*>(L.k[1]);
+    ra.k3 = static_cast<const double*>(L.k[2]);
+    ra.kout = static_cast<double*>(L.k[stage - 1]);
+    ra.ynew = L.y[nxt(L)];
+    ra.table = static_cast<double*>(table);
+    ra.vstride = L.total;
+    ra.stage = stage;
+    ra.cdt = cnext[stage] * L.dt;
+    ra.dt6 = L.dt / 6.0;
+    ra.h = L.dx;
+    for (int d = 0; d < 3; ++d) ra.origin[d] = c->hier.geo.origin[d];
+    HIPCHK(c, launch_z4c_rad_fill(ra, c->stream));
+    ++c->launches;
+  }
   Z4cCombineArgs cb{};
   cb.nvars = c->nvars;
   cb.boxes = L.d_boxes;
@@ -835,22 +862,31 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
     ++c->launches;
     return SC_OK;
   };
-  if (!per_block) return run(L.d_tiles, (int)L.tiles.size(), std::min<int>((int)L.tiles.size(), c->grid_cap));
-  // per block: every block's stage vector must be complete before any block's
-  // stencil reads its neighbours, so all combines go first
-  const int nblk = (int)L.btile_start.size() - 1;
-  for (int b = 0; b < nblk; ++b) {
-    const int n = L.btile_start[b + 1] - L.btile_start[b];
-    cb.tiles = L.d_btiles + L.btile_start[b];
-    cb.ntiles = n;
-    HIPCHK(c, launch_z4c_combine(cb, n, c->mixed, c->stream));
-    ++c->launches;
+  if (!per_block) {
+    const int rc = run(L.d_tiles, (int)L.tiles.size(),
+                       std::min<int>((int)L.tiles.size(), c->grid_cap));
+    if (rc) return rc;
+  } else {
+    // per block: every block's stage vector must be complete before any
+    // block's stencil reads its neighbours, so all combines go first
+    const int nblk = (int)L.btile_start.size() - 1;
+    for (int b = 0; b < nblk; ++b) {
+      const int n = L.btile_start[b + 1] - L.btile_start[b];
+      cb.tiles = L.d_btiles + L.btile_start[b];
+      cb.ntiles = n;
+      HIPCHK(c, launch_z4c_combine(cb, n, c->mixed, c->stream));
+      ++c->launches;
+    }
+    for (int b = 0; b < nblk; ++b) {
+      const int n = L.btile_start[b + 1] - L.btile_start[b];
+      a.tiles = L.d_btiles + L.btile_start[b];
+      a.ntiles = n;
+      HIPCHK(c, launch_z4c_stage(a, n, c->mixed, c->stream));
+      ++c->launches;
+    }
   }
-  for (int b = 0; b < nblk; ++b) {
-    const int n = L.btile_start[b + 1] - L.btile_start[b];
-    a.tiles = L.d_btiles + L.btile_start[b];
-    a.ntiles = n;
-    HIPCHK(c, launch_z4c_stage(a, n, c->mixed, c->stream));
+  if (rad) {
+    HIPCHK(c, launch_z4c_radiative(ra, c->stream));
     ++c->launches;
   }
   return SC_OK;
@@ -1154,12 +1190,17 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
       (cfg->fd_order == 4 && cfg->nghost == 3) ||
       (cfg->fd_order == 8 && cfg->nghost == 4 && cfg->rhs == SC_RHS_WAVE &&
        cfg->precision == SC_FP64 && cfg->time_stepping != SC_BUFFER_ZONES);
-  if (!rhs_ok || !order_ok || cfg->reserved != 0 || !(cfg->z4c_eta_s > 0.0) ||
+  // radiative outer boundary: Z4c, FP64
+  const bool bc_ok = cfg->outer_bc == SC_BC_FROZEN ||
+                     (cfg->outer_bc == SC_BC_RADIATIVE && cfg->rhs == SC_RHS_Z4C &&
+                      cfg->precision == SC_FP64);
+  if (!rhs_ok || !order_ok || !bc_ok || !(cfg->z4c_eta_s > 0.0) ||
       !(cfg->cfl > 0.0 && cfg->cfl <= 0.5) ||
       cfg->ko_sigma < 0.0 || (cfg->precision != SC_FP64 && cfg->precision != SC_MIXED) ||
       cfg->exec < 0 || cfg->exec > 2) {
     g_create_error = "unsupported configuration (rhs, time stepping (buffer zones: wave, FP64), "
                      "fd_order 4 with nghost 3 or 8 with nghost 4 (wave, FP64, no buffer zones), "
+                     "outer_bc (radiative: Z4c, FP64), "
                      "0 < cfl <= 0.5, sigma >= 0, precision, exec)";
     return SC_E_ARG;
   }
@@ -1234,6 +1275,13 @@ int sc_build_hierarchy(sc_ctx* c, int32_t nmembers, const double origin[3], doub
   if (!e.empty()) return fail(c, SC_E_NEST, e);
   e = validate_layout(c);
   if (!e.empty()) return fail(c, SC_E_ARG, "internal layout check: " + e);
+  if (c->cfg.outer_bc == SC_BC_RADIATIVE) {
+    for (size_t l = 1; l < c->lev.size(); ++l)
+      if (!c->lev[l].phys.empty())
+        return fail(c, SC_E_ARG, "radiative boundary: only level 0 may touch the outer boundary");
+    for (int d = 0; d < 3; ++d)
+      if (g.periodic[d]) return fail(c, SC_E_ARG, "radiative boundary: the domain must not be periodic");
+  }
   plan_arena(c);
   c->state = 1;
   return SC_OK;

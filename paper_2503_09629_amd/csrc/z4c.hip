@@ -618,7 +618,76 @@ __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
   }
 }
 
+// Stage values of the radiative ghosts: Y = y_n + c_s dt k_{s-1} (y_n at
+// stage 1), evaluated as for an owned point.
+__global__ __launch_bounds__(256) void k_z4c_rad_fill(Z4cRadArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int64_t o = a.idx[i];
+  for (int v = 0; v < NV; ++v) {
+    const int64_t ov = o + v * a.vstride;
+    a.table[ov] = a.kprev ? a.yn[ov] + a.cdt * a.kprev[ov] : a.yn[ov];
+  }
+}
+
+// Outgoing (radiative) condition at a ghost point outside the domain:
+// d_t f = -(v / r) (x^i d_i f + (f - f0)), r from the coordinate origin, with
+// second-order one-sided differences pointing inwards along directions in
+// which the point lies outside the box and centred ones along the others.
+// f0 = 1 for W, the conformal metric's diagonal and the lapse, 0 otherwise;
+// v = sqrt(2) for the lapse, 1 otherwise.  Stage 4 also forms y_{n+1}.
+__global__ __launch_bounds__(256) void k_z4c_radiative(Z4cRadArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const BoxDev B = a.boxes[i / a.per_member];
+  const int64_t o = a.idx[i];
+  const int64_t r = o - B.base, pxy = (int64_t)B.px * B.py;
+  const int c[3] = {(int)(r % B.px) - B.pad, (int)((r / B.px) % B.py) - B.pad,
+                    (int)(r / pxy) - B.pad};
+  const int n[3] = {B.nx, B.ny, B.nz};
+  const int64_t st[3] = {1, B.px, pxy};
+  double x[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) x[d] = a.origin[d] + (double)(B.lo[d] + c[d]) * a.h;
+  const double rad = sqrt((x[0] * x[0] + x[1] * x[1]) + x[2] * x[2]);
+  for (int v = 0; v < NV; ++v) {
+    const double* F = a.Y + o + v * a.vstride;
+    const double f = F[0];
+    double dv[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t s = st[d];
+      if (c[d] < 0) dv[d] = ((-3.0 * f + 4.0 * F[s]) - F[2 * s]) / (2.0 * a.h);
+      else if (c[d] >= n[d]) dv[d] = ((3.0 * f - 4.0 * F[-s]) + F[-2 * s]) / (2.0 * a.h);
+      else dv[d] = (F[s] - F[-s]) / (2.0 * a.h);
+    }
+    const double adv = (x[0] * dv[0] + x[1] * dv[1]) + x[2] * dv[2];
+    const bool one = v == VW || v == VG || v == VG + 3 || v == VG + 5 || v == VALP;
+    const double f0 = one ? 1.0 : 0.0;
+    const double sp = v == VALP ? sqrt(2.0) : 1.0;
+    const double k = -(sp / rad) * (adv + (f - f0));
+    const int64_t ov = o + v * a.vstride;
+    a.kout[ov] = k;
+    if (a.stage == 4) {
+      const double sm = ((a.k1[ov] + 2.0 * a.k2[ov]) + 2.0 * a.k3[ov]) + k;
+      a.ynew[ov] = a.yn[ov] + a.dt6 * sm;
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_z4c_rad_fill(const Z4cRadArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_z4c_rad_fill, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_z4c_radiative(const Z4cRadArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_z4c_radiative, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, bool f32, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;

@@ -43,6 +43,34 @@ struct Z4cCombineArgs {
   double cdt;
 };
 
+// Radiative outer boundary (level 0, FP64): the physical-boundary ghost slots
+// of the level's single box, all members.
+struct Z4cRadArgs {
+  const int64_t* idx;    // halo offsets of the ghost slots (member-major)
+  int64_t n;             // slots, all members
+  int64_t per_member;    // slots per member
+  const BoxDev* boxes;   // level-0 boxes, one per member
+  const double* Y;       // stage vector table (owned and halo)
+  const double* yn;      // y_n (ghost values live in the halo of the state arrays)
+  const double* kprev;   // k_{s-1} (stage fill), null at stage 1
+  const double* k1;      // stage 4
+  const double* k2;
+  const double* k3;
+  double* kout;          // k_s at the ghosts
+  double* ynew;          // y_{n+1} at the ghosts (stage 4)
+  double* table;         // stage fill output: the stage vector table
+  int64_t vstride;
+  int32_t stage;
+  double cdt;            // c_s dt (stage fill)
+  double dt6;
+  double h;
+  double origin[3];
+};
+// the ghosts' stage values y_n + c_s dt k_{s-1} into the table (before the
+// interior stencils), and their right-hand side (after)
+hipError_t launch_z4c_rad_fill(const Z4cRadArgs& a, hipStream_t s);
+hipError_t launch_z4c_radiative(const Z4cRadArgs& a, hipStream_t s);
+
 // f32: FP32-RHS variant (TS = float)
 hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, bool f32, hipStream_t s);
 hipError_t launch_z4c_combine(const Z4cCombineArgs& a, int grid, bool f32, hipStream_t s);

@@ -18,11 +18,13 @@ TOL = 1e-12
 KW = dict(min_block=8, max_block=16)
 
 
-def _pair(spec, exec=sc.SC_EXEC_BATCHED, precision=sc.SC_FP64):
-    ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=exec, precision=precision)
+def _pair(spec, exec=sc.SC_EXEC_BATCHED, precision=sc.SC_FP64, outer_bc=sc.SC_BC_FROZEN):
+    ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=exec, precision=precision,
+                     outer_bc=outer_bc)
     ctx.build_spec(spec, **KW)
     ctx.bind()
-    ref = OracleRun(Hierarchy(spec, **KW), rhs="z4c")
+    ref = OracleRun(Hierarchy(spec, **KW), rhs="z4c",
+                    outer_bc="radiative" if outer_bc == sc.SC_BC_RADIATIVE else "frozen")
     for l in range(spec.nlevels):
         for v, f in enumerate(brill_lindquist_on_spec(spec, l)):
             ctx.set_initial_data(0, l, v, f)
@@ -129,3 +131,19 @@ def test_z4c_fp32_rhs_variant_hamiltonian():
         e = np.abs(a - b).max() / np.abs(b).max()
         print("level", l, "H rel diff fp32-rhs vs fp64", e)
         assert e < 1e-3
+
+
+@pytest.mark.parametrize("exec", [sc.SC_EXEC_BATCHED, sc.SC_EXEC_GRAPH, sc.SC_EXEC_PER_BLOCK])
+def test_z4c_radiative_boundary_matches_reference(exec):
+    """Evolved outer ghosts (radiative condition) on level 0: fields and slopes
+    on every level after two coarse steps, and the Hamiltonian constraint."""
+    spec = config_z4c_small()
+    ctx, ref = _pair(spec, exec=exec, outer_bc=sc.SC_BC_RADIATIVE)
+    ctx.advance(2)
+    ref.advance(2)
+    w = _compare(ctx, ref, arrays=(sc.SC_ARR_Y, sc.SC_ARR_K1, sc.SC_ARR_K4))
+    print("z4c radiative exec", exec, "worst rel diff", w)
+    if exec == sc.SC_EXEC_BATCHED:
+        for l in range(spec.nlevels):
+            a, b = ctx.hamiltonian(0, l), ref.hamiltonian(l)
+            assert np.abs(a - b).max() / np.abs(b).max() <= 1e-10

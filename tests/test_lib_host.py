@@ -194,3 +194,16 @@ def test_eighth_order_configuration_rules():
         with pytest.raises(sc.ScError) as e:
             sc.Context(**dict(dict(fd_order=8), **kw))
         assert e.value.code == sc.SC_E_ARG
+
+
+def test_radiative_boundary_configuration_rules():
+    sc.Context(rhs=sc.SC_RHS_Z4C, outer_bc=sc.SC_BC_RADIATIVE)
+    for kw in (dict(rhs=sc.SC_RHS_WAVE), dict(rhs=sc.SC_RHS_Z4C, precision=sc.SC_MIXED),
+               dict(rhs=sc.SC_RHS_Z4C, outer_bc=2)):
+        with pytest.raises(sc.ScError) as e:
+            sc.Context(**dict(dict(outer_bc=sc.SC_BC_RADIATIVE), **kw))
+        assert e.value.code == sc.SC_E_ARG
+    ctx = sc.Context(rhs=sc.SC_RHS_Z4C, outer_bc=sc.SC_BC_RADIATIVE)
+    with pytest.raises(sc.ScError) as e:     # periodic domain
+        ctx.build_spec(config_c2(16), min_block=4, max_block=9)
+    assert e.value.code == sc.SC_E_ARG
