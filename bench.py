@@ -128,8 +128,10 @@ def z4c_run(args):
     U = spec.updates_per_coarse_step()
     log(f"workload {spec.name}: {spec.total_points()} points, {U} updates per coarse step")
     mixed = args.z4c_precision == "mixed"
+    radiative = args.z4c_bc == "radiative"
     ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=sc.SC_EXEC_GRAPH,
-                     precision=sc.SC_MIXED if mixed else sc.SC_FP64)
+                     precision=sc.SC_MIXED if mixed else sc.SC_FP64,
+                     outer_bc=sc.SC_BC_RADIATIVE if radiative else sc.SC_BC_FROZEN)
     ctx.build_spec(spec)
     ctx.bind()
     for l in range(spec.nlevels):
@@ -144,6 +146,9 @@ def z4c_run(args):
     for l in range(spec.nlevels):
         x, y, z = canonical_coords(spec, l)
         masks.append((composite_weights(spec, l), np.sqrt(x * x + y * y + z * z) < 30.0))
+    x0, y0, z0 = canonical_coords(spec, 0)
+    r0 = np.sqrt(x0 * x0 + y0 * y0 + z0 * z0)
+    outer = (r0 > 64.0) & (np.maximum(np.maximum(abs(x0), abs(y0)), abs(z0)) < 112.0)
 
     def hnorm():
         num = den = 0.0
@@ -156,6 +161,11 @@ def z4c_run(args):
             den += float(np.sum(w[m]))
         return np.sqrt(num / den) if den > 0 else float("nan")
 
+    def hnorm_outer():
+        # level 0 between r = 64 and 6 points inside the outer boundary (|x_i| < 112)
+        H = ctx.hamiltonian(0, 0)
+        return float(np.sqrt(np.mean(H[outer] ** 2)))
+
     hist = []
     log("z4c: initial data set; first coarse step (graph capture) ...")
     t0 = time.perf_counter()
@@ -163,6 +173,7 @@ def z4c_run(args):
     ctx.synchronize()
     log(f"z4c: first coarse step {time.perf_counter() - t0:.2f} s")
     hist.append((ctx.level_time(0), hnorm()))
+    outer_hist = [(ctx.level_time(0), hnorm_outer())]
     log(f"z4c: t = {hist[-1][0]:.4f}, ||H|| = {hist[-1][1]:.4e}")
     steps = args.z4c_steps - 1
     torch.cuda.synchronize()
@@ -173,6 +184,10 @@ def z4c_run(args):
         ctx.synchronize()
         T += time.perf_counter() - t0
         log(f"z4c: coarse step {i + 2}/{args.z4c_steps}: {T / (i + 1) * 1e3:.1f} ms per step")
+        if args.z4c_h_every and (i + 2) % args.z4c_h_every == 0:
+            outer_hist.append((ctx.level_time(0), hnorm_outer()))
+            log(f"z4c: t = {outer_hist[-1][0]:.2f}: ||H|| near the outer boundary "
+                f"{outer_hist[-1][1]:.4e}")
     hist.append((ctx.level_time(0), hnorm()))
     log(f"z4c: {1e3 * T / steps:.1f} ms per coarse step, {U * steps / T:.4g} updates/s")
     finite = ctx.check_finite() == sc.SC_OK
@@ -183,7 +198,10 @@ def z4c_run(args):
             "config": {"workload": "Z4c Brill-Lindquist punctures m=0.5 at x=+-3, 7 levels of "
                                    "96^3, [-128,128]^3, graph mode"
                                    + (", FP32 right-hand side" if mixed else "")},
-            "hamiltonian_L2": [{"t": t, "H": h} for t, h in hist], "finite": finite}
+            "outer_bc": args.z4c_bc,
+            "hamiltonian_L2": [{"t": t, "H": h} for t, h in hist],
+            "hamiltonian_L2_outer_shell": [{"t": t, "H": h} for t, h in outer_hist],
+            "finite": finite}
 
 
 def e1_run(args):
@@ -440,6 +458,9 @@ def main():
     ap.add_argument("--e1-modes", default="subcycled,uniform")
     ap.add_argument("--z4c-steps", type=int, default=16)
     ap.add_argument("--z4c-precision", default="fp64", choices=("fp64", "mixed"))
+    ap.add_argument("--z4c-bc", default="frozen", choices=("frozen", "radiative"))
+    ap.add_argument("--z4c-h-every", type=int, default=0,
+                    help="also report the constraint near the outer boundary every N coarse steps")
     ap.add_argument("--report-n0", type=int, nargs="+", default=[64, 128, 256])
     args = ap.parse_args()
     if args.gpus != 1:
