@@ -223,8 +223,8 @@ class OracleRun:
     """Reference evolution of one member of a hierarchy.
 
     rhs: "wave" (variables u, Pi) or "z4c" (22 variables, Sec. III.A; see
-    oracle/z4c.c).  fd_order: 4, or 8 for the wave system's eighth-order
-    Laplacian (oracle/stencil.c; needs a hierarchy with G >= 4).  sigma: Kreiss-Oliger strength.  cfl: dt_l = cfl * dx_l.
+    oracle/z4c.c).  fd_order: 4, or 8 for eighth-order derivatives
+    (oracle/stencil.c, oracle/z4c.c; needs a hierarchy with G >= 4).  sigma: Kreiss-Oliger strength.  cfl: dt_l = cfl * dx_l.
     z4c: kappa1, kappa2, eta_c, eta_o, eta_s.
     """
 
@@ -233,8 +233,8 @@ class OracleRun:
                  buffer_zones: bool = False, fd_order: int = 4, outer_bc: str = "frozen"):
         if rhs not in ("wave", "z4c"):
             raise ValueError(rhs)
-        if fd_order not in (4, 8) or (fd_order == 8 and (rhs != "wave" or hier.G < 4)):
-            raise ValueError("fd_order 8 needs the wave system and G >= 4")
+        if fd_order not in (4, 8) or (fd_order == 8 and hier.G < 4):
+            raise ValueError("fd_order 8 needs G >= 4")
         self.fd_order = fd_order
         if outer_bc not in ("frozen", "radiative"):
             raise ValueError(outer_bc)
@@ -402,10 +402,9 @@ class OracleRun:
             f(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total, cbuild.ptr(Y), cbuild.ptr(k),
               self.dx[l], self.sigma)
         else:
-            self.lib.orc_z4c_rhs(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
-                                 cbuild.ptr(Y), cbuild.ptr(k), self.dx[l],
-                                 cbuild.ptr(self.z4c_par), cbuild.ptr(self.block_origin[l]),
-                                 None, None)
+            f = self.lib.orc_z4c_rhs8 if self.fd_order == 8 else self.lib.orc_z4c_rhs
+            f(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total, cbuild.ptr(Y), cbuild.ptr(k),
+              self.dx[l], cbuild.ptr(self.z4c_par), cbuild.ptr(self.block_origin[l]), None, None)
 
     def hamiltonian(self, l: int) -> np.ndarray:
         """Hamiltonian constraint of the current state on owned points (canonical order)."""
@@ -420,7 +419,8 @@ class OracleRun:
         self.P[l] = saved
         k = np.zeros_like(A)
         ham = np.zeros(st.total)
-        self.lib.orc_z4c_rhs(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
+        f = self.lib.orc_z4c_rhs8 if self.fd_order == 8 else self.lib.orc_z4c_rhs
+        f(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total,
                              cbuild.ptr(A), cbuild.ptr(k), self.dx[l], cbuild.ptr(self.z4c_par),
                              cbuild.ptr(self.block_origin[l]), None, cbuild.ptr(ham))
         return ham[st.canon]

@@ -15,7 +15,11 @@
  *   Dt_i Dt_j W = d_i d_j W - Gt^k_ij d_k W,  R = W^2 gtu^ij R_ij,
  *   [X]^TF_ij = X_ij - gt_ij gtu^kl X_kl / 3,  indices raised with gtu.
  * Derivatives: fourth-order centred D1, D2, and D1_x(D1_y) for mixed second
- * derivatives; advection beta^k d_k uses the centred D1.
+ * derivatives; advection beta^k d_k uses the centred D1.  With order 8 (the
+ * paper's production stencil, Sec. III.C; G >= 4) the same with the
+ * eighth-order centred weights: D1 = (3, -32, 168, -672, 0, 672, -168, 32, -3)
+ * / (840 h), D2 = (-9, 128, -1008, 8064, -14350, 8064, -1008, 128, -9)
+ * / (5040 h^2); the dissipation stays the r = 4 operator.
  * Variables (slot order): W, gt_xx,xy,xz,yy,yz,zz, Khat, At_xx..zz, Theta,
  * Gt^x,y,z, alpha, beta^x,y,z.
  * Storage as in stencil.c: padded blocks {base, nx, ny, nz}, variable v at
@@ -29,17 +33,32 @@ enum { VW = 0, VG = 1, VKH = 7, VA = 8, VTH = 14, VGAM = 15, VALP = 18, VB = 19,
 
 static const int SYM[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
 
+static int ORDER = 4;   /* set per call of the right-hand side */
+
 static double D1(const double* a, int64_t o, int64_t s, double c1) {
+  if (ORDER == 8)
+    return (((((((3.0 * a[o - 4 * s] - 32.0 * a[o - 3 * s]) + 168.0 * a[o - 2 * s]) -
+                672.0 * a[o - s]) + 672.0 * a[o + s]) - 168.0 * a[o + 2 * s]) +
+             32.0 * a[o + 3 * s]) - 3.0 * a[o + 4 * s]) * c1;
   return (((a[o - 2 * s] - 8.0 * a[o - s]) + 8.0 * a[o + s]) - a[o + 2 * s]) * c1;
 }
 
 static double D2(const double* a, int64_t o, int64_t s, double c2) {
+  if (ORDER == 8)
+    return ((((((((-9.0 * a[o - 4 * s] + 128.0 * a[o - 3 * s]) - 1008.0 * a[o - 2 * s]) +
+                 8064.0 * a[o - s]) - 14350.0 * a[o]) + 8064.0 * a[o + s]) -
+              1008.0 * a[o + 2 * s]) + 128.0 * a[o + 3 * s]) - 9.0 * a[o + 4 * s]) * c2;
   return ((((-a[o - 2 * s] + 16.0 * a[o - s]) - 30.0 * a[o]) + 16.0 * a[o + s]) - a[o + 2 * s]) *
          c2;
 }
 
 static double DM(const double* a, int64_t o, int64_t s, int64_t t, double c1) {
   /* D1 along s of D1 along t */
+  if (ORDER == 8)
+    return (((((((3.0 * D1(a, o - 4 * s, t, c1) - 32.0 * D1(a, o - 3 * s, t, c1)) +
+                 168.0 * D1(a, o - 2 * s, t, c1)) - 672.0 * D1(a, o - s, t, c1)) +
+               672.0 * D1(a, o + s, t, c1)) - 168.0 * D1(a, o + 2 * s, t, c1)) +
+             32.0 * D1(a, o + 3 * s, t, c1)) - 3.0 * D1(a, o + 4 * s, t, c1)) * c1;
   return (((D1(a, o - 2 * s, t, c1) - 8.0 * D1(a, o - s, t, c1)) + 8.0 * D1(a, o + s, t, c1)) -
           D1(a, o + 2 * s, t, c1)) *
          c1;
@@ -54,7 +73,8 @@ static double KO(const double* a, int64_t o, int64_t s) {
 static void z4c_point(const double* Y, int64_t o, int64_t vs, const int64_t st[3], double h,
                       const double* par, const double xyz[3], double* rhs, double* ricci,
                       double* ham) {
-  const double c1 = 1.0 / (12.0 * h), c2 = 1.0 / (12.0 * h * h);
+  const double c1 = ORDER == 8 ? 1.0 / (840.0 * h) : 1.0 / (12.0 * h);
+  const double c2 = ORDER == 8 ? 1.0 / (5040.0 * h * h) : 1.0 / (12.0 * h * h);
   const double kappa1 = par[0], kappa2 = par[1], eta_c = par[2], eta_o = par[3],
                eta_s = par[4], sigma = par[5];
   double v[NV], d[NV][3];
@@ -283,8 +303,9 @@ static void z4c_point(const double* Y, int64_t o, int64_t vs, const int64_t st[3
 /* k = Z4c RHS of Y on owned points.  origin[3*b..] = coordinates of block b's
  * owned point (0,0,0).  ricci (6 slots) and ham (1 slot) are optional outputs
  * in the same padded layout. */
-void orc_z4c_rhs(int nb, const int64_t* desc, int G, int64_t vstride, const double* Y, double* k,
-                 double h, const double* par, const double* origin, double* ricci, double* ham) {
+static void z4c_rhs(int nb, const int64_t* desc, int G, int64_t vstride, const double* Y,
+                    double* k, double h, const double* par, const double* origin, double* ricci,
+                    double* ham) {
   for (int b = 0; b < nb; ++b) {
     const int64_t base = desc[4 * b];
     const int nx = (int)desc[4 * b + 1], ny = (int)desc[4 * b + 2], nz = (int)desc[4 * b + 3];
@@ -304,4 +325,18 @@ void orc_z4c_rhs(int nb, const int64_t* desc, int G, int64_t vstride, const doub
           if (ham) ham[o] = hm;
         }
   }
+}
+
+void orc_z4c_rhs(int nb, const int64_t* desc, int G, int64_t vstride, const double* Y, double* k,
+                 double h, const double* par, const double* origin, double* ricci, double* ham) {
+  ORDER = 4;
+  z4c_rhs(nb, desc, G, vstride, Y, k, h, par, origin, ricci, ham);
+}
+
+/* The same with the eighth-order derivatives (G >= 4). */
+void orc_z4c_rhs8(int nb, const int64_t* desc, int G, int64_t vstride, const double* Y,
+                  double* k, double h, const double* par, const double* origin, double* ricci,
+                  double* ham) {
+  ORDER = 8;
+  z4c_rhs(nb, desc, G, vstride, Y, k, h, par, origin, ricci, ham);
 }
