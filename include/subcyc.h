@@ -129,10 +129,10 @@ typedef struct {
   double z4c_eta_c;    /* shift damping eta(r) = (eta_c - eta_o) exp(-(r/eta_s)^4) + eta_o, */
   double z4c_eta_o;    /*   r the distance from the coordinate origin; defaults 2, 0.25, 40 */
   double z4c_eta_s;    /*   (Sec. III.A, M = 1) */
-  int32_t fd_order;    /* wave Laplacian order: 4 (default), or 8 with nghost 4 (the
-                          production stencil of Sec. III.C: nine-point centred second
-                          differences, the same fifth-order dissipation; wave RHS,
-                          FP64, SC_SUBCYCLED or SC_UNIFORM_DT) */
+  int32_t fd_order;    /* derivative order: 4 (default), or 8 with nghost 4 (the
+                          production stencil of Sec. III.C: nine-point centred first
+                          and second differences, the same fifth-order dissipation;
+                          wave or Z4c, FP64, SC_SUBCYCLED or SC_UNIFORM_DT) */
   int32_t outer_bc;    /* SC_BC_FROZEN (default) or SC_BC_RADIATIVE */
 } sc_config;
 

@@ -794,6 +794,7 @@ Z4cArgs z4c_args(sc_ctx* c, int l) {
   a.eta_o = c->cfg.z4c_eta_o;
   a.eta_s = c->cfg.z4c_eta_s;
   for (int d = 0; d < 3; ++d) a.origin[d] = c->hier.geo.origin[d];
+  a.ord = c->fd_order;
   return a;
 }
 
@@ -1188,8 +1189,8 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
   // eighth order: wave, FP64, four ghost layers, subcycled or uniform steps
   const bool order_ok =
       (cfg->fd_order == 4 && cfg->nghost == 3) ||
-      (cfg->fd_order == 8 && cfg->nghost == 4 && cfg->rhs == SC_RHS_WAVE &&
-       cfg->precision == SC_FP64 && cfg->time_stepping != SC_BUFFER_ZONES);
+      (cfg->fd_order == 8 && cfg->nghost == 4 && cfg->precision == SC_FP64 &&
+       cfg->time_stepping != SC_BUFFER_ZONES);
   // radiative outer boundary: Z4c, FP64
   const bool bc_ok = cfg->outer_bc == SC_BC_FROZEN ||
                      (cfg->outer_bc == SC_BC_RADIATIVE && cfg->rhs == SC_RHS_Z4C &&
@@ -1199,7 +1200,7 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
       cfg->ko_sigma < 0.0 || (cfg->precision != SC_FP64 && cfg->precision != SC_MIXED) ||
       cfg->exec < 0 || cfg->exec > 2) {
     g_create_error = "unsupported configuration (rhs, time stepping (buffer zones: wave, FP64), "
-                     "fd_order 4 with nghost 3 or 8 with nghost 4 (wave, FP64, no buffer zones), "
+                     "fd_order 4 with nghost 3 or 8 with nghost 4 (FP64, no buffer zones), "
                      "outer_bc (radiative: Z4c, FP64), "
                      "0 < cfl <= 0.5, sigma >= 0, precision, exec)";
     return SC_E_ARG;

@@ -36,7 +36,8 @@ __device__ __forceinline__ int sym(int i, int j) {
   return a == 0 ? b : (a == 1 ? 2 + b : 5);
 }
 
-template <typename TS>
+// ORD: 4 (five-point centred derivatives) or 8 (nine-point, four ghost layers)
+template <typename TS, int ORD>
 struct Pt {
   const Z4cArgs* a;
   BoxDev B;
@@ -51,12 +52,26 @@ struct Pt {
   __device__ TS tap(int v, int d, int j) const {
     return at(v, d == 0 ? j : 0, d == 1 ? j : 0, d == 2 ? j : 0);
   }
+  // first difference from the taps t(-R..R) (c1 = 1/(12h) or 1/(840h))
+  template <typename Tap>
+  __device__ static TS diff1(const Tap& t, TS c1) {
+    if constexpr (ORD == 8)
+      return (((((((TS(3.0) * t(-4) - TS(32.0) * t(-3)) + TS(168.0) * t(-2)) - TS(672.0) * t(-1)) +
+                 TS(672.0) * t(1)) - TS(168.0) * t(2)) + TS(32.0) * t(3)) - TS(3.0) * t(4)) * c1;
+    else
+      return (((t(-2) - TS(8.0) * t(-1)) + TS(8.0) * t(1)) - t(2)) * c1;
+  }
   __device__ TS d1(int v, int d, TS c1) const {
-    return (((tap(v, d, -2) - TS(8.0) * tap(v, d, -1)) + TS(8.0) * tap(v, d, 1)) - tap(v, d, 2)) * c1;
+    return diff1([&](int j) { return tap(v, d, j); }, c1);
   }
   __device__ TS d2(int v, int d, TS c2) const {
-    return ((((-tap(v, d, -2) + TS(16.0) * tap(v, d, -1)) - TS(30.0) * tap(v, d, 0)) + TS(16.0) * tap(v, d, 1)) -
-            tap(v, d, 2)) * c2;
+    if constexpr (ORD == 8)
+      return ((((((((-TS(9.0) * tap(v, d, -4) + TS(128.0) * tap(v, d, -3)) - TS(1008.0) * tap(v, d, -2)) +
+                   TS(8064.0) * tap(v, d, -1)) - TS(14350.0) * tap(v, d, 0)) + TS(8064.0) * tap(v, d, 1)) -
+                TS(1008.0) * tap(v, d, 2)) + TS(128.0) * tap(v, d, 3)) - TS(9.0) * tap(v, d, 4)) * c2;
+    else
+      return ((((-tap(v, d, -2) + TS(16.0) * tap(v, d, -1)) - TS(30.0) * tap(v, d, 0)) + TS(16.0) * tap(v, d, 1)) -
+              tap(v, d, 2)) * c2;
   }
   // D1 along d of D1 along e
   __device__ TS dm(int v, int d, int e, TS c1) const {
@@ -65,9 +80,9 @@ struct Pt {
       auto t = [&](int i) {
         return at(v, sx + (e == 0 ? i : 0), sy + (e == 1 ? i : 0), sz + (e == 2 ? i : 0));
       };
-      return (((t(-2) - TS(8.0) * t(-1)) + TS(8.0) * t(1)) - t(2)) * c1;
+      return diff1(t, c1);
     };
-    return (((inner(-2) - TS(8.0) * inner(-1)) + TS(8.0) * inner(1)) - inner(2)) * c1;
+    return diff1(inner, c1);
   }
   __device__ TS ko(int v, int d) const {
     return (((((tap(v, d, -3) - TS(6.0) * tap(v, d, -2)) + TS(15.0) * tap(v, d, -1)) - TS(20.0) * tap(v, d, 0)) +
@@ -85,10 +100,11 @@ struct Pt {
 // (24 values: R and D_i D_j alpha in symmetric order, then Gt^i,
 // Gt^i_jk At^jk, gt^jk d_j d_k beta^i, d_i d_k beta^k), or the Hamiltonian
 // constraint.
-template <typename TS>
-__device__ void z4c_geom(const Pt<TS>& p, const Z4cArgs& a, TS* out, double* ham_out) {
+template <typename TS, int ORD>
+__device__ void z4c_geom(const Pt<TS, ORD>& p, const Z4cArgs& a, TS* out, double* ham_out) {
   const TS h = TS(a.h);
-  const TS c1 = TS(1.0) / (TS(12.0) * h), c2 = TS(1.0) / (TS(12.0) * h * h);
+  const TS c1 = TS(1.0) / (TS(ORD == 8 ? 840.0 : 12.0) * h);
+  const TS c2 = TS(1.0) / (TS(ORD == 8 ? 5040.0 : 12.0) * h * h);
   TS v[NV], d[NV][3];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
@@ -325,10 +341,10 @@ __device__ void z4c_geom(const Pt<TS>& p, const Z4cArgs& a, TS* out, double* ham
 // Evolution pass (one point): every right-hand side except advection and
 // dissipation, from the curvature scratch of the same point.
 // geo(c) returns curvature value c of the point (the order z4c_geom writes).
-template <typename TS, typename Geo>
-__device__ void z4c_evol(const Pt<TS>& p, const Z4cArgs& a, const Geo& geo, TS* rhs) {
+template <typename TS, int ORD, typename Geo>
+__device__ void z4c_evol(const Pt<TS, ORD>& p, const Z4cArgs& a, const Geo& geo, TS* rhs) {
   const TS h = TS(a.h);
-  const TS c1 = TS(1.0) / (TS(12.0) * h);
+  const TS c1 = TS(1.0) / (TS(ORD == 8 ? 840.0 : 12.0) * h);
   TS v[NV], d[NV][3];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
@@ -470,7 +486,7 @@ __device__ void z4c_evol(const Pt<TS>& p, const Z4cArgs& a, const Geo& geo, TS* 
 }
 
 // One thread per owned point of the tiles: calls point(p) for each.
-template <typename TS, typename F>
+template <typename TS, int ORD, typename F>
 __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
   const int tx = threadIdx.x % kTileMaxX, ty = threadIdx.x / kTileMaxX;
   constexpr int BY = kZ4cThreads / kTileMaxX;
@@ -480,7 +496,7 @@ __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
     for (int ry = ty; ry < T.ny; ry += BY) {
       if (tx >= T.nx) continue;
       for (int iz = 0; iz < T.nz; ++iz) {
-        Pt<TS> p;
+        Pt<TS, ORD> p;
         p.a = &a;
         p.B = B;
         p.x = T.x0 + tx;
@@ -496,20 +512,20 @@ __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
 }
 
 // Curvature pass into the per-point scratch, or the Hamiltonian constraint.
-template <typename TS>
+template <typename TS, int ORD>
 __global__ __launch_bounds__(kZ4cThreads) void k_z4c_geom(Z4cArgs a) {
   TS* geo = static_cast<TS*>(a.geo);
-  z4c_points<TS>(a, [&](const Pt<TS>& p) {
+  z4c_points<TS, ORD>(a, [&](const Pt<TS, ORD>& p) {
     if constexpr (sizeof(TS) == 8) {
       if (a.ham) {
         double hm;
-        z4c_geom<TS>(p, a, nullptr, &hm);
+        z4c_geom<TS, ORD>(p, a, nullptr, &hm);
         a.ham[p.o] = hm;
         return;
       }
     }
     TS g[kZ4cGeo];
-    z4c_geom<TS>(p, a, g, nullptr);
+    z4c_geom<TS, ORD>(p, a, g, nullptr);
 #pragma unroll
     for (int c = 0; c < kZ4cGeo; ++c) geo[p.o + c * a.vstride] = g[c];
   });
@@ -519,18 +535,18 @@ __global__ __launch_bounds__(kZ4cThreads) void k_z4c_geom(Z4cArgs a) {
 // advection, no dissipation) from the curvature scratch.
 // FUSED: the curvature pass runs in the same thread and hands its values over
 // in registers (no scratch traffic, more registers live).
-template <typename TS, bool FUSED>
+template <typename TS, bool FUSED, int ORD>
 __global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
   TS* kout = static_cast<TS*>(a.kout);
-  z4c_points<TS>(a, [&](const Pt<TS>& p) {
+  z4c_points<TS, ORD>(a, [&](const Pt<TS, ORD>& p) {
     TS rhs[NV];
     if constexpr (FUSED) {
       TS g[kZ4cGeo];
-      z4c_geom<TS>(p, a, g, nullptr);
-      z4c_evol<TS>(p, a, [&](int c) -> TS { return g[c]; }, rhs);
+      z4c_geom<TS, ORD>(p, a, g, nullptr);
+      z4c_evol<TS, ORD>(p, a, [&](int c) -> TS { return g[c]; }, rhs);
     } else {
       const TS* geo = static_cast<const TS*>(a.geo);
-      z4c_evol<TS>(p, a, [&](int c) -> TS { return geo[p.o + c * a.vstride]; }, rhs);
+      z4c_evol<TS, ORD>(p, a, [&](int c) -> TS { return geo[p.o + c * a.vstride]; }, rhs);
     }
 #pragma unroll
     for (int i = 0; i < NV; ++i) kout[p.o + i * a.vstride] = rhs[i];
@@ -541,7 +557,7 @@ __global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
 // first differences) and the Kreiss-Oliger dissipation of every variable;
 // at stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4) in
 // FP64.  Both stencils read the same seven taps per axis.
-template <int STAGE, typename TS>
+template <int STAGE, typename TS, int ORD>
 __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
   const int tx = threadIdx.x % kTileMaxX, ty = threadIdx.x / kTileMaxX;
   const TS* Y = static_cast<const TS*>(a.Y);
@@ -550,8 +566,9 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
   const TS* k2 = static_cast<const TS*>(a.k2);
   const TS* k3 = static_cast<const TS*>(a.k3);
   const TS h = TS(a.h);
-  const TS c1 = TS(1.0) / (TS(12.0) * h);
+  const TS c1 = TS(1.0) / (TS(ORD == 8 ? 840.0 : 12.0) * h);
   const TS cko = TS(a.sigma) / (TS(64.0) * h);
+  constexpr int R = ORD == 8 ? 4 : 3;   // taps per side: the first difference's, at least KO's 3
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
@@ -569,13 +586,13 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
           TS adv = TS(0.0), ko[3];
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
-            TS tp[7];
+            TS tp[2 * R + 1];
 #pragma unroll
-            for (int j = 0; j < 7; ++j) tp[j] = Y[oi + (j - 3) * st[d]];
-            const TS d1 = (((tp[1] - TS(8.0) * tp[2]) + TS(8.0) * tp[4]) - tp[5]) * c1;
+            for (int j = 0; j < 2 * R + 1; ++j) tp[j] = Y[oi + (j - R) * st[d]];
+            const TS d1 = Pt<TS, ORD>::diff1([&](int j) { return tp[R + j]; }, c1);
             adv += beta[d] * d1;
-            ko[d] = (((((tp[0] - TS(6.0) * tp[1]) + TS(15.0) * tp[2]) - TS(20.0) * tp[3]) +
-                      TS(15.0) * tp[4]) - TS(6.0) * tp[5]) + tp[6];
+            ko[d] = (((((tp[R - 3] - TS(6.0) * tp[R - 2]) + TS(15.0) * tp[R - 1]) - TS(20.0) * tp[R]) +
+                      TS(15.0) * tp[R + 1]) - TS(6.0) * tp[R + 2]) + tp[R + 3];
           }
           const TS k = (kout[oi] + adv) + cko * ((ko[0] + ko[1]) + ko[2]);
           kout[oi] = k;
@@ -689,22 +706,31 @@ hipError_t launch_z4c_radiative(const Z4cRadArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int ORD>
+void z4c_stage_f64(const Z4cArgs& a, dim3 g, dim3 b, dim3 b2, hipStream_t s) {
+  hipLaunchKernelGGL((k_z4c_geom<double, ORD>), g, b, 0, s, a);
+  if (!a.ham) {
+    hipLaunchKernelGGL((k_z4c_stage<double, false, ORD>), g, b, 0, s, a);
+    if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, double, ORD>), g, b2, 0, s, a);
+    else hipLaunchKernelGGL((k_z4c_advko<1, double, ORD>), g, b2, 0, s, a);
+  }
+}
+
 hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, bool f32, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g(grid > 0 ? grid : a.ntiles), b(kZ4cThreads), b2(256);
+  if (a.ord != 4 && a.ord != 8) return hipErrorInvalidValue;
   if (f32) {
+    if (a.ord != 4) return hipErrorInvalidValue;   // the FP32 variant is fourth order
     // FP32: the fused kernel fits the register file; FP64: two passes, since
     // one would spill
-    hipLaunchKernelGGL((k_z4c_stage<float, true>), g, b, 0, s, a);
-    if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, float>), g, b2, 0, s, a);
-    else hipLaunchKernelGGL((k_z4c_advko<1, float>), g, b2, 0, s, a);
+    hipLaunchKernelGGL((k_z4c_stage<float, true, 4>), g, b, 0, s, a);
+    if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, float, 4>), g, b2, 0, s, a);
+    else hipLaunchKernelGGL((k_z4c_advko<1, float, 4>), g, b2, 0, s, a);
+  } else if (a.ord == 8) {
+    z4c_stage_f64<8>(a, g, b, b2, s);
   } else {
-    hipLaunchKernelGGL(k_z4c_geom<double>, g, b, 0, s, a);
-    if (!a.ham) {
-      hipLaunchKernelGGL((k_z4c_stage<double, false>), g, b, 0, s, a);
-      if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, double>), g, b2, 0, s, a);
-      else hipLaunchKernelGGL((k_z4c_advko<1, double>), g, b2, 0, s, a);
-    }
+    z4c_stage_f64<4>(a, g, b, b2, s);
   }
   return hipGetLastError();
 }

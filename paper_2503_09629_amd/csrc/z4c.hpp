@@ -29,6 +29,7 @@ struct Z4cArgs {
   int64_t vstride;
   double h, dt6, sigma, kappa1, kappa2, eta_c, eta_o, eta_s;
   double origin[3];   // coordinates of global index (0,0,0) of the level
+  int32_t ord;        // derivative order: 4, or 8 (FP64, boxes padded by 4)
 };
 
 struct Z4cCombineArgs {

@@ -18,13 +18,15 @@ TOL = 1e-12
 KW = dict(min_block=8, max_block=16)
 
 
-def _pair(spec, exec=sc.SC_EXEC_BATCHED, precision=sc.SC_FP64, outer_bc=sc.SC_BC_FROZEN):
+def _pair(spec, exec=sc.SC_EXEC_BATCHED, precision=sc.SC_FP64, outer_bc=sc.SC_BC_FROZEN,
+          fd_order=4):
     ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=exec, precision=precision,
-                     outer_bc=outer_bc)
+                     outer_bc=outer_bc, fd_order=fd_order)
     ctx.build_spec(spec, **KW)
     ctx.bind()
-    ref = OracleRun(Hierarchy(spec, **KW), rhs="z4c",
-                    outer_bc="radiative" if outer_bc == sc.SC_BC_RADIATIVE else "frozen")
+    ref = OracleRun(Hierarchy(spec, G=4 if fd_order == 8 else 3, **KW), rhs="z4c",
+                    outer_bc="radiative" if outer_bc == sc.SC_BC_RADIATIVE else "frozen",
+                    fd_order=fd_order)
     for l in range(spec.nlevels):
         for v, f in enumerate(brill_lindquist_on_spec(spec, l)):
             ctx.set_initial_data(0, l, v, f)
@@ -143,6 +145,23 @@ def test_z4c_radiative_boundary_matches_reference(exec):
     ref.advance(2)
     w = _compare(ctx, ref, arrays=(sc.SC_ARR_Y, sc.SC_ARR_K1, sc.SC_ARR_K4))
     print("z4c radiative exec", exec, "worst rel diff", w)
+    if exec == sc.SC_EXEC_BATCHED:
+        for l in range(spec.nlevels):
+            a, b = ctx.hamiltonian(0, l), ref.hamiltonian(l)
+            assert np.abs(a - b).max() / np.abs(b).max() <= 1e-10
+
+
+@pytest.mark.parametrize("exec", [sc.SC_EXEC_BATCHED, sc.SC_EXEC_GRAPH])
+@pytest.mark.parametrize("bc", [sc.SC_BC_FROZEN, sc.SC_BC_RADIATIVE])
+def test_z4c_eighth_order_matches_reference(exec, bc):
+    """Eighth-order derivatives with four ghost layers (the production stencil
+    of Sec. III.C), with both outer boundaries."""
+    spec = config_z4c_small()
+    ctx, ref = _pair(spec, exec=exec, outer_bc=bc, fd_order=8)
+    ctx.advance(2)
+    ref.advance(2)
+    w = _compare(ctx, ref, arrays=(sc.SC_ARR_Y, sc.SC_ARR_K1, sc.SC_ARR_K4))
+    print("z4c eighth order exec", exec, "bc", bc, "worst rel diff", w)
     if exec == sc.SC_EXEC_BATCHED:
         for l in range(spec.nlevels):
             a, b = ctx.hamiltonian(0, l), ref.hamiltonian(l)

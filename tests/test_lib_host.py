@@ -189,7 +189,8 @@ def test_four_ghost_layer_maps_bit_identical_to_reference(name):
 def test_eighth_order_configuration_rules():
     sc.Context(fd_order=8)
     sc.Context(fd_order=8, time_stepping=sc.SC_UNIFORM_DT)
-    for kw in (dict(precision=sc.SC_MIXED), dict(rhs=sc.SC_RHS_Z4C),
+    sc.Context(fd_order=8, rhs=sc.SC_RHS_Z4C)
+    for kw in (dict(precision=sc.SC_MIXED), dict(rhs=sc.SC_RHS_Z4C, precision=sc.SC_MIXED),
                dict(time_stepping=sc.SC_BUFFER_ZONES), dict(fd_order=6)):
         with pytest.raises(sc.ScError) as e:
             sc.Context(**dict(dict(fd_order=8), **kw))
