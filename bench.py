@@ -131,7 +131,8 @@ def z4c_run(args):
     radiative = args.z4c_bc == "radiative"
     ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=sc.SC_EXEC_GRAPH,
                      precision=sc.SC_MIXED if mixed else sc.SC_FP64,
-                     outer_bc=sc.SC_BC_RADIATIVE if radiative else sc.SC_BC_FROZEN)
+                     outer_bc=sc.SC_BC_RADIATIVE if radiative else sc.SC_BC_FROZEN,
+                     fd_order=args.z4c_fd_order)
     ctx.build_spec(spec)
     ctx.bind()
     for l in range(spec.nlevels):
@@ -198,7 +199,7 @@ def z4c_run(args):
             "config": {"workload": "Z4c Brill-Lindquist punctures m=0.5 at x=+-3, 7 levels of "
                                    "96^3, [-128,128]^3, graph mode"
                                    + (", FP32 right-hand side" if mixed else "")},
-            "outer_bc": args.z4c_bc,
+            "outer_bc": args.z4c_bc, "fd_order": args.z4c_fd_order,
             "hamiltonian_L2": [{"t": t, "H": h} for t, h in hist],
             "hamiltonian_L2_outer_shell": [{"t": t, "H": h} for t, h in outer_hist],
             "finite": finite}
@@ -459,6 +460,7 @@ def main():
     ap.add_argument("--z4c-steps", type=int, default=16)
     ap.add_argument("--z4c-precision", default="fp64", choices=("fp64", "mixed"))
     ap.add_argument("--z4c-bc", default="frozen", choices=("frozen", "radiative"))
+    ap.add_argument("--z4c-fd-order", type=int, default=4, choices=(4, 8))
     ap.add_argument("--z4c-h-every", type=int, default=0,
                     help="also report the constraint near the outer boundary every N coarse steps")
     ap.add_argument("--report-n0", type=int, nargs="+", default=[64, 128, 256])
