@@ -467,7 +467,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "layout is a design, not part of this build", file=sys.stderr)
+              "layout is described in the design notes, not implemented", file=sys.stderr)
         sys.exit(2)
     if args.copy_probe_mib > 0:
         import torch
