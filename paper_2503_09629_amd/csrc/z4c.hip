@@ -517,26 +517,26 @@ __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
 }
 
 // Curvature pass into the per-point scratch, or the Hamiltonian constraint.
-// PART selects what one launch stores (the rest of the curvature pass is dead
-// code the compiler drops, so each part holds fewer values live): 0 the Ricci
-// tensor (scratch values 0..5), 1 the other 18 values, 2 the Hamiltonian
-// constraint (FP64), 3 all 24 values, 4 all 24 values or, when a.ham is set,
-// the constraint (one kernel for both, as measured fastest).
-template <typename TS, int ORD, int PART>
+// Curvature pass into the per-point scratch, or the Hamiltonian constraint.
+// (One kernel for both modes: on C5 this allocation runs faster than a
+// constraint-free variant without spills, 3.7 against 4.2 s per coarse step,
+// or a split of the pass by output, 4.3 s.)
+template <typename TS, int ORD>
 __global__ __launch_bounds__(kZ4cThreads) void k_z4c_geom(Z4cArgs a) {
   TS* geo = static_cast<TS*>(a.geo);
   z4c_points<TS, ORD>(a, [&](const Pt<TS, ORD>& p) {
-    if (PART == 2 || (PART == 4 && a.ham)) {
-      double hm;
-      z4c_geom<TS, ORD>(p, a, nullptr, &hm);
-      a.ham[p.o] = hm;
-    } else {
-      TS g[kZ4cGeo];
-      z4c_geom<TS, ORD>(p, a, g, nullptr);
-      constexpr int c0 = PART == 1 ? 6 : 0, c1 = PART == 0 ? 6 : kZ4cGeo;
-#pragma unroll
-      for (int c = c0; c < c1; ++c) geo[p.o + c * a.vstride] = g[c];
+    if constexpr (sizeof(TS) == 8) {
+      if (a.ham) {
+        double hm;
+        z4c_geom<TS, ORD>(p, a, nullptr, &hm);
+        a.ham[p.o] = hm;
+        return;
+      }
     }
+    TS g[kZ4cGeo];
+    z4c_geom<TS, ORD>(p, a, g, nullptr);
+#pragma unroll
+    for (int c = 0; c < kZ4cGeo; ++c) geo[p.o + c * a.vstride] = g[c];
   });
 }
 
@@ -717,13 +717,8 @@ hipError_t launch_z4c_radiative(const Z4cRadArgs& a, hipStream_t s) {
 
 template <int ORD>
 void z4c_stage_f64(const Z4cArgs& a, dim3 g, dim3 b, dim3 b2, hipStream_t s) {
-  if (a.ham) {
-    hipLaunchKernelGGL((k_z4c_geom<double, ORD, 2>), g, b, 0, s, a);
-  } else {
-    // one pass for all 24 values (part 4): on C5 it runs faster than the
-    // unspilled part 3 (3.7 against 4.2 s per coarse step at fourth order) and
-    // than the two-pass split by output (4.3 s)
-    hipLaunchKernelGGL((k_z4c_geom<double, ORD, 4>), g, b, 0, s, a);
+  hipLaunchKernelGGL((k_z4c_geom<double, ORD>), g, b, 0, s, a);
+  if (!a.ham) {
     hipLaunchKernelGGL((k_z4c_stage<double, false, ORD>), g, b, 0, s, a);
     if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, double, ORD>), g, b2, 0, s, a);
     else hipLaunchKernelGGL((k_z4c_advko<1, double, ORD>), g, b2, 0, s, a);
