@@ -1774,7 +1774,7 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
       HIPCHK(c, upload(c, L.d_tiles, tl));
       L.tiles = tl;
       for (int depth : {1, 2})
-      for (int g : {2 * ncu, 4 * ncu, 8 * ncu, 1 << 30}) {
+      for (int g : {2 * ncu, 3 * ncu, 4 * ncu, 8 * ncu, 1 << 30}) {
         if (!stage_variant_ok(slots, depth, threads)) break;
         sh.grid = std::min<int>(g, (int)tl.size());
         sh.depth = depth;

@@ -22,8 +22,11 @@ struct TileShape {
 };
 
 // z-chunk depths the autotuner tries; the tile table region is sized for the
-// shallowest (most tiles).
-constexpr int kTuneTz[] = {4, 6, 8, 12, 16, 24, 32, 48, 64, 1 << 20};
+// shallowest (most tiles).  Consecutive depths up to 16 let the tile count land
+// just under a whole number of rounds of resident workgroups: a tile takes a
+// sizeable part of a launch, so a last round that fills few CUs costs much.
+constexpr int kTuneTz[] = {4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 18, 20,
+                           24, 28, 32, 40, 48, 64, 1 << 20};
 constexpr int kTuneTzMin = 4;
 
 struct LevelDev {
