@@ -225,6 +225,14 @@ std::string build_layout(sc_ctx* c) {
     L.has_child = l + 1 < nl;
     L.nbuf = c->cfg.time_stepping == SC_BUFFER_ZONES ? 3 : 2;
     L.shape.radius = c->fd_order == 8 ? 4 : 3;
+    if (c->cfg.rhs == SC_RHS_Z4C) {
+      // the Z4c kernels run one wave per SIMD (two 128-thread workgroups per
+      // CU): short, half-height tiles (four planes, at most 256 points per
+      // plane) give each CU several to interleave instead of leaving it idle
+      // after the box's few tall tiles are handed out
+      L.shape.tz = kTuneTzMin;
+      L.shape.slots = 1;
+    }
     L.nyh = l == 0 ? 1 : 8;
     // boxes of member 0
     std::vector<BoxDev> b0(L.nb_member);

@@ -493,18 +493,18 @@ __device__ void z4c_evol(const Pt<TS, ORD>& p, const Z4cArgs& a, const Geo& geo,
 // One thread per owned point of the tiles: calls point(p) for each.
 template <typename TS, int ORD, typename F>
 __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
-  const int tx = threadIdx.x % kTileMaxX, ty = threadIdx.x / kTileMaxX;
-  constexpr int BY = kZ4cThreads / kTileMaxX;
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
-    for (int ry = ty; ry < T.ny; ry += BY) {
-      if (tx >= T.nx) continue;
+    // threads packed over the tile's x-y points row by row: no lane idles on
+    // a tile narrower than a wavefront
+    for (int i = threadIdx.x; i < T.nx * T.ny; i += kZ4cThreads) {
+      const int rx = i % T.nx, ry = i / T.nx;
       for (int iz = 0; iz < T.nz; ++iz) {
         Pt<TS, ORD> p;
         p.a = &a;
         p.B = B;
-        p.x = T.x0 + tx;
+        p.x = T.x0 + rx;
         p.y = T.y0 + ry;
         p.z = T.z0 + iz;
         p.px = B.px;
@@ -517,10 +517,9 @@ __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
 }
 
 // Curvature pass into the per-point scratch, or the Hamiltonian constraint.
-// Curvature pass into the per-point scratch, or the Hamiltonian constraint.
-// (One kernel for both modes: on C5 this allocation runs faster than a
-// constraint-free variant without spills, 3.7 against 4.2 s per coarse step,
-// or a split of the pass by output, 4.3 s.)
+// (One kernel for both modes: on C5, measured with 16-plane tiles, this
+// allocation ran faster than a constraint-free variant without spills, 3.7
+// against 4.2 s per coarse step, or a split of the pass by output, 4.3 s.)
 template <typename TS, int ORD>
 __global__ __launch_bounds__(kZ4cThreads) void k_z4c_geom(Z4cArgs a) {
   TS* geo = static_cast<TS*>(a.geo);
@@ -568,7 +567,6 @@ __global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
 // FP64.  Both stencils read the same seven taps per axis.
 template <int STAGE, typename TS, int ORD>
 __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
-  const int tx = threadIdx.x % kTileMaxX, ty = threadIdx.x / kTileMaxX;
   const TS* Y = static_cast<const TS*>(a.Y);
   TS* kout = static_cast<TS*>(a.kout);
   const TS* k1 = static_cast<const TS*>(a.k1);
@@ -582,11 +580,11 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
     const int64_t st[3] = {1, (int64_t)B.px, (int64_t)B.px * B.py};
-    for (int ry = ty; ry < T.ny; ry += 256 / kTileMaxX) {
-      if (tx >= T.nx) continue;
+    for (int i = threadIdx.x; i < T.nx * T.ny; i += 256) {   // packed, as in z4c_points
+      const int rx = i % T.nx, ry = i / T.nx;
       for (int iz = 0; iz < T.nz; ++iz) {
         const int64_t o = B.base + ((int64_t)(T.z0 + iz + B.pad) * B.py + (T.y0 + ry + B.pad)) *
-                                       (int64_t)B.px + (T.x0 + tx + B.pad);
+                                       (int64_t)B.px + (T.x0 + rx + B.pad);
         TS beta[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) beta[k] = Y[o + (VB + k) * a.vstride];
@@ -622,7 +620,6 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
 // Y = y_n when kprev is null (stage 1).
 template <typename TS>
 __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
-  const int tx = threadIdx.x % kTileMaxX, ty = threadIdx.x / kTileMaxX;
   const TS* yn = static_cast<const TS*>(a.yn);
   const TS* kprev = static_cast<const TS*>(a.kprev);
   TS* Y = static_cast<TS*>(a.Y);
@@ -630,11 +627,11 @@ __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
-    for (int ry = ty; ry < T.ny; ry += 256 / kTileMaxX) {
-      if (tx >= T.nx) continue;
+    for (int i = threadIdx.x; i < T.nx * T.ny; i += 256) {   // packed, as in z4c_points
+      const int rx = i % T.nx, ry = i / T.nx;
       for (int iz = 0; iz < T.nz; ++iz) {
         const int64_t o = B.base + ((int64_t)(T.z0 + iz + B.pad) * B.py + (T.y0 + ry + B.pad)) *
-                                       (int64_t)B.px + (T.x0 + tx + B.pad);
+                                       (int64_t)B.px + (T.x0 + rx + B.pad);
         for (int i = 0; i < a.nvars; ++i) {
           const int64_t oi = o + i * a.vstride;
           Y[oi] = kprev ? yn[oi] + cdt * kprev[oi] : yn[oi];
