@@ -227,10 +227,11 @@ std::string build_layout(sc_ctx* c) {
     L.shape.radius = c->fd_order == 8 ? 4 : 3;
     if (c->cfg.rhs == SC_RHS_Z4C) {
       // the Z4c kernels run one wave per SIMD (two 128-thread workgroups per
-      // CU): short, half-height tiles (four planes, at most 256 points per
+      // CU): short, half-height tiles (two planes, at most 256 points per
       // plane) give each CU several to interleave instead of leaving it idle
-      // after the box's few tall tiles are handed out
-      L.shape.tz = kTuneTzMin;
+      // after the box's few tall tiles are handed out (the tile table is
+      // sized for at least this many)
+      L.shape.tz = 2;
       L.shape.slots = 1;
     }
     L.nyh = l == 0 ? 1 : 8;
