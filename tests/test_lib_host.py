@@ -208,3 +208,20 @@ def test_radiative_boundary_configuration_rules():
     with pytest.raises(sc.ScError) as e:     # periodic domain
         ctx.build_spec(config_c2(16), min_block=4, max_block=9)
     assert e.value.code == sc.SC_E_ARG
+
+
+def test_z4c_contexts_cut_short_tiles():
+    """The Z4c kernels run one wave per SIMD, so Z4c contexts cut two-plane
+    tiles of at most 256 points per plane (several per resident workgroup
+    slot); wave contexts keep the stencil kernel's default cut."""
+    spec = config_c5(96)
+    z = sc.Context(rhs=sc.SC_RHS_Z4C)
+    z.build_spec(spec)
+    w = sc.Context()
+    w.build_spec(spec)
+    for l in range(spec.nlevels):
+        zs, ws = z.tile_shape(l), w.tile_shape(l)
+        assert zs["tz"] == 2 and zs["slots"] == 1, zs
+        assert zs["tx"] * zs["ty"] <= 256, zs
+        assert zs["tiles"] >= 10 * ws["tiles"], (zs, ws)
+        assert ws["tz"] == 16 and ws["slots"] == 2, ws
