@@ -300,7 +300,10 @@ int sc_poison_halos(sc_ctx* ctx);
 int sc_autotune(sc_ctx* ctx, int32_t reps);
 /* Tile shape of a level: out = {widest tile, tallest tile, z-chunk, persistent
  * workgroups, tiles, planes of loads in flight, points per thread, threads per
- * workgroup}. */
+ * workgroup}.  Until sc_autotune or sc_set_tile_shape changes it, a wave
+ * context cuts 16-plane tiles of at most 512 points per plane and a Z4c
+ * context two-plane tiles of at most 256 points per plane (its kernels run one
+ * wave per SIMD and need many tiles to fill the chip). */
 int sc_tile_shape(const sc_ctx* ctx, int32_t level, int32_t out[8]);
 /* Set a level's stencil tile shape without timing (for instance one found by
  * sc_autotune in an earlier run): z-chunk tz >= 4, persistent workgroups grid
