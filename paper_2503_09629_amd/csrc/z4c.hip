@@ -498,8 +498,8 @@ __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
     const BoxDev B = a.boxes[T.box];
     // threads packed over the tile's x-y points row by row: no lane idles on
     // a tile narrower than a wavefront
-    for (int i = threadIdx.x; i < T.nx * T.ny; i += kZ4cThreads) {
-      const int rx = i % T.nx, ry = i / T.nx;
+    for (int ixy = threadIdx.x; ixy < T.nx * T.ny; ixy += kZ4cThreads) {
+      const int rx = ixy % T.nx, ry = ixy / T.nx;
       for (int iz = 0; iz < T.nz; ++iz) {
         Pt<TS, ORD> p;
         p.a = &a;
@@ -580,8 +580,8 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
     const int64_t st[3] = {1, (int64_t)B.px, (int64_t)B.px * B.py};
-    for (int i = threadIdx.x; i < T.nx * T.ny; i += 256) {   // packed, as in z4c_points
-      const int rx = i % T.nx, ry = i / T.nx;
+    for (int ixy = threadIdx.x; ixy < T.nx * T.ny; ixy += 256) {   // packed, as in z4c_points
+      const int rx = ixy % T.nx, ry = ixy / T.nx;
       for (int iz = 0; iz < T.nz; ++iz) {
         const int64_t o = B.base + ((int64_t)(T.z0 + iz + B.pad) * B.py + (T.y0 + ry + B.pad)) *
                                        (int64_t)B.px + (T.x0 + rx + B.pad);
@@ -627,8 +627,8 @@ __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
   for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
-    for (int i = threadIdx.x; i < T.nx * T.ny; i += 256) {   // packed, as in z4c_points
-      const int rx = i % T.nx, ry = i / T.nx;
+    for (int ixy = threadIdx.x; ixy < T.nx * T.ny; ixy += 256) {   // packed, as in z4c_points
+      const int rx = ixy % T.nx, ry = ixy / T.nx;
       for (int iz = 0; iz < T.nz; ++iz) {
         const int64_t o = B.base + ((int64_t)(T.z0 + iz + B.pad) * B.py + (T.y0 + ry + B.pad)) *
                                        (int64_t)B.px + (T.x0 + rx + B.pad);
