@@ -158,6 +158,12 @@ bool tile_fits(int nx, int ny, int slots, int threads, int R) {
          2 * R * (nx + 2 * R) + 2 * R * ny <= threads * stage_ring_slots(threads);
 }
 
+// Grid of the batched Z4c launches: one workgroup per tile, rounded up to
+// whole rounds of the 8 XCDs (the kernels give each XCD a contiguous run of
+// the tile list; the spare workgroups exit at once).  No persistent second
+// pass: its tiles would all fall to the first XCDs' workgroups.
+int z4c_grid(int ntiles) { return (ntiles + 7) / 8 * 8; }
+
 void tile_region(int box, const int64_t o[3], const int64_t n[3], const TileShape& s,
                  std::vector<TileDev>* out) {
   std::vector<std::pair<int, int>> sx, sy, sz;
@@ -873,8 +879,7 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
     return SC_OK;
   };
   if (!per_block) {
-    const int rc = run(L.d_tiles, (int)L.tiles.size(),
-                       std::min<int>((int)L.tiles.size(), c->grid_cap));
+    const int rc = run(L.d_tiles, (int)L.tiles.size(), z4c_grid((int)L.tiles.size()));
     if (rc) return rc;
   } else {
     // per block: every block's stage vector must be complete before any
@@ -1474,7 +1479,7 @@ int sc_hamiltonian(sc_ctx* c, int32_t member, int32_t level, double* host, int64
   a.ham = L.Ys;   // scratch: one variable's worth of the stage-vector array
   a.tiles = L.d_tiles;
   a.ntiles = (int32_t)L.tiles.size();
-  HIPCHK(c, launch_z4c_stage(a, std::min<int>(a.ntiles, c->grid_cap), false, c->stream));
+  HIPCHK(c, launch_z4c_stage(a, z4c_grid(a.ntiles), false, c->stream));
   PackArgs pa = member_pack(c, member, level, L.Ys);
   HIPCHK(c, launch_pack(pa, false, false, c->stream));
   HIPCHK(c, hipMemcpyAsync(host, c->d_stage, sizeof(double) * n, hipMemcpyDeviceToHost,

@@ -490,10 +490,18 @@ __device__ void z4c_evol(const Pt<TS, ORD>& p, const Z4cArgs& a, const Geo& geo,
   // the advection terms beta^k d_k and the dissipation are added by k_z4c_advko
 }
 
+// First tile of a persistent workgroup.  Consecutive workgroups land on
+// different XCDs (round robin over 8); giving each XCD a contiguous run of the
+// tile list lets neighbouring tiles, whose stencil halos overlap, share its L2.
+__device__ __forceinline__ int xcd_first_tile() {
+  return gridDim.x % 8 == 0 ? (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8)
+                            : (int)blockIdx.x;
+}
+
 // One thread per owned point of the tiles: calls point(p) for each.
 template <typename TS, int ORD, typename F>
 __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+  for (int t = xcd_first_tile(); t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
     // threads packed over the tile's x-y points row by row: no lane idles on
@@ -576,7 +584,7 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
   const TS c1 = TS(1.0) / (TS(ORD == 8 ? 840.0 : 12.0) * h);
   const TS cko = TS(a.sigma) / (TS(64.0) * h);
   constexpr int R = ORD == 8 ? 4 : 3;   // taps per side: the first difference's, at least KO's 3
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+  for (int t = xcd_first_tile(); t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
     const int64_t st[3] = {1, (int64_t)B.px, (int64_t)B.px * B.py};
@@ -624,7 +632,7 @@ __global__ __launch_bounds__(256) void k_z4c_combine(Z4cCombineArgs a) {
   const TS* kprev = static_cast<const TS*>(a.kprev);
   TS* Y = static_cast<TS*>(a.Y);
   const TS cdt = TS(a.cdt);
-  for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+  for (int t = xcd_first_tile(); t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
     for (int ixy = threadIdx.x; ixy < T.nx * T.ny; ixy += 256) {   // packed, as in z4c_points
