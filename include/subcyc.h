@@ -303,7 +303,9 @@ int sc_autotune(sc_ctx* ctx, int32_t reps);
  * workgroup}.  Until sc_autotune or sc_set_tile_shape changes it, a wave
  * context cuts 16-plane tiles of at most 512 points per plane and a Z4c
  * context two-plane tiles of at most 256 points per plane (its kernels run one
- * wave per SIMD and need many tiles to fill the chip). */
+ * wave per SIMD and need many tiles to fill the chip; they launch one
+ * workgroup per tile, rounded up to a multiple of 8, which is what a Z4c
+ * context reports as its workgroup count). */
 int sc_tile_shape(const sc_ctx* ctx, int32_t level, int32_t out[8]);
 /* Set a level's stencil tile shape without timing (for instance one found by
  * sc_autotune in an earlier run): z-chunk tz >= 4, persistent workgroups grid

@@ -225,3 +225,14 @@ def test_z4c_contexts_cut_short_tiles():
         assert zs["tx"] * zs["ty"] <= 256, zs
         assert zs["tiles"] >= 10 * ws["tiles"], (zs, ws)
         assert ws["tz"] == 16 and ws["slots"] == 2, ws
+
+
+def test_z4c_contexts_launch_one_workgroup_per_tile():
+    """Z4c launches: one workgroup per tile, rounded up to whole rounds of the
+    eight XCDs."""
+    spec = config_c5(96)
+    z = sc.Context(rhs=sc.SC_RHS_Z4C)
+    z.build_spec(spec)
+    for l in range(spec.nlevels):
+        s = z.tile_shape(l)
+        assert s["grid"] % 8 == 0 and s["tiles"] <= s["grid"] < s["tiles"] + 8, s
