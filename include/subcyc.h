@@ -298,9 +298,10 @@ int sc_poison_halos(sc_ctx* ctx);
  * between coarse steps).  Invalidates captured graphs.  Synchronises the
  * stream. */
 int sc_autotune(sc_ctx* ctx, int32_t reps);
-/* Tile shape of a level: out = {widest tile, tallest tile, z-chunk, persistent
- * workgroups, tiles, planes of loads in flight, points per thread, threads per
- * workgroup}.  Until sc_autotune or sc_set_tile_shape changes it, a wave
+/* Tile shape of a level: out = {widest tile, tallest tile, z-chunk, workgroups
+ * launched (a multiple of 8: the kernels give each of the 8 XCDs a contiguous
+ * run of tiles), tiles, planes of loads in flight, points per thread, threads
+ * per workgroup}.  Until sc_autotune or sc_set_tile_shape changes it, a wave
  * context cuts 16-plane tiles of at most 512 points per plane and a Z4c
  * context two-plane tiles of at most 256 points per plane (its kernels run one
  * wave per SIMD and need many tiles to fill the chip; they launch one

@@ -1845,9 +1845,12 @@ int sc_tile_shape(const sc_ctx* c, int32_t level, int32_t out[8]) {
     out[1] = std::max<int32_t>(out[1], t.ny);
   }
   out[2] = L.shape.tz;
-  out[3] = c->cfg.rhs == SC_RHS_Z4C ? z4c_grid((int)L.tiles.size())
-          : L.shape.grid > 0        ? L.shape.grid
-                                    : std::min<int>((int)L.tiles.size(), c->grid_cap);
+  // the launched grid: Z4c one workgroup per tile; the stencil kernel its
+  // persistent grid, both rounded up to a multiple of the XCD count
+  out[3] = c->cfg.rhs == SC_RHS_Z4C
+               ? z4c_grid((int)L.tiles.size())
+               : (std::min<int>((int)L.tiles.size(), L.shape.grid > 0 ? L.shape.grid : c->grid_cap) +
+                  7) / 8 * 8;
   out[4] = (int32_t)L.tiles.size();
   out[5] = L.shape.depth;
   out[6] = L.shape.slots;
