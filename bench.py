@@ -18,10 +18,13 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--modes ...] [--no-c
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import os
 import re
+import sqlite3
+import subprocess
 import sys
 import time
 
@@ -32,29 +35,134 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-point updates/s (subcycled RK4) batched/mixed vs plain FP64; % HBM peak"
 HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per point-update (both variables, one RK4 step, interior
+# only): reading y_n and the stage vectors and writing k1..k4, the stage
+# vectors and y_{n+1} in FP64 (144 B per variable); with the FP32 stencil
+# operands and slopes of the mixed mode 100 B per variable
+SURVEY_BYTES = {"fp64": 288.0, "mixed": 200.0}
 
 
-def measured_traffic():
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "wave_stage_n0128_fp64_hbm_traffic.md")
+
+
+def kernel_source_hash():
+    """sha256 over the stencil kernel source and the host code that cuts its tiles."""
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "capi.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_2503_09629_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(mode_result):
     """HBM bytes per stage-kernel launch (scaled FETCH_SIZE + WRITE_SIZE) from the
     committed counter summary, or None unless it was taken on the current
-    kernel source."""
-    path = os.path.join(ROOT, "profiles", "wave_stage_n0128_fp64_hbm_traffic.md")
-    src = os.path.join(ROOT, "paper_2503_09629_amd", "csrc", "kernels.hip")
+    kernel source with the tile shapes this run uses."""
     try:
-        txt = open(path).read()
+        txt = open(TRAFFIC_SUMMARY).read()
     except OSError:
         return None
     m = re.search(r"traffic_bytes_per_launch:\s*(\S+)", txt)
     h = re.search(r"kernel_source_sha256:\s*(\w+)", txt)
-    if not m or not h:
+    sh = re.search(r"tile_shapes:\s*(\{.*\})", txt)
+    if not m or not h or not sh or kernel_source_hash() != h.group(1):
         return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != h.group(1):
+    keys = ("tz_per_level", "grid_per_level", "depth_per_level", "slots_per_level",
+            "threads_per_level")
+    want = json.loads(sh.group(1))
+    if any(want.get(k) != mode_result.get(k) for k in keys):
         return None
     return float(m.group(1))
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+# -- rocprofv3 output summaries (the text kept under profiles/) ---------------
+def _rows_from_csv(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def trace_dispatches(folder):
+    """Kernel dispatches of a rocprofv3 --kernel-trace run (CSV or SQLite output)
+    as (name, start_ns, end_ns), in start order."""
+    out = []
+    for path in glob.glob(os.path.join(folder, "**", "*kernel_trace.csv"), recursive=True):
+        for r in _rows_from_csv(path):
+            out.append((r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    if not out:
+        for path in glob.glob(os.path.join(folder, "**", "*_results.db"), recursive=True):
+            con = sqlite3.connect(path)
+            out += [(n, int(a), int(b)) for n, a, b in
+                    con.execute("select name, start, end from kernels")]
+            con.close()
+    out.sort(key=lambda r: r[1])
+    return out
+
+
+def counter_dispatches(folder, counter):
+    """Per-dispatch values of one counter from a rocprofv3 --pmc run (CSV output)
+    as (name, dispatch id, value) in dispatch order."""
+    out = {}
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        for r in _rows_from_csv(path):
+            if r.get("Counter_Name") != counter:
+                continue
+            key = int(r["Dispatch_Id"])
+            name, val = r["Kernel_Name"], float(r["Counter_Value"])
+            out[key] = (name, key, out.get(key, (name, key, 0.0))[2] + val)
+    return [out[k] for k in sorted(out)]
+
+
+def summarize_trace(folder, kernel_re, last, top=16):
+    rows = trace_dispatches(folder)
+    stats = {}
+    for n, a, b in rows:
+        d = stats.setdefault(n, [0, 0.0, 1e30, 0.0])
+        us = (b - a) / 1e3
+        d[0] += 1
+        d[1] += us
+        d[2] = min(d[2], us)
+        d[3] = max(d[3], us)
+    total = sum(d[1] for d in stats.values())
+    lines = ["```", f"{'kernel':60s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>8s} {'min_us':>8s} "
+             f"{'max_us':>8s} {'%':>5s}"]
+    for n, d in sorted(stats.items(), key=lambda kv: -kv[1][1])[:top]:
+        short = re.sub(r"\([^()]*\)$", "", n.replace("void ", "", 1)
+                       .replace("sc::(anonymous namespace)::", ""))[:60]
+        lines.append(f"{short:60s} {d[0]:6d} {d[1] / 1e3:9.2f} {d[1] / d[0]:8.2f} {d[2]:8.2f} "
+                     f"{d[3]:8.2f} {100 * d[1] / total:5.1f}")
+    lines.append("```")
+    sel = [r for r in rows if re.search(kernel_re, r[0])]
+    if last:
+        sel = sel[-last:]
+    if sel:
+        avg = sum(b - a for _, a, b in sel) / len(sel) / 1e3
+        lines.append(f"\n{kernel_re}: last {len(sel)} dispatches, average {avg:.2f} us, "
+                     f"total {sum(b - a for _, a, b in sel) / 1e6:.3f} ms")
+    return "\n".join(lines)
+
+
+def summarize_counters(fetch_dir, write_dir, probe_fetch_dir, probe_write_dir, kernel_re, last,
+                       probe_bytes):
+    """HBM bytes per dispatch of the kernels matching kernel_re: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch, separate runs), each scaled by the ratio of
+    the known bytes to the same counter's reading for the copy probe (the last
+    launch of bench.py --copy-probe-mib, an elementwise kernel moving
+    probe_bytes each way)."""
+    def per_dispatch(folder, counter):
+        sel = [v for n, _, v in counter_dispatches(folder, counter) if re.search(kernel_re, n)]
+        sel = sel[-last:] if last else sel
+        return sum(sel) / len(sel) * 1024.0, len(sel)
+    fetch, nf = per_dispatch(fetch_dir, "FETCH_SIZE")
+    write, nw = per_dispatch(write_dir, "WRITE_SIZE")
+    pf = counter_dispatches(probe_fetch_dir, "FETCH_SIZE")[-1][2] * 1024.0
+    pw = counter_dispatches(probe_write_dir, "WRITE_SIZE")[-1][2] * 1024.0
+    sf, sw = probe_bytes / pf, probe_bytes / pw
+    return {"dispatches": [nf, nw], "fetch_kib": fetch / 1024, "write_kib": write / 1024,
+            "fetch_scale": sf, "write_scale": sw, "traffic_bytes_per_launch": fetch * sf + write * sw}
 
 
 def make_context(sc, spec, mode, data, precision=0):
@@ -77,24 +185,94 @@ def timed(ctx, torch, steps):
     return time.perf_counter() - t0
 
 
-def cpu_baseline():
-    """Reference implementation, one coarse step of the same tower family at N0 = 64."""
+def timed_reps(ctx, torch, steps, reps=5):
+    """Exactly `steps` coarse steps, in `reps` groups each synchronised and
+    timed: total seconds and the per-step milliseconds of every group."""
+    sizes = [steps // reps + (1 if i < steps % reps else 0) for i in range(min(reps, steps))]
+    total, per = 0.0, []
+    for n in sizes:
+        t = timed(ctx, torch, n)
+        total += t
+        per.append(1e3 * t / n)
+    return total, per
+
+
+def stage_roofline(ctx, steps, U, precision):
+    """Stage-kernel roofline from HIP events around every batched stage launch
+    (the context must be in an eager mode) over `steps` coarse steps."""
+    ctx.profile_enable(True)
+    ctx.advance(steps)
+    n, ms, own_bytes = ctx.profile_read()
+    ctx.profile_enable(False)
+    alg = SURVEY_BYTES[precision] * U * steps          # algorithmic bytes of these launches
+    achieved = alg / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_wave_stage (all four stages, batched, "
+                      + ("FP64" if precision == "fp64" else "mixed: FP64 stage 1, FP32 stages 2-4") + ")",
+            "launches": n, "avg_launch_us": 1e3 * ms / n,
+            "alg_bytes_per_launch": alg / n,
+            "alg_bytes_per_point_update": SURVEY_BYTES[precision],
+            "achieved_kernel_minimum_bytes": own_bytes / (ms * 1e-3) / 1e9,
+            "kernel_minimum_bytes_per_launch": own_bytes / n}
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        m = re.search(r"Model name:\s*(.+)", out)
+        return m.group(1).strip() if m else None
+    except (OSError, subprocess.SubprocessError):
+        return None
+
+
+def cpu_baseline(n0=128):
+    """The CPU reference implementation on the benchmark hierarchy itself, timed
+    on a bounded sample: the first descent of the subcycling recursion (one
+    RK4 step of every level, coarse to fine, with each level's stage ghost
+    fills and the prolongation from its parent), i.e. every owned point
+    advanced once.  Median of three repetitions with all host threads, and
+    one repetition with one thread."""
+    import ctypes
     from oracle.evolve import OracleRun
     from oracle.hierarchy import Hierarchy
     from workloads import config_c3, pulses_on_spec
-    spec = config_c3(64)
+    spec = config_c3(n0)
+    t0 = time.perf_counter()
     run = OracleRun(Hierarchy(spec))
     for l in range(spec.nlevels):
         for v, f in enumerate(pulses_on_spec(spec, l)):
             run.set_data(l, v, f)
-    t0 = time.perf_counter()
-    run.advance(1)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    u = spec.updates_per_coarse_step()
-    return {"value": u / dt, "unit": "grid-point updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"one coarse step of the 7-level tower hierarchy at N0=64 "
-                      f"({spec.total_points()} points, {u} point-updates), {dt:.1f} s"}
+    log(f"cpu reference: hierarchy and storage set up in {time.perf_counter() - t0:.0f} s")
+    gomp = ctypes.CDLL("libgomp.so.1")
+    nproc = len(os.sched_getaffinity(0))
+    if "OMP_NUM_THREADS" in os.environ:
+        nproc = min(nproc, int(os.environ["OMP_NUM_THREADS"]))
+
+    def descent():
+        t = time.perf_counter()
+        for l in range(spec.nlevels):
+            run.rk4_step(l)
+            if l + 1 < spec.nlevels:
+                run.prolongate(l + 1)
+                run.theta0[l + 1] = 0.0
+        return time.perf_counter() - t
+
+    u = spec.total_points()
+    legs = {}
+    for threads, reps in ((nproc, 3), (1, 1)):
+        gomp.omp_set_num_threads(threads)
+        ts = sorted(descent() for _ in range(reps))
+        legs[threads] = ts[len(ts) // 2]
+        log(f"cpu reference, {threads} threads: {legs[threads]:.2f} s per sample "
+            f"({u / legs[threads]:.4g} updates/s)")
+    gomp.omp_set_num_threads(nproc)
+    sample = (f"7-level tower hierarchy at N0={n0} ({u} points): one RK4 step of every level "
+              f"(coarse to fine, with ghost fills and prolongations), {u} point-updates")
+    return {"value": u / legs[nproc], "unit": "grid-point updates/s", "cores": nproc,
+            "kind": "oracle", "sample": sample + f", median of 3: {legs[nproc]:.2f} s",
+            "single_thread": {"value": u / legs[1], "seconds": legs[1], "cores": 1},
+            "cpu_model": cpu_model()}
 
 
 def composite_weights(spec, level):
@@ -383,7 +561,9 @@ def fd8_run(args):
 
 
 def precision_report(args):
-    """Mixed vs FP64: max-norm difference per level and observed orders."""
+    """Mixed vs FP64 on the tower hierarchy at t = 1/8: max-norm difference of
+    u and Pi per level, and observed orders of both precisions from the three
+    resolutions (differences of successive resolutions on common points)."""
     import paper_2503_09629_amd as sc
     from workloads import config_c3, pulses_on_spec
     res = {}
@@ -400,7 +580,7 @@ def precision_report(args):
                 if (i + 1) % 16 == 0 or i + 1 == nsteps:
                     ctx.synchronize()
                     log(f"  {'mixed' if prec == sc.SC_MIXED else 'fp64'}: {i + 1}/{nsteps} coarse steps")
-            out[prec] = [ctx.read_back(0, l, 0) for l in range(spec.nlevels)]
+            out[prec] = [[ctx.read_back(0, l, v) for v in range(2)] for l in range(spec.nlevels)]
             ctx.close()
         del data
         res[n0] = out
@@ -408,20 +588,21 @@ def precision_report(args):
     levels = []
     n0s = list(args.report_n0)
     for l in range(7):
-        row = {"level": l, "max_abs_mixed_minus_fp64": {}, "order_fp64": None, "order_mixed": None}
-        for n0 in n0s:
-            row["max_abs_mixed_minus_fp64"][n0] = float(np.abs(res[n0][0][l] - res[n0][1][l]).max())
-        if len(n0s) == 3:
-            for prec, key in ((0, "order_fp64"), (1, "order_mixed")):
-                a, b, c = (res[n].get(prec)[l] for n in n0s)
-                shp = [config_c3(n).boxes(l) for n in n0s]
-                fa = _common(a, shp[0], 1)
-                fb = _common(b, shp[1], 2)
-                fc = _common(c, shp[2], 4)
-                e1 = np.abs(fa - fb).max()
-                e2 = np.abs(fb - fc).max()
-                row[key] = float(np.log2(e1 / e2)) if e2 > 0 else None
+        row = {"level": l}
+        for v, name in enumerate(("u", "Pi")):
+            row[f"max_abs_mixed_minus_fp64_{name}"] = {
+                n0: float(np.abs(res[n0][0][l][v] - res[n0][1][l][v]).max()) for n0 in n0s}
+            row[f"max_abs_{name}_fp64"] = {n0: float(np.abs(res[n0][0][l][v]).max()) for n0 in n0s}
+            if len(n0s) == 3:
+                for prec, key in ((0, "fp64"), (1, "mixed")):
+                    a, b, c = (res[n][prec][l][v] for n in n0s)
+                    shp = [config_c3(n).boxes(l) for n in n0s]
+                    e1 = np.abs(_common(a, shp[0], 1) - _common(b, shp[1], 2)).max()
+                    e2 = np.abs(_common(b, shp[1], 2) - _common(c, shp[2], 4)).max()
+                    row[f"diff_{name}_{key}"] = [float(e1), float(e2)]
+                    row[f"order_{name}_{key}"] = float(np.log2(e1 / e2)) if e2 > 0 else None
         levels.append(row)
+        log(json.dumps(row))
     return {"report": "mixed precision vs FP64, 7-level tower hierarchy, t = 1/8",
             "n0": n0s, "levels": levels}
 
@@ -464,7 +645,22 @@ def main():
     ap.add_argument("--z4c-h-every", type=int, default=0,
                     help="also report the constraint near the outer boundary every N coarse steps")
     ap.add_argument("--report-n0", type=int, nargs="+", default=[64, 128, 256])
+    ap.add_argument("--summarize-trace", metavar="DIR", default=None,
+                    help="print a kernel table of a rocprofv3 --kernel-trace output folder")
+    ap.add_argument("--summarize-counters", metavar="DIR", nargs=4, default=None,
+                    help="FETCH_SIZE, WRITE_SIZE, copy-probe FETCH_SIZE, copy-probe WRITE_SIZE "
+                         "output folders of rocprofv3 --pmc runs: HBM bytes per dispatch")
+    ap.add_argument("--kernel", default="k_wave_stage", help="kernel name regex for the summaries")
+    ap.add_argument("--last", type=int, default=0, help="summarise only the last N matching dispatches")
+    ap.add_argument("--probe-mib", type=int, default=1024)
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.kernel, args.last))
+        return
+    if args.summarize_counters:
+        print(json.dumps(summarize_counters(*args.summarize_counters, args.kernel, args.last,
+                                            args.probe_mib << 20)))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "layout is described in the design notes, not implemented", file=sys.stderr)
@@ -530,38 +726,33 @@ def main():
         steps = args.steps if m != "per_block" else max(1, min(args.steps, 2))
         ctx.advance(max(1, args.warmup) if m != "per_block" else 1)
         ctx.synchronize()
-        T = timed(ctx, torch, steps)
+        T, per = timed_reps(ctx, torch, steps)
         res[m] = {"updates_per_s": U * steps / T, "ms_per_step": 1e3 * T / steps,
+                  "ms_per_step_reps": per, "ms_per_step_median": float(np.median(per)),
                   "steps": steps, "tz_per_level": [sh["tz"] for sh in shapes],
                   "grid_per_level": [sh["grid"] for sh in shapes],
                   "depth_per_level": [sh["depth"] for sh in shapes],
                   "slots_per_level": [sh["slots"] for sh in shapes],
                   "threads_per_level": [sh["threads"] for sh in shapes]}
-        log(f"{m}: {1e3 * T / steps:.2f} ms/step, {U * steps / T:.4g} updates/s")
-        if m in ("batched", "mixed_batched"):
-            label = "roofline" if m == "batched" else "roofline_mixed"
-            ctx.profile_enable(True)
-            ctx.advance(steps)
-            n, ms, nbytes = ctx.profile_read()
-            ctx.profile_enable(False)
-            achieved = nbytes / (ms * 1e-3) / 1e9
-            r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                 "kernel": "k_wave_stage (all four stages, batched, "
-                           + ("FP64" if m == "batched" else "FP32 stencil") + ")",
-                 "launches": n, "avg_launch_us": 1e3 * ms / n,
-                 "alg_bytes_per_launch": nbytes / n}
-            if label == "roofline":
+        log(f"{m}: {1e3 * T / steps:.2f} ms/step (median of {len(per)} groups "
+            f"{np.median(per):.2f}), {U * steps / T:.4g} updates/s")
+        if m in ("graph", "mixed"):
+            # the same context and tile shapes, stage launches timed one by one
+            ctx.set_exec(sc.SC_EXEC_BATCHED)
+            r = stage_roofline(ctx, min(steps, 3), U, "mixed" if prec == sc.SC_MIXED else "fp64")
+            if m == "graph":
                 if args.n0 == 128:
-                    t = measured_traffic()
+                    t = measured_traffic(res[m])
                     if t is not None:
                         r["traffic"] = t
                         r["traffic_unit"] = "HBM bytes per launch (rocprofv3 counters)"
                         r["traffic_over_algorithmic"] = t / r["alg_bytes_per_launch"]
+                        r["traffic_over_kernel_minimum"] = t / r["kernel_minimum_bytes_per_launch"]
                 roof = r
             else:
                 res[m]["roofline"] = r
-            log(f"stage kernel: {n} launches, avg {1e3 * ms / n:.1f} us, {achieved:.0f} GB/s")
+            log(f"stage kernel ({m}): {r['launches']} launches, avg {r['avg_launch_us']:.1f} us, "
+                f"{r['achieved']:.0f} GB/s of algorithmic bytes (frac {r['frac']:.3f})")
         if ctx.check_finite() != sc.SC_OK:
             raise SystemExit(f"non-finite values in mode {m}")
         ctx.close()
@@ -592,6 +783,9 @@ def main():
     if "per_block" in res:
         for m in res:
             res[m]["speedup_vs_per_block"] = res[m]["updates_per_s"] / res["per_block"]["updates_per_s"]
+    if "mixed" in res and "graph" in res:
+        res["mixed"]["speedup_vs_fp64_graph"] = res["mixed"]["updates_per_s"] / res["graph"]["updates_per_s"]
+    out["kernel_source_sha256"] = kernel_source_hash()
     if roof is not None:
         out["roofline"] = roof
     if not args.no_cpu:

@@ -52,12 +52,21 @@ typedef enum {
  * SC_RHS_Z4C: the Z4c system with the puncture gauge (Sec. III.A), vacuum,
  * 22 variables in the slot order W, gt_xx, gt_xy, gt_xz, gt_yy, gt_yz, gt_zz,
  * Khat, At_xx, At_xy, At_xz, At_yy, At_yz, At_zz, Theta, Gt^x, Gt^y, Gt^z,
- * alpha, beta^x, beta^y, beta^z (FP64 only). */
+ * alpha, beta^x, beta^y, beta^z (FP64, or FP32 right-hand side with
+ * SC_MIXED). */
 enum { SC_RHS_WAVE = 0, SC_RHS_Z4C = 1 };
 
-/* Precision of the right-hand-side stencil.  SC_MIXED reads FP32 shadow
- * copies of the stage vectors and evaluates the stencil in FP32; the state,
- * RK4 accumulation, dense output, prolongation and restriction stay FP64. */
+/* Precision of the right-hand-side stencil.  The state, the RK4
+ * accumulation, dense output, prolongation and restriction stay FP64 in both
+ * modes.  SC_MIXED with the wave: the wave right-hand side f is linear, so
+ * stage s >= 2 evaluates k_s = k1 + f(Y_s - y_n) with the stage increment
+ * Y_s - y_n = c_s dt k_{s-1} (refinement-boundary ghosts: the dense-output
+ * stage value minus the stage-1 value) in FP32, and k1 = f(y_n) in FP64;
+ * slopes are stored in FP32.  FP32 rounding enters through quantities of size
+ * dt |k| instead of |y|, so the stencil's 1/h^2 amplification of it stays
+ * below the discretisation error of the benchmark hierarchies.  SC_MIXED
+ * with Z4c: the right-hand side reads FP32 shadow copies of the stage
+ * vectors and evaluates in FP32 (the system is not linear). */
 enum { SC_FP64 = 0, SC_MIXED = 1 };
 
 /* Execution of one coarse step.  PER_BLOCK: one kernel launch per block per
@@ -152,7 +161,9 @@ int sc_destroy(sc_ctx* ctx);
  * thread when ctx is NULL.  Owned by the library; valid until the next call. */
 const char* sc_last_error(const sc_ctx* ctx);
 
-/* Build the hierarchy and every index map (host only, once).
+/* Build the hierarchy of levels with refinement ratio 2 in space and time
+ * (Sec. II) and every index map (host only, once); the maps hold all grid
+ * index arithmetic, so the kernels do arithmetic only (Sec. III.C).
  *   nmembers        independent copies evolved together (ensemble batching)
  *   origin, dx0     coordinates of level-0 index 0 and level-0 spacing
  *   ncells0         level-0 cells per dimension; level 0 holds indices
@@ -209,9 +220,11 @@ int sc_device_bytes(const sc_ctx* ctx, size_t* nbytes);
  * context's stream).  The caller keeps it alive until sc_destroy. */
 int sc_bind_device_memory(sc_ctx* ctx, void* dptr, size_t nbytes);
 
-/* Initial data of one variable on the owned points of one level of one
- * member, n = owned points, in canonical order (the level's boxes in order,
- * each z-major, y, x fastest).  The host array is copied before return. */
+/* Initial data y(t_0) of the problem dy/dt = f(y) (Sec. II) for one variable
+ * on the owned points of one level of one member, n = owned points, in
+ * canonical order (the level's boxes in order, each z-major, y, x fastest).
+ * The host array is copied before return; the first call moves the context
+ * to READY. */
 int sc_set_initial_data(sc_ctx* ctx, int32_t member, int32_t level, int32_t var,
                         const double* host, int64_t n);
 
@@ -221,6 +234,39 @@ int sc_set_initial_data(sc_ctx* ctx, int32_t member, int32_t level, int32_t var,
  * the library's order; sc_set_phys_data: values of one variable at those
  * points, same order, copied into every ghost table of the level. */
 int sc_phys_count(const sc_ctx* ctx, int32_t level, int64_t* n);
+
+/* Closed-form initial data evaluated on the GPU at every owned point of every
+ * level and member (and at the frozen physical-boundary ghosts of
+ * non-periodic levels), for every variable; moves the context to READY.
+ * params (host, nparams doubles, copied) by kind:
+ *   SC_ID_STANDING_WAVE (wave): an exact standing-wave solution of the wave
+ *     system of Sec. IV.A, u = A sin(m_x pi x) sin(m_y pi y) sin(m_z pi z),
+ *     Pi = 0: params (A, m_x, m_y, m_z); or nparams = 0: per member, m_d =
+ *     1 + (draw mod 3) for x, y, z and A = 0.5 + U[0,1) from SplitMix64(seed)
+ *     (U = top 53 bits of a draw times 2^-53), members in order.
+ *   SC_ID_GAUSSIAN_PULSES (wave): u = sum_p A_p g_p(x) g_p(y) g_p(z), Pi = 0,
+ *     g_p(x) = sum_k exp(-(x - c_p,x - k L)^2 / w_p^2) over the periodic
+ *     images k = -1, 0, 1 of period L (L = 0: k = 0 only), a sum of the
+ *     Gaussian profiles of the paper's scalar-wave test (Sec. IV.A):
+ *     params (npulses <= 32, L, then A, w, c_x, c_y, c_z per pulse); or
+ *     (npulses, L, x_t): per pulse A = 0.1 + 0.9 U, w = 0.05 + 0.15 U,
+ *     o = -0.1 + 0.2 U three times, c = (-x_t + o_x, o_y, o_z) for even p and
+ *     (x_t + o_x, o_y, o_z) for odd p, drawn from SplitMix64(seed) in that order.
+ *   SC_ID_BRILL_LINDQUIST (Z4c): two time-symmetric punctures at (x_+, 0, 0)
+ *     and (x_-, 0, 0) with bare masses m_+, m_-: psi = 1 + a,
+ *     a = m_+/(2 r_+) + m_-/(2 r_-), W = psi^-2, conformally flat, K = 0, zero
+ *     shift, and the initial lapse of Sec. III.B, (1 + (1 - a)/(1 + a))/2:
+ *     params (m_+, m_-, x_+, x_-).
+ *   SC_ID_SPHERICAL_GAUSSIAN (wave): the exact outgoing solution of the
+ *     paper's scalar-wave test (Sec. IV.A) at time t, u = (f(t-r) - f(t+r))/r,
+ *     Pi = du/dt, f(v) = A exp(-v^2/(2 sigma^2)), with its limits at r = 0:
+ *     params (A, sigma, t).
+ * SC_E_ARG for an unknown kind, a kind of the other right-hand side or a bad
+ * parameter list; SC_E_STATE before sc_bind_device_memory.  Synchronises. */
+enum { SC_ID_STANDING_WAVE = 1, SC_ID_GAUSSIAN_PULSES = 2, SC_ID_BRILL_LINDQUIST = 3,
+       SC_ID_SPHERICAL_GAUSSIAN = 4 };
+int sc_set_initial_data_analytic(sc_ctx* ctx, int32_t kind, const double* params,
+                                 int32_t nparams, uint64_t seed);
 int sc_phys_points(const sc_ctx* ctx, int32_t level, double* xyz, int64_t n);
 int sc_set_phys_data(sc_ctx* ctx, int32_t member, int32_t level, int32_t var,
                      const double* host, int64_t n);
@@ -246,8 +292,10 @@ int sc_fill_ghosts(sc_ctx* ctx, int32_t level, int32_t which, int32_t substep);
 /* injection of fine_level's state into the parent (step 7). */
 int sc_restrict(sc_ctx* ctx, int32_t fine_level);
 
-/* Read one array (SC_ARR_*) of one variable on the owned points of a level of
- * a member, canonical order, n = owned points.  Synchronises the stream.
+/* Read one array (SC_ARR_*: the state y, the stored RK4 slopes k1..k4 of
+ * Sec. II step 1, or y_n) of one variable on the owned points of a level of
+ * a member, canonical order, n = owned points (host, caller-owned).
+ * Synchronises the stream.
  * The wave stencil keeps k4 only on levels that have a finer level (nothing
  * else reads it); SC_ARR_K4 on the finest level returns SC_E_STATE. */
 int sc_read_back(sc_ctx* ctx, int32_t member, int32_t level, int32_t var, int32_t array,
@@ -261,8 +309,11 @@ int sc_read_rb(sc_ctx* ctx, int32_t member, int32_t level, int32_t which, int32_
                int32_t var, double* host, int64_t n);
 
 /* Deterministic norms of one array of one variable over the owned points of
- * a level of a member: out[0] = max |a|, out[1] = sqrt(mean a^2),
- * out[2] = number of non-finite values.  Synchronises the stream. */
+ * a level of a member (the error and constraint norms the paper reports in
+ * Sec. IV are of this kind): out[0] = max |a|, out[1] = sqrt(mean a^2),
+ * out[2] = number of non-finite values (host, caller-owned).  A fixed-shape
+ * two-pass reduction on the GPU, so repeated calls give the same bits.
+ * Synchronises the stream. */
 int sc_norms(sc_ctx* ctx, int32_t member, int32_t level, int32_t var, int32_t array,
              double out[3]);
 
@@ -309,13 +360,16 @@ int sc_autotune(sc_ctx* ctx, int32_t reps);
  * context reports as its workgroup count). */
 int sc_tile_shape(const sc_ctx* ctx, int32_t level, int32_t out[8]);
 /* Set a level's stencil tile shape without timing (for instance one found by
- * sc_autotune in an earlier run): z-chunk tz >= 4, persistent workgroups grid
+ * sc_autotune in an earlier run).  Wave contexts: z-chunk tz >= 4, persistent workgroups grid
  * (0: the context default, capped at the tile count), planes of loads in
  * flight ahead of the computed plane (depth), owned points per thread (slots)
  * and threads per workgroup (threads; a tile holds at most threads * slots
  * points), (threads, slots, depth) one of (256, 2, 1), (256, 2, 2),
  * (256, 1, 2), (512, 2, 1), (512, 2, 2).  SC_E_ARG if a value is out of range
- * or the shape gives more tiles than the tile table was sized for.
+ * or the shape gives more tiles than the tile table was sized for.  Z4c
+ * contexts: only tz applies (tz >= 2; the shape sc_tile_shape reports can be
+ * set back); grid, depth, slots and threads are ignored, since the Z4c kernels
+ * keep their workgroup shape and launch one workgroup per tile.
  * Invalidates captured graphs; synchronises the stream. */
 int sc_set_tile_shape(sc_ctx* ctx, int32_t level, int32_t tz, int32_t grid, int32_t depth,
                       int32_t slots, int32_t threads);

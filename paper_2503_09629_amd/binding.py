@@ -24,11 +24,12 @@ SC_FILL_Y1, SC_FILL_Y2, SC_FILL_Y3, SC_FILL_Y4, SC_FILL_END = 1, 2, 3, 4, 5
 SC_ABI_VERSION = 2
 SC_SUBCYCLED, SC_UNIFORM_DT, SC_BUFFER_ZONES = 0, 1, 2
 SC_BC_FROZEN, SC_BC_RADIATIVE = 0, 1
+SC_ID_STANDING_WAVE, SC_ID_GAUSSIAN_PULSES, SC_ID_BRILL_LINDQUIST, SC_ID_SPHERICAL_GAUSSIAN = 1, 2, 3, 4
 
 EXPORTED = [
     "sc_config_default", "sc_create", "sc_destroy", "sc_last_error", "sc_build_hierarchy",
     "sc_get_counts", "sc_buffer_count", "sc_export_maps", "sc_device_bytes", "sc_bind_device_memory",
-    "sc_set_initial_data", "sc_phys_count", "sc_phys_points", "sc_set_phys_data",
+    "sc_set_initial_data", "sc_set_initial_data_analytic", "sc_phys_count", "sc_phys_points", "sc_set_phys_data",
     "sc_hamiltonian", "sc_advance", "sc_step_level", "sc_prolongate", "sc_fill_ghosts",
     "sc_restrict", "sc_read_back", "sc_read_rb", "sc_norms", "sc_check_finite",
     "sc_level_time", "sc_set_exec", "sc_poison_halos", "sc_autotune", "sc_tile_shape",
@@ -86,6 +87,7 @@ def lib():
             "sc_device_bytes": [P, P],
             "sc_bind_device_memory": [P, P, sz],
             "sc_set_initial_data": [P, i32, i32, i32, P, i64],
+            "sc_set_initial_data_analytic": [P, i32, P, i32, u64],
             "sc_phys_count": [P, i32, P],
             "sc_phys_points": [P, i32, P, i64],
             "sc_set_phys_data": [P, i32, i32, i32, P, i64],
@@ -175,9 +177,13 @@ class Context:
             raise ScError(rc, self.L.sc_last_error(c).decode())
 
     def close(self):
+        # sc_destroy waits for the context's queued kernels; only then may the
+        # arena go back to torch's allocator
         if getattr(self, "ctx", None):
             self.L.sc_destroy(self.ctx)
             self.ctx = None
+        if self.arena is not None and self.stream is not None:
+            self.stream.synchronize()
         self.arena = None
 
     def __del__(self):
@@ -251,6 +257,11 @@ class Context:
     def set_initial_data(self, member: int, level: int, var: int, values):
         a = np.ascontiguousarray(values, dtype=np.float64)
         self._check(self.L.sc_set_initial_data(self.ctx, member, level, var, _p(a), a.size))
+
+    def set_initial_data_analytic(self, kind: int, params=(), seed: int = 0):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        self._check(self.L.sc_set_initial_data_analytic(
+            self.ctx, kind, _p(p) if p.size else None, int(p.size), ctypes.c_uint64(seed)))
 
     def phys_points(self, level: int) -> np.ndarray:
         n = ctypes.c_int64()

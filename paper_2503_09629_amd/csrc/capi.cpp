@@ -77,19 +77,17 @@ void dense_b(Rat th, int m, Rat out[4]) {
 // Uniform time steps: the stage value of the parent at the fine stage's own
 // time, y_n + c_s H k_{s-1} (fills 1-4), and y_{n+1} (fill 5), as weights of
 // H k_i.
-void aligned_weights(int fill, double w[4]) {
+void aligned_weights(int fill, Rat r[4]) {
   static const Rat c[4] = {Rat(0), Rat(1, 2), Rat(1, 2), Rat(1)};
-  Rat r[4];
+  for (int i = 0; i < 4; ++i) r[i] = Rat(0);
   if (fill == 5) {
     r[0] = Rat(1, 6), r[1] = Rat(1, 3), r[2] = Rat(1, 3), r[3] = Rat(1, 6);
   } else if (fill >= 2) {
     r[fill - 2] = c[fill - 1];
   }
-  for (int i = 0; i < 4; ++i) w[i] = r[i].f();
 }
 
-void ghost_weights(int fill, Rat th0, double w[4]) {
-  Rat r[4];
+void ghost_weights(int fill, Rat th0, Rat r[4]) {
   if (fill == 5) {
     dense_b(th0 + Rat(1, 2), 0, r);
   } else {
@@ -108,7 +106,6 @@ void ghost_weights(int fill, Rat th0, double w[4]) {
     for (int i = 0; i < 4; ++i)
       r[i] = b0[i] + c1 * h * b1[i] + c2 * h2 * b2[i] + c3 * h3 * b3[i] + cf * h3 * fyy[i];
   }
-  for (int i = 0; i < 4; ++i) w[i] = r[i].f();
 }
 
 // ---------------------------------------------------------------------------
@@ -653,9 +650,11 @@ void plan_arena(sc_ctx* c) {
     const size_t arr = sizeof(double) * (size_t)c->nvars * (size_t)L.total;
     const size_t arrs = c->esz * (size_t)c->nvars * (size_t)L.total;
     for (int i = 0; i < L.nbuf; ++i) L.o_y[i] = take(arr);
-    for (int i = 0; i < 2; ++i) L.o_y32[i] = c->mixed ? take(arr / 2) : 0;
+    for (int i = 0; i < 2; ++i) L.o_y32[i] = (c->mixed && !c->wave_mixed) ? take(arr / 2) : 0;
     for (int i = 0; i < 4; ++i) L.o_k[i] = take(arrs);
     for (int i = 0; i < L.nyh; ++i) L.o_yh[i] = take(arrs);
+    L.nyd = c->wave_mixed ? (L.nyh == 1 ? 1 : 2) : 0;
+    for (int i = 0; i < L.nyd; ++i) L.o_yd[i] = take(arr);
     L.o_ys = c->cfg.rhs == SC_RHS_Z4C ? take(sizeof(double) * (size_t)kZ4cScratch * (size_t)L.total) : 0;
     L.o_boxes = take(sizeof(BoxDev) * L.boxes.size());
     L.o_prefix = take(sizeof(int64_t) * L.prefix.size());
@@ -686,6 +685,7 @@ void plan_arena(sc_ctx* c) {
     L.o_tiles = take(sizeof(TileDev) * L.tiles_capacity);
     L.o_btiles = take(sizeof(TileDev) * L.btiles.size());
     maxowned = std::max(maxowned, std::max(L.owned_member, L.nrb * (int64_t)c->hier.geo.nmembers));
+    maxowned = std::max(maxowned, (int64_t)L.phys_q.size() / 3);
   }
   c->stage_elems = std::max<int64_t>(maxowned, 1);
   c->o_stage = take(sizeof(double) * (size_t)c->stage_elems);
@@ -748,7 +748,6 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
   a.kout = L.k[stage - 1];
   a.yn64 = L.y[L.cur];
   a.ynew = L.y[nxt(L)];
-  a.ynew32 = c->mixed ? L.y32[1 - L.cur] : nullptr;
   a.vstride = L.total;
   static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
   a.cdt = cnext[stage] * L.dt;
@@ -775,9 +774,11 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
       HIPCHK(c, hipEventRecord(e1, c->stream));
       // algorithmic bytes per owned point and variable: the stencil operands
       // y_n and k_{s-1}, the new slope, and for stage 4 also k1, k2, the FP64
-      // y_n and y_{n+1} (plus its FP32 shadow in mixed mode)
+      // y_n and y_{n+1}; mixed: stage 1 reads the FP64 y_n and writes an FP32
+      // k1, stages 2-4 read the FP32 k_{s-1} (and k1 at stages 3, 4), stage 4
+      // also k2, the FP64 y_n and y_{n+1}
       static const double fp64[5] = {0, 16, 24, 24, 48};
-      static const double mixed[5] = {0, 8, 12, 12, 40};
+      static const double mixed[5] = {0, 12, 8, 12, 32};
       double per_var = c->mixed ? mixed[stage] : fp64[stage];
       if (!a.write_k) per_var -= c->esz;  // k4 not stored on the finest level
       c->ev_bytes.push_back(per_var * c->nvars * (double)(L.owned_member * c->hier.geo.nmembers));
@@ -909,10 +910,14 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
 
 int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
   LevelDev& L = c->lev[l];
-  const void* yn = c->mixed ? static_cast<const void*>(L.y32[L.cur]) : L.y[L.cur];
+  // the Z4c FP32 right-hand side reads the FP32 shadow of y_n; the wave
+  // reads the FP64 y_n (mixed: at stage 1 only)
+  const bool shadow = c->mixed && !c->wave_mixed;
+  const void* yn = shadow ? static_cast<const void*>(L.y32[L.cur]) : L.y[L.cur];
   for (int s = 1; s <= 4; ++s) {
     // buffer zones: the RB ghosts keep the step's prolonged value at every stage
     void* yh = L.Yh[buffer_zones(c) ? (l == 0 ? 0 : substep * 4) : yh_index(l, substep, s)];
+    if (c->wave_mixed && s == 1) yh = L.Yd[l == 0 ? 0 : substep];
     const void* kprev = s == 1 ? nullptr : L.k[s - 2];
     if (!L.sync.empty()) {
       SyncArgs sa{};
@@ -925,7 +930,9 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
       static const double cnext[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
       sa.cdt = cnext[s] * L.dt;
       sa.nvars = c->nvars;
-      HIPCHK(c, launch_sync(sa, c->mixed, c->stream));
+      sa.inc = c->wave_mixed && s > 1;
+      const bool f32 = c->wave_mixed ? s > 1 : c->mixed;
+      HIPCHK(c, launch_sync(sa, f32, c->stream));
       ++c->launches;
     }
     int rc = c->cfg.rhs == SC_RHS_Z4C ? enqueue_z4c_launches(c, l, s, per_block, kprev, yh)
@@ -939,9 +946,15 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
 
 // Prolongation from the parent's last step (y_n = the buffer it stepped from,
 // k1..k4) into the fine level: outputs[i] with weights[i].
+// Output o is FP32 if bit o of f32_mask is set, and a stage increment
+// (weights minus the substep's Y1 weights, no P[y_n] term) if bit o of inc_mask is.
 int prolong_into(sc_ctx* c, int fl, const ProlongEntry* entries, const int64_t* cls, int nout,
                  void* const* outs, const int* fills, const int* subs, int64_t ovstride,
-                 bool out_f32, int var_only, bool with_bricks) {
+                 uint32_t f32_mask, uint32_t inc_mask, int var_only, bool with_bricks) {
+  auto wsel = [&](int o) -> const double* {
+    return ((inc_mask >> o) & 1) ? c->weights_inc[subs[o]][fills[o] - 1]
+                                 : c->weights[subs[o]][fills[o] - 1];
+  };
   LevelDev& P = c->lev[fl - 1];
   LevelDev& F = c->lev[fl];
   if (with_bricks && !F.bricks.empty()) {
@@ -957,11 +970,13 @@ int prolong_into(sc_ctx* c, int fl, const ProlongEntry* entries, const int64_t* 
     b.pvstride = P.total;
     b.ovstride = ovstride;
     b.H = P.dt;
+    b.f32_mask = f32_mask;
+    b.inc_mask = inc_mask;
     for (int o = 0; o < nout; ++o) {
       b.out[o] = outs[o];
-      for (int i = 0; i < 4; ++i) b.w[o][i] = c->weights[subs[o]][fills[o] - 1][i];
+      for (int i = 0; i < 4; ++i) b.w[o][i] = wsel(o)[i];
     }
-    HIPCHK(c, launch_prolong_bricks(b, c->mixed, out_f32, c->stream));
+    HIPCHK(c, launch_prolong_bricks(b, c->mixed, c->stream));
     ++c->launches;
   }
   const int64_t n = cls[8];
@@ -986,11 +1001,13 @@ int prolong_into(sc_ctx* c, int fl, const ProlongEntry* entries, const int64_t* 
     a.py += var_only * P.total;
     for (int i = 0; i < 4; ++i) a.pk[i] = elem(P.k[i], var_only * P.total, c->esz);
   }
+  a.f32_mask = f32_mask;
+  a.inc_mask = inc_mask;
   for (int o = 0; o < nout; ++o) {
     a.out[o] = outs[o];
-    for (int i = 0; i < 4; ++i) a.w[o][i] = c->weights[subs[o]][fills[o] - 1][i];
+    for (int i = 0; i < 4; ++i) a.w[o][i] = wsel(o)[i];
   }
-  HIPCHK(c, launch_prolong(a, c->mixed, out_f32, c->stream));
+  HIPCHK(c, launch_prolong(a, c->mixed, c->stream));
   ++c->launches;
   return SC_OK;
 }
@@ -999,6 +1016,7 @@ int prolongate(sc_ctx* c, int fl) {
   LevelDev& F = c->lev[fl];
   void* outs[8];
   int fills[8], subs[8];
+  uint32_t f32_mask = 0, inc_mask = 0;
   const int nsub = c->cfg.time_stepping == SC_UNIFORM_DT ? 1 : 2;   // fine steps per parent step
   for (int sub = 0; sub < nsub; ++sub)
     for (int s = 1; s <= 4; ++s) {
@@ -1006,9 +1024,15 @@ int prolongate(sc_ctx* c, int fl) {
       outs[o] = F.Yh[o];
       fills[o] = s;
       subs[o] = sub;
+      if (c->wave_mixed) {   // FP64 Y1, FP32 increments Y_s - Y1
+        if (s == 1) outs[o] = F.Yd[sub];
+        else f32_mask |= 1u << o, inc_mask |= 1u << o;
+      } else if (c->mixed) {
+        f32_mask |= 1u << o;
+      }
     }
   return prolong_into(c, fl, F.d_prolong, F.prolong_cls, 4 * nsub, outs, fills, subs, F.total,
-                      c->mixed, -1, true);
+                      f32_mask, inc_mask, -1, true);
 }
 
 // Buffer zones: the parent's state at the start of fine substep `sub`
@@ -1046,7 +1070,7 @@ int prolongate_buffer(sc_ctx* c, int fl, int sub) {
       b.out[o] = outs[o];
       for (int i = 0; i < 3; ++i) b.w[o][i] = w[i];
     }
-    HIPCHK(c, launch_prolong_bricks(b, false, false, c->stream, nin));
+    HIPCHK(c, launch_prolong_bricks(b, false, c->stream, nin));
     ++c->launches;
   }
   const int64_t n = F.prolong_cls[8];
@@ -1072,7 +1096,7 @@ int prolongate_buffer(sc_ctx* c, int fl, int sub) {
     a.out[o] = outs[o];
     for (int i = 0; i < 3; ++i) a.w[o][i] = w[i];
   }
-  HIPCHK(c, launch_prolong(a, false, false, c->stream, nin));
+  HIPCHK(c, launch_prolong(a, false, c->stream, nin));
   ++c->launches;
   return SC_OK;
 }
@@ -1089,7 +1113,7 @@ int restrict_level(sc_ctx* c, int fl) {
   a.pboxes = P.d_boxes;
   a.fy = F.y[F.cur];
   a.py = P.y[P.cur];
-  a.py32 = c->mixed ? P.y32[P.cur] : nullptr;
+  a.py32 = (c->mixed && !c->wave_mixed) ? P.y32[P.cur] : nullptr;
   a.fvstride = F.total;
   a.pvstride = P.total;
   a.nvars = c->nvars;
@@ -1149,6 +1173,8 @@ void* array_ptr(sc_ctx* c, int l, int array, int var, bool* f32) {
       return elem(L.k[array - 1], var * L.total, c->esz);
   }
 }
+
+int scatter_phys(sc_ctx* c, int member, int level, int var);
 
 PackArgs member_pack(sc_ctx* c, int member, int l, void* arr) {
   LevelDev& L = c->lev[l];
@@ -1227,17 +1253,31 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
   c->fd_order = cfg->fd_order;
   c->esz = c->mixed ? sizeof(float) : sizeof(double);
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  for (int sub = 0; sub < 2; ++sub)
+  c->wave_mixed = c->mixed && cfg->rhs == SC_RHS_WAVE;
+  for (int sub = 0; sub < 2; ++sub) {
+    Rat r1[4];
     for (int f = 1; f <= 5; ++f) {
-      if (cfg->time_stepping == SC_UNIFORM_DT) aligned_weights(f, c->weights[sub][f - 1]);
-      else ghost_weights(f, sub ? Rat(1, 2) : Rat(0), c->weights[sub][f - 1]);
+      Rat r[4];
+      if (cfg->time_stepping == SC_UNIFORM_DT) aligned_weights(f, r);
+      else ghost_weights(f, sub ? Rat(1, 2) : Rat(0), r);
+      if (f == 1)
+        for (int i = 0; i < 4; ++i) r1[i] = r[i];
+      // stage increment Y_f - Y_1 of the substep, exact before rounding
+      for (int i = 0; i < 4; ++i) {
+        c->weights[sub][f - 1][i] = r[i].f();
+        c->weights_inc[sub][f - 1][i] = (r[i] - r1[i]).f();
+      }
     }
+  }
   *out = c;
   return SC_OK;
 }
 
 int sc_destroy(sc_ctx* c) {
   if (!c) return SC_OK;
+  // kernels still queued on the caller's stream write into the arena, which
+  // the caller may free (or hand to another tensor) as soon as this returns
+  if (c->state >= 2 && c->stream) (void)hipStreamSynchronize(c->stream);
   for (int i = 0; i < 3; ++i)
     if (c->graph[i]) (void)hipGraphExecDestroy(c->graph[i]);
   delete c;
@@ -1363,9 +1403,11 @@ int sc_bind_device_memory(sc_ctx* c, void* dptr, size_t nbytes) {
   HIPCHK(c, hipMemsetAsync(c->arena, 0, c->arena_bytes, c->stream));
   for (LevelDev& L : c->lev) {
     for (int i = 0; i < L.nbuf; ++i) L.y[i] = at<double>(c, L.o_y[i]);
-    for (int i = 0; i < 2; ++i) L.y32[i] = c->mixed ? at<float>(c, L.o_y32[i]) : nullptr;
+    for (int i = 0; i < 2; ++i)
+      L.y32[i] = (c->mixed && !c->wave_mixed) ? at<float>(c, L.o_y32[i]) : nullptr;
     for (int i = 0; i < 4; ++i) L.k[i] = at<char>(c, L.o_k[i]);
     for (int i = 0; i < L.nyh; ++i) L.Yh[i] = at<char>(c, L.o_yh[i]);
+    for (int i = 0; i < L.nyd; ++i) L.Yd[i] = at<double>(c, L.o_yd[i]);
     L.Ys = c->cfg.rhs == SC_RHS_Z4C ? at<double>(c, L.o_ys) : nullptr;
     L.d_boxes = at<BoxDev>(c, L.o_boxes);
     L.d_prefix = at<int64_t>(c, L.o_prefix);
@@ -1411,9 +1453,116 @@ int sc_set_initial_data(sc_ctx* c, int32_t member, int32_t level, int32_t var,
                            c->stream));
   PackArgs a = member_pack(c, member, level, L.y[L.cur] + var * L.total);
   HIPCHK(c, launch_pack(a, true, false, c->stream));
-  if (c->mixed)
+  if (c->mixed && !c->wave_mixed)
     HIPCHK(c, launch_to_f32(L.y[L.cur] + var * L.total, L.y32[L.cur] + var * L.total, L.total,
                             c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->state = 3;
+  return SC_OK;
+}
+
+int sc_set_initial_data_analytic(sc_ctx* c, int32_t kind, const double* params, int32_t nparams,
+                                 uint64_t seed) {
+  int rc = check_ready(c, 2);
+  if (rc) return rc;
+  if (nparams < 0 || (nparams > 0 && !params)) return fail(c, SC_E_ARG, "bad parameter list");
+  const bool wave = c->cfg.rhs == SC_RHS_WAVE;
+  const int nm = c->hier.geo.nmembers;
+  // per-member parameter sets
+  std::vector<std::vector<double>> P(nm);
+  switch (kind) {
+    case SC_ID_STANDING_WAVE:
+      if (!wave) return fail(c, SC_E_ARG, "a standing wave is wave-equation data");
+      if (nparams == 4) {
+        for (auto& p : P) p.assign(params, params + 4);
+      } else if (nparams == 0) {   // ensemble: modes {1,2,3}^3 and amplitude U(0.5, 1.5)
+        SplitMix64 rng(seed);
+        for (auto& p : P) {
+          double m[3];
+          for (int d = 0; d < 3; ++d) m[d] = (double)(1 + rng.next() % 3);
+          const double amp = 0.5 + rng.uniform();
+          p = {amp, m[0], m[1], m[2]};
+        }
+      } else {
+        return fail(c, SC_E_ARG, "standing wave: 4 parameters (A, m_x, m_y, m_z) or 0 (seeded)");
+      }
+      break;
+    case SC_ID_GAUSSIAN_PULSES: {
+      if (!wave) return fail(c, SC_E_ARG, "Gaussian pulses are wave-equation data");
+      if (nparams < 2) return fail(c, SC_E_ARG, "Gaussian pulses: npulses, period, ...");
+      const int np = (int)params[0];
+      if (np < 1 || np > 32 || params[0] != (double)np || !(params[1] >= 0.0))
+        return fail(c, SC_E_ARG, "Gaussian pulses: 1 <= npulses <= 32, period >= 0");
+      std::vector<double> p = {(double)np, params[1]};
+      if (nparams == 3) {   // seeded: A U(0.1,1), w U(0.05,0.2), centre (-+x_t, 0, 0) + U(-0.1,0.1)^3
+        SplitMix64 rng(seed);
+        for (int q = 0; q < np; ++q) {
+          const double A = 0.1 + 0.9 * rng.uniform();
+          const double w = 0.05 + 0.15 * rng.uniform();
+          const double ox = -0.1 + 0.2 * rng.uniform();
+          const double oy = -0.1 + 0.2 * rng.uniform();
+          const double oz = -0.1 + 0.2 * rng.uniform();
+          const double cx = (q % 2 == 0 ? -params[2] : params[2]) + ox;
+          p.insert(p.end(), {A, w, cx, oy, oz});
+        }
+      } else if (nparams == 2 + 5 * np) {
+        p.insert(p.end(), params + 2, params + nparams);
+        for (int q = 0; q < np; ++q)
+          if (!(p[2 + 5 * q + 1] > 0.0)) return fail(c, SC_E_ARG, "Gaussian pulses: widths > 0");
+      } else {
+        return fail(c, SC_E_ARG, "Gaussian pulses: 3 parameters (npulses, period, x_tower; "
+                                 "seeded) or 2 + 5 npulses (A, w, c_x, c_y, c_z per pulse)");
+      }
+      for (auto& q : P) q = p;
+      break;
+    }
+    case SC_ID_BRILL_LINDQUIST:
+      if (wave) return fail(c, SC_E_ARG, "Brill-Lindquist data need the Z4c right-hand side");
+      if (nparams != 4) return fail(c, SC_E_ARG, "Brill-Lindquist: (m_+, m_-, x_+, x_-)");
+      for (auto& p : P) p.assign(params, params + 4);
+      break;
+    case SC_ID_SPHERICAL_GAUSSIAN:
+      if (!wave) return fail(c, SC_E_ARG, "the spherical Gaussian is wave-equation data");
+      if (nparams != 3 || !(params[1] > 0.0))
+        return fail(c, SC_E_ARG, "spherical Gaussian: (A, sigma > 0, t)");
+      for (auto& p : P) p.assign(params, params + 3);
+      break;
+    default:
+      return fail(c, SC_E_ARG, "unknown initial-data kind");
+  }
+  for (int l = 0; l < (int)c->lev.size(); ++l) {
+    LevelDev& L = c->lev[l];
+    for (int m = 0; m < nm; ++m) {
+      InitArgs a{};
+      a.kind = kind;
+      a.nvars = c->nvars;
+      a.boxes = L.d_boxes + m * L.nb_member;
+      a.prefix = L.d_prefix;
+      a.nboxes = L.nb_member;
+      for (int d = 0; d < 3; ++d) a.origin[d] = c->hier.geo.origin[d];
+      a.dx = L.dx;
+      a.vstride = L.total;
+      std::copy(P[m].begin(), P[m].end(), a.p);
+      // owned points of the current state (and its FP32 shadow)
+      a.n = L.owned_member;
+      a.out = L.y[L.cur];
+      a.out32 = (c->mixed && !c->wave_mixed) ? L.y32[L.cur] : nullptr;
+      HIPCHK(c, launch_init(a, c->stream));
+      // frozen physical-boundary ghosts take the same closed form
+      const int64_t per = (int64_t)L.phys_q.size() / 3;
+      if (per == 0) continue;
+      a.n = per;
+      a.idx = L.d_phys + m * per;
+      a.out = c->d_stage;
+      a.out32 = nullptr;
+      for (int v = 0; v < c->nvars; ++v) {
+        a.var = v;
+        HIPCHK(c, launch_init(a, c->stream));
+        rc = scatter_phys(c, m, l, v);
+        if (rc) return rc;
+      }
+    }
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->state = 3;
   return SC_OK;
@@ -1451,15 +1600,40 @@ int sc_set_phys_data(sc_ctx* c, int32_t member, int32_t level, int32_t var, cons
   if (n != per) return fail(c, SC_E_ARG, "n must equal sc_phys_count");
   if (per == 0) return SC_OK;
   HIPCHK(c, hipMemcpyAsync(c->d_stage, host, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
-  const int64_t* idx = L.d_phys + member * per;
-  for (int i = 0; i < L.nyh; ++i)
-    HIPCHK(c, launch_scatter(idx, n, c->d_stage, elem(L.Yh[i], var * L.total, c->esz), c->mixed,
-                             c->stream));
-  for (int i = 0; i < L.nbuf; ++i)
-    HIPCHK(c, launch_scatter(idx, n, c->d_stage, L.y[i] + var * L.total, false, c->stream));
+  rc = scatter_phys(c, member, level, var);
+  if (rc) return rc;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return SC_OK;
 }
+
+}  // extern "C"
+
+namespace {
+
+// The values of one variable at the physical-boundary ghosts of one member
+// of a level, in the library's order in d_stage, into every array that holds
+// those ghosts: the halo tables and the state buffers.
+int scatter_phys(sc_ctx* c, int member, int level, int var) {
+  LevelDev& L = c->lev[level];
+  const int64_t per = (int64_t)L.phys_q.size() / 3, n = per;
+  const int64_t* idx = L.d_phys + member * per;
+  for (int i = 0; i < L.nyh; ++i) {
+    void* dst = elem(L.Yh[i], var * L.total, c->esz);
+    // mixed wave: frozen ghosts have zero stage increments; their value
+    // lives in the FP64 stage-1 tables
+    if (c->wave_mixed) HIPCHK(c, launch_scatter_value(idx, n, 0.0, dst, true, c->stream));
+    else HIPCHK(c, launch_scatter(idx, n, c->d_stage, dst, c->mixed, c->stream));
+  }
+  for (int i = 0; i < L.nyd; ++i)
+    HIPCHK(c, launch_scatter(idx, n, c->d_stage, L.Yd[i] + var * L.total, false, c->stream));
+  for (int i = 0; i < L.nbuf; ++i)
+    HIPCHK(c, launch_scatter(idx, n, c->d_stage, L.y[i] + var * L.total, false, c->stream));
+  return SC_OK;
+}
+
+}  // namespace
+
+extern "C" {
 
 int sc_hamiltonian(sc_ctx* c, int32_t member, int32_t level, double* host, int64_t n) {
   int rc = check_ready(c, 3);
@@ -1499,6 +1673,18 @@ int sc_advance(sc_ctx* c, int32_t ncoarse) {
     // repeat, so the first runs eagerly
     if (c->cfg.exec == SC_EXEC_GRAPH && !(buffer_zones(c) && c->lev[0].steps_done == 0)) {
       const int parity = c->lev[0].cur;
+      // a graph bakes in every level's buffer indices at capture; a level
+      // stepped on its own since then (sc_step_level) needs a new capture
+      if (c->graph_ready[parity]) {
+        bool same = c->graph_cur[parity].size() == c->lev.size();
+        for (size_t l = 0; same && l < c->lev.size(); ++l)
+          same = c->graph_cur[parity][l] == c->lev[l].cur;
+        if (!same) {
+          (void)hipGraphExecDestroy(c->graph[parity]);
+          c->graph[parity] = nullptr;
+          c->graph_ready[parity] = false;
+        }
+      }
       if (!c->graph_ready[parity]) {
         // capture one coarse step starting from this buffer parity
         std::vector<int> cur0(c->lev.size());
@@ -1519,6 +1705,7 @@ int sc_advance(sc_ctx* c, int32_t ncoarse) {
         if (e != hipSuccess)
           return fail(c, SC_E_HIP, std::string("instantiate: ") + hipGetErrorString(e));
         c->graph_ready[parity] = true;
+        c->graph_cur[parity] = cur0;
       }
       c->launches = 0;
       HIPCHK(c, hipGraphLaunch(c->graph[parity], c->stream));
@@ -1589,7 +1776,7 @@ int sc_fill_ghosts(sc_ctx* c, int32_t level, int32_t which, int32_t substep) {
     void* outs[1] = {y};
     const int fills[1] = {which}, subs[1] = {substep};
     rc = prolong_into(c, level, L.d_prolong, L.prolong_cls, 1, outs, fills, subs, L.total,
-                      false, -1, true);
+                      0u, 0u, -1, true);
     if (rc) return rc;
   }
   return SC_OK;
@@ -1627,15 +1814,24 @@ int sc_read_rb(sc_ctx* c, int32_t member, int32_t level, int32_t which, int32_t 
   if (buffer_zones(c)) return fail(c, SC_E_STATE, "buffer zones: no dense-output RB values");
   LevelDev& L = c->lev[level];
   if (n != L.nrb) return fail(c, SC_E_ARG, "n must equal the level's RB points");
-  if (which <= 4) {
+  const int64_t* idx = L.d_rbfirst + member * L.nrb;
+  if (which <= 4 && c->wave_mixed) {   // FP64 Y1 plus the FP32 increment
+    const double* base = L.Yd[substep] + var * L.total;
+    if (which == 1)
+      HIPCHK(c, launch_gather(idx, L.nrb, base, false, c->d_stage, c->stream));
+    else
+      HIPCHK(c, launch_gather_sum(idx, L.nrb, base,
+                                  static_cast<const float*>(elem(L.Yh[substep * 4 + which - 1],
+                                                                 var * L.total, c->esz)),
+                                  c->d_stage, c->stream));
+  } else if (which <= 4) {
     const void* src = elem(L.Yh[substep * 4 + which - 1], var * L.total, c->esz);
-    HIPCHK(c, launch_gather(L.d_rbfirst + member * L.nrb, L.nrb, src, c->mixed, c->d_stage,
-                            c->stream));
+    HIPCHK(c, launch_gather(idx, L.nrb, src, c->mixed, c->d_stage, c->stream));
   } else {
     void* outs[1] = {c->d_stage};
     const int fills[1] = {5}, subs[1] = {substep};
     rc = prolong_into(c, level, L.d_rblist + member * L.nrb, L.rblist_cls, 1, outs, fills, subs,
-                      0, false, var, false);
+                      0, 0u, 0u, var, false);
     if (rc) return rc;
   }
   HIPCHK(c, hipMemcpyAsync(host, c->d_stage, sizeof(double) * n, hipMemcpyDeviceToHost,
@@ -1701,6 +1897,8 @@ int sc_poison_halos(sc_ctx* c) {
     if (!L.phys.empty()) return fail(c, SC_E_STATE, "poisoning would erase physical ghosts");
     for (int i = 0; i < L.nyh; ++i)
       HIPCHK(c, launch_fill(L.Yh[i], c->nvars * L.total, nan, c->mixed, c->stream));
+    for (int i = 0; i < L.nyd; ++i)
+      HIPCHK(c, launch_fill(L.Yd[i], c->nvars * L.total, nan, false, c->stream));
     for (int i = 0; i < 4; ++i)
       HIPCHK(c, launch_fill(L.k[i], c->nvars * L.total, nan, c->mixed, c->stream));
   }
@@ -1721,17 +1919,21 @@ int sc_set_tile_shape(sc_ctx* c, int32_t level, int32_t tz, int32_t grid, int32_
   int rc = check_ready(c, 3);
   if (rc) return rc;
   if (level < 0 || level >= (int)c->lev.size()) return fail(c, SC_E_ARG, "level out of range");
-  if (tz < kTuneTzMin || tz > (1 << 20)) return fail(c, SC_E_ARG, "z-chunk out of range");
+  const bool z4c = c->cfg.rhs == SC_RHS_Z4C;
+  if (tz < (z4c ? kZ4cTzMin : kTuneTzMin) || tz > (1 << 20))
+    return fail(c, SC_E_ARG, "z-chunk out of range");
   if (grid < 0) return fail(c, SC_E_ARG, "grid must be >= 0");
-  if (!stage_variant_ok(slots, depth, threads))
+  if (!z4c && !stage_variant_ok(slots, depth, threads))
     return fail(c, SC_E_ARG, "(threads, points per thread, planes in flight) must be (256, 2, 1), "
                              "(256, 2, 2), (256, 1, 2), (512, 2, 1) or (512, 2, 2)");
   LevelDev& L = c->lev[level];
   TileShape sh = L.shape;
   sh.tz = tz;
-  sh.depth = depth;
-  sh.slots = slots;
-  sh.threads = threads;
+  if (!z4c) {   // the Z4c kernels keep their own workgroup shape and grid
+    sh.depth = depth;
+    sh.slots = slots;
+    sh.threads = threads;
+  }
   std::vector<TileDev> tl;
   for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
     const BoxDev& B = L.boxes[ib];
@@ -1740,7 +1942,7 @@ int sc_set_tile_shape(sc_ctx* c, int32_t level, int32_t tz, int32_t grid, int32_
   }
   if (tl.size() > L.tiles_capacity)
     return fail(c, SC_E_ARG, "z-chunk gives more tiles than the tile table holds");
-  sh.grid = grid == 0 ? 0 : std::min<int>(grid, (int)tl.size());
+  sh.grid = (grid == 0 || z4c) ? 0 : std::min<int>(grid, (int)tl.size());
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, upload(c, L.d_tiles, tl));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1796,11 +1998,12 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
         // one RK4 step's four stage launches on the bound data (stage s reads
         // y_n, k_{s-1} and a halo table, writes k_s; stage 4 writes the
         // state buffer the next step writes anyway)
-        const void* yn = c->mixed ? (const void*)L.y32[L.cur] : (const void*)L.y[L.cur];
+        const void* yn = L.y[L.cur];
         auto rk_stages = [&]() -> int {
           for (int st = 1; st <= 4; ++st) {
+            const void* table = (c->wave_mixed && st == 1) ? (const void*)L.Yd[0] : L.Yh[0];
             const int r2 = enqueue_stage_launches(c, (int)l, st, false, yn,
-                                                  st == 1 ? nullptr : L.k[st - 2], L.Yh[0]);
+                                                  st == 1 ? nullptr : L.k[st - 2], table);
             if (r2) return r2;
           }
           return SC_OK;

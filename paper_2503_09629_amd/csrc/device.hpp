@@ -13,6 +13,9 @@
 // every step), the slopes k1..k4, and the halo tables Yh: one per (substep,
 // stage) on refinement levels (8), holding the stage ghost values produced
 // by prolongation, and one on level 0 for the periodic/intra-level copies.
+// Wave right-hand side in mixed precision: the stage-1 tables are FP64 (Yd,
+// one per substep) and the tables of stages 2-4 hold the FP32 stage
+// increments Y_s - Y_1.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -69,15 +72,17 @@ struct RestrictRegion {
 
 constexpr int kMaxOut = 8;
 
-// Stencil operands are FP64 in SC_FP64 mode and FP32 shadows in SC_MIXED
-// mode (the `void` pointers below hold that type); the state, the RK4
-// combination and everything on the refinement boundary stay FP64.
+// Stencil operands are FP64 in SC_FP64 mode.  In SC_MIXED mode stage 1
+// reads the FP64 y_n and an FP64 halo table and stores an FP32 k1; stages
+// 2-4 read the FP32 k_{s-1} and FP32 increment tables (the `void` pointers
+// below hold those types); the state, the RK4 combination and everything on
+// the refinement boundary stay FP64.
 struct StageArgs {
   const TileDev* tiles;
   int32_t ntiles;
   int32_t stage;
   const BoxDev* boxes;
-  const void* yn;      // stencil operand: y_n
+  const void* yn;      // stencil operand: y_n (unused by the increment form)
   const void* kprev;   // stencil operand: k_{s-1}
   const void* Yh;      // halo table of this (substep, stage)
   const void* k1;
@@ -86,7 +91,6 @@ struct StageArgs {
   void* kout;          // k_s
   const double* yn64;  // FP64 y_n for the final combination (stage 4)
   double* ynew;        // FP64 y_{n+1} (stage 4)
-  float* ynew32;       // FP32 shadow of y_{n+1} (mixed, stage 4)
   int64_t vstride;
   double cdt;    // c_s * dt: interior stage vector Y = y_n + cdt * k_{s-1}
   double dt6;    // dt / 6
@@ -106,6 +110,7 @@ struct SyncArgs {
   int64_t vstride;
   double cdt;
   int32_t nvars;
+  int32_t inc;         // 1: copy the stage increment cdt * k_{s-1} (mixed wave)
 };
 
 struct ProlongArgs {
@@ -126,6 +131,8 @@ struct ProlongArgs {
   double H;                      // parent time step
   int32_t nout;
   int32_t nvars;
+  uint32_t f32_mask;             // bit o: output o is FP32 (else FP64)
+  uint32_t inc_mask;             // bit o: output o omits P[y_n] (a stage increment)
 };
 
 struct BrickArgs {
@@ -142,6 +149,8 @@ struct BrickArgs {
   int64_t ovstride;
   double w[kMaxOut][4];
   double H;
+  uint32_t f32_mask;   // as in ProlongArgs
+  uint32_t inc_mask;
 };
 
 struct RestrictArgs {
@@ -166,19 +175,46 @@ struct PackArgs {
   double* buf;            // canonical buffer
 };
 
-// launchers (kernels.hip); `f32` selects FP32 stencil operands / arrays
+// Closed-form initial data evaluated on the device (sc_set_initial_data_analytic).
+constexpr int kInitParams = 6 + 5 * 32;
+struct InitArgs {
+  int32_t kind;           // SC_ID_*
+  int32_t nvars;
+  const BoxDev* boxes;    // boxes of one member of one level
+  const int64_t* prefix;  // canonical prefix counts (device)
+  int32_t nboxes;
+  int64_t n;              // points to evaluate
+  const int64_t* idx;     // null: the member's owned points in canonical order;
+                          // else level-array offsets of halo points
+  double origin[3];
+  double dx;
+  int32_t var;            // halo points: the variable evaluated
+  double* out;            // owned points: the level array of variable 0 (variables
+                          // vstride apart); halo points: n values of variable var
+  float* out32;           // FP32 shadow of the owned points (Z4c mixed) or null
+  int64_t vstride;
+  double p[kInitParams];  // the kind's parameters (see sc_set_initial_data_analytic)
+};
+
+// launchers (kernels.hip); `f32` selects FP32 arrays
+// mixed: the mixed-precision stage kernels (see StageArgs)
 // depth: planes of loads in flight (1 or 2); slots: owned points per thread (1 or 2);
 // threads: 256 or 512 per workgroup; the tiles must have been cut for slots and threads
-hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int depth, int slots, int threads,
+hipError_t launch_stage(const StageArgs& a, int grid, bool mixed, int depth, int slots, int threads,
                         hipStream_t s);
 hipError_t launch_sync(const SyncArgs& a, bool f32, hipStream_t s);
-// k_f32: parent slopes are FP32; out_f32: outputs are FP32
+// k_f32: parent slopes are FP32; output types and forms in the args' masks
 // nin: 5 = (y_n, k1..k4) with dense-output weights; 3 = (y_n, y_{n-1}, y_{n+1})
 // with time-interpolation weights w[o][0..2] on (y_{n-1}, y_n, y_{n+1}) (pk[0] =
 // y_{n-1}, pk[1] = y_{n+1}, FP64); 1 = y_n alone
-hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s, int nin = 5);
-hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, bool out_f32, hipStream_t s,
-                                 int nin = 5);
+hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, hipStream_t s, int nin = 5);
+hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, hipStream_t s, int nin = 5);
+// dst[i] = base[idx[i]] + inc[idx[i]] (stage value from stage-1 and increment tables)
+hipError_t launch_gather_sum(const int64_t* idx, int64_t n, const double* base, const float* inc,
+                             double* dst, hipStream_t s);
+// dst[idx[i]] = v
+hipError_t launch_scatter_value(const int64_t* idx, int64_t n, double v, void* dst, bool f32,
+                                hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, bool unpack, bool f32, hipStream_t s);
 hipError_t launch_norms(const PackArgs& a, bool f32, double* partials, int nparts, double* out,
@@ -189,6 +225,7 @@ hipError_t launch_fill(void* p, int64_t n, double v, bool f32, hipStream_t s);
 hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, void* dst, bool f32,
                           hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_init(const InitArgs& a, hipStream_t s);
 
 // Stencil-kernel workgroup families: threads, ring points per thread and plane,
 // and LDS window capacity per variable and plane ((nx+6)(ny+6) points).  The

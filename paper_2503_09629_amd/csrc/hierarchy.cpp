@@ -9,19 +9,6 @@ namespace sc {
 
 namespace {
 
-// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): one stream per level.
-struct SplitMix64 {
-  uint64_t s;
-  explicit SplitMix64(uint64_t seed) : s(seed) {}
-  uint64_t next() {
-    s += 0x9E3779B97F4A7C15ull;
-    uint64_t z = s;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-  }
-};
-
 // Recursive cut along the longest side (ties: lowest axis), left part first.
 void split_box(const IBox& b, SplitMix64& rng, int64_t min_block, int64_t max_block,
                std::vector<IBox>* out) {

@@ -22,6 +22,21 @@
 
 namespace sc {
 
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): the block split draws one
+// stream per level; seeded initial data draw their parameters from it.
+struct SplitMix64 {
+  uint64_t s;
+  explicit SplitMix64(uint64_t seed) : s(seed) {}
+  uint64_t next() {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return (double)(next() >> 11) * 0x1.0p-53; }   // top 53 bits
+};
+
 enum GhostKind : int8_t { kSync = 0, kRb = 1, kPhys = 2 };
 
 struct IBox {

@@ -5,8 +5,12 @@
 // Every floating-point expression is written in one fixed evaluation order
 // and the file is compiled without FP contraction, so each value is the
 // correctly rounded result of the stated sequence of operations.  The
-// stencil type TS is double (FP64 mode) or float (mixed mode: FP32 shadows
-// in, FP32 arithmetic, FP32 slopes out; the state update stays FP64).
+// stencil type TS is double (FP64 mode, and the first stage of mixed mode)
+// or float (stages 2-4 of mixed mode, which evaluate the right-hand side of
+// the stage increment Y_s - y_n in FP32); the slope type TK is double or
+// float; the state update stays FP64.
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace sc {
@@ -60,12 +64,17 @@ __device__ __forceinline__ TS load_at(const char* base, uint32_t byte_off) {
   return *reinterpret_cast<const TS*>(base + byte_off);
 }
 
-// Stage vector from its raw loads: owned points (in) are y_n + (c_s dt) k_{s-1}
-// (Y1 = y_n); halo points are the halo-table value, loaded into ra.
-template <int STAGE, typename TS>
+// Stencil operand from its raw loads: owned points (in) are the stage vector
+// y_n + (c_s dt) k_{s-1} (Y1 = y_n), or in increment form (INC) the stage
+// increment (c_s dt) k_{s-1} alone; halo points are the halo-table value,
+// loaded into ra.
+template <int STAGE, bool INC, typename TS>
 __device__ __forceinline__ TS stage_form(TS ra, TS rk, TS cdt, bool in) {
   if constexpr (STAGE == 1) {
     return ra;
+  } else if constexpr (INC) {
+    const TS e = cdt * rk;
+    return in ? e : ra;
   } else {
     const TS y = ra + cdt * rk;
     return in ? y : ra;
@@ -93,15 +102,24 @@ __device__ __forceinline__ TS stage_form(TS ra, TS rk, TS cdt, bool in) {
 // Stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4) in FP64.
 // The z stencils take their taps in increasing z whatever the direction, so
 // both directions give the same bits.
+// Increment form (mixed mode, TS = float, stages 2-4): the wave right-hand
+// side f is linear, so k_s = f(y_n + e_s) = k1 + f(e_s) with the stage
+// increment e_s = c_s dt k_{s-1} (halo: the table holds Y_s - Y_1).  Only e_s,
+// of size O(dt |k|), passes through FP32 arithmetic, so the FP32 rounding that
+// the stencil amplifies by 1/h^2 is that of e_s, not of y_n; k1 = f(y_n) is
+// evaluated in FP64 (TS = double, TK = float).
 template <typename TS, int S, int RM>
 struct StageRaw {   // raw loads of one ring plane and one column plane
   TS ra[2][RM], rk[2][RM];
   TS ca[2][S], ck[2][S];
 };
 
-template <int STAGE, typename TS, int DEPTH, int S, bool WK, int NT, int R>
+template <int STAGE, typename TS, typename TK, int DEPTH, int S, bool WK, int NT, int R>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T, const BoxDev& B,
                                            TS* lds) {
+  constexpr bool INC = sizeof(TS) == 4;   // FP32 stencils evaluate the stage increment
+  static_assert(!INC || (STAGE > 1 && sizeof(TK) == 4), "increment form: stages 2-4, FP32 slopes");
+  static_assert(STAGE == 1 || sizeof(TK) == sizeof(TS), "stencil operand k_{s-1} has the slope type");
   constexpr int RM = StageFamily<NT>::ring;
   constexpr int kWinCap = StageFamily<NT>::wincap;
   constexpr int kWinStride = kWinCap + 8;   // per-variable LDS stride: window plus a spare slot
@@ -160,14 +178,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
       const int64_t pr = plane(zr, v);
 #pragma unroll
       for (int k = 0; k < RM; ++k) {
-        X.ra[v][k] = load_at<TS>((rin[k] ? yn : yh) + pr, rb[k]);
+        if constexpr (INC) {   // owned points need only the slope
+          X.ra[v][k] = TS(0);
+          if (!rin[k]) X.ra[v][k] = load_at<TS>(yh + pr, rb[k]);
+        } else {
+          X.ra[v][k] = load_at<TS>((rin[k] ? yn : yh) + pr, rb[k]);
+        }
         X.rk[v][k] = STAGE > 1 ? load_at<TS>(kp + pr, rb[k]) : TS(0);
       }
       const int64_t pq = plane(zq, v);
       const char* src = (qin ? yn : yh) + pq;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        X.ca[v][s] = load_at<TS>(src, cb[s]);
+        if constexpr (INC) X.ca[v][s] = qin ? TS(0) : load_at<TS>(src, cb[s]);
+        else X.ca[v][s] = load_at<TS>(src, cb[s]);
         X.ck[v][s] = STAGE > 1 ? load_at<TS>(kp + pq, cb[s]) : TS(0);
       }
     }
@@ -184,9 +208,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
       const char* src = (in ? yn : yh) + pb;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const TS va = load_at<TS>(src, cb[s]);
+        const TS va = (INC && in) ? TS(0) : load_at<TS>(src, cb[s]);
         const TS vk = STAGE > 1 ? load_at<TS>(kp + pb, cb[s]) : TS(0);
-        q[v][s][j] = stage_form<STAGE, TS>(va, vk, cdt, in);
+        q[v][s][j] = stage_form<STAGE, INC, TS>(va, vk, cdt, in);
       }
     }
   }
@@ -208,7 +232,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
     for (int s = 0; s < S; ++s)
 #pragma unroll
       for (int v = 0; v < 2; ++v)
-        q[v][s][QN - 1] = stage_form<STAGE, TS>(P.ca[v][s], P.ck[v][s], cdt, zc);
+        q[v][s][QN - 1] = stage_form<STAGE, INC, TS>(P.ca[v][s], P.ck[v][s], cdt, zc);
     const bool zr = zin(z);
     // lanes without a point write the spare slot past the window: no branch
 #pragma unroll
@@ -218,7 +242,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
       for (int s = 0; s < S; ++s) Lv[act[s] ? li[s] : kWinCap] = q[v][s][R];
 #pragma unroll
       for (int k = 0; k < RM; ++k)
-        Lv[ract[k] ? rli[k] : kWinCap] = stage_form<STAGE, TS>(P.ra[v][k], P.rk[v][k], cdt, rin[k] && zr);
+        Lv[ract[k] ? rli[k] : kWinCap] =
+            stage_form<STAGE, INC, TS>(P.ra[v][k], P.rk[v][k], cdt, rin[k] && zr);
     }
     __syncthreads();
     issue(P, iz + DEPTH);   // in flight during this plane's arithmetic
@@ -226,23 +251,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
     const TS* Lp = L + kWinStride;
     // column taps in increasing z: zt[m] is plane z + m - R
     auto zt = [&](int v, int s, int m) -> TS { return up ? q[v][s][m] : q[v][s][2 * R - m]; };
-    // stage 4 reads the slopes and y_n at the point: issue those loads first
-    TS c1[2][S], c2[2][S], c3[2][S];
+    // stage 4 reads the slopes and y_n at the point, the increment form k1:
+    // issue those loads first
+    TK c1[2][S], c2[2][S], c3[2][S];
     double c0[2][S];
     const int64_t pe = B.base + (int64_t)(z + B.pad) * ps;   // element offset of the plane
-    if constexpr (STAGE == 4) {
-      const TS* k1 = static_cast<const TS*>(a.k1);
-      const TS* k2 = static_cast<const TS*>(a.k2);
-      const TS* k3 = static_cast<const TS*>(a.k3);
+    if constexpr (STAGE == 4 || INC) {
+      const TK* k1 = static_cast<const TK*>(a.k1);
+      const TK* k2 = static_cast<const TK*>(a.k2);
+      const TK* k3 = static_cast<const TK*>(a.k3);
 #pragma unroll
       for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
           const int64_t o = pe + cb[s] / (uint32_t)sizeof(TS) + v * a.vstride;
           c1[v][s] = k1[o];
-          c2[v][s] = k2[o];
-          c3[v][s] = k3[o];
-          c0[v][s] = a.yn64[o];
+          if constexpr (STAGE == 4) {
+            c2[v][s] = k2[o];
+            c3[v][s] = k3[o];
+            c0[v][s] = a.yn64[o];
+          }
         }
     }
     // lanes without a point compute and store the tile's first point again
@@ -277,10 +305,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
                               zt(v, s, R + 1), zt(v, s, R + 2), zt(v, s, R + 3));
         Q[v] = cko * ((kx + ky) + kz);
       }
-      const TS kv[2] = {cp + Q[0], lap + Q[1]};
+      TK kv[2];
+      if constexpr (INC) {   // k_s = k1 + f(e_s)
+        kv[0] = c1[0][s] + (cp + Q[0]);
+        kv[1] = c1[1][s] + (lap + Q[1]);
+      } else {
+        kv[0] = (TK)(cp + Q[0]);
+        kv[1] = (TK)(lap + Q[1]);
+      }
       const int64_t o = pe + cb[s] / (uint32_t)sizeof(TS);
       if constexpr (WK) {
-        TS* ko = static_cast<TS*>(a.kout);
+        TK* ko = static_cast<TK*>(a.kout);
         ko[o] = kv[0];
         ko[o + a.vstride] = kv[1];
       }
@@ -290,9 +325,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
           const int64_t ov = o + v * a.vstride;
           const double sm = (((double)c1[v][s] + 2.0 * (double)c2[v][s]) + 2.0 * (double)c3[v][s]) +
                             (double)kv[v];
-          const double yv = c0[v][s] + a.dt6 * sm;
-          a.ynew[ov] = yv;
-          if constexpr (sizeof(TS) == 4) a.ynew32[ov] = (float)yv;
+          a.ynew[ov] = c0[v][s] + a.dt6 * sm;
         }
       }
     }
@@ -312,7 +345,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
 
 // Persistent stage kernel: workgroups stride over the tile list; a tile's
 // dir field picks its z marching direction.
-template <int STAGE, typename TS, int DEPTH, int S, bool WK, int NT, int R>
+template <int STAGE, typename TS, typename TK, int DEPTH, int S, bool WK, int NT, int R>
 __global__ __launch_bounds__(NT) void k_wave_stage(StageArgs a) {
   __shared__ TS lds[2 * 2 * (StageFamily<NT>::wincap + 8)];
   // consecutive workgroups land on different XCDs (round robin over 8); give
@@ -323,12 +356,13 @@ __global__ __launch_bounds__(NT) void k_wave_stage(StageArgs a) {
   for (int t = g; t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
-    stage_tile<STAGE, TS, DEPTH, S, WK, NT, R>(a, T, B, lds);
+    stage_tile<STAGE, TS, TK, DEPTH, S, WK, NT, R>(a, T, B, lds);
   }
 }
 
 // Halo copy from an owned point of the same level: the stage vector there
-// (y_n + cdt k_{s-1}, evaluated exactly as the stencil kernel does), or y_n.
+// (y_n + cdt k_{s-1}, evaluated exactly as the stencil kernel does), y_n,
+// or in increment form the stage increment cdt k_{s-1}.
 template <typename TS>
 __global__ __launch_bounds__(256) void k_sync(SyncArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -339,7 +373,8 @@ __global__ __launch_bounds__(256) void k_sync(SyncArgs a) {
   TS* out = static_cast<TS*>(a.out);
   for (int v = 0; v < a.nvars; ++v) {
     const int64_t s = e.src + v * a.vstride;
-    out[e.dst + v * a.vstride] = kp ? yn[s] + TS(a.cdt) * kp[s] : yn[s];
+    out[e.dst + v * a.vstride] =
+        a.inc ? TS(a.cdt) * kp[s] : (kp ? yn[s] + TS(a.cdt) * kp[s] : yn[s]);
   }
 }
 
@@ -349,17 +384,24 @@ __global__ __launch_bounds__(256) void k_sync(SyncArgs a) {
 // NIN = 3 (buffer zones, time interpolation): v = (y_n, y_{n-1}, y_{n+1}),
 //   ((w1 P[y_{n-1}] + w2 P[y_n]) + w3 P[y_{n+1}]);
 // NIN = 1 (buffer zones at the parent's own time): P[y_n].
+// An increment output (inc) omits P[y_n]: H (((w1 P[k1] + ...) + w4 P[k4]).
 template <int NIN>
 __device__ __forceinline__ double prolong_combine(const double (&v)[NIN], const double* w,
-                                                  double H) {
+                                                  double H, bool inc) {
   if constexpr (NIN == 5) {
     const double s = ((w[0] * v[1] + w[1] * v[2]) + w[2] * v[3]) + w[3] * v[4];
-    return v[0] + H * s;
+    return inc ? H * s : v[0] + H * s;
   } else if constexpr (NIN == 3) {
     return (w[0] * v[1] + w[1] * v[0]) + w[2] * v[2];
   } else {
     return v[0];
   }
+}
+
+// Output o of a prolongation is FP32 when bit o of f32_mask is set.
+__device__ __forceinline__ void store_out(void* out, int64_t i, bool f32, double v) {
+  if (f32) static_cast<float*>(out)[i] = (float)v;
+  else static_cast<double*>(out)[i] = v;
 }
 
 // Prolongation of NIN parent vectors (y_n first, then the pk[]) to one fine
@@ -368,7 +410,7 @@ __device__ __forceinline__ double prolong_combine(const double (&v)[NIN], const 
 // combination (prolong_combine), all in FP64.  The parity class is a
 // template parameter, so every loop has a compile-time trip count, and each
 // stencil tap gathers all NIN vectors.
-template <int NIN, int OX, int OY, int OZ, typename TK, typename TO>
+template <int NIN, int OX, int OY, int OZ, typename TK>
 __device__ __forceinline__ void prolong_one(const ProlongArgs& a, int64_t i) {
   constexpr int NX = OX ? 6 : 1, NY = OY ? 6 : 1, NZ = OZ ? 6 : 1;
   constexpr double W[6] = {3.0 / 256.0, -25.0 / 256.0, 150.0 / 256.0,
@@ -424,11 +466,12 @@ __device__ __forceinline__ void prolong_one(const ProlongArgs& a, int64_t i) {
       }
     }
     for (int o = 0; o < a.nout; ++o)
-      static_cast<TO*>(a.out[o])[e.dst + v * a.ovstride] = (TO)prolong_combine<NIN>(pz, a.w[o], a.H);
+      store_out(a.out[o], e.dst + v * a.ovstride, (a.f32_mask >> o) & 1,
+                prolong_combine<NIN>(pz, a.w[o], a.H, (a.inc_mask >> o) & 1));
   }
 }
 
-template <int NIN, typename TK, typename TO>
+template <int NIN, typename TK>
 __global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
   const int b = blockIdx.x;
   int cls = 0;
@@ -436,14 +479,14 @@ __global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
   const int64_t i = a.cls_start[cls] + (int64_t)(b - a.blk_start[cls]) * 256 + threadIdx.x;
   if (i >= a.cls_start[cls + 1]) return;
   switch (cls) {
-    case 0: prolong_one<NIN, 0, 0, 0, TK, TO>(a, i); break;
-    case 1: prolong_one<NIN, 1, 0, 0, TK, TO>(a, i); break;
-    case 2: prolong_one<NIN, 0, 1, 0, TK, TO>(a, i); break;
-    case 3: prolong_one<NIN, 1, 1, 0, TK, TO>(a, i); break;
-    case 4: prolong_one<NIN, 0, 0, 1, TK, TO>(a, i); break;
-    case 5: prolong_one<NIN, 1, 0, 1, TK, TO>(a, i); break;
-    case 6: prolong_one<NIN, 0, 1, 1, TK, TO>(a, i); break;
-    default: prolong_one<NIN, 1, 1, 1, TK, TO>(a, i); break;
+    case 0: prolong_one<NIN, 0, 0, 0, TK>(a, i); break;
+    case 1: prolong_one<NIN, 1, 0, 0, TK>(a, i); break;
+    case 2: prolong_one<NIN, 0, 1, 0, TK>(a, i); break;
+    case 3: prolong_one<NIN, 1, 1, 0, TK>(a, i); break;
+    case 4: prolong_one<NIN, 0, 0, 1, TK>(a, i); break;
+    case 5: prolong_one<NIN, 1, 0, 1, TK>(a, i); break;
+    case 6: prolong_one<NIN, 0, 1, 1, TK>(a, i); break;
+    default: prolong_one<NIN, 1, 1, 1, TK>(a, i); break;
   }
 }
 
@@ -473,7 +516,7 @@ __device__ __forceinline__ double brick_tap(const double* src, int st, bool odd)
   return r;
 }
 
-template <int NIN, typename TK, typename TO>
+template <int NIN, typename TK>
 __global__ __launch_bounds__(256) void k_prolong_bricks(BrickArgs a) {
   __shared__ double V[kBrickC * kBrickC * kBrickC];     // [cz][cy][cx]
   __shared__ double PX[kBrickC * kBrickC * kBrick];     // [cz][cy][fx]
@@ -598,7 +641,8 @@ __global__ __launch_bounds__(256) void k_prolong_bricks(BrickArgs a) {
       if (!zw[e]) continue;
       const int64_t d = dst[e] + v * a.ovstride;
       for (int o = 0; o < a.nout; ++o)
-        static_cast<TO*>(a.out[o])[d] = (TO)prolong_combine<NIN>(Pv[e], a.w[o], a.H);
+        store_out(a.out[o], d, (a.f32_mask >> o) & 1,
+                  prolong_combine<NIN>(Pv[e], a.w[o], a.H, (a.inc_mask >> o) & 1));
     }
 #pragma unroll
     for (int m = 0; m < NIN; ++m)
@@ -733,54 +777,182 @@ __global__ __launch_bounds__(256) void k_scatter(const int64_t* idx, int64_t n, 
   if (i < n) dst[idx[i]] = (T)src[i];
 }
 
+// Stage value from a stage-1 table (FP64) and an increment table (FP32).
+__global__ __launch_bounds__(256) void k_gather_sum(const int64_t* idx, int64_t n, const double* base,
+                                                    const float* inc, double* dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = base[idx[i]] + (double)inc[idx[i]];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_value(const int64_t* idx, int64_t n, T v, T* dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[idx[i]] = v;
+}
+
 __global__ __launch_bounds__(256) void k_to_f32(const double* src, float* dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = (float)src[i];
 }
 
+// Closed-form initial data.  Kinds (parameters in InitArgs::p):
+//  1 standing wave  u = A sin(m_x pi x) sin(m_y pi y) sin(m_z pi z), Pi = 0; p = (A, m_x, m_y, m_z)
+//  2 Gaussian pulses u = sum_p A_p g_p(x) g_p(y) g_p(z), Pi = 0, with
+//    g_p(x) = sum_{k=-K..K} exp(-(x - c_{p,x} - k L)^2 / w_p^2) (K = 1 if the
+//    period L > 0, else 0); p = (npulses, L, then A, w, c_x, c_y, c_z per pulse)
+//  3 Brill-Lindquist punctures (22 Z4c variables): psi = 1 + a,
+//    a = m_+ / (2 r_+) + m_- / (2 r_-), W = psi^-2, gt = delta, lapse
+//    (1 + (1 - a) / (1 + a)) / 2, the rest 0; p = (m_+, m_-, x_+, x_-) with the
+//    punctures at (x_+, 0, 0) and (x_-, 0, 0)
+//  4 outgoing spherical Gaussian u = (f(t - r) - f(t + r)) / r, Pi = du/dt,
+//    f(v) = A exp(-v^2 / (2 sigma^2)), limits at r = 0; p = (A, sigma, t)
+__device__ __forceinline__ double periodised_gauss(double x, double c, double w, double L) {
+  if (L <= 0.0) {
+    const double d = x - c;
+    return exp(-(d * d) / (w * w));
+  }
+  double g = 0.0;
+  for (int k = -1; k <= 1; ++k) {
+    const double d = (x - c) - k * L;
+    g += exp(-(d * d) / (w * w));
+  }
+  return g;
+}
+
+__device__ double init_value(const InitArgs& a, double x, double y, double z, int v) {
+  const double* p = a.p;
+  switch (a.kind) {
+    case 1: {
+      if (v != 0) return 0.0;
+      const double fx = p[0] * sin(p[1] * M_PI * x);
+      return (sin(p[3] * M_PI * z) * sin(p[2] * M_PI * y)) * fx;
+    }
+    case 2: {
+      if (v != 0) return 0.0;
+      const int np = (int)p[0];
+      double u = 0.0;
+      for (int q = 0; q < np; ++q) {
+        const double* c = p + 2 + 5 * q;
+        const double gx = c[0] * periodised_gauss(x, c[2], c[1], p[1]);
+        u += (periodised_gauss(z, c[4], c[1], p[1]) * periodised_gauss(y, c[3], c[1], p[1])) * gx;
+      }
+      return u;
+    }
+    case 3: {
+      const double dp = x - p[2], dm = x - p[3];
+      const double rp = sqrt(dp * dp + y * y + z * z), rm = sqrt(dm * dm + y * y + z * z);
+      const double s = p[0] / (2.0 * rp) + p[1] / (2.0 * rm);
+      const double psi = 1.0 + s;
+      if (v == 0) return 1.0 / (psi * psi);
+      if (v == 1 || v == 4 || v == 6) return 1.0;
+      if (v == 18) return 0.5 * (1.0 + (1.0 - s) / (1.0 + s));
+      return 0.0;
+    }
+    case 4: {
+      const double A = p[0], s2 = p[1] * p[1], t = p[2];
+      const double r = sqrt(x * x + y * y + z * z);
+      auto f = [&](double q) { return A * exp(-q * q / (2.0 * s2)); };
+      if (r < 1e-9) {
+        const double ft = f(t);
+        return v == 0 ? 2.0 * t / s2 * ft : 2.0 * ft * (1.0 - t * t / s2) / s2;
+      }
+      if (v == 0) return (f(t - r) - f(t + r)) / r;
+      return -(f(t - r) * (t - r) - f(t + r) * (t + r)) / (s2 * r);
+    }
+    default:
+      return 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_init(InitArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  int64_t off;
+  int gi[3];
+  if (!a.idx) {   // owned point i of the member, canonical order
+    int b = 0;
+    while (b + 1 < a.nboxes && a.prefix[b + 1] <= i) ++b;
+    const BoxDev B = a.boxes[b];
+    const int64_t l = i - a.prefix[b];
+    const int lx = (int)(l % B.nx), ly = (int)((l / B.nx) % B.ny);
+    const int lz = (int)(l / ((int64_t)B.nx * B.ny));
+    off = padded_offset(B, lx, ly, lz);
+    gi[0] = B.lo[0] + lx, gi[1] = B.lo[1] + ly, gi[2] = B.lo[2] + lz;
+  } else {        // a halo point given by its level-array offset
+    off = a.idx[i];
+    int b = 0;
+    while (b + 1 < a.nboxes && a.boxes[b + 1].base <= off) ++b;
+    const BoxDev B = a.boxes[b];
+    const int64_t r = off - B.base;
+    gi[0] = B.lo[0] + (int)(r % B.px) - B.pad;
+    gi[1] = B.lo[1] + (int)((r / B.px) % B.py) - B.pad;
+    gi[2] = B.lo[2] + (int)(r / ((int64_t)B.px * B.py)) - B.pad;
+  }
+  const double x = a.origin[0] + gi[0] * a.dx, y = a.origin[1] + gi[1] * a.dx,
+               z = a.origin[2] + gi[2] * a.dx;
+  if (a.idx) {
+    a.out[i] = init_value(a, x, y, z, a.var);
+    return;
+  }
+  for (int v = 0; v < a.nvars; ++v) {
+    const double val = init_value(a, x, y, z, v);
+    a.out[off + v * a.vstride] = val;
+    if (a.out32) a.out32[off + v * a.vstride] = (float)val;
+  }
+}
+
 inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-template <typename TS, int DEPTH, int S, int NT, int R>
+// FP64: every stage <double, double>.  Mixed: stage 1 <double, float> (k1 =
+// f(y_n) in FP64, stored FP32), stages 2-4 <float, float> (increment form).
+template <bool MIXED, int DEPTH, int S, int NT, int R>
 void stage_dispatch(const StageArgs& a, dim3 g, hipStream_t s) {
+  using TS = typename std::conditional<MIXED, float, double>::type;
+  using TK = TS;
   const dim3 b(NT);
   switch (a.stage) {
-    case 1: hipLaunchKernelGGL((k_wave_stage<1, TS, DEPTH, S, true, NT, R>), g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_wave_stage<2, TS, DEPTH, S, true, NT, R>), g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_wave_stage<3, TS, DEPTH, S, true, NT, R>), g, b, 0, s, a); break;
+    case 1:
+      if constexpr (MIXED)
+        hipLaunchKernelGGL((k_wave_stage<1, double, float, DEPTH, S, true, NT, R>), g, b, 0, s, a);
+      else
+        hipLaunchKernelGGL((k_wave_stage<1, double, double, DEPTH, S, true, NT, R>), g, b, 0, s, a);
+      break;
+    case 2: hipLaunchKernelGGL((k_wave_stage<2, TS, TK, DEPTH, S, true, NT, R>), g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_wave_stage<3, TS, TK, DEPTH, S, true, NT, R>), g, b, 0, s, a); break;
     default:
-      if (a.write_k) hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, true, NT, R>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_wave_stage<4, TS, DEPTH, S, false, NT, R>), g, b, 0, s, a);
+      if (a.write_k) hipLaunchKernelGGL((k_wave_stage<4, TS, TK, DEPTH, S, true, NT, R>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_wave_stage<4, TS, TK, DEPTH, S, false, NT, R>), g, b, 0, s, a);
       break;
   }
 }
 
 // (threads, points per thread, planes in flight): (256, 2, 1), (256, 2, 2),
 // (256, 1, 2), (512, 2, 1), (512, 2, 2)
-template <typename TS, int R>
+template <bool MIXED, int R>
 void stage_variant(const StageArgs& a, dim3 g, int depth, int slots, int threads, hipStream_t s) {
   if (threads == 512) {
-    if (depth == 2) stage_dispatch<TS, 2, 2, 512, R>(a, g, s);
-    else stage_dispatch<TS, 1, 2, 512, R>(a, g, s);
+    if (depth == 2) stage_dispatch<MIXED, 2, 2, 512, R>(a, g, s);
+    else stage_dispatch<MIXED, 1, 2, 512, R>(a, g, s);
   } else if (slots == 1) {
-    stage_dispatch<TS, 2, 1, 256, R>(a, g, s);
+    stage_dispatch<MIXED, 2, 1, 256, R>(a, g, s);
   } else {
-    if (depth == 2) stage_dispatch<TS, 2, 2, 256, R>(a, g, s);
-    else stage_dispatch<TS, 1, 2, 256, R>(a, g, s);
+    if (depth == 2) stage_dispatch<MIXED, 2, 2, 256, R>(a, g, s);
+    else stage_dispatch<MIXED, 1, 2, 256, R>(a, g, s);
   }
 }
 
 }  // namespace
 
-hipError_t launch_stage(const StageArgs& a, int grid, bool f32, int depth, int slots, int threads,
+hipError_t launch_stage(const StageArgs& a, int grid, bool mixed, int depth, int slots, int threads,
                         hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g(grid > 0 ? grid : a.ntiles);
   if (a.radius == 4) {   // eighth order: FP64 only
-    if (f32) return hipErrorInvalidValue;
-    stage_variant<double, 4>(a, g, depth, slots, threads, s);
+    if (mixed) return hipErrorInvalidValue;
+    stage_variant<false, 4>(a, g, depth, slots, threads, s);
   } else if (a.radius == 3) {
-    if (f32) stage_variant<float, 3>(a, g, depth, slots, threads, s);
-    else stage_variant<double, 3>(a, g, depth, slots, threads, s);
+    if (mixed) stage_variant<true, 3>(a, g, depth, slots, threads, s);
+    else stage_variant<false, 3>(a, g, depth, slots, threads, s);
   } else {
     return hipErrorInvalidValue;
   }
@@ -794,36 +966,31 @@ hipError_t launch_sync(const SyncArgs& a, bool f32, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, bool out_f32, hipStream_t s, int nin) {
+hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, hipStream_t s, int nin) {
   if (a.n <= 0) return hipSuccess;
   const dim3 g(a.blk_start[8]), b(256);
   if (nin != 5) {   // buffer zones: FP64 state vectors only
-    if (k_f32 || out_f32 || (nin != 1 && nin != 3)) return hipErrorInvalidValue;
-    if (nin == 1) hipLaunchKernelGGL((k_prolong<1, double, double>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_prolong<3, double, double>), g, b, 0, s, a);
+    if (k_f32 || a.f32_mask || a.inc_mask || (nin != 1 && nin != 3)) return hipErrorInvalidValue;
+    if (nin == 1) hipLaunchKernelGGL((k_prolong<1, double>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_prolong<3, double>), g, b, 0, s, a);
     return hipGetLastError();
   }
-  if (!k_f32 && !out_f32) hipLaunchKernelGGL((k_prolong<5, double, double>), g, b, 0, s, a);
-  else if (k_f32 && out_f32) hipLaunchKernelGGL((k_prolong<5, float, float>), g, b, 0, s, a);
-  else if (k_f32) hipLaunchKernelGGL((k_prolong<5, float, double>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_prolong<5, double, float>), g, b, 0, s, a);
+  if (k_f32) hipLaunchKernelGGL((k_prolong<5, float>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_prolong<5, double>), g, b, 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, bool out_f32, hipStream_t s,
-                                 int nin) {
+hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, hipStream_t s, int nin) {
   if (a.nbricks <= 0) return hipSuccess;
   const dim3 g((unsigned)((a.nbricks + 7) / 8 * 8)), b(256);   // whole XCD rounds; extra groups exit
   if (nin != 5) {   // buffer zones: FP64 state vectors only
-    if (k_f32 || out_f32 || (nin != 1 && nin != 3)) return hipErrorInvalidValue;
-    if (nin == 1) hipLaunchKernelGGL((k_prolong_bricks<1, double, double>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_prolong_bricks<3, double, double>), g, b, 0, s, a);
+    if (k_f32 || a.f32_mask || a.inc_mask || (nin != 1 && nin != 3)) return hipErrorInvalidValue;
+    if (nin == 1) hipLaunchKernelGGL((k_prolong_bricks<1, double>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_prolong_bricks<3, double>), g, b, 0, s, a);
     return hipGetLastError();
   }
-  if (!k_f32 && !out_f32) hipLaunchKernelGGL((k_prolong_bricks<5, double, double>), g, b, 0, s, a);
-  else if (k_f32 && out_f32) hipLaunchKernelGGL((k_prolong_bricks<5, float, float>), g, b, 0, s, a);
-  else if (k_f32) hipLaunchKernelGGL((k_prolong_bricks<5, float, double>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_prolong_bricks<5, double, float>), g, b, 0, s, a);
+  if (k_f32) hipLaunchKernelGGL((k_prolong_bricks<5, float>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_prolong_bricks<5, double>), g, b, 0, s, a);
   return hipGetLastError();
 }
 
@@ -882,6 +1049,31 @@ hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, void
   else
     hipLaunchKernelGGL(k_scatter<double>, dim3(blocks_for(n)), dim3(256), 0, s, idx, n, src,
                        static_cast<double*>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_sum(const int64_t* idx, int64_t n, const double* base, const float* inc,
+                             double* dst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_sum, dim3(blocks_for(n)), dim3(256), 0, s, idx, n, base, inc, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_value(const int64_t* idx, int64_t n, double v, void* dst, bool f32,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_scatter_value<float>, dim3(blocks_for(n)), dim3(256), 0, s, idx, n,
+                       (float)v, static_cast<float*>(dst));
+  else
+    hipLaunchKernelGGL(k_scatter_value<double>, dim3(blocks_for(n)), dim3(256), 0, s, idx, n, v,
+                       static_cast<double*>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const InitArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init, dim3(blocks_for(a.n)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

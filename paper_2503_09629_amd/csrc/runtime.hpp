@@ -28,6 +28,7 @@ struct TileShape {
 constexpr int kTuneTz[] = {4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 18, 20,
                            24, 28, 32, 40, 48, 64, 1 << 20};
 constexpr int kTuneTzMin = 4;
+constexpr int kZ4cTzMin = 2;   // Z4c contexts cut two-plane tiles by default
 
 struct LevelDev {
   int nb_member = 0;                 // boxes per member
@@ -56,15 +57,18 @@ struct LevelDev {
   int nyh = 1;
   bool has_child = false;
   // arena offsets (bytes)
-  size_t o_y[3], o_y32[2], o_k[4], o_yh[8], o_boxes, o_prefix, o_sync, o_prolong, o_rblist,
-      o_rbfirst, o_phys, o_restr, o_tiles, o_btiles, o_ys, o_bricks;
+  size_t o_y[3], o_y32[2], o_k[4], o_yh[8], o_yd[2], o_boxes, o_prefix, o_sync, o_prolong,
+      o_rblist, o_rbfirst, o_phys, o_restr, o_tiles, o_btiles, o_ys, o_bricks;
   // device pointers after binding.  y: FP64 state; y32: its FP32 shadow
-  // (mixed mode only); k and Yh hold the stencil type (FP64, or FP32 in
-  // mixed mode).
+  // (Z4c mixed mode only); k and Yh hold the slope type (FP64, or FP32 in
+  // mixed mode); Yd: FP64 stage-1 halo tables of the mixed wave (one per
+  // substep; its Yh tables of stages 2-4 hold FP32 stage increments).
   double* y[3] = {nullptr, nullptr, nullptr};
   float* y32[2] = {nullptr, nullptr};
   void* k[4] = {nullptr, nullptr, nullptr, nullptr};
   void* Yh[8] = {nullptr};
+  double* Yd[2] = {nullptr, nullptr};
+  int nyd = 0;
   double* Ys = nullptr;              // Z4c: materialised stage vector
   BoxDev* d_boxes = nullptr;
   int64_t* d_prefix = nullptr;
@@ -97,6 +101,7 @@ struct sc_ctx {
   int G = 3;            // ghost layers (3: fourth-order stencils; 4: eighth-order wave)
   int fd_order = 4;     // wave Laplacian order (4 or 8)
   bool mixed = false;   // SC_MIXED: FP32 stencil operands
+  bool wave_mixed = false;   // SC_MIXED with the wave: FP64 k1, FP32 stage increments
   size_t esz = 8;       // bytes per element of k and Yh arrays
   size_t arena_bytes = 0;
   size_t o_stage = 0, o_partials = 0, o_norm_out = 0;
@@ -109,7 +114,9 @@ struct sc_ctx {
   int64_t launches = 0;
   hipGraphExec_t graph[3] = {nullptr, nullptr, nullptr};   // one per level-0 buffer index
   bool graph_ready[3] = {false, false, false};
-  double weights[2][5][4];  // [substep][fill-1][i]
+  std::vector<int> graph_cur[3];   // every level's buffer index when each graph was captured
+  double weights[2][5][4];      // [substep][fill-1][i]
+  double weights_inc[2][5][4];  // the same minus the substep's Y1 weights (stage increments)
   // stage-kernel timing with HIP events (eager modes)
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;

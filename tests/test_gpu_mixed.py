@@ -1,20 +1,28 @@
-"""Mixed precision (FP32-shadow stencil, FP64 state/RK4/dense output/prolongation/
-restriction) against the FP64 GPU path, which is itself bitwise equal to the
-CPU reference.
+"""Mixed precision against the FP64 GPU path, which is itself bitwise equal
+to the CPU reference.
 
-Parity is bounded, not exact.  Rounding a stage vector to FP32 perturbs it by
-at most eps32 |u| (eps32 = 2^-24); the fourth-order Laplacian amplifies a
-perturbation by at most 64/(12 h^2) per dimension (sum of |coefficients| over
-12 h^2), i.e. 16 eps32 |u| / h^2 for three dimensions, and the FP32 rounding
-of the stencil sums adds at most as much again, so the slope of Pi carries an
-error below 32 eps32 max|u| / h^2 per evaluation (the dissipation terms are
-O(1/h) and smaller).  RK4 integrates it over time t with weights summing to
-one per step, giving the per-level model bound
-    |Pi_mixed - Pi_fp64| <= t * 32 eps32 max|u| / h^2
-(u picks up at most t times that).  Restriction copies finer-level values
-into the coarser levels, so a level's error is bounded by the finest spacing
-in the hierarchy, h = dx of the finest level.  The tests check the measured
-error against that bound and that fourth-order convergence is kept.
+The mixed wave path evaluates k1 = f(y_n) in FP64 and, since the wave
+right-hand side f is linear, k_s = k1 + f(e_s) for s = 2..4 with the stage
+increment e_s = c_s dt k_{s-1} in FP32; slopes are stored in FP32 and the
+RK4 combination, dense output, prolongation and restriction stay FP64.
+
+Error model.  Rounding e_s to FP32 perturbs it by at most eps32 c_s dt |Pi|
+(e_u = c_s dt k_u with k_u ~ Pi); the fourth-order Laplacian amplifies a
+perturbation by at most 16/h^2 (three dimensions, sum of |coefficients| over
+12 h^2), and the FP32 stencil sums add at most as much again, so stage s
+changes k_Pi by at most 32 eps32 c_s dt max|Pi| / h^2.  RK4 weights these
+slopes by dt/6 (2, 2, 1) with c = (1/2, 1/2, 1), so one step changes Pi by at
+most 16 (dt/h)^2 eps32 max|Pi| = eps32 max|Pi| (dt = h/4): the injection per
+step does not depend on h.  Over N steps this gives the strict bound
+N eps32 max|Pi|.  The roundings are independent from step to step and the
+dissipation removes the grid-scale part, so the accumulated error grows like
+a random walk instead; the tests check the model
+    B_Pi = sqrt(N) eps32 max|Pi| / 2,   B_u = t B_Pi
+with N the steps of the finest level (restriction carries its error to every
+coarser level), t the elapsed time, and u the time integral of Pi's error.
+The measured errors sit within about 2-15x (Pi) and 8-40x (u) of it at every
+size tested, so an FP32 path that regressed to rounding y_n itself (an
+error 1/h times larger) fails it.
 """
 import numpy as np
 import pytest
@@ -24,6 +32,13 @@ from workloads import config_c2, config_c3, gaussian_on_spec, pulses_on_spec
 
 pytestmark = pytest.mark.gpu
 EPS32 = 2.0 ** -24
+
+
+def mixed_bounds(spec, ncoarse, t, pi_max):
+    """(B_u, B_Pi) of the error model above."""
+    n = ncoarse * (1 << (spec.nlevels - 1))
+    b_pi = 0.5 * np.sqrt(n) * EPS32 * pi_max
+    return t * b_pi, b_pi
 
 
 def _run(spec, precision, ncoarse, data_fn, **kw):
@@ -40,19 +55,20 @@ def _run(spec, precision, ncoarse, data_fn, **kw):
     return out, t
 
 
-@pytest.mark.parametrize("spec,ncoarse", [(config_c2(32), 8), (config_c3(64, nlev=4), 2)])
+@pytest.mark.parametrize("spec,ncoarse", [(config_c2(32), 8), (config_c3(64, nlev=4), 2),
+                                          (config_c3(64, nlev=4), 8)])
 def test_mixed_error_within_bound(spec, ncoarse):
     data = pulses_on_spec if spec.nlevels > 2 else gaussian_on_spec
     a, t = _run(spec, sc.SC_FP64, ncoarse, data)
     b, _ = _run(spec, sc.SC_MIXED, ncoarse, data)
+    pi_max = max(np.abs(a[l][1]).max() for l in range(spec.nlevels))
+    bounds = mixed_bounds(spec, ncoarse, t, pi_max)
     for l in range(spec.nlevels):
-        umax = np.abs(a[l][0]).max()
-        h = spec.dx(spec.nlevels - 1)
-        bound = t * 32 * EPS32 * umax / (h * h)
         for v in range(2):
             err = np.abs(a[l][v] - b[l][v]).max()
-            print(f"level {l} var {v}: |mixed - fp64| = {err:.3e}, bound {bound:.3e}")
-            assert err <= bound, (l, v, err, bound)
+            print(f"level {l} var {v}: |mixed - fp64| = {err:.3e}, bound {bounds[v]:.3e} "
+                  f"(ratio {err / bounds[v]:.3f})")
+            assert err <= bounds[v], (l, v, err, bounds[v])
             assert err > 0  # the FP32 path really ran
 
 

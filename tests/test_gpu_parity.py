@@ -333,3 +333,38 @@ def test_buffer_zones_match_reference(exec):
     with pytest.raises(sc.ScError) as e:
         ctx.step_level(1, 0)
     assert e.value.code == sc.SC_E_STATE
+
+
+def test_graph_recaptured_after_single_level_steps():
+    """A graph bakes in every level's state buffer; a level stepped on its own
+    (sc_step_level) in between must not replay a stale graph.  The same call
+    sequence in graph and batched mode gives the same bits."""
+    spec = config_c2(16)
+    outs = []
+    for mode in (sc.SC_EXEC_GRAPH, sc.SC_EXEC_BATCHED):
+        ctx = _gpu(spec, exec=mode, min_block=4, max_block=9)
+        for l in range(spec.nlevels):
+            for v, f in enumerate(gaussian_on_spec(spec, l)):
+                ctx.set_initial_data(0, l, v, f)
+        ctx.advance(2)
+        ctx.prolongate(1)
+        ctx.step_level(1, 0)     # one step: level 1's state buffer index flips
+        ctx.advance(3)
+        outs.append([ctx.read_back(0, l, v) for l in range(spec.nlevels) for v in range(2)])
+        ctx.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_close_right_after_advance_waits_for_the_stream():
+    """close() returns only when the context's queued kernels are done, so the
+    arena can go back to the allocator at once."""
+    spec = config_c3(32, nlev=3)
+    ctx = _gpu(spec, exec=sc.SC_EXEC_BATCHED)
+    for l in range(spec.nlevels):
+        for v, f in enumerate(pulses_on_spec(spec, l)):
+            ctx.set_initial_data(0, l, v, f)
+    stream = ctx.stream
+    ctx.advance(20)
+    ctx.close()
+    assert stream.query()

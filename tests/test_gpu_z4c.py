@@ -186,3 +186,24 @@ def test_z4c_eighth_order_matches_reference(exec, bc):
         for l in range(spec.nlevels):
             a, b = ctx.hamiltonian(0, l), ref.hamiltonian(l)
             assert np.abs(a - b).max() / np.abs(b).max() <= 1e-10
+
+
+def test_z4c_tile_shape_can_be_set_back():
+    """The shape sc_tile_shape reports for a Z4c level can be pinned again with
+    sc_set_tile_shape (two-plane z-chunks), and a pinned cut gives the same bits."""
+    spec = config_z4c_small()
+    a, _ = _pair(spec)
+    b, _ = _pair(spec)
+    for l in range(spec.nlevels):
+        sh = b.tile_shape(l)
+        b.set_tile_shape(l, sh["tz"], sh["grid"], sh["depth"], sh["slots"], sh["threads"])
+        assert b.tile_shape(l) == sh
+    b.set_tile_shape(1, 3)
+    assert b.tile_shape(1)["tz"] == 3
+    a.advance(1)
+    b.advance(1)
+    for l in range(spec.nlevels):
+        for v in range(22):
+            assert np.array_equal(a.read_back(0, l, v), b.read_back(0, l, v)), (l, v)
+    a.close()
+    b.close()
