@@ -44,7 +44,7 @@ typedef enum {
   SC_E_NEST = -3,      /* hierarchy not properly nested or not aligned */
   SC_E_MEM = -4,       /* bound arena too small or misaligned */
   SC_E_HIP = -5,       /* a HIP runtime call failed; the message names it */
-  SC_E_NONFINITE = -6  /* sc_check_finite found a NaN or infinity */
+  SC_E_NONFINITE = -6  /* a NaN or infinity in the state (sc_check_finite, sc_advance) */
 } sc_status;
 
 /* Right-hand sides.  SC_RHS_WAVE: the scalar wave as a first-order system,
@@ -275,7 +275,10 @@ int sc_set_phys_data(sc_ctx* ctx, int32_t member, int32_t level, int32_t var,
  * subcycling schedule (Sec. II, steps 1-7): a level takes one RK4 step,
  * prolongs (y_n, k1..k4) to its child's refinement boundary, the child takes
  * two steps at theta0 = 0 and 1/2, and the child's solution is restricted by
- * injection.  Asynchronous. */
+ * injection.  Asynchronous.  Every RK4 step flags a non-finite y_{n+1} on the
+ * device; the flag is copied back after the steps without a wait, and a later
+ * sc_advance that finds it set (once the copy has arrived) returns
+ * SC_E_NONFINITE and enqueues nothing.  New initial data clear the flag. */
 int sc_advance(sc_ctx* ctx, int32_t ncoarse);
 
 /* The pieces of sc_advance, for callers that drive the schedule themselves:
@@ -317,6 +320,30 @@ int sc_read_rb(sc_ctx* ctx, int32_t member, int32_t level, int32_t which, int32_
 int sc_norms(sc_ctx* ctx, int32_t member, int32_t level, int32_t var, int32_t array,
              double out[3]);
 
+/* Error of the state against a closed-form solution at time t, over the owned
+ * points of one level of one member, for one variable: out[0] = max |y - exact|,
+ * out[1] = sqrt(mean (y - exact)^2), out[2] = number of non-finite state
+ * values (host, caller-owned).  The error norms of the paper's scalar-wave
+ * test (Sec. IV.A, Fig. 2) are of this kind.  kind and params as in
+ * sc_set_initial_data_analytic at time t: SC_ID_STANDING_WAVE with
+ * (A, m_x, m_y, m_z, t) (u = A cos(w t) S, Pi = -A w sin(w t) S,
+ * w = pi |m|) or SC_ID_SPHERICAL_GAUSSIAN with (A, sigma, t); wave only.
+ * The same deterministic reduction as sc_norms.  Synchronises. */
+int sc_error_norms(sc_ctx* ctx, int32_t member, int32_t level, int32_t var, int32_t kind,
+                   const double* params, int32_t nparams, double out[3]);
+
+/* Z4c only: the composite-grid L2 norm of the Hamiltonian constraint that the
+ * paper monitors (Sec. IV.B), over the points with r < rmax (distance from
+ * the coordinate origin) where the lapse exceeds alpha_min (outside the
+ * horizons), each point counted once on the finest level that has it, with
+ * weight dx_l^3: out[0] = sqrt(sum w H^2 / sum w), out[1] = max |H| over
+ * those points, out[2] = non-finite H values there (host, caller-owned).  H
+ * as in sc_hamiltonian, reduced on the GPU level by level (deterministic
+ * order).  Fills the state's ghosts; call it between coarse steps, after the
+ * first.  Synchronises. */
+int sc_constraint_norm(sc_ctx* ctx, int32_t member, double rmax, double alpha_min,
+                       double out[3]);
+
 /* Z4c only: Hamiltonian constraint H = R + 2/3 (Khat + 2 Theta)^2 - At_ij At^ij
  * (vacuum) of the current state on the owned points of a level of a member,
  * canonical order, n = owned points.  Fills the state's ghosts first (SYNC,
@@ -324,7 +351,8 @@ int sc_norms(sc_ctx* ctx, int32_t member, int32_t level, int32_t var, int32_t ar
  * refinement boundaries), so call it between coarse steps.  Synchronises. */
 int sc_hamiltonian(sc_ctx* ctx, int32_t member, int32_t level, double* host, int64_t n);
 
-/* SC_E_NONFINITE if any owned value of the state is not finite on any level. */
+/* SC_E_NONFINITE if any owned value of the state is not finite on any level
+ * (a full scan, which names the level, member and variable).  Synchronises. */
 int sc_check_finite(sc_ctx* ctx);
 
 /* Simulation time of a level (host bookkeeping). */

@@ -30,7 +30,7 @@ EXPORTED = [
     "sc_config_default", "sc_create", "sc_destroy", "sc_last_error", "sc_build_hierarchy",
     "sc_get_counts", "sc_buffer_count", "sc_export_maps", "sc_device_bytes", "sc_bind_device_memory",
     "sc_set_initial_data", "sc_set_initial_data_analytic", "sc_phys_count", "sc_phys_points", "sc_set_phys_data",
-    "sc_hamiltonian", "sc_advance", "sc_step_level", "sc_prolongate", "sc_fill_ghosts",
+    "sc_hamiltonian", "sc_error_norms", "sc_constraint_norm", "sc_advance", "sc_step_level", "sc_prolongate", "sc_fill_ghosts",
     "sc_restrict", "sc_read_back", "sc_read_rb", "sc_norms", "sc_check_finite",
     "sc_level_time", "sc_set_exec", "sc_poison_halos", "sc_autotune", "sc_tile_shape",
     "sc_set_tile_shape", "sc_profile_enable",
@@ -92,6 +92,8 @@ def lib():
             "sc_phys_points": [P, i32, P, i64],
             "sc_set_phys_data": [P, i32, i32, i32, P, i64],
             "sc_hamiltonian": [P, i32, i32, P, i64],
+            "sc_error_norms": [P, i32, i32, i32, i32, P, i32, P],
+            "sc_constraint_norm": [P, i32, f64, f64, P],
             "sc_advance": [P, i32],
             "sc_step_level": [P, i32, i32],
             "sc_prolongate": [P, i32],
@@ -296,6 +298,21 @@ class Context:
     def norms(self, member: int, level: int, var: int, array: int = SC_ARR_Y):
         out = np.empty(3)
         self._check(self.L.sc_norms(self.ctx, member, level, var, array, _p(out)))
+        return out
+
+    def error_norms(self, member: int, level: int, var: int, kind: int, params):
+        """(max |y - exact|, rms, non-finite count) against a closed form at time t."""
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        out = np.empty(3)
+        self._check(self.L.sc_error_norms(self.ctx, member, level, var, kind, _p(p), int(p.size),
+                                          _p(out)))
+        return out
+
+    def constraint_norm(self, member: int = 0, rmax: float = 30.0, alpha_min: float = 0.3):
+        """(composite L2 of H over r < rmax, alpha > alpha_min; max |H| there; non-finite count)."""
+        out = np.empty(3)
+        self._check(self.L.sc_constraint_norm(self.ctx, member, float(rmax), float(alpha_min),
+                                              _p(out)))
         return out
 
     # -- evolution ----------------------------------------------------------------

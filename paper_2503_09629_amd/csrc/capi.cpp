@@ -689,8 +689,10 @@ void plan_arena(sc_ctx* c) {
   }
   c->stage_elems = std::max<int64_t>(maxowned, 1);
   c->o_stage = take(sizeof(double) * (size_t)c->stage_elems);
-  c->o_partials = take(sizeof(double) * 3 * 256);
+  c->norm_parts_max = norm_parts(maxowned);
+  c->o_partials = take(sizeof(double) * 4 * (size_t)c->norm_parts_max);
   c->o_norm_out = take(sizeof(double) * 4);
+  c->o_flag = take(sizeof(unsigned int));
   c->arena_bytes = off;
 }
 
@@ -755,6 +757,7 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
   a.radius = L.shape.radius;
   a.clap = a.radius == 4 ? 1.0 / (5040.0 * L.dx * L.dx) : 1.0 / (12.0 * L.dx * L.dx);
   a.cko = c->cfg.ko_sigma / (64.0 * L.dx);
+  a.nonfinite = c->d_nonfinite;
   // k4 is read only by the prolongation into a finer level
   a.write_k = (stage < 4 || L.has_child) ? 1 : 0;
   if (!per_block) {
@@ -811,6 +814,7 @@ Z4cArgs z4c_args(sc_ctx* c, int l) {
   a.eta_s = c->cfg.z4c_eta_s;
   for (int d = 0; d < 3; ++d) a.origin[d] = c->hier.geo.origin[d];
   a.ord = c->fd_order;
+  a.nonfinite = c->d_nonfinite;
   return a;
 }
 
@@ -1176,6 +1180,27 @@ void* array_ptr(sc_ctx* c, int l, int array, int var, bool* f32) {
 
 int scatter_phys(sc_ctx* c, int member, int level, int var);
 
+// One deterministic reduction (NormArgs) with the given partials and output
+// buffers; r = {max, sum, weight sum, non-finite count}.  Synchronises.
+int reduce(sc_ctx* c, const NormArgs& a, bool f32, double* partials, double* dout, double r[4]) {
+  HIPCHK(c, launch_norms(a, f32, partials, dout, c->stream));
+  HIPCHK(c, hipMemcpyAsync(r, dout, sizeof(double) * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SC_OK;
+}
+
+int hamiltonian_into_scratch(sc_ctx* c, int level);
+
+// New data: clear the device flag of non-finite state values and its host copy
+// (a fill kernel, not a memset, so the call may sit in captured work).
+int reset_nonfinite(sc_ctx* c) {
+  HIPCHK(c, launch_fill_u32(c->d_nonfinite, 1, 0u, c->stream));
+  if (c->flag_pending) HIPCHK(c, hipEventSynchronize(c->flag_ev));
+  c->flag_pending = false;
+  *c->h_flag = 0;
+  return SC_OK;
+}
+
 PackArgs member_pack(sc_ctx* c, int member, int l, void* arr) {
   LevelDev& L = c->lev[l];
   PackArgs a{};
@@ -1435,6 +1460,10 @@ int sc_bind_device_memory(sc_ctx* c, void* dptr, size_t nbytes) {
   c->d_stage = at<double>(c, c->o_stage);
   c->d_partials = at<double>(c, c->o_partials);
   c->d_norm_out = at<double>(c, c->o_norm_out);
+  c->d_nonfinite = at<unsigned int>(c, c->o_flag);   // zeroed with the arena
+  if (!c->h_flag) HIPCHK(c, hipHostMalloc((void**)&c->h_flag, sizeof(unsigned int)));
+  *c->h_flag = 0;
+  if (!c->flag_ev) HIPCHK(c, hipEventCreateWithFlags(&c->flag_ev, hipEventDisableTiming));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->state = 2;
   return SC_OK;
@@ -1456,6 +1485,8 @@ int sc_set_initial_data(sc_ctx* c, int32_t member, int32_t level, int32_t var,
   if (c->mixed && !c->wave_mixed)
     HIPCHK(c, launch_to_f32(L.y[L.cur] + var * L.total, L.y32[L.cur] + var * L.total, L.total,
                             c->stream));
+  rc = reset_nonfinite(c);
+  if (rc) return rc;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->state = 3;
   return SC_OK;
@@ -1473,18 +1504,22 @@ int sc_set_initial_data_analytic(sc_ctx* c, int32_t kind, const double* params, 
   switch (kind) {
     case SC_ID_STANDING_WAVE:
       if (!wave) return fail(c, SC_E_ARG, "a standing wave is wave-equation data");
-      if (nparams == 4) {
-        for (auto& p : P) p.assign(params, params + 4);
+      if (nparams == 4 || nparams == 5) {
+        for (auto& p : P) {
+          p.assign(params, params + nparams);
+          p.resize(5, 0.0);
+        }
       } else if (nparams == 0) {   // ensemble: modes {1,2,3}^3 and amplitude U(0.5, 1.5)
         SplitMix64 rng(seed);
         for (auto& p : P) {
           double m[3];
           for (int d = 0; d < 3; ++d) m[d] = (double)(1 + rng.next() % 3);
           const double amp = 0.5 + rng.uniform();
-          p = {amp, m[0], m[1], m[2]};
+          p = {amp, m[0], m[1], m[2], 0.0};
         }
       } else {
-        return fail(c, SC_E_ARG, "standing wave: 4 parameters (A, m_x, m_y, m_z) or 0 (seeded)");
+        return fail(c, SC_E_ARG, "standing wave: 4 or 5 parameters (A, m_x, m_y, m_z[, t]) or 0 "
+                                 "(seeded)");
       }
       break;
     case SC_ID_GAUSSIAN_PULSES: {
@@ -1563,6 +1598,8 @@ int sc_set_initial_data_analytic(sc_ctx* c, int32_t kind, const double* params, 
       }
     }
   }
+  rc = reset_nonfinite(c);
+  if (rc) return rc;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->state = 3;
   return SC_OK;
@@ -1646,14 +1683,8 @@ int sc_hamiltonian(sc_ctx* c, int32_t member, int32_t level, double* host, int64
   if (n != L.owned_member) return fail(c, SC_E_ARG, "n must equal the level's owned points");
   if (level > 0 && c->lev[level - 1].t == 0.0)
     return fail(c, SC_E_STATE, "refinement-boundary ghosts need one parent step first");
-  rc = sc_fill_ghosts(c, level, SC_FILL_END, 1);
+  rc = hamiltonian_into_scratch(c, level);
   if (rc) return rc;
-  Z4cArgs a = z4c_args(c, level);
-  a.Y = L.y[L.cur];   // the END fill wrote the state's own halo
-  a.ham = L.Ys;   // scratch: one variable's worth of the stage-vector array
-  a.tiles = L.d_tiles;
-  a.ntiles = (int32_t)L.tiles.size();
-  HIPCHK(c, launch_z4c_stage(a, z4c_grid(a.ntiles), false, c->stream));
   PackArgs pa = member_pack(c, member, level, L.Ys);
   HIPCHK(c, launch_pack(pa, false, false, c->stream));
   HIPCHK(c, hipMemcpyAsync(host, c->d_stage, sizeof(double) * n, hipMemcpyDeviceToHost,
@@ -1662,10 +1693,39 @@ int sc_hamiltonian(sc_ctx* c, int32_t member, int32_t level, double* host, int64
   return SC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Hamiltonian constraint of the current state of a level (all members) into
+// the level's scratch array, after filling the state's ghosts (SYNC,
+// physical, and the dense-output end value on refinement boundaries).
+int hamiltonian_into_scratch(sc_ctx* c, int level) {
+  LevelDev& L = c->lev[level];
+  int rc = sc_fill_ghosts(c, level, SC_FILL_END, 1);
+  if (rc) return rc;
+  Z4cArgs a = z4c_args(c, level);
+  a.Y = L.y[L.cur];   // the END fill wrote the state's own halo
+  a.ham = L.Ys;       // scratch: one variable's worth of the curvature array
+  a.tiles = L.d_tiles;
+  a.ntiles = (int32_t)L.tiles.size();
+  HIPCHK(c, launch_z4c_stage(a, z4c_grid(a.ntiles), false, c->stream));
+  return SC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int sc_advance(sc_ctx* c, int32_t ncoarse) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
   if (ncoarse < 0) return fail(c, SC_E_ARG, "ncoarse < 0");
+  // the flag copied after the previous call's steps, if it has arrived (no wait)
+  if (c->flag_pending && hipEventQuery(c->flag_ev) == hipSuccess) c->flag_pending = false;
+  if (!c->flag_pending && *c->h_flag)
+    return fail(c, SC_E_NONFINITE, "an earlier coarse step produced a non-finite state value "
+                                   "(sc_check_finite locates it; new initial data clear it)");
   c->launches = 0;
   for (int i = 0; i < ncoarse; ++i) {
     // buffer zones: the first coarse step interpolates linearly in time at
@@ -1722,6 +1782,12 @@ int sc_advance(sc_ctx* c, int32_t ncoarse) {
       rc = advance_level(c, 0, 0, c->cfg.exec == SC_EXEC_PER_BLOCK);
       if (rc) return rc;
     }
+  }
+  if (ncoarse > 0 && !c->flag_pending) {
+    HIPCHK(c, hipMemcpyAsync(c->h_flag, c->d_nonfinite, sizeof(unsigned int),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipEventRecord(c->flag_ev, c->stream));
+    c->flag_pending = true;
   }
   return SC_OK;
 }
@@ -1849,17 +1915,103 @@ int sc_norms(sc_ctx* c, int32_t member, int32_t level, int32_t var, int32_t arra
       !out)
     return fail(c, SC_E_ARG, "bad norm arguments");
   bool f32 = false;
-  PackArgs a = member_pack(c, member, level, array_ptr(c, level, array, var, &f32));
-  HIPCHK(c, launch_norms(a, f32, c->d_partials, 256, c->d_norm_out, c->stream));
-  HIPCHK(c, hipMemcpyAsync(out, c->d_norm_out, sizeof(double) * 3, hipMemcpyDeviceToHost,
-                           c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
+  NormArgs a{};
+  a.p = member_pack(c, member, level, array_ptr(c, level, array, var, &f32));
+  a.mode = 0;
+  double r[4];
+  rc = reduce(c, a, f32, c->d_partials, c->d_norm_out, r);
+  if (rc) return rc;
+  out[0] = r[0];
+  out[1] = r[2] > 0 ? std::sqrt(r[1] / r[2]) : 0.0;
+  out[2] = r[3];
+  return SC_OK;
+}
+
+int sc_error_norms(sc_ctx* c, int32_t member, int32_t level, int32_t var, int32_t kind,
+                   const double* params, int32_t nparams, double out[3]) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || member < 0 ||
+      member >= c->hier.geo.nmembers || var < 0 || var >= c->nvars || !out)
+    return fail(c, SC_E_ARG, "bad error-norm arguments");
+  if (kind != SC_ID_STANDING_WAVE && kind != SC_ID_SPHERICAL_GAUSSIAN)
+    return fail(c, SC_E_ARG, "error norms need a closed-form solution at time t: "
+                             "SC_ID_STANDING_WAVE or SC_ID_SPHERICAL_GAUSSIAN");
+  if (c->cfg.rhs != SC_RHS_WAVE) return fail(c, SC_E_ARG, "closed forms are wave solutions");
+  if (kind == SC_ID_STANDING_WAVE && nparams != 5)
+    return fail(c, SC_E_ARG, "standing wave: (A, m_x, m_y, m_z, t)");
+  if (kind == SC_ID_SPHERICAL_GAUSSIAN && (nparams != 3 || !(params && params[1] > 0.0)))
+    return fail(c, SC_E_ARG, "spherical Gaussian: (A, sigma > 0, t)");
+  if (!params) return fail(c, SC_E_ARG, "null parameters");
+  LevelDev& L = c->lev[level];
+  NormArgs a{};
+  bool f32 = false;
+  a.p = member_pack(c, member, level, array_ptr(c, level, SC_ARR_Y, var, &f32));
+  a.mode = 1;
+  a.exact.kind = kind;
+  a.exact.var = var;
+  a.exact.dx = L.dx;
+  for (int d = 0; d < 3; ++d) a.exact.origin[d] = c->hier.geo.origin[d];
+  std::copy(params, params + nparams, a.exact.p);
+  double r[4];
+  rc = reduce(c, a, false, c->d_partials, c->d_norm_out, r);
+  if (rc) return rc;
+  out[0] = r[0];
+  out[1] = r[2] > 0 ? std::sqrt(r[1] / r[2]) : 0.0;
+  out[2] = r[3];
+  return SC_OK;
+}
+
+int sc_constraint_norm(sc_ctx* c, int32_t member, double rmax, double alpha_min, double out[3]) {
+  int rc = check_ready(c, 3);
+  if (rc) return rc;
+  if (c->cfg.rhs != SC_RHS_Z4C) return fail(c, SC_E_STATE, "the Hamiltonian constraint needs Z4c");
+  if (member < 0 || member >= c->hier.geo.nmembers || !out || !(rmax > 0.0))
+    return fail(c, SC_E_ARG, "bad constraint-norm arguments");
+  const int nl = (int)c->lev.size();
+  for (int l = 1; l < nl; ++l)
+    if (c->lev[l - 1].t == 0.0)
+      return fail(c, SC_E_STATE, "refinement-boundary ghosts need one parent step first");
+  double num = 0.0, den = 0.0, hmax = 0.0, bad = 0.0;
+  for (int l = 0; l < nl; ++l) {   // levels in order: a fixed summation order
+    LevelDev& L = c->lev[l];
+    rc = hamiltonian_into_scratch(c, l);
+    if (rc) return rc;
+    NormArgs a{};
+    a.p = member_pack(c, member, l, L.Ys);
+    a.mode = 2;
+    a.exact.dx = L.dx;
+    for (int d = 0; d < 3; ++d) a.exact.origin[d] = c->hier.geo.origin[d];
+    a.alpha = L.y[L.cur] + 18 * L.total;
+    if (l + 1 < nl) {
+      const LevelDev& F = c->lev[l + 1];
+      a.child = F.d_boxes + member * F.nb_member;
+      a.nchild = F.nb_member;
+    }
+    a.rmax = rmax;
+    a.amin = alpha_min;
+    a.cell = L.dx * L.dx * L.dx;
+    double r[4];
+    rc = reduce(c, a, false, c->d_partials, c->d_norm_out, r);
+    if (rc) return rc;
+    hmax = std::max(hmax, r[0]);
+    num += r[1];
+    den += r[2];
+    bad += r[3];
+  }
+  out[0] = den > 0 ? std::sqrt(num / den) : 0.0;
+  out[1] = hmax;
+  out[2] = bad;
   return SC_OK;
 }
 
 int sc_check_finite(sc_ctx* c) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
+  if (c->flag_pending) {
+    HIPCHK(c, hipEventSynchronize(c->flag_ev));
+    c->flag_pending = false;
+  }
   for (int l = 0; l < (int)c->lev.size(); ++l)
     for (int m = 0; m < c->hier.geo.nmembers; ++m)
       for (int v = 0; v < c->nvars; ++v) {

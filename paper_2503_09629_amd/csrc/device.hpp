@@ -99,6 +99,7 @@ struct StageArgs {
   int32_t write_k;
   int32_t radius;  // stencil radius: 3 (fourth order) or 4 (eighth order, FP64); the
                    // boxes must be padded by at least this much
+  unsigned int* nonfinite;   // set to 1 when stage 4 writes a non-finite y_{n+1}
 };
 
 struct SyncArgs {
@@ -196,6 +197,26 @@ struct InitArgs {
   double p[kInitParams];  // the kind's parameters (see sc_set_initial_data_analytic)
 };
 
+// Deterministic reductions over the owned points of one member of a level
+// (see k_norms_partial): per point a value v and a weight w (1 unless mode 2);
+// the result is {max |v|, sum w v^2, sum w, non-finite count}.
+//   mode 0: v = the array's value
+//   mode 1: v = the array's value minus the closed form `exact` (variable exact.var)
+//   mode 2: v = the array's value (a constraint), w = cell at points that no child box
+//           covers, with r < rmax and the lapse alpha > amin, else the point is skipped
+constexpr int64_t kNormPointsPerPart = 8192;   // points per partial workgroup
+struct NormArgs {
+  PackArgs p;             // the points (p.arr: the level array of the variable)
+  int32_t mode;
+  InitArgs exact;         // modes 1, 2: origin and dx (mode 1: the closed form)
+  const double* alpha;    // mode 2: the lapse (level array)
+  const BoxDev* child;    // mode 2: boxes of the finer level (same member)
+  int32_t nchild;
+  double rmax, amin, cell;
+};
+// partial workgroups of a reduction over n points (the partials array holds 4 per part)
+int norm_parts(int64_t n);
+
 // launchers (kernels.hip); `f32` selects FP32 arrays
 // mixed: the mixed-precision stage kernels (see StageArgs)
 // depth: planes of loads in flight (1 or 2); slots: owned points per thread (1 or 2);
@@ -217,14 +238,15 @@ hipError_t launch_scatter_value(const int64_t* idx, int64_t n, double v, void* d
                                 hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, hipStream_t s);
 hipError_t launch_pack(const PackArgs& a, bool unpack, bool f32, hipStream_t s);
-hipError_t launch_norms(const PackArgs& a, bool f32, double* partials, int nparts, double* out,
-                        hipStream_t s);
+// out: 4 doubles {max, sum, weight sum, non-finite count}
+hipError_t launch_norms(const NormArgs& a, bool f32, double* partials, double* out, hipStream_t s);
 hipError_t launch_gather(const int64_t* idx, int64_t n, const void* src, bool f32, double* dst,
                          hipStream_t s);
 hipError_t launch_fill(void* p, int64_t n, double v, bool f32, hipStream_t s);
 hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, void* dst, bool f32,
                           hipStream_t s);
 hipError_t launch_to_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 
 // Stencil-kernel workgroup families: threads, ring points per thread and plane,

@@ -9,6 +9,7 @@
 // or float (stages 2-4 of mixed mode, which evaluate the right-hand side of
 // the stage increment Y_s - y_n in FP32); the slope type TK is double or
 // float; the state update stays FP64.
+#include <algorithm>
 #include <type_traits>
 
 #include "device.hpp"
@@ -325,7 +326,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
           const int64_t ov = o + v * a.vstride;
           const double sm = (((double)c1[v][s] + 2.0 * (double)c2[v][s]) + 2.0 * (double)c3[v][s]) +
                             (double)kv[v];
-          a.ynew[ov] = c0[v][s] + a.dt6 * sm;
+          const double yv = c0[v][s] + a.dt6 * sm;
+          a.ynew[ov] = yv;
+          if (!isfinite(yv)) atomicOr(a.nonfinite, 1u);
         }
       }
     }
@@ -694,66 +697,191 @@ __global__ __launch_bounds__(256) void k_pack(PackArgs a, int unpack) {
   else a.buf[i] = (double)arr[o];
 }
 
-// Deterministic norms: fixed grid, fixed per-thread stride, fixed tree order.
-template <typename T>
-__global__ __launch_bounds__(256) void k_norms_partial(PackArgs a, double* partials) {
-  __shared__ double smax[256], ssum[256], sbad[256];
-  double m = 0.0, s = 0.0, bad = 0.0;
-  const T* arr = static_cast<const T*>(a.arr);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = (double)arr[canonical_to_offset(a, i)];
-    if (!isfinite(v)) {
-      bad += 1.0;
-    } else {
-      m = fmax(m, fabs(v));
-      s += v * v;
-    }
+// Closed-form initial data.  Kinds (parameters in InitArgs::p):
+//  1 standing wave  u = A cos(w t) S, Pi = -A w sin(w t) S with
+//    S = sin(m_x pi x) sin(m_y pi y) sin(m_z pi z), w = pi |m|; p = (A, m_x, m_y, m_z, t)
+//    (at t = 0: u = A S, Pi = 0)
+//  2 Gaussian pulses u = sum_p A_p g_p(x) g_p(y) g_p(z), Pi = 0, with
+//    g_p(x) = sum_{k=-K..K} exp(-(x - c_{p,x} - k L)^2 / w_p^2) (K = 1 if the
+//    period L > 0, else 0); p = (npulses, L, then A, w, c_x, c_y, c_z per pulse)
+//  3 Brill-Lindquist punctures (22 Z4c variables): psi = 1 + a,
+//    a = m_+ / (2 r_+) + m_- / (2 r_-), W = psi^-2, gt = delta, lapse
+//    (1 + (1 - a) / (1 + a)) / 2, the rest 0; p = (m_+, m_-, x_+, x_-) with the
+//    punctures at (x_+, 0, 0) and (x_-, 0, 0)
+//  4 outgoing spherical Gaussian u = (f(t - r) - f(t + r)) / r, Pi = du/dt,
+//    f(v) = A exp(-v^2 / (2 sigma^2)), limits at r = 0; p = (A, sigma, t)
+__device__ __forceinline__ double periodised_gauss(double x, double c, double w, double L) {
+  if (L <= 0.0) {
+    const double d = x - c;
+    return exp(-(d * d) / (w * w));
   }
-  smax[threadIdx.x] = m;
-  ssum[threadIdx.x] = s;
-  sbad[threadIdx.x] = bad;
+  double g = 0.0;
+  for (int k = -1; k <= 1; ++k) {
+    const double d = (x - c) - k * L;
+    g += exp(-(d * d) / (w * w));
+  }
+  return g;
+}
+
+__device__ double init_value(const InitArgs& a, double x, double y, double z, int v) {
+  const double* p = a.p;
+  switch (a.kind) {
+    case 1: {
+      const double t = p[4];
+      if (t == 0.0) {
+        if (v != 0) return 0.0;
+        const double fx = p[0] * sin(p[1] * M_PI * x);
+        return (sin(p[3] * M_PI * z) * sin(p[2] * M_PI * y)) * fx;
+      }
+      const double w = M_PI * sqrt((p[1] * p[1] + p[2] * p[2]) + p[3] * p[3]);
+      const double S = (sin(p[3] * M_PI * z) * sin(p[2] * M_PI * y)) * sin(p[1] * M_PI * x);
+      return v == 0 ? (p[0] * cos(w * t)) * S : (-p[0] * w * sin(w * t)) * S;
+    }
+    case 2: {
+      if (v != 0) return 0.0;
+      const int np = (int)p[0];
+      double u = 0.0;
+      for (int q = 0; q < np; ++q) {
+        const double* c = p + 2 + 5 * q;
+        const double gx = c[0] * periodised_gauss(x, c[2], c[1], p[1]);
+        u += (periodised_gauss(z, c[4], c[1], p[1]) * periodised_gauss(y, c[3], c[1], p[1])) * gx;
+      }
+      return u;
+    }
+    case 3: {
+      const double dp = x - p[2], dm = x - p[3];
+      const double rp = sqrt(dp * dp + y * y + z * z), rm = sqrt(dm * dm + y * y + z * z);
+      const double s = p[0] / (2.0 * rp) + p[1] / (2.0 * rm);
+      const double psi = 1.0 + s;
+      if (v == 0) return 1.0 / (psi * psi);
+      if (v == 1 || v == 4 || v == 6) return 1.0;
+      if (v == 18) return 0.5 * (1.0 + (1.0 - s) / (1.0 + s));
+      return 0.0;
+    }
+    case 4: {
+      const double A = p[0], s2 = p[1] * p[1], t = p[2];
+      const double r = sqrt(x * x + y * y + z * z);
+      auto f = [&](double q) { return A * exp(-q * q / (2.0 * s2)); };
+      if (r < 1e-9) {
+        const double ft = f(t);
+        return v == 0 ? 2.0 * t / s2 * ft : 2.0 * ft * (1.0 - t * t / s2) / s2;
+      }
+      if (v == 0) return (f(t - r) - f(t + r)) / r;
+      return -(f(t - r) * (t - r) - f(t + r) * (t + r)) / (s2 * r);
+    }
+    default:
+      return 0.0;
+  }
+}
+
+// Deterministic reductions: a grid of ceil(n / kNormPointsPerPart)
+// workgroups (the count depends only on n), each thread accumulating a fixed
+// strided subset, then a fixed butterfly over the 64 lanes of each wave
+// (cross-lane shuffles), the four waves combined in order, and one final
+// workgroup combining the partials the same way.  Every call on the same data
+// gives the same bits.  Accumulated per point: a max term, a sum term, a
+// weight term and a count of non-finite values.
+struct Acc {
+  double m, s, w, bad;
+};
+
+__device__ __forceinline__ Acc acc_combine(Acc a, Acc b) {
+  return {fmax(a.m, b.m), a.s + b.s, a.w + b.w, a.bad + b.bad};
+}
+
+__device__ __forceinline__ Acc acc_block(Acc a, Acc* lds) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    Acc o;
+    o.m = __shfl_xor(a.m, off, 64);
+    o.s = __shfl_xor(a.s, off, 64);
+    o.w = __shfl_xor(a.w, off, 64);
+    o.bad = __shfl_xor(a.bad, off, 64);
+    a = acc_combine(a, o);
+  }
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) lds[wave] = a;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
-      ssum[threadIdx.x] += ssum[threadIdx.x + w];
-      sbad[threadIdx.x] += sbad[threadIdx.x + w];
+  Acc r = lds[0];
+  for (int w = 1; w < (int)(blockDim.x / 64); ++w) r = acc_combine(r, lds[w]);
+  return r;
+}
+
+// Point i of a reduction: its canonical offset and global index.
+__device__ __forceinline__ int64_t canonical_point(const PackArgs& a, int64_t i, int gi[3]) {
+  int b = 0;
+  while (b + 1 < a.nboxes && a.prefix[b + 1] <= i) ++b;
+  const BoxDev B = a.boxes[b];
+  const int64_t l = i - a.prefix[b];
+  const int x = (int)(l % B.nx), y = (int)((l / B.nx) % B.ny), z = (int)(l / ((int64_t)B.nx * B.ny));
+  gi[0] = B.lo[0] + x, gi[1] = B.lo[1] + y, gi[2] = B.lo[2] + z;
+  return padded_offset(B, x, y, z);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_norms_partial(NormArgs a, double* partials) {
+  __shared__ Acc lds[4];
+  Acc r{0.0, 0.0, 0.0, 0.0};
+  const T* arr = static_cast<const T*>(a.p.arr);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.p.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int gi[3];
+    const int64_t o = canonical_point(a.p, i, gi);
+    double v = (double)arr[o], w = 1.0;
+    if (a.mode == 1) {            // difference to the closed form
+      const double x = a.exact.origin[0] + gi[0] * a.exact.dx;
+      const double y = a.exact.origin[1] + gi[1] * a.exact.dx;
+      const double z = a.exact.origin[2] + gi[2] * a.exact.dx;
+      v = v - init_value(a.exact, x, y, z, a.exact.var);
+    } else if (a.mode == 2) {     // composite-grid weight of a constraint value
+      bool covered = false;
+      for (int c = 0; c < a.nchild; ++c) {
+        const BoxDev& C = a.child[c];
+        bool in = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int n = d == 0 ? C.nx : (d == 1 ? C.ny : C.nz);
+          in = in && 2 * gi[d] >= C.lo[d] && 2 * gi[d] < C.lo[d] + n;
+        }
+        covered = covered || in;
+      }
+      const double x = a.exact.origin[0] + gi[0] * a.exact.dx;
+      const double y = a.exact.origin[1] + gi[1] * a.exact.dx;
+      const double z = a.exact.origin[2] + gi[2] * a.exact.dx;
+      const double rr = sqrt((x * x + y * y) + z * z);
+      w = (!covered && rr < a.rmax && a.alpha[o] > a.amin) ? a.cell : 0.0;
+      if (w == 0.0) continue;
     }
-    __syncthreads();
+    if (!isfinite(v)) {
+      r.bad += 1.0;
+    } else {
+      r.m = fmax(r.m, fabs(v));
+      r.s += w * (v * v);
+      r.w += w;
+    }
   }
+  r = acc_block(r, lds);
   if (threadIdx.x == 0) {
-    partials[3 * blockIdx.x + 0] = smax[0];
-    partials[3 * blockIdx.x + 1] = ssum[0];
-    partials[3 * blockIdx.x + 2] = sbad[0];
+    partials[4 * blockIdx.x + 0] = r.m;
+    partials[4 * blockIdx.x + 1] = r.s;
+    partials[4 * blockIdx.x + 2] = r.w;
+    partials[4 * blockIdx.x + 3] = r.bad;
   }
 }
 
 __global__ __launch_bounds__(256) void k_norms_final(const double* partials, int nparts,
-                                                     int64_t n, double* out) {
-  __shared__ double smax[256], ssum[256], sbad[256];
-  double m = 0.0, s = 0.0, bad = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-    m = fmax(m, partials[3 * i]);
-    s += partials[3 * i + 1];
-    bad += partials[3 * i + 2];
-  }
-  smax[threadIdx.x] = m;
-  ssum[threadIdx.x] = s;
-  sbad[threadIdx.x] = bad;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
-      ssum[threadIdx.x] += ssum[threadIdx.x + w];
-      sbad[threadIdx.x] += sbad[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
+                                                     double* out) {
+  __shared__ Acc lds[4];
+  Acc r{0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x)
+    r = acc_combine(r, Acc{partials[4 * i], partials[4 * i + 1], partials[4 * i + 2],
+                           partials[4 * i + 3]});
+  r = acc_block(r, lds);
   if (threadIdx.x == 0) {
-    out[0] = smax[0];
-    out[1] = n > 0 ? sqrt(ssum[0] / (double)n) : 0.0;
-    out[2] = sbad[0];
+    out[0] = r.m;
+    out[1] = r.s;
+    out[2] = r.w;
+    out[3] = r.bad;
   }
 }
 
@@ -793,75 +921,6 @@ __global__ __launch_bounds__(256) void k_scatter_value(const int64_t* idx, int64
 __global__ __launch_bounds__(256) void k_to_f32(const double* src, float* dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = (float)src[i];
-}
-
-// Closed-form initial data.  Kinds (parameters in InitArgs::p):
-//  1 standing wave  u = A sin(m_x pi x) sin(m_y pi y) sin(m_z pi z), Pi = 0; p = (A, m_x, m_y, m_z)
-//  2 Gaussian pulses u = sum_p A_p g_p(x) g_p(y) g_p(z), Pi = 0, with
-//    g_p(x) = sum_{k=-K..K} exp(-(x - c_{p,x} - k L)^2 / w_p^2) (K = 1 if the
-//    period L > 0, else 0); p = (npulses, L, then A, w, c_x, c_y, c_z per pulse)
-//  3 Brill-Lindquist punctures (22 Z4c variables): psi = 1 + a,
-//    a = m_+ / (2 r_+) + m_- / (2 r_-), W = psi^-2, gt = delta, lapse
-//    (1 + (1 - a) / (1 + a)) / 2, the rest 0; p = (m_+, m_-, x_+, x_-) with the
-//    punctures at (x_+, 0, 0) and (x_-, 0, 0)
-//  4 outgoing spherical Gaussian u = (f(t - r) - f(t + r)) / r, Pi = du/dt,
-//    f(v) = A exp(-v^2 / (2 sigma^2)), limits at r = 0; p = (A, sigma, t)
-__device__ __forceinline__ double periodised_gauss(double x, double c, double w, double L) {
-  if (L <= 0.0) {
-    const double d = x - c;
-    return exp(-(d * d) / (w * w));
-  }
-  double g = 0.0;
-  for (int k = -1; k <= 1; ++k) {
-    const double d = (x - c) - k * L;
-    g += exp(-(d * d) / (w * w));
-  }
-  return g;
-}
-
-__device__ double init_value(const InitArgs& a, double x, double y, double z, int v) {
-  const double* p = a.p;
-  switch (a.kind) {
-    case 1: {
-      if (v != 0) return 0.0;
-      const double fx = p[0] * sin(p[1] * M_PI * x);
-      return (sin(p[3] * M_PI * z) * sin(p[2] * M_PI * y)) * fx;
-    }
-    case 2: {
-      if (v != 0) return 0.0;
-      const int np = (int)p[0];
-      double u = 0.0;
-      for (int q = 0; q < np; ++q) {
-        const double* c = p + 2 + 5 * q;
-        const double gx = c[0] * periodised_gauss(x, c[2], c[1], p[1]);
-        u += (periodised_gauss(z, c[4], c[1], p[1]) * periodised_gauss(y, c[3], c[1], p[1])) * gx;
-      }
-      return u;
-    }
-    case 3: {
-      const double dp = x - p[2], dm = x - p[3];
-      const double rp = sqrt(dp * dp + y * y + z * z), rm = sqrt(dm * dm + y * y + z * z);
-      const double s = p[0] / (2.0 * rp) + p[1] / (2.0 * rm);
-      const double psi = 1.0 + s;
-      if (v == 0) return 1.0 / (psi * psi);
-      if (v == 1 || v == 4 || v == 6) return 1.0;
-      if (v == 18) return 0.5 * (1.0 + (1.0 - s) / (1.0 + s));
-      return 0.0;
-    }
-    case 4: {
-      const double A = p[0], s2 = p[1] * p[1], t = p[2];
-      const double r = sqrt(x * x + y * y + z * z);
-      auto f = [&](double q) { return A * exp(-q * q / (2.0 * s2)); };
-      if (r < 1e-9) {
-        const double ft = f(t);
-        return v == 0 ? 2.0 * t / s2 * ft : 2.0 * ft * (1.0 - t * t / s2) / s2;
-      }
-      if (v == 0) return (f(t - r) - f(t + r)) / r;
-      return -(f(t - r) * (t - r) - f(t + r) * (t + r)) / (s2 * r);
-    }
-    default:
-      return 0.0;
-  }
 }
 
 __global__ __launch_bounds__(256) void k_init(InitArgs a) {
@@ -1009,11 +1068,16 @@ hipError_t launch_pack(const PackArgs& a, bool unpack, bool f32, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_norms(const PackArgs& a, bool f32, double* partials, int nparts, double* out,
+int norm_parts(int64_t n) {
+  return (int)std::max<int64_t>(1, (n + kNormPointsPerPart - 1) / kNormPointsPerPart);
+}
+
+hipError_t launch_norms(const NormArgs& a, bool f32, double* partials, double* out,
                         hipStream_t s) {
+  const int nparts = norm_parts(a.p.n);
   if (f32) hipLaunchKernelGGL(k_norms_partial<float>, dim3(nparts), dim3(256), 0, s, a, partials);
   else hipLaunchKernelGGL(k_norms_partial<double>, dim3(nparts), dim3(256), 0, s, a, partials);
-  hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(256), 0, s, partials, nparts, a.n, out);
+  hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(256), 0, s, partials, nparts, out);
   return hipGetLastError();
 }
 
@@ -1049,6 +1113,12 @@ hipError_t launch_scatter(const int64_t* idx, int64_t n, const double* src, void
   else
     hipLaunchKernelGGL(k_scatter<double>, dim3(blocks_for(n)), dim3(256), 0, s, idx, n, src,
                        static_cast<double*>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<unsigned int>, dim3(blocks_for(n)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

@@ -104,7 +104,12 @@ struct sc_ctx {
   bool wave_mixed = false;   // SC_MIXED with the wave: FP64 k1, FP32 stage increments
   size_t esz = 8;       // bytes per element of k and Yh arrays
   size_t arena_bytes = 0;
-  size_t o_stage = 0, o_partials = 0, o_norm_out = 0;
+  size_t o_stage = 0, o_partials = 0, o_norm_out = 0, o_flag = 0;
+  int norm_parts_max = 1;        // partial workgroups of the largest reduction
+  unsigned int* d_nonfinite = nullptr;   // set by stage 4 on a non-finite y_{n+1}
+  unsigned int* h_flag = nullptr;        // pinned host copy, read after flag_ev
+  hipEvent_t flag_ev = nullptr;
+  bool flag_pending = false;
   int64_t stage_elems = 0;
   char* arena = nullptr;
   double* d_stage = nullptr;
@@ -124,5 +129,7 @@ struct sc_ctx {
   std::vector<double> ev_bytes;        // algorithmic bytes per recorded launch
   ~sc_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (flag_ev) (void)hipEventDestroy(flag_ev);
+    if (h_flag) (void)hipHostFree(h_flag);
   }
 };

@@ -617,6 +617,7 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
             const double yv = a.yn[oi] + a.dt6 * s;
             a.ynew[oi] = yv;
             if constexpr (sizeof(TS) == 4) a.ynew32[oi] = (float)yv;
+            if (!isfinite(yv)) atomicOr(a.nonfinite, 1u);
           }
         }
       }

@@ -30,6 +30,7 @@ struct Z4cArgs {
   double h, dt6, sigma, kappa1, kappa2, eta_c, eta_o, eta_s;
   double origin[3];   // coordinates of global index (0,0,0) of the level
   int32_t ord;        // derivative order: 4, or 8 (FP64, boxes padded by 4)
+  unsigned int* nonfinite;   // set to 1 when stage 4 writes a non-finite y_{n+1}
 };
 
 struct Z4cCombineArgs {

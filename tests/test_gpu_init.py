@@ -68,7 +68,7 @@ def test_gaussian_explicit_parameters():
 
 @pytest.mark.parametrize("precision", [sc.SC_FP64, sc.SC_MIXED])
 def test_seeded_pulses_on_the_towers(precision):
-    spec = config_c3(32, nlev=4)
+    spec = config_c3(64, nlev=4)
     ctx = _ctx(spec, precision=precision)
     ctx.set_initial_data_analytic(sc.SC_ID_GAUSSIAN_PULSES, (8, 2.0, 0.3), seed=2)
     _check(ctx, spec, lambda l: pulses_on_spec(spec, l, seed=2))

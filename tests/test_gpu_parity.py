@@ -359,7 +359,7 @@ def test_graph_recaptured_after_single_level_steps():
 def test_close_right_after_advance_waits_for_the_stream():
     """close() returns only when the context's queued kernels are done, so the
     arena can go back to the allocator at once."""
-    spec = config_c3(32, nlev=3)
+    spec = config_c3(64, nlev=3)
     ctx = _gpu(spec, exec=sc.SC_EXEC_BATCHED)
     for l in range(spec.nlevels):
         for v, f in enumerate(pulses_on_spec(spec, l)):
