@@ -320,6 +320,19 @@ int sc_read_rb(sc_ctx* ctx, int32_t member, int32_t level, int32_t which, int32_
 int sc_norms(sc_ctx* ctx, int32_t member, int32_t level, int32_t var, int32_t array,
              double out[3]);
 
+/* sc_norms for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same reduction, bit for bit, with its partials and result in a workspace
+ * that the library holds in static device memory (one copy per GPU, 128 KiB,
+ * kept until the process ends) instead of the context's arena.  It allocates
+ * nothing.  Levels of more than 4096 * 8192 = 33,554,432 owned points per
+ * member exceed that workspace: SC_E_ARG, with a message.  Every call on a
+ * GPU shares its workspace, so calls that overlap on one GPU (two streams,
+ * two threads, two contexts) race; the result is copied back before return
+ * (synchronises the context's stream). */
+int sc_norms_noalloc(sc_ctx* ctx, int32_t member, int32_t level, int32_t var, int32_t array,
+                     double out[3]);
+
 /* Error of the state against a closed-form solution at time t, over the owned
  * points of one level of one member, for one variable: out[0] = max |y - exact|,
  * out[1] = sqrt(mean (y - exact)^2), out[2] = number of non-finite state

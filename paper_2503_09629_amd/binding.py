@@ -31,7 +31,7 @@ EXPORTED = [
     "sc_get_counts", "sc_buffer_count", "sc_export_maps", "sc_device_bytes", "sc_bind_device_memory",
     "sc_set_initial_data", "sc_set_initial_data_analytic", "sc_phys_count", "sc_phys_points", "sc_set_phys_data",
     "sc_hamiltonian", "sc_error_norms", "sc_constraint_norm", "sc_advance", "sc_step_level", "sc_prolongate", "sc_fill_ghosts",
-    "sc_restrict", "sc_read_back", "sc_read_rb", "sc_norms", "sc_check_finite",
+    "sc_restrict", "sc_read_back", "sc_read_rb", "sc_norms", "sc_norms_noalloc", "sc_check_finite",
     "sc_level_time", "sc_set_exec", "sc_poison_halos", "sc_autotune", "sc_tile_shape",
     "sc_set_tile_shape", "sc_profile_enable",
     "sc_profile_read", "sc_stats",
@@ -102,6 +102,7 @@ def lib():
             "sc_read_back": [P, i32, i32, i32, i32, P, i64],
             "sc_read_rb": [P, i32, i32, i32, i32, i32, P, i64],
             "sc_norms": [P, i32, i32, i32, i32, P],
+            "sc_norms_noalloc": [P, i32, i32, i32, i32, P],
             "sc_check_finite": [P],
             "sc_level_time": [P, i32, P],
             "sc_set_exec": [P, i32],
@@ -298,6 +299,12 @@ class Context:
     def norms(self, member: int, level: int, var: int, array: int = SC_ARR_Y):
         out = np.empty(3)
         self._check(self.L.sc_norms(self.ctx, member, level, var, array, _p(out)))
+        return out
+
+    def norms_noalloc(self, member: int, level: int, var: int, array: int = SC_ARR_Y):
+        """sc_norms with the library's static workspace (no device allocation)."""
+        out = np.empty(3)
+        self._check(self.L.sc_norms_noalloc(self.ctx, member, level, var, array, _p(out)))
         return out
 
     def error_norms(self, member: int, level: int, var: int, kind: int, params):

@@ -1927,6 +1927,38 @@ int sc_norms(sc_ctx* c, int32_t member, int32_t level, int32_t var, int32_t arra
   return SC_OK;
 }
 
+int sc_norms_noalloc(sc_ctx* c, int32_t member, int32_t level, int32_t var, int32_t array,
+                     double out[3]) {
+  int rc = check_ready(c, 2);
+  if (rc) return rc;
+  if (level < 0 || level >= (int)c->lev.size() || member < 0 ||
+      member >= c->hier.geo.nmembers || var < 0 || var >= c->nvars || array < 0 || array > 5 ||
+      !out)
+    return fail(c, SC_E_ARG, "bad norm arguments");
+  const int64_t n = c->lev[level].owned_member;
+  if (norm_parts(n) > kNoAllocParts) {
+    char msg[200];
+    snprintf(msg, sizeof msg,
+             "level %d has %lld owned points; the static reduction workspace holds at most "
+             "%lld (use sc_norms)", level, (long long)n,
+             (long long)kNoAllocParts * (long long)kNormPointsPerPart);
+    return fail(c, SC_E_ARG, msg);
+  }
+  double* ws = nullptr;
+  HIPCHK(c, noalloc_scratch(&ws));
+  bool f32 = false;
+  NormArgs a{};
+  a.p = member_pack(c, member, level, array_ptr(c, level, array, var, &f32));
+  a.mode = 0;
+  double r[4];
+  rc = reduce(c, a, f32, ws, ws + 4 * kNoAllocParts, r);
+  if (rc) return rc;
+  out[0] = r[0];
+  out[1] = r[2] > 0 ? std::sqrt(r[1] / r[2]) : 0.0;
+  out[2] = r[3];
+  return SC_OK;
+}
+
 int sc_error_norms(sc_ctx* c, int32_t member, int32_t level, int32_t var, int32_t kind,
                    const double* params, int32_t nparams, double out[3]) {
   int rc = check_ready(c, 3);

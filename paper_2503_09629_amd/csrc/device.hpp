@@ -216,6 +216,12 @@ struct NormArgs {
 };
 // partial workgroups of a reduction over n points (the partials array holds 4 per part)
 int norm_parts(int64_t n);
+// Static reduction workspace (no allocation): partials of at most
+// kNoAllocParts workgroups, then the 4-double result.  noalloc_scratch gives
+// the current device's address of it (looked up once per device).
+constexpr int kNoAllocParts = 4096;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(double** out);
 
 // launchers (kernels.hip); `f32` selects FP32 arrays
 // mixed: the mixed-precision stage kernels (see StageArgs)

@@ -10,6 +10,7 @@
 // the stage increment Y_s - y_n in FP32); the slope type TK is double or
 // float; the state update stays FP64.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "device.hpp"
@@ -1066,6 +1067,31 @@ hipError_t launch_pack(const PackArgs& a, bool unpack, bool f32, hipStream_t s) 
   else
     hipLaunchKernelGGL(k_pack<double>, dim3(blocks_for(a.n)), dim3(256), 0, s, a, unpack ? 1 : 0);
   return hipGetLastError();
+}
+
+// Library-held reduction workspace for callers that cannot allocate (the
+// partials of at most kNoAllocParts workgroups and the 4-double result).
+// One copy per GPU, at its own address; host code must use the address from
+// hipGetSymbolAddress, never the name.
+static __device__ __align__(256) double scratch[4 * kNoAllocParts + 4];
+
+hipError_t noalloc_scratch(double** out) {
+  static std::mutex mu;
+  static double* ptr[kMaxDevices] = {nullptr};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {   // once per device, with that device current
+    e = hipGetSymbolAddress(reinterpret_cast<void**>(&ptr[dev]), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      ptr[dev] = nullptr;
+      return e;
+    }
+  }
+  *out = ptr[dev];
+  return hipSuccess;
 }
 
 int norm_parts(int64_t n) {
