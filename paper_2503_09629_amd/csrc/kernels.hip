@@ -199,6 +199,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
     }
   };
   TS q[2][S][QN];   // stage values of the z column, in marching order
+  bool bad = false;  // stage 4: a non-finite y_{n+1} was written (reported once per tile)
   // prologue: column planes z0 - R DZ .. z0 + (R - 1) DZ into q[1..2R]
 #pragma unroll
   for (int j = 1; j < QN; ++j) {
@@ -329,7 +330,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
                             (double)kv[v];
           const double yv = c0[v][s] + a.dt6 * sm;
           a.ynew[ov] = yv;
-          if (!isfinite(yv)) atomicOr(a.nonfinite, 1u);
+          bad = bad || !isfinite(yv);
         }
       }
     }
@@ -344,6 +345,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
 #pragma unroll
   for (int j = 0; j < DEPTH - 1; ++j)
     if (iz + j < T.nz) step(iz + j, regs[j], lds + ((iz + j) & 1) * 2 * kWinStride);
+  if (STAGE == 4 && bad) atomicOr(a.nonfinite, 1u);
   __syncthreads();
 }
 

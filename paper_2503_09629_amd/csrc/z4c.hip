@@ -584,6 +584,7 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
   const TS c1 = TS(1.0) / (TS(ORD == 8 ? 840.0 : 12.0) * h);
   const TS cko = TS(a.sigma) / (TS(64.0) * h);
   constexpr int R = ORD == 8 ? 4 : 3;   // taps per side: the first difference's, at least KO's 3
+  bool bad = false;   // stage 4: a non-finite y_{n+1} was written (reported once per thread)
   for (int t = xcd_first_tile(); t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
     const BoxDev B = a.boxes[T.box];
@@ -617,12 +618,13 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
             const double yv = a.yn[oi] + a.dt6 * s;
             a.ynew[oi] = yv;
             if constexpr (sizeof(TS) == 4) a.ynew32[oi] = (float)yv;
-            if (!isfinite(yv)) atomicOr(a.nonfinite, 1u);
+            bad = bad || !isfinite(yv);
           }
         }
       }
     }
   }
+  if (STAGE == 4 && bad) atomicOr(a.nonfinite, 1u);
 }
 
 // Y = y_n + cdt k_{s-1} on the owned points of the tiles (all variables);
