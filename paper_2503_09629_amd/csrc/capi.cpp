@@ -687,6 +687,12 @@ void plan_arena(sc_ctx* c) {
     maxowned = std::max(maxowned, std::max(L.owned_member, L.nrb * (int64_t)c->hier.geo.nmembers));
     maxowned = std::max(maxowned, (int64_t)L.phys_q.size() / 3);
   }
+  // Z4c: one FP64 derivative scratch (the FP64 right-hand side and the
+  // constraint), sized for the largest level (levels run one after another)
+  int64_t maxtotal = 0;
+  for (const LevelDev& L : c->lev) maxtotal = std::max(maxtotal, L.total);
+  c->o_der = c->cfg.rhs == SC_RHS_Z4C
+                 ? take(sizeof(double) * (size_t)kZ4cDer * (size_t)maxtotal) : 0;
   c->stage_elems = std::max<int64_t>(maxowned, 1);
   c->o_stage = take(sizeof(double) * (size_t)c->stage_elems);
   c->norm_parts_max = norm_parts(maxowned);
@@ -815,6 +821,7 @@ Z4cArgs z4c_args(sc_ctx* c, int l) {
   for (int d = 0; d < 3; ++d) a.origin[d] = c->hier.geo.origin[d];
   a.ord = c->fd_order;
   a.nonfinite = c->d_nonfinite;
+  a.der = c->d_der;
   return a;
 }
 
@@ -1458,6 +1465,7 @@ int sc_bind_device_memory(sc_ctx* c, void* dptr, size_t nbytes) {
     HIPCHK(c, upload(c, L.d_btiles, L.btiles));
   }
   c->d_stage = at<double>(c, c->o_stage);
+  c->d_der = c->cfg.rhs == SC_RHS_Z4C ? at<double>(c, c->o_der) : nullptr;
   c->d_partials = at<double>(c, c->o_partials);
   c->d_norm_out = at<double>(c, c->o_norm_out);
   c->d_nonfinite = at<unsigned int>(c, c->o_flag);   // zeroed with the arena

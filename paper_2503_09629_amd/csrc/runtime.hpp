@@ -104,7 +104,8 @@ struct sc_ctx {
   bool wave_mixed = false;   // SC_MIXED with the wave: FP64 k1, FP32 stage increments
   size_t esz = 8;       // bytes per element of k and Yh arrays
   size_t arena_bytes = 0;
-  size_t o_stage = 0, o_partials = 0, o_norm_out = 0, o_flag = 0;
+  size_t o_stage = 0, o_partials = 0, o_norm_out = 0, o_flag = 0, o_der = 0;
+  double* d_der = nullptr;       // Z4c FP64: derivative scratch of the largest level
   int norm_parts_max = 1;        // partial workgroups of the largest reduction
   unsigned int* d_nonfinite = nullptr;   // set by stage 4 on a non-finite y_{n+1}
   unsigned int* h_flag = nullptr;        // pinned host copy, read after flag_ev

@@ -36,18 +36,41 @@ __device__ __forceinline__ int sym(int i, int j) {
   return a == 0 ? b : (a == 1 ? 2 + b : 5);
 }
 
+// Scratch slot of the first derivative d_k of variable v, and of the second
+// derivative d_k d_l (k <= l), in the derivative pass's arrays (-1: not stored).
+__host__ __device__ constexpr int der1_slot(int v, int k) {
+  const int s = v == VW ? 0 : (v >= VG && v < VG + 6) ? v : v == VKH ? 7 : v == VTH ? 8
+              : (v >= VGAM && v < VGAM + 3) ? 9 + (v - VGAM) : v == VALP ? 12
+              : (v >= VB && v < VB + 3) ? 13 + (v - VB) : -1;
+  return s < 0 ? -1 : 3 * s + k;
+}
+__host__ __device__ constexpr int der2_slot(int v, int k, int l) {
+  const int s = (v >= VG && v < VG + 6) ? v - VG : v == VW ? 6 : v == VALP ? 7
+              : (v >= VB && v < VB + 3) ? 8 + (v - VB) : -1;
+  const int a = k < l ? k : l, b = k < l ? l : k;
+  const int pr = a == 0 ? b : (a == 1 ? 2 + b : 5);
+  return s < 0 ? -1 : kZ4cDer1 + 6 * s + pr;
+}
+
 // ORD: 4 (five-point centred derivatives) or 8 (nine-point, four ghost layers)
-template <typename TS, int ORD>
+// SCR: take first derivatives and second derivatives from the derivative
+// pass's scratch (FP64) instead of forming them from stencil taps
+// LDS: the taps come from one variable's block staged in LDS (lds, at local
+// offset lo with row and plane pitches lpx, lpxy) instead of the stage vector
+template <typename TS, int ORD, bool SCR = false, bool LDS = false>
 struct Pt {
   const Z4cArgs* a;
   BoxDev B;
   int x, y, z;
   int64_t o;
   int64_t px, pxy;
+  const TS* lds;
+  int lo, lpx, lpxy;
   // the stage vector on the whole padded box (owned points and halo) is one
   // array, so a tap is one unconditional load
   __device__ TS at(int v, int dx, int dy, int dz) const {
-    return static_cast<const TS*>(a->Y)[o + dx + dy * px + dz * pxy + v * a->vstride];
+    if constexpr (LDS) return lds[lo + dx + dy * lpx + dz * lpxy];
+    else return static_cast<const TS*>(a->Y)[o + dx + dy * px + dz * pxy + v * a->vstride];
   }
   __device__ TS tap(int v, int d, int j) const {
     return at(v, d == 0 ? j : 0, d == 1 ? j : 0, d == 2 ? j : 0);
@@ -62,7 +85,9 @@ struct Pt {
       return (((t(-2) - TS(8.0) * t(-1)) + TS(8.0) * t(1)) - t(2)) * c1;
   }
   __device__ TS d1(int v, int d, TS c1) const {
-    if constexpr (ORD == 8)
+    if constexpr (SCR)
+      return a->der[o + der1_slot(v, d) * a->vstride];
+    else if constexpr (ORD == 8)
       return diff1([&](int j) { return tap(v, d, j); }, c1);
     else   // written out: this form keeps the fourth-order kernels' register allocation
       return (((tap(v, d, -2) - TS(8.0) * tap(v, d, -1)) + TS(8.0) * tap(v, d, 1)) - tap(v, d, 2)) * c1;
@@ -95,7 +120,8 @@ struct Pt {
   }
   // second derivative (k, l) with k <= l
   __device__ TS dd(int v, int k, int l, TS c1, TS c2) const {
-    return k == l ? d2(v, k, c2) : dm(v, k, l, c1);
+    if constexpr (SCR) return a->der[o + der2_slot(v, k, l) * a->vstride];
+    else return k == l ? d2(v, k, c2) : dm(v, k, l, c1);
   }
 };
 
@@ -105,8 +131,8 @@ struct Pt {
 // (24 values: R and D_i D_j alpha in symmetric order, then Gt^i,
 // Gt^i_jk At^jk, gt^jk d_j d_k beta^i, d_i d_k beta^k), or the Hamiltonian
 // constraint.
-template <typename TS, int ORD>
-__device__ void z4c_geom(const Pt<TS, ORD>& p, const Z4cArgs& a, TS* out, double* ham_out) {
+template <typename TS, int ORD, bool SCR>
+__device__ void z4c_geom(const Pt<TS, ORD, SCR>& p, const Z4cArgs& a, TS* out, double* ham_out) {
   const TS h = TS(a.h);
   const TS c1 = TS(1.0) / (TS(ORD == 8 ? 840.0 : 12.0) * h);
   const TS c2 = TS(1.0) / (TS(ORD == 8 ? 5040.0 : 12.0) * h * h);
@@ -346,8 +372,8 @@ __device__ void z4c_geom(const Pt<TS, ORD>& p, const Z4cArgs& a, TS* out, double
 // Evolution pass (one point): every right-hand side except advection and
 // dissipation, from the curvature scratch of the same point.
 // geo(c) returns curvature value c of the point (the order z4c_geom writes).
-template <typename TS, int ORD, typename Geo>
-__device__ void z4c_evol(const Pt<TS, ORD>& p, const Z4cArgs& a, const Geo& geo, TS* rhs) {
+template <typename TS, int ORD, bool SCR, typename Geo>
+__device__ void z4c_evol(const Pt<TS, ORD, SCR>& p, const Z4cArgs& a, const Geo& geo, TS* rhs) {
   const TS h = TS(a.h);
   const TS c1 = TS(1.0) / (TS(ORD == 8 ? 840.0 : 12.0) * h);
   TS v[NV], d[NV][3];
@@ -499,7 +525,7 @@ __device__ __forceinline__ int xcd_first_tile() {
 }
 
 // One thread per owned point of the tiles: calls point(p) for each.
-template <typename TS, int ORD, typename F>
+template <typename TS, int ORD, bool SCR, typename F>
 __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
   for (int t = xcd_first_tile(); t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
@@ -509,7 +535,7 @@ __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
     for (int ixy = threadIdx.x; ixy < T.nx * T.ny; ixy += kZ4cThreads) {
       const int rx = ixy % T.nx, ry = ixy / T.nx;
       for (int iz = 0; iz < T.nz; ++iz) {
-        Pt<TS, ORD> p;
+        Pt<TS, ORD, SCR> p;
         p.a = &a;
         p.B = B;
         p.x = T.x0 + rx;
@@ -531,20 +557,101 @@ __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
 template <typename TS, int ORD>
 __global__ __launch_bounds__(kZ4cThreads) void k_z4c_geom(Z4cArgs a) {
   TS* geo = static_cast<TS*>(a.geo);
-  z4c_points<TS, ORD>(a, [&](const Pt<TS, ORD>& p) {
+  z4c_points<TS, ORD, true>(a, [&](const Pt<TS, ORD, true>& p) {
     if constexpr (sizeof(TS) == 8) {
       if (a.ham) {
         double hm;
-        z4c_geom<TS, ORD>(p, a, nullptr, &hm);
+        z4c_geom<TS, ORD, true>(p, a, nullptr, &hm);
         a.ham[p.o] = hm;
         return;
       }
     }
     TS g[kZ4cGeo];
-    z4c_geom<TS, ORD>(p, a, g, nullptr);
+    z4c_geom<TS, ORD, true>(p, a, g, nullptr);
 #pragma unroll
     for (int c = 0; c < kZ4cGeo; ++c) geo[p.o + c * a.vstride] = g[c];
   });
+}
+
+// Derivative pass (FP64): every first and second derivative the curvature
+// and evolution passes read, formed with the same stencils as the tap form
+// (so the same bits) and stored at once.  Each variable's block around a
+// slab of at most two planes of the tile (the stencil reach H on every side)
+// is staged in LDS, so a point's 63 taps per variable come from LDS and every
+// stage-vector value is read from memory once per slab; few registers are
+// live, so several waves per SIMD run.  A tile slab whose block does not fit
+// takes its taps from memory instead.
+// LDS block in doubles: a 16 x 16 x 2 slab at H = 4; any slab of at most 256
+// points per plane and at most 64 wide at H = 2
+template <int ORD> constexpr int kDerLds = ORD == 8 ? 6144 : 3328;
+template <int ORD>
+__global__ __launch_bounds__(256) void k_z4c_derivs(Z4cArgs a) {
+  __shared__ double blk[kDerLds<ORD>];
+  constexpr int H = ORD == 8 ? 4 : 2;   // reach of the first and mixed differences
+  constexpr int ZS = 2;                 // planes per slab
+  const double h = a.h;
+  const double c1 = 1.0 / ((ORD == 8 ? 840.0 : 12.0) * h);
+  const double c2 = 1.0 / ((ORD == 8 ? 5040.0 : 12.0) * h * h);
+  // the 16 variables with stored first derivatives; the first 11 of them in
+  // V2 order have stored second derivatives too
+  constexpr int VS[16] = {VG, VG + 1, VG + 2, VG + 3, VG + 4, VG + 5, VW, VALP, VB, VB + 1, VB + 2,
+                          VKH, VTH, VGAM, VGAM + 1, VGAM + 2};
+  for (int t = xcd_first_tile(); t < a.ntiles; t += gridDim.x) {
+    const TileDev T = a.tiles[t];
+    const BoxDev B = a.boxes[T.box];
+    for (int z0 = 0; z0 < T.nz; z0 += ZS) {
+      const int nz = T.nz - z0 < ZS ? T.nz - z0 : ZS;
+      const int bx = T.nx + 2 * H, by = T.ny + 2 * H, bz = nz + 2 * H;
+      const bool fits = bx * by * bz <= kDerLds<ORD>;   // uniform over the workgroup
+#pragma unroll 1
+      for (int n = 0; n < 16; ++n) {
+        const int v = VS[n];
+        if (fits) {
+          __syncthreads();   // the previous variable's block has been read
+          for (int i = threadIdx.x; i < bx * by * bz; i += 256) {
+            const int lx = i % bx, ly = (i / bx) % by, lz = i / (bx * by);
+            const int64_t go = B.base + v * a.vstride +
+                               ((int64_t)(T.z0 + z0 + lz - H + B.pad) * B.py + (T.y0 + ly - H + B.pad)) *
+                                   (int64_t)B.px + (T.x0 + lx - H + B.pad);
+            blk[i] = static_cast<const double*>(a.Y)[go];
+          }
+          __syncthreads();
+        }
+        for (int ixy = threadIdx.x; ixy < T.nx * T.ny; ixy += 256) {   // packed, as in z4c_points
+          const int rx = ixy % T.nx, ry = ixy / T.nx;
+          for (int iz = 0; iz < nz; ++iz) {
+            const int64_t o = B.base + ((int64_t)(T.z0 + z0 + iz + B.pad) * B.py + (T.y0 + ry + B.pad)) *
+                                           (int64_t)B.px + (T.x0 + rx + B.pad);
+            auto emit = [&](const auto& p) {
+#pragma unroll
+              for (int k = 0; k < 3; ++k) a.der[o + der1_slot(v, k) * a.vstride] = p.d1(v, k, c1);
+              if (n < 11)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                  for (int l = k; l < 3; ++l)
+                    a.der[o + der2_slot(v, k, l) * a.vstride] = p.dd(v, k, l, c1, c2);
+            };
+            if (fits) {
+              Pt<double, ORD, false, true> p;
+              p.lds = blk;
+              p.lpx = bx;
+              p.lpxy = bx * by;
+              p.lo = ((iz + H) * by + (ry + H)) * bx + (rx + H);
+              emit(p);
+            } else {
+              Pt<double, ORD> p;
+              p.a = &a;
+              p.px = B.px;
+              p.pxy = (int64_t)B.px * B.py;
+              p.o = o;
+              emit(p);
+            }
+          }
+        }
+      }
+    }
+  }
 }
 
 // Gauge, constraint-damping and source terms of the right-hand side (no
@@ -554,16 +661,34 @@ __global__ __launch_bounds__(kZ4cThreads) void k_z4c_geom(Z4cArgs a) {
 template <typename TS, bool FUSED, int ORD>
 __global__ __launch_bounds__(kZ4cThreads) void k_z4c_stage(Z4cArgs a) {
   TS* kout = static_cast<TS*>(a.kout);
-  z4c_points<TS, ORD>(a, [&](const Pt<TS, ORD>& p) {
+  // FP32 (fused): taps; FP64: derivatives from the derivative pass
+  constexpr bool SCR = !FUSED;
+  z4c_points<TS, ORD, SCR>(a, [&](const Pt<TS, ORD, SCR>& p) {
     TS rhs[NV];
     if constexpr (FUSED) {
       TS g[kZ4cGeo];
-      z4c_geom<TS, ORD>(p, a, g, nullptr);
-      z4c_evol<TS, ORD>(p, a, [&](int c) -> TS { return g[c]; }, rhs);
+      z4c_geom<TS, ORD, SCR>(p, a, g, nullptr);
+      z4c_evol<TS, ORD, SCR>(p, a, [&](int c) -> TS { return g[c]; }, rhs);
     } else {
       const TS* geo = static_cast<const TS*>(a.geo);
-      z4c_evol<TS, ORD>(p, a, [&](int c) -> TS { return geo[p.o + c * a.vstride]; }, rhs);
+      z4c_evol<TS, ORD, SCR>(p, a, [&](int c) -> TS { return geo[p.o + c * a.vstride]; }, rhs);
     }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) kout[p.o + i * a.vstride] = rhs[i];
+  });
+}
+
+// Evolution pass, FP64: k_z4c_stage without the fused curvature, held to two
+// waves per SIMD (it needs a few registers more than half the file).
+template <int ORD>
+__global__ __launch_bounds__(kZ4cThreads) __attribute__((amdgpu_waves_per_eu(2)))
+void k_z4c_evol(Z4cArgs a) {
+  double* kout = static_cast<double*>(a.kout);
+  const double* geo = static_cast<const double*>(a.geo);
+  z4c_points<double, ORD, true>(a, [&](const Pt<double, ORD, true>& p) {
+    double rhs[NV];
+    z4c_evol<double, ORD, true>(p, a, [&](int c) -> double { return geo[p.o + c * a.vstride]; },
+                                rhs);
 #pragma unroll
     for (int i = 0; i < NV; ++i) kout[p.o + i * a.vstride] = rhs[i];
   });
@@ -725,9 +850,10 @@ hipError_t launch_z4c_radiative(const Z4cRadArgs& a, hipStream_t s) {
 
 template <int ORD>
 void z4c_stage_f64(const Z4cArgs& a, dim3 g, dim3 b, dim3 b2, hipStream_t s) {
+  hipLaunchKernelGGL((k_z4c_derivs<ORD>), g, b2, 0, s, a);
   hipLaunchKernelGGL((k_z4c_geom<double, ORD>), g, b, 0, s, a);
   if (!a.ham) {
-    hipLaunchKernelGGL((k_z4c_stage<double, false, ORD>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_z4c_evol<ORD>), g, b, 0, s, a);
     if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, double, ORD>), g, b2, 0, s, a);
     else hipLaunchKernelGGL((k_z4c_advko<1, double, ORD>), g, b2, 0, s, a);
   }
@@ -737,6 +863,7 @@ hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, bool f32, hipStream_t s)
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g(grid > 0 ? grid : a.ntiles), b(kZ4cThreads), b2(256);
   if (a.ord != 4 && a.ord != 8) return hipErrorInvalidValue;
+  if (!f32 && !a.der) return hipErrorInvalidValue;   // FP64 needs the derivative scratch
   if (f32) {
     if (a.ord != 4) return hipErrorInvalidValue;   // the FP32 variant is fourth order
     // FP32: the fused kernel fits the register file; FP64: two passes, since

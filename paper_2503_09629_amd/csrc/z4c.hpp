@@ -10,6 +10,12 @@ constexpr int kZ4cThreads = 128;
 // pass; the level's scratch array holds this many arrays of double.
 constexpr int kZ4cGeo = 24;
 constexpr int kZ4cScratch = kZ4cGeo;
+// Derivative pass (FP64): the first derivatives of W, gt_ij, Khat, Theta,
+// Gt^i, alpha, beta^i (16 variables x 3) and the second derivatives of gt_ij,
+// W, alpha, beta^i (11 variables x 6 pairs) that the curvature and evolution
+// passes use, stored per point in the level's padded layout.
+constexpr int kZ4cDer1 = 16 * 3;
+constexpr int kZ4cDer = kZ4cDer1 + 11 * 6;
 
 struct Z4cArgs {
   const TileDev* tiles;
@@ -26,6 +32,7 @@ struct Z4cArgs {
   float* ynew32;      // its FP32 shadow (FP32 variant, stage 4)
   double* ham;        // constraint mode (FP64 only): Hamiltonian constraint out, else null
   void* geo;          // curvature scratch: 24 arrays of TS in the level's padded layout
+  double* der;        // FP64: derivative scratch, kZ4cDer arrays in the level's padded layout
   int64_t vstride;
   double h, dt6, sigma, kappa1, kappa2, eta_c, eta_o, eta_s;
   double origin[3];   // coordinates of global index (0,0,0) of the level
