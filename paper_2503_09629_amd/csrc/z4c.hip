@@ -85,8 +85,8 @@ struct Pt {
       return (((t(-2) - TS(8.0) * t(-1)) + TS(8.0) * t(1)) - t(2)) * c1;
   }
   __device__ TS d1(int v, int d, TS c1) const {
-    if constexpr (SCR)
-      return a->der[o + der1_slot(v, d) * a->vstride];
+    if constexpr (SCR)   // the passes never use the derivatives that are not stored
+      return der1_slot(v, d) < 0 ? TS(0.0) : a->der[o + der1_slot(v, d) * a->vstride];
     else if constexpr (ORD == 8)
       return diff1([&](int j) { return tap(v, d, j); }, c1);
     else   // written out: this form keeps the fourth-order kernels' register allocation
@@ -120,7 +120,8 @@ struct Pt {
   }
   // second derivative (k, l) with k <= l
   __device__ TS dd(int v, int k, int l, TS c1, TS c2) const {
-    if constexpr (SCR) return a->der[o + der2_slot(v, k, l) * a->vstride];
+    if constexpr (SCR)
+      return der2_slot(v, k, l) < 0 ? TS(0.0) : a->der[o + der2_slot(v, k, l) * a->vstride];
     else return k == l ? d2(v, k, c2) : dm(v, k, l, c1);
   }
 };
