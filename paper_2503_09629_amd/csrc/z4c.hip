@@ -132,7 +132,10 @@ struct Pt {
 // (24 values: R and D_i D_j alpha in symmetric order, then Gt^i,
 // Gt^i_jk At^jk, gt^jk d_j d_k beta^i, d_i d_k beta^k), or the Hamiltonian
 // constraint.
-template <typename TS, int ORD, bool SCR>
+// PART 0: all 24 values (or the constraint); 1: R_ij and Gt^i (or the
+// constraint); 2: D_i D_j alpha, Gt^i_jk At^jk and the shift terms.  Each
+// value is computed the same way in every part.
+template <typename TS, int ORD, bool SCR, int PART = 0>
 __device__ void z4c_geom(const Pt<TS, ORD, SCR>& p, const Z4cArgs& a, TS* out, double* ham_out) {
   const TS h = TS(a.h);
   const TS c1 = TS(1.0) / (TS(ORD == 8 ? 840.0 : 12.0) * h);
@@ -195,6 +198,9 @@ __device__ void z4c_geom(const Pt<TS, ORD, SCR>& p, const Z4cArgs& a, TS* out, d
       for (int k = 0; k < 3; ++k) s += gu[j][k] * G[i][j][k];
     Gd[i] = s;
   }
+  const TS dW[3] = {d[VW][0], d[VW][1], d[VW][2]};
+  TS R[3][3], Rs = TS(0.0);
+  if constexpr (PART != 2) {
   // -1/2 gt^lm d_l d_m gt_ij, contracted as each second derivative is formed
   TS Rlap[6];
 #pragma unroll
@@ -214,18 +220,15 @@ __device__ void z4c_geom(const Pt<TS, ORD, SCR>& p, const Z4cArgs& a, TS* out, d
       for (int m = 0; m < 3; ++m) s -= TS(0.5) * gu[l][m] * dd[l][m];
     Rlap[c] = s;
   }
-  TS ddW[3][3], dda[3][3];
+  TS ddW[3][3];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int l = k; l < 3; ++l) {
       ddW[k][l] = p.dd(VW, k, l, c1, c2);
       ddW[l][k] = ddW[k][l];
-      dda[k][l] = p.dd(VALP, k, l, c1, c2);
-      dda[l][k] = dda[k][l];
     }
   // Ricci tensor R_ij = R^W_ij + Rt_ij
-  const TS dW[3] = {d[VW][0], d[VW][1], d[VW][2]};
   TS DDW[3][3], lapW = TS(0.0), dWsq = TS(0.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -244,7 +247,6 @@ __device__ void z4c_geom(const Pt<TS, ORD, SCR>& p, const Z4cArgs& a, TS* out, d
       dWsq += gu[i][j] * dW[i] * dW[j];
     }
   dWsq /= W * W;
-  TS R[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -268,12 +270,12 @@ __device__ void z4c_geom(const Pt<TS, ORD, SCR>& p, const Z4cArgs& a, TS* out, d
       const TS rw = DDW[i][j] / W + gt[i][j] * lapW / W - TS(2.0) * gt[i][j] * dWsq;
       R[i][j] = rw + rt;
     }
-  TS Rs = TS(0.0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) Rs += gu[i][j] * R[i][j];
   Rs *= W * W;
+  }   // PART != 2
   // raised At
   TS Atu[3][3], Atm[3][3], AtA = TS(0.0);
 #pragma unroll
@@ -295,10 +297,30 @@ __device__ void z4c_geom(const Pt<TS, ORD, SCR>& p, const Z4cArgs& a, TS* out, d
 #pragma unroll
     for (int j = 0; j < 3; ++j) AtA += At[i][j] * Atu[i][j];
   const TS Kt = Kh + TS(2.0) * Th;
-  if (ham_out) {
-    *ham_out = (double)(Rs + (TS(2.0) / TS(3.0)) * Kt * Kt - AtA);
-    return;
+  if constexpr (PART != 2) {
+    if (ham_out) {
+      *ham_out = (double)(Rs + (TS(2.0) / TS(3.0)) * Kt * Kt - AtA);
+      return;
+    }
   }
+  if constexpr (PART != 2) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) out[sym(i, j)] = R[i][j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) out[12 + i] = Gd[i];
+  }
+  if constexpr (PART == 1) return;
+  else {
+  TS dda[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = k; l < 3; ++l) {
+      dda[k][l] = p.dd(VALP, k, l, c1, c2);
+      dda[l][k] = dda[k][l];
+    }
   // lapse: D_i D_j alpha with the physical Christoffels
   const TS da[3] = {d[VALP][0], d[VALP][1], d[VALP][2]};
   TS gudW[3];
@@ -336,10 +358,7 @@ __device__ void z4c_geom(const Pt<TS, ORD, SCR>& p, const Z4cArgs& a, TS* out, d
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = i; j < 3; ++j) {
-      out[sym(i, j)] = R[i][j];
-      out[6 + sym(i, j)] = DDa[i][j];
-    }
+    for (int j = i; j < 3; ++j) out[6 + sym(i, j)] = DDa[i][j];
   // shift: gt^jk d_j d_k beta^i and d_j (d_k beta^k)
   TS lapb[3], gdivb[3] = {TS(0.0), TS(0.0), TS(0.0)};
 #pragma unroll
@@ -363,11 +382,11 @@ __device__ void z4c_geom(const Pt<TS, ORD, SCR>& p, const Z4cArgs& a, TS* out, d
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    out[12 + i] = Gd[i];
     out[15 + i] = t2[i];
     out[18 + i] = lapb[i];
     out[21 + i] = gdivb[i];
   }
+  }   // PART != 1
 }
 
 // Evolution pass (one point): every right-hand side except advection and
@@ -555,22 +574,33 @@ __device__ __forceinline__ void z4c_points(const Z4cArgs& a, F point) {
 // (One kernel for both modes: on C5, measured with 16-plane tiles, this
 // allocation ran faster than a constraint-free variant without spills, 3.7
 // against 4.2 s per coarse step, or a split of the pass by output, 4.3 s.)
-template <typename TS, int ORD>
+// Two launches share the work (PART 1: R_ij, Gt^i or the constraint; PART 2:
+// the rest), so each holds about half of the curvature algebra's live values.
+template <typename TS, int ORD, int PART>
 __global__ __launch_bounds__(kZ4cThreads) void k_z4c_geom(Z4cArgs a) {
   TS* geo = static_cast<TS*>(a.geo);
   z4c_points<TS, ORD, true>(a, [&](const Pt<TS, ORD, true>& p) {
-    if constexpr (sizeof(TS) == 8) {
+    if constexpr (sizeof(TS) == 8 && PART == 1) {
       if (a.ham) {
         double hm;
-        z4c_geom<TS, ORD, true>(p, a, nullptr, &hm);
+        z4c_geom<TS, ORD, true, PART>(p, a, nullptr, &hm);
         a.ham[p.o] = hm;
         return;
       }
     }
     TS g[kZ4cGeo];
-    z4c_geom<TS, ORD, true>(p, a, g, nullptr);
+    z4c_geom<TS, ORD, true, PART>(p, a, g, nullptr);
+    if constexpr (PART == 1) {
 #pragma unroll
-    for (int c = 0; c < kZ4cGeo; ++c) geo[p.o + c * a.vstride] = g[c];
+      for (int c = 0; c < 6; ++c) geo[p.o + c * a.vstride] = g[c];
+#pragma unroll
+      for (int c = 12; c < 15; ++c) geo[p.o + c * a.vstride] = g[c];
+    } else {
+#pragma unroll
+      for (int c = 6; c < 12; ++c) geo[p.o + c * a.vstride] = g[c];
+#pragma unroll
+      for (int c = 15; c < kZ4cGeo; ++c) geo[p.o + c * a.vstride] = g[c];
+    }
   });
 }
 
@@ -852,8 +882,9 @@ hipError_t launch_z4c_radiative(const Z4cRadArgs& a, hipStream_t s) {
 template <int ORD>
 void z4c_stage_f64(const Z4cArgs& a, dim3 g, dim3 b, dim3 b2, hipStream_t s) {
   hipLaunchKernelGGL((k_z4c_derivs<ORD>), g, b2, 0, s, a);
-  hipLaunchKernelGGL((k_z4c_geom<double, ORD>), g, b, 0, s, a);
+  hipLaunchKernelGGL((k_z4c_geom<double, ORD, 1>), g, b, 0, s, a);
   if (!a.ham) {
+    hipLaunchKernelGGL((k_z4c_geom<double, ORD, 2>), g, b, 0, s, a);
     hipLaunchKernelGGL((k_z4c_evol<ORD>), g, b, 0, s, a);
     if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, double, ORD>), g, b2, 0, s, a);
     else hipLaunchKernelGGL((k_z4c_advko<1, double, ORD>), g, b2, 0, s, a);

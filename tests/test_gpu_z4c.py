@@ -109,7 +109,7 @@ def test_z4c_hamiltonian_constraint_matches_reference():
         b = ref.hamiltonian(l)
         e = np.abs(a - b).max() / np.abs(b).max()
         print("level", l, "H max", np.abs(b).max(), "rel diff", e)
-        assert e <= 1e-10
+        assert e <= TOL
 
 
 def test_z4c_fp32_rhs_variant_within_bound():
@@ -168,7 +168,9 @@ def test_z4c_radiative_boundary_matches_reference(exec):
     if exec == sc.SC_EXEC_BATCHED:
         for l in range(spec.nlevels):
             a, b = ctx.hamiltonian(0, l), ref.hamiltonian(l)
-            assert np.abs(a - b).max() / np.abs(b).max() <= 1e-10
+            e = np.abs(a - b).max() / np.abs(b).max()
+            print("level", l, "H rel diff", e)
+            assert e <= TOL
 
 
 @pytest.mark.parametrize("exec", [sc.SC_EXEC_BATCHED, sc.SC_EXEC_GRAPH])
@@ -185,7 +187,9 @@ def test_z4c_eighth_order_matches_reference(exec, bc):
     if exec == sc.SC_EXEC_BATCHED:
         for l in range(spec.nlevels):
             a, b = ctx.hamiltonian(0, l), ref.hamiltonian(l)
-            assert np.abs(a - b).max() / np.abs(b).max() <= 1e-10
+            e = np.abs(a - b).max() / np.abs(b).max()
+            print("level", l, "H rel diff", e)
+            assert e <= TOL
 
 
 def test_z4c_tile_shape_can_be_set_back():
