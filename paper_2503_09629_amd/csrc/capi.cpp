@@ -323,14 +323,23 @@ std::string build_layout(sc_ctx* c) {
       pro0.push_back(e);
     }
     const int npb = l > 0 ? c->lev[l - 1].nb_member : 0;
-    // group RB halo slots (and buffer points) into bricks of at most 8^3 fine points (cells of a
-    // global 8-point lattice, shrunk to the bounding box of their RB slots);
-    // slots that wrap periodically or whose brick spans two parent boxes stay
-    // per point
+    // group RB halo slots (and buffer points) into bricks: the slots of each
+    // face of a fine box form slabs of the shell's full thickness by up to
+    // kBrickDim points along the face (the face cut into near-equal chunks
+    // whose starts are even), edge pieces and corners likewise; buffer points
+    // inside the box go into cells of a box-local 8-point lattice.  A group
+    // too large for one brick is cut into 8-point cells.  Slots that wrap
+    // periodically or whose stencils span two parent boxes stay per point.
     std::vector<ProlongEntry> rest0;
     std::vector<ProlongBrick> bricks0;
     {
-      std::map<std::array<int64_t, 4>, std::vector<size_t>> cells;  // (box, cell) -> slots
+      auto chunk = [](int p, int n) {   // face chunks of 16 points, the last up to 17
+        const int nc = std::max(1, (n - 1 + 15) / 16);
+        return std::min(p / 16, nc - 1);
+      };
+      // key: box, kind (0 shell, 1 inside), side code, then per-dimension chunk or cell
+      std::map<std::array<int64_t, 6>, std::vector<size_t>> groups;
+      std::vector<std::array<int, 4>> where(pro0.size());   // box and box-local point
       for (size_t i = 0; i < pro0.size(); ++i) {
         const ProlongEntry& e = pro0[i];
         int ib = -1;
@@ -340,36 +349,45 @@ std::string build_layout(sc_ctx* c) {
             ib = b;
         const BoxDev& B = b0[ib];
         const int64_t r = e.dst - B.base;
-        const int64_t hx = r % B.px - G, hy = (r / B.px) % B.py - G, hz = r / ((int64_t)B.px * B.py) - G;
-        const int64_t p[3] = {B.lo[0] + hx, B.lo[1] + hy, B.lo[2] + hz};
-        if (p[0] != e.q[0] || p[1] != e.q[1] || p[2] != e.q[2]) {
+        const int hx = (int)(r % B.px) - G, hy = (int)((r / B.px) % B.py) - G,
+                  hz = (int)(r / ((int64_t)B.px * B.py)) - G;
+        if (B.lo[0] + hx != e.q[0] || B.lo[1] + hy != e.q[1] || B.lo[2] + hz != e.q[2]) {
           rest0.push_back(e);
           continue;
         }
-        cells[{(int64_t)ib, p[0] >> 3, p[1] >> 3, p[2] >> 3}].push_back(i);
+        where[i] = {ib, hx, hy, hz};
+        const int h[3] = {hx, hy, hz}, bn[3] = {B.nx, B.ny, B.nz};
+        int side = 0, outside = 0;
+        int64_t c[3];
+        for (int d = 2; d >= 0; --d) {
+          const int sd = h[d] < 0 ? 1 : (h[d] >= bn[d] ? 2 : 0);
+          side = side * 3 + sd;
+          outside |= sd;
+          c[d] = sd ? 0 : chunk(h[d], bn[d]);
+        }
+        if (!outside)
+          groups[{(int64_t)ib, 1, 0, h[2] >> 3, h[1] >> 3, h[0] >> 3}].push_back(i);
+        else
+          groups[{(int64_t)ib, 0, side, c[2], c[1], c[0]}].push_back(i);
       }
-      for (auto& kv : cells) {
-        const auto& idx = kv.second;
+      auto emit = [&](const std::vector<size_t>& idx) -> bool {
         const int pb = pro0[idx[0]].pbox;
-        bool same = true;
         int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
         for (size_t i : idx) {
-          same = same && pro0[i].pbox == pb;
+          if (pro0[i].pbox != pb) return false;
           for (int d = 0; d < 3; ++d) {
             lo[d] = std::min(lo[d], pro0[i].q[d]);
             hi[d] = std::max(hi[d], pro0[i].q[d]);
           }
         }
-        if (!same) {
-          for (size_t i : idx) rest0.push_back(pro0[i]);
-          continue;
-        }
+        int n[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
+        if (!sc::brick_fits(lo, n)) return false;
         ProlongBrick bk{};
-        bk.fbox = (int32_t)kv.first[0];
+        bk.fbox = where[idx[0]][0];
         bk.pbox = pb;
         for (int d = 0; d < 3; ++d) {
           bk.a[d] = lo[d];
-          bk.n[d] = hi[d] - lo[d] + 1;
+          bk.n[d] = n[d];
         }
         for (size_t i : idx) {
           const int fx = pro0[i].q[0] - lo[0], fy = pro0[i].q[1] - lo[1], fz = pro0[i].q[2] - lo[2];
@@ -377,6 +395,16 @@ std::string build_layout(sc_ctx* c) {
           bk.mask[bit >> 6] |= uint64_t(1) << (bit & 63);
         }
         bricks0.push_back(bk);
+        return true;
+      };
+      for (auto& kv : groups) {
+        if (emit(kv.second)) continue;
+        std::map<std::array<int, 3>, std::vector<size_t>> cells;   // box-local 8-point cells
+        for (size_t i : kv.second)
+          cells[{where[i][3] >> 3, where[i][2] >> 3, where[i][1] >> 3}].push_back(i);
+        for (auto& ck : cells)
+          if (!emit(ck.second))
+            for (size_t i : ck.second) rest0.push_back(pro0[i]);
       }
     }
     for (int m = 0; m < nm; ++m) {
@@ -388,6 +416,7 @@ std::string build_layout(sc_ctx* c) {
         L.prolong.push_back(e);
       }
       for (auto bk : bricks0) {
+        L.brick_max_pts = std::max(L.brick_max_pts, bk.n[0] * bk.n[1] * bk.n[2]);
         bk.fbox += m * L.nb_member;
         bk.pbox += m * npb;
         L.bricks.push_back(bk);
@@ -594,9 +623,13 @@ std::string validate_layout(const sc_ctx* c) {
           return "brick box out of range";
         const BoxDev& F = L.boxes[bk.fbox];
         const int fn[3] = {F.nx, F.ny, F.nz};
+        if (!sc::brick_fits(bk.a, bk.n)) return "brick exceeds the kernel's limits";
+        const BoxDev& Pb = P.boxes[bk.pbox];
+        if ((int64_t)F.px * F.py * (F.nz + 2 * G) >= (int64_t(1) << 32) ||
+            (int64_t)Pb.px * Pb.py * (Pb.nz + 2 * G) >= (int64_t(1) << 32))
+          return "box too large for the bricks' 32-bit offsets";
         for (int d = 0; d < 3; ++d)
-          if (bk.n[d] < 1 || bk.n[d] > 8 || bk.a[d] < 0 || bk.a[d] - F.lo[d] < -G ||
-              bk.a[d] + bk.n[d] - 1 - F.lo[d] >= fn[d] + G)
+          if (bk.a[d] < 0 || bk.a[d] - F.lo[d] < -G || bk.a[d] + bk.n[d] - 1 - F.lo[d] >= fn[d] + G)
             return "brick outside its fine box halo";
         for (int z = 0; z < bk.n[2]; ++z)
           for (int y = 0; y < bk.n[1]; ++y)
@@ -972,6 +1005,7 @@ int prolong_into(sc_ctx* c, int fl, const ProlongEntry* entries, const int64_t* 
     BrickArgs b{};
     b.b = F.d_bricks;
     b.nbricks = (int32_t)F.bricks.size();
+    b.max_pts = F.brick_max_pts;
     b.nout = nout;
     b.nvars = c->nvars;
     b.fboxes = F.d_boxes;
@@ -1067,6 +1101,7 @@ int prolongate_buffer(sc_ctx* c, int fl, int sub) {
     BrickArgs b{};
     b.b = F.d_bricks;
     b.nbricks = (int32_t)F.bricks.size();
+    b.max_pts = F.brick_max_pts;
     b.nout = 2;
     b.nvars = c->nvars;
     b.fboxes = F.d_boxes;

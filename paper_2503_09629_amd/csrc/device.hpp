@@ -53,15 +53,42 @@ struct ProlongEntry {   // refinement-boundary halo point
 };
 
 // A brick of refinement-boundary halo points of one fine box: the fine
-// index range [a, a + n) (n <= 8 per dimension), the parent box holding every
-// stencil of its RB points, and a bitmask of which points are RB slots
-// (bit (z * n_y + y) * n_x + x).
+// index range [a, a + n), the parent box holding every stencil of its RB
+// points, and a bitmask of which points are RB slots (bit (z * n_y + y) *
+// n_x + x).  Bricks are face slabs of the RB shell (its full thickness by at
+// most kBrickDim points along the face), edge pieces and corners; the parent
+// region under a brick, its x-interpolated and its xy-interpolated planes
+// must fit the LDS and per-thread limits below (brick_fits).
+constexpr int kBrickThreads = 512;
+constexpr int kBrickDim = 17;                      // fine points per dimension
+constexpr int kBrickPts = 3 * kBrickThreads;       // fine points per brick
+constexpr int kBrickV = 4 * kBrickThreads;         // parent points under a brick
+constexpr int kBrickPX = 4 * kBrickThreads;        // after the x pass
+constexpr int kBrickPY = 5 * kBrickThreads;        // after the y pass
+constexpr int kBrickLds = 6144;                    // V + PX + PY doubles
 struct ProlongBrick {
   int32_t fbox, pbox;
   int32_t a[3];
   int32_t n[3];
-  uint64_t mask[8];
+  uint64_t mask[kBrickPts / 64];
 };
+
+// Parent points per dimension under the fine range [a, a + n) (a >= 0): from
+// the first stencil start to the last stencil end of the degree-5 operator.
+inline __host__ __device__ int brick_parent_first(int a) { return (a >> 1) - 2; }
+inline __host__ __device__ int brick_parent_count(int a, int n) {
+  return ((a + n - 1) >> 1) + 3 - brick_parent_first(a) + 1;
+}
+inline bool brick_fits(const int a[3], const int n[3]) {
+  int cn[3];
+  for (int d = 0; d < 3; ++d) {
+    if (n[d] < 1 || n[d] > kBrickDim) return false;
+    cn[d] = brick_parent_count(a[d], n[d]);
+  }
+  const int nv = cn[0] * cn[1] * cn[2], npx = cn[2] * cn[1] * n[0], npy = cn[2] * n[1] * n[0];
+  return n[0] * n[1] * n[2] <= kBrickPts && nv <= kBrickV && npx <= kBrickPX &&
+         npy <= kBrickPY && nv + npx + npy <= kBrickLds;
+}
 
 struct RestrictRegion {
   int32_t fbox, pbox;
@@ -139,6 +166,7 @@ struct ProlongArgs {
 struct BrickArgs {
   const ProlongBrick* b;
   int32_t nbricks;
+  int32_t max_pts;     // largest n_x n_y n_z over the bricks (picks the kernel variant)
   int32_t nout;
   int32_t nvars;
   const BoxDev* fboxes;

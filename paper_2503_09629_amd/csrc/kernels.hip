@@ -496,22 +496,18 @@ __global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
   }
 }
 
-// Brick prolongation: one workgroup per brick.  For each variable and each
-// of the five vectors, the coarse region under the brick (at most 10^3
-// points) is staged in LDS, interpolated along x for every fine x of the
-// brick, then along y, then along z (the same left-to-right sums as the
-// per-point form, so the values are identical), and the eight dense-output
-// combinations are written for the brick's RB points.  Each thread's share
-// of every pass (source and destination places in LDS) is worked out once
-// per brick; the coarse values of all five vectors of the next variable are
-// loaded into registers while the current variable is interpolated.
-constexpr int kBrick = 8, kBrickC = 10;
-constexpr int kBrickLoads = (kBrickC * kBrickC * kBrickC + 255) / 256;   // per thread and vector
-constexpr int kBrickXE = (kBrickC * kBrickC * kBrick + 255) / 256;       // x-pass outputs per thread
-constexpr int kBrickYE = (kBrickC * kBrick * kBrick + 255) / 256;        // y-pass outputs per thread
-constexpr int kBrickZE = (kBrick * kBrick * kBrick + 255) / 256;         // fine points per thread
-
-// 6-point Lagrange value at the midpoint, or a copy, from src[0], src[st], ...
+// Brick prolongation: one workgroup per brick (a face slab, edge piece or
+// corner of a fine box's RB shell).  For each variable and each of the input
+// vectors, the parent region under the brick is staged in LDS, interpolated
+// along x for every fine x of the brick, then along y, then along z (the same
+// left-to-right sums as the per-point form, so the values are identical), and
+// the dense-output combinations are written for the brick's RB points.  Each
+// vector's parent values for the next variable are loaded as soon as the
+// current ones are in LDS, so they have the rest of the variable's passes to
+// arrive.  Each thread's share of the three passes is worked out once per
+// brick and packed as (source place, odd, in range): the destination of
+// entry i of a pass is place i of that pass's array.  ZE: fine points per
+// thread (2 covers the three-layer shell's slabs, 3 the four-layer one's).
 __device__ __forceinline__ double brick_tap(const double* src, int st, bool odd) {
   constexpr double W[6] = {3.0 / 256.0, -25.0 / 256.0, 150.0 / 256.0,
                            150.0 / 256.0, -25.0 / 256.0, 3.0 / 256.0};
@@ -522,138 +518,140 @@ __device__ __forceinline__ double brick_tap(const double* src, int st, bool odd)
   return r;
 }
 
-template <int NIN, typename TK>
-__global__ __launch_bounds__(256) void k_prolong_bricks(BrickArgs a) {
-  __shared__ double V[kBrickC * kBrickC * kBrickC];     // [cz][cy][cx]
-  __shared__ double PX[kBrickC * kBrickC * kBrick];     // [cz][cy][fx]
-  __shared__ double PY[kBrickC * kBrick * kBrick];      // [cz][fy][fx]
-  constexpr int NL = kBrickLoads, XE = kBrickXE, YE = kBrickYE, ZE = kBrickZE;
+// i / d for i * d < 2^20, with m = brick_magic(d): i m / 2^20 exceeds i / d
+// by less than i / 2^20 < 1 / d, which cannot carry it past the next integer.
+__device__ __forceinline__ unsigned brick_magic(unsigned d) { return (1u << 20) / d + 1u; }
+__device__ __forceinline__ unsigned brick_div(unsigned i, unsigned m) { return (i * m) >> 20; }
+
+constexpr unsigned kTapOdd = 1u << 12, kTapOn = 1u << 13, kTapWrite = 1u << 14;
+constexpr unsigned kNoPoint = 0xffffffffu;
+
+template <int NIN, typename TK, int ZE>
+__global__ __launch_bounds__(kBrickThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_prolong_bricks(BrickArgs a) {
+  constexpr int NT = kBrickThreads;
+  constexpr int NL = kBrickV / NT, XE = kBrickPX / NT, YE = kBrickPY / NT;
+  static_assert(kBrickV % NT == 0 && kBrickPX % NT == 0 && kBrickPY % NT == 0 &&
+                ZE * NT <= kBrickPts && kBrickPY < 4096, "brick limits");
+  __shared__ double S[kBrickLds];
   // consecutive workgroups land on different XCDs; give each XCD a
-  // contiguous run of bricks so overlapping coarse regions share its L2
+  // contiguous run of bricks so overlapping parent regions share its L2
   const int g = (gridDim.x % 8 == 0)
                     ? (int)(blockIdx.x % 8) * (int)(gridDim.x / 8) + (int)(blockIdx.x / 8)
                     : (int)blockIdx.x;
   if (g >= a.nbricks) return;
-  const ProlongBrick Bk = a.b[g];
+  const ProlongBrick& Bk = a.b[g];
+  const int ba[3] = {Bk.a[0], Bk.a[1], Bk.a[2]};
+  const int n0 = Bk.n[0], n1 = Bk.n[1], n2 = Bk.n[2];
   const BoxDev F = a.fboxes[Bk.fbox];
   const BoxDev P = a.pboxes[Bk.pbox];
   int C0[3], cn[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    C0[d] = (Bk.a[d] >> 1) - 2;                       // a >= 0: shift is floor
-    cn[d] = ((Bk.a[d] + Bk.n[d] - 1) >> 1) + 3 - C0[d] + 1;
+    C0[d] = brick_parent_first(ba[d]);
+    cn[d] = brick_parent_count(ba[d], Bk.n[d]);
   }
-  const int n0 = Bk.n[0], n1 = Bk.n[1];
+  const int nv = cn[0] * cn[1] * cn[2], npx = cn[2] * cn[1] * n0, npy = cn[2] * n1 * n0;
+  const int n01 = n0 * n1, npts = n01 * n2;
+  double* V = S;                 // [cz][cy][cx]
+  double* PX = S + nv;           // [cz][cy][fx]
+  double* PY = PX + npx;         // [cz][fy][fx]
   const int pn[3] = {P.nx, P.ny, P.nz};
-  const int64_t pitch[3] = {1, (int64_t)P.px, (int64_t)P.px * P.py};
-  const int npts = n0 * n1 * Bk.n[2];
-  const int ncoarse = cn[0] * cn[1] * cn[2];
+  const unsigned pitch[3] = {1u, (unsigned)P.px, (unsigned)P.px * (unsigned)P.py};
   const int tid = threadIdx.x;
-  // coarse points of this thread: offset in the parent arrays (periodic wrap,
-  // then clamped into the padded box) and place in V
-  int64_t co[NL];
-  int vi[NL];
+  // parent points of this thread (place tid + j NT of V): offset from the
+  // parent box's base (periodic wrap, then clamped into the padded box)
+  unsigned co[NL];
 #pragma unroll
   for (int j = 0; j < NL; ++j) {
-    const int i = tid + j * 256;
-    const int ic = i < ncoarse ? i : 0;
-    const int c[3] = {ic % cn[0], (ic / cn[0]) % cn[1], ic / (cn[0] * cn[1])};
-    int64_t o = P.base;
+    const int i = tid + j * NT;
+    const int c[3] = {i % cn[0], (i / cn[0]) % cn[1], i / (cn[0] * cn[1])};
+    unsigned o = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       int I = C0[d] + c[d];
       if (P.wrapN[d] > 0) I = ((I % P.wrapN[d]) + P.wrapN[d]) % P.wrapN[d];
       int loc = I - P.lo[d];
       loc = loc < -P.pad ? -P.pad : (loc > pn[d] + P.pad - 1 ? pn[d] + P.pad - 1 : loc);
-      o += (int64_t)(loc + P.pad) * pitch[d];
+      o += (unsigned)(loc + P.pad) * pitch[d];
     }
-    co[j] = o;
-    vi[j] = i < ncoarse ? (c[2] * kBrickC + c[1]) * kBrickC + c[0] : -1;
+    co[j] = i < nv ? o : kNoPoint;
   }
-  // pass assignments: source base and stride in the input array, output place
-  int xs[XE], xd[XE], ys[YE], yd[YE], zs[ZE];
-  bool xo[XE], yo[YE], zo[ZE];
+  const unsigned m0 = brick_magic(n0), m1 = brick_magic(n1), m01 = brick_magic(n01);
+  unsigned xa[XE], ya[YE], za[ZE], dst[ZE];
 #pragma unroll
-  for (int e = 0; e < XE; ++e) {
-    const int i = tid + e * 256;
-    const bool ok = i < cn[2] * cn[1] * n0;
-    const int ic = ok ? i : 0;
-    const int fx = ic % n0, cy = (ic / n0) % cn[1], cz = ic / (n0 * cn[1]);
-    const int q = Bk.a[0] + fx, b = (q >> 1) - C0[0];
-    xo[e] = q & 1;
-    xs[e] = (cz * kBrickC + cy) * kBrickC + (xo[e] ? b - 2 : b);
-    xd[e] = ok ? (cz * kBrickC + cy) * kBrick + fx : -1;
+  for (int e = 0; e < XE; ++e) {            // PX place i = r n0 + fx, r = cz cn1 + cy
+    const unsigned i = tid + e * NT, r = brick_div(i, m0), fx = i - r * n0;
+    const int q = ba[0] + (int)fx, b = (q >> 1) - C0[0] - ((q & 1) ? 2 : 0);
+    xa[e] = (int)i < npx ? (r * cn[0] + b) | ((q & 1) ? kTapOdd : 0u) | kTapOn : 0u;
   }
 #pragma unroll
-  for (int e = 0; e < YE; ++e) {
-    const int i = tid + e * 256;
-    const bool ok = i < cn[2] * n1 * n0;
-    const int ic = ok ? i : 0;
-    const int fx = ic % n0, fy = (ic / n0) % n1, cz = ic / (n0 * n1);
-    const int q = Bk.a[1] + fy, b = (q >> 1) - C0[1];
-    yo[e] = q & 1;
-    ys[e] = (cz * kBrickC + (yo[e] ? b - 2 : b)) * kBrick + fx;
-    yd[e] = ok ? (cz * kBrick + fy) * kBrick + fx : -1;
+  for (int e = 0; e < YE; ++e) {            // PY place i = (cz n1 + fy) n0 + fx
+    const unsigned i = tid + e * NT, t = brick_div(i, m0), fx = i - t * n0;
+    const unsigned cz = brick_div(t, m1), fy = t - cz * n1;
+    const int q = ba[1] + (int)fy, b = (q >> 1) - C0[1] - ((q & 1) ? 2 : 0);
+    ya[e] = (int)i < npy ? ((cz * cn[1] + b) * n0 + fx) | ((q & 1) ? kTapOdd : 0u) | kTapOn : 0u;
   }
-  int64_t dst[ZE];
-  bool zw[ZE];
 #pragma unroll
-  for (int e = 0; e < ZE; ++e) {
-    const int i = tid + e * 256;
-    const bool ok = i < npts;
-    const int ic = ok ? i : 0;
-    const int fx = ic % n0, fy = (ic / n0) % n1, fz = ic / (n0 * n1);
-    const int q = Bk.a[2] + fz, b = (q >> 1) - C0[2];
-    zo[e] = q & 1;
-    zs[e] = ((zo[e] ? b - 2 : b) * kBrick + fy) * kBrick + fx;
-    zw[e] = ok && ((a.b[g].mask[ic >> 6] >> (ic & 63)) & 1);
-    dst[e] = F.base + ((int64_t)(Bk.a[2] + fz - F.lo[2] + F.pad) * F.py + (Bk.a[1] + fy - F.lo[1] + F.pad)) *
-                          (int64_t)F.px + (Bk.a[0] + fx - F.lo[0] + F.pad);
+  for (int e = 0; e < ZE; ++e) {            // fine point i = fz n01 + (fy n0 + fx)
+    const unsigned i = tid + e * NT, fz = brick_div(i, m01), j = i - fz * n01;
+    const unsigned fy = brick_div(j, m0), fx = j - fy * n0;
+    const int q = ba[2] + (int)fz, b = (q >> 1) - C0[2] - ((q & 1) ? 2 : 0);
+    const bool on = (int)i < npts;
+    const bool w = on && ((Bk.mask[i >> 6] >> (i & 63)) & 1);
+    za[e] = on ? (b * n01 + j) | ((q & 1) ? kTapOdd : 0u) | kTapOn | (w ? kTapWrite : 0u) : 0u;
+    dst[e] = ((unsigned)(ba[2] + (int)fz - F.lo[2] + F.pad) * (unsigned)F.py +
+              (unsigned)(ba[1] + (int)fy - F.lo[1] + F.pad)) * (unsigned)F.px +
+             (unsigned)(ba[0] + (int)fx - F.lo[0] + F.pad);
   }
-  auto load_var = [&](int v, double (&R)[NIN][NL]) {
-    const int64_t vo = (int64_t)v * a.pvstride;
-#pragma unroll
-    for (int j = 0; j < NL; ++j) R[0][j] = a.py[co[j] + vo];
-#pragma unroll
-    for (int m = 1; m < NIN; ++m)
+  const int sty = n0, stz = n01;
+  auto load = [&](int v, int m, double (&R)[NL]) {
+    const int64_t vo = P.base + (int64_t)v * a.pvstride;
+    if (m == 0) {
+      const double* src = a.py + vo;
 #pragma unroll
       for (int j = 0; j < NL; ++j)
-        R[m][j] = (double)static_cast<const TK*>(a.pk[m - 1])[co[j] + vo];
+        if (co[j] != kNoPoint) R[j] = src[co[j]];
+    } else {
+      const TK* src = static_cast<const TK*>(a.pk[m - 1]) + vo;
+#pragma unroll
+      for (int j = 0; j < NL; ++j)
+        if (co[j] != kNoPoint) R[j] = (double)src[co[j]];
+    }
   };
-  double R[NIN][NL], Rn[NIN][NL];
-  load_var(0, R);
+  double R[NIN][NL];
+#pragma unroll
+  for (int m = 0; m < NIN; ++m) load(0, m, R[m]);
   for (int v = 0; v < a.nvars; ++v) {
-    load_var(v + 1 < a.nvars ? v + 1 : v, Rn);   // in flight while v is interpolated
     double Pv[ZE][NIN];
 #pragma unroll
     for (int m = 0; m < NIN; ++m) {
 #pragma unroll
       for (int j = 0; j < NL; ++j)
-        if (vi[j] >= 0) V[vi[j]] = R[m][j];
+        if (co[j] != kNoPoint) V[tid + j * NT] = R[m][j];
       __syncthreads();
+      if (v + 1 < a.nvars) load(v + 1, m, R[m]);   // in flight for the rest of this variable
 #pragma unroll
       for (int e = 0; e < XE; ++e)
-        if (xd[e] >= 0) PX[xd[e]] = brick_tap(V + xs[e], 1, xo[e]);
+        if (xa[e] & kTapOn) PX[tid + e * NT] = brick_tap(V + (xa[e] & 4095u), 1, xa[e] & kTapOdd);
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < YE; ++e)
-        if (yd[e] >= 0) PY[yd[e]] = brick_tap(PX + ys[e], kBrick, yo[e]);
+        if (ya[e] & kTapOn) PY[tid + e * NT] = brick_tap(PX + (ya[e] & 4095u), sty, ya[e] & kTapOdd);
       __syncthreads();
 #pragma unroll
-      for (int e = 0; e < ZE; ++e) Pv[e][m] = brick_tap(PY + zs[e], kBrick * kBrick, zo[e]);
+      for (int e = 0; e < ZE; ++e)
+        Pv[e][m] = (za[e] & kTapOn) ? brick_tap(PY + (za[e] & 4095u), stz, za[e] & kTapOdd) : 0.0;
     }
+    const int64_t ob = F.base + (int64_t)v * a.ovstride;
 #pragma unroll
     for (int e = 0; e < ZE; ++e) {
-      if (!zw[e]) continue;
-      const int64_t d = dst[e] + v * a.ovstride;
+      if (!(za[e] & kTapWrite)) continue;
+      const int64_t d = ob + dst[e];
       for (int o = 0; o < a.nout; ++o)
         store_out(a.out[o], d, (a.f32_mask >> o) & 1,
                   prolong_combine<NIN>(Pv[e], a.w[o], a.H, (a.inc_mask >> o) & 1));
     }
-#pragma unroll
-    for (int m = 0; m < NIN; ++m)
-#pragma unroll
-      for (int j = 0; j < NL; ++j) R[m][j] = Rn[m][j];
   }
 }
 
@@ -1044,15 +1042,27 @@ hipError_t launch_prolong(const ProlongArgs& a, bool k_f32, hipStream_t s, int n
 
 hipError_t launch_prolong_bricks(const BrickArgs& a, bool k_f32, hipStream_t s, int nin) {
   if (a.nbricks <= 0) return hipSuccess;
-  const dim3 g((unsigned)((a.nbricks + 7) / 8 * 8)), b(256);   // whole XCD rounds; extra groups exit
+  if (a.max_pts > 3 * kBrickThreads) return hipErrorInvalidValue;
+  const dim3 g((unsigned)((a.nbricks + 7) / 8 * 8)), b(kBrickThreads);   // whole XCD rounds; extra groups exit
+  const bool ze2 = a.max_pts <= 2 * kBrickThreads;
   if (nin != 5) {   // buffer zones: FP64 state vectors only
     if (k_f32 || a.f32_mask || a.inc_mask || (nin != 1 && nin != 3)) return hipErrorInvalidValue;
-    if (nin == 1) hipLaunchKernelGGL((k_prolong_bricks<1, double>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_prolong_bricks<3, double>), g, b, 0, s, a);
+    if (nin == 1) {
+      if (ze2) hipLaunchKernelGGL((k_prolong_bricks<1, double, 2>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_prolong_bricks<1, double, 3>), g, b, 0, s, a);
+    } else {
+      if (ze2) hipLaunchKernelGGL((k_prolong_bricks<3, double, 2>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_prolong_bricks<3, double, 3>), g, b, 0, s, a);
+    }
     return hipGetLastError();
   }
-  if (k_f32) hipLaunchKernelGGL((k_prolong_bricks<5, float>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_prolong_bricks<5, double>), g, b, 0, s, a);
+  if (k_f32) {
+    if (ze2) hipLaunchKernelGGL((k_prolong_bricks<5, float, 2>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_prolong_bricks<5, float, 3>), g, b, 0, s, a);
+  } else {
+    if (ze2) hipLaunchKernelGGL((k_prolong_bricks<5, double, 2>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_prolong_bricks<5, double, 3>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ struct LevelDev {
   std::vector<int64_t> prefix;       // canonical prefix per member box (nb_member + 1)
   std::vector<SyncEntry> sync;
   std::vector<ProlongBrick> bricks;   // RB halo slots grouped in bricks (all members)
+  int brick_max_pts = 0;              // largest brick (fine points of its index box)
   std::vector<ProlongEntry> prolong; // remaining RB halo slots, sorted by parity class
   int64_t prolong_cls[9] = {0};      // class prefix of `prolong`
   int64_t rblist_cls[9] = {0};       // class prefix of one member's `rblist`
