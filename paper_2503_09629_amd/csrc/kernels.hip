@@ -505,8 +505,8 @@ __global__ __launch_bounds__(256) void k_prolong(ProlongArgs a) {
 // vector's parent values for the next variable are loaded as soon as the
 // current ones are in LDS, so they have the rest of the variable's passes to
 // arrive.  Each thread's share of the three passes is worked out once per
-// brick and packed as (source place, odd, in range): the destination of
-// entry i of a pass is place i of that pass's array.  ZE: fine points per
+// brick and packed as (source place, destination place, odd, in range); in
+// the z pass the destination of entry i is fine point i.  ZE: fine points per
 // thread (2 covers the three-layer shell's slabs, 3 the four-layer one's).
 __device__ __forceinline__ double brick_tap(const double* src, int st, bool odd) {
   constexpr double W[6] = {3.0 / 256.0, -25.0 / 256.0, 150.0 / 256.0,
@@ -524,6 +524,7 @@ __device__ __forceinline__ unsigned brick_magic(unsigned d) { return (1u << 20) 
 __device__ __forceinline__ unsigned brick_div(unsigned i, unsigned m) { return (i * m) >> 20; }
 
 constexpr unsigned kTapOdd = 1u << 12, kTapOn = 1u << 13, kTapWrite = 1u << 14;
+constexpr unsigned kPassOdd = 1u << 24, kPassOn = 1u << 25;
 constexpr unsigned kNoPoint = 0xffffffffu;
 
 template <int NIN, typename TK, int ZE>
@@ -577,20 +578,37 @@ void k_prolong_bricks(BrickArgs a) {
     }
     co[j] = i < nv ? o : kNoPoint;
   }
-  const unsigned m0 = brick_magic(n0), m1 = brick_magic(n1), m01 = brick_magic(n01);
+  const unsigned m0 = brick_magic(n0), m01 = brick_magic(n01);
+  // x and y passes: the entries whose fine index is even (copies) come first,
+  // then the odd ones (six-point sums), so that a wave's lanes take one branch
+  const int ex = ba[0] & 1, nex = (n0 - ex + 1) >> 1, nox = n0 - nex;   // first even fx, counts
+  const int ey = ba[1] & 1, ney = (n1 - ey + 1) >> 1, noy = n1 - ney;
+  const int rows = cn[2] * cn[1];
+  const unsigned mex = brick_magic(nex > 0 ? nex : 1), mox = brick_magic(nox > 0 ? nox : 1);
+  const unsigned mey = brick_magic(ney > 0 ? ney : 1), moy = brick_magic(noy > 0 ? noy : 1);
   unsigned xa[XE], ya[YE], za[ZE], dst[ZE];
 #pragma unroll
-  for (int e = 0; e < XE; ++e) {            // PX place i = r n0 + fx, r = cz cn1 + cy
-    const unsigned i = tid + e * NT, r = brick_div(i, m0), fx = i - r * n0;
-    const int q = ba[0] + (int)fx, b = (q >> 1) - C0[0] - ((q & 1) ? 2 : 0);
-    xa[e] = (int)i < npx ? (r * cn[0] + b) | ((q & 1) ? kTapOdd : 0u) | kTapOn : 0u;
+  for (int e = 0; e < XE; ++e) {            // PX place r n0 + fx, r = cz cn1 + cy
+    const int i = tid + e * NT;
+    const bool odd = i >= rows * nex;
+    const unsigned ii = odd ? i - rows * nex : i;
+    const unsigned r = brick_div(ii, odd ? mox : mex), k = ii - r * (odd ? nox : nex);
+    const unsigned fx = (odd ? 1 - ex : ex) + 2 * k;
+    const int q = ba[0] + (int)fx, b = (q >> 1) - C0[0] - (odd ? 2 : 0);
+    xa[e] = i < npx ? (r * cn[0] + b) | ((r * n0 + fx) << 12) | (odd ? kPassOdd : 0u) | kPassOn : 0u;
   }
 #pragma unroll
-  for (int e = 0; e < YE; ++e) {            // PY place i = (cz n1 + fy) n0 + fx
-    const unsigned i = tid + e * NT, t = brick_div(i, m0), fx = i - t * n0;
-    const unsigned cz = brick_div(t, m1), fy = t - cz * n1;
-    const int q = ba[1] + (int)fy, b = (q >> 1) - C0[1] - ((q & 1) ? 2 : 0);
-    ya[e] = (int)i < npy ? ((cz * cn[1] + b) * n0 + fx) | ((q & 1) ? kTapOdd : 0u) | kTapOn : 0u;
+  for (int e = 0; e < YE; ++e) {            // PY place (cz n1 + fy) n0 + fx
+    const int i = tid + e * NT;
+    const bool odd = i >= cn[2] * ney * n0;
+    const unsigned ii = odd ? i - cn[2] * ney * n0 : i;
+    const unsigned t = brick_div(ii, m0), fx = ii - t * n0;
+    const unsigned cz = brick_div(t, odd ? moy : mey), k = t - cz * (odd ? noy : ney);
+    const unsigned fy = (odd ? 1 - ey : ey) + 2 * k;
+    const int q = ba[1] + (int)fy, b = (q >> 1) - C0[1] - (odd ? 2 : 0);
+    ya[e] = i < npy ? ((cz * cn[1] + b) * n0 + fx) | (((cz * n1 + fy) * n0 + fx) << 12) |
+                          (odd ? kPassOdd : 0u) | kPassOn
+                    : 0u;
   }
 #pragma unroll
   for (int e = 0; e < ZE; ++e) {            // fine point i = fz n01 + (fy n0 + fx)
@@ -633,11 +651,13 @@ void k_prolong_bricks(BrickArgs a) {
       if (v + 1 < a.nvars) load(v + 1, m, R[m]);   // in flight for the rest of this variable
 #pragma unroll
       for (int e = 0; e < XE; ++e)
-        if (xa[e] & kTapOn) PX[tid + e * NT] = brick_tap(V + (xa[e] & 4095u), 1, xa[e] & kTapOdd);
+        if (xa[e] & kPassOn)
+          PX[(xa[e] >> 12) & 4095u] = brick_tap(V + (xa[e] & 4095u), 1, xa[e] & kPassOdd);
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < YE; ++e)
-        if (ya[e] & kTapOn) PY[tid + e * NT] = brick_tap(PX + (ya[e] & 4095u), sty, ya[e] & kTapOdd);
+        if (ya[e] & kPassOn)
+          PY[(ya[e] >> 12) & 4095u] = brick_tap(PX + (ya[e] & 4095u), sty, ya[e] & kPassOdd);
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < ZE; ++e)
