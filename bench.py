@@ -35,6 +35,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "grid-point updates/s (subcycled RK4) batched/mixed vs plain FP64; % HBM peak"
 HBM_PEAK_GBS = 8000.0
+HBM_PEAK_BPS = HBM_PEAK_GBS * 1e9
+FP64_VALU_PEAK = 78.6e12          # FP64 vector FLOP/s
 # algorithmic HBM bytes per point-update (both variables, one RK4 step, interior
 # only): reading y_n and the stage vectors and writing k1..k4, the stage
 # vectors and y_{n+1} in FP64 (144 B per variable); with the FP32 stencil
@@ -43,6 +45,7 @@ SURVEY_BYTES = {"fp64": 288.0, "mixed": 200.0}
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "wave_stage_n0128_fp64_hbm_traffic.md")
+Z4C_COUNTERS = os.path.join(ROOT, "profiles", "z4c_c5_fp64_step_counters.md")
 
 
 def kernel_source_hash():
@@ -165,6 +168,111 @@ def summarize_counters(fetch_dir, write_dir, probe_fetch_dir, probe_write_dir, k
             "fetch_scale": sf, "write_scale": sw, "traffic_bytes_per_launch": fetch * sf + write * sw}
 
 
+def z4c_source_hash():
+    """sha256 over the Z4c kernels, the shared kernels and the host code that launches them."""
+    h = hashlib.sha256()
+    for f in ("z4c.hip", "kernels.hip", "capi.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_2503_09629_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def step_window(rows, anchor_re, per_step, step=1):
+    """Dispatch index range [i0, i1) of one coarse step: from the first anchor
+    dispatch of coarse step `step` (0-based) to the first of the next.  This is
+    the step shifted cyclically, which holds the same dispatches as long as the
+    two steps run the same launch sequence (no other work between them)."""
+    idx = [i for i, r in enumerate(rows) if re.search(anchor_re, r[0])]
+    if len(idx) <= (step + 1) * per_step:
+        raise SystemExit(f"{len(idx)} dispatches of {anchor_re}: fewer than {step + 2} steps of "
+                         f"{per_step}")
+    return idx[step * per_step], idx[(step + 1) * per_step]
+
+
+def short_name(n):
+    return re.sub(r"\([^()]*\)$", "", n.replace("void ", "", 1)
+                  .replace("sc::(anonymous namespace)::", ""))
+
+
+def summarize_step(trace_dir, fetch_dir, write_dir, flops_dir, probe_fetch_dir, probe_write_dir,
+                   anchor_re, per_step, probe_bytes):
+    """Per-kernel time, HBM bytes and FP64 VALU FLOPs over one coarse step
+    (step_window in each run), against 8 TB/s and 78.6 TFLOP/s."""
+    pf = counter_dispatches(probe_fetch_dir, "FETCH_SIZE")[-1][2] * 1024.0
+    pw = counter_dispatches(probe_write_dir, "WRITE_SIZE")[-1][2] * 1024.0
+    sf, sw = probe_bytes / pf, probe_bytes / pw
+    per = {}
+
+    def add(rows, key, scale):
+        i0, i1 = step_window(rows, anchor_re, per_step)
+        for r in rows[i0:i1]:
+            d = per.setdefault(short_name(r[0]), {"calls": 0, "us": 0.0, "fetch": 0.0, "write": 0.0,
+                                                  "flops": 0.0})
+            if key == "us":
+                d["calls"] += 1
+                d["us"] += (r[2] - r[1]) / 1e3
+            else:
+                d[key] += r[2] * scale
+    add(trace_dispatches(trace_dir), "us", 1.0)
+    add(counter_dispatches(fetch_dir, "FETCH_SIZE"), "fetch", 1024.0 * sf)
+    add(counter_dispatches(write_dir, "WRITE_SIZE"), "write", 1024.0 * sw)
+    # the counter adds each FP64 VALU instruction's operations per lane (FMA 2)
+    # once per wave: times 64 lanes (an upper bound where lanes are masked off)
+    add(counter_dispatches(flops_dir, "SQ_INSTS_VALU_FLOPS_FP64"), "flops", 64.0)
+    fma = sum(r[2] for r in counter_dispatches(flops_dir, "SQ_INSTS_VALU_FMA_F64")[
+        slice(*step_window(counter_dispatches(flops_dir, "SQ_INSTS_VALU_FMA_F64"), anchor_re,
+                           per_step))])
+    lines = ["| kernel | calls | ms | HBM GB | TB/s | % HBM | FP64 GFLOP | TFLOP/s | % FP64 VALU |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    tot = {"us": 0.0, "bytes": 0.0, "flops": 0.0}
+    for n, d in sorted(per.items(), key=lambda kv: -kv[1]["us"]):
+        b = d["fetch"] + d["write"]
+        tot["us"] += d["us"]
+        tot["bytes"] += b
+        tot["flops"] += d["flops"]
+        if d["us"] <= 0:
+            continue
+        s_ = d["us"] * 1e-6
+        lines.append(f"| `{n}` | {d['calls']} | {d['us'] / 1e3:.2f} | {b / 1e9:.2f} | "
+                     f"{b / s_ / 1e12:.2f} | {100 * b / s_ / HBM_PEAK_BPS:.1f} | "
+                     f"{d['flops'] / 1e9:.1f} | {d['flops'] / s_ / 1e12:.2f} | "
+                     f"{100 * d['flops'] / s_ / FP64_VALU_PEAK:.1f} |")
+    s_ = tot["us"] * 1e-6
+    lines.append(f"| all kernels | | {tot['us'] / 1e3:.2f} | {tot['bytes'] / 1e9:.2f} | "
+                 f"{tot['bytes'] / s_ / 1e12:.2f} | {100 * tot['bytes'] / s_ / HBM_PEAK_BPS:.1f} | "
+                 f"{tot['flops'] / 1e9:.1f} | {tot['flops'] / s_ / 1e12:.2f} | "
+                 f"{100 * tot['flops'] / s_ / FP64_VALU_PEAK:.1f} |")
+    lines += ["", f"copy-probe scale FETCH / WRITE: {sf:.4f} / {sw:.4f}; "
+                  f"FP64 FMA instructions (wave level) in the step: {fma:.4g}", "",
+              f"hbm_bytes_per_coarse_step: {tot['bytes']:.6e}",
+              f"fp64_flops_per_coarse_step: {tot['flops']:.6e}",
+              f"kernel_ms_per_coarse_step: {tot['us'] / 1e3:.3f}",
+              f"kernel_source_sha256: {z4c_source_hash()}"]
+    return "\n".join(lines)
+
+
+def z4c_roofline(step_s):
+    """Whole-step %HBM and %FP64-VALU of the Z4c run: counted HBM bytes and FP64
+    VALU FLOPs per coarse step from the committed counter summary (taken on the
+    same kernels, FP64, frozen boundary, fourth order), over this run's time."""
+    try:
+        txt = open(Z4C_COUNTERS).read()
+    except OSError:
+        return {"unavailable": "no counter summary"}
+    b = re.search(r"hbm_bytes_per_coarse_step:\s*(\S+)", txt)
+    f = re.search(r"fp64_flops_per_coarse_step:\s*(\S+)", txt)
+    h = re.search(r"kernel_source_sha256:\s*(\w+)", txt)
+    if not (b and f and h) or h.group(1) != z4c_source_hash():
+        return {"unavailable": "counter summary taken on other kernel sources"}
+    by, fl = float(b.group(1)), float(f.group(1))
+    hb, fp = by / step_s / HBM_PEAK_BPS, fl / step_s / FP64_VALU_PEAK
+    return {"bound": "hbm" if hb >= fp else "alu", "scope": "whole coarse step, all kernels",
+            "achieved": by / step_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hb,
+            "traffic": by, "fp64_valu": {"achieved": fl / step_s / 1e12,
+                                         "peak": FP64_VALU_PEAK / 1e12, "unit": "TFLOP/s",
+                                         "frac": fp, "flops_per_coarse_step": fl},
+            "counters": os.path.relpath(Z4C_COUNTERS, ROOT)}
+
+
 def make_context(sc, spec, mode, data, precision=0):
     ctx = sc.Context(device="cuda:0", exec=mode, precision=precision)
     ctx.build_spec(spec, block_seed=1, min_block=16, max_block=48)
@@ -275,26 +383,50 @@ def cpu_baseline(n0=128):
             "cpu_model": cpu_model()}
 
 
-def composite_weights(spec, level):
-    """dx^3 on points not covered by a finer level (each point counted on the
-    finest level that has it), else 0; canonical order of the level."""
-    from workloads import canonical_coords
-    n = spec.npoints(level)
-    w = np.full(n, spec.dx(level) ** 3)
-    if level + 1 < spec.nlevels:
-        idx = []
-        for lo, hi in spec.boxes(level):
-            z, y, x = np.meshgrid(*[np.arange(lo[d], hi[d] + 1) for d in (2, 1, 0)], indexing="ij")
-            idx.append(np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1))
-        idx = np.concatenate(idx)
-        cov = np.zeros(n, dtype=bool)
-        for lo, hi in spec.boxes(level + 1):
-            inside = np.ones(n, dtype=bool)
-            for d in range(3):
-                inside &= (2 * idx[:, d] >= lo[d]) & (2 * idx[:, d] <= hi[d])
-            cov |= inside
-        w[cov] = 0.0
-    return w
+def ens_run(args):
+    """C1 ensembles: B independent periodic 32^3 standing-wave members (seeded
+    modes m_d in {1, 2, 3} and amplitudes in [0.5, 1.5]) advanced together, one
+    batched launch per RK4 stage over all members, 64 steps of dt = 1/64 to
+    t = 1, then 8 more.  Per B: the stage kernel's event-timed roofline over
+    the first 8 steps (batched eager), graph-mode throughput over the other
+    64 (one capture step, 63 timed in 5 groups, median) and the largest
+    max-norm error of u against the members' exact solutions at t = 9/8."""
+    import torch
+    import paper_2503_09629_amd as sc
+    from workloads import ensemble_c1
+    from workloads.data import ensemble_params
+    out = {"workload": "C1 ensembles: B members of a periodic 32^3 scalar-wave level on [-1,1]^3, "
+                       "seeded standing waves (seed 2), dt = 1/64, 72 steps", "runs": []}
+    for B in args.ens_b:
+        spec = ensemble_c1(B, 32)
+        U = B * spec.updates_per_coarse_step()
+        ctx = sc.Context(device="cuda:0", exec=sc.SC_EXEC_BATCHED)
+        ctx.build_spec(spec, block_seed=1, min_block=16, max_block=48)
+        ctx.bind()
+        ctx.set_initial_data_analytic(sc.SC_ID_STANDING_WAVE, (), seed=2)
+        if not args.no_tune:
+            ctx.autotune()
+        roof = stage_roofline(ctx, 8, U, "fp64")        # the first 8 of 72 steps
+        ctx.set_exec(sc.SC_EXEC_GRAPH)
+        ctx.advance(1)                      # graph capture
+        ctx.synchronize()
+        total, per = timed_reps(ctx, torch, 63)
+        t = ctx.level_time(0)
+        err = 0.0
+        for m, (modes, a0) in enumerate(ensemble_params(B, 2)):
+            e = ctx.error_norms(m, 0, 0, sc.SC_ID_STANDING_WAVE, (a0,) + tuple(modes) + (t,))
+            err = max(err, float(e[0]))
+        ms = float(np.median(per))
+        log(f"ens B={B}: {ms:.3f} ms per step, {U / ms * 1e3:.4g} updates/s, stage kernel "
+            f"{roof['frac']:.3f} of HBM, max error {err:.3e} at t = {t}")
+        out["runs"].append({"B": B, "points": B * spec.total_points(), "ms_per_step": ms,
+                            "ms_per_step_groups": per, "updates_per_s": U / ms * 1e3,
+                            "roofline": roof, "max_error_u": err, "t": t,
+                            "tile_shape": ctx.tile_shape(0)})
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    return out
 
 
 def z4c_run(args):
@@ -321,24 +453,14 @@ def z4c_run(args):
             vals = brill_lindquist(p[:, 0], p[:, 1], p[:, 2])
             for v in range(22):
                 ctx.set_phys_data(0, l, v, vals[v])
-    masks = []
-    for l in range(spec.nlevels):
-        x, y, z = canonical_coords(spec, l)
-        masks.append((composite_weights(spec, l), np.sqrt(x * x + y * y + z * z) < 30.0))
     x0, y0, z0 = canonical_coords(spec, 0)
     r0 = np.sqrt(x0 * x0 + y0 * y0 + z0 * z0)
     outer = (r0 > 64.0) & (np.maximum(np.maximum(abs(x0), abs(y0)), abs(z0)) < 112.0)
 
     def hnorm():
-        num = den = 0.0
-        for l in range(spec.nlevels):
-            H = ctx.hamiltonian(0, l)
-            alpha = ctx.read_back(0, l, 18)
-            w, inside = masks[l]
-            m = inside & (alpha > 0.3)
-            num += float(np.sum(w[m] * H[m] ** 2))
-            den += float(np.sum(w[m]))
-        return np.sqrt(num / den) if den > 0 else float("nan")
+        # composite-grid L2 over r < 30 where alpha > 0.3, each point on the
+        # finest level that has it, weight dx^3 (on the device)
+        return float(ctx.constraint_norm(0, 30.0, 0.3)[0])
 
     def hnorm_outer():
         # level 0 between r = 64 and 6 points inside the outer boundary (|x_i| < 112)
@@ -370,9 +492,11 @@ def z4c_run(args):
     hist.append((ctx.level_time(0), hnorm()))
     log(f"z4c: {1e3 * T / steps:.1f} ms per coarse step, {U * steps / T:.4g} updates/s")
     finite = ctx.check_finite() == sc.SC_OK
+    profiled = not mixed and not radiative and args.z4c_fd_order == 4
     return {"metric": "Z4c grid-point updates/s (subcycled RK4, 22 variables)",
             "value": U * steps / T, "unit": "grid-point updates/s", "n_gpus": 1,
             "steps": steps, "ms_per_step": 1e3 * T / steps,
+            "roofline": z4c_roofline(T / steps) if profiled else None,
             "dtype": "f32 RHS, f64 state" if mixed else "f64",
             "config": {"workload": "Z4c Brill-Lindquist punctures m=0.5 at x=+-3, 7 levels of "
                                    "96^3, [-128,128]^3, graph mode"
@@ -392,6 +516,7 @@ def e1_run(args):
     import paper_2503_09629_amd as sc
     from workloads import (canonical_coords, config_e1, grown_for_buffer_zones, spherical_gaussian,
                            spherical_gaussian_on_spec)
+    from workloads.data import E1_AMPLITUDE, E1_SIGMA
     checkpoints = [round(0.4 * (i + 1), 10) for i in range(int(round(args.e1_t / 0.4)))]
     modes = [m.strip() for m in args.e1_modes.split(",") if m.strip()]
     out = {"workload": "scalar wave E1: spherical Gaussian A=1, sigma=0.25/sqrt(2), periodic "
@@ -438,8 +563,12 @@ def e1_run(args):
                 T += time.perf_counter() - t0
                 steps_done += nsteps
                 t = ctx.level_time(lev)
-                ue, _ = spherical_gaussian(t, x, y, z)
-                e = float(np.abs(ctx.read_back(0, lev, 0)[sel] - ue).max())
+                if buffered:   # a sub-box of the level: on the host
+                    ue, _ = spherical_gaussian(t, x, y, z)
+                    e = float(np.abs(ctx.read_back(0, lev, 0)[sel] - ue).max())
+                else:
+                    e = float(ctx.error_norms(0, lev, 0, sc.SC_ID_SPHERICAL_GAUSSIAN,
+                                              (E1_AMPLITUDE, E1_SIGMA, t))[0])
                 errs.append(e)
                 log(f"  t = {t:.4f}: max |u - u_exact| on level {lev} = {e:.4e} "
                     f"({steps_done} steps, {U * steps_done / T:.4g} updates/s)")
@@ -632,7 +761,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--workload", default="wave",
-                    choices=("wave", "z4c", "precision", "e1", "carpet", "fd8"))
+                    choices=("wave", "z4c", "precision", "e1", "carpet", "fd8", "ens"))
+    ap.add_argument("--ens-b", type=int, nargs="+", default=[64, 512, 1024])
     ap.add_argument("--carpet-steps", type=int, default=8)
     ap.add_argument("--carpet-warmup", type=int, default=4)
     ap.add_argument("--e1-n0", type=int, nargs="+", default=[375, 450, 540])
@@ -650,12 +780,24 @@ def main():
     ap.add_argument("--summarize-counters", metavar="DIR", nargs=4, default=None,
                     help="FETCH_SIZE, WRITE_SIZE, copy-probe FETCH_SIZE, copy-probe WRITE_SIZE "
                          "output folders of rocprofv3 --pmc runs: HBM bytes per dispatch")
+    ap.add_argument("--summarize-step", metavar="DIR", nargs=6, default=None,
+                    help="kernel-trace, FETCH_SIZE, WRITE_SIZE, FP64-FLOP counter, copy-probe "
+                         "FETCH_SIZE and copy-probe WRITE_SIZE output folders: per-kernel time, "
+                         "HBM bytes and FP64 FLOPs of one coarse step")
+    ap.add_argument("--anchor", default="k_z4c_evol",
+                    help="kernel launched a fixed number of times per coarse step (--summarize-step)")
+    ap.add_argument("--per-step", type=int, default=508,
+                    help="launches of the anchor kernel per coarse step (--summarize-step)")
     ap.add_argument("--kernel", default="k_wave_stage", help="kernel name regex for the summaries")
     ap.add_argument("--last", type=int, default=0, help="summarise only the last N matching dispatches")
     ap.add_argument("--probe-mib", type=int, default=1024)
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.kernel, args.last))
+        return
+    if args.summarize_step:
+        print(summarize_step(*args.summarize_step, args.anchor, args.per_step,
+                             args.probe_mib << 20))
         return
     if args.summarize_counters:
         print(json.dumps(summarize_counters(*args.summarize_counters, args.kernel, args.last,
@@ -691,6 +833,9 @@ def main():
         return
     if args.workload == "fd8":
         print(json.dumps(fd8_run(args)), flush=True)
+        return
+    if args.workload == "ens":
+        print(json.dumps(ens_run(args)), flush=True)
         return
 
     import torch
