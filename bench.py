@@ -273,6 +273,22 @@ def z4c_roofline(step_s):
             "counters": os.path.relpath(Z4C_COUNTERS, ROOT)}
 
 
+def summarize_markers(folder):
+    """roctx ranges of a rocprofv3 --marker-trace run, grouped by name with the
+    step counters taken out: calls, total and average host duration."""
+    stats = {}
+    for path in glob.glob(os.path.join(folder, "**", "*marker_api_trace.csv"), recursive=True):
+        for r in _rows_from_csv(path):
+            name = re.sub(r"step \d+", "step n", r["Function"])
+            d = stats.setdefault(name, [0, 0.0])
+            d[0] += 1
+            d[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    lines = ["| range | calls | total ms | average us |", "|---|---|---|---|"]
+    for n, d in sorted(stats.items()):
+        lines.append(f"| {n} | {d[0]} | {d[1] / 1e3:.2f} | {d[1] / d[0]:.1f} |")
+    return "\n".join(lines)
+
+
 def make_context(sc, spec, mode, data, precision=0):
     ctx = sc.Context(device="cuda:0", exec=mode, precision=precision)
     ctx.build_spec(spec, block_seed=1, min_block=16, max_block=48)
@@ -433,7 +449,7 @@ def z4c_run(args):
     """Z4c two-puncture evolution on the 7-level 96^3 tower hierarchy."""
     import torch
     import paper_2503_09629_amd as sc
-    from workloads import brill_lindquist, brill_lindquist_on_spec, canonical_coords, config_c5
+    from workloads import canonical_coords, config_c5
     spec = config_c5(96)
     U = spec.updates_per_coarse_step()
     log(f"workload {spec.name}: {spec.total_points()} points, {U} updates per coarse step")
@@ -445,14 +461,9 @@ def z4c_run(args):
                      fd_order=args.z4c_fd_order)
     ctx.build_spec(spec)
     ctx.bind()
-    for l in range(spec.nlevels):
-        for v, f in enumerate(brill_lindquist_on_spec(spec, l)):
-            ctx.set_initial_data(0, l, v, f)
-        p = ctx.phys_points(l)
-        if len(p):
-            vals = brill_lindquist(p[:, 0], p[:, 1], p[:, 2])
-            for v in range(22):
-                ctx.set_phys_data(0, l, v, vals[v])
+    # Brill-Lindquist punctures m = 0.5 at x = +-3, evaluated on the device
+    # (fields and the frozen physical-boundary ghosts)
+    ctx.set_initial_data_analytic(sc.SC_ID_BRILL_LINDQUIST, (0.5, 0.5, 3.0, -3.0))
     x0, y0, z0 = canonical_coords(spec, 0)
     r0 = np.sqrt(x0 * x0 + y0 * y0 + z0 * z0)
     outer = (r0 > 64.0) & (np.maximum(np.maximum(abs(x0), abs(y0)), abs(z0)) < 112.0)
@@ -514,8 +525,7 @@ def e1_run(args):
     against the exact solution, subcycled and uniform time steps."""
     import torch
     import paper_2503_09629_amd as sc
-    from workloads import (canonical_coords, config_e1, grown_for_buffer_zones, spherical_gaussian,
-                           spherical_gaussian_on_spec)
+    from workloads import canonical_coords, config_e1, grown_for_buffer_zones, spherical_gaussian
     from workloads.data import E1_AMPLITUDE, E1_SIGMA
     checkpoints = [round(0.4 * (i + 1), 10) for i in range(int(round(args.e1_t / 0.4)))]
     modes = [m.strip() for m in args.e1_modes.split(",") if m.strip()]
@@ -539,9 +549,8 @@ def e1_run(args):
             ctx = sc.Context(device="cuda:0", exec=sc.SC_EXEC_GRAPH, time_stepping=ts)
             ctx.build_spec(spec, block_seed=1, min_block=16, max_block=48)
             ctx.bind()
-            for l in range(spec.nlevels):
-                for v, f in enumerate(spherical_gaussian_on_spec(spec, l, 0.0)):
-                    ctx.set_initial_data(0, l, v, f)
+            ctx.set_initial_data_analytic(sc.SC_ID_SPHERICAL_GAUSSIAN,
+                                          (E1_AMPLITUDE, E1_SIGMA, 0.0))
             lev = spec.nlevels - 1
             x, y, z = canonical_coords(spec, lev)
             sel = slice(None)
@@ -755,6 +764,8 @@ def main():
     ap.add_argument("--n0", type=int, default=128)
     ap.add_argument("--modes", default="graph,batched,per_block,mixed")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the short C5 Z4c and C1-ensemble runs of the default line")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--shapes", default=None,
                     help="JSON line of an earlier run: take its tile shapes instead of tuning")
@@ -780,6 +791,8 @@ def main():
     ap.add_argument("--summarize-counters", metavar="DIR", nargs=4, default=None,
                     help="FETCH_SIZE, WRITE_SIZE, copy-probe FETCH_SIZE, copy-probe WRITE_SIZE "
                          "output folders of rocprofv3 --pmc runs: HBM bytes per dispatch")
+    ap.add_argument("--summarize-markers", metavar="DIR", default=None,
+                    help="table of the roctx ranges of a rocprofv3 --marker-trace output folder")
     ap.add_argument("--summarize-step", metavar="DIR", nargs=6, default=None,
                     help="kernel-trace, FETCH_SIZE, WRITE_SIZE, FP64-FLOP counter, copy-probe "
                          "FETCH_SIZE and copy-probe WRITE_SIZE output folders: per-kernel time, "
@@ -794,6 +807,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.kernel, args.last))
+        return
+    if args.summarize_markers:
+        print(summarize_markers(args.summarize_markers))
         return
     if args.summarize_step:
         print(summarize_step(*args.summarize_step, args.anchor, args.per_step,
@@ -933,6 +949,22 @@ def main():
     out["kernel_source_sha256"] = kernel_source_hash()
     if roof is not None:
         out["roofline"] = roof
+    if not args.no_secondary:
+        # short runs of the other measured workloads, so that their numbers
+        # come from the same benchmark invocation (reported, not the metric)
+        sec = {}
+        for name, fn in (("z4c_c5_fp64", lambda: z4c_run(argparse.Namespace(
+                             z4c_steps=3, z4c_precision="fp64", z4c_bc="frozen",
+                             z4c_fd_order=4, z4c_h_every=0))),
+                         ("c1_ensemble_b512", lambda: ens_run(argparse.Namespace(
+                             ens_b=[512], no_tune=args.no_tune)))):
+            log(f"secondary workload {name} ...")
+            try:
+                sec[name] = fn()
+            except Exception as e:      # reported in the line, the metric stands
+                sec[name] = {"error": f"{type(e).__name__}: {e}"}
+            torch.cuda.empty_cache()
+        out["secondary"] = sec
     if not args.no_cpu:
         log("timing the CPU reference implementation ...")
         out["cpu_baseline"] = cpu_baseline()

@@ -14,6 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsubcyc.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM_LIB = "/opt/rocm/lib"     # librocprofiler-sdk-roctx: the level-step ranges
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall",
@@ -60,7 +61,8 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + f".tmp{os.getpid()}"
     tl = torch_lib_dir()
     link = ["g++", "-shared", "-fPIC", "-o", tmp, *objs, f"-L{tl}", "-l:libamdhip64.so",
-            f"-Wl,-rpath,{tl}", "-Wl,--no-undefined"]
+            f"-L{ROCM_LIB}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{tl}",
+            f"-Wl,-rpath,{ROCM_LIB}", "-Wl,--no-undefined"]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)

@@ -8,10 +8,29 @@
 #include <map>
 #include <numeric>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "runtime.hpp"
 #include "z4c.hpp"
 
 using namespace sc;
+
+namespace {
+// A roctx range over a host scope (a level step, a stage, a prolongation),
+// visible in rocprofv3 --marker-trace; without a profiler the calls do nothing.
+// In graph mode the ranges mark the capture, not the replays.
+struct Range {
+  template <typename... A>
+  explicit Range(const char* fmt, A... args) {
+    char buf[96];
+    std::snprintf(buf, sizeof buf, fmt, args...);
+    roctxRangePushA(buf);
+  }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+}  // namespace
 
 namespace {
 
@@ -1170,6 +1189,8 @@ int restrict_level(sc_ctx* c, int fl) {
 
 // Buffer zones (Carpet): refill from the parent, step, recurse, restrict.
 int advance_level_buffer(sc_ctx* c, int l, int substep, bool per_block) {
+  Range r("level %d step %lld (substep %d, buffer zones)", l, (long long)c->lev[l].steps_done,
+          substep);
   int rc;
   if (l > 0 && (rc = prolongate_buffer(c, l, substep))) return rc;
   if ((rc = rk4_step(c, l, substep, per_block))) return rc;
@@ -1184,10 +1205,17 @@ int advance_level_buffer(sc_ctx* c, int l, int substep, bool per_block) {
 
 int advance_level(sc_ctx* c, int l, int substep, bool per_block) {
   if (buffer_zones(c)) return advance_level_buffer(c, l, substep, per_block);
-  int rc = rk4_step(c, l, substep, per_block);
-  if (rc) return rc;
+  Range r("level %d step %lld (substep %d)", l, (long long)c->lev[l].steps_done, substep);
+  int rc;
+  {
+    Range r4("rk4 level %d", l);
+    if ((rc = rk4_step(c, l, substep, per_block))) return rc;
+  }
   if (l + 1 < (int)c->lev.size()) {
-    if ((rc = prolongate(c, l + 1))) return rc;
+    {
+      Range rp("prolongate level %d", l + 1);
+      if ((rc = prolongate(c, l + 1))) return rc;
+    }
     if ((rc = advance_level(c, l + 1, 0, per_block))) return rc;
     if (c->cfg.time_stepping != SC_UNIFORM_DT &&
         (rc = advance_level(c, l + 1, 1, per_block)))
@@ -1771,6 +1799,7 @@ int sc_advance(sc_ctx* c, int32_t ncoarse) {
                                    "(sc_check_finite locates it; new initial data clear it)");
   c->launches = 0;
   for (int i = 0; i < ncoarse; ++i) {
+    Range r("coarse step %lld", (long long)c->lev[0].steps_done);
     // buffer zones: the first coarse step interpolates linearly in time at
     // each level's first step, later ones quadratically; only the latter
     // repeat, so the first runs eagerly
@@ -1795,6 +1824,7 @@ int sc_advance(sc_ctx* c, int32_t ncoarse) {
         std::vector<int64_t> n0(c->lev.size());
         for (size_t l = 0; l < c->lev.size(); ++l)
           cur0[l] = c->lev[l].cur, t0[l] = c->lev[l].t, n0[l] = c->lev[l].steps_done;
+        Range rc_("graph capture (level-0 buffer %d)", parity);
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
         rc = advance_level(c, 0, 0, false);
         hipGraph_t g = nullptr;
