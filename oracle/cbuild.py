@@ -42,6 +42,8 @@ def lib():
         _lib.orc_wave_rhs.argtypes = [i, i64p, i, L, i64p, i64p, d, d]
         _lib.orc_wave_rhs8.argtypes = [i, i64p, i, L, i64p, i64p, d, d]
         _lib.orc_wave_rhs8.restype = None
+        _lib.orc_wave_rhs8_ko9.argtypes = [i, i64p, i, L, i64p, i64p, d, d]
+        _lib.orc_wave_rhs8_ko9.restype = None
         _lib.orc_stage.argtypes = [i, i64p, i, L, i, i64p, i64p, i64p, d]
         _lib.orc_final.argtypes = [i, i64p, i, L, i, i64p, i64p, i64p, i64p, i64p, i64p, d]
         _lib.orc_copy_points.argtypes = [L, i64p, i64p, i, L, i64p]

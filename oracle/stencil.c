@@ -23,6 +23,12 @@
  *    - 1008u[+2] + 128u[+3] - 9u[+4]), summed x + y + z, times 1/(5040 h^2)
  *   (the centred weights -1/560, 8/315, -1/5, 8/5, -205/72 over 5040), with the
  *   same fifth-order (r = 4) dissipation; needs G >= 4.
+ * Ninth-order dissipation (r = 8, the option Sec. III.C adds beside the
+ * eighth-order derivatives; orc_wave_rhs8_ko9): the same Qu with r = 8,
+ *   Q u = sigma/2^10 * sum_i h^9 D+^5 D-^5 u
+ *       = sigma/(1024 h) * sum_i (u[-5] - 10u[-4] + 45u[-3] - 120u[-2] + 210u[-1] - 252u[0]
+ *                                 + 210u[+1] - 120u[+2] + 45u[+3] - 10u[+4] + u[+5])
+ *   (the tenth difference: binomial weights of (D+ D-)^5 h^10); needs G >= 5.
  * RK4 (Eqs. rk1-rk5): Y_{s+1} = y_n + (c_{s+1} dt) k_s with c = 1/2, 1/2, 1;
  *   y_{n+1} = y_n + (dt/6) * (((k1 + 2 k2) + 2 k3) + k4).
  */
@@ -81,6 +87,50 @@ static inline double d8(double m4, double m3, double m2, double m1, double c, do
                         double p2, double p3, double p4) {
   return (((((((-9.0 * m4 + 128.0 * m3) - 1008.0 * m2) + 8064.0 * m1) - 14350.0 * c) +
             8064.0 * p1) - 1008.0 * p2) + 128.0 * p3) - 9.0 * p4;
+}
+
+static inline double ko11(const double* A, int64_t o, int64_t s) {
+  return (((((((((P(A, o - 5 * s) - 10.0 * P(A, o - 4 * s)) + 45.0 * P(A, o - 3 * s)) -
+               120.0 * P(A, o - 2 * s)) + 210.0 * P(A, o - s)) - 252.0 * P(A, o)) +
+            210.0 * P(A, o + s)) - 120.0 * P(A, o + 2 * s)) + 45.0 * P(A, o + 3 * s)) -
+          10.0 * P(A, o + 4 * s)) + P(A, o + 5 * s);
+}
+
+/* Eighth-order Laplacian with the r = 8 dissipation (G >= 5). */
+void orc_wave_rhs8_ko9(int nb, const int64_t* desc, int G, int64_t vstride, const double* Y,
+                       double* k, double h, double sigma) {
+  const double clap = 1.0 / (5040.0 * h * h);
+  const double cko = sigma / (1024.0 * h);
+  for (int b = 0; b < nb; ++b) {
+    const int64_t base = desc[4 * b];
+    const int nx = (int)desc[4 * b + 1], ny = (int)desc[4 * b + 2], nz = (int)desc[4 * b + 3];
+    const int64_t sx = 1, sy = nx + 2 * G, sz = (int64_t)(nx + 2 * G) * (ny + 2 * G);
+    const double* U = Y + base;
+    const double* PI = Y + vstride + base;
+    double* KU = k + base;
+    double* KP = k + vstride + base;
+#pragma omp parallel for schedule(static)
+    for (int z = G; z < G + nz; ++z)
+      for (int y = G; y < G + ny; ++y)
+        for (int x = G; x < G + nx; ++x) {
+          const int64_t o = z * sz + y * sy + x * sx;
+          double l[3];
+          const int64_t st[3] = {sx, sy, sz};
+          for (int d = 0; d < 3; ++d) {
+            const int64_t s = st[d];
+            l[d] = d8(P(U, o - 4 * s), P(U, o - 3 * s), P(U, o - 2 * s), P(U, o - s), P(U, o),
+                      P(U, o + s), P(U, o + 2 * s), P(U, o + 3 * s), P(U, o + 4 * s));
+          }
+          const double lap = ((l[0] + l[1]) + l[2]) * clap;
+          double q[2];
+          for (int v = 0; v < 2; ++v) {
+            const double* A = v == 0 ? U : PI;
+            q[v] = cko * ((ko11(A, o, sx) + ko11(A, o, sy)) + ko11(A, o, sz));
+          }
+          KU[o] = P(PI, o) + q[0];
+          KP[o] = lap + q[1];
+        }
+  }
 }
 
 void orc_wave_rhs8(int nb, const int64_t* desc, int G, int64_t vstride, const double* Y,
