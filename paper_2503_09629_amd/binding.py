@@ -140,13 +140,15 @@ class Context:
                  precision: int = SC_FP64, stream=None, device: Optional[str] = None,
                  rhs: int = SC_RHS_WAVE, z4c: Optional[dict] = None,
                  time_stepping: int = SC_SUBCYCLED, fd_order: int = 4,
-                 outer_bc: int = SC_BC_FROZEN):
+                 outer_bc: int = SC_BC_FROZEN, ko_order: int = 5):
         self.L = lib()
         cfg = ScConfig()
         self._check(self.L.sc_config_default(ctypes.byref(cfg)), None)
         cfg.time_stepping = time_stepping
         cfg.fd_order = fd_order
-        cfg.nghost = 4 if fd_order == 8 else 3
+        # ghost width: 3 (fourth order), 4 (eighth order), 5 (eighth order with
+        # the r = 8 dissipation, ko_order 9)
+        cfg.nghost = (5 if ko_order == 9 else 4) if fd_order == 8 else 3
         cfg.outer_bc = outer_bc
         cfg.ko_sigma = sigma
         cfg.cfl = cfl

@@ -246,7 +246,7 @@ std::string build_layout(sc_ctx* c) {
     L.nb_member = (int)M.boxes.size();
     L.has_child = l + 1 < nl;
     L.nbuf = c->cfg.time_stepping == SC_BUFFER_ZONES ? 3 : 2;
-    L.shape.radius = c->fd_order == 8 ? 4 : 3;
+    L.shape.radius = c->fd_order == 8 ? (c->G == 5 ? 5 : 4) : 3;
     if (c->cfg.rhs == SC_RHS_Z4C) {
       // the Z4c kernels run one wave per SIMD (two 128-thread workgroups per
       // CU): short, half-height tiles (two planes, at most 256 points per
@@ -813,8 +813,8 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
   a.cdt = cnext[stage] * L.dt;
   a.dt6 = L.dt / 6.0;
   a.radius = L.shape.radius;
-  a.clap = a.radius == 4 ? 1.0 / (5040.0 * L.dx * L.dx) : 1.0 / (12.0 * L.dx * L.dx);
-  a.cko = c->cfg.ko_sigma / (64.0 * L.dx);
+  a.clap = a.radius >= 4 ? 1.0 / (5040.0 * L.dx * L.dx) : 1.0 / (12.0 * L.dx * L.dx);
+  a.cko = c->cfg.ko_sigma / ((a.radius == 5 ? 1024.0 : 64.0) * L.dx);
   a.nonfinite = c->d_nonfinite;
   // k4 is read only by the prolongation into a finer level
   a.write_k = (stage < 4 || L.has_child) ? 1 : 0;
@@ -1324,7 +1324,8 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
   // eighth order: wave, FP64, four ghost layers, subcycled or uniform steps
   const bool order_ok =
       (cfg->fd_order == 4 && cfg->nghost == 3) ||
-      (cfg->fd_order == 8 && cfg->nghost == 4 && cfg->precision == SC_FP64 &&
+      (cfg->fd_order == 8 && (cfg->nghost == 4 || (cfg->nghost == 5 && cfg->rhs == SC_RHS_WAVE)) &&
+       cfg->precision == SC_FP64 &&
        cfg->time_stepping != SC_BUFFER_ZONES);
   // radiative outer boundary: Z4c, FP64
   const bool bc_ok = cfg->outer_bc == SC_BC_FROZEN ||
@@ -1335,7 +1336,8 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
       cfg->ko_sigma < 0.0 || (cfg->precision != SC_FP64 && cfg->precision != SC_MIXED) ||
       cfg->exec < 0 || cfg->exec > 2) {
     g_create_error = "unsupported configuration (rhs, time stepping (buffer zones: wave, FP64), "
-                     "fd_order 4 with nghost 3 or 8 with nghost 4 (FP64, no buffer zones), "
+                     "fd_order 4 with nghost 3 or 8 with nghost 4 (FP64, no buffer zones) or "
+                     "nghost 5 (r = 8 dissipation: wave, FP64, no buffer zones), "
                      "outer_bc (radiative: Z4c, FP64), "
                      "0 < cfl <= 0.5, sigma >= 0, precision, exec)";
     return SC_E_ARG;

@@ -54,6 +54,15 @@ __device__ __forceinline__ void ring_coord(int i, int nx, int ny, int* lx, int* 
   }
 }
 
+// tenth difference: h^10 D+^5 D-^5 u, the r = 8 Kreiss-Oliger stencil
+// (Sec. III.C's ninth-order option), taps t(-5..5)
+template <typename T, typename Tap>
+__device__ __forceinline__ T ko11(const Tap& t) {
+  return (((((((((t(-5) - T(10) * t(-4)) + T(45) * t(-3)) - T(120) * t(-2)) + T(210) * t(-1)) -
+              T(252) * t(0)) + T(210) * t(1)) - T(120) * t(2)) + T(45) * t(3)) - T(10) * t(4)) +
+         t(5);
+}
+
 template <typename T>
 __device__ __forceinline__ T d8(T m4, T m3, T m2, T m1, T c, T p1, T p2, T p3, T p4) {
   // eighth-order centred second difference times 5040 h^2 (Sec. III.C's production stencil)
@@ -86,7 +95,8 @@ __device__ __forceinline__ TS stage_form(TS ra, TS rk, TS cdt, bool in) {
 // One RK4 stage of the scalar wave on one tile of nx x ny points in x-y (at
 // most S per thread, threads mapped row by row) and nz planes, marched in z
 // direction DZ (+1 upward, -1 downward) one plane per step.  R is the stencil
-// radius: 3 for the fourth-order Laplacian, 4 for the eighth-order one.  The
+// radius: 3 for the fourth-order Laplacian, 4 for the eighth-order one, 5 for
+// the eighth-order one with the r = 8 dissipation.  The
 // x-y plane of stage values (tile plus the R-point ring) is staged in LDS
 // (double buffered, row pitch nx + 2R): the tile's own points come from the
 // (2R+1)-plane z column each thread keeps in registers, only the ring is read
@@ -100,7 +110,8 @@ __device__ __forceinline__ TS stage_form(TS ra, TS rk, TS cdt, bool in) {
 //   k_u  = Pi + Q u,   k_Pi = Lap u + Q Pi
 //   Lap  = ((d2_x + d2_y) + d2_z) / (12 h^2)        (R = 3)
 //        = ((d8_x + d8_y) + d8_z) / (5040 h^2)      (R = 4)
-//   Q    = sigma/(64 h) ((ko_x + ko_y) + ko_z)       (both)
+//   Q    = sigma/(64 h) ((ko_x + ko_y) + ko_z)       (R = 3, 4: sixth differences)
+//        = sigma/(1024 h) ((ko_x + ko_y) + ko_z)     (R = 5: tenth differences)
 // Stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4) in FP64.
 // The z stencils take their taps in increasing z whatever the direction, so
 // both directions give the same bits.
@@ -292,8 +303,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
                       Lu[c + 3], Lu[c + 4]);
         lapy = d8<TS>(Lu[c - 4 * W], Lu[c - 3 * W], Lu[c - 2 * W], Lu[c - W], cu, Lu[c + W],
                       Lu[c + 2 * W], Lu[c + 3 * W], Lu[c + 4 * W]);
-        lapz = d8<TS>(zt(0, s, 0), zt(0, s, 1), zt(0, s, 2), zt(0, s, 3), cu, zt(0, s, 5),
-                      zt(0, s, 6), zt(0, s, 7), zt(0, s, 8));
+        lapz = d8<TS>(zt(0, s, R - 4), zt(0, s, R - 3), zt(0, s, R - 2), zt(0, s, R - 1), cu,
+                      zt(0, s, R + 1), zt(0, s, R + 2), zt(0, s, R + 3), zt(0, s, R + 4));
       }
       const TS lap = ((lapx + lapy) + lapz) * clap;
       TS Q[2];
@@ -301,12 +312,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const TileDev& T,
       for (int v = 0; v < 2; ++v) {
         const TS* Lv = v == 0 ? Lu : Lp;
         const TS cc = q[v][s][R];
-        const TS kx = ko7<TS>(Lv[c - 3], Lv[c - 2], Lv[c - 1], cc, Lv[c + 1], Lv[c + 2], Lv[c + 3]);
-        const TS ky = ko7<TS>(Lv[c - 3 * W], Lv[c - 2 * W], Lv[c - W], cc, Lv[c + W],
-                              Lv[c + 2 * W], Lv[c + 3 * W]);
-        const TS kz = ko7<TS>(zt(v, s, R - 3), zt(v, s, R - 2), zt(v, s, R - 1), cc,
-                              zt(v, s, R + 1), zt(v, s, R + 2), zt(v, s, R + 3));
-        Q[v] = cko * ((kx + ky) + kz);
+        if constexpr (R == 5) {   // r = 8 dissipation
+          const TS kx = ko11<TS>([&](int j) { return j == 0 ? cc : Lv[c + j]; });
+          const TS ky = ko11<TS>([&](int j) { return j == 0 ? cc : Lv[c + j * W]; });
+          const TS kz = ko11<TS>([&](int j) { return j == 0 ? cc : zt(v, s, R + j); });
+          Q[v] = cko * ((kx + ky) + kz);
+        } else {
+          const TS kx = ko7<TS>(Lv[c - 3], Lv[c - 2], Lv[c - 1], cc, Lv[c + 1], Lv[c + 2], Lv[c + 3]);
+          const TS ky = ko7<TS>(Lv[c - 3 * W], Lv[c - 2 * W], Lv[c - W], cc, Lv[c + W],
+                                Lv[c + 2 * W], Lv[c + 3 * W]);
+          const TS kz = ko7<TS>(zt(v, s, R - 3), zt(v, s, R - 2), zt(v, s, R - 1), cc,
+                                zt(v, s, R + 1), zt(v, s, R + 2), zt(v, s, R + 3));
+          Q[v] = cko * ((kx + ky) + kz);
+        }
       }
       TK kv[2];
       if constexpr (INC) {   // k_s = k1 + f(e_s)
@@ -1027,9 +1045,10 @@ hipError_t launch_stage(const StageArgs& a, int grid, bool mixed, int depth, int
                         hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g(grid > 0 ? grid : a.ntiles);
-  if (a.radius == 4) {   // eighth order: FP64 only
+  if (a.radius == 4 || a.radius == 5) {   // eighth order (r = 4 or r = 8 dissipation): FP64 only
     if (mixed) return hipErrorInvalidValue;
-    stage_variant<false, 4>(a, g, depth, slots, threads, s);
+    if (a.radius == 4) stage_variant<false, 4>(a, g, depth, slots, threads, s);
+    else stage_variant<false, 5>(a, g, depth, slots, threads, s);
   } else if (a.radius == 3) {
     if (mixed) stage_variant<true, 3>(a, g, depth, slots, threads, s);
     else stage_variant<false, 3>(a, g, depth, slots, threads, s);

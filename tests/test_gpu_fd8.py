@@ -2,7 +2,8 @@
 stencil of Sec. III.C) against the CPU reference: every field and slope on
 every level within 1e-12 relative max-norm (the kernel sums in the
 reference's order without contraction, so the difference is expected to be
-zero), in all exec modes, with subcycled and uniform time steps.
+zero), in all exec modes, with subcycled and uniform time steps.  The same
+with the ninth-order dissipation (five ghost layers, ko9 cases).
 """
 import numpy as np
 import pytest
@@ -19,12 +20,13 @@ ARRS = {"y": sc.SC_ARR_Y, "yn": sc.SC_ARR_YN, "k1": sc.SC_ARR_K1, "k2": sc.SC_AR
         "k3": sc.SC_ARR_K3, "k4": sc.SC_ARR_K4}
 
 
-def _pair(spec, data_fn, exec=sc.SC_EXEC_BATCHED, time_stepping=sc.SC_SUBCYCLED, **kw):
-    ctx = sc.Context(device="cuda:0", exec=exec, fd_order=8, time_stepping=time_stepping)
+def _pair(spec, data_fn, exec=sc.SC_EXEC_BATCHED, time_stepping=sc.SC_SUBCYCLED, ko=5, **kw):
+    ctx = sc.Context(device="cuda:0", exec=exec, fd_order=8, time_stepping=time_stepping,
+                     ko_order=ko)
     ctx.build_spec(spec, **kw)
     ctx.bind()
-    ref = OracleRun(Hierarchy(spec, G=4, **kw), sigma=0.32, fd_order=8,
-                    subcycling=time_stepping == sc.SC_SUBCYCLED)
+    ref = OracleRun(Hierarchy(spec, G=5 if ko == 9 else 4, **kw), sigma=0.32, fd_order=8,
+                    subcycling=time_stepping == sc.SC_SUBCYCLED, ko_order=ko)
     for l in range(spec.nlevels):
         for v, f in enumerate(data_fn(spec, l)):
             ctx.set_initial_data(0, l, v, f)
@@ -103,3 +105,38 @@ def test_fd8_nan_poisoned_halos_are_never_read():
     ref.advance(2)
     _compare(ctx, ref, ("y",))
     assert ctx.check_finite() == sc.SC_OK
+
+
+def test_ko9_single_level_to_t1():
+    spec = config_c1(32)
+    ctx, ref = _pair(spec, lambda s, l: standing_wave_on_spec(s, l, (3, 2, 3), 1.0), ko=9,
+                     min_block=8, max_block=24)
+    ctx.advance(64)
+    ref.advance(64)
+    print("ko9 single level worst rel diff", _compare(ctx, ref))
+
+
+@pytest.mark.parametrize("exec", [sc.SC_EXEC_BATCHED, sc.SC_EXEC_GRAPH, sc.SC_EXEC_PER_BLOCK])
+def test_ko9_two_level(exec):
+    spec = config_c2(16)
+    ctx, ref = _pair(spec, gaussian_on_spec, exec=exec, ko=9, min_block=5, max_block=10)
+    ctx.advance(3)
+    ref.advance(3)
+    print("ko9 two levels exec", exec, "worst rel diff", _compare(ctx, ref))
+
+
+def test_ko9_towers_small():
+    spec = config_c3(64, nlev=4)
+    ctx, ref = _pair(spec, pulses_on_spec, ko=9)
+    ctx.advance(1)
+    ref.advance(1)
+    print("ko9 towers (64, 4 levels) worst rel diff", _compare(ctx, ref, ("y", "k4")))
+
+
+def test_ko9_uniform_time_steps():
+    spec = config_c2(16)
+    ctx, ref = _pair(spec, gaussian_on_spec, time_stepping=sc.SC_UNIFORM_DT, ko=9,
+                     min_block=5, max_block=10)
+    ctx.advance(4)
+    ref.advance(4)
+    print("ko9 uniform steps worst rel diff", _compare(ctx, ref))

@@ -331,6 +331,42 @@ def test_z4c_level0_step_sampled(punctures):
     ctx.close()
 
 
+def test_z4c_first_descent_every_level_against_reference(punctures):
+    """The puncture hierarchy at full size: one RK4 step of every level, coarse
+    to fine, each level's RB ghosts prolonged from its parent's step (the
+    recursion's first descent), against the reference doing the same; every
+    owned point of every level and variable, 1e-12 relative to the reference's
+    max norm."""
+    import time
+    spec, data = punctures
+    ctx = _z4c_ctx(spec, data)
+    ref = OracleRun(Hierarchy(spec, min_block=16, max_block=48), rhs="z4c")
+    for l in range(spec.nlevels):
+        for v in range(22):
+            ref.set_data(l, v, data[l][v])
+        pr = ref.phys_coords(l)
+        if len(pr):
+            ref.set_phys(l, np.array(brill_lindquist(pr[:, 0], pr[:, 1], pr[:, 2])))
+    t0 = time.perf_counter()
+    for l in range(spec.nlevels):
+        ctx.step_level(l, 0)
+        ref.rk4_step(l)
+        if l + 1 < spec.nlevels:
+            ctx.prolongate(l + 1)
+            ref.prolongate(l + 1)
+            ref.theta0[l + 1] = 0.0
+    print(f"reference descent in {time.perf_counter() - t0:.0f} s", flush=True)
+    worst = 0.0
+    for l in range(spec.nlevels):
+        for v in range(22):
+            want = ref.get(l, v)
+            e = np.abs(ctx.read_back(0, l, v) - want).max() / max(np.abs(want).max(), 1e-300)
+            assert e <= TOL, (l, v, e)
+            worst = max(worst, e)
+        print(f"level {l}: {len(want)} points, worst rel diff so far {worst:.3e}", flush=True)
+    ctx.close()
+
+
 def test_z4c_fp32_rhs_full_size_within_bound(punctures):
     """After one coarse step of the 7-level puncture hierarchy the FP32
     right-hand side stays within t * 32 eps32 max|y| / h_finest^2 of FP64."""

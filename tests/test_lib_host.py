@@ -197,6 +197,35 @@ def test_eighth_order_configuration_rules():
         assert e.value.code == sc.SC_E_ARG
 
 
+@pytest.mark.parametrize("name", ["two-level-tiny", "c2-16"])
+def test_five_ghost_layer_maps_bit_identical_to_reference(name):
+    spec, kw = SPECS[name]
+    ref = Hierarchy(spec, G=5, **kw).export()
+    ctx = sc.Context(fd_order=8, ko_order=9)
+    ctx.build_spec(spec, **kw)
+    got = ctx.export_maps()
+    assert got.shape == ref.shape
+    assert hashlib.sha256(got.tobytes()).hexdigest() == hashlib.sha256(ref.tobytes()).hexdigest()
+
+
+def test_ninth_order_dissipation_configuration_rules():
+    """Five ghost layers (the r = 8 dissipation) with the eighth-order wave,
+    FP64; not with Z4c, mixed precision or buffer zones; a hierarchy whose
+    five-layer RB stencils leave the parent level is a nesting error."""
+    sc.Context(fd_order=8, ko_order=9)
+    sc.Context(fd_order=8, ko_order=9, time_stepping=sc.SC_UNIFORM_DT)
+    for kw in (dict(rhs=sc.SC_RHS_Z4C), dict(precision=sc.SC_MIXED),
+               dict(time_stepping=sc.SC_BUFFER_ZONES)):
+        with pytest.raises(sc.ScError) as e:
+            sc.Context(**dict(dict(fd_order=8, ko_order=9), **kw))
+        assert e.value.code == sc.SC_E_ARG
+    spec, kw = SPECS["three-level-two-boxes"]
+    ctx = sc.Context(fd_order=8, ko_order=9)
+    with pytest.raises(sc.ScError) as e:
+        ctx.build_spec(spec, **kw)
+    assert e.value.code == sc.SC_E_NEST
+
+
 def test_radiative_boundary_configuration_rules():
     sc.Context(rhs=sc.SC_RHS_Z4C, outer_bc=sc.SC_BC_RADIATIVE)
     for kw in (dict(rhs=sc.SC_RHS_WAVE), dict(rhs=sc.SC_RHS_Z4C, precision=sc.SC_MIXED),
