@@ -273,6 +273,38 @@ def z4c_roofline(step_s):
             "counters": os.path.relpath(Z4C_COUNTERS, ROOT)}
 
 
+def summarize_runs(folder, nruns, steps, anchor_re, per_step):
+    """Kernel table per run of a trace holding several benchmark runs in one
+    process (separated at the nruns - 1 longest idle gaps): the dispatches from
+    the start of the last `steps` coarse steps of each run (located by the
+    anchor kernel, per_step launches per coarse step), per kernel family
+    (template arguments dropped), divided by `steps`."""
+    rows = trace_dispatches(folder)
+    gaps = sorted(range(1, len(rows)), key=lambda i: rows[i][1] - rows[i - 1][2])[-(nruns - 1):]
+    cuts = [0] + sorted(gaps) + [len(rows)]
+    out = []
+    for r in range(nruns):
+        run = rows[cuts[r]:cuts[r + 1]]
+        idx = [i for i, x in enumerate(run) if re.search(anchor_re, x[0])]
+        i0 = idx[-steps * per_step] if len(idx) >= steps * per_step else 0
+        fam = {}
+        for n, a, b in run[i0:]:
+            k = re.sub(r"<.*", "", short_name(n))
+            d = fam.setdefault(k, [0, 0.0])
+            d[0] += 1
+            d[1] += (b - a) / 1e3
+        tot = sum(d[1] for d in fam.values())
+        lines = [f"### run {r + 1}: kernels of its last {steps} coarse steps, per coarse step", "",
+                 "| kernel | launches / step | ms / step | share |", "|---|---|---|---|"]
+        for k, d in sorted(fam.items(), key=lambda kv: -kv[1][1]):
+            lines.append(f"| `{k}` | {d[0] / steps:.1f} | {d[1] / steps / 1e3:.2f} | "
+                         f"{100 * d[1] / tot:.1f} % |")
+        lines.append(f"| total | {sum(d[0] for d in fam.values()) / steps:.1f} | "
+                     f"{tot / steps / 1e3:.2f} | |")
+        out.append("\n".join(lines))
+    return "\n\n".join(out)
+
+
 def summarize_markers(folder):
     """roctx ranges of a rocprofv3 --marker-trace run, grouped by name with the
     step counters taken out: calls, total and average host duration."""
@@ -794,6 +826,10 @@ def main():
     ap.add_argument("--summarize-counters", metavar="DIR", nargs=4, default=None,
                     help="FETCH_SIZE, WRITE_SIZE, copy-probe FETCH_SIZE, copy-probe WRITE_SIZE "
                          "output folders of rocprofv3 --pmc runs: HBM bytes per dispatch")
+    ap.add_argument("--summarize-runs", metavar="DIR", default=None,
+                    help="kernel table per run of a trace of several runs (--runs, --per-step, "
+                         "--anchor k_wave_stage, --last: coarse steps per run)")
+    ap.add_argument("--runs", type=int, default=2)
     ap.add_argument("--summarize-markers", metavar="DIR", default=None,
                     help="table of the roctx ranges of a rocprofv3 --marker-trace output folder")
     ap.add_argument("--summarize-step", metavar="DIR", nargs=6, default=None,
@@ -810,6 +846,10 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.kernel, args.last))
+        return
+    if args.summarize_runs:
+        print(summarize_runs(args.summarize_runs, args.runs, args.last or 1, args.anchor,
+                             args.per_step))
         return
     if args.summarize_markers:
         print(summarize_markers(args.summarize_markers))

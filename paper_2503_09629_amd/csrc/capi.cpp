@@ -343,19 +343,39 @@ std::string build_layout(sc_ctx* c) {
     }
     const int npb = l > 0 ? c->lev[l - 1].nb_member : 0;
     // group RB halo slots (and buffer points) into bricks: the slots of each
-    // face of a fine box form slabs of the shell's full thickness by up to
-    // kBrickDim points along the face (the face cut into near-equal chunks
-    // whose starts are even), edge pieces and corners likewise; buffer points
-    // inside the box go into cells of a box-local 8-point lattice.  A group
-    // too large for one brick is cut into 8-point cells.  Slots that wrap
-    // periodically or whose stencils span two parent boxes stay per point.
+    // face of a fine box form slabs of the shell's full thickness (with buffer
+    // zones the buffer points under the face too) by up to 17 points along the
+    // face (the face cut into chunks of even start), edge pieces and corners
+    // likewise; any other point goes into a cell of a box-local 8-point
+    // lattice.  A group too large for one brick is cut into 8-point cells.
+    // Slots that wrap periodically or whose stencils span two parent boxes
+    // stay per point.
     std::vector<ProlongEntry> rest0;
     std::vector<ProlongBrick> bricks0;
     {
-      auto chunk = [](int p, int n) {   // face chunks of 16 points, the last up to 17
-        const int nc = std::max(1, (n - 1 + 15) / 16);
-        return std::min(p / 16, nc - 1);
+      // shell depth: the ghost layers, and with buffer zones the buffer points
+      // inside the box (at most 3G deep); the chunk width along a face is the
+      // largest of 16, 14, ... whose slabs (the last chunk one wider) fit a brick
+      const int depth = G + (c->cfg.time_stepping == SC_BUFFER_ZONES ? 3 * G : 0);
+      int cw = 16;
+      for (; cw > 4; cw -= 2) {
+        bool ok = true;
+        for (int dn = 0; dn < 3 && ok; ++dn)
+          for (int al = 0; al < 2 && ok; ++al) {
+            int a[3], n[3];
+            for (int d = 0; d < 3; ++d) {
+              a[d] = 2 + al;   // both parities of the first index
+              n[d] = d == dn ? depth : cw + 1;
+            }
+            ok = sc::brick_fits(a, n);
+          }
+        if (ok) break;
+      }
+      auto chunk = [cw](int p, int n) {   // face chunks of cw points, the last up to cw + 1
+        const int nc = std::max(1, (n - 1 + cw - 1) / cw);
+        return std::min(p / cw, nc - 1);
       };
+      const int bdepth = depth - G;   // buffer points this deep inside count as the shell
       // key: box, kind (0 shell, 1 inside), side code, then per-dimension chunk or cell
       std::map<std::array<int64_t, 6>, std::vector<size_t>> groups;
       std::vector<std::array<int, 4>> where(pro0.size());   // box and box-local point
@@ -379,7 +399,7 @@ std::string build_layout(sc_ctx* c) {
         int side = 0, outside = 0;
         int64_t c[3];
         for (int d = 2; d >= 0; --d) {
-          const int sd = h[d] < 0 ? 1 : (h[d] >= bn[d] ? 2 : 0);
+          const int sd = h[d] < bdepth ? 1 : (h[d] >= bn[d] - bdepth ? 2 : 0);
           side = side * 3 + sd;
           outside |= sd;
           c[d] = sd ? 0 : chunk(h[d], bn[d]);
