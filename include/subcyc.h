@@ -420,8 +420,10 @@ int sc_set_tile_shape(sc_ctx* ctx, int32_t level, int32_t tz, int32_t grid, int3
                       int32_t slots, int32_t threads);
 
 /* Timing of the stencil stage kernel with HIP events recorded on the
- * context's stream around every batched stage launch (eager modes only;
- * SC_E_STATE in graph mode).  Enabling clears the record. */
+ * context's stream (eager modes only; SC_E_STATE in graph mode): one pair
+ * around a level step's four batched stage launches when no other kernel
+ * runs between them (no intra-level ghost sync), else one pair around each
+ * batched stage launch.  Enabling clears the record. */
 int sc_profile_enable(sc_ctx* ctx, int32_t on);
 /* Synchronise, then return the recorded launches, their summed duration in
  * milliseconds and their summed algorithmic bytes: per owned point and

@@ -844,15 +844,17 @@ int enqueue_stage_launches(sc_ctx* c, int l, int stage, bool per_block, const vo
     int grid = std::min<int>(a.ntiles, L.shape.grid > 0 ? L.shape.grid : c->grid_cap);
     grid = (grid + 7) / 8 * 8;  // a multiple of the XCD count (the kernel's tile remap)
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->profiling) {
+    const bool own_events = c->profiling && !c->ev_grouped;   // else the level step's pair
+    if (own_events) {
       int rc = take_events(c, &e0, &e1);
       if (rc) return rc;
       HIPCHK(c, hipEventRecord(e0, c->stream));
     }
     HIPCHK(c, launch_stage(a, grid, c->mixed, L.shape.depth, L.shape.slots, L.shape.threads,
                            c->stream));
+    if (own_events) HIPCHK(c, hipEventRecord(e1, c->stream));
     if (c->profiling) {
-      HIPCHK(c, hipEventRecord(e1, c->stream));
+      ++c->ev_launches;
       // algorithmic bytes per owned point and variable: the stencil operands
       // y_n and k_{s-1}, the new slope, and for stage 4 also k1, k2, the FP64
       // y_n and y_{n+1}; mixed: stage 1 reads the FP64 y_n and writes an FP32
@@ -997,6 +999,16 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
   // reads the FP64 y_n (mixed: at stage 1 only)
   const bool shadow = c->mixed && !c->wave_mixed;
   const void* yn = shadow ? static_cast<const void*>(L.y32[L.cur]) : L.y[L.cur];
+  // kernel timing: when nothing but the four batched stage launches runs on
+  // the stream during the step (no ghost sync), one event pair spans all four
+  hipEvent_t g0 = nullptr, g1 = nullptr;
+  c->ev_grouped = false;
+  if (c->profiling && !per_block && L.sync.empty() && c->cfg.rhs == SC_RHS_WAVE) {
+    int rc = take_events(c, &g0, &g1);
+    if (rc) return rc;
+    HIPCHK(c, hipEventRecord(g0, c->stream));
+    c->ev_grouped = true;
+  }
   for (int s = 1; s <= 4; ++s) {
     // buffer zones: the RB ghosts keep the step's prolonged value at every stage
     void* yh = L.Yh[buffer_zones(c) ? (l == 0 ? 0 : substep * 4) : yh_index(l, substep, s)];
@@ -1020,7 +1032,14 @@ int rk4_step(sc_ctx* c, int l, int substep, bool per_block) {
     }
     int rc = c->cfg.rhs == SC_RHS_Z4C ? enqueue_z4c_launches(c, l, s, per_block, kprev, yh)
                                       : enqueue_stage_launches(c, l, s, per_block, yn, kprev, yh);
-    if (rc) return rc;
+    if (rc) {
+      c->ev_grouped = false;
+      return rc;
+    }
+  }
+  if (c->ev_grouped) {
+    c->ev_grouped = false;
+    HIPCHK(c, hipEventRecord(g1, c->stream));
   }
   L.cur = nxt(L);
   ++L.steps_done;
@@ -2347,6 +2366,7 @@ int sc_profile_enable(sc_ctx* c, int32_t on) {
     return fail(c, SC_E_STATE, "kernel timing needs an eager execution mode");
   c->profiling = on != 0;
   c->ev_used = 0;
+  c->ev_launches = 0;
   c->ev_bytes.clear();
   return SC_OK;
 }
@@ -2363,10 +2383,11 @@ int sc_profile_read(sc_ctx* c, int64_t* nlaunches, double* total_ms, double* alg
     ms += t;
   }
   for (double b : c->ev_bytes) bytes += b;
-  *nlaunches = (int64_t)(c->ev_used / 2);
+  *nlaunches = c->ev_launches;
   *total_ms = ms;
   *alg_bytes = bytes;
   c->ev_used = 0;
+  c->ev_launches = 0;
   c->ev_bytes.clear();
   return SC_OK;
 }

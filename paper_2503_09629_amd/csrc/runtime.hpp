@@ -128,6 +128,8 @@ struct sc_ctx {
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;                  // events handed out (pairs use 2)
+  int64_t ev_launches = 0;             // stage launches the recorded pairs span
+  bool ev_grouped = false;             // a level step's pair spans its stage launches
   std::vector<double> ev_bytes;        // algorithmic bytes per recorded launch
   ~sc_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);

@@ -402,3 +402,34 @@ def test_restart_from_read_back_state_is_bitwise(mode):
         for v in range(2):
             assert np.array_equal(b.read_back(0, l, v), want[l][v]), (l, v)
     b.close()
+
+
+def test_stage_kernel_timing_counts_every_launch_and_its_bytes():
+    """sc_profile_read after eager coarse steps: one record per batched stage
+    launch (levels without ghost sync share one event pair per level step),
+    positive time, and the algorithmic bytes of every launch: per owned point
+    and variable 16, 24, 24, 48 B for stages 1-4, 8 B less at stage 4 of the
+    finest level (no k4 stored); graph mode refuses timing."""
+    spec = config_c3(64, nlev=4)
+    ctx = _gpu(spec, exec=sc.SC_EXEC_BATCHED)
+    for l in range(spec.nlevels):
+        for v, f in enumerate(pulses_on_spec(spec, l)):
+            ctx.set_initial_data(0, l, v, f)
+    ctx.profile_enable(True)
+    ctx.advance(2)
+    n, ms, b = ctx.profile_read()
+    steps = [2 * (1 << l) for l in range(spec.nlevels)]
+    assert n == 4 * sum(steps)
+    assert ms > 0.0
+    want = 0.0
+    for l in range(spec.nlevels):
+        per = 16 + 24 + 24 + (48 if l + 1 < spec.nlevels else 40)
+        want += steps[l] * per * 2 * spec.npoints(l)
+    assert b == want
+    ctx.profile_enable(False)
+    ctx.close()
+    g = _gpu(spec, exec=sc.SC_EXEC_GRAPH)
+    with pytest.raises(sc.ScError) as e:
+        g.profile_enable(True)
+    assert e.value.code == sc.SC_E_STATE
+    g.close()
