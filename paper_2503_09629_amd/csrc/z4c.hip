@@ -616,7 +616,7 @@ __global__ __launch_bounds__(kZ4cThreads) void k_z4c_geom(Z4cArgs a) {
 // points per plane and at most 64 wide at H = 2
 template <int ORD> constexpr int kDerLds = ORD == 8 ? 6144 : 3328;
 template <int ORD>
-__global__ __launch_bounds__(256) void k_z4c_derivs(Z4cArgs a) {
+__global__ __launch_bounds__(256, ORD == 4 ? 4 : 2) void k_z4c_derivs(Z4cArgs a) {
   __shared__ double blk[kDerLds<ORD>];
   constexpr int H = ORD == 8 ? 4 : 2;   // reach of the first and mixed differences
   constexpr int ZS = 2;                 // planes per slab
@@ -633,18 +633,32 @@ __global__ __launch_bounds__(256) void k_z4c_derivs(Z4cArgs a) {
     for (int z0 = 0; z0 < T.nz; z0 += ZS) {
       const int nz = T.nz - z0 < ZS ? T.nz - z0 : ZS;
       const int bx = T.nx + 2 * H, by = T.ny + 2 * H, bz = nz + 2 * H;
-      const bool fits = bx * by * bz <= kDerLds<ORD>;   // uniform over the workgroup
+      const int nxy = bx * by;
+      const bool fits = nxy * bz <= kDerLds<ORD>;   // uniform over the workgroup
+      // this thread's x-y places of the block (threadIdx.x + k 256), as
+      // offsets within a plane of the box, worked out once per slab
+      constexpr int KXY = 3;   // a block that fits has at most 3 * 256 points per plane
+      int32_t oxy[KXY];
+#pragma unroll
+      for (int k = 0; k < KXY; ++k) {
+        const int e = threadIdx.x + k * 256;
+        const int ly = e / bx, lx = e - ly * bx;
+        oxy[k] = (T.y0 + ly - H + B.pad) * B.px + (T.x0 + lx - H + B.pad);
+      }
+      const int64_t pxy = (int64_t)B.px * B.py;
 #pragma unroll 1
       for (int n = 0; n < 16; ++n) {
         const int v = VS[n];
         if (fits) {
           __syncthreads();   // the previous variable's block has been read
-          for (int i = threadIdx.x; i < bx * by * bz; i += 256) {
-            const int lx = i % bx, ly = (i / bx) % by, lz = i / (bx * by);
-            const int64_t go = B.base + v * a.vstride +
-                               ((int64_t)(T.z0 + z0 + lz - H + B.pad) * B.py + (T.y0 + ly - H + B.pad)) *
-                                   (int64_t)B.px + (T.x0 + lx - H + B.pad);
-            blk[i] = static_cast<const double*>(a.Y)[go];
+          const double* src = static_cast<const double*>(a.Y) + B.base + v * a.vstride +
+                              (int64_t)(T.z0 + z0 - H + B.pad) * pxy;
+          for (int lz = 0; lz < bz; ++lz) {
+#pragma unroll
+            for (int k = 0; k < KXY; ++k) {
+              const int e = threadIdx.x + k * 256;
+              if (e < nxy) blk[lz * nxy + e] = src[lz * pxy + oxy[k]];
+            }
           }
           __syncthreads();
         }
