@@ -209,6 +209,30 @@ void tile_region(int box, const int64_t o[3], const int64_t n[3], const TileShap
       }
 }
 
+// Columns of the Z4c derivative pass over a region of box `box`: x-y tiles
+// of at most kDerTx x kDerTy points, z chunks of at most tz planes.
+void der_region(int box, const int64_t o[3], const int64_t n[3], int tz,
+                std::vector<TileDev>* out) {
+  std::vector<std::pair<int, int>> sx, sy, sz;
+  split_even(n[0], kDerTx, &sx);
+  split_even(n[1], kDerTy, &sy);
+  split_even(n[2], tz, &sz);
+  for (auto& y : sy)
+    for (auto& x : sx)
+      for (auto& z : sz) {
+        TileDev t;
+        t.box = box;
+        t.x0 = (int)o[0] + x.first;
+        t.y0 = (int)o[1] + y.first;
+        t.z0 = (int)o[2] + z.first;
+        t.nx = x.second;
+        t.ny = y.second;
+        t.nz = z.second;
+        t.dir = 0;
+        out->push_back(t);
+      }
+}
+
 // parent box of level l-1 holding the whole prolongation stencil of q
 int stencil_parent(const LevelMaps& P, const int64_t q[3]) {
   int64_t smin[3], smax[3];
@@ -605,6 +629,24 @@ std::string build_layout(sc_ctx* c) {
         tile_region(m * L.nb_member + ib, o, n, L.shape, &L.btiles);
         L.btile_start.push_back((int32_t)L.btiles.size());
       }
+    if (c->cfg.rhs == SC_RHS_Z4C) {
+      for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
+        const BoxDev& B = L.boxes[ib];
+        const int64_t o[3] = {0, 0, 0}, n[3] = {B.nx, B.ny, B.nz};
+        der_region(ib, o, n, der_tz(c->fd_order), &L.dtiles);
+      }
+      L.bdtile_start.push_back(0);
+      for (int m = 0; m < nm; ++m)
+        for (size_t b = 0; b < M.blocks.size(); ++b) {
+          const IBox& bl = M.blocks[b];
+          const int ib = M.block_box[b];
+          const IBox& bx = M.boxes[ib];
+          const int64_t o[3] = {bl.lo[0] - bx.lo[0], bl.lo[1] - bx.lo[1], bl.lo[2] - bx.lo[2]};
+          const int64_t n[3] = {bl.n(0), bl.n(1), bl.n(2)};
+          der_region(m * L.nb_member + ib, o, n, der_tz(c->fd_order), &L.bdtiles);
+          L.bdtile_start.push_back((int32_t)L.bdtiles.size());
+        }
+    }
   }
   return "";
 }
@@ -628,6 +670,15 @@ std::string validate_layout(const sc_ctx* c) {
       if (!tile_ok(t, L.shape.slots, L.shape.threads)) return "tile outside its box";
     for (const TileDev& t : L.btiles)
       if (!tile_ok(t, kStageSlotsMax, kStageThreads)) return "block tile outside its box";
+    for (const std::vector<TileDev>* v : {&L.dtiles, &L.bdtiles})
+      for (const TileDev& t : *v) {
+        if (t.box < 0 || t.box >= (int)L.boxes.size()) return "derivative column outside its box";
+        const BoxDev& B = L.boxes[t.box];
+        if (t.nx < 1 || t.ny < 1 || t.nz < 1 || t.nx > kDerTx || t.ny > kDerTy ||
+            t.nz > der_tz(c->fd_order) || t.x0 < 0 || t.y0 < 0 || t.z0 < 0 || t.x0 + t.nx > B.nx ||
+            t.y0 + t.ny > B.ny || t.z0 + t.nz > B.nz)
+          return "derivative column outside its box";
+      }
     for (const BoxDev& B : L.boxes)
       if (!in_level(B.base) ||
           B.base + (int64_t)B.px * B.py * (B.nz + 2 * G) > L.total)
@@ -756,6 +807,8 @@ void plan_arena(sc_ctx* c) {
     }
     L.o_tiles = take(sizeof(TileDev) * L.tiles_capacity);
     L.o_btiles = take(sizeof(TileDev) * L.btiles.size());
+    L.o_dtiles = take(sizeof(TileDev) * L.dtiles.size());
+    L.o_bdtiles = take(sizeof(TileDev) * L.bdtiles.size());
     maxowned = std::max(maxowned, std::max(L.owned_member, L.nrb * (int64_t)c->hier.geo.nmembers));
     maxowned = std::max(maxowned, (int64_t)L.phys_q.size() / 3);
   }
@@ -896,6 +949,8 @@ Z4cArgs z4c_args(sc_ctx* c, int l) {
   a.ord = c->fd_order;
   a.nonfinite = c->d_nonfinite;
   a.der = c->d_der;
+  a.dtiles = L.d_dtiles;   // the whole level; per-block launches narrow it
+  a.ndtiles = (int32_t)L.dtiles.size();
   return a;
 }
 
@@ -982,6 +1037,8 @@ int enqueue_z4c_launches(sc_ctx* c, int l, int stage, bool per_block, const void
       const int n = L.btile_start[b + 1] - L.btile_start[b];
       a.tiles = L.d_btiles + L.btile_start[b];
       a.ntiles = n;
+      a.dtiles = L.d_bdtiles + L.bdtile_start[b];
+      a.ndtiles = L.bdtile_start[b + 1] - L.bdtile_start[b];
       HIPCHK(c, launch_z4c_stage(a, n, c->mixed, c->stream));
       ++c->launches;
     }
@@ -1556,6 +1613,8 @@ int sc_bind_device_memory(sc_ctx* c, void* dptr, size_t nbytes) {
     L.d_restr = at<RestrictRegion>(c, L.o_restr);
     L.d_tiles = at<TileDev>(c, L.o_tiles);
     L.d_btiles = at<TileDev>(c, L.o_btiles);
+    L.d_dtiles = at<TileDev>(c, L.o_dtiles);
+    L.d_bdtiles = at<TileDev>(c, L.o_bdtiles);
     HIPCHK(c, upload(c, L.d_boxes, L.boxes));
     HIPCHK(c, upload(c, L.d_prefix, L.prefix));
     HIPCHK(c, upload(c, L.d_sync, L.sync));
@@ -1567,6 +1626,8 @@ int sc_bind_device_memory(sc_ctx* c, void* dptr, size_t nbytes) {
     HIPCHK(c, upload(c, L.d_restr, L.restr));
     HIPCHK(c, upload(c, L.d_tiles, L.tiles));
     HIPCHK(c, upload(c, L.d_btiles, L.btiles));
+    HIPCHK(c, upload(c, L.d_dtiles, L.dtiles));
+    HIPCHK(c, upload(c, L.d_bdtiles, L.bdtiles));
   }
   c->d_stage = at<double>(c, c->o_stage);
   c->d_der = c->cfg.rhs == SC_RHS_Z4C ? at<double>(c, c->o_der) : nullptr;

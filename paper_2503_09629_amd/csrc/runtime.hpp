@@ -54,12 +54,17 @@ struct LevelDev {
   size_t tiles_capacity = 0;         // tile slots reserved in the arena
   std::vector<TileDev> btiles;       // per block: tiles clipped to blocks
   std::vector<int32_t> btile_start;  // nblocks (all members) + 1
+  // Z4c FP64: the derivative pass's columns over the boxes, and per block
+  std::vector<TileDev> dtiles;
+  std::vector<TileDev> bdtiles;
+  std::vector<int32_t> bdtile_start;  // nblocks (all members) + 1
   TileShape shape;
   int nyh = 1;
   bool has_child = false;
   // arena offsets (bytes)
   size_t o_y[3], o_y32[2], o_k[4], o_yh[8], o_yd[2], o_boxes, o_prefix, o_sync, o_prolong,
-      o_rblist, o_rbfirst, o_phys, o_restr, o_tiles, o_btiles, o_ys, o_bricks;
+      o_rblist, o_rbfirst, o_phys, o_restr, o_tiles, o_btiles, o_ys, o_bricks, o_dtiles,
+      o_bdtiles;
   // device pointers after binding.  y: FP64 state; y32: its FP32 shadow
   // (Z4c mixed mode only); k and Yh hold the slope type (FP64, or FP32 in
   // mixed mode); Yd: FP64 stage-1 halo tables of the mixed wave (one per
@@ -82,6 +87,8 @@ struct LevelDev {
   RestrictRegion* d_restr = nullptr;
   TileDev* d_tiles = nullptr;
   TileDev* d_btiles = nullptr;
+  TileDev* d_dtiles = nullptr;
+  TileDev* d_bdtiles = nullptr;
   int cur = 0;
   int nbuf = 2;                      // state buffers in rotation (3 with buffer zones)
   int64_t steps_done = 0;            // RK4 steps taken (buffer zones: time-interpolation history)

@@ -55,8 +55,9 @@ __host__ __device__ constexpr int der2_slot(int v, int k, int l) {
 // ORD: 4 (five-point centred derivatives) or 8 (nine-point, four ghost layers)
 // SCR: take first derivatives and second derivatives from the derivative
 // pass's scratch (FP64) instead of forming them from stencil taps
-// LDS: the taps come from one variable's block staged in LDS (lds, at local
-// offset lo with row and plane pitches lpx, lpxy) instead of the stage vector
+// LDS: the taps come from one variable's planes staged in LDS (plane z + dz
+// at lds + zb[dz + reach], the point at offset lo, row pitch lpx) instead of
+// the stage vector
 template <typename TS, int ORD, bool SCR = false, bool LDS = false>
 struct Pt {
   const Z4cArgs* a;
@@ -65,11 +66,12 @@ struct Pt {
   int64_t o;
   int64_t px, pxy;
   const TS* lds;
-  int lo, lpx, lpxy;
+  int lo, lpx;
+  int zb[ORD == 8 ? 9 : 5];
   // the stage vector on the whole padded box (owned points and halo) is one
   // array, so a tap is one unconditional load
   __device__ TS at(int v, int dx, int dy, int dz) const {
-    if constexpr (LDS) return lds[lo + dx + dy * lpx + dz * lpxy];
+    if constexpr (LDS) return lds[zb[dz + (ORD == 8 ? 4 : 2)] + lo + dx + dy * lpx];
     else return static_cast<const TS*>(a->Y)[o + dx + dy * px + dz * pxy + v * a->vstride];
   }
   __device__ TS tap(int v, int d, int j) const {
@@ -606,20 +608,28 @@ __global__ __launch_bounds__(kZ4cThreads) void k_z4c_geom(Z4cArgs a) {
 
 // Derivative pass (FP64): every first and second derivative the curvature
 // and evolution passes read, formed with the same stencils as the tap form
-// (so the same bits) and stored at once.  Each variable's block around a
-// slab of at most two planes of the tile (the stencil reach H on every side)
-// is staged in LDS, so a point's 63 taps per variable come from LDS and every
-// stage-vector value is read from memory once per slab; few registers are
-// live, so several waves per SIMD run.  A tile slab whose block does not fit
-// takes its taps from memory instead.
-// LDS block in doubles: a 16 x 16 x 2 slab at H = 4; any slab of at most 256
-// points per plane and at most 64 wide at H = 2
-template <int ORD> constexpr int kDerLds = ORD == 8 ? 6144 : 3328;
+// (so the same bits) and stored at once.  Work item: one variable on one
+// derivative column (a tile of at most kDerTx x kDerTy points in x-y, a
+// chunk of at most der_tz(ORD) planes in z).  The workgroup marches the
+// column in z with a ring of 2H + 2 planes of the variable's block (the
+// column's x-y extent plus the stencil reach H on every side) in LDS: the
+// taps of a point come from the planes z - H .. z + H, and the plane H + 1
+// ahead is read from memory while the current plane's derivatives are formed,
+// so each stage-vector value of the block is read once per column.  At fourth order the work items run
+// variable by variable over the column list, so neighbouring columns, whose
+// blocks overlap, are read together from one XCD's L2; at eighth order
+// (two workgroups per CU) column by column, all 16 variables of a column
+// together (the faster order there, measured on C5).
+template <int ORD> constexpr int kDerPlane = (kDerTx + 2 * (ORD == 8 ? 4 : 2)) *
+                                             (kDerTy + 2 * (ORD == 8 ? 4 : 2));
 template <int ORD>
 __global__ __launch_bounds__(256, ORD == 4 ? 4 : 2) void k_z4c_derivs(Z4cArgs a) {
-  __shared__ double blk[kDerLds<ORD>];
   constexpr int H = ORD == 8 ? 4 : 2;   // reach of the first and mixed differences
-  constexpr int ZS = 2;                 // planes per slab
+  constexpr int NP = 2 * H + 2;         // ring slots
+  constexpr int P = kDerPlane<ORD>;     // slot size in doubles
+  constexpr int KL = (P + 255) / 256;   // block values per thread and plane
+  static_assert(kDerTx * kDerTy <= 256, "one point per thread and plane");
+  __shared__ double ring[NP * P];
   const double h = a.h;
   const double c1 = 1.0 / ((ORD == 8 ? 840.0 : 12.0) * h);
   const double c2 = 1.0 / ((ORD == 8 ? 5040.0 : 12.0) * h * h);
@@ -627,74 +637,75 @@ __global__ __launch_bounds__(256, ORD == 4 ? 4 : 2) void k_z4c_derivs(Z4cArgs a)
   // V2 order have stored second derivatives too
   constexpr int VS[16] = {VG, VG + 1, VG + 2, VG + 3, VG + 4, VG + 5, VW, VALP, VB, VB + 1, VB + 2,
                           VKH, VTH, VGAM, VGAM + 1, VGAM + 2};
-  for (int t = xcd_first_tile(); t < a.ntiles; t += gridDim.x) {
-    const TileDev T = a.tiles[t];
+  const int nwork = a.ndtiles * 16;
+  const int tid = threadIdx.x;
+  for (int w = xcd_first_tile(); w < nwork; w += gridDim.x) {
+    const int n = ORD == 8 ? w % 16 : w / a.ndtiles;
+    const TileDev T = a.dtiles[ORD == 8 ? w / 16 : w - n * a.ndtiles];
     const BoxDev B = a.boxes[T.box];
-    for (int z0 = 0; z0 < T.nz; z0 += ZS) {
-      const int nz = T.nz - z0 < ZS ? T.nz - z0 : ZS;
-      const int bx = T.nx + 2 * H, by = T.ny + 2 * H, bz = nz + 2 * H;
-      const int nxy = bx * by;
-      const bool fits = nxy * bz <= kDerLds<ORD>;   // uniform over the workgroup
-      // this thread's x-y places of the block (threadIdx.x + k 256), as
-      // offsets within a plane of the box, worked out once per slab
-      constexpr int KXY = 3;   // a block that fits has at most 3 * 256 points per plane
-      int32_t oxy[KXY];
+    const int v = VS[n];
+    const int bx = T.nx + 2 * H, nxy = bx * (T.ny + 2 * H);
+    const int64_t pxy = (int64_t)B.px * B.py;
+    // this thread's places of the block plane (tid + 256 k), as offsets
+    // within a plane of the box
+    int32_t oxy[KL];
 #pragma unroll
-      for (int k = 0; k < KXY; ++k) {
-        const int e = threadIdx.x + k * 256;
-        const int ly = e / bx, lx = e - ly * bx;
-        oxy[k] = (T.y0 + ly - H + B.pad) * B.px + (T.x0 + lx - H + B.pad);
+    for (int k = 0; k < KL; ++k) {
+      const int e = tid + k * 256;
+      const int ly = e / bx, lx = e - ly * bx;
+      oxy[k] = (T.y0 + ly - H + B.pad) * B.px + (T.x0 + lx - H + B.pad);
+    }
+    // block plane j (z = z0 - H + j) of the variable
+    const double* src = static_cast<const double*>(a.Y) + B.base + v * a.vstride +
+                        (int64_t)(T.z0 - H + B.pad) * pxy;
+    for (int j = 0; j <= 2 * H; ++j)
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        const int e = tid + k * 256;
+        if (e < nxy) ring[j * P + e] = src[j * pxy + oxy[k]];
       }
-      const int64_t pxy = (int64_t)B.px * B.py;
-#pragma unroll 1
-      for (int n = 0; n < 16; ++n) {
-        const int v = VS[n];
-        if (fits) {
-          __syncthreads();   // the previous variable's block has been read
-          const double* src = static_cast<const double*>(a.Y) + B.base + v * a.vstride +
-                              (int64_t)(T.z0 + z0 - H + B.pad) * pxy;
-          for (int lz = 0; lz < bz; ++lz) {
+    __syncthreads();
+    const bool own = tid < T.nx * T.ny;
+    const int rx = own ? tid % T.nx : 0, ry = own ? tid / T.nx : 0;
+    int64_t o = B.base + ((int64_t)(T.z0 + B.pad) * B.py + (T.y0 + ry + B.pad)) * (int64_t)B.px +
+                (T.x0 + rx + B.pad);
+    int s0 = 0;   // ring slot of block plane iz (z - H)
+    for (int iz = 0; iz < T.nz; ++iz) {
+      // block plane iz + 2H + 1, needed from the next plane on
+      const bool more = iz + 1 < T.nz;
+      double pre[KL];
 #pragma unroll
-            for (int k = 0; k < KXY; ++k) {
-              const int e = threadIdx.x + k * 256;
-              if (e < nxy) blk[lz * nxy + e] = src[lz * pxy + oxy[k]];
-            }
-          }
-          __syncthreads();
-        }
-        for (int ixy = threadIdx.x; ixy < T.nx * T.ny; ixy += 256) {   // packed, as in z4c_points
-          const int rx = ixy % T.nx, ry = ixy / T.nx;
-          for (int iz = 0; iz < nz; ++iz) {
-            const int64_t o = B.base + ((int64_t)(T.z0 + z0 + iz + B.pad) * B.py + (T.y0 + ry + B.pad)) *
-                                           (int64_t)B.px + (T.x0 + rx + B.pad);
-            auto emit = [&](const auto& p) {
-#pragma unroll
-              for (int k = 0; k < 3; ++k) a.der[o + der1_slot(v, k) * a.vstride] = p.d1(v, k, c1);
-              if (n < 11)
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                  for (int l = k; l < 3; ++l)
-                    a.der[o + der2_slot(v, k, l) * a.vstride] = p.dd(v, k, l, c1, c2);
-            };
-            if (fits) {
-              Pt<double, ORD, false, true> p;
-              p.lds = blk;
-              p.lpx = bx;
-              p.lpxy = bx * by;
-              p.lo = ((iz + H) * by + (ry + H)) * bx + (rx + H);
-              emit(p);
-            } else {
-              Pt<double, ORD> p;
-              p.a = &a;
-              p.px = B.px;
-              p.pxy = (int64_t)B.px * B.py;
-              p.o = o;
-              emit(p);
-            }
-          }
-        }
+      for (int k = 0; k < KL; ++k) {
+        const int e = tid + k * 256;
+        pre[k] = (more && e < nxy) ? src[(int64_t)(iz + 2 * H + 1) * pxy + oxy[k]] : 0.0;
       }
+      if (own) {
+        Pt<double, ORD, false, true> p;
+        p.lds = ring;
+        p.lpx = bx;
+        p.lo = (ry + H) * bx + (rx + H);
+#pragma unroll
+        for (int m = 0; m <= 2 * H; ++m) p.zb[m] = (s0 + m < NP ? s0 + m : s0 + m - NP) * P;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.der[o + der1_slot(v, k) * a.vstride] = p.d1(v, k, c1);
+        if (n < 11)
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int l = k; l < 3; ++l)
+              a.der[o + der2_slot(v, k, l) * a.vstride] = p.dd(v, k, l, c1, c2);
+      }
+      // the slot of block plane iz - 1, which no thread reads any more
+      const int sw = s0 == 0 ? NP - 1 : s0 - 1;
+      if (more)
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+          const int e = tid + k * 256;
+          if (e < nxy) ring[sw * P + e] = pre[k];
+        }
+      __syncthreads();
+      s0 = s0 + 1 == NP ? 0 : s0 + 1;
+      o += pxy;
     }
   }
 }
@@ -895,7 +906,10 @@ hipError_t launch_z4c_radiative(const Z4cRadArgs& a, hipStream_t s) {
 
 template <int ORD>
 void z4c_stage_f64(const Z4cArgs& a, dim3 g, dim3 b, dim3 b2, hipStream_t s) {
-  hipLaunchKernelGGL((k_z4c_derivs<ORD>), g, b2, 0, s, a);
+  // one workgroup per variable and derivative column, in whole rounds of the
+  // 8 XCDs (the spare workgroups exit at once)
+  const dim3 gd((unsigned)((a.ndtiles * 16 + 7) / 8 * 8));
+  hipLaunchKernelGGL((k_z4c_derivs<ORD>), gd, b2, 0, s, a);
   hipLaunchKernelGGL((k_z4c_geom<double, ORD, 1>), g, b, 0, s, a);
   if (!a.ham) {
     hipLaunchKernelGGL((k_z4c_geom<double, ORD, 2>), g, b, 0, s, a);
@@ -909,7 +923,8 @@ hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, bool f32, hipStream_t s)
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g(grid > 0 ? grid : a.ntiles), b(kZ4cThreads), b2(256);
   if (a.ord != 4 && a.ord != 8) return hipErrorInvalidValue;
-  if (!f32 && !a.der) return hipErrorInvalidValue;   // FP64 needs the derivative scratch
+  // FP64 needs the derivative scratch and the derivative columns
+  if (!f32 && (!a.der || !a.dtiles || a.ndtiles <= 0)) return hipErrorInvalidValue;
   if (f32) {
     if (a.ord != 4) return hipErrorInvalidValue;   // the FP32 variant is fourth order
     // FP32: the fused kernel fits the register file; FP64: two passes, since

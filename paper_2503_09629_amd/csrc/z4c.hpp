@@ -16,11 +16,21 @@ constexpr int kZ4cScratch = kZ4cGeo;
 // passes use, stored per point in the level's padded layout.
 constexpr int kZ4cDer1 = 16 * 3;
 constexpr int kZ4cDer = kZ4cDer1 + 11 * 6;
+// The derivative pass's own columns: at most kDerTx x kDerTy points in x-y
+// (one per thread of a 256-thread workgroup; wide rows, so that the stores of
+// neighbouring columns complete whole memory lines) and der_tz(order) planes
+// in z (deeper at eighth order, whose four-plane reach costs more per column;
+// sizes chosen by timing C5).
+constexpr int kDerTx = 64;
+constexpr int kDerTy = 4;
+constexpr int der_tz(int ord) { return ord == 8 ? 32 : 16; }
 
 struct Z4cArgs {
   const TileDev* tiles;
   int32_t ntiles;
   int32_t stage;
+  const TileDev* dtiles;   // the derivative pass's columns over the same region (FP64)
+  int32_t ndtiles;
   const BoxDev* boxes;
   const void* Y;      // stage vector on the padded boxes (owned points and halo), TS
   const double* yn;   // FP64 y_n (stage 4)
