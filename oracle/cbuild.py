@@ -52,7 +52,7 @@ def lib():
         for f in (_lib.orc_wave_rhs, _lib.orc_stage, _lib.orc_final, _lib.orc_copy_points):
             f.restype = None
         if hasattr(_lib, "orc_z4c_rhs"):
-            for f in (_lib.orc_z4c_rhs, _lib.orc_z4c_rhs8):
+            for f in (_lib.orc_z4c_rhs, _lib.orc_z4c_rhs8, _lib.orc_z4c_rhs8_ko9):
                 f.argtypes = [i, i64p, i, L, i64p, i64p, d, i64p, i64p, i64p, i64p]
                 f.restype = None
     return _lib

@@ -225,8 +225,8 @@ class OracleRun:
     rhs: "wave" (variables u, Pi) or "z4c" (22 variables, Sec. III.A; see
     oracle/z4c.c).  fd_order: 4, or 8 for eighth-order derivatives
     (oracle/stencil.c, oracle/z4c.c; needs a hierarchy with G >= 4).  ko_order:
-    5 (the r = 4 dissipation of Sec. III.C), or 9 (r = 8: the wave with
-    fd_order 8 on a hierarchy with G >= 5).  sigma: Kreiss-Oliger strength.  cfl: dt_l = cfl * dx_l.
+    5 (the r = 4 dissipation of Sec. III.C), or 9 (r = 8, with fd_order 8 on
+    a hierarchy with G >= 5).  sigma: Kreiss-Oliger strength.  cfl: dt_l = cfl * dx_l.
     z4c: kappa1, kappa2, eta_c, eta_o, eta_s.
     """
 
@@ -238,9 +238,8 @@ class OracleRun:
             raise ValueError(rhs)
         if fd_order not in (4, 8) or (fd_order == 8 and hier.G < 4):
             raise ValueError("fd_order 8 needs G >= 4")
-        if ko_order not in (5, 9) or (ko_order == 9 and (rhs != "wave" or fd_order != 8 or
-                                                          hier.G < 5)):
-            raise ValueError("ko_order 9 needs the wave, fd_order 8 and G >= 5")
+        if ko_order not in (5, 9) or (ko_order == 9 and (fd_order != 8 or hier.G < 5)):
+            raise ValueError("ko_order 9 needs fd_order 8 and G >= 5")
         self.fd_order = fd_order
         self.ko_order = ko_order
         if outer_bc not in ("frozen", "radiative"):
@@ -410,7 +409,8 @@ class OracleRun:
             f(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total, cbuild.ptr(Y), cbuild.ptr(k),
               self.dx[l], self.sigma)
         else:
-            f = self.lib.orc_z4c_rhs8 if self.fd_order == 8 else self.lib.orc_z4c_rhs
+            f = (self.lib.orc_z4c_rhs8_ko9 if self.ko_order == 9 else
+                 self.lib.orc_z4c_rhs8 if self.fd_order == 8 else self.lib.orc_z4c_rhs)
             f(st.lev.nblocks, cbuild.ptr(st.desc), st.G, st.total, cbuild.ptr(Y), cbuild.ptr(k),
               self.dx[l], cbuild.ptr(self.z4c_par), cbuild.ptr(self.block_origin[l]), None, None)
 

@@ -19,7 +19,10 @@
  * paper's production stencil, Sec. III.C; G >= 4) the same with the
  * eighth-order centred weights: D1 = (3, -32, 168, -672, 0, 672, -168, 32, -3)
  * / (840 h), D2 = (-9, 128, -1008, 8064, -14350, 8064, -1008, 128, -9)
- * / (5040 h^2); the dissipation stays the r = 4 operator.
+ * / (5040 h^2); the dissipation stays the r = 4 operator, or (Sec. III.C's
+ * ninth-order option, G >= 5) is the r = 8 operator
+ *   Q u = sigma / (1024 h) sum_d delta_d^10 u,
+ *   delta^10 = (1, -10, 45, -120, 210, -252, 210, -120, 45, -10, 1).
  * Variables (slot order): W, gt_xx,xy,xz,yy,yz,zz, Khat, At_xx..zz, Theta,
  * Gt^x,y,z, alpha, beta^x,y,z.
  * Storage as in stencil.c: padded blocks {base, nx, ny, nz}, variable v at
@@ -34,6 +37,7 @@ enum { VW = 0, VG = 1, VKH = 7, VA = 8, VTH = 14, VGAM = 15, VALP = 18, VB = 19,
 static const int SYM[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
 
 static int ORDER = 4;   /* set per call of the right-hand side */
+static int KORD = 4;    /* dissipation operator r: 4, or 8 */
 
 static double D1(const double* a, int64_t o, int64_t s, double c1) {
   if (ORDER == 8)
@@ -65,6 +69,11 @@ static double DM(const double* a, int64_t o, int64_t s, int64_t t, double c1) {
 }
 
 static double KO(const double* a, int64_t o, int64_t s) {
+  if (KORD == 8)
+    return (((((((((a[o - 5 * s] - 10.0 * a[o - 4 * s]) + 45.0 * a[o - 3 * s]) -
+                  120.0 * a[o - 2 * s]) + 210.0 * a[o - s]) - 252.0 * a[o]) +
+               210.0 * a[o + s]) - 120.0 * a[o + 2 * s]) + 45.0 * a[o + 3 * s]) -
+             10.0 * a[o + 4 * s]) + a[o + 5 * s];
   return (((((a[o - 3 * s] - 6.0 * a[o - 2 * s]) + 15.0 * a[o - s]) - 20.0 * a[o]) +
            15.0 * a[o + s]) - 6.0 * a[o + 2 * s]) + a[o + 3 * s];
 }
@@ -289,7 +298,7 @@ static void z4c_point(const double* Y, int64_t o, int64_t vs, const int64_t st[3
   const double eta = (eta_c - eta_o) * exp(-(rq * rq) * (rq * rq)) + eta_o;
   for (int i = 0; i < 3; ++i) rhs[VB + i] = adv[VB + i] + 0.75 * Gt[i] - eta * beta[i];
   /* Kreiss-Oliger dissipation on every variable */
-  const double cko = sigma / (64.0 * h);
+  const double cko = sigma / ((KORD == 8 ? 1024.0 : 64.0) * h);
   for (int i = 0; i < NV; ++i) {
     const double* a = Y + i * vs;
     rhs[i] += cko * ((KO(a, o, st[0]) + KO(a, o, st[1])) + KO(a, o, st[2]));
@@ -330,6 +339,7 @@ static void z4c_rhs(int nb, const int64_t* desc, int G, int64_t vstride, const d
 void orc_z4c_rhs(int nb, const int64_t* desc, int G, int64_t vstride, const double* Y, double* k,
                  double h, const double* par, const double* origin, double* ricci, double* ham) {
   ORDER = 4;
+  KORD = 4;
   z4c_rhs(nb, desc, G, vstride, Y, k, h, par, origin, ricci, ham);
 }
 
@@ -338,5 +348,15 @@ void orc_z4c_rhs8(int nb, const int64_t* desc, int G, int64_t vstride, const dou
                   double* k, double h, const double* par, const double* origin, double* ricci,
                   double* ham) {
   ORDER = 8;
+  KORD = 4;
+  z4c_rhs(nb, desc, G, vstride, Y, k, h, par, origin, ricci, ham);
+}
+
+/* Eighth-order derivatives with the r = 8 dissipation (G >= 5). */
+void orc_z4c_rhs8_ko9(int nb, const int64_t* desc, int G, int64_t vstride, const double* Y,
+                      double* k, double h, const double* par, const double* origin,
+                      double* ricci, double* ham) {
+  ORDER = 8;
+  KORD = 8;
   z4c_rhs(nb, desc, G, vstride, Y, k, h, par, origin, ricci, ham);
 }
