@@ -130,7 +130,7 @@ typedef struct {
   int32_t precision;   /* SC_FP64 or SC_MIXED */
   int32_t exec;        /* SC_EXEC_* */
   int32_t nghost;      /* ghost width: 3 for fd_order 4, 4 for fd_order 8; 5 for fd_order 8
-                          with the ninth-order dissipation (the wave only) */
+                          with the ninth-order dissipation */
   int32_t time_stepping; /* SC_SUBCYCLED (default), SC_UNIFORM_DT or SC_BUFFER_ZONES */
   double ko_sigma;     /* Kreiss-Oliger strength sigma (Sec. III.C), e.g. 0.32 */
   double cfl;          /* dt_l = cfl * dx_l, 0 < cfl <= 0.5 */
@@ -145,7 +145,8 @@ typedef struct {
                           wave or Z4c, FP64, SC_SUBCYCLED or SC_UNIFORM_DT); fd_order 8
                           with nghost 5 selects the ninth-order dissipation of the
                           same section (its Q u with r = 8: sigma/(1024 h) times the
-                          eleven-point tenth difference per dimension; wave, FP64) */
+                          eleven-point tenth difference per dimension; wave or Z4c,
+                          FP64) */
   int32_t outer_bc;    /* SC_BC_FROZEN (default) or SC_BC_RADIATIVE */
 } sc_config;
 

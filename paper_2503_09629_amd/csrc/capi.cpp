@@ -947,6 +947,7 @@ Z4cArgs z4c_args(sc_ctx* c, int l) {
   a.eta_s = c->cfg.z4c_eta_s;
   for (int d = 0; d < 3; ++d) a.origin[d] = c->hier.geo.origin[d];
   a.ord = c->fd_order;
+  a.ko_r = c->G == 5 ? 8 : 4;
   a.nonfinite = c->d_nonfinite;
   a.der = c->d_der;
   a.dtiles = L.d_dtiles;   // the whole level; per-block launches narrow it
@@ -1417,10 +1418,11 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
                      (cfg->time_stepping == SC_SUBCYCLED || cfg->time_stepping == SC_UNIFORM_DT ||
                       (cfg->time_stepping == SC_BUFFER_ZONES && cfg->rhs == SC_RHS_WAVE &&
                        cfg->precision == SC_FP64));
-  // eighth order: wave, FP64, four ghost layers, subcycled or uniform steps
+  // eighth order: FP64, four ghost layers (five: the r = 8 dissipation),
+  // subcycled or uniform steps
   const bool order_ok =
       (cfg->fd_order == 4 && cfg->nghost == 3) ||
-      (cfg->fd_order == 8 && (cfg->nghost == 4 || (cfg->nghost == 5 && cfg->rhs == SC_RHS_WAVE)) &&
+      (cfg->fd_order == 8 && (cfg->nghost == 4 || cfg->nghost == 5) &&
        cfg->precision == SC_FP64 &&
        cfg->time_stepping != SC_BUFFER_ZONES);
   // radiative outer boundary: Z4c, FP64
@@ -1433,7 +1435,7 @@ int sc_create(const sc_config* cfg, void* hip_stream, sc_ctx** out) {
       cfg->exec < 0 || cfg->exec > 2) {
     g_create_error = "unsupported configuration (rhs, time stepping (buffer zones: wave, FP64), "
                      "fd_order 4 with nghost 3 or 8 with nghost 4 (FP64, no buffer zones) or "
-                     "nghost 5 (r = 8 dissipation: wave, FP64, no buffer zones), "
+                     "nghost 5 (r = 8 dissipation, FP64, no buffer zones), "
                      "outer_bc (radiative: Z4c, FP64), "
                      "0 < cfl <= 0.5, sigma >= 0, precision, exec)";
     return SC_E_ARG;

@@ -750,12 +750,16 @@ void k_z4c_evol(Z4cArgs a) {
   });
 }
 
-// Completes k_s: adds the advection terms beta^k d_k Y (centred fourth-order
-// first differences) and the Kreiss-Oliger dissipation of every variable;
-// at stage 4 also forms y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4) in
-// FP64.  Both stencils read the same seven taps per axis.
-template <int STAGE, typename TS, int ORD>
+// Completes k_s: adds the advection terms beta^k d_k Y (centred first
+// differences of the derivative order) and the Kreiss-Oliger dissipation of
+// every variable; at stage 4 also forms
+// y_{n+1} = y_n + (dt/6) (((k1 + 2 k2) + 2 k3) + k4) in FP64.  Both stencils
+// read taps along the axes only.  KR: the dissipation's reach, 3 (r = 4,
+// sigma/(64 h) delta^6) or 5 (r = 8, sigma/(1024 h) delta^10, Sec. III.C's
+// ninth-order option).
+template <int STAGE, typename TS, int ORD, int KR = 3>
 __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
+  static_assert(KR == 3 || (KR == 5 && ORD == 8), "r = 8 dissipation: eighth order only");
   const TS* Y = static_cast<const TS*>(a.Y);
   TS* kout = static_cast<TS*>(a.kout);
   const TS* k1 = static_cast<const TS*>(a.k1);
@@ -763,8 +767,9 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
   const TS* k3 = static_cast<const TS*>(a.k3);
   const TS h = TS(a.h);
   const TS c1 = TS(1.0) / (TS(ORD == 8 ? 840.0 : 12.0) * h);
-  const TS cko = TS(a.sigma) / (TS(64.0) * h);
-  constexpr int R = ORD == 8 ? 4 : 3;   // taps per side: the first difference's, at least KO's 3
+  const TS cko = TS(a.sigma) / (TS(KR == 5 ? 1024.0 : 64.0) * h);
+  // taps per side: the first difference's (2 or 4) or the dissipation's
+  constexpr int R = KR == 5 ? 5 : (ORD == 8 ? 4 : 3);
   bool bad = false;   // stage 4: a non-finite y_{n+1} was written (reported once per thread)
   for (int t = xcd_first_tile(); t < a.ntiles; t += gridDim.x) {
     const TileDev T = a.tiles[t];
@@ -788,8 +793,14 @@ __global__ __launch_bounds__(256) void k_z4c_advko(Z4cArgs a) {
             for (int j = 0; j < 2 * R + 1; ++j) tp[j] = Y[oi + (j - R) * st[d]];
             const TS d1 = Pt<TS, ORD>::diff1([&](int j) { return tp[R + j]; }, c1);
             adv += beta[d] * d1;
-            ko[d] = (((((tp[R - 3] - TS(6.0) * tp[R - 2]) + TS(15.0) * tp[R - 1]) - TS(20.0) * tp[R]) +
-                      TS(15.0) * tp[R + 1]) - TS(6.0) * tp[R + 2]) + tp[R + 3];
+            if constexpr (KR == 5)
+              ko[d] = (((((((((tp[R - 5] - TS(10.0) * tp[R - 4]) + TS(45.0) * tp[R - 3]) -
+                             TS(120.0) * tp[R - 2]) + TS(210.0) * tp[R - 1]) - TS(252.0) * tp[R]) +
+                          TS(210.0) * tp[R + 1]) - TS(120.0) * tp[R + 2]) + TS(45.0) * tp[R + 3]) -
+                       TS(10.0) * tp[R + 4]) + tp[R + 5];
+            else
+              ko[d] = (((((tp[R - 3] - TS(6.0) * tp[R - 2]) + TS(15.0) * tp[R - 1]) - TS(20.0) * tp[R]) +
+                        TS(15.0) * tp[R + 1]) - TS(6.0) * tp[R + 2]) + tp[R + 3];
           }
           const TS k = (kout[oi] + adv) + cko * ((ko[0] + ko[1]) + ko[2]);
           kout[oi] = k;
@@ -914,6 +925,13 @@ void z4c_stage_f64(const Z4cArgs& a, dim3 g, dim3 b, dim3 b2, hipStream_t s) {
   if (!a.ham) {
     hipLaunchKernelGGL((k_z4c_geom<double, ORD, 2>), g, b, 0, s, a);
     hipLaunchKernelGGL((k_z4c_evol<ORD>), g, b, 0, s, a);
+    if constexpr (ORD == 8) {
+      if (a.ko_r == 8) {
+        if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, double, 8, 5>), g, b2, 0, s, a);
+        else hipLaunchKernelGGL((k_z4c_advko<1, double, 8, 5>), g, b2, 0, s, a);
+        return;
+      }
+    }
     if (a.stage == 4) hipLaunchKernelGGL((k_z4c_advko<4, double, ORD>), g, b2, 0, s, a);
     else hipLaunchKernelGGL((k_z4c_advko<1, double, ORD>), g, b2, 0, s, a);
   }
@@ -923,6 +941,7 @@ hipError_t launch_z4c_stage(const Z4cArgs& a, int grid, bool f32, hipStream_t s)
   if (a.ntiles <= 0) return hipSuccess;
   const dim3 g(grid > 0 ? grid : a.ntiles), b(kZ4cThreads), b2(256);
   if (a.ord != 4 && a.ord != 8) return hipErrorInvalidValue;
+  if (a.ko_r != 4 && !(a.ko_r == 8 && a.ord == 8 && !f32)) return hipErrorInvalidValue;
   // FP64 needs the derivative scratch and the derivative columns
   if (!f32 && (!a.der || !a.dtiles || a.ndtiles <= 0)) return hipErrorInvalidValue;
   if (f32) {

@@ -47,6 +47,7 @@ struct Z4cArgs {
   double h, dt6, sigma, kappa1, kappa2, eta_c, eta_o, eta_s;
   double origin[3];   // coordinates of global index (0,0,0) of the level
   int32_t ord;        // derivative order: 4, or 8 (FP64, boxes padded by 4)
+  int32_t ko_r;       // dissipation operator r: 4, or 8 (eighth order, FP64, boxes padded by 5)
   unsigned int* nonfinite;   // set to 1 when stage 4 writes a non-finite y_{n+1}
 };
 

@@ -19,14 +19,15 @@ KW = dict(min_block=8, max_block=16)
 
 
 def _pair(spec, exec=sc.SC_EXEC_BATCHED, precision=sc.SC_FP64, outer_bc=sc.SC_BC_FROZEN,
-          fd_order=4):
+          fd_order=4, ko_order=5):
     ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=exec, precision=precision,
-                     outer_bc=outer_bc, fd_order=fd_order)
+                     outer_bc=outer_bc, fd_order=fd_order, ko_order=ko_order)
     ctx.build_spec(spec, **KW)
     ctx.bind()
-    ref = OracleRun(Hierarchy(spec, G=4 if fd_order == 8 else 3, **KW), rhs="z4c",
+    G = (5 if ko_order == 9 else 4) if fd_order == 8 else 3
+    ref = OracleRun(Hierarchy(spec, G=G, **KW), rhs="z4c",
                     outer_bc="radiative" if outer_bc == sc.SC_BC_RADIATIVE else "frozen",
-                    fd_order=fd_order)
+                    fd_order=fd_order, ko_order=ko_order)
     for l in range(spec.nlevels):
         for v, f in enumerate(brill_lindquist_on_spec(spec, l)):
             ctx.set_initial_data(0, l, v, f)
@@ -190,6 +191,21 @@ def test_z4c_eighth_order_matches_reference(exec, bc):
             e = np.abs(a - b).max() / np.abs(b).max()
             print("level", l, "H rel diff", e)
             assert e <= TOL
+
+
+@pytest.mark.parametrize("exec", [sc.SC_EXEC_BATCHED, sc.SC_EXEC_GRAPH, sc.SC_EXEC_PER_BLOCK])
+@pytest.mark.parametrize("bc", [sc.SC_BC_FROZEN, sc.SC_BC_RADIATIVE])
+def test_z4c_ninth_order_dissipation_matches_reference(exec, bc):
+    """Eighth-order derivatives with the r = 8 dissipation (Sec. III.C's
+    ninth-order option), five ghost layers, both outer boundaries (towers of
+    20 cells: the five-layer refinement-boundary stencils stay inside one
+    parent box)."""
+    spec = config_z4c_small(nt=20)
+    ctx, ref = _pair(spec, exec=exec, outer_bc=bc, fd_order=8, ko_order=9)
+    ctx.advance(2)
+    ref.advance(2)
+    w = _compare(ctx, ref, arrays=(sc.SC_ARR_Y, sc.SC_ARR_K1, sc.SC_ARR_K4))
+    print("z4c ninth-order dissipation exec", exec, "bc", bc, "worst rel diff", w)
 
 
 def test_z4c_tile_shape_can_be_set_back():

@@ -209,12 +209,15 @@ def test_five_ghost_layer_maps_bit_identical_to_reference(name):
 
 
 def test_ninth_order_dissipation_configuration_rules():
-    """Five ghost layers (the r = 8 dissipation) with the eighth-order wave,
-    FP64; not with Z4c, mixed precision or buffer zones; a hierarchy whose
-    five-layer RB stencils leave the parent level is a nesting error."""
+    """Five ghost layers (the r = 8 dissipation) with eighth-order derivatives,
+    wave or Z4c (either outer boundary), FP64; not with mixed precision or
+    buffer zones; a hierarchy whose five-layer RB stencils leave the parent
+    level is a nesting error."""
     sc.Context(fd_order=8, ko_order=9)
     sc.Context(fd_order=8, ko_order=9, time_stepping=sc.SC_UNIFORM_DT)
-    for kw in (dict(rhs=sc.SC_RHS_Z4C), dict(precision=sc.SC_MIXED),
+    sc.Context(fd_order=8, ko_order=9, rhs=sc.SC_RHS_Z4C)
+    sc.Context(fd_order=8, ko_order=9, rhs=sc.SC_RHS_Z4C, outer_bc=sc.SC_BC_RADIATIVE)
+    for kw in (dict(precision=sc.SC_MIXED), dict(rhs=sc.SC_RHS_Z4C, precision=sc.SC_MIXED),
                dict(time_stepping=sc.SC_BUFFER_ZONES)):
         with pytest.raises(sc.ScError) as e:
             sc.Context(**dict(dict(fd_order=8, ko_order=9), **kw))
