@@ -2,9 +2,11 @@
 // dissipation (Sec. III.C), fused with the RK4 stage update, for gfx950.
 //
 // Variables (slot order): W, gt_xx,xy,xz,yy,yz,zz, Khat, At_xx..zz, Theta,
-// Gt^x,y,z, alpha, beta^x,y,z.  Vacuum.  Derivatives: fourth-order centred
-// first and second differences, mixed second derivatives as D1_a(D1_b);
-// advection beta^k d_k with the centred first difference.  The relations the
+// Gt^x,y,z, alpha, beta^x,y,z.  Vacuum.  Derivatives: fourth-order (or,
+// with four ghost layers, eighth-order) centred first and second differences,
+// mixed second derivatives as D1_a(D1_b); advection beta^k d_k with the
+// centred first difference; dissipation with r = 4 (or, with five ghost
+// layers, r = 8).  The relations the
 // paper's equations use without printing them are the standard conformal
 // ones: Gt_kij = (d_i gt_jk + d_j gt_ik - d_k gt_ij)/2, Gt^k_ij = gt^kl Gt_lij,
 // Gd^i = gt^jk Gt^i_jk, physical Christoffels
@@ -19,9 +21,16 @@
 // The stage vector is materialised once per stage (k_z4c_combine writes the
 // owned points into the stage's halo table, whose halo the ghost fills have
 // written), because every one of its 22 components is read about 40 times by
-// the stencils; a stencil tap is then one load from one padded array.  One thread computes one point: the 66 first derivatives live in
-// registers and every second derivative is contracted as soon as it is
-// formed.
+// the stencils; a stencil tap is then one load from one padded array.
+//
+// FP64 right-hand side, in passes over the level: k_z4c_derivs stores the 114
+// first and second derivatives the later passes use in a per-point scratch;
+// k_z4c_geom (two launches) forms the curvature terms into a second scratch;
+// k_z4c_evol the evolution, gauge and damping terms; k_z4c_advko adds the
+// advection and the dissipation and completes the stage.  The FP32 variant
+// runs the curvature and evolution terms in one pass, one thread per point,
+// with the first derivatives in registers and every second derivative
+// contracted as soon as it is formed.
 #include "device.hpp"
 #include "z4c.hpp"
 
