@@ -390,7 +390,9 @@ int sc_poison_halos(sc_ctx* ctx);
  * variant (threads per workgroup, owned points per thread, planes of loads
  * kept in flight ahead of the computed plane: see sc_set_tile_shape) with
  * HIP events (reps times the four stage launches of one RK4 step, on the
- * bound data) and keep the fastest.  Overwrites the slopes of every level
+ * bound data) and keep the first candidate, in search order, within 1.5 % of
+ * the fastest (so that near-equal shapes do not trade places between runs).
+ * Overwrites the slopes of every level
  * and the state buffer that the next step writes (call it before a run or
  * between coarse steps).  Invalidates captured graphs.  Synchronises the
  * stream. */

@@ -2328,9 +2328,18 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
   HIPCHK(c, hipEventCreate(&e1));
   for (size_t l = 0; l < c->lev.size(); ++l) {
     LevelDev& L = c->lev[l];
-    float best = 1e30f;
-    TileShape best_shape = L.shape;
-    std::vector<TileDev> best_tiles = L.tiles;
+    // every candidate's time, in search order; the first one within
+    // kTuneSlack of the fastest wins, so that shapes whose times differ by
+    // less than the timing noise do not trade places from run to run
+    struct Cand {
+      float ms;
+      TileShape shape;
+      size_t tiles;   // index into tables
+    };
+    std::vector<Cand> cands;
+    std::vector<std::vector<TileDev>> tables;
+    const TileShape shape0 = L.shape;
+    const std::vector<TileDev> tiles0 = L.tiles;
     for (int tx : {kTileMaxX, 32})
     for (int threads : {256, 512})
     for (int slots : {2, 1})
@@ -2350,6 +2359,7 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
       if (tl.size() > L.tiles_capacity) continue;
       HIPCHK(c, upload(c, L.d_tiles, tl));
       L.tiles = tl;
+      tables.push_back(tl);
       for (int depth : {1, 2})
       for (int g : {2 * ncu, 3 * ncu, 4 * ncu, 8 * ncu, 1 << 30}) {
         if (!stage_variant_ok(slots, depth, threads)) break;
@@ -2377,16 +2387,22 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
         HIPCHK(c, hipEventSynchronize(e1));
         float ms = 0.f;
         HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-          best = ms;
-          best_shape = sh;
-          best_tiles = tl;
-        }
+        cands.push_back({ms, sh, tables.size() - 1});
         if (g >= (int)tl.size()) break;
       }
     }
-    L.shape = best_shape;
-    L.tiles = best_tiles;
+    L.shape = shape0;
+    L.tiles = tiles0;
+    if (!cands.empty()) {
+      float best = cands[0].ms;
+      for (const Cand& k : cands) best = std::min(best, k.ms);
+      for (const Cand& k : cands)
+        if (k.ms <= best * (1.0f + kTuneSlack)) {
+          L.shape = k.shape;
+          L.tiles = tables[k.tiles];
+          break;
+        }
+    }
     HIPCHK(c, upload(c, L.d_tiles, L.tiles));
   }
   (void)hipEventDestroy(e0);

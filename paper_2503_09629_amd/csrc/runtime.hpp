@@ -28,6 +28,7 @@ struct TileShape {
 constexpr int kTuneTz[] = {4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 18, 20,
                            24, 28, 32, 40, 48, 64, 1 << 20};
 constexpr int kTuneTzMin = 4;
+constexpr float kTuneSlack = 0.015f;   // autotuner: candidates this close to the fastest tie
 constexpr int kZ4cTzMin = 2;   // Z4c contexts cut two-plane tiles by default
 
 struct LevelDev {
