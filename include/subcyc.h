@@ -405,7 +405,9 @@ int sc_autotune(sc_ctx* ctx, int32_t reps);
  * context two-plane tiles of at most 256 points per plane (its kernels run one
  * wave per SIMD and need many tiles to fill the chip; they launch one
  * workgroup per tile, rounded up to a multiple of 8, which is what a Z4c
- * context reports as its workgroup count). */
+ * context reports as its workgroup count).  The FP64 Z4c derivative pass
+ * keeps its own fixed columns (64 x 4 points, 16 planes; 32 at eighth
+ * order), which neither call reports or changes. */
 int sc_tile_shape(const sc_ctx* ctx, int32_t level, int32_t out[8]);
 /* Set a level's stencil tile shape without timing (for instance one found by
  * sc_autotune in an earlier run).  Wave contexts: z-chunk tz >= 4, persistent workgroups grid
