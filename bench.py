@@ -69,8 +69,8 @@ def measured_traffic(mode_result):
     sh = re.search(r"tile_shapes:\s*(\{.*\})", txt)
     if not m or not h or not sh or kernel_source_hash() != h.group(1):
         return None
-    keys = ("tz_per_level", "grid_per_level", "depth_per_level", "slots_per_level",
-            "threads_per_level")
+    keys = ("tx_per_level", "tz_per_level", "grid_per_level", "depth_per_level",
+            "slots_per_level", "threads_per_level")
     want = json.loads(sh.group(1))
     if any(want.get(k) != mode_result.get(k) for k in keys):
         return None
@@ -926,7 +926,7 @@ def main():
             for l in range(spec.nlevels):
                 ctx.set_tile_shape(l, tuned["tz_per_level"][l], tuned["grid_per_level"][l],
                                    tuned["depth_per_level"][l], tuned["slots_per_level"][l],
-                                   tuned["threads_per_level"][l])
+                                   tuned["threads_per_level"][l], tuned["tx_per_level"][l])
         elif m != "per_block" and not args.no_tune:
             ctx.autotune(3)
         shapes = [ctx.tile_shape(l) for l in range(spec.nlevels)]
@@ -936,7 +936,8 @@ def main():
         T, per = timed_reps(ctx, torch, steps)
         res[m] = {"updates_per_s": U * steps / T, "ms_per_step": 1e3 * T / steps,
                   "ms_per_step_reps": per, "ms_per_step_median": float(np.median(per)),
-                  "steps": steps, "tz_per_level": [sh["tz"] for sh in shapes],
+                  "steps": steps, "tx_per_level": [sh["tx"] for sh in shapes],
+                  "tz_per_level": [sh["tz"] for sh in shapes],
                   "grid_per_level": [sh["grid"] for sh in shapes],
                   "depth_per_level": [sh["depth"] for sh in shapes],
                   "slots_per_level": [sh["slots"] for sh in shapes],

@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define SC_ABI_VERSION 2
+#define SC_ABI_VERSION 3
 
 typedef enum {
   SC_OK = 0,
@@ -386,6 +386,7 @@ int sc_set_exec(sc_ctx* ctx, int32_t exec);
 int sc_poison_halos(sc_ctx* ctx);
 
 /* Autotune the batched stencil kernel: for every level, time candidate
+ * tile widths (the widest the LDS window and ring allow, 64 and 32 points),
  * z-chunk depths of the tile table, persistent grid sizes and the stencil
  * variant (threads per workgroup, owned points per thread, planes of loads
  * kept in flight ahead of the computed plane: see sc_set_tile_shape) with
@@ -415,14 +416,17 @@ int sc_tile_shape(const sc_ctx* ctx, int32_t level, int32_t out[8]);
  * flight ahead of the computed plane (depth), owned points per thread (slots)
  * and threads per workgroup (threads; a tile holds at most threads * slots
  * points), (threads, slots, depth) one of (256, 2, 1), (256, 2, 2),
- * (256, 1, 2), (512, 2, 1), (512, 2, 2).  SC_E_ARG if a value is out of range
+ * (256, 1, 2), (512, 2, 1), (512, 2, 2); widest tile tx in 1..128 (0: the
+ * untuned default, 64; the LDS window and ring slots cap it lower, at 78 for
+ * the fourth-order stencil), so that the widths sc_tile_shape reports, set
+ * back, cut the same tiles.  SC_E_ARG if a value is out of range
  * or the shape gives more tiles than the tile table was sized for.  Z4c
  * contexts: only tz applies (tz >= 2; the shape sc_tile_shape reports can be
- * set back); grid, depth, slots and threads are ignored, since the Z4c kernels
- * keep their workgroup shape and launch one workgroup per tile.
+ * set back); grid, depth, slots, threads and tx are ignored, since the Z4c
+ * kernels keep their workgroup shape and launch one workgroup per tile.
  * Invalidates captured graphs; synchronises the stream. */
 int sc_set_tile_shape(sc_ctx* ctx, int32_t level, int32_t tz, int32_t grid, int32_t depth,
-                      int32_t slots, int32_t threads);
+                      int32_t slots, int32_t threads, int32_t tx);
 
 /* Timing of the stencil stage kernel with HIP events recorded on the
  * context's stream (eager modes only; SC_E_STATE in graph mode): one pair

@@ -21,7 +21,7 @@ SC_FP64, SC_MIXED = 0, 1
 SC_EXEC_PER_BLOCK, SC_EXEC_BATCHED, SC_EXEC_GRAPH = 0, 1, 2
 SC_ARR_Y, SC_ARR_K1, SC_ARR_K2, SC_ARR_K3, SC_ARR_K4, SC_ARR_YN = range(6)
 SC_FILL_Y1, SC_FILL_Y2, SC_FILL_Y3, SC_FILL_Y4, SC_FILL_END = 1, 2, 3, 4, 5
-SC_ABI_VERSION = 2
+SC_ABI_VERSION = 3
 SC_SUBCYCLED, SC_UNIFORM_DT, SC_BUFFER_ZONES = 0, 1, 2
 SC_BC_FROZEN, SC_BC_RADIATIVE = 0, 1
 SC_ID_STANDING_WAVE, SC_ID_GAUSSIAN_PULSES, SC_ID_BRILL_LINDQUIST, SC_ID_SPHERICAL_GAUSSIAN = 1, 2, 3, 4
@@ -109,7 +109,7 @@ def lib():
             "sc_poison_halos": [P],
             "sc_autotune": [P, i32],
             "sc_tile_shape": [P, i32, P],
-            "sc_set_tile_shape": [P, i32, i32, i32, i32, i32, i32],
+            "sc_set_tile_shape": [P, i32, i32, i32, i32, i32, i32, i32],
             "sc_profile_enable": [P, i32],
             "sc_profile_read": [P, P, P, P],
             "sc_stats": [P, P, P],
@@ -363,8 +363,9 @@ class Context:
         return dict(zip(("tx", "ty", "tz", "grid", "tiles", "depth", "slots", "threads"), list(out)))
 
     def set_tile_shape(self, level: int, tz: int, grid: int = 0, depth: int = 1, slots: int = 2,
-                       threads: int = 256):
-        self._check(self.L.sc_set_tile_shape(self.ctx, level, tz, grid, depth, slots, threads))
+                       threads: int = 256, tx: int = 0):
+        self._check(self.L.sc_set_tile_shape(self.ctx, level, tz, grid, depth, slots, threads,
+                                             tx))
 
     def profile_enable(self, on: bool = True):
         self._check(self.L.sc_profile_enable(self.ctx, int(bool(on))))

@@ -154,7 +154,7 @@ int tile_ty_cap(int nxm, int slots, int threads, int R) {
 }
 
 // Widest tile whose one-row window and ring fit the family's LDS window and
-// ring slots (64 for radius 3; 55 for radius 4).
+// ring slots (78 for radius 3; 55 for radius 4; 40 for radius 5).
 int tile_tx_cap(int threads, int R) {
   const int by_ring = threads * stage_ring_slots(threads) / (2 * R) - 2 * R - 1;
   const int by_win = stage_win_cap(threads) / (1 + 2 * R) - 2 * R;
@@ -2276,7 +2276,7 @@ static void drop_graphs(sc_ctx* c) {
 }
 
 int sc_set_tile_shape(sc_ctx* c, int32_t level, int32_t tz, int32_t grid, int32_t depth,
-                      int32_t slots, int32_t threads) {
+                      int32_t slots, int32_t threads, int32_t tx) {
   int rc = check_ready(c, 3);
   if (rc) return rc;
   if (level < 0 || level >= (int)c->lev.size()) return fail(c, SC_E_ARG, "level out of range");
@@ -2284,6 +2284,7 @@ int sc_set_tile_shape(sc_ctx* c, int32_t level, int32_t tz, int32_t grid, int32_
   if (tz < (z4c ? kZ4cTzMin : kTuneTzMin) || tz > (1 << 20))
     return fail(c, SC_E_ARG, "z-chunk out of range");
   if (grid < 0) return fail(c, SC_E_ARG, "grid must be >= 0");
+  if (tx < 0 || tx > kTileMaxX) return fail(c, SC_E_ARG, "tile width out of range");
   if (!z4c && !stage_variant_ok(slots, depth, threads))
     return fail(c, SC_E_ARG, "(threads, points per thread, planes in flight) must be (256, 2, 1), "
                              "(256, 2, 2), (256, 1, 2), (512, 2, 1) or (512, 2, 2)");
@@ -2294,6 +2295,7 @@ int sc_set_tile_shape(sc_ctx* c, int32_t level, int32_t tz, int32_t grid, int32_
     sh.depth = depth;
     sh.slots = slots;
     sh.threads = threads;
+    sh.tx = tx > 0 ? tx : kTileDefaultX;
   }
   std::vector<TileDev> tl;
   for (int ib = 0; ib < (int)L.boxes.size(); ++ib) {
@@ -2340,7 +2342,7 @@ int sc_autotune(sc_ctx* c, int32_t reps) {
     std::vector<std::vector<TileDev>> tables;
     const TileShape shape0 = L.shape;
     const std::vector<TileDev> tiles0 = L.tiles;
-    for (int tx : {kTileMaxX, 32})
+    for (int tx : {kTileMaxX, kTileDefaultX, 32})
     for (int threads : {256, 512})
     for (int slots : {2, 1})
     for (int tz : kTuneTz) {

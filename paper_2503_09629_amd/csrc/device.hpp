@@ -294,6 +294,8 @@ constexpr int kStageThreads = 256;   // the default family (per-block mode uses 
 constexpr int kStageSlotsMax = 2;    // owned points per thread and plane of a stencil tile (1 or 2)
 inline int stage_ring_slots(int threads) { return threads == 512 ? 1 : 2; }
 inline int stage_win_cap(int threads) { return threads == 512 ? 1600 : 1024; }
-constexpr int kTileMaxX = 64;     // widest stencil tile (points in x)
+constexpr int kTileMaxX = 128;    // widest stencil tile (points in x; the LDS window and ring
+                                  // slots cap it lower, at 78 for radius 3)
+constexpr int kTileDefaultX = 64; // widest tile of a context's untuned shape
 
 }  // namespace sc

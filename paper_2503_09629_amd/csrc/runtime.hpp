@@ -13,7 +13,7 @@
 namespace sc {
 
 struct TileShape {
-  int tx = kTileMaxX, ty = 1 << 20, tz = 16;   // tx, ty: caps on the tile width and height
+  int tx = kTileDefaultX, ty = 1 << 20, tz = 16;   // tx, ty: caps on the tile width and height
   int grid = 0;   // persistent workgroups for the batched stage kernel (0: context default)
   int depth = 1;  // stage kernel: planes of loads in flight ahead of the computed plane
   int slots = 2;  // owned points per stage-kernel thread (tiles of at most threads * slots points)

@@ -215,7 +215,8 @@ def test_pinned_tile_shapes_bitwise_equal(mixed):
     spec = config_c3(64, nlev=4)
     prec = sc.SC_MIXED if mixed else sc.SC_FP64
     shapes = [None, (4, 0, 2, 1), (7, 0, 2, 2), (12, 64, 1, 2), (1 << 20, 0, 2, 1), (5, 16, 2, 1),
-              (9, 0, 2, 2), (6, 24, 1, 2), (8, 0, 2, 2, 512), (13, 16, 1, 2, 512), (5, 0, 1, 2, 512)]
+              (9, 0, 2, 2), (6, 24, 1, 2), (8, 0, 2, 2, 512), (13, 16, 1, 2, 512), (5, 0, 1, 2, 512),
+              (7, 0, 2, 2, 256, 128), (9, 0, 1, 2, 512, 40), (6, 0, 2, 1, 256, 17)]
     outs = []
     for sh in shapes:
         ctx = _gpu(spec, precision=prec)
@@ -228,12 +229,34 @@ def test_pinned_tile_shapes_bitwise_equal(mixed):
                 got = ctx.tile_shape(l)
                 assert (got["tz"], got["depth"], got["slots"]) == (sh[0], sh[2], sh[3])
                 assert got["threads"] == (sh[4] if len(sh) > 4 else 256)
+                assert got["tx"] <= (min(sh[5], 78) if len(sh) > 5 else 64)
         ctx.advance(2)
         outs.append([ctx.read_back(0, l, v) for l in range(spec.nlevels) for v in range(2)])
         ctx.close()
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+def test_autotuned_shapes_set_back_cut_the_same_tiles():
+    """The shape sc_tile_shape reports after autotuning (widths included),
+    passed to sc_set_tile_shape in a fresh context, cuts the same tiles."""
+    spec = config_c3(64, nlev=4)
+    shapes = []
+    for k in range(2):
+        ctx = _gpu(spec)
+        for l in range(spec.nlevels):
+            for v, f in enumerate(pulses_on_spec(spec, l)):
+                ctx.set_initial_data(0, l, v, f)
+        if k == 0:
+            ctx.autotune(1)
+        else:
+            for l, sh in enumerate(shapes[0]):
+                ctx.set_tile_shape(l, sh["tz"], sh["grid"], sh["depth"], sh["slots"],
+                                   sh["threads"], sh["tx"])
+        shapes.append([ctx.tile_shape(l) for l in range(spec.nlevels)])
+        ctx.close()
+    assert shapes[0] == shapes[1]
 
 
 def test_set_tile_shape_rejects_bad_arguments():
@@ -244,7 +267,7 @@ def test_set_tile_shape_rejects_bad_arguments():
             ctx.set_initial_data(0, l, v, f)
     for args in ((0, 3, 0, 1, 2), (0, 8, -1, 1, 2), (0, 8, 0, 3, 2), (0, 8, 0, 1, 4), (5, 8, 0, 1, 2),
                  (0, 8, 0, 1, 1), (0, 8, 0, 4, 2), (0, 8, 0, 4, 1), (0, 8, 0, 2, 1, 512),
-                 (0, 8, 0, 2, 2, 384)):
+                 (0, 8, 0, 2, 2, 384), (0, 8, 0, 2, 2, 256, -1), (0, 8, 0, 2, 2, 256, 129)):
         with pytest.raises(sc.ScError):
             ctx.set_tile_shape(*args)
     ctx.set_tile_shape(0, 8, 0, 2, 1)
