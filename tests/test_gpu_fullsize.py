@@ -279,9 +279,9 @@ def punctures():
     return spec, [brill_lindquist_on_spec(spec, l) for l in range(spec.nlevels)]
 
 
-def _z4c_ctx(spec, data, precision=sc.SC_FP64):
+def _z4c_ctx(spec, data, precision=sc.SC_FP64, fd_order=4, ko_order=5):
     ctx = sc.Context(device="cuda:0", rhs=sc.SC_RHS_Z4C, exec=sc.SC_EXEC_GRAPH,
-                     precision=precision)
+                     precision=precision, fd_order=fd_order, ko_order=ko_order)
     ctx.build_spec(spec)
     ctx.bind()
     for l in range(spec.nlevels):
@@ -331,16 +331,22 @@ def test_z4c_level0_step_sampled(punctures):
     ctx.close()
 
 
-def test_z4c_first_descent_every_level_against_reference(punctures):
+@pytest.mark.parametrize("orders", [(4, 5), (8, 9)], ids=["fd4-ko5", "fd8-ko9"])
+def test_z4c_first_descent_every_level_against_reference(punctures, orders):
     """The puncture hierarchy at full size: one RK4 step of every level, coarse
     to fine, each level's RB ghosts prolonged from its parent's step (the
     recursion's first descent), against the reference doing the same; every
     owned point of every level and variable, 1e-12 relative to the reference's
-    max norm."""
+    max norm.  Fourth order, and eighth-order derivatives with the r = 8
+    dissipation (five ghost layers: the derivative pass's 32-plane columns and
+    the eleven-tap dissipation on the full-size boxes)."""
     import time
+    fd, ko = orders
     spec, data = punctures
-    ctx = _z4c_ctx(spec, data)
-    ref = OracleRun(Hierarchy(spec, min_block=16, max_block=48), rhs="z4c")
+    ctx = _z4c_ctx(spec, data, fd_order=fd, ko_order=ko)
+    G = 5 if ko == 9 else 3
+    ref = OracleRun(Hierarchy(spec, G=G, min_block=16, max_block=48), rhs="z4c", fd_order=fd,
+                    ko_order=ko)
     for l in range(spec.nlevels):
         for v in range(22):
             ref.set_data(l, v, data[l][v])
