@@ -331,20 +331,21 @@ def test_z4c_level0_step_sampled(punctures):
     ctx.close()
 
 
-@pytest.mark.parametrize("orders", [(4, 5), (8, 9)], ids=["fd4-ko5", "fd8-ko9"])
+@pytest.mark.parametrize("orders", [(4, 5), (8, 5), (8, 9)], ids=["fd4-ko5", "fd8-ko5", "fd8-ko9"])
 def test_z4c_first_descent_every_level_against_reference(punctures, orders):
     """The puncture hierarchy at full size: one RK4 step of every level, coarse
     to fine, each level's RB ghosts prolonged from its parent's step (the
     recursion's first descent), against the reference doing the same; every
     owned point of every level and variable, 1e-12 relative to the reference's
-    max norm.  Fourth order, and eighth-order derivatives with the r = 8
-    dissipation (five ghost layers: the derivative pass's 32-plane columns and
-    the eleven-tap dissipation on the full-size boxes)."""
+    max norm.  Fourth order, and eighth-order derivatives with the r = 4 and the
+    r = 8 dissipation (four and five ghost layers: the derivative pass's
+    32-plane columns, the nine- and eleven-tap advection/dissipation pass on the
+    full-size boxes)."""
     import time
     fd, ko = orders
     spec, data = punctures
     ctx = _z4c_ctx(spec, data, fd_order=fd, ko_order=ko)
-    G = 5 if ko == 9 else 3
+    G = (5 if ko == 9 else 4) if fd == 8 else 3
     ref = OracleRun(Hierarchy(spec, G=G, min_block=16, max_block=48), rhs="z4c", fd_order=fd,
                     ko_order=ko)
     for l in range(spec.nlevels):
